@@ -1,0 +1,149 @@
+"""Seeded synthetic inputs shared by the oracle, the tests and the benchmark.
+
+This module only draws inputs (point sets, right-hand sides, request traces).
+It holds none of the compression method's arithmetic, so both the CPU oracle
+and the GPU library may consume what it produces without sharing any code.
+
+The paper's experiments use a closed planar contour (boundary integral
+equation) and points uniform on the unit sphere (3D Laplace / FMM); it names
+no public dataset.  The generators below are synthetic stand-ins with those
+shapes:
+
+* ``uniform_line``     -- N i.i.d. points uniform on [0, 1] (HODLR workload).
+* ``star_curve``       -- N points equispaced in angle on r = 1 + 0.3 cos(5 t).
+* ``sphere``           -- N points uniform on the unit sphere (normalised
+                          Gaussians).
+* ``ellipse``          -- N points equispaced in angle on an axis-aligned
+                          ellipse with semi-axes (a, b).
+* ``batched_ellipses`` -- 64 instances with N log-uniform in [2048, 32768].
+* ``serve_trace``      -- Poisson arrivals of compress / hmatvec requests.
+
+All arrays are float64, shape (N, d), C-contiguous (row-major).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+def uniform_line(n: int, seed: int = 1) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    return np.ascontiguousarray(rng.uniform(0.0, 1.0, size=(n, 1)))
+
+
+def star_curve(n: int) -> np.ndarray:
+    t = 2.0 * np.pi * np.arange(n, dtype=np.float64) / n
+    rho = 1.0 + 0.3 * np.cos(5.0 * t)
+    return np.ascontiguousarray(np.stack([rho * np.cos(t), rho * np.sin(t)], axis=1))
+
+
+def sphere(n: int, seed: int = 3) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    g = rng.standard_normal(size=(n, 3))
+    g /= np.linalg.norm(g, axis=1, keepdims=True)
+    return np.ascontiguousarray(g)
+
+
+def ellipse(n: int, a: float, b: float) -> np.ndarray:
+    t = 2.0 * np.pi * np.arange(n, dtype=np.float64) / n
+    return np.ascontiguousarray(np.stack([a * np.cos(t), b * np.sin(t)], axis=1))
+
+
+def grid_1d(n: int) -> np.ndarray:
+    """Cell-centred grid on [0, 1] (the paper's 1D worked example)."""
+    return np.ascontiguousarray(((np.arange(n) + 0.5) / n).reshape(n, 1))
+
+
+def random_points(n: int, dim: int, seed: int) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    return np.ascontiguousarray(rng.uniform(0.0, 1.0, size=(n, dim)))
+
+
+def gaussian_rhs(n: int, nrhs: int, seed: int, dtype=np.float64) -> np.ndarray:
+    """Column-major-friendly right-hand sides: returned as (nrhs, n) C order,
+    i.e. the transpose of an N x nrhs column-major matrix."""
+    rng = np.random.default_rng(seed)
+    return np.ascontiguousarray(rng.standard_normal(size=(nrhs, n)).astype(dtype))
+
+
+@dataclass
+class Instance:
+    points: np.ndarray
+    kernel: str          # "log" or "inv_r"
+    tree: str            # "index_binary" or "geometric"
+    adm: str             # "weak" or "strong"
+    leaf: int
+    rank: int = 0        # fixed rank k (0 -> tolerance mode)
+    tol: float = 0.0
+    r: int = 0           # columns per test matrix (k + p when 0)
+    p: int = 10
+    seed: int = 0        # test-matrix seed
+    name: str = ""
+
+
+def config(idx: int, n: int | None = None) -> Instance:
+    """The five benchmark workloads (index 0..2 are single compressions;
+    3 and 4 are built from the generators above by ``batched_ellipses`` and
+    ``serve_trace``).  ``n`` overrides the point count for reduced runs."""
+    if idx == 0:
+        N = 1024 if n is None else n
+        return Instance(uniform_line(N, 1), "log", "index_binary", "weak", 64,
+                        rank=20, r=30, seed=101, name=f"hodlr_line_N{N}")
+    if idx == 1:
+        N = 16384 if n is None else n
+        return Instance(star_curve(N), "log", "geometric", "strong", 64,
+                        tol=1e-8, r=48, seed=102, name=f"star_curve_N{N}")
+    if idx == 2:
+        N = 65536 if n is None else n
+        return Instance(sphere(N, 3), "inv_r", "geometric", "strong", 128,
+                        tol=1e-6, r=64, seed=103, name=f"sphere_N{N}")
+    raise ValueError(idx)
+
+
+def batched_ellipses(count: int = 64, seed: int = 4, nmin: int = 2048,
+                     nmax: int = 32768) -> list[Instance]:
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        N = int(round(math.exp(rng.uniform(math.log(nmin), math.log(nmax)))))
+        a, b = rng.uniform(0.5, 2.0, size=2)
+        out.append(Instance(ellipse(N, float(a), float(b)), "log", "geometric",
+                            "strong", 64, tol=1e-6, r=40, seed=104 + i,
+                            name=f"ellipse{i}_N{N}"))
+    return out
+
+
+@dataclass
+class Request:
+    t_arrival: float
+    kind: str                 # "compress" or "matvec"
+    geometry: str = ""        # compress: "curve" or "sphere"
+    n: int = 0                # compress: point count
+    nrhs: int = 0             # matvec: right-hand sides
+    target: int = -1          # matvec: index of a resident H-matrix
+    seed: int = 0
+    extra: dict = field(default_factory=dict)
+
+
+def serve_trace(count: int, rate_per_s: float, seed: int = 5,
+                n_resident: int = 8, nmin: int = 4096,
+                nmax: int = 65536) -> list[Request]:
+    """Poisson arrivals; 1 in 10 requests is a compression (curve or sphere,
+    N log-uniform in [nmin, nmax]), the rest are hmatvec applies with 1..64
+    right-hand sides on a uniformly chosen resident H-matrix."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for i in range(count):
+        t += rng.exponential(1.0 / rate_per_s)
+        if rng.uniform() < 0.1:
+            N = int(round(math.exp(rng.uniform(math.log(nmin), math.log(nmax)))))
+            geom = "curve" if rng.uniform() < 0.5 else "sphere"
+            out.append(Request(t, "compress", geometry=geom, n=N, seed=1000 + i))
+        else:
+            out.append(Request(t, "matvec", nrhs=int(rng.integers(1, 65)),
+                               target=int(rng.integers(0, n_resident)),
+                               seed=2000 + i))
+    return out
