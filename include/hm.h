@@ -1,0 +1,263 @@
+/*
+ * hm.h -- C ABI of the MI355X colored-peeling library (libhm.so).
+ *
+ * The library builds an H^1 representation of an N x N operator A that is
+ * reachable only through products with A and A* (Levitt & Martinsson,
+ * "Randomized compression of rank-structured matrices accelerated with graph
+ * coloring", arXiv 2205.03406, introduction: the user can evaluate
+ * Y = A Omega and Z = A* Psi; the partition comes from the geometry).
+ *
+ * Conventions for every entry point:
+ *   - Return value: HM_OK (0) or a negative hm_status.  Nothing aborts; on
+ *     error no handle is created and outputs are left untouched.  The
+ *     thread-local message of the last error is hm_last_error().
+ *   - Host pointers are marked "host", device pointers "device".  Device
+ *     buffers are ordinary HIP device allocations on the current device.
+ *   - Dense matrices are column-major with an explicit leading dimension.
+ *   - "Tree order" is the point order after the tree's permutation
+ *     (hm_tree_perm maps tree position -> original index); "original order"
+ *     is the caller's order.
+ *   - Streams are hipStream_t passed as void* (NULL = the default stream).
+ *     Work is enqueued on that stream; a call returns after enqueueing
+ *     unless stated otherwise.
+ *   - Handles are not thread-safe; distinct handles may be used from
+ *     distinct threads.
+ */
+#ifndef HM_H
+#define HM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int hm_status;
+#define HM_OK 0
+#define HM_E_ARG (-1)       /* invalid argument (null pointer, bad size or enum) */
+#define HM_E_NOMEM (-2)     /* host or device allocation failed */
+#define HM_E_DEVICE (-3)    /* a HIP call failed */
+#define HM_E_CALLBACK (-4)  /* the user black box returned nonzero */
+#define HM_E_NUMERIC (-5)   /* NaN or Inf in the samples */
+#define HM_E_STATE (-6)     /* handle not ready (e.g. tree not colored) */
+#define HM_E_SATURATED (-7) /* tolerance not reached within r - p columns */
+
+enum { HM_TREE_GEOMETRIC = 0, HM_TREE_INDEX_BINARY = 1 };
+enum { HM_ADM_STRONG = 0, HM_ADM_WEAK = 1 };
+enum { HM_F64 = 0, HM_F32 = 1 };
+enum { HM_PREC_F64 = 0, HM_PREC_MIXED = 1 };
+enum { HM_KERNEL_LOG = 0, HM_KERNEL_INV_R = 1 };
+enum { HM_ORDER_ORIGINAL = 0, HM_ORDER_TREE = 1 };
+enum { HM_LIST_NEIGHBOR = 0, HM_LIST_INTERACTION = 1 };
+
+typedef struct hm_tree hm_tree;
+typedef struct hm_hmatrix hm_hmatrix;
+
+const char *hm_last_error(void);
+
+/* ------------------------------------------------------------------ tree
+ * hm_build_tree: the box tree of the section "Rank-structured matrices"
+ * (every box bisected along each dimension, empty children omitted, boxes
+ * with more than leaf_size points split; fig:tree for the index-halving
+ * variant), its neighbor lists (same-level boxes whose closed cubes touch,
+ * the box itself included) and interaction lists (children of the parent's
+ * neighbors that are not neighbors), and the constraint incompatibility
+ * graphs of every level (def:incompatibility_graph, eq:h1constraints) and of
+ * the leaf level (section on extracting inadmissible blocks).
+ *
+ *   points     host, n x dim row-major FP64, copied (1 <= dim <= 3)
+ *   leaf_size  m >= 1
+ *   tree_kind  HM_TREE_GEOMETRIC: root = bounding cube of the points, integer
+ *              cell c = min(2^21-1, floor(((x-lo)/s) 2^21)), tree order =
+ *              stable sort by the interleaved cell bits (x lowest); a box that
+ *              stops splitting is carried unchanged to finer levels.
+ *              HM_TREE_INDEX_BINARY: points stably sorted by x, ranges halved
+ *              at lo + (hi-lo)/2 while longer than leaf_size (requires
+ *              HM_ADM_WEAK).
+ *   adm        HM_ADM_STRONG: interaction lists as above.  HM_ADM_WEAK
+ *              (HODLR): neighbors = {box}, interaction list = the other
+ *              children of the parent.
+ *   out        receives the handle; free with hm_tree_free.
+ */
+hm_status hm_build_tree(const double *points, int64_t n, int dim, int leaf_size, int tree_kind,
+                        int adm, hm_tree **out);
+void hm_tree_free(hm_tree *tree);
+
+/* levels are 0..nlevels-1; nlevels-1 is the leaf level L */
+hm_status hm_tree_info(const hm_tree *tree, int32_t *nlevels, int64_t *n, int32_t *dim);
+/* perm: host, n entries: perm[i] = original index of tree position i */
+hm_status hm_tree_perm(const hm_tree *tree, int64_t *perm);
+/* box ranges of one level: start (host, nbox+1; box b holds tree positions
+ * [start[b], start[b+1])), parent (host, nbox; box id at level-1, -1 at
+ * level 0), org (host, 3*nbox; integer cube origin in 2^-21 root units),
+ * blev (host, nbox; level whose cube size the box has).  Any output may be
+ * NULL; nbox is always written. */
+hm_status hm_tree_level(const hm_tree *tree, int level, int32_t *nbox, int64_t *start,
+                        int32_t *parent, int64_t *org, int32_t *blev);
+/* CSR list of one level (which = HM_LIST_*): nnz always written; ptr (host,
+ * nbox+1) and idx (host, nnz) written when non-NULL; lists ascending. */
+hm_status hm_tree_list(const hm_tree *tree, int level, int which, int64_t *nnz, int32_t *ptr,
+                       int32_t *idx);
+
+/* ------------------------------------------------------------------ graphs
+ * hm_incompat_graph: the constraint incompatibility graph of `level`
+ * (level = -1: the leaf graph).  Vertices are distinct constraint sets
+ * (active box beta, box set S) where the test matrix must equal a Gaussian
+ * block on beta and vanish on S minus {beta}; for an admissible pair (a, b)
+ * of the level, beta = b and S = children of the neighbors of a's parent
+ * (= neighbors of a plus its interaction list); for a leaf pair, beta = b and
+ * S = neighbors of a.  Two vertices are adjacent when the active box of one
+ * lies in the zero set of the other.  Vertex order: parents ascending, then
+ * active boxes ascending (leaf: row boxes ascending, then neighbors).
+ *
+ * Outputs point into memory owned by the tree (valid until hm_tree_free):
+ *   xadj (nv+1), adj (nadj) CSR adjacency, ascending;  vbox (nv) active box;
+ *   pair_a, pair_b (npairs) the pairs of the level (a ascending, then b
+ *   ascending), pair_v (npairs) the vertex of each pair.
+ */
+hm_status hm_incompat_graph(const hm_tree *tree, int level, int64_t *nv, int64_t *nadj,
+                            const int64_t **xadj, const int32_t **adj, const int32_t **vbox,
+                            int64_t *npairs, const int32_t **pair_a, const int32_t **pair_b,
+                            const int32_t **pair_v);
+
+/* hm_color: DSatur greedy coloring (alg:dsatur) of a CSR graph.  The next
+ * vertex is the uncolored one with the largest saturation (number of
+ * distinct colors among its neighbors), ties by larger degree, then lower
+ * id; it gets the smallest color not used by a neighbor.
+ *   xadj (host, nv+1), adj (host, xadj[nv]) symmetric adjacency
+ *   color (host, nv) output; ncolors output. */
+hm_status hm_color(int64_t nv, const int64_t *xadj, const int32_t *adj, int32_t *color,
+                   int32_t *ncolors);
+/* Colors every graph of the tree with hm_color and stores the result. */
+hm_status hm_tree_color(hm_tree *tree);
+/* Installs a caller-chosen coloring of one graph (checked for validity). */
+hm_status hm_tree_set_colors(hm_tree *tree, int level, const int32_t *color);
+/* The stored coloring (owned by the tree). */
+hm_status hm_tree_colors(const hm_tree *tree, int level, int32_t *ncolors, const int32_t **color);
+
+/* ------------------------------------------------------------------ black box
+ * The black box computes Y = A X (transpose = 0) or Y = A* X (transpose = 1)
+ * for a device block X of ncols columns, enqueued on `stream`.
+ *   dtype  HM_F64 or HM_F32 (X and Y element type)
+ *   order  the point order of the rows of X and Y the box expects
+ * It must not keep X or Y after returning; nonzero return = failure. */
+typedef int (*hm_apply_fn)(void *ctx, int transpose, int64_t n, int64_t ncols, int dtype,
+                           const void *X, int64_t ldx, void *Y, int64_t ldy, void *stream);
+
+typedef struct {
+  hm_apply_fn apply;
+  void *ctx;
+  int32_t order;     /* HM_ORDER_ORIGINAL or HM_ORDER_TREE */
+  int32_t symmetric; /* nonzero when A* = A: one call may serve both passes */
+  int32_t dtypes;    /* bit (1 << HM_F64) | (1 << HM_F32) of supported types */
+} hm_blackbox;
+
+/* Built-in black box: A(i,j) = K(x_i, x_j) generated on the fly from the
+ * tree's points, K = log|x-y| (HM_KERNEL_LOG) or 1/|x-y| (HM_KERNEL_INV_R),
+ * A(i,j) = 0 when x_i = x_j (the diagonal included).  Stands in for the fast
+ * black boxes of the experiments section.  Tree order, symmetric, FP64 and
+ * FP32 (FP32: kernel evaluated and accumulated on MFMA in FP32 from FP64
+ * point differences).  The ctx is owned by the tree. */
+hm_status hm_kernel_blackbox(hm_tree *tree, int kernel, hm_blackbox *out);
+/* Direct call of the built-in kernel apply: Y = K X (rows in `order`). */
+hm_status hm_kernel_apply(hm_tree *tree, int kernel, int64_t ncols, int dtype, const void *X,
+                          int64_t ldx, void *Y, int64_t ldy, int order, void *stream);
+
+/* Dense black box for tests and small operators: A is a device FP64 n x n
+ * column-major matrix (lda >= n) in `order`, not copied (must outlive every
+ * compression that uses it).  Y = A X or A* X by a tiled FP64 GEMM. */
+hm_status hm_dense_blackbox(const double *A, int64_t n, int64_t lda, int order, hm_blackbox *out);
+void hm_dense_blackbox_free(hm_blackbox *bb);
+
+/* ------------------------------------------------------------------ compression
+ * hm_compress: alg:h1_pseudocode.  For each sampled level (coarsest first):
+ * draw the colored Gaussian test matrices Omega, Psi (one N x r block per
+ * color; eq:neartestmatrices), apply the black box, subtract the levels
+ * already compressed (the level-truncated matrix), and recover every
+ * admissible pair (a, b): U = qr(Y(I_a, block), k), V = qr(Z(I_b, block), k)
+ * and B = (G2* U)^+ (G2* Y(I_a, block)) (V* G1)^+ (alg:compress_double_random).
+ * Then extract the leaf neighbor blocks with identity test matrices.
+ *
+ * qr(., k) is column-pivoted Householder QR truncated to k columns; in
+ * tolerance mode k = first j with |R_jj| <= tol |R_00|, capped at r - p
+ * (each cap hit is counted as saturation in hm_stats).
+ *
+ * Test-matrix entries: Philox4x32-10 keyed by seed, counter (tree row,
+ * column/2, color, 4*level + pass), two 53-bit uniforms, Box-Muller.
+ *
+ *   tree   colored (hm_tree_color) tree
+ *   bb     black box; its columns are padded to a multiple of 16
+ *   opts   see hm_compress_opts
+ *   out    the H-matrix (device resident), free with hm_hmatrix_free.
+ * The call synchronizes `stream` before returning.
+ */
+typedef struct {
+  int32_t rank;       /* fixed rank k > 0, or 0 for tolerance mode */
+  double tol;         /* relative per-block tolerance (rank == 0) */
+  int32_t oversample; /* p (default 10 when 0) */
+  int32_t r;          /* columns per test matrix (0: rank + oversample) */
+  int32_t prec;       /* HM_PREC_F64, or HM_PREC_MIXED: black box and peel in FP32,
+                         QR and coupling solves in FP64 */
+  int32_t flags;      /* bit 0: record stage times (adds device syncs) */
+  uint64_t seed;
+} hm_compress_opts;
+
+hm_status hm_compress(hm_tree *tree, const hm_blackbox *bb, const hm_compress_opts *opts,
+                      void *stream, hm_hmatrix **out);
+void hm_hmatrix_free(hm_hmatrix *H);
+
+/* hm_matvec: Y = H X (the H^1 apply: all admissible blocks U B V* plus the
+ * leaf neighbor blocks).  X, Y device, n x nrhs, dtype HM_F64 or HM_F32,
+ * rows in `order`.  Enqueued on stream. */
+hm_status hm_matvec(const hm_hmatrix *H, int64_t nrhs, int dtype, const void *X, int64_t ldx,
+                    void *Y, int64_t ldy, int order, void *stream);
+
+/* Device test matrix of one level and pass (0 = Omega, 1 = Psi) exactly as
+ * hm_compress draws it: out (device, n x ncolors*r, ld) in tree order. */
+hm_status hm_test_matrix(const hm_tree *tree, int level, int pass, int32_t r, uint64_t seed,
+                         int dtype, void *out, int64_t ld, void *stream);
+/* Raw Philox4x32-10: ctr (device, 4*count u32, counter i at 4i..4i+3),
+ * out (device, 4*count u32). */
+hm_status hm_philox4x32_10(const uint32_t *ctr, int64_t count, uint32_t key0, uint32_t key1,
+                           uint32_t *out, void *stream);
+
+typedef struct {
+  int32_t nlevels;
+  int32_t r;
+  int64_t n;
+  int64_t cols_A;            /* black-box columns through A */
+  int64_t cols_At;           /* ... and through A* */
+  int32_t colors[32];        /* colors per level (0: level not sampled) */
+  int32_t leaf_colors;
+  int32_t leaf_width;        /* m: columns per leaf color */
+  int32_t max_rank;
+  int64_t npairs;            /* admissible pairs over all levels */
+  int64_t nnear;             /* leaf neighbor pairs */
+  int64_t saturated;         /* rank caps hit */
+  int64_t nfloats;           /* stored values (U, B, V at their ranks, near blocks) */
+  double flops_blackbox;     /* 2 N^2 per black-box column */
+  double flops_peel;         /* level-truncated products subtracted */
+  double flops_qr;           /* pivoted QR + basis formation */
+  double flops_solve;        /* coupling solves */
+  double ms_total, ms_blackbox, ms_peel, ms_qr, ms_solve, ms_other; /* flags bit 0 */
+} hm_stats;
+hm_status hm_hmatrix_stats(const hm_hmatrix *H, hm_stats *out);
+
+/* Export for parity checks (host copies).  For `level`: npairs, then per
+ * pair the two ranks and the factors U (|a| x kU), B (kU x kV), V (|b| x kV)
+ * packed column-major one after another in pair order; sizes are returned
+ * when the buffers are NULL. */
+hm_status hm_hmatrix_export_level(const hm_hmatrix *H, int level, int64_t *npairs,
+                                  int32_t *pair_a, int32_t *pair_b, int32_t *rank_u,
+                                  int32_t *rank_v, int64_t *size_u, int64_t *size_b,
+                                  int64_t *size_v, double *U, double *B, double *V);
+/* Leaf neighbor blocks: pairs (a, b) in leaf-pair order, blocks packed
+ * column-major |a| x |b|. */
+hm_status hm_hmatrix_export_near(const hm_hmatrix *H, int64_t *npairs, int32_t *pair_a,
+                                 int32_t *pair_b, int64_t *size, double *D);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HM_H */

@@ -1,0 +1,393 @@
+"""Thin Python binding of libhm (include/hm.h): argument marshalling only.
+
+Every step of colored peeling runs in the native library; this module only
+converts arguments.  Device buffers are torch CUDA (HIP) tensors holding
+column-major N x ncols blocks: a tensor of shape (N, ncols) with strides
+(1, ld), e.g. ``torch.empty(ncols, N, device="cuda").t()``.  Streams default
+to torch's current stream.
+
+Importing this module loads ``libhm.so`` from the package directory and
+raises if it is missing: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "libhm.so")
+
+HM_OK = 0
+HM_TREE_GEOMETRIC, HM_TREE_INDEX_BINARY = 0, 1
+HM_ADM_STRONG, HM_ADM_WEAK = 0, 1
+HM_F64, HM_F32 = 0, 1
+HM_PREC_F64, HM_PREC_MIXED = 0, 1
+HM_KERNEL_LOG, HM_KERNEL_INV_R = 0, 1
+HM_ORDER_ORIGINAL, HM_ORDER_TREE = 0, 1
+HM_LIST_NEIGHBOR, HM_LIST_INTERACTION = 0, 1
+
+EXPORTED = [
+    "hm_last_error", "hm_build_tree", "hm_tree_free", "hm_tree_info", "hm_tree_perm",
+    "hm_tree_level", "hm_tree_list", "hm_incompat_graph", "hm_color", "hm_tree_color",
+    "hm_tree_set_colors", "hm_tree_colors", "hm_kernel_blackbox", "hm_kernel_apply",
+    "hm_dense_blackbox", "hm_dense_blackbox_free", "hm_compress", "hm_hmatrix_free",
+    "hm_matvec", "hm_test_matrix", "hm_philox4x32_10", "hm_hmatrix_stats",
+    "hm_hmatrix_export_level", "hm_hmatrix_export_near",
+]
+
+
+class HMError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("hm error %d: %s" % (code, msg))
+        self.code = code
+
+
+APPLY_FN = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int, C.c_int64, C.c_int64, C.c_int,
+                       C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p)
+
+
+class BlackBox(C.Structure):
+    _fields_ = [("apply", APPLY_FN), ("ctx", C.c_void_p), ("order", C.c_int32),
+                ("symmetric", C.c_int32), ("dtypes", C.c_int32)]
+
+
+class Opts(C.Structure):
+    _fields_ = [("rank", C.c_int32), ("tol", C.c_double), ("oversample", C.c_int32),
+                ("r", C.c_int32), ("prec", C.c_int32), ("flags", C.c_int32),
+                ("seed", C.c_uint64)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("nlevels", C.c_int32), ("r", C.c_int32), ("n", C.c_int64),
+                ("cols_A", C.c_int64), ("cols_At", C.c_int64), ("colors", C.c_int32 * 32),
+                ("leaf_colors", C.c_int32), ("leaf_width", C.c_int32), ("max_rank", C.c_int32),
+                ("npairs", C.c_int64), ("nnear", C.c_int64), ("saturated", C.c_int64),
+                ("nfloats", C.c_int64), ("flops_blackbox", C.c_double),
+                ("flops_peel", C.c_double), ("flops_qr", C.c_double),
+                ("flops_solve", C.c_double), ("ms_total", C.c_double),
+                ("ms_blackbox", C.c_double), ("ms_peel", C.c_double), ("ms_qr", C.c_double),
+                ("ms_solve", C.c_double), ("ms_other", C.c_double)]
+
+    def as_dict(self):
+        d = {}
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            d[name] = list(v) if name == "colors" else v
+        return d
+
+
+def _load():
+    if not os.path.exists(_SO):
+        raise ImportError("libhm.so is not built (run __graft_entry__.build() or "
+                          "python -m paper_2205_03406_amd.build)")
+    lib = C.CDLL(_SO)
+    P, I, I64, D = C.c_void_p, C.c_int, C.c_int64, C.c_double
+    pp = C.POINTER(C.c_void_p)
+    lib.hm_last_error.restype = C.c_char_p
+    sigs = {
+        "hm_build_tree": [P, I64, I, I, I, I, pp],
+        "hm_tree_free": [P],
+        "hm_tree_info": [P, P, P, P],
+        "hm_tree_perm": [P, P],
+        "hm_tree_level": [P, I, P, P, P, P, P],
+        "hm_tree_list": [P, I, I, P, P, P],
+        "hm_incompat_graph": [P, I, P, P, pp, pp, pp, P, pp, pp, pp],
+        "hm_color": [I64, P, P, P, P],
+        "hm_tree_color": [P],
+        "hm_tree_set_colors": [P, I, P],
+        "hm_tree_colors": [P, I, P, pp],
+        "hm_kernel_blackbox": [P, I, C.POINTER(BlackBox)],
+        "hm_kernel_apply": [P, I, I64, I, P, I64, P, I64, I, P],
+        "hm_dense_blackbox": [P, I64, I64, I, C.POINTER(BlackBox)],
+        "hm_dense_blackbox_free": [C.POINTER(BlackBox)],
+        "hm_compress": [P, C.POINTER(BlackBox), C.POINTER(Opts), P, pp],
+        "hm_hmatrix_free": [P],
+        "hm_matvec": [P, I64, I, P, I64, P, I64, I, P],
+        "hm_test_matrix": [P, I, I, C.c_int32, C.c_uint64, I, P, I64, P],
+        "hm_philox4x32_10": [P, I64, C.c_uint32, C.c_uint32, P, P],
+        "hm_hmatrix_stats": [P, C.POINTER(Stats)],
+        "hm_hmatrix_export_level": [P, I, P, P, P, P, P, P, P, P, P, P, P],
+        "hm_hmatrix_export_near": [P, P, P, P, P, P],
+    }
+    for name, args in sigs.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        if name in ("hm_tree_free", "hm_hmatrix_free", "hm_dense_blackbox_free"):
+            f.restype = None
+        else:
+            f.restype = C.c_int
+    return lib
+
+
+_lib = _load()
+
+
+def lib():
+    return _lib
+
+
+def _check(rc):
+    if rc != HM_OK:
+        raise HMError(rc, _lib.hm_last_error().decode())
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _colmajor(t, name):
+    """(pointer, ld, ncols, dtype code) of an (N, ncols) column-major tensor."""
+    import torch
+    if t.dim() == 1:
+        return C.c_void_p(t.data_ptr()), t.shape[0], 1, _dtype(t)
+    if t.stride(0) != 1 and t.shape[1] > 1:
+        raise ValueError("%s must be column-major: shape (N, ncols), stride (1, ld)" % name)
+    ld = t.stride(1) if t.shape[1] > 1 else t.shape[0]
+    return C.c_void_p(t.data_ptr()), ld, t.shape[1], _dtype(t)
+
+
+def _dtype(t):
+    import torch
+    if t.dtype == torch.float64:
+        return HM_F64
+    if t.dtype == torch.float32:
+        return HM_F32
+    raise TypeError("dtype must be float64 or float32")
+
+
+def colmajor(n, ncols, dtype=None, device="cuda", fill=None):
+    """An (n, ncols) column-major device tensor (ld = n)."""
+    import torch
+    dtype = dtype or torch.float64
+    t = torch.empty(ncols, n, dtype=dtype, device=device).t()
+    if fill is not None:
+        t.fill_(fill)
+    return t
+
+
+class Graph:
+    def __init__(self, nv, xadj, adj, vbox, pa, pb, pv, color=None, ncolors=0):
+        self.nv, self.xadj, self.adj, self.vbox = nv, xadj, adj, vbox
+        self.pair_a, self.pair_b, self.pair_v = pa, pb, pv
+        self.color, self.ncolors = color, ncolors
+
+    @property
+    def nedges(self):
+        return int(self.xadj[-1]) // 2
+
+
+class Tree:
+    """hm_build_tree handle (box tree, lists, constraint graphs)."""
+
+    def __init__(self, points, leaf, kind="geometric", adm="strong"):
+        pts = np.ascontiguousarray(points, np.float64)
+        if pts.ndim == 1:
+            pts = pts.reshape(-1, 1)
+        n, dim = pts.shape
+        h = C.c_void_p()
+        _check(_lib.hm_build_tree(_ptr(pts), n, dim, leaf,
+                                  HM_TREE_INDEX_BINARY if kind == "index_binary" else HM_TREE_GEOMETRIC,
+                                  HM_ADM_WEAK if adm == "weak" else HM_ADM_STRONG, C.byref(h)))
+        self.h = h
+        self.n, self.dim, self.leaf = n, dim, leaf
+        nl = C.c_int32()
+        _check(_lib.hm_tree_info(h, C.byref(nl), None, None))
+        self.nlev = nl.value
+        self.L = self.nlev - 1
+        self._bbs = []
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.hm_tree_free(self.h)
+            self.h = None
+
+    def perm(self):
+        out = np.zeros(self.n, np.int64)
+        _check(_lib.hm_tree_perm(self.h, _ptr(out)))
+        return out
+
+    def level(self, l):
+        nb = C.c_int32()
+        _check(_lib.hm_tree_level(self.h, l, C.byref(nb), None, None, None, None))
+        nb = nb.value
+        start = np.zeros(nb + 1, np.int64)
+        parent = np.zeros(nb, np.int32)
+        org = np.zeros(3 * nb, np.int64)
+        blev = np.zeros(nb, np.int32)
+        _check(_lib.hm_tree_level(self.h, l, None, _ptr(start), _ptr(parent), _ptr(org), _ptr(blev)))
+        return start, parent, org.reshape(nb, 3), blev
+
+    def list(self, l, which):
+        nnz = C.c_int64()
+        _check(_lib.hm_tree_list(self.h, l, which, C.byref(nnz), None, None))
+        nb = len(self.level(l)[1])
+        ptr = np.zeros(nb + 1, np.int32)
+        idx = np.zeros(max(nnz.value, 1), np.int32)
+        _check(_lib.hm_tree_list(self.h, l, which, None, _ptr(ptr), _ptr(idx)))
+        return ptr, idx[:nnz.value]
+
+    def graph(self, level):
+        """level = -1: leaf graph."""
+        nv, nadj, npairs = C.c_int64(), C.c_int64(), C.c_int64()
+        xadj, adj, vbox, pa, pb, pv = (C.c_void_p() for _ in range(6))
+        _check(_lib.hm_incompat_graph(self.h, level, C.byref(nv), C.byref(nadj), C.byref(xadj),
+                                      C.byref(adj), C.byref(vbox), C.byref(npairs), C.byref(pa),
+                                      C.byref(pb), C.byref(pv)))
+
+        def arr(p, n, t):
+            if n == 0 or not p.value:
+                return np.zeros(0, t)
+            return np.ctypeslib.as_array(C.cast(p, C.POINTER(np.ctypeslib.as_ctypes_type(t))),
+                                         shape=(n,)).copy()
+        g = Graph(nv.value, arr(xadj, nv.value + 1, np.int64), arr(adj, nadj.value, np.int32),
+                  arr(vbox, nv.value, np.int32), arr(pa, npairs.value, np.int32),
+                  arr(pb, npairs.value, np.int32), arr(pv, npairs.value, np.int32))
+        if nv.value == 0:
+            g.xadj = np.zeros(1, np.int64)
+        nc, col = C.c_int32(), C.c_void_p()
+        if _lib.hm_tree_colors(self.h, level, C.byref(nc), C.byref(col)) == HM_OK:
+            g.ncolors = nc.value
+            g.color = arr(col, nv.value, np.int32)
+        return g
+
+    def color(self):
+        _check(_lib.hm_tree_color(self.h))
+        return self
+
+    def set_colors(self, level, colors):
+        c = np.ascontiguousarray(colors, np.int32)
+        _check(_lib.hm_tree_set_colors(self.h, level, _ptr(c)))
+
+    def kernel_blackbox(self, kernel="log"):
+        bb = BlackBox()
+        _check(_lib.hm_kernel_blackbox(self.h, HM_KERNEL_INV_R if kernel == "inv_r" else HM_KERNEL_LOG,
+                                       C.byref(bb)))
+        self._bbs.append(bb)
+        return bb
+
+    def kernel_apply(self, kernel, X, Y, order=HM_ORDER_TREE, stream=None):
+        px, ldx, nc, dt = _colmajor(X, "X")
+        py, ldy, nc2, dt2 = _colmajor(Y, "Y")
+        if nc != nc2 or dt != dt2:
+            raise ValueError("X and Y shapes/dtypes differ")
+        _check(_lib.hm_kernel_apply(self.h, HM_KERNEL_INV_R if kernel == "inv_r" else HM_KERNEL_LOG,
+                                    nc, dt, px, ldx, py, ldy, order, _stream(stream)))
+
+    def test_matrix(self, level, pas, r, seed, out, stream=None):
+        po, ld, nc, dt = _colmajor(out, "out")
+        _check(_lib.hm_test_matrix(self.h, level, pas, r, seed, dt, po, ld, _stream(stream)))
+
+
+def color(xadj, adj):
+    """DSatur (hm_color) of a CSR graph; returns (colors, ncolors)."""
+    xadj = np.ascontiguousarray(xadj, np.int64)
+    adj = np.ascontiguousarray(adj if len(adj) else np.zeros(1, np.int32), np.int32)
+    nv = len(xadj) - 1
+    col = np.zeros(max(nv, 1), np.int32)
+    nc = C.c_int32()
+    _check(_lib.hm_color(nv, _ptr(xadj), _ptr(adj), _ptr(col), C.byref(nc)))
+    return col[:nv], nc.value
+
+
+def dense_blackbox(A, order=HM_ORDER_ORIGINAL):
+    """Dense FP64 black box over a device (n, n) column-major tensor A (kept
+    alive by the returned object)."""
+    pa, lda, n2, dt = _colmajor(A, "A")
+    if dt != HM_F64:
+        raise TypeError("dense black box is FP64")
+    bb = BlackBox()
+    _check(_lib.hm_dense_blackbox(pa, A.shape[0], lda, order, C.byref(bb)))
+    bb._keep = A
+    return bb
+
+
+def philox(ctr, key0, key1, out, stream=None):
+    _check(_lib.hm_philox4x32_10(C.c_void_p(ctr.data_ptr()), ctr.numel() // 4, key0, key1,
+                                 C.c_void_p(out.data_ptr()), _stream(stream)))
+
+
+class HMatrix:
+    def __init__(self, h, tree):
+        self.h = h
+        self.tree = tree
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.hm_hmatrix_free(self.h)
+            self.h = None
+
+    def stats(self):
+        s = Stats()
+        _check(_lib.hm_hmatrix_stats(self.h, C.byref(s)))
+        return s.as_dict()
+
+    def matvec(self, X, Y, order=HM_ORDER_ORIGINAL, stream=None):
+        px, ldx, nc, dt = _colmajor(X, "X")
+        py, ldy, nc2, dt2 = _colmajor(Y, "Y")
+        if nc != nc2 or dt != dt2:
+            raise ValueError("X and Y shapes/dtypes differ")
+        _check(_lib.hm_matvec(self.h, nc, dt, px, ldx, py, ldy, order, _stream(stream)))
+
+    def export_level(self, level):
+        """List of (a, b, U, B, V) in pair order (host float64 arrays)."""
+        npairs, su, sb, sv = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64()
+        _check(_lib.hm_hmatrix_export_level(self.h, level, C.byref(npairs), None, None, None, None,
+                                            C.byref(su), C.byref(sb), C.byref(sv), None, None, None))
+        np_ = npairs.value
+        if np_ == 0:
+            return []
+        pa, pb = np.zeros(np_, np.int32), np.zeros(np_, np.int32)
+        ru, rv = np.zeros(np_, np.int32), np.zeros(np_, np.int32)
+        U, B, V = np.zeros(max(su.value, 1)), np.zeros(max(sb.value, 1)), np.zeros(max(sv.value, 1))
+        _check(_lib.hm_hmatrix_export_level(self.h, level, None, _ptr(pa), _ptr(pb), _ptr(ru),
+                                            _ptr(rv), None, None, None, _ptr(U), _ptr(B), _ptr(V)))
+        start = self.tree.level(level)[0]
+        out = []
+        ou = ob = ov = 0
+        for q in range(np_):
+            ma = int(start[pa[q] + 1] - start[pa[q]])
+            mb = int(start[pb[q] + 1] - start[pb[q]])
+            ku, kv = int(ru[q]), int(rv[q])
+            Uq = U[ou:ou + ma * ku].reshape(ku, ma).T
+            Bq = B[ob:ob + ku * kv].reshape(kv, ku).T
+            Vq = V[ov:ov + mb * kv].reshape(kv, mb).T
+            out.append((int(pa[q]), int(pb[q]), Uq, Bq, Vq))
+            ou += ma * ku
+            ob += ku * kv
+            ov += mb * kv
+        return out
+
+    def export_near(self):
+        npairs, size = C.c_int64(), C.c_int64()
+        _check(_lib.hm_hmatrix_export_near(self.h, C.byref(npairs), None, None, C.byref(size), None))
+        np_ = npairs.value
+        pa, pb = np.zeros(max(np_, 1), np.int32), np.zeros(max(np_, 1), np.int32)
+        D = np.zeros(max(size.value, 1))
+        _check(_lib.hm_hmatrix_export_near(self.h, None, _ptr(pa), _ptr(pb), None, _ptr(D)))
+        start = self.tree.level(self.tree.L)[0]
+        out, o = [], 0
+        for q in range(np_):
+            ma = int(start[pa[q] + 1] - start[pa[q]])
+            mb = int(start[pb[q] + 1] - start[pb[q]])
+            out.append((int(pa[q]), int(pb[q]), D[o:o + ma * mb].reshape(mb, ma).T))
+            o += ma * mb
+        return out
+
+
+def compress(tree: Tree, bb: BlackBox, rank=0, tol=0.0, r=0, p=10, prec=HM_PREC_F64, seed=0,
+             timing=False, stream=None) -> HMatrix:
+    o = Opts(rank=rank, tol=tol, oversample=p, r=r, prec=prec, flags=1 if timing else 0, seed=seed)
+    h = C.c_void_p()
+    _check(_lib.hm_compress(tree.h, C.byref(bb), C.byref(o), _stream(stream), C.byref(h)))
+    return HMatrix(h, tree)

@@ -1,0 +1,1129 @@
+// libhm engine: the C ABI of include/hm.h and the level pipeline of
+// alg:h1_pseudocode on one GPU.
+//
+// Per sampled level l (coarsest first), on one stream:
+//   1. draw [Omega | Psi] (N x 2*cpad, tree order; FP64, or FP32 in the mixed
+//      path) -- Philox4x32-10 + Box-Muller, colored by the level's graph;
+//   2. black box: [Y | Z] = [A Omega | A* Psi]; one call when A* = A;
+//   3. peel: subtract the levels already compressed (grouped low-rank
+//      products, deterministic, no atomics);
+//   4. recover every admissible pair: C = G2^T Y_ab, pivoted QR bases for U
+//      and V, coupling solve B, W = U B -- all FP64;
+// then the leaf pass with identity test matrices.  Ranks live on the device
+// (tolerance mode needs no host round trip); factor slots are sized for the
+// largest rank the level can produce.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "hm_internal.h"
+#include "kernels.h"
+
+namespace hm {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+hm_status fail(hm_status code, const std::string &msg) {
+  g_last_error = msg;
+  return code;
+}
+
+#define HIP_TRY(x)                                                                     \
+  do {                                                                                 \
+    hipError_t e_ = (x);                                                               \
+    if (e_ != hipSuccess)                                                              \
+      throw Error{HM_E_DEVICE, std::string(#x) + ": " + hipGetErrorString(e_)};        \
+  } while (0)
+
+#define LAUNCH_CHECK()                                                                 \
+  do {                                                                                 \
+    hipError_t e_ = hipGetLastError();                                                 \
+    if (e_ != hipSuccess)                                                              \
+      throw Error{HM_E_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e_)}; \
+  } while (0)
+
+// ------------------------------------------------------------------ device buffers
+struct DBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+  DBuf() = default;
+  DBuf(const DBuf &) = delete;
+  DBuf &operator=(const DBuf &) = delete;
+  DBuf(DBuf &&o) noexcept : p(o.p), bytes(o.bytes) {
+    o.p = nullptr;
+    o.bytes = 0;
+  }
+  DBuf &operator=(DBuf &&o) noexcept {
+    release();
+    p = o.p;
+    bytes = o.bytes;
+    o.p = nullptr;
+    o.bytes = 0;
+    return *this;
+  }
+  ~DBuf() { release(); }
+  void alloc(size_t b) {
+    release();
+    if (b == 0) b = 64;
+    if (hipMalloc(&p, b) != hipSuccess) {
+      p = nullptr;
+      (void)hipGetLastError();
+      throw Error{HM_E_NOMEM, "device allocation of " + std::to_string(b) + " bytes failed"};
+    }
+    bytes = b;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <class T>
+  T *as() const {
+    return (T *)p;
+  }
+};
+
+template <class T>
+void upload(DBuf &d, const std::vector<T> &v, hipStream_t s) {
+  d.alloc(v.size() * sizeof(T));
+  if (!v.empty())
+    HIP_TRY(hipMemcpyAsync(d.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+}
+
+inline int64_t pad16(int64_t x) { return (x + 15) / 16 * 16; }
+
+// ------------------------------------------------------------------ device tree
+struct DeviceTree {
+  int device = -1;
+  DBuf pts;                    // dim x n, tree order
+  DBuf perm;                   // n (tree -> original)
+  std::vector<DBuf> rowbox;    // per level: box of every row
+  std::vector<DBuf> start;     // per level: box starts
+};
+
+DeviceTree &device_tree(Tree &T, hipStream_t s) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (T.dev && T.dev->device == dev) return *T.dev;
+  auto D = std::make_shared<DeviceTree>();
+  D->device = dev;
+  std::vector<double> soa((size_t)T.dim * T.n);
+  for (int64_t i = 0; i < T.n; ++i)
+    for (int d = 0; d < T.dim; ++d) soa[(size_t)d * T.n + i] = T.pts[T.perm[i] * T.dim + d];
+  upload(D->pts, soa, s);
+  upload(D->perm, T.perm, s);
+  D->rowbox.resize(T.nlev());
+  D->start.resize(T.nlev());
+  for (int l = 0; l < T.nlev(); ++l) {
+    std::vector<int32_t> rb(T.n);
+    const Level &Lv = T.lev[l];
+    for (int b = 0; b < Lv.nbox(); ++b)
+      for (int64_t i = Lv.start[b]; i < Lv.start[b + 1]; ++i) rb[i] = b;
+    upload(D->rowbox[l], rb, s);
+    upload(D->start[l], Lv.start, s);
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  T.dev = D;
+  return *D;
+}
+
+// ------------------------------------------------------------------ black boxes
+struct KernelBB {
+  Tree *tree;
+  int kernel;
+};
+
+int kernel_bb_apply(void *ctx, int /*transpose*/, int64_t n, int64_t ncols, int dtype,
+                    const void *X, int64_t ldx, void *Y, int64_t ldy, void *stream) {
+  KernelBB *k = (KernelBB *)ctx;
+  if (!k || !k->tree || !k->tree->dev || n != k->tree->n) return 1;
+  launch_kapply(k->kernel, k->tree->dim, n, k->tree->dev->pts.as<double>(), ncols,
+                dtype == HM_F32, X, ldx, Y, ldy, (hipStream_t)stream);
+  return hipGetLastError() == hipSuccess ? 0 : 2;
+}
+
+struct DenseBB {
+  const double *A;
+  int64_t n, lda;
+};
+
+int dense_bb_apply(void *ctx, int transpose, int64_t n, int64_t ncols, int dtype, const void *X,
+                   int64_t ldx, void *Y, int64_t ldy, void *stream) {
+  DenseBB *d = (DenseBB *)ctx;
+  if (!d || n != d->n || dtype != HM_F64) return 1;
+  launch_dense_gemm(n, d->A, d->lda, transpose != 0, ncols, (const double *)X, ldx, (double *)Y,
+                    ldy, (hipStream_t)stream);
+  return hipGetLastError() == hipSuccess ? 0 : 2;
+}
+
+}  // namespace hm
+
+// ------------------------------------------------------------------ the H-matrix
+struct hm_hmatrix {
+  struct Lv {
+    int level = 0;
+    int64_t np = 0;   // pairs
+    int64_t g0 = 0;   // first global pair index
+    std::vector<int32_t> pa, pb;
+    std::vector<int64_t> offU, offV, offW, offB;
+    hm::DBuf projA, chunksA, entriesA, projT, chunksT, entriesT;
+    int32_t nchA = 0, nchT = 0;
+  };
+  int device = 0;
+  int64_t n = 0;
+  int nlev = 0;
+  int32_t r = 0, kmax = 0;
+  int64_t np_total = 0;
+  std::vector<std::vector<int64_t>> start;  // host box starts per level
+  hm::DBuf perm;
+  hm::DBuf U, V, W, B, Vf, Wf, D;
+  hm::DBuf ranks;                  // [0, np): rank_u, [np, 2np): rank_v
+  std::vector<int32_t> h_ranks;
+  std::vector<Lv> lv;
+  // leaf neighbor blocks
+  std::vector<int32_t> na, nb;
+  std::vector<int64_t> offD;
+  hm::DBuf nchunks, nentries;
+  int32_t nnch = 0;
+  int64_t max_np = 0;
+  hm_stats stats{};
+};
+
+namespace hm {
+
+namespace {
+
+// Pair-slot layout and apply plans of one level.
+void build_level_plans(hm_hmatrix &H, hm_hmatrix::Lv &L, const Level &Lev, hipStream_t s) {
+  const int64_t np = L.np;
+  const int32_t kmax = H.kmax;
+  auto sz = [&](int b) { return (int32_t)(Lev.start[b + 1] - Lev.start[b]); };
+  // A orientation: project with V over beta, expand with W into alpha rows
+  std::vector<ProjJob> pa(np), pt(np);
+  for (int64_t p = 0; p < np; ++p) {
+    pa[p] = ProjJob{Lev.start[L.pb[p]], L.offV[p], sz(L.pb[p]), (int32_t)(H.np_total + L.g0 + p),
+                    (int32_t)p, 0};
+    pt[p] = ProjJob{Lev.start[L.pa[p]], L.offW[p], sz(L.pa[p]), (int32_t)(H.np_total + L.g0 + p),
+                    (int32_t)p, 0};
+  }
+  auto expand = [&](bool trans, std::vector<ExpandChunk> &ch, std::vector<ExpandEntry> &en) {
+    std::vector<int64_t> order(np);
+    for (int64_t p = 0; p < np; ++p) order[p] = p;
+    const std::vector<int32_t> &rowbox = trans ? L.pb : L.pa;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int64_t a, int64_t b) { return rowbox[a] < rowbox[b]; });
+    int64_t i = 0;
+    while (i < np) {
+      int64_t j = i;
+      const int rb = rowbox[order[i]];
+      while (j < np && rowbox[order[j]] == rb) ++j;
+      const int32_t m = sz(rb);
+      for (int32_t off = 0; off < m; off += 64) {
+        ExpandChunk c{Lev.start[rb] + off, std::min<int32_t>(64, m - off), (int32_t)en.size(), 0, 0};
+        for (int64_t q = i; q < j; ++q) {
+          const int64_t p = order[q];
+          en.push_back(ExpandEntry{trans ? L.offV[p] : L.offW[p], m, off,
+                                   (int32_t)(H.np_total + L.g0 + p), (int32_t)p});
+        }
+        c.last = (int32_t)en.size();
+        ch.push_back(c);
+      }
+      i = j;
+    }
+  };
+  std::vector<ExpandChunk> ca, ct;
+  std::vector<ExpandEntry> ea, et;
+  expand(false, ca, ea);
+  expand(true, ct, et);
+  upload(L.projA, pa, s);
+  upload(L.projT, pt, s);
+  upload(L.chunksA, ca, s);
+  upload(L.entriesA, ea, s);
+  upload(L.chunksT, ct, s);
+  upload(L.entriesT, et, s);
+  L.nchA = (int32_t)ca.size();
+  L.nchT = (int32_t)ct.size();
+}
+
+// Y +=/-= (levels of H in `li_end`) X, one level at a time; T is scratch of
+// tcap elements.
+void apply_levels(const hm_hmatrix &H, size_t li_end, bool trans, bool f32, const void *X,
+                  int64_t ldx, int64_t ncols, void *Y, int64_t ldy, double sign, void *T,
+                  int64_t tcap, hipStream_t s) {
+  const size_t es = f32 ? 4 : 8;
+  const void *Rp = trans ? (f32 ? H.Wf.p : H.W.p) : (f32 ? H.Vf.p : H.V.p);
+  const void *Lp = trans ? (f32 ? H.Vf.p : H.V.p) : (f32 ? H.Wf.p : H.W.p);
+  for (size_t li = 0; li < li_end; ++li) {
+    const hm_hmatrix::Lv &L = H.lv[li];
+    if (L.np == 0) continue;
+    int64_t cw = tcap / (L.np * H.kmax);
+    if (cw < 1) throw Error{HM_E_NOMEM, "low-rank scratch too small"};
+    cw = std::min<int64_t>(cw, ncols);
+    if (cw < ncols) cw = std::max<int64_t>(64, cw / 64 * 64);
+    for (int64_t c0 = 0; c0 < ncols; c0 += cw) {
+      const int64_t w = std::min(cw, ncols - c0);
+      const int64_t tstride = (int64_t)H.kmax * w;
+      launch_lr_project((int32_t)L.np, (trans ? L.projT : L.projA).as<ProjJob>(), H.kmax, tstride,
+                        H.ranks.as<int32_t>(), f32, Rp, (const char *)X + c0 * ldx * es, ldx, w, T,
+                        s);
+      LAUNCH_CHECK();
+      launch_lr_expand(trans ? L.nchT : L.nchA, (trans ? L.chunksT : L.chunksA).as<ExpandChunk>(),
+                       (trans ? L.entriesT : L.entriesA).as<ExpandEntry>(), H.kmax, tstride,
+                       H.ranks.as<int32_t>(), f32, Lp, T, w, sign, (char *)Y + c0 * ldy * es,
+                       ldy, s);
+      LAUNCH_CHECK();
+    }
+  }
+}
+
+int64_t tscratch_elems(const hm_hmatrix &H, int64_t ncols) {
+  // enough for one level at full width, capped at 64 M elements
+  int64_t need = H.max_np * H.kmax * std::max<int64_t>(ncols, 1);
+  int64_t cap = int64_t(64) << 20;
+  int64_t minimum = H.max_np * H.kmax * 64;
+  return std::max<int64_t>(std::min(need, cap), minimum);
+}
+
+struct Events {
+  bool on = false;
+  std::vector<std::pair<hipEvent_t, int>> marks;  // event, stage id
+  hipStream_t s = nullptr;
+  void mark(int stage) {
+    if (!on) return;
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return;
+    (void)hipEventRecord(e, s);
+    marks.push_back({e, stage});
+  }
+  ~Events() {
+    for (auto &m : marks) (void)hipEventDestroy(m.first);
+  }
+};
+
+hm_status call_blackbox(const hm_blackbox &bb, int transpose, int64_t n, int64_t ncols, bool f32,
+                        const void *X, int64_t ldx, void *Y, int64_t ldy, const DeviceTree &D,
+                        DBuf &tmpx, DBuf &tmpy, hipStream_t s) {
+  const int dtype = f32 ? HM_F32 : HM_F64;
+  const size_t es = f32 ? 4 : 8;
+  if (bb.order == HM_ORDER_TREE) {
+    const int rc = bb.apply(bb.ctx, transpose, n, ncols, dtype, X, ldx, Y, ldy, (void *)s);
+    if (rc != 0) throw Error{HM_E_CALLBACK, "black box returned " + std::to_string(rc)};
+    return HM_OK;
+  }
+  const size_t need = (size_t)n * ncols * es;
+  if (tmpx.bytes < need) tmpx.alloc(need);
+  if (tmpy.bytes < need) tmpy.alloc(need);
+  launch_permute_rows(n, ncols, D.perm.as<int64_t>(), true, f32, X, ldx, tmpx.p, n, s);
+  LAUNCH_CHECK();
+  const int rc = bb.apply(bb.ctx, transpose, n, ncols, dtype, tmpx.p, n, tmpy.p, n, (void *)s);
+  if (rc != 0) throw Error{HM_E_CALLBACK, "black box returned " + std::to_string(rc)};
+  launch_permute_rows(n, ncols, D.perm.as<int64_t>(), false, f32, tmpy.p, n, Y, ldy, s);
+  LAUNCH_CHECK();
+  return HM_OK;
+}
+
+double qr_flops(int64_t m, int64_t r, int64_t k) {
+  double f = 2.0 * m * r;  // initial norms
+  for (int64_t j = 0; j < k; ++j) f += 2.0 * (m - j) + 6.0 * (m - j) * (r - j - 1);
+  for (int64_t j = 0; j < k; ++j) f += 4.0 * (m - j) * (k - j);
+  return f;
+}
+
+hm_status compress_impl(Tree &T, const hm_blackbox &bb, const hm_compress_opts &o,
+                        hipStream_t s, hm_hmatrix **out) {
+  // ---------------- options
+  if (T.n <= 0) return fail(HM_E_ARG, "empty tree");
+  for (const Graph &G : T.graphs)
+    if (!G.colored && G.nv() > 0) return fail(HM_E_STATE, "tree is not colored (hm_tree_color)");
+  const int p = o.oversample > 0 ? o.oversample : 10;
+  const int kfix = o.rank > 0 ? o.rank : 0;
+  if (kfix == 0 && !(o.tol > 0)) return fail(HM_E_ARG, "need rank > 0 or tol > 0");
+  const int r = o.r > 0 ? o.r : (kfix > 0 ? kfix + p : 0);
+  if (r <= 0) return fail(HM_E_ARG, "tolerance mode needs r > 0");
+  if (r > 64) return fail(HM_E_ARG, "r must be <= 64");
+  if (kfix == 0 && r - p < 1) return fail(HM_E_ARG, "r - p must be >= 1 in tolerance mode");
+  const bool mixed = o.prec == HM_PREC_MIXED;
+  if (mixed && !(bb.dtypes & (1 << HM_F32))) return fail(HM_E_ARG, "black box has no FP32 apply");
+  if (!mixed && !(bb.dtypes & (1 << HM_F64))) return fail(HM_E_ARG, "black box has no FP64 apply");
+  if (!bb.apply) return fail(HM_E_ARG, "black box without apply");
+  const int32_t kmax = kfix > 0 ? std::min(kfix, r) : r - p;
+  const size_t es = mixed ? 4 : 8;
+  const int64_t n = T.n;
+
+  DeviceTree &D = device_tree(T, s);
+  auto H = std::make_unique<hm_hmatrix>();
+  HIP_TRY(hipGetDevice(&H->device));
+  H->n = n;
+  H->nlev = T.nlev();
+  H->r = r;
+  H->kmax = kmax;
+  for (const Level &Lv : T.lev) H->start.push_back(Lv.start);
+  {
+    H->perm.alloc(n * sizeof(int64_t));
+    HIP_TRY(hipMemcpyAsync(H->perm.p, D.perm.p, n * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+  }
+  Events ev;
+  ev.on = (o.flags & 1) != 0;
+  ev.s = s;
+  auto t_host0 = std::chrono::steady_clock::now();
+
+  // ---------------- layout of the factor pools
+  std::vector<int> levels;
+  for (int l = 1; l < T.nlev(); ++l)
+    if (!T.graphs[l].pa.empty()) levels.push_back(l);
+  int64_t np_total = 0, szU = 0, szV = 0, szB = 0;
+  for (int l : levels) {
+    const Graph &G = T.graphs[l];
+    const Level &Lv = T.lev[l];
+    hm_hmatrix::Lv L;
+    L.level = l;
+    L.np = (int64_t)G.pa.size();
+    L.g0 = np_total;
+    L.pa = G.pa;
+    L.pb = G.pb;
+    for (int64_t q = 0; q < L.np; ++q) {
+      const int64_t ma = Lv.start[G.pa[q] + 1] - Lv.start[G.pa[q]];
+      const int64_t mb = Lv.start[G.pb[q] + 1] - Lv.start[G.pb[q]];
+      L.offU.push_back(szU);
+      L.offW.push_back(szU);
+      szU += ma * kmax;
+      L.offV.push_back(szV);
+      szV += mb * kmax;
+      L.offB.push_back(szB);
+      szB += (int64_t)kmax * kmax;
+    }
+    np_total += L.np;
+    H->max_np = std::max(H->max_np, L.np);
+    H->lv.push_back(std::move(L));
+  }
+  H->np_total = np_total;
+  H->U.alloc(szU * 8);
+  H->W.alloc(szU * 8);
+  H->V.alloc(szV * 8);
+  H->B.alloc(szB * 8);
+  H->Wf.alloc(szU * 4);
+  H->Vf.alloc(szV * 4);
+  H->ranks.alloc(2 * np_total * sizeof(int32_t));
+  launch_fill(H->W.p, szU, false, 0.0, s);
+  launch_fill(H->V.p, szV, false, 0.0, s);
+  launch_fill(H->ranks.p, np_total, true, 0.0, s);  // int32 zeros share the float bit pattern
+  launch_fill((char *)H->ranks.p + np_total * 4, np_total, true, 0.0, s);
+  LAUNCH_CHECK();
+  for (size_t li = 0; li < H->lv.size(); ++li) {
+    build_level_plans(*H, H->lv[li], T.lev[H->lv[li].level], s);
+    HIP_TRY(hipStreamSynchronize(s));  // plan vectors were host temporaries
+  }
+
+  // leaf neighbor blocks
+  const Graph &GL = T.leaf_graph();
+  const Level &LL = T.lev[T.L()];
+  int64_t szD = 0;
+  {
+    std::vector<ExpandChunk> ch;
+    std::vector<NearEntry> en;
+    H->na = GL.pa;
+    H->nb = GL.pb;
+    for (size_t q = 0; q < GL.pa.size(); ++q) {
+      H->offD.push_back(szD);
+      szD += T.box_size(T.L(), GL.pa[q]) * T.box_size(T.L(), GL.pb[q]);
+    }
+    size_t i = 0;
+    while (i < GL.pa.size()) {
+      size_t j = i;
+      while (j < GL.pa.size() && GL.pa[j] == GL.pa[i]) ++j;
+      const int a = GL.pa[i];
+      const int32_t m = (int32_t)T.box_size(T.L(), a);
+      for (int32_t off = 0; off < m; off += 64) {
+        ExpandChunk c{LL.start[a] + off, std::min<int32_t>(64, m - off), (int32_t)en.size(), 0, 0};
+        for (size_t q = i; q < j; ++q)
+          en.push_back(NearEntry{H->offD[q], LL.start[GL.pb[q]], m,
+                                 (int32_t)T.box_size(T.L(), GL.pb[q]), off, 0});
+        c.last = (int32_t)en.size();
+        ch.push_back(c);
+      }
+      i = j;
+    }
+    upload(H->nchunks, ch, s);
+    upload(H->nentries, en, s);
+    H->nnch = (int32_t)ch.size();
+    H->D.alloc(szD * 8);
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+
+  // ---------------- working buffers
+  int64_t cmax = 0;
+  for (int l : levels) cmax = std::max<int64_t>(cmax, pad16((int64_t)T.graphs[l].ncolors * r));
+  const int32_t mw = T.leaf_width();
+  const int64_t leaf_cols = pad16((int64_t)GL.ncolors * mw);
+  const int64_t wcols = std::max<int64_t>(2 * cmax, leaf_cols);
+  DBuf Xb, Yb, tmpx, tmpy, Tb, work, core, scratch, jobs, sat, flag;
+  Xb.alloc((size_t)n * wcols * es);
+  Yb.alloc((size_t)n * wcols * es);
+  const int64_t tcap = tscratch_elems(*H, wcols);
+  Tb.alloc((size_t)tcap * es);
+  int64_t wmax = 0, cmax_np = 0;
+  for (size_t li = 0; li < H->lv.size(); ++li) {
+    const hm_hmatrix::Lv &L = H->lv[li];
+    const Level &Lv = T.lev[L.level];
+    int64_t rows = 0;
+    for (int64_t q = 0; q < L.np; ++q)
+      rows += (Lv.start[L.pa[q] + 1] - Lv.start[L.pa[q]]) + (Lv.start[L.pb[q] + 1] - Lv.start[L.pb[q]]);
+    wmax = std::max(wmax, rows * r);
+    cmax_np = std::max(cmax_np, L.np);
+  }
+  work.alloc((size_t)std::max<int64_t>(wmax, 1) * 8);
+  core.alloc((size_t)std::max<int64_t>(cmax_np, 1) * r * r * 8);
+  scratch.alloc((size_t)std::max<int64_t>(cmax_np, 1) * r * r * 8);
+  sat.alloc((size_t)std::max<int64_t>(2 * np_total, 1) * 4);
+  launch_fill(sat.p, std::max<int64_t>(2 * np_total, 1), true, 0.0, s);
+  flag.alloc(64);
+  launch_fill(flag.p, 1, true, 0.0, s);
+  LAUNCH_CHECK();
+
+  // ---------------- every job list of every level, uploaded once up front
+  struct LevelJobs {
+    DBuf act, ju, jv, jc;
+  };
+  std::vector<LevelJobs> jobs_of(H->lv.size());
+  for (size_t li = 0; li < H->lv.size(); ++li) {
+    hm_hmatrix::Lv &L = H->lv[li];
+    const Graph &G = T.graphs[L.level];
+    const Level &Lv = T.lev[L.level];
+    const int64_t cpad = pad16((int64_t)G.ncolors * r);
+    std::vector<uint8_t> act((size_t)Lv.nbox() * G.ncolors, 0);
+    for (int64_t v = 0; v < G.nv(); ++v) act[(size_t)G.vbox[v] * G.ncolors + G.color[v]] = 1;
+    std::unordered_map<int64_t, int64_t> pidx;
+    pidx.reserve(L.np * 2);
+    for (int64_t q = 0; q < L.np; ++q) pidx[(int64_t)L.pa[q] * Lv.nbox() + L.pb[q]] = q;
+    std::vector<QrJob> ju(L.np), jv(L.np);
+    std::vector<CoreJob> jc(L.np);
+    int64_t wofs = 0;
+    for (int64_t q = 0; q < L.np; ++q) {
+      const int a = L.pa[q], b = L.pb[q];
+      const int64_t cu = G.color[G.pv[q]];
+      const int64_t cv = G.color[G.pv[pidx.at((int64_t)b * Lv.nbox() + a)]];
+      const int32_t ma = (int32_t)(Lv.start[a + 1] - Lv.start[a]);
+      const int32_t mb = (int32_t)(Lv.start[b + 1] - Lv.start[b]);
+      ju[q] = QrJob{Lv.start[a], cu * r, L.offU[q], wofs, ma, 0};
+      wofs += (int64_t)ma * r;
+      jv[q] = QrJob{Lv.start[b], cpad + cv * r, L.offV[q], wofs, mb, 0};
+      wofs += (int64_t)mb * r;
+      jc[q] = CoreJob{Lv.start[a], Lv.start[b], cu * r, cpad + cv * r, L.offU[q], L.offV[q],
+                      L.offW[q], L.offB[q], q * r * r, ma, mb,
+                      (int32_t)(L.g0 + q), (int32_t)(np_total + L.g0 + q)};
+    }
+    upload(jobs_of[li].act, act, s);
+    upload(jobs_of[li].ju, ju, s);
+    upload(jobs_of[li].jv, jv, s);
+    upload(jobs_of[li].jc, jc, s);
+    HIP_TRY(hipStreamSynchronize(s));  // the host vectors die here
+  }
+
+  int64_t cols_A = 0, cols_At = 0;
+  // ---------------- the level loop (no host round trips)
+  for (size_t li = 0; li < H->lv.size(); ++li) {
+    hm_hmatrix::Lv &L = H->lv[li];
+    const int l = L.level;
+    const Graph &G = T.graphs[l];
+    const int64_t c = (int64_t)G.ncolors * r;
+    const int64_t cpad = pad16(c);
+    void *Om = Xb.p;
+    void *Ps = (char *)Xb.p + (size_t)cpad * n * es;
+    void *Yl = Yb.p;
+    void *Zl = (char *)Yb.p + (size_t)cpad * n * es;
+    DBuf &dact = jobs_of[li].act;
+    ev.mark(0);
+    launch_testmat(n, D.rowbox[l].as<int32_t>(), dact.as<uint8_t>(), G.ncolors, r, l, 0, o.seed,
+                   mixed, Om, n, cpad, s);
+    launch_testmat(n, D.rowbox[l].as<int32_t>(), dact.as<uint8_t>(), G.ncolors, r, l, 1, o.seed,
+                   mixed, Ps, n, cpad, s);
+    LAUNCH_CHECK();
+    ev.mark(1);
+    if (bb.symmetric) {
+      call_blackbox(bb, 0, n, 2 * cpad, mixed, Om, n, Yl, n, D, tmpx, tmpy, s);
+    } else {
+      call_blackbox(bb, 0, n, cpad, mixed, Om, n, Yl, n, D, tmpx, tmpy, s);
+      call_blackbox(bb, 1, n, cpad, mixed, Ps, n, Zl, n, D, tmpx, tmpy, s);
+    }
+    cols_A += c;
+    cols_At += c;
+    ev.mark(2);
+    apply_levels(*H, li, false, mixed, Om, n, cpad, Yl, n, -1.0, Tb.p, tcap, s);
+    apply_levels(*H, li, true, mixed, Ps, n, cpad, Zl, n, -1.0, Tb.p, tcap, s);
+    launch_check_finite(n, 2 * cpad, mixed, Yb.p, n, flag.as<int32_t>(), s);
+    LAUNCH_CHECK();
+    ev.mark(3);
+    DBuf &dju = jobs_of[li].ju, &djv = jobs_of[li].jv, &djc = jobs_of[li].jc;
+    const int32_t cap = kfix > 0 ? kfix : r - p;
+    launch_core((int32_t)L.np, djc.as<CoreJob>(), r, mixed, Xb.p, n, Yb.p, n, core.as<double>(), s);
+    LAUNCH_CHECK();
+    launch_pivqr((int32_t)L.np, dju.as<QrJob>(), r, kfix, o.tol, cap, mixed, Yb.p, n,
+                 work.as<double>(), H->U.as<double>(), H->ranks.as<int32_t>() + L.g0,
+                 sat.as<int32_t>() + L.g0, s);
+    LAUNCH_CHECK();
+    launch_pivqr((int32_t)L.np, djv.as<QrJob>(), r, kfix, o.tol, cap, mixed, Yb.p, n,
+                 work.as<double>(), H->V.as<double>(), H->ranks.as<int32_t>() + np_total + L.g0,
+                 sat.as<int32_t>() + np_total + L.g0, s);
+    LAUNCH_CHECK();
+    ev.mark(4);
+    launch_coupling((int32_t)L.np, djc.as<CoreJob>(), r, kmax, mixed, Xb.p, n, Xb.p, n,
+                    H->U.as<double>(), H->V.as<double>(), H->ranks.as<int32_t>(),
+                    core.as<double>(), scratch.as<double>(), H->B.as<double>(),
+                    H->W.as<double>(), s);
+    LAUNCH_CHECK();
+    // FP32 copies of this level's apply factors
+    {
+      const int64_t u0 = L.offU.empty() ? 0 : L.offU[0];
+      const int64_t u1 = li + 1 < H->lv.size() ? H->lv[li + 1].offU[0] : szU;
+      const int64_t v0 = L.offV.empty() ? 0 : L.offV[0];
+      const int64_t v1 = li + 1 < H->lv.size() ? H->lv[li + 1].offV[0] : szV;
+      launch_convert(u1 - u0, 1, false, H->W.as<double>() + u0, u1 - u0, H->Wf.as<float>() + u0,
+                     u1 - u0, s);
+      launch_convert(v1 - v0, 1, false, H->V.as<double>() + v0, v1 - v0, H->Vf.as<float>() + v0,
+                     v1 - v0, s);
+      LAUNCH_CHECK();
+    }
+    ev.mark(5);
+  }
+
+  // ---------------- leaf pass
+  {
+    std::vector<int32_t> ib, ic;
+    for (int64_t v = 0; v < GL.nv(); ++v) {
+      ib.push_back(GL.vbox[v]);
+      ic.push_back(GL.color[v]);
+    }
+    // one item per (box, color) is enough; duplicates write the same ones
+    DBuf dib, dic;
+    upload(dib, ib, s);
+    upload(dic, ic, s);
+    ev.mark(0);
+    launch_leaf_identity(n, (int32_t)ib.size(), dib.as<int32_t>(), dic.as<int32_t>(),
+                         D.start[T.L()].as<int64_t>(), mw, mixed, Xb.p, n, leaf_cols, s);
+    LAUNCH_CHECK();
+    ev.mark(1);
+    call_blackbox(bb, 0, n, leaf_cols, mixed, Xb.p, n, Yb.p, n, D, tmpx, tmpy, s);
+    cols_A += (int64_t)GL.ncolors * mw;
+    ev.mark(2);
+    apply_levels(*H, H->lv.size(), false, mixed, Xb.p, n, leaf_cols, Yb.p, n, -1.0, Tb.p, tcap, s);
+    launch_check_finite(n, leaf_cols, mixed, Yb.p, n, flag.as<int32_t>(), s);
+    LAUNCH_CHECK();
+    ev.mark(3);
+    std::vector<int64_t> r0(GL.pa.size()), c0(GL.pa.size());
+    std::vector<int32_t> ma(GL.pa.size()), mb(GL.pa.size());
+    for (size_t q = 0; q < GL.pa.size(); ++q) {
+      r0[q] = LL.start[GL.pa[q]];
+      ma[q] = (int32_t)T.box_size(T.L(), GL.pa[q]);
+      mb[q] = (int32_t)T.box_size(T.L(), GL.pb[q]);
+      c0[q] = (int64_t)GL.color[GL.pv[q]] * mw;
+    }
+    DBuf dr0, dc0, dma, dmb, doff;
+    upload(dr0, r0, s);
+    upload(dc0, c0, s);
+    upload(dma, ma, s);
+    upload(dmb, mb, s);
+    upload(doff, H->offD, s);
+    launch_extract_near((int32_t)GL.pa.size(), dr0.as<int64_t>(), dma.as<int32_t>(),
+                        dc0.as<int64_t>(), dmb.as<int32_t>(), doff.as<int64_t>(), mixed, Yb.p, n,
+                        H->D.as<double>(), s);
+    LAUNCH_CHECK();
+    ev.mark(5);
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+
+  // ---------------- results back on the host
+  H->h_ranks.resize(2 * np_total);
+  std::vector<int32_t> hsat(2 * np_total);
+  int32_t hflag = 0;
+  if (np_total) {
+    HIP_TRY(hipMemcpy(H->h_ranks.data(), H->ranks.p, 2 * np_total * 4, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(hsat.data(), sat.p, 2 * np_total * 4, hipMemcpyDeviceToHost));
+  }
+  HIP_TRY(hipMemcpy(&hflag, flag.p, 4, hipMemcpyDeviceToHost));
+  if (hflag) return fail(HM_E_NUMERIC, "NaN or Inf in the black-box samples");
+
+  // ---------------- statistics
+  hm_stats &st = H->stats;
+  st = hm_stats{};
+  st.nlevels = T.nlev();
+  st.r = r;
+  st.n = n;
+  st.cols_A = cols_A;
+  st.cols_At = cols_At;
+  for (int l : levels)
+    if (l < 32) st.colors[l] = T.graphs[l].ncolors;
+  st.leaf_colors = GL.ncolors;
+  st.leaf_width = mw;
+  st.npairs = np_total;
+  st.nnear = (int64_t)GL.pa.size();
+  double fpeel = 0, fqr = 0, fsolve = 0;
+  int64_t nfloats = szD;
+  std::vector<double> level_apply_cost;  // per column, levels already compressed
+  for (size_t li = 0; li < H->lv.size(); ++li) {
+    const hm_hmatrix::Lv &L = H->lv[li];
+    const Level &Lv = T.lev[L.level];
+    double apply_cost = 0;
+    for (int64_t q = 0; q < L.np; ++q) {
+      const int64_t ma = Lv.start[L.pa[q] + 1] - Lv.start[L.pa[q]];
+      const int64_t mb = Lv.start[L.pb[q] + 1] - Lv.start[L.pb[q]];
+      const int ku = H->h_ranks[L.g0 + q], kv = H->h_ranks[np_total + L.g0 + q];
+      st.max_rank = std::max(st.max_rank, std::max(ku, kv));
+      st.saturated += hsat[L.g0 + q] + hsat[np_total + L.g0 + q];
+      nfloats += ma * ku + (int64_t)ku * kv + mb * kv;
+      apply_cost += 2.0 * kv * (ma + mb);
+      fqr += qr_flops(ma, r, ku) + qr_flops(mb, r, kv);
+      fsolve += 2.0 * ma * r * r + 2.0 * ma * r * ku + 2.0 * mb * r * kv + 4.0 * r * ku * ku +
+                4.0 * r * kv * kv + 2.0 * r * r * (ku + kv) + 2.0 * ma * ku * kv;
+    }
+    level_apply_cost.push_back(apply_cost);
+  }
+  for (size_t li = 0; li < H->lv.size(); ++li) {
+    const double c = (double)T.graphs[H->lv[li].level].ncolors * r;
+    double prev = 0;
+    for (size_t j = 0; j < li; ++j) prev += level_apply_cost[j];
+    fpeel += 2.0 * c * prev;  // Y and Z passes
+  }
+  {
+    double all = 0;
+    for (double v : level_apply_cost) all += v;
+    fpeel += (double)GL.ncolors * mw * all;
+  }
+  st.nfloats = nfloats;
+  st.flops_blackbox = 2.0 * (double)n * n * (double)(cols_A + cols_At);
+  st.flops_peel = fpeel;
+  st.flops_qr = fqr;
+  st.flops_solve = fsolve;
+  if (ev.on && !ev.marks.empty()) {
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (size_t i = 0; i + 1 < ev.marks.size(); ++i) {
+      float ms = 0;
+      (void)hipEventElapsedTime(&ms, ev.marks[i].first, ev.marks[i + 1].first);
+      acc[ev.marks[i].second] += ms;
+    }
+    st.ms_blackbox = acc[1];
+    st.ms_peel = acc[2];
+    st.ms_qr = acc[3];
+    st.ms_solve = acc[4];
+    st.ms_other = acc[0] + acc[5];
+  }
+  st.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_host0).count();
+  *out = H.release();
+  return HM_OK;
+}
+
+}  // namespace
+
+}  // namespace hm
+
+// ================================================================== C ABI
+using namespace hm;
+
+#define API_BEGIN try {
+#define API_END                                              \
+  }                                                          \
+  catch (const hm::Error &e) {                               \
+    return fail(e.code, e.msg);                              \
+  }                                                          \
+  catch (const std::bad_alloc &) {                           \
+    return fail(HM_E_NOMEM, "host allocation failed");       \
+  }                                                          \
+  catch (const std::exception &e) {                          \
+    return fail(HM_E_ARG, e.what());                         \
+  }
+
+extern "C" {
+
+const char *hm_last_error(void) { return g_last_error.c_str(); }
+
+hm_status hm_build_tree(const double *points, int64_t n, int dim, int leaf_size, int tree_kind,
+                        int adm, hm_tree **out) {
+  API_BEGIN
+  if (!points || !out || n <= 0 || dim < 1 || dim > 3 || leaf_size < 1)
+    return fail(HM_E_ARG, "hm_build_tree: bad argument");
+  if (tree_kind != HM_TREE_GEOMETRIC && tree_kind != HM_TREE_INDEX_BINARY)
+    return fail(HM_E_ARG, "hm_build_tree: bad tree kind");
+  if (adm != HM_ADM_STRONG && adm != HM_ADM_WEAK) return fail(HM_E_ARG, "hm_build_tree: bad adm");
+  if (tree_kind == HM_TREE_INDEX_BINARY && adm != HM_ADM_WEAK)
+    return fail(HM_E_ARG, "hm_build_tree: the index-halving tree needs weak admissibility");
+  for (int64_t i = 0; i < n * dim; ++i)
+    if (!std::isfinite(points[i])) return fail(HM_E_ARG, "hm_build_tree: non-finite point");
+  auto t = std::make_unique<hm_tree>();
+  hm_status st = build_tree(points, n, dim, leaf_size, tree_kind, adm, t->t);
+  if (st != HM_OK) return st;
+  *out = t.release();
+  return HM_OK;
+  API_END
+}
+
+void hm_tree_free(hm_tree *tree) { delete tree; }
+
+hm_status hm_tree_info(const hm_tree *tree, int32_t *nlevels, int64_t *n, int32_t *dim) {
+  if (!tree) return fail(HM_E_ARG, "null tree");
+  if (nlevels) *nlevels = tree->t.nlev();
+  if (n) *n = tree->t.n;
+  if (dim) *dim = tree->t.dim;
+  return HM_OK;
+}
+
+hm_status hm_tree_perm(const hm_tree *tree, int64_t *perm) {
+  if (!tree || !perm) return fail(HM_E_ARG, "null argument");
+  std::memcpy(perm, tree->t.perm.data(), tree->t.n * sizeof(int64_t));
+  return HM_OK;
+}
+
+hm_status hm_tree_level(const hm_tree *tree, int level, int32_t *nbox, int64_t *start,
+                        int32_t *parent, int64_t *org, int32_t *blev) {
+  if (!tree || level < 0 || level >= tree->t.nlev()) return fail(HM_E_ARG, "bad level");
+  const Level &Lv = tree->t.lev[level];
+  if (nbox) *nbox = Lv.nbox();
+  if (start) std::memcpy(start, Lv.start.data(), Lv.start.size() * 8);
+  if (parent) std::memcpy(parent, Lv.parent.data(), Lv.parent.size() * 4);
+  if (org) std::memcpy(org, Lv.org.data(), Lv.org.size() * 8);
+  if (blev) std::memcpy(blev, Lv.blev.data(), Lv.blev.size() * 4);
+  return HM_OK;
+}
+
+hm_status hm_tree_list(const hm_tree *tree, int level, int which, int64_t *nnz, int32_t *ptr,
+                       int32_t *idx) {
+  if (!tree || level < 0 || level >= tree->t.nlev()) return fail(HM_E_ARG, "bad level");
+  if (which != HM_LIST_NEIGHBOR && which != HM_LIST_INTERACTION) return fail(HM_E_ARG, "bad list");
+  const Level &Lv = tree->t.lev[level];
+  const std::vector<int32_t> &p = which == HM_LIST_NEIGHBOR ? Lv.nei_ptr : Lv.int_ptr;
+  const std::vector<int32_t> &x = which == HM_LIST_NEIGHBOR ? Lv.nei : Lv.intl;
+  if (nnz) *nnz = (int64_t)x.size();
+  if (ptr) std::memcpy(ptr, p.data(), p.size() * 4);
+  if (idx) std::memcpy(idx, x.data(), x.size() * 4);
+  return HM_OK;
+}
+
+static const Graph *graph_of(const hm_tree *tree, int level) {
+  if (!tree) return nullptr;
+  if (level == -1) return &tree->t.leaf_graph();
+  if (level < 0 || level >= tree->t.nlev()) return nullptr;
+  return &tree->t.graphs[level];
+}
+
+hm_status hm_incompat_graph(const hm_tree *tree, int level, int64_t *nv, int64_t *nadj,
+                            const int64_t **xadj, const int32_t **adj, const int32_t **vbox,
+                            int64_t *npairs, const int32_t **pair_a, const int32_t **pair_b,
+                            const int32_t **pair_v) {
+  const Graph *G = graph_of(tree, level);
+  if (!G) return fail(HM_E_ARG, "bad level");
+  if (nv) *nv = G->nv();
+  if (nadj) *nadj = (int64_t)G->adj.size();
+  if (xadj) *xadj = G->xadj.data();
+  if (adj) *adj = G->adj.data();
+  if (vbox) *vbox = G->vbox.data();
+  if (npairs) *npairs = (int64_t)G->pa.size();
+  if (pair_a) *pair_a = G->pa.data();
+  if (pair_b) *pair_b = G->pb.data();
+  if (pair_v) *pair_v = G->pv.data();
+  return HM_OK;
+}
+
+hm_status hm_color(int64_t nv, const int64_t *xadj, const int32_t *adj, int32_t *color,
+                   int32_t *ncolors) {
+  API_BEGIN
+  if (nv < 0 || (nv > 0 && (!xadj || !color))) return fail(HM_E_ARG, "hm_color: bad argument");
+  if (nv > 0 && xadj[nv] > 0 && !adj) return fail(HM_E_ARG, "hm_color: null adjacency");
+  for (int64_t v = 0; v < nv; ++v)
+    for (int64_t t = xadj[v]; t < xadj[v + 1]; ++t)
+      if (adj[t] < 0 || adj[t] >= nv || adj[t] == v) return fail(HM_E_ARG, "hm_color: bad edge");
+  const int32_t nc = dsatur(nv, xadj, adj, color);
+  if (ncolors) *ncolors = nc;
+  return HM_OK;
+  API_END
+}
+
+hm_status hm_tree_color(hm_tree *tree) {
+  API_BEGIN
+  if (!tree) return fail(HM_E_ARG, "null tree");
+  for (Graph &G : tree->t.graphs) {
+    G.color.assign(G.nv(), 0);
+    G.ncolors = dsatur(G.nv(), G.xadj.data(), G.adj.data(), G.color.data());
+    G.colored = true;
+  }
+  return HM_OK;
+  API_END
+}
+
+hm_status hm_tree_set_colors(hm_tree *tree, int level, const int32_t *color) {
+  API_BEGIN
+  Graph *G = const_cast<Graph *>(graph_of(tree, level));
+  if (!G || (!color && G->nv() > 0)) return fail(HM_E_ARG, "bad argument");
+  int32_t nc = 0;
+  for (int64_t v = 0; v < G->nv(); ++v) {
+    if (color[v] < 0) return fail(HM_E_ARG, "negative color");
+    nc = std::max(nc, color[v] + 1);
+    for (int64_t t = G->xadj[v]; t < G->xadj[v + 1]; ++t)
+      if (color[G->adj[t]] == color[v]) return fail(HM_E_ARG, "coloring is not valid");
+  }
+  G->color.assign(color, color + G->nv());
+  G->ncolors = nc;
+  G->colored = true;
+  return HM_OK;
+  API_END
+}
+
+hm_status hm_tree_colors(const hm_tree *tree, int level, int32_t *ncolors, const int32_t **color) {
+  const Graph *G = graph_of(tree, level);
+  if (!G) return fail(HM_E_ARG, "bad level");
+  if (!G->colored) return fail(HM_E_STATE, "graph not colored");
+  if (ncolors) *ncolors = G->ncolors;
+  if (color) *color = G->color.data();
+  return HM_OK;
+}
+
+hm_status hm_kernel_blackbox(hm_tree *tree, int kernel, hm_blackbox *out) {
+  API_BEGIN
+  if (!tree || !out) return fail(HM_E_ARG, "null argument");
+  if (kernel != HM_KERNEL_LOG && kernel != HM_KERNEL_INV_R) return fail(HM_E_ARG, "bad kernel");
+  auto k = std::make_shared<KernelBB>();
+  k->tree = &tree->t;
+  k->kernel = kernel;
+  tree->t.keep.push_back(k);
+  out->apply = kernel_bb_apply;
+  out->ctx = k.get();
+  out->order = HM_ORDER_TREE;
+  out->symmetric = 1;
+  out->dtypes = (1 << HM_F64) | (1 << HM_F32);
+  device_tree(tree->t, nullptr);
+  return HM_OK;
+  API_END
+}
+
+hm_status hm_kernel_apply(hm_tree *tree, int kernel, int64_t ncols, int dtype, const void *X,
+                          int64_t ldx, void *Y, int64_t ldy, int order, void *stream) {
+  API_BEGIN
+  if (!tree || !X || !Y || ncols < 0 || ldx < tree->t.n || ldy < tree->t.n)
+    return fail(HM_E_ARG, "hm_kernel_apply: bad argument");
+  if (kernel != HM_KERNEL_LOG && kernel != HM_KERNEL_INV_R) return fail(HM_E_ARG, "bad kernel");
+  if (dtype != HM_F64 && dtype != HM_F32) return fail(HM_E_ARG, "bad dtype");
+  hipStream_t s = (hipStream_t)stream;
+  DeviceTree &D = device_tree(tree->t, s);
+  const bool f32 = dtype == HM_F32;
+  const int64_t n = tree->t.n;
+  if (order == HM_ORDER_TREE) {
+    launch_kapply(kernel, tree->t.dim, n, D.pts.as<double>(), ncols, f32, X, ldx, Y, ldy, s);
+    LAUNCH_CHECK();
+    return HM_OK;
+  }
+  const size_t es = f32 ? 4 : 8;
+  DBuf tx, ty;
+  tx.alloc((size_t)n * std::max<int64_t>(ncols, 1) * es);
+  ty.alloc((size_t)n * std::max<int64_t>(ncols, 1) * es);
+  launch_permute_rows(n, ncols, D.perm.as<int64_t>(), false, f32, X, ldx, tx.p, n, s);
+  launch_kapply(kernel, tree->t.dim, n, D.pts.as<double>(), ncols, f32, tx.p, n, ty.p, n, s);
+  launch_permute_rows(n, ncols, D.perm.as<int64_t>(), true, f32, ty.p, n, Y, ldy, s);
+  LAUNCH_CHECK();
+  HIP_TRY(hipStreamSynchronize(s));
+  return HM_OK;
+  API_END
+}
+
+hm_status hm_dense_blackbox(const double *A, int64_t n, int64_t lda, int order, hm_blackbox *out) {
+  if (!A || !out || n <= 0 || lda < n) return fail(HM_E_ARG, "hm_dense_blackbox: bad argument");
+  DenseBB *d = new (std::nothrow) DenseBB{A, n, lda};
+  if (!d) return fail(HM_E_NOMEM, "host allocation failed");
+  out->apply = dense_bb_apply;
+  out->ctx = d;
+  out->order = order == HM_ORDER_TREE ? HM_ORDER_TREE : HM_ORDER_ORIGINAL;
+  out->symmetric = 0;
+  out->dtypes = 1 << HM_F64;
+  return HM_OK;
+}
+
+void hm_dense_blackbox_free(hm_blackbox *bb) {
+  if (bb && bb->apply == dense_bb_apply) {
+    delete (DenseBB *)bb->ctx;
+    bb->ctx = nullptr;
+    bb->apply = nullptr;
+  }
+}
+
+hm_status hm_compress(hm_tree *tree, const hm_blackbox *bb, const hm_compress_opts *opts,
+                      void *stream, hm_hmatrix **out) {
+  API_BEGIN
+  if (!tree || !bb || !opts || !out) return fail(HM_E_ARG, "hm_compress: null argument");
+  return compress_impl(tree->t, *bb, *opts, (hipStream_t)stream, out);
+  API_END
+}
+
+void hm_hmatrix_free(hm_hmatrix *H) { delete H; }
+
+hm_status hm_matvec(const hm_hmatrix *H, int64_t nrhs, int dtype, const void *X, int64_t ldx,
+                    void *Y, int64_t ldy, int order, void *stream) {
+  API_BEGIN
+  if (!H || !X || !Y || nrhs < 0 || ldx < H->n || ldy < H->n)
+    return fail(HM_E_ARG, "hm_matvec: bad argument");
+  if (dtype != HM_F64 && dtype != HM_F32) return fail(HM_E_ARG, "bad dtype");
+  if (nrhs == 0) return HM_OK;
+  hipStream_t s = (hipStream_t)stream;
+  const bool f32 = dtype == HM_F32;
+  const size_t es = f32 ? 4 : 8;
+  const int64_t n = H->n;
+  const int64_t tcap = tscratch_elems(*H, nrhs);
+  void *Tb = nullptr, *xt = nullptr, *yt = nullptr;
+  HIP_TRY(hipMallocAsync(&Tb, (size_t)tcap * es, s));
+  const bool orig = order != HM_ORDER_TREE;
+  const void *Xt = X;
+  void *Yt = Y;
+  int64_t ldxt = ldx, ldyt = ldy;
+  if (orig) {
+    HIP_TRY(hipMallocAsync(&xt, (size_t)n * nrhs * es, s));
+    HIP_TRY(hipMallocAsync(&yt, (size_t)n * nrhs * es, s));
+    launch_permute_rows(n, nrhs, H->perm.as<int64_t>(), false, f32, X, ldx, xt, n, s);
+    Xt = xt;
+    Yt = yt;
+    ldxt = ldyt = n;
+    launch_fill(yt, n * nrhs, f32, 0.0, s);
+  } else {
+    for (int64_t c = 0; c < nrhs; ++c) launch_fill((char *)Y + c * ldy * es, n, f32, 0.0, s);
+  }
+  LAUNCH_CHECK();
+  apply_levels(*H, H->lv.size(), false, f32, Xt, ldxt, nrhs, Yt, ldyt, 1.0, Tb, tcap, s);
+  launch_near_apply(H->nnch, H->nchunks.as<ExpandChunk>(), H->nentries.as<NearEntry>(), f32,
+                    H->D.p, Xt, ldxt, nrhs, Yt, ldyt, s);
+  LAUNCH_CHECK();
+  if (orig) {
+    launch_permute_rows(n, nrhs, H->perm.as<int64_t>(), true, f32, yt, n, Y, ldy, s);
+    LAUNCH_CHECK();
+    HIP_TRY(hipFreeAsync(xt, s));
+    HIP_TRY(hipFreeAsync(yt, s));
+  }
+  HIP_TRY(hipFreeAsync(Tb, s));
+  return HM_OK;
+  API_END
+}
+
+hm_status hm_test_matrix(const hm_tree *tree, int level, int pass, int32_t r, uint64_t seed,
+                         int dtype, void *out, int64_t ld, void *stream) {
+  API_BEGIN
+  if (!tree || !out || level < 0 || level >= tree->t.nlev() || r <= 0 || ld < tree->t.n ||
+      (pass != 0 && pass != 1) || (dtype != HM_F64 && dtype != HM_F32))
+    return fail(HM_E_ARG, "hm_test_matrix: bad argument");
+  const Graph &G = tree->t.graphs[level];
+  if (!G.colored && G.nv() > 0) return fail(HM_E_STATE, "graph not colored");
+  hipStream_t s = (hipStream_t)stream;
+  DeviceTree &D = device_tree(const_cast<Tree &>(tree->t), s);
+  std::vector<uint8_t> act((size_t)tree->t.lev[level].nbox() * std::max(G.ncolors, 1), 0);
+  for (int64_t v = 0; v < G.nv(); ++v) act[(size_t)G.vbox[v] * G.ncolors + G.color[v]] = 1;
+  DBuf dact;
+  upload(dact, act, s);
+  launch_testmat(tree->t.n, D.rowbox[level].as<int32_t>(), dact.as<uint8_t>(), G.ncolors, r,
+                 level, pass, seed, dtype == HM_F32, out, ld, (int64_t)G.ncolors * r, s);
+  LAUNCH_CHECK();
+  HIP_TRY(hipStreamSynchronize(s));
+  return HM_OK;
+  API_END
+}
+
+hm_status hm_philox4x32_10(const uint32_t *ctr, int64_t count, uint32_t key0, uint32_t key1,
+                           uint32_t *out, void *stream) {
+  API_BEGIN
+  if (!ctr || !out || count < 0) return fail(HM_E_ARG, "bad argument");
+  launch_philox_raw(ctr, count, key0, key1, out, (hipStream_t)stream);
+  LAUNCH_CHECK();
+  return HM_OK;
+  API_END
+}
+
+hm_status hm_hmatrix_stats(const hm_hmatrix *H, hm_stats *out) {
+  if (!H || !out) return fail(HM_E_ARG, "null argument");
+  *out = H->stats;
+  return HM_OK;
+}
+
+hm_status hm_hmatrix_export_level(const hm_hmatrix *H, int level, int64_t *npairs,
+                                  int32_t *pair_a, int32_t *pair_b, int32_t *rank_u,
+                                  int32_t *rank_v, int64_t *size_u, int64_t *size_b,
+                                  int64_t *size_v, double *U, double *B, double *V) {
+  API_BEGIN
+  if (!H) return fail(HM_E_ARG, "null H");
+  const hm_hmatrix::Lv *L = nullptr;
+  for (const auto &x : H->lv)
+    if (x.level == level) L = &x;
+  if (!L) {
+    if (npairs) *npairs = 0;
+    if (size_u) *size_u = 0;
+    if (size_b) *size_b = 0;
+    if (size_v) *size_v = 0;
+    return HM_OK;
+  }
+  const std::vector<int64_t> &st = H->start[level];
+  int64_t su = 0, sb = 0, sv = 0;
+  for (int64_t q = 0; q < L->np; ++q) {
+    const int ku = H->h_ranks[L->g0 + q], kv = H->h_ranks[H->np_total + L->g0 + q];
+    su += (st[L->pa[q] + 1] - st[L->pa[q]]) * ku;
+    sb += (int64_t)ku * kv;
+    sv += (st[L->pb[q] + 1] - st[L->pb[q]]) * kv;
+  }
+  if (npairs) *npairs = L->np;
+  if (size_u) *size_u = su;
+  if (size_b) *size_b = sb;
+  if (size_v) *size_v = sv;
+  if (pair_a) std::memcpy(pair_a, L->pa.data(), L->np * 4);
+  if (pair_b) std::memcpy(pair_b, L->pb.data(), L->np * 4);
+  for (int64_t q = 0; q < L->np; ++q) {
+    if (rank_u) rank_u[q] = H->h_ranks[L->g0 + q];
+    if (rank_v) rank_v[q] = H->h_ranks[H->np_total + L->g0 + q];
+  }
+  if (U || B || V) {
+    HIP_TRY(hipDeviceSynchronize());
+    int64_t ou = 0, ob = 0, ov = 0;
+    std::vector<double> bt((size_t)H->kmax * H->kmax);
+    for (int64_t q = 0; q < L->np; ++q) {
+      const int ku = H->h_ranks[L->g0 + q], kv = H->h_ranks[H->np_total + L->g0 + q];
+      const int64_t ma = st[L->pa[q] + 1] - st[L->pa[q]];
+      const int64_t mb = st[L->pb[q] + 1] - st[L->pb[q]];
+      if (U && ku)
+        HIP_TRY(hipMemcpy(U + ou, H->U.as<double>() + L->offU[q], ma * ku * 8, hipMemcpyDeviceToHost));
+      if (V && kv)
+        HIP_TRY(hipMemcpy(V + ov, H->V.as<double>() + L->offV[q], mb * kv * 8, hipMemcpyDeviceToHost));
+      if (B && ku && kv) {
+        HIP_TRY(hipMemcpy(bt.data(), H->B.as<double>() + L->offB[q], bt.size() * 8,
+                          hipMemcpyDeviceToHost));
+        for (int c = 0; c < kv; ++c)
+          for (int t = 0; t < ku; ++t) B[ob + c * ku + t] = bt[(size_t)c * H->kmax + t];
+      }
+      ou += ma * ku;
+      ob += (int64_t)ku * kv;
+      ov += mb * kv;
+    }
+  }
+  return HM_OK;
+  API_END
+}
+
+hm_status hm_hmatrix_export_near(const hm_hmatrix *H, int64_t *npairs, int32_t *pair_a,
+                                 int32_t *pair_b, int64_t *size, double *D) {
+  API_BEGIN
+  if (!H) return fail(HM_E_ARG, "null H");
+  if (npairs) *npairs = (int64_t)H->na.size();
+  const std::vector<int64_t> &st = H->start[H->nlev - 1];
+  int64_t total = 0;
+  for (size_t q = 0; q < H->na.size(); ++q)
+    total += (st[H->na[q] + 1] - st[H->na[q]]) * (st[H->nb[q] + 1] - st[H->nb[q]]);
+  if (size) *size = total;
+  if (pair_a) std::memcpy(pair_a, H->na.data(), H->na.size() * 4);
+  if (pair_b) std::memcpy(pair_b, H->nb.data(), H->nb.size() * 4);
+  if (D && total) {
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemcpy(D, H->D.p, total * 8, hipMemcpyDeviceToHost));
+  }
+  return HM_OK;
+  API_END
+}
+
+}  // extern "C"

@@ -1,0 +1,72 @@
+// Internal declarations shared by the host and device sources of libhm.
+#pragma once
+
+#include <cstdint>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/hm.h"
+
+namespace hm {
+
+// ------------------------------------------------------------------ errors
+void set_error(const std::string &msg);
+hm_status fail(hm_status code, const std::string &msg);
+
+struct Error {
+  hm_status code;
+  std::string msg;
+};
+
+// ------------------------------------------------------------------ tree
+struct Level {
+  std::vector<int64_t> start;    // nbox + 1
+  std::vector<int32_t> parent;   // nbox
+  std::vector<int64_t> org;      // 3 * nbox
+  std::vector<int32_t> blev;     // nbox
+  std::vector<int32_t> nei_ptr, nei;
+  std::vector<int32_t> int_ptr, intl;
+  int32_t nbox() const { return (int32_t)parent.size(); }
+};
+
+struct Graph {
+  std::vector<int32_t> vbox;     // active box per vertex
+  std::vector<int32_t> vclass;   // neighbor-set class of the vertex's box set
+  std::vector<int64_t> xadj;
+  std::vector<int32_t> adj;
+  std::vector<int32_t> pa, pb, pv;  // pairs and their vertex
+  std::vector<int32_t> color;
+  int32_t ncolors = 0;
+  bool colored = false;
+  int64_t nv() const { return (int64_t)vbox.size(); }
+};
+
+struct DeviceTree;  // device copies, defined in the engine
+
+struct Tree {
+  int64_t n = 0;
+  int dim = 0, kind = 0, adm = 0, leaf = 0;
+  std::vector<double> pts;        // original order, n x dim row-major
+  std::vector<int64_t> perm;      // tree position -> original index
+  std::vector<Level> lev;
+  std::vector<Graph> graphs;      // one per level + the leaf graph last
+  std::shared_ptr<DeviceTree> dev;
+  std::vector<std::shared_ptr<void>> keep;  // objects whose lifetime is the tree's
+  int nlev() const { return (int)lev.size(); }
+  int L() const { return nlev() - 1; }
+  Graph &leaf_graph() { return graphs.back(); }
+  const Graph &leaf_graph() const { return graphs.back(); }
+  int64_t box_size(int l, int b) const { return lev[l].start[b + 1] - lev[l].start[b]; }
+  int32_t leaf_width() const;
+};
+
+hm_status build_tree(const double *pts, int64_t n, int dim, int leaf, int kind, int adm,
+                     Tree &T);
+int32_t dsatur(int64_t nv, const int64_t *xadj, const int32_t *adj, int32_t *color);
+
+}  // namespace hm
+
+struct hm_tree {
+  hm::Tree t;
+};

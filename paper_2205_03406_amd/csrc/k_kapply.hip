@@ -1,0 +1,202 @@
+// On-the-fly kernel-matrix apply Y = K X on the MFMA units (the built-in
+// black box standing in for the fast matvecs of the experiments section:
+// K(x, y) = log|x - y| in 1D/2D, 1/|x - y| in 3D, 0 where x = y).
+//
+// Design (gfx950): a workgroup of 4 waves owns 64 rows of Y and BN = 16*NT
+// columns.  Each wave owns 16 rows.  The K(rows, k-block) operand is never
+// stored: every lane evaluates one kernel entry per 4-deep MFMA step in
+// registers, in exactly the A-operand layout of the 16x16x4 MFMA (lane l
+// holds row l%16, depth l/16), so K costs one VALU evaluation per entry per
+// column tile while the matrix core does 2*BN flops with it.  X k-blocks and
+// the matching point coordinates are staged through LDS, double-buffered.
+// The contraction over all N points is the whole cost: 2 N^2 ncols flops
+// against N*ncols*8 bytes of X per row block, far above the FP64 ridge.
+#include <type_traits>
+
+#include "device_common.h"
+#include "kernels.h"
+
+namespace hm {
+
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int BK = 16;   // k-block (points) staged per LDS buffer
+
+template <int KER>
+__device__ __forceinline__ double kval64(double r2) {
+  if (!(r2 > 0.0)) return 0.0;
+  if (KER == 0) return 0.5 * log(r2);
+  return rsqrt(r2);
+}
+
+template <int KER>
+__device__ __forceinline__ float kval32(float r2) {
+  if (!(r2 > 0.0f)) return 0.0f;
+  if (KER == 0) return 0.34657359027997264f * __log2f(r2);  // 0.5 ln(2) log2(r2)
+  return rsqrtf(r2);
+}
+
+template <typename T, int NT, int KER, int DIM>
+__global__ void __launch_bounds__(256)
+kapply_kernel(int64_t n, const double *__restrict__ pts, int64_t ncols, const T *__restrict__ X,
+              int64_t ldx, T *__restrict__ Y, int64_t ldy) {
+  constexpr int BN = 16 * NT;
+  constexpr int LDT = BN + 2;
+  __shared__ T Xs[2][BK][LDT];
+  __shared__ double Ps[2][DIM][BK];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int64_t row_blk = (int64_t)blockIdx.x * 64;
+  const int64_t col0 = (int64_t)blockIdx.y * BN;
+  const int64_t my_row = row_blk + wave * 16 + (lane & 15);
+  const int kq = lane >> 4;  // depth index of this lane inside an MFMA step
+
+  double pr[DIM];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) pr[d] = my_row < n ? pts[(int64_t)d * n + my_row] : 0.0;
+
+  typedef typename std::conditional<sizeof(T) == 8, d4, f4>::type acc_t;
+  acc_t acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = (acc_t){0, 0, 0, 0};
+
+  // X k-block and point coordinates: fetched into registers one block ahead
+  // (global latency overlaps the MFMA work), written to LDS after compute.
+  constexpr int PER = (BK * BN) / 256;  // elements per thread (NT)
+  T xr[PER];
+  double pk = 0.0;
+  auto fetch = [&](int64_t k0) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = tid + 256 * q;
+      const int kr = e % BK, cc = e / BK;
+      const int64_t gk = k0 + kr, gc = col0 + cc;
+      xr[q] = (gk < n && gc < ncols) ? X[gc * ldx + gk] : (T)0;
+    }
+    if (tid < BK * DIM) {
+      const int64_t gk = k0 + tid % BK;
+      pk = gk < n ? pts[(int64_t)(tid / BK) * n + gk] : 0.0;
+    }
+  };
+  auto commit = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = tid + 256 * q;
+      Xs[buf][e % BK][e / BK] = xr[q];
+    }
+    if (tid < BK * DIM) Ps[buf][tid / BK][tid % BK] = pk;
+  };
+
+  const int64_t nk = (n + BK - 1) / BK;
+  fetch(0);
+  commit(0);
+  __syncthreads();
+  for (int64_t kb = 0; kb < nk; ++kb) {
+    const int buf = (int)(kb & 1);
+    if (kb + 1 < nk) fetch((kb + 1) * BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      const int kl = kk + kq;
+      const int64_t gk = kb * BK + kl;
+      double r2 = 0.0;
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        const double df = pr[d] - Ps[buf][d][kl];
+        r2 += df * df;
+      }
+      const bool live = gk < n && my_row < n;
+      if constexpr (sizeof(T) == 8) {
+        const double a = live ? kval64<KER>(r2) : 0.0;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          const double b = Xs[buf][kl][t * 16 + (lane & 15)];
+          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
+        }
+      } else {
+        const float a = live ? kval32<KER>((float)r2) : 0.0f;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          const float b = Xs[buf][kl][t * 16 + (lane & 15)];
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[t], 0, 0, 0);
+        }
+      }
+    }
+    if (kb + 1 < nk) commit(buf ^ 1);
+    __syncthreads();
+  }
+  // D layout of the 16x16 MFMA tile: lane l, item i -> row 4*(l/16)+i, col l%16
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int64_t c = col0 + t * 16 + (lane & 15);
+    if (c >= ncols) continue;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t rr = row_blk + wave * 16 + 4 * kq + i;
+      if (rr < n) Y[c * ldy + rr] = (T)acc[t][i];
+    }
+  }
+}
+
+template <typename T, int NT, int KER, int DIM>
+void launch_nt(int64_t n, const double *pts, int64_t ncols, const T *X, int64_t ldx, T *Y,
+               int64_t ldy, hipStream_t s) {
+  const int64_t bn = 16 * NT;
+  dim3 g((unsigned)((n + 63) / 64), (unsigned)((ncols + bn - 1) / bn));
+  kapply_kernel<T, NT, KER, DIM><<<g, 256, 0, s>>>(n, pts, ncols, X, ldx, Y, ldy);
+}
+
+template <typename T, int KER, int DIM>
+void launch_dim(int64_t n, const double *pts, int64_t ncols, const T *X, int64_t ldx, T *Y,
+                int64_t ldy, hipStream_t s) {
+  // columns in 16-wide fragments, at most 16 fragments per workgroup; pick
+  // the narrowest instantiated tile that covers an even split
+  const int64_t frags = (ncols + 15) / 16;
+  const int64_t tiles = (frags + 15) / 16;
+  const int64_t need = (frags + tiles - 1) / tiles;
+  if (need <= 2)
+    launch_nt<T, 2, KER, DIM>(n, pts, ncols, X, ldx, Y, ldy, s);
+  else if (need <= 4)
+    launch_nt<T, 4, KER, DIM>(n, pts, ncols, X, ldx, Y, ldy, s);
+  else if (need <= 8)
+    launch_nt<T, 8, KER, DIM>(n, pts, ncols, X, ldx, Y, ldy, s);
+  else if (need <= 12)
+    launch_nt<T, 12, KER, DIM>(n, pts, ncols, X, ldx, Y, ldy, s);
+  else
+    launch_nt<T, 16, KER, DIM>(n, pts, ncols, X, ldx, Y, ldy, s);
+}
+
+template <typename T, int KER>
+void launch_ker(int dim, int64_t n, const double *pts, int64_t ncols, const T *X, int64_t ldx,
+                T *Y, int64_t ldy, hipStream_t s) {
+  if (dim == 1)
+    launch_dim<T, KER, 1>(n, pts, ncols, X, ldx, Y, ldy, s);
+  else if (dim == 2)
+    launch_dim<T, KER, 2>(n, pts, ncols, X, ldx, Y, ldy, s);
+  else
+    launch_dim<T, KER, 3>(n, pts, ncols, X, ldx, Y, ldy, s);
+}
+
+}  // namespace
+
+void launch_kapply(int kernel, int dim, int64_t n, const double *pts, int64_t ncols, bool f32,
+                   const void *X, int64_t ldx, void *Y, int64_t ldy, hipStream_t s) {
+  if (n <= 0 || ncols <= 0) return;
+  if (f32) {
+    if (kernel == 0)
+      launch_ker<float, 0>(dim, n, pts, ncols, (const float *)X, ldx, (float *)Y, ldy, s);
+    else
+      launch_ker<float, 1>(dim, n, pts, ncols, (const float *)X, ldx, (float *)Y, ldy, s);
+  } else {
+    if (kernel == 0)
+      launch_ker<double, 0>(dim, n, pts, ncols, (const double *)X, ldx, (double *)Y, ldy, s);
+    else
+      launch_ker<double, 1>(dim, n, pts, ncols, (const double *)X, ldx, (double *)Y, ldy, s);
+  }
+}
+
+}  // namespace hm

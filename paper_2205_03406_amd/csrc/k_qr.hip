@@ -1,0 +1,386 @@
+// Per-pair recovery of alg:compress_double_random, batched over all
+// admissible pairs of a level, one workgroup (4 waves) per pair:
+//
+//   pivqr     U = qr(S, k): column-pivoted Householder QR of the sample block
+//             S (m x r) in an FP64 workspace, stopped at the fixed rank or at
+//             the first |R_jj| <= tol |R_00| (eq:QR, partial QR), then the
+//             explicit Q[:, 0:k] by backward accumulation of the reflectors.
+//   core      C = G2^T S (r x r), the sketch of the block seen from both sides.
+//   coupling  B = (G2^T U)^+ C (V^T G1)^+ through two small Householder
+//             least-squares solves in LDS, and W = U B for the apply.
+//
+// All of this stays in FP64 in every precision mode.  Reductions over rows
+// are wave-wide shuffles; every column update is owned by one wave.
+#include "device_common.h"
+#include "kernels.h"
+
+namespace hm {
+
+namespace {
+
+using dev::wave_sum;
+
+// ------------------------------------------------------------------ pivqr
+template <typename T>
+__global__ void __launch_bounds__(256)
+pivqr_kernel(const QrJob *__restrict__ jobs, int32_t r, int32_t rank_fixed, double tol,
+             int32_t cap, const T *__restrict__ S, int64_t lds, double *__restrict__ Wk,
+             double *__restrict__ U, int32_t *__restrict__ ranks, int32_t *__restrict__ sat) {
+  __shared__ double nrm2[64];
+  __shared__ int piv[64];
+  __shared__ double tau[64];
+  __shared__ double bcast[4];
+  __shared__ int stop_s;
+  const QrJob job = jobs[blockIdx.x];
+  const int m = job.m;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const T *A = S + job.col0 * lds + job.row0;
+  double *W = Wk + job.wslot;  // m x r, ld = m
+  const int kmax_here = m < r ? m : r;
+  const int kcap = rank_fixed > 0 ? (rank_fixed < kmax_here ? rank_fixed : kmax_here)
+                                  : (cap < kmax_here ? cap : kmax_here);
+
+  // copy to the FP64 workspace and take squared column norms
+  for (int c = wave; c < r; c += 4) {
+    double s2 = 0.0;
+    for (int i = lane; i < m; i += 64) {
+      const double v = (double)A[(int64_t)c * lds + i];
+      W[(int64_t)c * m + i] = v;
+      s2 += v * v;
+    }
+    s2 = wave_sum(s2);
+    if (lane == 0) nrm2[c] = s2;
+  }
+  if (tid < 64) piv[tid] = tid;
+  __syncthreads();
+
+  int rank = 0;
+  int saturated = 0;
+  double r00 = 0.0;
+  for (int j = 0; j < kcap; ++j) {
+    if (tid == 0) {
+      // largest remaining column (first one on ties)
+      int p = j;
+      for (int c = j + 1; c < r; ++c)
+        if (nrm2[c] > nrm2[p]) p = c;
+      const double tn = nrm2[j];
+      nrm2[j] = nrm2[p];
+      nrm2[p] = tn;
+      const int tp = piv[j];
+      piv[j] = piv[p];
+      piv[p] = tp;
+    }
+    __syncthreads();
+    const int pc = piv[j];
+    double *x = W + (int64_t)pc * m;
+    if (wave == 0) {
+      double s2 = 0.0;
+      for (int i = j + lane; i < m; i += 64) s2 += x[i] * x[i];
+      s2 = wave_sum(s2);
+      if (lane == 0) {
+        const double nrm = sqrt(s2);
+        if (j == 0) bcast[1] = nrm;
+        const double ref = j == 0 ? nrm : bcast[1];
+        int stop = !(nrm > 0.0);
+        if (rank_fixed <= 0 && !(nrm > tol * ref)) stop = 1;
+        stop_s = stop;
+        if (!stop) {
+          const double alpha = x[j];
+          const double beta = alpha >= 0.0 ? -nrm : nrm;
+          tau[j] = (beta - alpha) / beta;
+          bcast[0] = 1.0 / (alpha - beta);
+          x[j] = beta;
+        }
+      }
+    }
+    __syncthreads();
+    r00 = bcast[1];
+    if (stop_s) break;
+    rank = j + 1;
+    const double sc = bcast[0];
+    for (int i = j + 1 + tid; i < m; i += 256) x[i] *= sc;
+    __syncthreads();
+    const double tj = tau[j];
+    for (int c = j + 1 + wave; c < r; c += 4) {
+      double *y = W + (int64_t)piv[c] * m;
+      double w = 0.0;
+      for (int i = j + 1 + lane; i < m; i += 64) w += x[i] * y[i];
+      w = wave_sum(w) + y[j];
+      const double f = tj * w;
+      if (lane == 0) y[j] -= f;
+      double s2 = 0.0;
+      for (int i = j + 1 + lane; i < m; i += 64) {
+        const double v = y[i] - f * x[i];
+        y[i] = v;
+        s2 += v * v;
+      }
+      s2 = wave_sum(s2);
+      if (lane == 0) nrm2[c] = s2;
+    }
+    __syncthreads();
+  }
+  // tolerance mode: the cap was reached while a remaining column still
+  // exceeds the threshold
+  if (rank_fixed <= 0 && rank == kcap && kcap < kmax_here) {
+    double mx = 0.0;
+    for (int c = kcap; c < r; ++c) mx = nrm2[c] > mx ? nrm2[c] : mx;
+    if (sqrt(mx) > tol * r00) saturated = 1;
+  }
+
+  // explicit basis: U = H_0 ... H_{rank-1} [I; 0], written column-major (ld = m)
+  double *Uo = U + job.uslot;
+  for (int c = wave; c < rank; c += 4)
+    for (int i = lane; i < m; i += 64) Uo[(int64_t)c * m + i] = (i == c) ? 1.0 : 0.0;
+  __syncthreads();
+  for (int j = rank - 1; j >= 0; --j) {
+    const double *x = W + (int64_t)piv[j] * m;
+    const double tj = tau[j];
+    for (int c = j + wave; c < rank; c += 4) {
+      double *y = Uo + (int64_t)c * m;
+      double w = 0.0;
+      for (int i = j + 1 + lane; i < m; i += 64) w += x[i] * y[i];
+      w = wave_sum(w) + y[j];
+      const double f = tj * w;
+      for (int i = j + 1 + lane; i < m; i += 64) y[i] -= f * x[i];
+      if (lane == 0) y[j] -= f;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    ranks[blockIdx.x] = rank;
+    sat[blockIdx.x] = saturated;
+  }
+}
+
+// ------------------------------------------------------------------ small dense helpers
+// out(i, c) = sum_t X(t, i) Y(t, c), i < a, c < b (a*b <= 4096); X and Y are
+// m-row column-major blocks; `stage` holds 32*(a+b) (+pad) doubles of LDS.
+template <typename TX, typename TY>
+__device__ void tn_gemm(int m, int a, int b, const TX *X, int64_t ldx, const TY *Y, int64_t ldy,
+                        double *out, int ldo, double *stage) {
+  const int tid = threadIdx.x;
+  constexpr int SP = 33;
+  double *sx = stage, *sy = stage + SP * a;
+  double acc[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+  for (int t0 = 0; t0 < m; t0 += 32) {
+    const int rows = m - t0 < 32 ? m - t0 : 32;
+    for (int e = tid; e < 32 * a; e += 256) {
+      const int tt = e % 32, i = e / 32;
+      sx[i * SP + tt] = tt < rows ? (double)X[(int64_t)i * ldx + t0 + tt] : 0.0;
+    }
+    for (int e = tid; e < 32 * b; e += 256) {
+      const int tt = e % 32, c = e / 32;
+      sy[c * SP + tt] = tt < rows ? (double)Y[(int64_t)c * ldy + t0 + tt] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int e = tid + 256 * q;
+      if (e < a * b) {
+        const int i = e % a, c = e / a;
+        double s = 0.0;
+#pragma unroll 8
+        for (int tt = 0; tt < 32; ++tt) s += sx[i * SP + tt] * sy[c * SP + tt];
+        acc[q] += s;
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int e = tid + 256 * q;
+    if (e < a * b) out[(e / a) * ldo + (e % a)] = acc[q];
+  }
+  __syncthreads();
+}
+
+// Householder QR of M (rows x cols, ld, rows <= 64) in place: R in the upper
+// triangle, reflector tails below it (leading 1 implicit), factors in tau.
+__device__ void lds_qr(double *M, int ld, int rows, int cols, double *tau, double *bc) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int j = 0; j < cols; ++j) {
+    if (wave == 0) {
+      const double v = (lane >= j && lane < rows) ? M[j * ld + lane] : 0.0;
+      const double s2 = wave_sum(v * v);
+      if (lane == 0) {
+        const double nrm = sqrt(s2);
+        const double alpha = M[j * ld + j];
+        if (nrm > 0.0) {
+          const double beta = alpha >= 0.0 ? -nrm : nrm;
+          tau[j] = (beta - alpha) / beta;
+          bc[0] = 1.0 / (alpha - beta);
+          M[j * ld + j] = beta;
+        } else {
+          tau[j] = 0.0;
+          bc[0] = 0.0;
+        }
+      }
+    }
+    __syncthreads();
+    if (tid > j && tid < rows) M[j * ld + tid] *= bc[0];
+    __syncthreads();
+    const double tj = tau[j];
+    for (int c = j + 1 + wave; c < cols; c += 4) {
+      const double v = (lane > j && lane < rows) ? M[j * ld + lane] : 0.0;
+      const double y = (lane > j && lane < rows) ? M[c * ld + lane] : 0.0;
+      const double w = wave_sum(v * y) + M[c * ld + j];
+      const double f = tj * w;
+      if (lane > j && lane < rows) M[c * ld + lane] = y - f * v;
+      if (lane == 0) M[c * ld + j] -= f;
+    }
+    __syncthreads();
+  }
+}
+
+// C <- Q^T C for the reflectors stored in M (rows x k); C is rows x nc (ldc)
+__device__ void lds_apply_qt(const double *M, int ld, int rows, int k, const double *tau,
+                             double *C, int ldc, int nc) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int j = 0; j < k; ++j) {
+    const double tj = tau[j];
+    for (int c = wave; c < nc; c += 4) {
+      const double v = (lane > j && lane < rows) ? M[j * ld + lane] : 0.0;
+      const double y = (lane > j && lane < rows) ? C[c * ldc + lane] : 0.0;
+      const double w = wave_sum(v * y) + C[c * ldc + j];
+      const double f = tj * w;
+      if (lane > j && lane < rows) C[c * ldc + lane] = y - f * v;
+      if (lane == 0) C[c * ldc + j] -= f;
+    }
+    __syncthreads();
+  }
+}
+
+// Solve R X = C[0:k, :] in place (R upper k x k in M), one thread per column
+__device__ void lds_backsolve(const double *M, int ld, int k, double *C, int ldc, int nc) {
+  const int tid = threadIdx.x;
+  for (int c = tid; c < nc; c += 256) {
+    for (int i = k - 1; i >= 0; --i) {
+      double s = C[c * ldc + i];
+      for (int t = i + 1; t < k; ++t) s -= M[t * ld + i] * C[c * ldc + t];
+      C[c * ldc + i] = s / M[i * ld + i];
+    }
+  }
+  __syncthreads();
+}
+
+// ------------------------------------------------------------------ core
+template <typename T>
+__global__ void __launch_bounds__(256)
+core_kernel(const CoreJob *__restrict__ jobs, int32_t r, const T *__restrict__ Psi, int64_t ldp,
+            const T *__restrict__ Y, int64_t ldy, double *__restrict__ core) {
+  extern __shared__ double smem[];  // staging, 33 * 2r doubles
+  const CoreJob job = jobs[blockIdx.x];
+  tn_gemm(job.ma, r, r, Psi + job.vcol0 * ldp + job.arow0, ldp, Y + job.ucol0 * ldy + job.arow0,
+          ldy, core + job.cslot, r, smem);
+}
+
+// ------------------------------------------------------------------ coupling
+template <typename T>
+__global__ void __launch_bounds__(256)
+coupling_kernel(const CoreJob *__restrict__ jobs, int32_t r, int32_t kmax,
+                const T *__restrict__ Omega, int64_t ldo, const T *__restrict__ Psi, int64_t ldp,
+                const double *__restrict__ U, const double *__restrict__ V,
+                const int32_t *__restrict__ ranks, const double *__restrict__ core,
+                double *__restrict__ scratch, double *__restrict__ B, double *__restrict__ Wout) {
+  extern __shared__ double smem[];
+  __shared__ double tau[64];
+  __shared__ double bc[2];
+  const CoreJob job = jobs[blockIdx.x];
+  const int ku = ranks[job.pu], kv = ranks[job.pv];
+  const int tid = threadIdx.x;
+  double *Bs = B + job.bslot;
+  double *W = Wout + job.wslot;
+  if (ku == 0 || kv == 0) {
+    // a zero block: B and W stay empty (ranks say so); clear for export
+    for (int e = tid; e < kmax * kmax; e += 256) Bs[e] = 0.0;
+    return;
+  }
+  const int sa = (r * r > 33 * (r + kmax)) ? r * r : 33 * (r + kmax);
+  double *A = smem;            // sa doubles: staging / C / X1
+  double *M = smem + sa;       // r x kmax: M1 then M2^T
+  const double *Ua = U + job.uslot;
+  const double *Vb = V + job.vslot;
+  // M1 = G2^T U  (r x ku), G2 = Psi(alpha rows, block of (b, a))
+  tn_gemm(job.ma, r, ku, Psi + job.vcol0 * ldp + job.arow0, ldp, Ua, (int64_t)job.ma, M, r, A);
+  lds_qr(M, r, r, ku, tau, bc);
+  // X1 = R^{-1} (Q^T C)[0:ku, :]
+  for (int e = tid; e < r * r; e += 256) A[e] = core[job.cslot + e];
+  __syncthreads();
+  lds_apply_qt(M, r, r, ku, tau, A, r, r);
+  lds_backsolve(M, r, ku, A, r, r);
+  double *X1 = scratch + job.cslot;  // ku x r, ld = r (rows 0..ku-1 of A)
+  for (int e = tid; e < r * r; e += 256) X1[e] = A[e];
+  __syncthreads();
+  // M2^T = G1^T V  (r x kv), G1 = Omega(beta rows, block of (a, b))
+  tn_gemm(job.mb, r, kv, Omega + job.ucol0 * ldo + job.brow0, ldo, Vb, (int64_t)job.mb, M, r, A);
+  lds_qr(M, r, r, kv, tau, bc);
+  // B^T = R^{-1} (Q^T X1^T)[0:kv, :] with X1^T (r x ku) in A (ld = r)
+  for (int e = tid; e < r * ku; e += 256) {
+    const int i = e % r, c = e / r;  // X1^T(i, c) = X1(c, i)
+    A[c * r + i] = X1[i * r + c];
+  }
+  __syncthreads();
+  lds_apply_qt(M, r, r, kv, tau, A, r, ku);
+  lds_backsolve(M, r, kv, A, r, ku);
+  // B(t, c) = B^T(c, t) = A[t * r + c], t < ku, c < kv; slot ld = kmax
+  for (int e = tid; e < kmax * kmax; e += 256) {
+    const int t = e % kmax, c = e / kmax;
+    Bs[e] = (t < ku && c < kv) ? A[t * r + c] : 0.0;
+  }
+  __syncthreads();
+  // W = U B  (ma x kv), ld = ma
+  for (int i = tid; i < job.ma; i += 256) {
+    for (int c = 0; c < kv; ++c) {
+      double s = 0.0;
+      for (int t = 0; t < ku; ++t) s += Ua[(int64_t)t * job.ma + i] * A[t * r + c];
+      W[(int64_t)c * job.ma + i] = s;
+    }
+  }
+}
+
+}  // namespace
+
+void launch_pivqr(int32_t njobs, const QrJob *jobs, int32_t r, int32_t rank_fixed, double tol,
+                  int32_t cap, bool f32, const void *S, int64_t lds, double *Wk, double *U,
+                  int32_t *ranks, int32_t *sat, hipStream_t s) {
+  if (njobs <= 0) return;
+  if (f32)
+    pivqr_kernel<float><<<njobs, 256, 0, s>>>(jobs, r, rank_fixed, tol, cap, (const float *)S, lds,
+                                              Wk, U, ranks, sat);
+  else
+    pivqr_kernel<double><<<njobs, 256, 0, s>>>(jobs, r, rank_fixed, tol, cap, (const double *)S,
+                                               lds, Wk, U, ranks, sat);
+}
+
+void launch_core(int32_t njobs, const CoreJob *jobs, int32_t r, bool f32, const void *Psi,
+                 int64_t ldp, const void *Y, int64_t ldy, double *core, hipStream_t s) {
+  if (njobs <= 0) return;
+  const size_t sh = sizeof(double) * (33 * 2 * (size_t)r);
+  if (f32)
+    core_kernel<float><<<njobs, 256, sh, s>>>(jobs, r, (const float *)Psi, ldp, (const float *)Y,
+                                              ldy, core);
+  else
+    core_kernel<double><<<njobs, 256, sh, s>>>(jobs, r, (const double *)Psi, ldp,
+                                               (const double *)Y, ldy, core);
+}
+
+void launch_coupling(int32_t njobs, const CoreJob *jobs, int32_t r, int32_t kmax, bool f32,
+                     const void *Omega, int64_t ldo, const void *Psi, int64_t ldp,
+                     const double *U, const double *V, const int32_t *ranks, const double *core,
+                     double *scratch, double *B, double *W, hipStream_t s) {
+  if (njobs <= 0) return;
+  const size_t sa = ((size_t)r * r > 33 * (size_t)(r + kmax)) ? (size_t)r * r : 33 * (size_t)(r + kmax);
+  const size_t sh = sizeof(double) * (sa + (size_t)r * kmax);
+  if (f32)
+    coupling_kernel<float><<<njobs, 256, sh, s>>>(jobs, r, kmax, (const float *)Omega, ldo,
+                                                  (const float *)Psi, ldp, U, V, ranks, core,
+                                                  scratch, B, W);
+  else
+    coupling_kernel<double><<<njobs, 256, sh, s>>>(jobs, r, kmax, (const double *)Omega, ldo,
+                                                   (const double *)Psi, ldp, U, V, ranks, core,
+                                                   scratch, B, W);
+}
+
+}  // namespace hm

@@ -1,0 +1,126 @@
+// Launchers of the libhm HIP kernels (host-callable, enqueue on `s`).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hm {
+
+// ---- test matrices and data movement (k_misc.hip)
+// Colored Gaussian test matrix of one level/pass: out (n x ncolors*r, ld)
+// in tree order; row i of color block c is nonzero iff active[rowbox[i]*ncol + c].
+void launch_testmat(int64_t n, const int32_t *rowbox, const uint8_t *active, int32_t ncolors,
+                    int32_t r, int32_t level, int32_t pass, uint64_t seed, bool f32, void *out,
+                    int64_t ld, int64_t ncols_pad, hipStream_t s);
+// Identity blocks of the leaf pass: out zeroed (n x ncols_pad), then
+// out[start[b] + t, color*m + t] = 1 for each (b, color) item, t < size(b).
+void launch_leaf_identity(int64_t n, int32_t nitems, const int32_t *item_box,
+                          const int32_t *item_color, const int64_t *box_start, int32_t m,
+                          bool f32, void *out, int64_t ld, int64_t ncols_pad, hipStream_t s);
+void launch_fill(void *p, int64_t count, bool f32, double value, hipStream_t s);
+// Row permutation of a column-major block: dst[i, :] = src[idx[i], :] (gather)
+// or dst[idx[i], :] = src[i, :] (scatter).
+void launch_permute_rows(int64_t n, int64_t ncols, const int64_t *idx, bool scatter, bool f32,
+                         const void *src, int64_t lds, void *dst, int64_t ldd, hipStream_t s);
+// dtype conversion of a column-major block (FP64 <-> FP32).
+void launch_convert(int64_t n, int64_t ncols, bool src_f32, const void *src, int64_t lds,
+                    void *dst, int64_t ldd, hipStream_t s);
+void launch_philox_raw(const uint32_t *ctr, int64_t count, uint32_t k0, uint32_t k1,
+                       uint32_t *out, hipStream_t s);
+// Leaf neighbor blocks: D_p = Y[a0:a0+ma, col0 : col0+mb] for each pair p.
+void launch_extract_near(int32_t np, const int64_t *row0, const int32_t *ma, const int64_t *col0,
+                         const int32_t *mb, const int64_t *dst_off, bool f32, const void *Y,
+                         int64_t ldy, double *D, hipStream_t s);
+// Sets *flag = 1 when the block holds a NaN or Inf (plain store, no atomics).
+void launch_check_finite(int64_t n, int64_t ncols, bool f32, const void *Y, int64_t ldy,
+                         int32_t *flag, hipStream_t s);
+
+// ---- black-box applies (k_kapply.hip, k_lowrank.hip)
+// Y = K X with K(i,j) = kernel(p_i, p_j) generated on the fly (points SoA,
+// tree order), 0 where p_i == p_j.  kernel: 0 = log, 1 = 1/r.
+void launch_kapply(int kernel, int dim, int64_t n, const double *pts, int64_t ncols, bool f32,
+                   const void *X, int64_t ldx, void *Y, int64_t ldy, hipStream_t s);
+// Dense Y = op(A) X, FP64.
+void launch_dense_gemm(int64_t n, const double *A, int64_t lda, bool trans, int64_t ncols,
+                       const double *X, int64_t ldx, double *Y, int64_t ldy, hipStream_t s);
+
+// ---- low-rank products (k_lowrank.hip)
+// Project: T_p[0:k_p, :] = R_p^T X[rows of p, :], one job per pair.  The
+// rank k_p is read from ranks[kidx] on the device; T_p lives at
+// T + tidx * tstride with leading dimension kmax.
+struct ProjJob {
+  int64_t row0;     // first row of the pair's column box in X
+  int64_t rslot;    // element offset of R_p (m x kmax, ld = m)
+  int32_t m;        // rows
+  int32_t kidx;     // index of the rank
+  int32_t tidx;     // T slot
+  int32_t pad;
+};
+// Expand: Y[row0 : row0+nrows, :] += sign * sum_q L_q[off_q : off_q+nrows, 0:k_q] T_q
+struct ExpandChunk {
+  int64_t row0;
+  int32_t nrows;
+  int32_t first, last;  // range in the entry list
+  int32_t pad;
+};
+struct ExpandEntry {
+  int64_t lslot;   // element offset of L_q (ld = mq)
+  int32_t mq;      // leading dimension of L_q (rows of its box)
+  int32_t off;     // row offset of the chunk inside L_q
+  int32_t kidx;
+  int32_t tidx;
+};
+void launch_lr_project(int32_t njobs, const ProjJob *jobs, int32_t kmax, int64_t tstride,
+                       const int32_t *ranks, bool f32, const void *R, const void *X, int64_t ldx,
+                       int64_t ncols, void *T, hipStream_t s);
+void launch_lr_expand(int32_t nchunks, const ExpandChunk *chunks, const ExpandEntry *entries,
+                      int32_t kmax, int64_t tstride, const int32_t *ranks, bool f32,
+                      const void *L, const void *T, int64_t ncols, double sign, void *Y,
+                      int64_t ldy, hipStream_t s);
+// Near field: Y[rows] += sum D_q(off: off+nrows, 0:mb) X[b0 : b0+mb, :]
+struct NearEntry {
+  int64_t dslot;   // element offset of D_q (ld = ma)
+  int64_t xrow0;   // first row of the column box in X
+  int32_t ma;      // leading dimension
+  int32_t mb;      // columns of D_q
+  int32_t off;     // row offset of the chunk inside D_q
+  int32_t pad;
+};
+void launch_near_apply(int32_t nchunks, const ExpandChunk *chunks, const NearEntry *entries,
+                       bool f32, const void *D, const void *X, int64_t ldx, int64_t ncols,
+                       void *Y, int64_t ldy, hipStream_t s);
+
+// ---- per-pair recovery (k_qr.hip)
+struct QrJob {
+  int64_t row0;    // first row of the block in the sample matrix
+  int64_t col0;    // first column (color block)
+  int64_t uslot;   // element offset of the output basis (m x kmax, ld = m)
+  int64_t wslot;   // element offset of the FP64 workspace (m x r, ld = m)
+  int32_t m;       // rows
+  int32_t pad;
+};
+// Column-pivoted Householder QR of S (m x r) in place, truncated by rank /
+// tolerance, and the explicit basis Q[:, 0:k] written to U.  ranks[j] = k,
+// sat[j] = 1 when the tolerance was not met within `cap` columns.
+void launch_pivqr(int32_t njobs, const QrJob *jobs, int32_t r, int32_t rank_fixed, double tol,
+                  int32_t cap, bool f32, const void *S, int64_t lds, double *Wk, double *U,
+                  int32_t *ranks, int32_t *sat, hipStream_t s);
+// C_p = G2^T S_U (r x r) for every pair, into core (np x r x r).
+struct CoreJob {
+  int64_t arow0;   // rows of alpha in Psi / Y
+  int64_t brow0;   // rows of beta in Omega / Z
+  int64_t ucol0;   // Omega / Y color block of the pair
+  int64_t vcol0;   // Psi / Z color block of the pair
+  int64_t uslot, vslot, wslot, bslot, cslot;
+  int32_t ma, mb;
+  int32_t pu, pv;  // index of the pair's U / V rank
+};
+void launch_core(int32_t njobs, const CoreJob *jobs, int32_t r, bool f32, const void *Psi,
+                 int64_t ldp, const void *Y, int64_t ldy, double *core, hipStream_t s);
+// B = (G2^T U)^+ C (V^T G1)^+ and W = U B for every pair.
+void launch_coupling(int32_t njobs, const CoreJob *jobs, int32_t r, int32_t kmax, bool f32,
+                     const void *Omega, int64_t ldo, const void *Psi, int64_t ldp,
+                     const double *U, const double *V, const int32_t *ranks, const double *core,
+                     double *scratch, double *B, double *W, hipStream_t s);
+
+}  // namespace hm

@@ -1,0 +1,291 @@
+"""GPU parity: every step of the path through the C ABI against the oracle.
+
+Tolerances (FP64 path): Philox words bit-exact; Gaussians within 8 ulps
+(libm vs device log/sin/cos); kernel apply within 1e-13 relative Frobenius
+(different summation order over N terms); reconstructed blocks within
+1e-8 of the block norm plus a floor of 1e-12 ||A|| (the tolerance the
+compression itself runs at, far above rounding; a pivot chosen differently
+between near-equal column norms moves the basis but not the block).
+Mixed path (FP32 kernel apply and peel): 1e-5 relative Frobenius against the
+FP64 result.
+"""
+import numpy as np
+import pytest
+
+import workloads
+import oracle
+from synth import exact_h1
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2205_03406_amd as m
+    return m
+
+
+def to_dev(X, dtype=None):
+    X = np.asarray(X)
+    if X.ndim == 1:
+        X = X.reshape(-1, 1)
+    t = torch.from_numpy(np.ascontiguousarray(X.T)).to("cuda")
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.t()
+
+
+def to_host(t):
+    torch.cuda.synchronize()
+    return t.double().cpu().numpy()
+
+
+def test_device_properties(hm):
+    p = torch.cuda.get_device_properties(0)
+    print("device:", p.name, "gcnArch:", getattr(p, "gcnArchName", "?"),
+          "CUs:", p.multi_processor_count, "mem GB:", p.total_memory / 2 ** 30,
+          "smem/block:", getattr(p, "shared_memory_per_block", "?"))
+
+
+def test_philox_known_answers(hm):
+    rows = []
+    for line in open("tests/golden/philox4x32_10_kat.txt"):
+        if not line.startswith("#") and line.strip():
+            rows.append([int(x, 16) for x in line.split()])
+    for w in rows:
+        ctr = np.array(w[:4], np.uint32)
+        c = torch.from_numpy(ctr.view(np.int32)).cuda()
+        out = torch.zeros(4, dtype=torch.int32, device="cuda")
+        hm.philox(c, w[4], w[5], out)
+        got = out.cpu().numpy().view(np.uint32)
+        assert [int(x) for x in got] == w[6:10]
+    # many counters against the oracle
+    rng = np.random.default_rng(1)
+    ctr = rng.integers(0, 2 ** 32, size=(5000, 4), dtype=np.uint64).astype(np.uint32)
+    c = torch.from_numpy(ctr.reshape(-1).view(np.int32)).cuda()
+    out = torch.zeros(5000 * 4, dtype=torch.int32, device="cuda")
+    hm.philox(c, 0x12345678, 0x9abcdef0, out)
+    got = out.cpu().numpy().view(np.uint32).reshape(5000, 4)
+    want = np.stack(oracle.philox4x32_10(ctr[:, 0], ctr[:, 1], ctr[:, 2], ctr[:, 3],
+                                         0x12345678, 0x9abcdef0), axis=1)
+    assert np.array_equal(got, want)
+
+
+TREES = [
+    ("grid", lambda: (workloads.grid_1d(64), 8, "geometric", "strong")),
+    ("hodlr", lambda: (workloads.uniform_line(1024, 1), 64, "index_binary", "weak")),
+    ("curve", lambda: (workloads.star_curve(2048), 64, "geometric", "strong")),
+    ("sphere", lambda: (workloads.sphere(2500, 3), 128, "geometric", "strong")),
+]
+
+
+@pytest.mark.parametrize("name,make", TREES)
+def test_test_matrices(hm, name, make):
+    pts, leaf, kind, adm = make()
+    T = hm.Tree(pts, leaf, kind, adm).color()
+    O = oracle.OTree(pts, leaf, kind, adm)
+    for r in (6, 7):
+        for l in O.sampled_levels():
+            for pas in (0, 1):
+                want = oracle.test_matrix(O, l, pas, 2024, r)
+                out = hm.colmajor(T.n, want.shape[1])
+                T.test_matrix(l, pas, r, 2024, out)
+                got = to_host(out)
+                assert np.array_equal(got == 0, want == 0)
+                nz = want != 0
+                assert np.max(np.abs(got[nz] - want[nz]) / np.abs(want[nz])) < 8 * 2.2e-16 * 4
+                out32 = hm.colmajor(T.n, want.shape[1], dtype=torch.float32)
+                T.test_matrix(l, pas, r, 2024, out32)
+                assert np.allclose(to_host(out32), want.astype(np.float32), rtol=3e-7, atol=0)
+
+
+KAPPLY = [(1, "log", 1000, 37), (2, "log", 1500, 300), (3, "inv_r", 1333, 70), (2, "log", 65, 1),
+          (3, "inv_r", 17, 16), (2, "inv_r", 700, 129), (1, "log", 3000, 257)]
+
+
+@pytest.mark.parametrize("dim,kernel,n,ncols", KAPPLY)
+def test_kernel_apply(hm, dim, kernel, n, ncols):
+    pts = workloads.random_points(n, dim, 100 + n)
+    T = hm.Tree(pts, 32, "geometric", "strong")
+    perm = T.perm()
+    X = np.random.default_rng(n).standard_normal((n, ncols))
+    A = oracle.kernel_matrix(pts, pts, kernel)
+    want = A @ X                               # original order
+    Xd, Yd = to_dev(X), hm.colmajor(n, ncols)
+    T.kernel_apply(kernel, Xd, Yd, order=hm.HM_ORDER_ORIGINAL)
+    got = to_host(Yd)
+    assert np.linalg.norm(got - want) <= 1e-13 * np.linalg.norm(want)
+    Xt = to_dev(X[perm])                       # tree order
+    T.kernel_apply(kernel, Xt, Yd, order=hm.HM_ORDER_TREE)
+    assert np.linalg.norm(to_host(Yd) - want[perm]) <= 1e-13 * np.linalg.norm(want)
+    X32, Y32 = to_dev(X, torch.float32), hm.colmajor(n, ncols, dtype=torch.float32)
+    T.kernel_apply(kernel, X32, Y32, order=hm.HM_ORDER_ORIGINAL)
+    assert np.linalg.norm(to_host(Y32) - want) <= 2e-5 * np.linalg.norm(want)
+
+
+def _block_parity(T, O, Hg, Ho, A, rel=1e-8):
+    floor = 1e-12 * np.linalg.norm(A)
+    perm = O.perm
+    for l in O.sampled_levels():
+        g = Hg.export_level(l)
+        o = Ho.lowrank[l]
+        assert len(g) == len(o)
+        for (a, b, U, B, V), (a2, b2, U2, B2, V2) in zip(g, o):
+            assert (a, b) == (a2, b2)
+            a0, a1 = O.box_range(l, a)
+            b0, b1 = O.box_range(l, b)
+            Ab = A[np.ix_(perm[a0:a1], perm[b0:b1])]
+            d = np.linalg.norm(U @ B @ V.T - U2 @ B2 @ V2.T)
+            assert d <= rel * np.linalg.norm(Ab) + floor, (l, a, b, d, np.linalg.norm(Ab))
+            # orthonormal bases
+            if U.shape[1]:
+                assert np.allclose(U.T @ U, np.eye(U.shape[1]), atol=1e-12)
+            if V.shape[1]:
+                assert np.allclose(V.T @ V, np.eye(V.shape[1]), atol=1e-12)
+    gn = Hg.export_near()
+    assert len(gn) == len(Ho.near)
+    for (a, b, D), (a2, b2, D2) in zip(gn, Ho.near):
+        assert (a, b) == (a2, b2)
+        assert np.linalg.norm(D - D2) <= rel * np.linalg.norm(D2) + floor
+
+
+def _dense_of(hm, H, n):
+    I = hm.colmajor(n, n)
+    I.zero_()
+    I.diagonal().fill_(1.0)
+    Y = hm.colmajor(n, n)
+    H.matvec(I, Y, order=hm.HM_ORDER_ORIGINAL)
+    return to_host(Y)
+
+
+@pytest.mark.parametrize("case", ["strong2d", "curve", "hodlr", "strong3d"])
+def test_exact_recovery_dense_blackbox(hm, case):
+    if case == "strong2d":
+        args = (workloads.random_points(700, 2, 11), 16, "geometric", "strong")
+    elif case == "strong3d":
+        args = (workloads.random_points(900, 3, 12), 24, "geometric", "strong")
+    elif case == "curve":
+        args = (workloads.star_curve(900), 20, "geometric", "strong")
+    else:
+        args = (workloads.uniform_line(512, 3), 32, "index_binary", "weak")
+    O = oracle.OTree(*args)
+    T = hm.Tree(*args).color()
+    A = exact_h1(O, 4, seed=5)
+    Ad = to_dev(A)
+    bb = hm.dense_blackbox(Ad)
+    H = hm.compress(T, bb, rank=4, r=10, seed=77)
+    n = O.n
+    D = _dense_of(hm, H, n)
+    assert np.linalg.norm(D - A) <= 1e-11 * np.linalg.norm(A)
+    Ho = oracle.compress(O, oracle.DenseBlackBox(A), 10, k=4, seed=77)
+    _block_parity(T, O, H, Ho, A, rel=1e-10)
+    st = H.stats()
+    chis = [T.graph(l).ncolors for l in O.sampled_levels()]
+    assert st["cols_At"] == 10 * sum(chis)
+    assert st["cols_A"] == 10 * sum(chis) + T.graph(-1).ncolors * O.leaf_max()
+    # tolerance mode finds the exact ranks
+    Ht = hm.compress(T, bb, tol=1e-9, r=14, seed=78)
+    assert np.linalg.norm(_dense_of(hm, Ht, n) - A) <= 1e-10 * np.linalg.norm(A)
+    assert Ht.stats()["max_rank"] <= 4
+
+
+def test_hodlr_config_parity(hm):
+    inst = workloads.config(0)
+    O = oracle.OTree(inst.points, inst.leaf, inst.tree, inst.adm)
+    T = hm.Tree(inst.points, inst.leaf, inst.tree, inst.adm).color()
+    bb = T.kernel_blackbox(inst.kernel)
+    H = hm.compress(T, bb, rank=inst.rank, r=inst.r, seed=inst.seed)
+    st = H.stats()
+    assert (st["cols_A"], st["cols_At"]) == (304, 240)
+    A = oracle.kernel_matrix(inst.points, inst.points, inst.kernel)
+    Ho = oracle.compress(O, oracle.DenseBlackBox(A), inst.r, k=inst.rank, seed=inst.seed)
+    _block_parity(T, O, H, Ho, A)
+    D = _dense_of(hm, H, O.n)
+    assert np.linalg.norm(D - A) <= 1e-8 * np.linalg.norm(A)
+
+
+@pytest.mark.parametrize("n,r", [(2048, 24), (4096, 24), (3000, 48)])
+def test_curve_tolerance_parity(hm, n, r):
+    inst = workloads.config(1, n=n)
+    O = oracle.OTree(inst.points, inst.leaf, inst.tree, inst.adm)
+    T = hm.Tree(inst.points, inst.leaf, inst.tree, inst.adm).color()
+    bb = T.kernel_blackbox(inst.kernel)
+    H = hm.compress(T, bb, tol=inst.tol, r=r, seed=inst.seed)
+    A = oracle.kernel_matrix(inst.points, inst.points, inst.kernel)
+    Ho = oracle.compress(O, oracle.DenseBlackBox(A), r, tol=inst.tol, seed=inst.seed)
+    _block_parity(T, O, H, Ho, A, rel=10 * inst.tol)
+    D = _dense_of(hm, H, O.n)
+    assert np.linalg.norm(D - A) <= inst.tol * np.linalg.norm(A)
+    assert H.stats()["saturated"] == 0
+
+
+def test_sphere_tolerance_parity(hm):
+    inst = workloads.config(2, n=3000)
+    O = oracle.OTree(inst.points, inst.leaf, inst.tree, inst.adm)
+    T = hm.Tree(inst.points, inst.leaf, inst.tree, inst.adm).color()
+    bb = T.kernel_blackbox(inst.kernel)
+    H = hm.compress(T, bb, tol=inst.tol, r=inst.r, seed=inst.seed)
+    A = oracle.kernel_matrix(inst.points, inst.points, inst.kernel)
+    Ho = oracle.compress(O, oracle.DenseBlackBox(A), inst.r, tol=inst.tol, seed=inst.seed)
+    _block_parity(T, O, H, Ho, A, rel=10 * inst.tol)
+    D = _dense_of(hm, H, O.n)
+    assert np.linalg.norm(D - A) <= 5 * inst.tol * np.linalg.norm(A)
+
+
+def test_matvec_against_exported_factors(hm):
+    inst = workloads.config(1, n=3000)
+    O = oracle.OTree(inst.points, inst.leaf, inst.tree, inst.adm)
+    T = hm.Tree(inst.points, inst.leaf, inst.tree, inst.adm).color()
+    H = hm.compress(T, T.kernel_blackbox("log"), tol=1e-8, r=24, seed=3)
+    Hc = oracle.HMatrix(O)          # the GPU factors, applied by the oracle's loop
+    for l in O.sampled_levels():
+        Hc.lowrank[l] = H.export_level(l)
+    Hc.near = H.export_near()
+    for nrhs in (1, 7, 64):
+        X = np.random.default_rng(nrhs).standard_normal((O.n, nrhs))
+        want = Hc.matvec(X)
+        Y = hm.colmajor(O.n, nrhs)
+        H.matvec(to_dev(X), Y)
+        assert np.linalg.norm(to_host(Y) - want) <= 1e-13 * np.linalg.norm(want)
+        Yt = hm.colmajor(O.n, nrhs)
+        H.matvec(to_dev(X[O.perm]), Yt, order=hm.HM_ORDER_TREE)
+        assert np.linalg.norm(to_host(Yt) - want[O.perm]) <= 1e-13 * np.linalg.norm(want)
+        Y32 = hm.colmajor(O.n, nrhs, dtype=torch.float32)
+        H.matvec(to_dev(X, torch.float32), Y32)
+        assert np.linalg.norm(to_host(Y32) - want) <= 1e-5 * np.linalg.norm(want)
+
+
+def test_mixed_precision_against_fp64(hm):
+    inst = workloads.config(1, n=4096)
+    T = hm.Tree(inst.points, inst.leaf, inst.tree, inst.adm).color()
+    bb = T.kernel_blackbox(inst.kernel)
+    H64 = hm.compress(T, bb, tol=1e-8, r=24, seed=inst.seed)
+    H32 = hm.compress(T, bb, tol=1e-6, r=24, seed=inst.seed, prec=hm.HM_PREC_MIXED)
+    D64 = _dense_of(hm, H64, T.n)
+    D32 = _dense_of(hm, H32, T.n)
+    A = oracle.kernel_matrix(inst.points, inst.points, inst.kernel)
+    e = np.linalg.norm(D32 - D64) / np.linalg.norm(D64)
+    print("mixed vs fp64:", e, "mixed vs dense:", np.linalg.norm(D32 - A) / np.linalg.norm(A))
+    assert e <= 1e-5
+
+
+def test_full_size_star_curve_sampled_rows(hm):
+    """The benchmark workload (N = 16384, tol 1e-8) in the launch shape the
+    benchmark times; rows of H X checked against the kernel rows one by one."""
+    inst = workloads.config(1)
+    T = hm.Tree(inst.points, inst.leaf, inst.tree, inst.adm).color()
+    bb = T.kernel_blackbox(inst.kernel)
+    H = hm.compress(T, bb, tol=inst.tol, r=24, seed=inst.seed)
+    st = H.stats()
+    assert st["saturated"] == 0 and st["max_rank"] <= 14
+    X = np.random.default_rng(5).standard_normal((T.n, 8))
+    Y = hm.colmajor(T.n, 8)
+    H.matvec(to_dev(X), Y)
+    got = to_host(Y)
+    rows = np.random.default_rng(6).choice(T.n, 96, replace=False)
+    kb = oracle.KernelBlackBox(inst.points, inst.kernel, dense_cache=False)
+    want = kb.rows(rows, X)
+    assert np.linalg.norm(got[rows] - want) <= 1e-7 * np.linalg.norm(want)
