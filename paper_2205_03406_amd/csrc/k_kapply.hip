@@ -129,14 +129,17 @@ kapply_kernel(int64_t n, const double *__restrict__ pts, int64_t ncols, const T 
     if (kb + 1 < nk) commit(buf ^ 1);
     __syncthreads();
   }
-  // D layout of the 16x16 MFMA tile: lane l, item i -> row 4*(l/16)+i, col l%16
+  // D layout of the 16x16 tiles, column l%16 for lane l:
+  //   FP32 16x16x4: item i -> row 4*(l/16) + i
+  //   FP64 16x16x4: item i -> row 4*i + l/16   (rows interleaved by item)
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     const int64_t c = col0 + t * 16 + (lane & 15);
     if (c >= ncols) continue;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int64_t rr = row_blk + wave * 16 + 4 * kq + i;
+      const int rin = sizeof(T) == 8 ? 4 * i + kq : 4 * kq + i;
+      const int64_t rr = row_blk + wave * 16 + rin;
       if (rr < n) Y[c * ldy + rr] = (T)acc[t][i];
     }
   }
