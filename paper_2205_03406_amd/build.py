@@ -53,7 +53,7 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
     for src in CXX_SOURCES:
         obj = os.path.join(BUILD, src + ".o")
         objs.append(obj)
-        cmds.append(["g++", "-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-I", CSRC,
+        cmds.append(["g++", "-O2", "-std=c++17", "-fPIC", "-pthread", "-ffp-contract=off", "-I", CSRC,
                      "-c", os.path.join(CSRC, src), "-o", obj])
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         for out in ex.map(_run, cmds):

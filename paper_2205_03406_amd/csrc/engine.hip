@@ -21,6 +21,7 @@
 #include <map>
 #include <memory>
 #include <string>
+#include <thread>
 #include <unordered_map>
 #include <vector>
 
@@ -177,8 +178,14 @@ struct hm_hmatrix {
     int64_t g0 = 0;   // first global pair index
     std::vector<int32_t> pa, pb;
     std::vector<int64_t> offU, offV, offW, offB;
-    hm::DBuf projA, chunksA, entriesA, projT, chunksT, entriesT;
-    int32_t nchA = 0, nchT = 0;
+  };
+  // Apply plan of one orientation (A, or A* with the roles of U and V swapped)
+  struct Orient {
+    hm::DBuf items, ppairs;              // projection work, levels in order
+    std::vector<int32_t> items_upto;     // [li]: items of the first li levels
+    std::vector<int32_t> slots_upto;     // [li]: partial slots of the first li levels
+    std::vector<hm::DBuf> chunks, entries;  // [li]: expand plan of the first li levels
+    std::vector<int32_t> nch;
   };
   int device = 0;
   int64_t n = 0;
@@ -197,6 +204,7 @@ struct hm_hmatrix {
   hm::DBuf nchunks, nentries;
   int32_t nnch = 0;
   int64_t max_np = 0;
+  Orient oA, oT;
   hm_stats stats{};
 };
 
@@ -204,95 +212,165 @@ namespace hm {
 
 namespace {
 
-// Pair-slot layout and apply plans of one level.
-void build_level_plans(hm_hmatrix &H, hm_hmatrix::Lv &L, const Level &Lev, hipStream_t s) {
-  const int64_t np = L.np;
-  const int32_t kmax = H.kmax;
-  auto sz = [&](int b) { return (int32_t)(Lev.start[b + 1] - Lev.start[b]); };
-  // A orientation: project with V over beta, expand with W into alpha rows
-  std::vector<ProjJob> pa(np), pt(np);
-  for (int64_t p = 0; p < np; ++p) {
-    pa[p] = ProjJob{Lev.start[L.pb[p]], L.offV[p], sz(L.pb[p]), (int32_t)(H.np_total + L.g0 + p),
-                    (int32_t)p, 0};
-    pt[p] = ProjJob{Lev.start[L.pa[p]], L.offW[p], sz(L.pa[p]), (int32_t)(H.np_total + L.g0 + p),
-                    (int32_t)p, 0};
-  }
-  auto expand = [&](bool trans, std::vector<ExpandChunk> &ch, std::vector<ExpandEntry> &en) {
-    std::vector<int64_t> order(np);
-    for (int64_t p = 0; p < np; ++p) order[p] = p;
-    const std::vector<int32_t> &rowbox = trans ? L.pb : L.pa;
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int64_t a, int64_t b) { return rowbox[a] < rowbox[b]; });
-    int64_t i = 0;
-    while (i < np) {
-      int64_t j = i;
-      const int rb = rowbox[order[i]];
-      while (j < np && rowbox[order[j]] == rb) ++j;
-      const int32_t m = sz(rb);
-      for (int32_t off = 0; off < m; off += 64) {
-        ExpandChunk c{Lev.start[rb] + off, std::min<int32_t>(64, m - off), (int32_t)en.size(), 0, 0};
-        for (int64_t q = i; q < j; ++q) {
-          const int64_t p = order[q];
-          en.push_back(ExpandEntry{trans ? L.offV[p] : L.offW[p], m, off,
-                                   (int32_t)(H.np_total + L.g0 + p), (int32_t)p});
-        }
-        c.last = (int32_t)en.size();
-        ch.push_back(c);
+constexpr int kSeg = 256;  // rows per projection segment
+
+// Apply plans of both orientations (levels in order).  Projection items
+// group up to 64/kmax pairs that share a column box and cover one segment of
+// it; each pair owns one partial slot per segment.  The expand plan for the
+// first li levels walks 64-row chunks of the finest of them and lists every
+// pair whose row box (at its own level) contains the chunk.
+void build_apply_plans(hm_hmatrix &H, const Tree &T, hipStream_t s) {
+  const int nlv = (int)H.lv.size();
+  const int per_group = std::max(1, 64 / std::max(1, (int)H.kmax));
+  for (int o = 0; o < 2; ++o) {
+    const bool trans = o == 1;
+    hm_hmatrix::Orient &O = trans ? H.oT : H.oA;
+    std::vector<ProjItem> items;
+    std::vector<ProjPair> pps;
+    O.items_upto.assign(1, 0);
+    O.slots_upto.assign(1, 0);
+    std::vector<std::vector<int32_t>> slot_base(nlv), nseg(nlv);
+    int32_t slots = 0;
+    for (int li = 0; li < nlv; ++li) {
+      const hm_hmatrix::Lv &L = H.lv[li];
+      const Level &Lev = T.lev[L.level];
+      const std::vector<int32_t> &colbox = trans ? L.pa : L.pb;
+      const std::vector<int64_t> &roff = trans ? L.offW : L.offV;
+      slot_base[li].resize(L.np);
+      nseg[li].resize(L.np);
+      for (int64_t p = 0; p < L.np; ++p) {
+        const int64_t m = Lev.start[colbox[p] + 1] - Lev.start[colbox[p]];
+        nseg[li][p] = (int32_t)((m + kSeg - 1) / kSeg);
+        slot_base[li][p] = slots;
+        slots += nseg[li][p];
       }
-      i = j;
+      std::vector<int64_t> order(L.np);
+      for (int64_t p = 0; p < L.np; ++p) order[p] = p;
+      std::stable_sort(order.begin(), order.end(),
+                       [&](int64_t a, int64_t b) { return colbox[a] < colbox[b]; });
+      int64_t i = 0;
+      while (i < L.np) {
+        const int cb = colbox[order[i]];
+        int64_t j = i;
+        while (j < L.np && colbox[order[j]] == cb && j - i < per_group) ++j;
+        const int32_t m = (int32_t)(Lev.start[cb + 1] - Lev.start[cb]);
+        for (int32_t sg = 0; sg * kSeg < m; ++sg) {
+          ProjItem it{Lev.start[cb] + (int64_t)sg * kSeg, std::min(kSeg, m - sg * kSeg), sg * kSeg,
+                      m, (int32_t)(j - i), (int32_t)pps.size(), 0};
+          for (int64_t q = i; q < j; ++q) {
+            const int64_t p = order[q];
+            pps.push_back(ProjPair{roff[p], (int32_t)(H.np_total + L.g0 + p), slot_base[li][p] + sg});
+          }
+          items.push_back(it);
+        }
+        i = j;
+      }
+      O.items_upto.push_back((int32_t)items.size());
+      O.slots_upto.push_back(slots);
     }
-  };
-  std::vector<ExpandChunk> ca, ct;
-  std::vector<ExpandEntry> ea, et;
-  expand(false, ca, ea);
-  expand(true, ct, et);
-  upload(L.projA, pa, s);
-  upload(L.projT, pt, s);
-  upload(L.chunksA, ca, s);
-  upload(L.entriesA, ea, s);
-  upload(L.chunksT, ct, s);
-  upload(L.entriesT, et, s);
-  L.nchA = (int32_t)ca.size();
-  L.nchT = (int32_t)ct.size();
+    upload(O.items, items, s);
+    upload(O.ppairs, pps, s);
+    HIP_TRY(hipStreamSynchronize(s));
+    // expand plans
+    O.chunks.clear();
+    O.entries.clear();
+    O.nch.assign(nlv + 1, 0);
+    O.chunks.resize(nlv + 1);
+    O.entries.resize(nlv + 1);
+    // rows grouped by row box, per level
+    std::vector<std::vector<int32_t>> rb_ptr(nlv), rb_idx(nlv);
+    for (int li = 0; li < nlv; ++li) {
+      const hm_hmatrix::Lv &L = H.lv[li];
+      const int nb = T.lev[L.level].nbox();
+      const std::vector<int32_t> &rowbox = trans ? L.pb : L.pa;
+      rb_ptr[li].assign(nb + 1, 0);
+      for (int64_t p = 0; p < L.np; ++p) rb_ptr[li][rowbox[p] + 1]++;
+      for (int b = 0; b < nb; ++b) rb_ptr[li][b + 1] += rb_ptr[li][b];
+      rb_idx[li].resize(L.np);
+      std::vector<int32_t> fill(rb_ptr[li].begin(), rb_ptr[li].end() - 1);
+      for (int64_t p = 0; p < L.np; ++p) rb_idx[li][fill[rowbox[p]]++] = (int32_t)p;
+    }
+    for (int le = 1; le <= nlv; ++le) {
+      const int fl = H.lv[le - 1].level;
+      const Level &F = T.lev[fl];
+      std::vector<ExpandChunk> ch;
+      std::vector<ExpandEntry> en;
+      std::vector<int32_t> anc(le);
+      for (int b = 0; b < F.nbox(); ++b) {
+        // ancestors of b at the levels of the plan
+        int box = b, lvl = fl;
+        for (int li = le - 1; li >= 0; --li) {
+          const int tl = H.lv[li].level;
+          while (lvl > tl) box = T.lev[lvl--].parent[box];
+          anc[li] = box;
+        }
+        const int32_t mb = (int32_t)(F.start[b + 1] - F.start[b]);
+        for (int32_t off = 0; off < mb; off += 64) {
+          ExpandChunk c{F.start[b] + off, std::min<int32_t>(64, mb - off), (int32_t)en.size(), 0, 0};
+          for (int li = 0; li < le; ++li) {
+            const hm_hmatrix::Lv &L = H.lv[li];
+            const Level &Lev = T.lev[L.level];
+            const int a = anc[li];
+            const std::vector<int64_t> &loff = trans ? L.offV : L.offW;
+            for (int32_t q = rb_ptr[li][a]; q < rb_ptr[li][a + 1]; ++q) {
+              const int32_t p = rb_idx[li][q];
+              en.push_back(ExpandEntry{loff[p], (int32_t)(Lev.start[a + 1] - Lev.start[a]),
+                                       (int32_t)(c.row0 - Lev.start[a]),
+                                       (int32_t)(H.np_total + L.g0 + p), slot_base[li][p],
+                                       nseg[li][p], 0});
+            }
+          }
+          c.last = (int32_t)en.size();
+          if (c.last > c.first) ch.push_back(c);
+        }
+      }
+      upload(O.chunks[le], ch, s);
+      upload(O.entries[le], en, s);
+      O.nch[le] = (int32_t)ch.size();
+      HIP_TRY(hipStreamSynchronize(s));
+    }
+  }
 }
 
-// Y +=/-= (levels of H in `li_end`) X, one level at a time; T is scratch of
-// tcap elements.
+// Y +=/-= (first li_end levels of H) X; T is scratch of tcap elements.
 void apply_levels(const hm_hmatrix &H, size_t li_end, bool trans, bool f32, const void *X,
                   int64_t ldx, int64_t ncols, void *Y, int64_t ldy, double sign, void *T,
                   int64_t tcap, hipStream_t s) {
+  if (li_end == 0 || ncols <= 0) return;
+  const hm_hmatrix::Orient &O = trans ? H.oT : H.oA;
+  const int32_t nitems = O.items_upto[li_end];
+  const int64_t nslots = O.slots_upto[li_end];
+  if (nitems == 0 || O.nch[li_end] == 0) return;
   const size_t es = f32 ? 4 : 8;
   const void *Rp = trans ? (f32 ? H.Wf.p : H.W.p) : (f32 ? H.Vf.p : H.V.p);
   const void *Lp = trans ? (f32 ? H.Vf.p : H.V.p) : (f32 ? H.Wf.p : H.W.p);
-  for (size_t li = 0; li < li_end; ++li) {
-    const hm_hmatrix::Lv &L = H.lv[li];
-    if (L.np == 0) continue;
-    int64_t cw = tcap / (L.np * H.kmax);
-    if (cw < 1) throw Error{HM_E_NOMEM, "low-rank scratch too small"};
-    cw = std::min<int64_t>(cw, ncols);
-    if (cw < ncols) cw = std::max<int64_t>(64, cw / 64 * 64);
-    for (int64_t c0 = 0; c0 < ncols; c0 += cw) {
-      const int64_t w = std::min(cw, ncols - c0);
-      const int64_t tstride = (int64_t)H.kmax * w;
-      launch_lr_project((int32_t)L.np, (trans ? L.projT : L.projA).as<ProjJob>(), H.kmax, tstride,
-                        H.ranks.as<int32_t>(), f32, Rp, (const char *)X + c0 * ldx * es, ldx, w, T,
-                        s);
-      LAUNCH_CHECK();
-      launch_lr_expand(trans ? L.nchT : L.nchA, (trans ? L.chunksT : L.chunksA).as<ExpandChunk>(),
-                       (trans ? L.entriesT : L.entriesA).as<ExpandEntry>(), H.kmax, tstride,
-                       H.ranks.as<int32_t>(), f32, Lp, T, w, sign, (char *)Y + c0 * ldy * es,
-                       ldy, s);
-      LAUNCH_CHECK();
-    }
+  int64_t cw = tcap / (nslots * H.kmax);
+  if (cw < 1) throw Error{HM_E_NOMEM, "low-rank scratch too small"};
+  cw = std::min<int64_t>(cw, ncols);
+  if (cw < ncols) cw = std::max<int64_t>(64, cw / 64 * 64);
+  for (int64_t c0 = 0; c0 < ncols; c0 += cw) {
+    const int64_t w = std::min(cw, ncols - c0);
+    const int64_t tstride = (int64_t)H.kmax * w;
+    launch_lr_project(nitems, O.items.as<ProjItem>(), O.ppairs.as<ProjPair>(), H.kmax, tstride,
+                      H.ranks.as<int32_t>(), f32, Rp, (const char *)X + c0 * ldx * es, ldx, w, T,
+                      s);
+    LAUNCH_CHECK();
+    launch_lr_expand(O.nch[li_end], O.chunks[li_end].as<ExpandChunk>(),
+                     O.entries[li_end].as<ExpandEntry>(), H.kmax, tstride, H.ranks.as<int32_t>(),
+                     f32, Lp, T, w, sign, (char *)Y + c0 * ldy * es, ldy, s);
+    LAUNCH_CHECK();
   }
 }
 
 int64_t tscratch_elems(const hm_hmatrix &H, int64_t ncols) {
-  // enough for one level at full width, capped at 64 M elements
-  int64_t need = H.max_np * H.kmax * std::max<int64_t>(ncols, 1);
+  // every partial slot at full width, capped at 64 M elements
+  const int64_t slots = std::max<int32_t>(
+      H.oA.slots_upto.empty() ? 0 : H.oA.slots_upto.back(),
+      H.oT.slots_upto.empty() ? 0 : H.oT.slots_upto.back());
+  int64_t need = slots * H.kmax * std::max<int64_t>(ncols, 1);
   int64_t cap = int64_t(64) << 20;
-  int64_t minimum = H.max_np * H.kmax * 64;
-  return std::max<int64_t>(std::min(need, cap), minimum);
+  int64_t minimum = slots * H.kmax * 64;
+  return std::max<int64_t>(std::min(need, cap), std::max<int64_t>(minimum, 64));
 }
 
 struct Events {
@@ -420,10 +498,7 @@ hm_status compress_impl(Tree &T, const hm_blackbox &bb, const hm_compress_opts &
   launch_fill(H->ranks.p, np_total, true, 0.0, s);  // int32 zeros share the float bit pattern
   launch_fill((char *)H->ranks.p + np_total * 4, np_total, true, 0.0, s);
   LAUNCH_CHECK();
-  for (size_t li = 0; li < H->lv.size(); ++li) {
-    build_level_plans(*H, H->lv[li], T.lev[H->lv[li].level], s);
-    HIP_TRY(hipStreamSynchronize(s));  // plan vectors were host temporaries
-  }
+  build_apply_plans(*H, T, s);
 
   // leaf neighbor blocks
   const Graph &GL = T.leaf_graph();
@@ -849,11 +924,16 @@ hm_status hm_color(int64_t nv, const int64_t *xadj, const int32_t *adj, int32_t 
 hm_status hm_tree_color(hm_tree *tree) {
   API_BEGIN
   if (!tree) return fail(HM_E_ARG, "null tree");
+  // independent graphs: one host thread each
+  std::vector<std::thread> th;
   for (Graph &G : tree->t.graphs) {
     G.color.assign(G.nv(), 0);
-    G.ncolors = dsatur(G.nv(), G.xadj.data(), G.adj.data(), G.color.data());
-    G.colored = true;
+    th.emplace_back([&G] {
+      G.ncolors = dsatur(G.nv(), G.xadj.data(), G.adj.data(), G.color.data());
+      G.colored = true;
+    });
   }
+  for (auto &t : th) t.join();
   return HM_OK;
   API_END
 }

@@ -21,48 +21,91 @@ constexpr int KC = 32;  // contraction chunk
 
 template <typename T>
 __global__ void __launch_bounds__(256)
-lr_project_kernel(const ProjJob *__restrict__ jobs, int32_t kmax, int64_t tstride,
-                  const int32_t *__restrict__ ranks, const T *__restrict__ R,
-                  const T *__restrict__ X, int64_t ldx, int64_t ncols, T *__restrict__ Tout) {
-  __shared__ T Rs[KC][TC + 1];
-  __shared__ T Xs[KC][TC + 1];
-  const ProjJob job = jobs[blockIdx.x];
-  const int k = ranks[job.kidx], m = job.m;
-  if (k <= 0) return;
+lr_project_kernel(const ProjItem *__restrict__ items, const ProjPair *__restrict__ pairs,
+                  int32_t kmax, int64_t tstride, const int32_t *__restrict__ ranks,
+                  const T *__restrict__ R, const T *__restrict__ X, int64_t ldx, int64_t ncols,
+                  T *__restrict__ Tout) {
+  __shared__ T Rs[2][KC][64 + 1];   // [row][pair*kmax + kk]
+  __shared__ T Xs[2][KC][TC + 1];   // [row][col]
+  __shared__ int64_t rsl[64];
+  __shared__ int kk_of[64];
+  const ProjItem it = items[blockIdx.x];
   const int64_t c0 = (int64_t)blockIdx.y * TC;
   const int tid = threadIdx.x;
   const int col = tid & 63, g = tid >> 6;
+  const int nout = it.npairs * kmax;  // output rows of this group (<= 64)
+  if (tid < 64) {
+    const int j = tid / kmax, kk = tid % kmax;
+    int k = 0;
+    int64_t rs = 0;
+    if (j < it.npairs) {
+      const ProjPair pp = pairs[it.first + j];
+      k = ranks[pp.kidx];
+      rs = pp.rslot + it.seg_off;
+    }
+    rsl[tid] = rs;
+    kk_of[tid] = (j < it.npairs && kk < k) ? kk : -1;
+  }
+  __syncthreads();
   T acc[16];
 #pragma unroll
   for (int q = 0; q < 16; ++q) acc[q] = 0;
-  const T *Rp = R + job.rslot;
-  for (int r0 = 0; r0 < m; r0 += KC) {
-    for (int e = tid; e < KC * TC; e += 256) {
-      const int rr = e % KC, cc = e / KC;
+  T rr_[8], xr_[8];
+  auto fetch = [&](int r0) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int e = tid + 256 * q;
+      const int rr = e % KC, o = e / KC;
       const int row = r0 + rr;
-      Rs[rr][cc] = (row < m && cc < k) ? Rp[(int64_t)cc * m + row] : (T)0;
-      const int64_t gc = c0 + cc;
-      Xs[rr][cc] = (row < m && gc < ncols) ? X[gc * ldx + job.row0 + row] : (T)0;
+      const int kk = kk_of[o];
+      rr_[q] = (row < it.nrows && kk >= 0) ? R[rsl[o] + (int64_t)kk * it.m + row] : (T)0;
+      const int64_t gc = c0 + o;
+      xr_[q] = (row < it.nrows && gc < ncols) ? X[gc * ldx + it.row0 + row] : (T)0;
     }
-    __syncthreads();
+  };
+  auto commit = [&](int b) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int e = tid + 256 * q;
+      Rs[b][e % KC][e / KC] = rr_[q];
+      Xs[b][e % KC][e / KC] = xr_[q];
+    }
+  };
+  fetch(0);
+  commit(0);
+  __syncthreads();
+  int b = 0;
+  for (int r0 = 0; r0 < it.nrows; r0 += KC) {
+    const bool more = r0 + KC < it.nrows;
+    if (more) fetch(r0 + KC);
 #pragma unroll 4
     for (int rr = 0; rr < KC; ++rr) {
-      const T xv = Xs[rr][col];
+      const T xv = Xs[b][rr][col];
 #pragma unroll
-      for (int q = 0; q < 16; ++q) acc[q] += Rs[rr][g + 4 * q] * xv;
+      for (int q = 0; q < 16; ++q) acc[q] += Rs[b][rr][g + 4 * q] * xv;
     }
+    if (more) commit(b ^ 1);
     __syncthreads();
+    b ^= 1;
   }
   const int64_t gc = c0 + col;
   if (gc < ncols) {
-    T *Tp = Tout + (int64_t)job.tidx * tstride + gc * kmax;
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
-      const int kk = g + 4 * q;
-      if (kk < k) Tp[kk] = acc[q];
+      const int o = g + 4 * q;
+      if (o < nout && kk_of[o] >= 0) {
+        const ProjPair pp = pairs[it.first + o / kmax];
+        Tout[(int64_t)pp.tslot * tstride + gc * kmax + kk_of[o]] = acc[q];
+      }
     }
   }
 }
+
+// All entries of a chunk form one contraction: their rank columns are laid
+// end to end (prefix sums in LDS), so a 32-deep stage mixes several pairs and
+// no stage waits on a single entry's descriptor.  The next stage is fetched
+// into registers while the current one is multiplied.
+constexpr int EMAX = 256;  // entries handled per pass over a chunk
 
 template <typename T>
 __global__ void __launch_bounds__(256)
@@ -70,8 +113,10 @@ lr_expand_kernel(const ExpandChunk *__restrict__ chunks, const ExpandEntry *__re
                  int32_t kmax, int64_t tstride, const int32_t *__restrict__ ranks,
                  const T *__restrict__ L, const T *__restrict__ Tin, int64_t ncols, T sign,
                  T *__restrict__ Y, int64_t ldy) {
-  __shared__ T Ls[KC][64 + 1];   // [kk][row]
-  __shared__ T Ts[KC][TC + 1];   // [kk][col]
+  __shared__ T Ls[2][KC][64 + 1];   // [kk][row]
+  __shared__ T Ts[2][KC][TC + 1];   // [kk][col]
+  __shared__ int64_t e_l[EMAX];      // lslot + off
+  __shared__ int32_t e_mq[EMAX], e_k[EMAX], e_ts[EMAX], e_ns[EMAX], e_ko[EMAX + 1];
   const ExpandChunk ch = chunks[blockIdx.x];
   const int64_t c0 = (int64_t)blockIdx.y * TC;
   const int tid = threadIdx.x;
@@ -79,28 +124,89 @@ lr_expand_kernel(const ExpandChunk *__restrict__ chunks, const ExpandEntry *__re
   T acc[16];
 #pragma unroll
   for (int q = 0; q < 16; ++q) acc[q] = 0;
-  for (int ei = ch.first; ei < ch.last; ++ei) {
-    const ExpandEntry en = entries[ei];
-    const T *Lp = L + en.lslot;
-    const T *Tp = Tin + (int64_t)en.tidx * tstride;
-    const int kq = ranks[en.kidx];
-    for (int k0 = 0; k0 < kq; k0 += KC) {
-      for (int e = tid; e < KC * 64; e += 256) {
-        const int rr = e % 64, kk = e / 64;
-        Ls[kk][rr] = (rr < ch.nrows && k0 + kk < kq)
-                         ? Lp[(int64_t)(k0 + kk) * en.mq + en.off + rr] : (T)0;
-        const int kt = e % KC, cc = e / KC;
-        const int64_t gc = c0 + cc;
-        Ts[kt][cc] = (k0 + kt < kq && gc < ncols) ? Tp[gc * kmax + k0 + kt] : (T)0;
+
+  for (int e0 = ch.first; e0 < ch.last; e0 += EMAX) {
+    const int ne = min(EMAX, ch.last - e0);
+    if (tid < ne) {
+      const ExpandEntry en = entries[e0 + tid];
+      e_l[tid] = en.lslot + en.off;
+      e_mq[tid] = en.mq;
+      e_k[tid] = ranks[en.kidx];
+      e_ts[tid] = en.tslot;
+      e_ns[tid] = en.nseg;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int acc_k = 0;
+      for (int i = 0; i < ne; ++i) {
+        e_ko[i] = acc_k;
+        acc_k += e_k[i];
       }
-      __syncthreads();
-#pragma unroll 4
-      for (int kk = 0; kk < KC; ++kk) {
-        const T tv = Ts[kk][col];
+      e_ko[ne] = acc_k;
+    }
+    __syncthreads();
+    const int ktot = e_ko[ne];
+    // stage element ownership: 8 L elements and 8 T elements per thread
+    T lr[8], tr[8];
+    auto fetch = [&](int k0) {
 #pragma unroll
-        for (int q = 0; q < 16; ++q) acc[q] += Ls[kk][g + 4 * q] * tv;
+      for (int q = 0; q < 8; ++q) {
+        const int e = tid + 256 * q;
+        // L: (row rr, depth kk); T: (depth kt, column cc)
+        const int rr = e % 64, kk = e / 64;
+        const int kt = e % KC, cc = e / KC;
+        lr[q] = 0;
+        tr[q] = 0;
+        int kg = k0 + kk;
+        if (kg < ktot && rr < ch.nrows) {
+          int lo = 0, hi = ne - 1;  // entry holding depth kg
+          while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (e_ko[mid] <= kg) lo = mid; else hi = mid - 1;
+          }
+          lr[q] = L[e_l[lo] + (int64_t)(kg - e_ko[lo]) * e_mq[lo] + rr];
+        }
+        kg = k0 + kt;
+        const int64_t gc = c0 + cc;
+        if (kg < ktot && gc < ncols) {
+          int lo = 0, hi = ne - 1;
+          while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (e_ko[mid] <= kg) lo = mid; else hi = mid - 1;
+          }
+          const T *tp = Tin + (int64_t)e_ts[lo] * tstride + gc * kmax + (kg - e_ko[lo]);
+          T t = 0;
+          for (int sg = 0; sg < e_ns[lo]; ++sg) t += tp[(int64_t)sg * tstride];
+          tr[q] = t;
+        }
       }
+    };
+    auto commit = [&](int b) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int e = tid + 256 * q;
+        Ls[b][e / 64][e % 64] = lr[q];
+        Ts[b][e % KC][e / KC] = tr[q];
+      }
+    };
+    if (ktot > 0) {
+      fetch(0);
+      commit(0);
       __syncthreads();
+      int b = 0;
+      for (int k0 = 0; k0 < ktot; k0 += KC) {
+        const bool more = k0 + KC < ktot;
+        if (more) fetch(k0 + KC);
+#pragma unroll 4
+        for (int kk = 0; kk < KC; ++kk) {
+          const T tv = Ts[b][kk][col];
+#pragma unroll
+          for (int q = 0; q < 16; ++q) acc[q] += Ls[b][kk][g + 4 * q] * tv;
+        }
+        if (more) commit(b ^ 1);
+        __syncthreads();
+        b ^= 1;
+      }
     }
   }
   const int64_t gc = c0 + col;
@@ -215,17 +321,19 @@ inline unsigned col_tiles(int64_t ncols) { return (unsigned)((ncols + TC - 1) / 
 
 }  // namespace
 
-void launch_lr_project(int32_t njobs, const ProjJob *jobs, int32_t kmax, int64_t tstride,
-                       const int32_t *ranks, bool f32, const void *R, const void *X, int64_t ldx,
-                       int64_t ncols, void *T, hipStream_t s) {
-  if (njobs <= 0 || ncols <= 0) return;
-  dim3 g(njobs, col_tiles(ncols));
+void launch_lr_project(int32_t nitems, const ProjItem *items, const ProjPair *pairs, int32_t kmax,
+                       int64_t tstride, const int32_t *ranks, bool f32, const void *R,
+                       const void *X, int64_t ldx, int64_t ncols, void *T, hipStream_t s) {
+  if (nitems <= 0 || ncols <= 0) return;
+  dim3 g(nitems, col_tiles(ncols));
   if (f32)
-    lr_project_kernel<float><<<g, 256, 0, s>>>(jobs, kmax, tstride, ranks, (const float *)R,
-                                               (const float *)X, ldx, ncols, (float *)T);
+    lr_project_kernel<float><<<g, 256, 0, s>>>(items, pairs, kmax, tstride, ranks,
+                                               (const float *)R, (const float *)X, ldx, ncols,
+                                               (float *)T);
   else
-    lr_project_kernel<double><<<g, 256, 0, s>>>(jobs, kmax, tstride, ranks, (const double *)R,
-                                                (const double *)X, ldx, ncols, (double *)T);
+    lr_project_kernel<double><<<g, 256, 0, s>>>(items, pairs, kmax, tstride, ranks,
+                                                (const double *)R, (const double *)X, ldx, ncols,
+                                                (double *)T);
 }
 
 void launch_lr_expand(int32_t nchunks, const ExpandChunk *chunks, const ExpandEntry *entries,

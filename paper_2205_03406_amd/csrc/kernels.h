@@ -45,18 +45,26 @@ void launch_dense_gemm(int64_t n, const double *A, int64_t lda, bool trans, int6
                        const double *X, int64_t ldx, double *Y, int64_t ldy, hipStream_t s);
 
 // ---- low-rank products (k_lowrank.hip)
-// Project: T_p[0:k_p, :] = R_p^T X[rows of p, :], one job per pair.  The
-// rank k_p is read from ranks[kidx] on the device; T_p lives at
-// T + tidx * tstride with leading dimension kmax.
-struct ProjJob {
-  int64_t row0;     // first row of the pair's column box in X
-  int64_t rslot;    // element offset of R_p (m x kmax, ld = m)
-  int32_t m;        // rows
-  int32_t kidx;     // index of the rank
-  int32_t tidx;     // T slot
+// Project: for one row segment of one column box and a group of pairs that
+// share that column box, T_{p,s}[0:k_p, :] = R_p(segment rows)^T X(segment rows, :).
+// The group holds at most 64 / kmax pairs; ranks are read from ranks[kidx];
+// the partial T_{p,s} lives at T + tslot * tstride (kmax x ncols, ld = kmax).
+struct ProjItem {
+  int64_t row0;     // first X row of the segment
+  int32_t nrows;    // rows in the segment
+  int32_t seg_off;  // row offset of the segment inside the box
+  int32_t m;        // rows of the box (leading dimension of R_p)
+  int32_t npairs;   // pairs in the group
+  int32_t first;    // first entry in the ProjPair list
   int32_t pad;
 };
+struct ProjPair {
+  int64_t rslot;    // element offset of R_p (m x kmax, ld = m)
+  int32_t kidx;     // index of the rank
+  int32_t tslot;    // partial slot of this pair and segment
+};
 // Expand: Y[row0 : row0+nrows, :] += sign * sum_q L_q[off_q : off_q+nrows, 0:k_q] T_q
+// with T_q = sum of its nseg partial slots starting at tslot.
 struct ExpandChunk {
   int64_t row0;
   int32_t nrows;
@@ -68,11 +76,13 @@ struct ExpandEntry {
   int32_t mq;      // leading dimension of L_q (rows of its box)
   int32_t off;     // row offset of the chunk inside L_q
   int32_t kidx;
-  int32_t tidx;
+  int32_t tslot;   // first partial slot
+  int32_t nseg;    // number of partial slots
+  int32_t pad;
 };
-void launch_lr_project(int32_t njobs, const ProjJob *jobs, int32_t kmax, int64_t tstride,
-                       const int32_t *ranks, bool f32, const void *R, const void *X, int64_t ldx,
-                       int64_t ncols, void *T, hipStream_t s);
+void launch_lr_project(int32_t nitems, const ProjItem *items, const ProjPair *pairs, int32_t kmax,
+                       int64_t tstride, const int32_t *ranks, bool f32, const void *R,
+                       const void *X, int64_t ldx, int64_t ncols, void *T, hipStream_t s);
 void launch_lr_expand(int32_t nchunks, const ExpandChunk *chunks, const ExpandEntry *entries,
                       int32_t kmax, int64_t tstride, const int32_t *ranks, bool f32,
                       const void *L, const void *T, int64_t ncols, double sign, void *Y,

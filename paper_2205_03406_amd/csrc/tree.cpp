@@ -10,10 +10,14 @@
 // (a box's neighbors are among the children of its parent's neighbors), so
 // the cost is O(N log N + boxes * 6^d + edges) rather than quadratic.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <set>
+#include <thread>
 #include <tuple>
 #include <unordered_map>
 
@@ -251,25 +255,52 @@ struct Builder {
   // the two active boxes differ.
   void edges(Graph &G, const std::vector<std::vector<int32_t>> &sets, int nboxes) {
     const int64_t nv = G.nv();
-    std::vector<std::vector<int32_t>> by_active(nboxes), containing(nboxes);
+    // CSR: vertices by active box, and vertices whose box set holds a box
+    std::vector<int64_t> pa(nboxes + 1, 0), pc(nboxes + 1, 0);
     for (int64_t v = 0; v < nv; ++v) {
-      by_active[G.vbox[v]].push_back((int32_t)v);
-      for (int32_t g : sets[G.vclass[v]]) containing[g].push_back((int32_t)v);
+      pa[G.vbox[v] + 1]++;
+      for (int32_t g : sets[G.vclass[v]]) pc[g + 1]++;
     }
+    for (int b = 0; b < nboxes; ++b) {
+      pa[b + 1] += pa[b];
+      pc[b + 1] += pc[b];
+    }
+    std::vector<int32_t> by_active(pa[nboxes]), containing(pc[nboxes]);
+    {
+      std::vector<int64_t> fa(pa.begin(), pa.end() - 1), fc(pc.begin(), pc.end() - 1);
+      for (int64_t v = 0; v < nv; ++v) {
+        by_active[fa[G.vbox[v]]++] = (int32_t)v;
+        for (int32_t g : sets[G.vclass[v]]) containing[fc[g]++] = (int32_t)v;
+      }
+    }
+    // each row is marked in a vertex bitmap and read back in ascending order
+    const int64_t words = (nv + 63) / 64;
+    std::vector<uint64_t> mark(words, 0);
+    std::vector<int64_t> touched;
+    auto put = [&](int32_t v) {
+      uint64_t &w = mark[v >> 6];
+      if (!w) touched.push_back(v >> 6);
+      w |= uint64_t(1) << (v & 63);
+    };
     G.xadj.assign(nv + 1, 0);
     G.adj.clear();
-    std::vector<int32_t> row;
     for (int64_t u = 0; u < nv; ++u) {
-      row.clear();
+      touched.clear();
       const int bu = G.vbox[u];
       for (int32_t g : sets[G.vclass[u]])
         if (g != bu)
-          for (int32_t v : by_active[g]) row.push_back(v);
-      for (int32_t v : containing[bu])
-        if (G.vbox[v] != bu) row.push_back(v);
-      std::sort(row.begin(), row.end());
-      row.erase(std::unique(row.begin(), row.end()), row.end());
-      G.adj.insert(G.adj.end(), row.begin(), row.end());
+          for (int64_t q = pa[g]; q < pa[g + 1]; ++q) put(by_active[q]);
+      for (int64_t q = pc[bu]; q < pc[bu + 1]; ++q)
+        if (G.vbox[containing[q]] != bu) put(containing[q]);
+      std::sort(touched.begin(), touched.end());
+      for (int64_t w : touched) {
+        uint64_t bits = mark[w];
+        mark[w] = 0;
+        while (bits) {
+          G.adj.push_back((int32_t)(w * 64 + __builtin_ctzll(bits)));
+          bits &= bits - 1;
+        }
+      }
       G.xadj[u + 1] = (int64_t)G.adj.size();
     }
   }
@@ -301,7 +332,9 @@ struct Builder {
         pcls[P] = it->second;
       }
     }
-    std::map<std::pair<int32_t, int32_t>, int32_t> vid;  // (active, class) -> vertex
+    std::unordered_map<int64_t, int32_t> vid;  // (active, class) -> vertex
+    vid.reserve((size_t)Lv.nbox() * 8);
+    auto vkey = [](int32_t b, int32_t c) { return ((int64_t)b << 32) | (uint32_t)c; };
     std::vector<int32_t> act;
     for (int P = 0; P < nbp; ++P) {
       act.clear();
@@ -312,9 +345,7 @@ struct Builder {
       std::sort(act.begin(), act.end());
       act.erase(std::unique(act.begin(), act.end()), act.end());
       for (int32_t b : act) {
-        auto key = std::make_pair(b, pcls[P]);
-        if (vid.find(key) == vid.end()) {
-          vid.emplace(key, (int32_t)G.vbox.size());
+        if (vid.emplace(vkey(b, pcls[P]), (int32_t)G.vbox.size()).second) {
           G.vbox.push_back(b);
           G.vclass.push_back(pcls[P]);
         }
@@ -324,7 +355,7 @@ struct Builder {
       for (int t = Lv.int_ptr[a]; t < Lv.int_ptr[a + 1]; ++t) {
         G.pa.push_back(a);
         G.pb.push_back(Lv.intl[t]);
-        G.pv.push_back(vid.at({Lv.intl[t], pcls[Lv.parent[a]]}));
+        G.pv.push_back(vid.at(vkey(Lv.intl[t], pcls[Lv.parent[a]])));
       }
     edges(G, sets, Lv.nbox());
   }
@@ -387,57 +418,98 @@ hm_status build_tree(const double *pts, int64_t n, int dim, int leaf, int kind, 
   T.leaf = leaf;
   T.pts.assign(pts, pts + n * dim);
   Builder B(T);
+  const bool timing = std::getenv("HM_TIMING") != nullptr;
+  auto t0 = std::chrono::steady_clock::now();
+  auto lap = [&](const char *what) {
+    if (!timing) return;
+    auto t1 = std::chrono::steady_clock::now();
+    std::fprintf(stderr, "[hm] %s %.2f ms\n", what,
+                 std::chrono::duration<double, std::milli>(t1 - t0).count());
+    t0 = t1;
+  };
   if (kind == HM_TREE_GEOMETRIC)
     B.geometric(pts);
   else
     B.index_binary(pts);
+  lap("tree");
   B.lists();
+  lap("lists");
   T.graphs.resize(T.nlev() + 1);
-  for (int l = 0; l < T.nlev(); ++l) B.level_graph(l, T.graphs[l]);
-  B.leaf_graph(T.graphs.back());
+  // the graphs of different levels are independent: one thread each
+  {
+    std::vector<std::thread> th;
+    for (int l = 0; l < T.nlev(); ++l) th.emplace_back([&B, &T, l] { B.level_graph(l, T.graphs[l]); });
+    th.emplace_back([&B, &T] { B.leaf_graph(T.graphs.back()); });
+    for (auto &t : th) t.join();
+  }
+  lap("graphs");
   return HM_OK;
 }
 
-// DSatur with an ordered set keyed by (-saturation, -degree, id); per-vertex
-// bitsets record which colors already sit on a neighbor.
+// DSatur.  Vertices are ranked once by (degree descending, id ascending); the
+// uncolored vertices of each saturation value sit in a bitset over ranks, so
+// the next vertex is the lowest set rank of the highest non-empty saturation.
+// Per-vertex bitsets record the colors already on a neighbor.
 int32_t dsatur(int64_t nv, const int64_t *xadj, const int32_t *adj, int32_t *color) {
   if (nv <= 0) return 0;
   int64_t maxdeg = 0;
   for (int64_t v = 0; v < nv; ++v) maxdeg = std::max(maxdeg, xadj[v + 1] - xadj[v]);
-  const int64_t words = (maxdeg + 2 + 63) / 64;
-  std::vector<uint64_t> seen((size_t)(nv * words), 0);
+  const int64_t cwords = (maxdeg + 2 + 63) / 64;
+  std::vector<uint64_t> seen((size_t)(nv * cwords), 0);
+  std::vector<int64_t> byrank(nv), rank(nv);
+  for (int64_t v = 0; v < nv; ++v) byrank[v] = v;
+  std::stable_sort(byrank.begin(), byrank.end(), [&](int64_t a, int64_t b) {
+    return xadj[a + 1] - xadj[a] > xadj[b + 1] - xadj[b];
+  });
+  for (int64_t i = 0; i < nv; ++i) rank[byrank[i]] = i;
+  const int64_t words = (nv + 63) / 64;
+  std::vector<std::vector<uint64_t>> level(1, std::vector<uint64_t>(words, 0));
+  std::vector<int64_t> count(1, nv), hint(1, 0);
+  for (int64_t i = 0; i < nv; ++i) level[0][i >> 6] |= uint64_t(1) << (i & 63);
   std::vector<int32_t> sat(nv, 0);
-  using Key = std::tuple<int32_t, int64_t, int64_t>;  // (-sat, -deg, id)
-  std::set<Key> q;
-  for (int64_t v = 0; v < nv; ++v) {
-    color[v] = -1;
-    q.insert(Key(0, -(xadj[v + 1] - xadj[v]), v));
-  }
+  for (int64_t v = 0; v < nv; ++v) color[v] = -1;
+  int64_t top = 0;
   int32_t ncol = 0;
-  while (!q.empty()) {
-    const int64_t v = std::get<2>(*q.begin());
-    q.erase(q.begin());
-    const uint64_t *sv = &seen[(size_t)(v * words)];
+  for (int64_t step = 0; step < nv; ++step) {
+    while (count[top] == 0) --top;
+    std::vector<uint64_t> &L = level[top];
+    int64_t w = hint[top];
+    while (!L[w]) ++w;
+    hint[top] = w;
+    const int64_t rk = w * 64 + __builtin_ctzll(L[w]);
+    L[w] &= L[w] - 1;
+    count[top]--;
+    const int64_t v = byrank[rk];
+    const uint64_t *sv = &seen[(size_t)(v * cwords)];
     int32_t c = 0;
-    for (int64_t w = 0; w < words; ++w) {
-      if (~sv[w]) {
-        c = int32_t(w * 64 + __builtin_ctzll(~sv[w]));
+    for (int64_t q = 0; q < cwords; ++q)
+      if (~sv[q]) {
+        c = int32_t(q * 64 + __builtin_ctzll(~sv[q]));
         break;
       }
-    }
     color[v] = c;
     ncol = std::max(ncol, c + 1);
+    const uint64_t mask = uint64_t(1) << (c % 64);
     for (int64_t t = xadj[v]; t < xadj[v + 1]; ++t) {
-      const int64_t w = adj[t];
-      uint64_t &bit = seen[(size_t)(w * words + c / 64)];
-      const uint64_t mask = uint64_t(1) << (c % 64);
+      const int64_t u = adj[t];
+      uint64_t &bit = seen[(size_t)(u * cwords + c / 64)];
       if (bit & mask) continue;
       bit |= mask;
-      if (color[w] >= 0) continue;
-      const int64_t deg = xadj[w + 1] - xadj[w];
-      q.erase(Key(-sat[w], -deg, w));
-      sat[w]++;
-      q.insert(Key(-sat[w], -deg, w));
+      if (color[u] >= 0) continue;
+      const int64_t ru = rank[u];
+      const int32_t s = sat[u];
+      level[s][ru >> 6] &= ~(uint64_t(1) << (ru & 63));
+      count[s]--;
+      sat[u] = s + 1;
+      if ((int64_t)level.size() <= s + 1) {
+        level.emplace_back(words, 0);
+        count.push_back(0);
+        hint.push_back(words);
+      }
+      level[s + 1][ru >> 6] |= uint64_t(1) << (ru & 63);
+      count[s + 1]++;
+      hint[s + 1] = std::min(hint[s + 1], ru >> 6);
+      top = std::max<int64_t>(top, s + 1);
     }
   }
   return ncol;
