@@ -25,11 +25,49 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int BK = 16;   // k-block (points) staged per LDS buffer
 
+// Natural logarithm of a positive finite x, written from the series
+//   x = 2^e m,  m in [1/sqrt2, sqrt2),  log m = 2 atanh(s) = 2 s sum_k s^(2k)/(2k+1),
+//   s = (m - 1) / (m + 1),  |s| <= 0.1716,
+// truncated after s^22 (next term below 2^-55 relative).  m - 1 is exact;
+// the quotient is refined once from the hardware reciprocal; e ln2 is added
+// in two parts.  About 30 straight-line FP64 instructions, a few ulp.
+__device__ __forceinline__ double log_pos(double x) {
+  int e = __builtin_amdgcn_frexp_exp(x);
+  double m = __builtin_amdgcn_frexp_mant(x);  // [0.5, 1)
+  const bool lo = m < 0.70710678118654752440;
+  m = lo ? 2.0 * m : m;
+  e = lo ? e - 1 : e;
+  const double num = m - 1.0;
+  const double den = m + 1.0;
+  double rc = __builtin_amdgcn_rcp(den);
+  rc = fma(fma(-den, rc, 1.0), rc, rc);
+  rc = fma(fma(-den, rc, 1.0), rc, rc);
+  double s = num * rc;
+  s = fma(fma(-s, den, num), rc, s);
+  const double t = s * s;
+  double p = 1.0 / 23.0;
+  p = fma(p, t, 1.0 / 21.0);
+  p = fma(p, t, 1.0 / 19.0);
+  p = fma(p, t, 1.0 / 17.0);
+  p = fma(p, t, 1.0 / 15.0);
+  p = fma(p, t, 1.0 / 13.0);
+  p = fma(p, t, 1.0 / 11.0);
+  p = fma(p, t, 1.0 / 9.0);
+  p = fma(p, t, 1.0 / 7.0);
+  p = fma(p, t, 1.0 / 5.0);
+  p = fma(p, t, 1.0 / 3.0);
+  const double lm = 2.0 * s + (2.0 * s) * (t * p);
+  const double fe = (double)e;
+  const double ln2_hi = 0.6931471526622772216796875;  // ln2 rounded to 24 bits
+  const double ln2_lo = 2.7897668087737545e-08;       // ln2 - ln2_hi
+  return fe * ln2_hi + (fe * ln2_lo + lm);
+}
+
 template <int KER>
 __device__ __forceinline__ double kval64(double r2) {
-  if (!(r2 > 0.0)) return 0.0;
-  if (KER == 0) return 0.5 * log(r2);
-  return rsqrt(r2);
+  const double safe = r2 > 0.0 ? r2 : 1.0;
+  const double v = KER == 0 ? 0.5 * log_pos(safe) : rsqrt(safe);
+  return r2 > 0.0 ? v : 0.0;
 }
 
 template <int KER>
@@ -70,17 +108,21 @@ kapply_kernel(int64_t n, const double *__restrict__ pts, int64_t ncols, const T 
   constexpr int PER = (BK * BN) / 256;  // elements per thread (NT)
   T xr[PER];
   double pk = 0.0;
+  // Out-of-range elements load from a clamped (valid, finite) address: the
+  // kernel value of a depth beyond n is set to zero, and columns beyond
+  // ncols are never stored, so nothing needs masking and the loads stay in
+  // flight across the MFMA work of the current block.
   auto fetch = [&](int64_t k0) {
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int e = tid + 256 * q;
       const int kr = e % BK, cc = e / BK;
       const int64_t gk = k0 + kr, gc = col0 + cc;
-      xr[q] = (gk < n && gc < ncols) ? X[gc * ldx + gk] : (T)0;
+      xr[q] = X[(gc < ncols ? gc : ncols - 1) * ldx + (gk < n ? gk : n - 1)];
     }
     if (tid < BK * DIM) {
       const int64_t gk = k0 + tid % BK;
-      pk = gk < n ? pts[(int64_t)(tid / BK) * n + gk] : 0.0;
+      pk = pts[(int64_t)(tid / BK) * n + (gk < n ? gk : n - 1)];
     }
   };
   auto commit = [&](int buf) {
@@ -99,31 +141,35 @@ kapply_kernel(int64_t n, const double *__restrict__ pts, int64_t ncols, const T 
   for (int64_t kb = 0; kb < nk; ++kb) {
     const int buf = (int)(kb & 1);
     if (kb + 1 < nk) fetch((kb + 1) * BK);
+    // the block's kernel values first (independent, good ILP), then its
+    // 4 * NT MFMAs; a depth beyond n gets the value 0
+    constexpr int KS = BK / 4;
+    T av[KS];
 #pragma unroll
-    for (int kk = 0; kk < BK; kk += 4) {
-      const int kl = kk + kq;
-      const int64_t gk = kb * BK + kl;
+    for (int s4 = 0; s4 < KS; ++s4) {
+      const int kl = 4 * s4 + kq;
       double r2 = 0.0;
 #pragma unroll
       for (int d = 0; d < DIM; ++d) {
         const double df = pr[d] - Ps[buf][d][kl];
         r2 += df * df;
       }
-      const bool live = gk < n && my_row < n;
-      if constexpr (sizeof(T) == 8) {
-        const double a = live ? kval64<KER>(r2) : 0.0;
+      const bool live = kb * BK + kl < n;
+      if constexpr (sizeof(T) == 8)
+        av[s4] = live ? kval64<KER>(r2) : 0.0;
+      else
+        av[s4] = live ? kval32<KER>((float)r2) : 0.0f;
+    }
 #pragma unroll
-        for (int t = 0; t < NT; ++t) {
-          const double b = Xs[buf][kl][t * 16 + (lane & 15)];
-          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
-        }
-      } else {
-        const float a = live ? kval32<KER>((float)r2) : 0.0f;
+    for (int s4 = 0; s4 < KS; ++s4) {
+      const int kl = 4 * s4 + kq;
 #pragma unroll
-        for (int t = 0; t < NT; ++t) {
-          const float b = Xs[buf][kl][t * 16 + (lane & 15)];
-          acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[t], 0, 0, 0);
-        }
+      for (int t = 0; t < NT; ++t) {
+        const T b = Xs[buf][kl][t * 16 + (lane & 15)];
+        if constexpr (sizeof(T) == 8)
+          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s4], b, acc[t], 0, 0, 0);
+        else
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s4], b, acc[t], 0, 0, 0);
       }
     }
     if (kb + 1 < nk) commit(buf ^ 1);
@@ -165,10 +211,16 @@ void launch_dim(int64_t n, const double *pts, int64_t ncols, const T *X, int64_t
     launch_nt<T, 2, KER, DIM>(n, pts, ncols, X, ldx, Y, ldy, s);
   else if (need <= 4)
     launch_nt<T, 4, KER, DIM>(n, pts, ncols, X, ldx, Y, ldy, s);
+  else if (need <= 6)
+    launch_nt<T, 6, KER, DIM>(n, pts, ncols, X, ldx, Y, ldy, s);
   else if (need <= 8)
     launch_nt<T, 8, KER, DIM>(n, pts, ncols, X, ldx, Y, ldy, s);
+  else if (need <= 10)
+    launch_nt<T, 10, KER, DIM>(n, pts, ncols, X, ldx, Y, ldy, s);
   else if (need <= 12)
     launch_nt<T, 12, KER, DIM>(n, pts, ncols, X, ldx, Y, ldy, s);
+  else if (need <= 14)
+    launch_nt<T, 14, KER, DIM>(n, pts, ncols, X, ldx, Y, ldy, s);
   else
     launch_nt<T, 16, KER, DIM>(n, pts, ncols, X, ldx, Y, ldy, s);
 }
