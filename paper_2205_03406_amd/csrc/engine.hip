@@ -221,7 +221,8 @@ constexpr int kSeg = 256;  // rows per projection segment
 // pair whose row box (at its own level) contains the chunk.
 void build_apply_plans(hm_hmatrix &H, const Tree &T, hipStream_t s) {
   const int nlv = (int)H.lv.size();
-  const int per_group = std::max(1, 64 / std::max(1, (int)H.kmax));
+  // pairs of one column box per projection item, at most 128 rank columns
+  const int per_group = std::max(1, 128 / std::max(1, (int)H.kmax));
   for (int o = 0; o < 2; ++o) {
     const bool trans = o == 1;
     hm_hmatrix::Orient &O = trans ? H.oT : H.oA;
@@ -924,14 +925,18 @@ hm_status hm_color(int64_t nv, const int64_t *xadj, const int32_t *adj, int32_t 
 hm_status hm_tree_color(hm_tree *tree) {
   API_BEGIN
   if (!tree) return fail(HM_E_ARG, "null tree");
-  // independent graphs: one host thread each
+  // independent graphs: the large ones get a host thread each
   std::vector<std::thread> th;
   for (Graph &G : tree->t.graphs) {
     G.color.assign(G.nv(), 0);
-    th.emplace_back([&G] {
+    auto job = [&G] {
       G.ncolors = dsatur(G.nv(), G.xadj.data(), G.adj.data(), G.color.data());
       G.colored = true;
-    });
+    };
+    if (G.adj.size() > (size_t)1 << 20)
+      th.emplace_back(job);
+    else
+      job();
   }
   for (auto &t : th) t.join();
   return HM_OK;

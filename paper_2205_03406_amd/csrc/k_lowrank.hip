@@ -19,114 +19,145 @@ namespace {
 constexpr int TC = 64;  // columns per workgroup
 constexpr int KC = 32;  // contraction chunk
 
+// Both kernels run on the matrix cores: a 64 x 64 output tile per
+// workgroup, wave w owning rows [16w, 16w + 16) as four 16 x 16 MFMA tiles;
+// the contraction is staged 32 deep through LDS (single buffer) with the next
+// stage fetched into registers while the current one is multiplied.  MFMA is
+// used for its issue efficiency on these skinny products (one instruction
+// per 16x16x4 block instead of 16 FMAs and their operand reads).
+typedef double d4v __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
 template <typename T>
-__global__ void __launch_bounds__(256)
+struct Acc;
+template <>
+struct Acc<double> {
+  typedef d4v type;
+  static __device__ __forceinline__ void step(double a, double b, d4v &c) {
+    c = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // row of item i of lane l inside a 16 x 16 tile
+  static __device__ __forceinline__ int row(int i, int lane) { return 4 * i + (lane >> 4); }
+};
+template <>
+struct Acc<float> {
+  typedef f4v type;
+  static __device__ __forceinline__ void step(float a, float b, f4v &c) {
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int i, int lane) { return 4 * (lane >> 4) + i; }
+};
+
+constexpr int PMAX = 128;  // packed output rows of one projection item
+
+// Projection: the pairs of one item share a column box; their rank columns
+// are packed end to end (actual device ranks) into at most PMAX output rows,
+// processed 64 at a time.
+template <typename T>
+__global__ void __launch_bounds__(256, 2)
 lr_project_kernel(const ProjItem *__restrict__ items, const ProjPair *__restrict__ pairs,
                   int32_t kmax, int64_t tstride, const int32_t *__restrict__ ranks,
                   const T *__restrict__ R, const T *__restrict__ X, int64_t ldx, int64_t ncols,
                   T *__restrict__ Tout) {
-  __shared__ T Rs[2][KC][64 + 1];   // [row][pair*kmax + kk]
-  __shared__ T Xs[2][KC][TC + 1];   // [row][col]
-  __shared__ int64_t rsl[64];
-  __shared__ int kk_of[64];
+  __shared__ T As[KC][64 + 1];   // [depth][output row]
+  __shared__ T Bs[KC][TC + 1];   // [depth][col]
+  __shared__ int64_t o_r[PMAX];  // R element offset of output row (segment start)
+  __shared__ int64_t o_t[PMAX];  // T element offset of output row
+  __shared__ int o_tot;
+  typedef typename Acc<T>::type acc_t;
   const ProjItem it = items[blockIdx.x];
   const int64_t c0 = (int64_t)blockIdx.y * TC;
-  const int tid = threadIdx.x;
-  const int col = tid & 63, g = tid >> 6;
-  const int nout = it.npairs * kmax;  // output rows of this group (<= 64)
-  if (tid < 64) {
-    const int j = tid / kmax, kk = tid % kmax;
-    int k = 0;
-    int64_t rs = 0;
-    if (j < it.npairs) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (tid == 0) {
+    int o = 0;
+    for (int j = 0; j < it.npairs; ++j) {
       const ProjPair pp = pairs[it.first + j];
-      k = ranks[pp.kidx];
-      rs = pp.rslot + it.seg_off;
+      const int k = ranks[pp.kidx];
+      for (int kk = 0; kk < k && o < PMAX; ++kk, ++o) {
+        o_r[o] = pp.rslot + it.seg_off + (int64_t)kk * it.m;
+        o_t[o] = (int64_t)pp.tslot * tstride + kk;
+      }
     }
-    rsl[tid] = rs;
-    kk_of[tid] = (j < it.npairs && kk < k) ? kk : -1;
+    o_tot = o;
   }
   __syncthreads();
-  T acc[16];
+  const int nout = o_tot;
+  for (int ob = 0; ob < nout; ob += 64) {
+    acc_t acc[4];
 #pragma unroll
-  for (int q = 0; q < 16; ++q) acc[q] = 0;
-  T rr_[8], xr_[8];
-  auto fetch = [&](int r0) {
+    for (int t = 0; t < 4; ++t) acc[t] = (acc_t){0, 0, 0, 0};
+    T av[8], bv[8];
+    auto fetch = [&](int r0) {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int e = tid + 256 * q;
-      const int rr = e % KC, o = e / KC;
-      const int row = r0 + rr;
-      const int kk = kk_of[o];
-      rr_[q] = (row < it.nrows && kk >= 0) ? R[rsl[o] + (int64_t)kk * it.m + row] : (T)0;
-      const int64_t gc = c0 + o;
-      xr_[q] = (row < it.nrows && gc < ncols) ? X[gc * ldx + it.row0 + row] : (T)0;
+      for (int q = 0; q < 8; ++q) {
+        const int e = tid + 256 * q;
+        const int rr = e % KC, o = e / KC;
+        const int row = r0 + rr;
+        av[q] = (row < it.nrows && ob + o < nout) ? R[o_r[ob + o] + row] : (T)0;
+        const int64_t gc = c0 + o;
+        bv[q] = (row < it.nrows && gc < ncols) ? X[gc * ldx + it.row0 + row] : (T)0;
+      }
+    };
+    fetch(0);
+    for (int r0 = 0; r0 < it.nrows; r0 += KC) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int e = tid + 256 * q;
+        As[e % KC][e / KC] = av[q];
+        Bs[e % KC][e / KC] = bv[q];
+      }
+      __syncthreads();
+      if (r0 + KC < it.nrows) fetch(r0 + KC);
+#pragma unroll
+      for (int ks = 0; ks < KC; ks += 4) {
+        const T a = As[ks + (lane >> 4)][16 * wave + (lane & 15)];
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          Acc<T>::step(a, Bs[ks + (lane >> 4)][16 * t + (lane & 15)], acc[t]);
+      }
+      __syncthreads();
     }
-  };
-  auto commit = [&](int b) {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int e = tid + 256 * q;
-      Rs[b][e % KC][e / KC] = rr_[q];
-      Xs[b][e % KC][e / KC] = xr_[q];
-    }
-  };
-  fetch(0);
-  commit(0);
-  __syncthreads();
-  int b = 0;
-  for (int r0 = 0; r0 < it.nrows; r0 += KC) {
-    const bool more = r0 + KC < it.nrows;
-    if (more) fetch(r0 + KC);
-#pragma unroll 4
-    for (int rr = 0; rr < KC; ++rr) {
-      const T xv = Xs[b][rr][col];
+    for (int t = 0; t < 4; ++t) {
+      const int64_t gc = c0 + 16 * t + (lane & 15);
+      if (gc >= ncols) continue;
 #pragma unroll
-      for (int q = 0; q < 16; ++q) acc[q] += Rs[b][rr][g + 4 * q] * xv;
-    }
-    if (more) commit(b ^ 1);
-    __syncthreads();
-    b ^= 1;
-  }
-  const int64_t gc = c0 + col;
-  if (gc < ncols) {
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int o = g + 4 * q;
-      if (o < nout && kk_of[o] >= 0) {
-        const ProjPair pp = pairs[it.first + o / kmax];
-        Tout[(int64_t)pp.tslot * tstride + gc * kmax + kk_of[o]] = acc[q];
+      for (int i = 0; i < 4; ++i) {
+        const int o = ob + 16 * wave + Acc<T>::row(i, lane);
+        if (o < nout) Tout[o_t[o] + gc * kmax] = acc[t][i];
       }
     }
   }
 }
 
-// All entries of a chunk form one contraction: their rank columns are laid
-// end to end (prefix sums in LDS), so a 32-deep stage mixes several pairs and
-// no stage waits on a single entry's descriptor.  The next stage is fetched
-// into registers while the current one is multiplied.
-constexpr int EMAX = 256;  // entries handled per pass over a chunk
+// Expansion: the entries of a chunk form one contraction of depth
+// sum_e rank_e (actual device ranks, packed end to end); a depth -> (entry,
+// column) table is built per pass of up to EMAX entries.
+constexpr int EMAX = 32;
+constexpr int KTAB = EMAX * 64;
 
 template <typename T>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, 2)
 lr_expand_kernel(const ExpandChunk *__restrict__ chunks, const ExpandEntry *__restrict__ entries,
                  int32_t kmax, int64_t tstride, const int32_t *__restrict__ ranks,
                  const T *__restrict__ L, const T *__restrict__ Tin, int64_t ncols, T sign,
                  T *__restrict__ Y, int64_t ldy) {
-  __shared__ T Ls[2][KC][64 + 1];   // [kk][row]
-  __shared__ T Ts[2][KC][TC + 1];   // [kk][col]
-  __shared__ int64_t e_l[EMAX];      // lslot + off
+  __shared__ T As[KC][64 + 1];   // [depth][row]
+  __shared__ T Bs[KC][TC + 1];   // [depth][col]
+  __shared__ int64_t e_l[EMAX];
   __shared__ int32_t e_mq[EMAX], e_k[EMAX], e_ts[EMAX], e_ns[EMAX], e_ko[EMAX + 1];
+  __shared__ int16_t d_e[KTAB];
+  __shared__ int8_t d_k[KTAB];
+  typedef typename Acc<T>::type acc_t;
   const ExpandChunk ch = chunks[blockIdx.x];
   const int64_t c0 = (int64_t)blockIdx.y * TC;
-  const int tid = threadIdx.x;
-  const int col = tid & 63, g = tid >> 6;
-  T acc[16];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  acc_t acc[4];
 #pragma unroll
-  for (int q = 0; q < 16; ++q) acc[q] = 0;
+  for (int t = 0; t < 4; ++t) acc[t] = (acc_t){0, 0, 0, 0};
 
   for (int e0 = ch.first; e0 < ch.last; e0 += EMAX) {
     const int ne = min(EMAX, ch.last - e0);
+    __syncthreads();
     if (tid < ne) {
       const ExpandEntry en = entries[e0 + tid];
       e_l[tid] = en.lslot + en.off;
@@ -137,86 +168,80 @@ lr_expand_kernel(const ExpandChunk *__restrict__ chunks, const ExpandEntry *__re
     }
     __syncthreads();
     if (tid == 0) {
-      int acc_k = 0;
+      int a = 0;
       for (int i = 0; i < ne; ++i) {
-        e_ko[i] = acc_k;
-        acc_k += e_k[i];
+        e_ko[i] = a;
+        a += e_k[i];
       }
-      e_ko[ne] = acc_k;
+      e_ko[ne] = a;
     }
     __syncthreads();
+    if (tid < ne)
+      for (int kk = 0; kk < e_k[tid]; ++kk) {
+        d_e[e_ko[tid] + kk] = (int16_t)tid;
+        d_k[e_ko[tid] + kk] = (int8_t)kk;
+      }
+    __syncthreads();
     const int ktot = e_ko[ne];
-    // stage element ownership: 8 L elements and 8 T elements per thread
-    T lr[8], tr[8];
+    T av[8], bv[8];
     auto fetch = [&](int k0) {
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         const int e = tid + 256 * q;
-        // L: (row rr, depth kk); T: (depth kt, column cc)
-        const int rr = e % 64, kk = e / 64;
-        const int kt = e % KC, cc = e / KC;
-        lr[q] = 0;
-        tr[q] = 0;
-        int kg = k0 + kk;
-        if (kg < ktot && rr < ch.nrows) {
-          int lo = 0, hi = ne - 1;  // entry holding depth kg
-          while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (e_ko[mid] <= kg) lo = mid; else hi = mid - 1;
+        {
+          const int rr = e % 64, kk = e / 64;   // L (row, depth)
+          const int d = k0 + kk;
+          T v = 0;
+          if (d < ktot && rr < ch.nrows) {
+            const int j = d_e[d];
+            v = L[e_l[j] + (int64_t)d_k[d] * e_mq[j] + rr];
           }
-          lr[q] = L[e_l[lo] + (int64_t)(kg - e_ko[lo]) * e_mq[lo] + rr];
+          av[q] = v;
         }
-        kg = k0 + kt;
-        const int64_t gc = c0 + cc;
-        if (kg < ktot && gc < ncols) {
-          int lo = 0, hi = ne - 1;
-          while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (e_ko[mid] <= kg) lo = mid; else hi = mid - 1;
+        {
+          const int kt = e % KC, cc = e / KC;   // T (depth, column)
+          const int d = k0 + kt;
+          const int64_t gc = c0 + cc;
+          T v = 0;
+          if (d < ktot && gc < ncols) {
+            const int j = d_e[d];
+            const T *tp = Tin + (int64_t)e_ts[j] * tstride + gc * kmax + d_k[d];
+            for (int sg = 0; sg < e_ns[j]; ++sg) v += tp[(int64_t)sg * tstride];
           }
-          const T *tp = Tin + (int64_t)e_ts[lo] * tstride + gc * kmax + (kg - e_ko[lo]);
-          T t = 0;
-          for (int sg = 0; sg < e_ns[lo]; ++sg) t += tp[(int64_t)sg * tstride];
-          tr[q] = t;
+          bv[q] = v;
         }
       }
     };
-    auto commit = [&](int b) {
+    if (ktot > 0) fetch(0);
+    for (int k0 = 0; k0 < ktot; k0 += KC) {
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         const int e = tid + 256 * q;
-        Ls[b][e / 64][e % 64] = lr[q];
-        Ts[b][e % KC][e / KC] = tr[q];
+        As[e / 64][e % 64] = av[q];
+        Bs[e % KC][e / KC] = bv[q];
       }
-    };
-    if (ktot > 0) {
-      fetch(0);
-      commit(0);
       __syncthreads();
-      int b = 0;
-      for (int k0 = 0; k0 < ktot; k0 += KC) {
-        const bool more = k0 + KC < ktot;
-        if (more) fetch(k0 + KC);
-#pragma unroll 4
-        for (int kk = 0; kk < KC; ++kk) {
-          const T tv = Ts[b][kk][col];
+      if (k0 + KC < ktot) fetch(k0 + KC);
 #pragma unroll
-          for (int q = 0; q < 16; ++q) acc[q] += Ls[b][kk][g + 4 * q] * tv;
-        }
-        if (more) commit(b ^ 1);
-        __syncthreads();
-        b ^= 1;
+      for (int ks = 0; ks < KC; ks += 4) {
+        const T a = As[ks + (lane >> 4)][16 * wave + (lane & 15)];
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          Acc<T>::step(a, Bs[ks + (lane >> 4)][16 * t + (lane & 15)], acc[t]);
       }
+      __syncthreads();
     }
   }
-  const int64_t gc = c0 + col;
-  if (gc < ncols) {
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int rr = g + 4 * q;
+  for (int t = 0; t < 4; ++t) {
+    const int64_t gc = c0 + 16 * t + (lane & 15);
+    if (gc >= ncols) continue;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int rr = 16 * wave + Acc<T>::row(i, lane);
       if (rr < ch.nrows) {
         T *y = Y + gc * ldy + ch.row0 + rr;
-        *y += sign * acc[q];
+        *y += sign * acc[t][i];
       }
     }
   }

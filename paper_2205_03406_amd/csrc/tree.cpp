@@ -30,26 +30,33 @@ namespace {
 constexpr int kBits = 21;
 constexpr uint32_t kMaxCell = (1u << kBits) - 1;
 
-// Spread the low 21 bits of v so that bit i lands at bit i*stride.
+// Spread the low 21 bits of v so that bit i lands at bit i*stride
+// (shift-and-mask interleave, stride 1, 2 or 3).
 uint64_t spread(uint32_t v, int stride) {
-  uint64_t out = 0;
-  uint64_t x = v;
-  int pos = 0;
-  while (x) {
-    if (x & 1) out |= uint64_t(1) << (pos * stride);
-    x >>= 1;
-    ++pos;
+  uint64_t x = v & kMaxCell;
+  if (stride == 2) {
+    x = (x | (x << 16)) & 0x0000FFFF0000FFFFull;
+    x = (x | (x << 8)) & 0x00FF00FF00FF00FFull;
+    x = (x | (x << 4)) & 0x0F0F0F0F0F0F0F0Full;
+    x = (x | (x << 2)) & 0x3333333333333333ull;
+    x = (x | (x << 1)) & 0x5555555555555555ull;
+  } else if (stride == 3) {
+    x = (x | (x << 32)) & 0x001F00000000FFFFull;
+    x = (x | (x << 16)) & 0x001F0000FF0000FFull;
+    x = (x | (x << 8)) & 0x100F00F00F00F00Full;
+    x = (x | (x << 4)) & 0x10C30C30C30C30C3ull;
+    x = (x | (x << 2)) & 0x1249249249249249ull;
   }
-  return out;
+  return x;
 }
 
+// Integer cell of one coordinate: floor(((x - lo) / s) * 2^21), clamped.
+// x >= lo, so the quotient is non-negative and truncation is the floor; the
+// division and the (exact) power-of-two product are separate roundings.
 uint32_t cell(double x, double lo, double s) {
-  // Evaluated as written, one rounding per operation (no contraction).
-  volatile double q = (x - lo) / s;
-  double t = q * 2097152.0;
-  double f = std::floor(t);
-  if (f >= double(kMaxCell)) return kMaxCell;
-  return uint32_t(f);
+  const double t = ((x - lo) / s) * 2097152.0;
+  if (t >= double(kMaxCell)) return kMaxCell;
+  return uint32_t(t);
 }
 
 struct Builder {
@@ -435,11 +442,20 @@ hm_status build_tree(const double *pts, int64_t n, int dim, int leaf, int kind, 
   B.lists();
   lap("lists");
   T.graphs.resize(T.nlev() + 1);
-  // the graphs of different levels are independent: one thread each
+  // the graphs of different levels are independent: large levels get a
+  // thread each, small ones are built on this thread
   {
     std::vector<std::thread> th;
-    for (int l = 0; l < T.nlev(); ++l) th.emplace_back([&B, &T, l] { B.level_graph(l, T.graphs[l]); });
-    th.emplace_back([&B, &T] { B.leaf_graph(T.graphs.back()); });
+    for (int l = 0; l < T.nlev(); ++l) {
+      if (T.lev[l].nbox() > 1024)
+        th.emplace_back([&B, &T, l] { B.level_graph(l, T.graphs[l]); });
+      else
+        B.level_graph(l, T.graphs[l]);
+    }
+    if (T.lev[T.L()].nbox() > 1024)
+      th.emplace_back([&B, &T] { B.leaf_graph(T.graphs.back()); });
+    else
+      B.leaf_graph(T.graphs.back());
     for (auto &t : th) t.join();
   }
   lap("graphs");
