@@ -42,6 +42,9 @@ def parse():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run this many steps, no extras (for profilers)")
+    ap.add_argument("--pmc-probe", action="store_true",
+                    help="with --profile-steps: add a 1 GiB device copy that calibrates "
+                         "the FETCH_SIZE / WRITE_SIZE counters")
     return ap.parse_args()
 
 
@@ -51,6 +54,26 @@ def step(hm, inst, bb_kernel, x, y, prec, tol):
     H = hm.compress(T, bb, tol=tol, r=R_COLS, seed=inst.seed, prec=prec, timing=True)
     H.matvec(x, y)
     return T, H
+
+
+def kapply_traffic_bytes():
+    """HBM bytes per kernel-apply launch from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE runs, scaled by the copy calibration), or
+    None when the kernel source changed since the counters were taken."""
+    import hashlib
+    try:
+        txt = open(os.path.join(ROOT, "profiles", "kapply_f64_star_curve_N16384_pmc.md")).read()
+        src = open(os.path.join(ROOT, "paper_2205_03406_amd", "csrc", "k_kapply.hip"), "rb").read()
+    except OSError:
+        return None
+    want = hashlib.sha256(src).hexdigest()[:16]
+    val = h = None
+    for line in txt.splitlines():
+        if line.startswith("kapply traffic bytes per launch:"):
+            val = float(line.split(":")[1])
+        if line.startswith("kapply source sha256 (first 16 hex):"):
+            h = line.split(":")[1].strip()
+    return val if (val is not None and h == want) else None
 
 
 def algorithmic_flops(st):
@@ -104,6 +127,14 @@ def main():
         for _ in range(args.profile_steps):
             step(hm, inst, inst.kernel, x, y, hm.HM_PREC_F64, inst.tol)
         torch.cuda.synchronize()
+        if args.pmc_probe:
+            # calibration for the HBM byte counters: one plain device copy of
+            # 1 GiB (reads 1 GiB, writes 1 GiB)
+            src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+            dst = torch.empty_like(src)
+            torch.cuda.synchronize()
+            dst.copy_(src)
+            torch.cuda.synchronize()
         print("profile run done", flush=True)
         return
 
@@ -147,7 +178,7 @@ def main():
     out["roofline"] = {"kernel": "kapply_kernel<double>", "bound": "mfma",
                        "achieved": round(ach / 1e12, 3), "peak": PEAK_FP64_MFMA / 1e12,
                        "unit": "TFLOP/s", "frac": round(ach / PEAK_FP64_MFMA, 4),
-                       "traffic": None,
+                       "traffic": kapply_traffic_bytes(),
                        "avg_launch_ms": round(r64["bb_ms"] / r64["launches"], 4),
                        "flops_per_launch": r64["bb_flops"] / r64["launches"]}
 
