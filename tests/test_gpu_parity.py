@@ -289,3 +289,30 @@ def test_full_size_star_curve_sampled_rows(hm):
     kb = oracle.KernelBlackBox(inst.points, inst.kernel, dense_cache=False)
     want = kb.rows(rows, X)
     assert np.linalg.norm(got[rows] - want) <= 1e-7 * np.linalg.norm(want)
+
+
+def test_full_size_sphere_sampled_rows(hm):
+    """The 3D workload at full size (N = 65536 on the unit sphere, 1/r kernel,
+    leaves <= 128, tol 1e-6, r = 32: at r = 24 a few blocks reach the rank
+    cap r - p): no rank saturation, and rows of H X against kernel rows
+    computed one by one."""
+    inst = workloads.config(2)
+    T = hm.Tree(inst.points, inst.leaf, inst.tree, inst.adm).color()
+    bb = T.kernel_blackbox(inst.kernel)
+    assert inst.r == 32
+    H = hm.compress(T, bb, tol=inst.tol, r=inst.r, seed=inst.seed)
+    st = H.stats()
+    print("sphere N=65536:", {k: st[k] for k in ("cols_A", "cols_At", "max_rank", "saturated",
+                                               "leaf_colors", "nfloats")},
+          [c for c in st["colors"] if c])
+    assert st["saturated"] == 0
+    X = np.random.default_rng(7).standard_normal((T.n, 4))
+    Y = hm.colmajor(T.n, 4)
+    H.matvec(to_dev(X), Y)
+    got = to_host(Y)
+    rows = np.random.default_rng(8).choice(T.n, 64, replace=False)
+    kb = oracle.KernelBlackBox(inst.points, inst.kernel, dense_cache=False)
+    want = kb.rows(rows, X)
+    err = np.linalg.norm(got[rows] - want) / np.linalg.norm(want)
+    print("sampled-row error", err)
+    assert err <= 10 * inst.tol
