@@ -84,6 +84,30 @@ hm_status hm_build_tree(const double *points, int64_t n, int dim, int leaf_size,
                         int adm, hm_tree **out);
 void hm_tree_free(hm_tree *tree);
 
+/* hm_build_forest: `ninst` independent problems compressed together (the
+ * batched form).  Instance i owns the counts[i] consecutive points of
+ * `points` (host, row-major, sum(counts) x dim, copied) and gets its own tree,
+ * lists and graphs exactly as hm_build_tree builds them.  The forest merges
+ * them level by level: rows of instance i are [off_i, off_i + counts[i]) in
+ * both the original and the tree order (off_i = counts[0] + ... +
+ * counts[i-1]), its boxes precede those of instance i+1 at every level, a
+ * tree shallower than the deepest one carries its leaves down unchanged,
+ * and every graph is the disjoint union of the instances' graphs (vertex
+ * ids instance-major).  No list or graph edge joins two instances, so a
+ * compression of the forest is the compression of the block-diagonal
+ * operator diag(A_0, ..., A_{ninst-1}); the built-in kernel black box
+ * evaluates exactly that, and a user black box must too.  Instance i draws
+ * its test matrices with seed opts->seed + i and its own row numbering, so
+ * its factors are those of a compression of instance i alone (same tree,
+ * colors, seed) up to floating-point summation order.
+ *   counts  host, ninst entries, each >= 1;  ninst >= 1.
+ * Other arguments as hm_build_tree; all instances share them. */
+hm_status hm_build_forest(const double *points, const int64_t *counts, int32_t ninst, int dim,
+                          int leaf_size, int tree_kind, int adm, hm_tree **out);
+/* ninst (always written) and offsets (host, ninst+1, or NULL): row ranges of
+ * the instances; a tree from hm_build_tree is a forest of one instance. */
+hm_status hm_tree_instances(const hm_tree *tree, int32_t *ninst, int64_t *offsets);
+
 /* levels are 0..nlevels-1; nlevels-1 is the leaf level L */
 hm_status hm_tree_info(const hm_tree *tree, int32_t *nlevels, int64_t *n, int32_t *dim);
 /* perm: host, n entries: perm[i] = original index of tree position i */
@@ -129,7 +153,10 @@ hm_status hm_incompat_graph(const hm_tree *tree, int level, int64_t *nv, int64_t
  *   color (host, nv) output; ncolors output. */
 hm_status hm_color(int64_t nv, const int64_t *xadj, const int32_t *adj, int32_t *color,
                    int32_t *ncolors);
-/* Colors every graph of the tree with hm_color and stores the result. */
+/* Colors every graph of the tree with hm_color and stores the result (in a
+ * forest: each instance's component on its own, which gives the colors
+ * hm_color gives on the whole graph; a level's color count is the largest
+ * over the instances). */
 hm_status hm_tree_color(hm_tree *tree);
 /* Installs a caller-chosen coloring of one graph (checked for validity). */
 hm_status hm_tree_set_colors(hm_tree *tree, int level, const int32_t *color);
@@ -184,7 +211,9 @@ void hm_dense_blackbox_free(hm_blackbox *bb);
  * (each cap hit is counted as saturation in hm_stats).
  *
  * Test-matrix entries: Philox4x32-10 keyed by seed, counter (tree row,
- * column/2, color, 4*level + pass), two 53-bit uniforms, Box-Muller.
+ * column/2, color, 4*level + pass), two 53-bit uniforms, Box-Muller.  In a
+ * forest (hm_build_forest) instance i uses key seed + i and its tree row
+ * counted from the instance's first row.
  *
  *   tree   colored (hm_tree_color) tree
  *   bb     black box; its columns are padded to a multiple of 16

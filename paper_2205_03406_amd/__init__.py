@@ -34,7 +34,8 @@ EXPORTED = [
     "hm_tree_set_colors", "hm_tree_colors", "hm_kernel_blackbox", "hm_kernel_apply",
     "hm_dense_blackbox", "hm_dense_blackbox_free", "hm_compress", "hm_hmatrix_free",
     "hm_matvec", "hm_test_matrix", "hm_philox4x32_10", "hm_hmatrix_stats",
-    "hm_hmatrix_export_level", "hm_hmatrix_export_near",
+    "hm_hmatrix_export_level", "hm_hmatrix_export_near", "hm_build_forest",
+    "hm_tree_instances",
 ]
 
 
@@ -88,6 +89,8 @@ def _load():
     lib.hm_last_error.restype = C.c_char_p
     sigs = {
         "hm_build_tree": [P, I64, I, I, I, I, pp],
+        "hm_build_forest": [P, P, C.c_int32, I, I, I, I, pp],
+        "hm_tree_instances": [P, P, P],
         "hm_tree_free": [P],
         "hm_tree_info": [P, P, P, P],
         "hm_tree_perm": [P, P],
@@ -191,14 +194,25 @@ class Tree:
     """hm_build_tree handle (box tree, lists, constraint graphs)."""
 
     def __init__(self, points, leaf, kind="geometric", adm="strong"):
-        pts = np.ascontiguousarray(points, np.float64)
-        if pts.ndim == 1:
-            pts = pts.reshape(-1, 1)
-        n, dim = pts.shape
+        """points: one (n, dim) array, or a list of them for a forest
+        (hm_build_forest: independent instances compressed together)."""
+        kd = HM_TREE_INDEX_BINARY if kind == "index_binary" else HM_TREE_GEOMETRIC
+        ad = HM_ADM_WEAK if adm == "weak" else HM_ADM_STRONG
         h = C.c_void_p()
-        _check(_lib.hm_build_tree(_ptr(pts), n, dim, leaf,
-                                  HM_TREE_INDEX_BINARY if kind == "index_binary" else HM_TREE_GEOMETRIC,
-                                  HM_ADM_WEAK if adm == "weak" else HM_ADM_STRONG, C.byref(h)))
+        if isinstance(points, (list, tuple)):
+            parts = [np.asarray(p, np.float64) for p in points]
+            parts = [p.reshape(-1, 1) if p.ndim == 1 else p for p in parts]
+            pts = np.ascontiguousarray(np.concatenate(parts, axis=0))
+            counts = np.array([p.shape[0] for p in parts], np.int64)
+            n, dim = pts.shape
+            _check(_lib.hm_build_forest(_ptr(pts), _ptr(counts), len(parts), dim, leaf, kd, ad,
+                                        C.byref(h)))
+        else:
+            pts = np.ascontiguousarray(points, np.float64)
+            if pts.ndim == 1:
+                pts = pts.reshape(-1, 1)
+            n, dim = pts.shape
+            _check(_lib.hm_build_tree(_ptr(pts), n, dim, leaf, kd, ad, C.byref(h)))
         self.h = h
         self.n, self.dim, self.leaf = n, dim, leaf
         nl = C.c_int32()
@@ -211,6 +225,14 @@ class Tree:
         if getattr(self, "h", None) and _lib is not None:
             _lib.hm_tree_free(self.h)
             self.h = None
+
+    def instances(self):
+        """Row offsets of the instances (ninst + 1 entries)."""
+        ni = C.c_int32()
+        _check(_lib.hm_tree_instances(self.h, C.byref(ni), None))
+        off = np.zeros(ni.value + 1, np.int64)
+        _check(_lib.hm_tree_instances(self.h, C.byref(ni), _ptr(off)))
+        return off
 
     def perm(self):
         out = np.zeros(self.n, np.int64)

@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -111,7 +112,28 @@ struct DeviceTree {
   DBuf perm;                   // n (tree -> original)
   std::vector<DBuf> rowbox;    // per level: box of every row
   std::vector<DBuf> start;     // per level: box starts
+  DBuf inst_off;               // ninst + 1 row offsets of the instances
+  DBuf kitems;                 // forest: full-width kernel-apply items
+  int32_t nkitems = 0;
 };
+
+// Kernel-apply work items of a forest: every 64-row block of every
+// instance, instances in decreasing size (the long contractions start
+// first); width[i] = live columns of instance i.
+std::vector<KItem> forest_items(const Tree &T, const std::vector<int32_t> &width) {
+  std::vector<int> order(T.ninst());
+  for (int i = 0; i < T.ninst(); ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return T.inst_off[a + 1] - T.inst_off[a] > T.inst_off[b + 1] - T.inst_off[b];
+  });
+  std::vector<KItem> it;
+  for (int i : order) {
+    const int64_t n = T.inst_off[i + 1] - T.inst_off[i];
+    for (int64_t r0 = 0; r0 < n; r0 += 64)
+      it.push_back(KItem{T.inst_off[i], (int32_t)n, (int32_t)r0, width[i], 0});
+  }
+  return it;
+}
 
 DeviceTree &device_tree(Tree &T, hipStream_t s) {
   int dev = 0;
@@ -134,6 +156,12 @@ DeviceTree &device_tree(Tree &T, hipStream_t s) {
     upload(D->rowbox[l], rb, s);
     upload(D->start[l], Lv.start, s);
   }
+  upload(D->inst_off, T.inst_off.empty() ? std::vector<int64_t>{0, T.n} : T.inst_off, s);
+  if (T.ninst() > 1) {
+    std::vector<KItem> it = forest_items(T, std::vector<int32_t>(T.ninst(), INT32_MAX));
+    upload(D->kitems, it, s);
+    D->nkitems = (int32_t)it.size();
+  }
   HIP_TRY(hipStreamSynchronize(s));
   T.dev = D;
   return *D;
@@ -145,12 +173,23 @@ struct KernelBB {
   int kernel;
 };
 
+// Y = K X in tree order; block-diagonal over the instances of a forest.
+void kernel_apply_tree(const Tree &T, int kernel, int64_t ncols, bool f32, const void *X,
+                       int64_t ldx, void *Y, int64_t ldy, hipStream_t s) {
+  const DeviceTree &D = *T.dev;
+  if (T.ninst() > 1)
+    launch_kapply_forest(kernel, T.dim, T.n, D.pts.as<double>(), D.nkitems, D.kitems.as<KItem>(),
+                         ncols, -1, 0, f32, X, ldx, Y, ldy, s);
+  else
+    launch_kapply(kernel, T.dim, T.n, D.pts.as<double>(), ncols, f32, X, ldx, Y, ldy, s);
+}
+
 int kernel_bb_apply(void *ctx, int /*transpose*/, int64_t n, int64_t ncols, int dtype,
                     const void *X, int64_t ldx, void *Y, int64_t ldy, void *stream) {
   KernelBB *k = (KernelBB *)ctx;
   if (!k || !k->tree || !k->tree->dev || n != k->tree->n) return 1;
-  launch_kapply(k->kernel, k->tree->dim, n, k->tree->dev->pts.as<double>(), ncols,
-                dtype == HM_F32, X, ldx, Y, ldy, (hipStream_t)stream);
+  kernel_apply_tree(*k->tree, k->kernel, ncols, dtype == HM_F32, X, ldx, Y, ldy,
+                    (hipStream_t)stream);
   return hipGetLastError() == hipSuccess ? 0 : 2;
 }
 
@@ -565,11 +604,34 @@ hm_status compress_impl(Tree &T, const hm_blackbox &bb, const hm_compress_opts &
   launch_fill(sat.p, std::max<int64_t>(2 * np_total, 1), true, 0.0, s);
   flag.alloc(64);
   launch_fill(flag.p, 1, true, 0.0, s);
+  // mixed path: per-block noise floors of the FP32 samples (see below)
+  DBuf floor_u, floor_v;
+  if (mixed) {
+    floor_u.alloc((size_t)std::max<int64_t>(cmax_np, 1) * 8);
+    floor_v.alloc((size_t)std::max<int64_t>(cmax_np, 1) * 8);
+  }
   LAUNCH_CHECK();
+
+  // ---------------- forest: live columns of each instance per level
+  const int ni = T.ninst();
+  auto inst_colors = [&](int g) {
+    std::vector<int32_t> w(ni, 0);
+    const Graph &Gg = T.graphs[g];
+    for (int i = 0; i < ni; ++i)
+      for (int64_t v = T.gvoff[g][i]; v < T.gvoff[g][i + 1]; ++v)
+        w[i] = std::max(w[i], Gg.color[v] + 1);
+    return w;
+  };
+  // the library's own kernel black box on this forest is called directly
+  // with the per-instance live widths: colors an instance does not use are
+  // zero columns in its rows, and their tiles are skipped
+  KernelBB *kbb = bb.apply == kernel_bb_apply ? (KernelBB *)bb.ctx : nullptr;
+  const bool direct = kbb && kbb->tree == &T && ni > 1;
 
   // ---------------- every job list of every level, uploaded once up front
   struct LevelJobs {
-    DBuf act, ju, jv, jc;
+    DBuf act, ju, jv, jc, kit;
+    int32_t nkit = 0;
   };
   std::vector<LevelJobs> jobs_of(H->lv.size());
   for (size_t li = 0; li < H->lv.size(); ++li) {
@@ -599,6 +661,13 @@ hm_status compress_impl(Tree &T, const hm_blackbox &bb, const hm_compress_opts &
                       L.offW[q], L.offB[q], q * r * r, ma, mb,
                       (int32_t)(L.g0 + q), (int32_t)(np_total + L.g0 + q)};
     }
+    if (direct) {
+      std::vector<int32_t> w = inst_colors(L.level);
+      for (int32_t &x : w) x *= r;
+      std::vector<KItem> kit = forest_items(T, w);
+      upload(jobs_of[li].kit, kit, s);
+      jobs_of[li].nkit = (int32_t)kit.size();
+    }
     upload(jobs_of[li].act, act, s);
     upload(jobs_of[li].ju, ju, s);
     upload(jobs_of[li].jv, jv, s);
@@ -621,12 +690,17 @@ hm_status compress_impl(Tree &T, const hm_blackbox &bb, const hm_compress_opts &
     DBuf &dact = jobs_of[li].act;
     ev.mark(0);
     launch_testmat(n, D.rowbox[l].as<int32_t>(), dact.as<uint8_t>(), G.ncolors, r, l, 0, o.seed,
-                   mixed, Om, n, cpad, s);
+                   D.inst_off.as<int64_t>(), ni, mixed, Om, n, cpad, s);
     launch_testmat(n, D.rowbox[l].as<int32_t>(), dact.as<uint8_t>(), G.ncolors, r, l, 1, o.seed,
-                   mixed, Ps, n, cpad, s);
+                   D.inst_off.as<int64_t>(), ni, mixed, Ps, n, cpad, s);
     LAUNCH_CHECK();
     ev.mark(1);
-    if (bb.symmetric) {
+    if (direct) {
+      launch_kapply_forest(kbb->kernel, T.dim, n, D.pts.as<double>(), jobs_of[li].nkit,
+                           jobs_of[li].kit.as<KItem>(), 2 * cpad, cpad, 0, mixed, Om, n, Yl, n,
+                           s);
+      LAUNCH_CHECK();
+    } else if (bb.symmetric) {
       call_blackbox(bb, 0, n, 2 * cpad, mixed, Om, n, Yl, n, D, tmpx, tmpy, s);
     } else {
       call_blackbox(bb, 0, n, cpad, mixed, Om, n, Yl, n, D, tmpx, tmpy, s);
@@ -634,6 +708,21 @@ hm_status compress_impl(Tree &T, const hm_blackbox &bb, const hm_compress_opts &
     }
     cols_A += c;
     cols_At += c;
+    // Mixed path: a sample block computed in FP32 carries rounding noise of
+    // about 3 u32 ||block||_F before the peel (measured for the compensated
+    // FP32 kernel apply, independent of N).  Rank decisions below
+    // kNoiseGamma u32 ||raw block||_F / sqrt(r) would be decided by that
+    // noise and drive every such block to the rank cap, so the pivoted QR
+    // stops there as well.
+    if (mixed) {
+      constexpr double kNoiseGamma = 8.0;
+      const double scale = kNoiseGamma * 0x1p-24 / std::sqrt((double)r);
+      launch_block_norms((int32_t)L.np, jobs_of[li].ju.as<QrJob>(), r, scale, true, Yb.p, n,
+                         floor_u.as<double>(), s);
+      launch_block_norms((int32_t)L.np, jobs_of[li].jv.as<QrJob>(), r, scale, true, Yb.p, n,
+                         floor_v.as<double>(), s);
+      LAUNCH_CHECK();
+    }
     ev.mark(2);
     apply_levels(*H, li, false, mixed, Om, n, cpad, Yl, n, -1.0, Tb.p, tcap, s);
     apply_levels(*H, li, true, mixed, Ps, n, cpad, Zl, n, -1.0, Tb.p, tcap, s);
@@ -644,11 +733,13 @@ hm_status compress_impl(Tree &T, const hm_blackbox &bb, const hm_compress_opts &
     const int32_t cap = kfix > 0 ? kfix : r - p;
     launch_core((int32_t)L.np, djc.as<CoreJob>(), r, mixed, Xb.p, n, Yb.p, n, core.as<double>(), s);
     LAUNCH_CHECK();
-    launch_pivqr((int32_t)L.np, dju.as<QrJob>(), r, kfix, o.tol, cap, mixed, Yb.p, n,
+    launch_pivqr((int32_t)L.np, dju.as<QrJob>(), r, kfix, o.tol, cap,
+                 mixed ? floor_u.as<double>() : nullptr, mixed, Yb.p, n,
                  work.as<double>(), H->U.as<double>(), H->ranks.as<int32_t>() + L.g0,
                  sat.as<int32_t>() + L.g0, s);
     LAUNCH_CHECK();
-    launch_pivqr((int32_t)L.np, djv.as<QrJob>(), r, kfix, o.tol, cap, mixed, Yb.p, n,
+    launch_pivqr((int32_t)L.np, djv.as<QrJob>(), r, kfix, o.tol, cap,
+                 mixed ? floor_v.as<double>() : nullptr, mixed, Yb.p, n,
                  work.as<double>(), H->V.as<double>(), H->ranks.as<int32_t>() + np_total + L.g0,
                  sat.as<int32_t>() + np_total + L.g0, s);
     LAUNCH_CHECK();
@@ -681,15 +772,28 @@ hm_status compress_impl(Tree &T, const hm_blackbox &bb, const hm_compress_opts &
       ic.push_back(GL.color[v]);
     }
     // one item per (box, color) is enough; duplicates write the same ones
-    DBuf dib, dic;
+    DBuf dib, dic, dkit;
     upload(dib, ib, s);
     upload(dic, ic, s);
+    std::vector<KItem> kit;
+    if (direct) {
+      std::vector<int32_t> w = inst_colors(T.nlev());
+      for (int32_t &x : w) x *= mw;
+      kit = forest_items(T, w);
+      upload(dkit, kit, s);
+    }
     ev.mark(0);
     launch_leaf_identity(n, (int32_t)ib.size(), dib.as<int32_t>(), dic.as<int32_t>(),
                          D.start[T.L()].as<int64_t>(), mw, mixed, Xb.p, n, leaf_cols, s);
     LAUNCH_CHECK();
     ev.mark(1);
-    call_blackbox(bb, 0, n, leaf_cols, mixed, Xb.p, n, Yb.p, n, D, tmpx, tmpy, s);
+    if (direct) {
+      launch_kapply_forest(kbb->kernel, T.dim, n, D.pts.as<double>(), (int32_t)kit.size(),
+                           dkit.as<KItem>(), leaf_cols, -1, 0, mixed, Xb.p, n, Yb.p, n, s);
+      LAUNCH_CHECK();
+    } else {
+      call_blackbox(bb, 0, n, leaf_cols, mixed, Xb.p, n, Yb.p, n, D, tmpx, tmpy, s);
+    }
     cols_A += (int64_t)GL.ncolors * mw;
     ev.mark(2);
     apply_levels(*H, H->lv.size(), false, mixed, Xb.p, n, leaf_cols, Yb.p, n, -1.0, Tb.p, tcap, s);
@@ -745,11 +849,18 @@ hm_status compress_impl(Tree &T, const hm_blackbox &bb, const hm_compress_opts &
   st.nnear = (int64_t)GL.pa.size();
   double fpeel = 0, fqr = 0, fsolve = 0;
   int64_t nfloats = szD;
-  std::vector<double> level_apply_cost;  // per column, levels already compressed
+  // algorithmic work is counted per instance: instance i applies its own
+  // operator to its own live columns and peels its own factors
+  auto inst_of_row = [&](int64_t row) {
+    return (int)(std::upper_bound(T.inst_off.begin(), T.inst_off.end(), row) -
+                 T.inst_off.begin()) - 1;
+  };
+  // apply_cost[li][i]: flops per column of instance i's level-li factors
+  std::vector<std::vector<double>> apply_cost_of(H->lv.size(), std::vector<double>(ni, 0.0));
   for (size_t li = 0; li < H->lv.size(); ++li) {
     const hm_hmatrix::Lv &L = H->lv[li];
     const Level &Lv = T.lev[L.level];
-    double apply_cost = 0;
+    std::vector<double> &apply_cost = apply_cost_of[li];
     for (int64_t q = 0; q < L.np; ++q) {
       const int64_t ma = Lv.start[L.pa[q] + 1] - Lv.start[L.pa[q]];
       const int64_t mb = Lv.start[L.pb[q] + 1] - Lv.start[L.pb[q]];
@@ -757,26 +868,41 @@ hm_status compress_impl(Tree &T, const hm_blackbox &bb, const hm_compress_opts &
       st.max_rank = std::max(st.max_rank, std::max(ku, kv));
       st.saturated += hsat[L.g0 + q] + hsat[np_total + L.g0 + q];
       nfloats += ma * ku + (int64_t)ku * kv + mb * kv;
-      apply_cost += 2.0 * kv * (ma + mb);
+      apply_cost[ni > 1 ? inst_of_row(Lv.start[L.pa[q]]) : 0] += 2.0 * kv * (ma + mb);
       fqr += qr_flops(ma, r, ku) + qr_flops(mb, r, kv);
       fsolve += 2.0 * ma * r * r + 2.0 * ma * r * ku + 2.0 * mb * r * kv + 4.0 * r * ku * ku +
                 4.0 * r * kv * kv + 2.0 * r * r * (ku + kv) + 2.0 * ma * ku * kv;
     }
-    level_apply_cost.push_back(apply_cost);
   }
-  for (size_t li = 0; li < H->lv.size(); ++li) {
-    const double c = (double)T.graphs[H->lv[li].level].ncolors * r;
-    double prev = 0;
-    for (size_t j = 0; j < li; ++j) prev += level_apply_cost[j];
-    fpeel += 2.0 * c * prev;  // Y and Z passes
-  }
+  double fbb = 0;
   {
-    double all = 0;
-    for (double v : level_apply_cost) all += v;
-    fpeel += (double)GL.ncolors * mw * all;
+    std::vector<double> prev(ni, 0.0);
+    for (size_t li = 0; li < H->lv.size(); ++li) {
+      const std::vector<int32_t> w = inst_colors(H->lv[li].level);
+      for (int i = 0; i < ni; ++i) {
+        const double c = (double)w[i] * r;
+        const double ni_rows = (double)(T.inst_off[i + 1] - T.inst_off[i]);
+        fpeel += 2.0 * c * prev[i];  // Y and Z passes
+        fbb += 2.0 * ni_rows * ni_rows * 2.0 * c;
+      }
+      for (int i = 0; i < ni; ++i) prev[i] += apply_cost_of[li][i];
+    }
+    // leaf pass: an instance's identity blocks are as wide as its own
+    // largest leaf
+    const std::vector<int32_t> wl = inst_colors(T.nlev());
+    std::vector<int64_t> mwi(ni, 0);
+    for (int b = 0; b < LL.nbox(); ++b) {
+      const int i = ni > 1 ? inst_of_row(LL.start[b]) : 0;
+      mwi[i] = std::max(mwi[i], LL.start[b + 1] - LL.start[b]);
+    }
+    for (int i = 0; i < ni; ++i) {
+      const double ni_rows = (double)(T.inst_off[i + 1] - T.inst_off[i]);
+      fpeel += (double)wl[i] * mwi[i] * prev[i];
+      fbb += 2.0 * ni_rows * ni_rows * (double)wl[i] * mwi[i];
+    }
   }
   st.nfloats = nfloats;
-  st.flops_blackbox = 2.0 * (double)n * n * (double)(cols_A + cols_At);
+  st.flops_blackbox = fbb;
   st.flops_peel = fpeel;
   st.flops_qr = fqr;
   st.flops_solve = fsolve;
@@ -840,6 +966,46 @@ hm_status hm_build_tree(const double *points, int64_t n, int dim, int leaf_size,
   *out = t.release();
   return HM_OK;
   API_END
+}
+
+hm_status hm_build_forest(const double *points, const int64_t *counts, int32_t ninst, int dim,
+                          int leaf_size, int tree_kind, int adm, hm_tree **out) {
+  API_BEGIN
+  if (!points || !counts || !out || ninst < 1 || dim < 1 || dim > 3 || leaf_size < 1)
+    return fail(HM_E_ARG, "hm_build_forest: bad argument");
+  if (tree_kind != HM_TREE_GEOMETRIC && tree_kind != HM_TREE_INDEX_BINARY)
+    return fail(HM_E_ARG, "hm_build_forest: bad tree kind");
+  if (adm != HM_ADM_STRONG && adm != HM_ADM_WEAK) return fail(HM_E_ARG, "hm_build_forest: bad adm");
+  if (tree_kind == HM_TREE_INDEX_BINARY && adm != HM_ADM_WEAK)
+    return fail(HM_E_ARG, "hm_build_forest: the index-halving tree needs weak admissibility");
+  int64_t n = 0;
+  for (int32_t i = 0; i < ninst; ++i) {
+    if (counts[i] < 1) return fail(HM_E_ARG, "hm_build_forest: empty instance");
+    n += counts[i];
+  }
+  if (n > INT32_MAX) return fail(HM_E_ARG, "hm_build_forest: more than 2^31 - 1 points");
+  for (int64_t i = 0; i < n * dim; ++i)
+    if (!std::isfinite(points[i])) return fail(HM_E_ARG, "hm_build_forest: non-finite point");
+  auto t = std::make_unique<hm_tree>();
+  hm_status st = build_forest(points, counts, ninst, dim, leaf_size, tree_kind, adm, t->t);
+  if (st != HM_OK) return st;
+  *out = t.release();
+  return HM_OK;
+  API_END
+}
+
+hm_status hm_tree_instances(const hm_tree *tree, int32_t *ninst, int64_t *offsets) {
+  if (!tree || !ninst) return fail(HM_E_ARG, "null argument");
+  *ninst = tree->t.ninst();
+  if (offsets) {
+    if (tree->t.inst_off.empty()) {
+      offsets[0] = 0;
+      offsets[1] = tree->t.n;
+    } else {
+      std::memcpy(offsets, tree->t.inst_off.data(), tree->t.inst_off.size() * 8);
+    }
+  }
+  return HM_OK;
 }
 
 void hm_tree_free(hm_tree *tree) { delete tree; }
@@ -925,20 +1091,67 @@ hm_status hm_color(int64_t nv, const int64_t *xadj, const int32_t *adj, int32_t 
 hm_status hm_tree_color(hm_tree *tree) {
   API_BEGIN
   if (!tree) return fail(HM_E_ARG, "null tree");
-  // independent graphs: the large ones get a host thread each
-  std::vector<std::thread> th;
-  for (Graph &G : tree->t.graphs) {
+  Tree &T = tree->t;
+  // One DSatur run per (graph, instance): the instances of a forest are
+  // disconnected components, and DSatur restricted to one component takes
+  // the same choices as on the whole graph (saturation and degree are
+  // component-local, ties go to the lower id, which keeps its order), so
+  // coloring them apart gives the same colors.  Large jobs run on a pool.
+  struct Job {
+    Graph *G;
+    int64_t v0, v1;
+  };
+  std::vector<Job> jobs;
+  int64_t total = 0;
+  for (size_t g = 0; g < T.graphs.size(); ++g) {
+    Graph &G = T.graphs[g];
     G.color.assign(G.nv(), 0);
-    auto job = [&G] {
-      G.ncolors = dsatur(G.nv(), G.xadj.data(), G.adj.data(), G.color.data());
-      G.colored = true;
-    };
-    if (G.adj.size() > (size_t)1 << 20)
-      th.emplace_back(job);
-    else
-      job();
+    G.ncolors = 0;
+    for (int i = 0; i < T.ninst(); ++i) {
+      const int64_t v0 = T.gvoff[g][i], v1 = T.gvoff[g][i + 1];
+      if (v1 > v0) {
+        jobs.push_back(Job{&G, v0, v1});
+        total += G.xadj[v1] - G.xadj[v0];
+      }
+    }
   }
-  for (auto &t : th) t.join();
+  std::vector<int32_t> ncol(jobs.size(), 0);
+  auto run = [&](size_t j) {
+    const Job &J = jobs[j];
+    const Graph &G = *J.G;
+    const int64_t nv = J.v1 - J.v0;
+    if (J.v0 == 0) {
+      ncol[j] = dsatur(nv, G.xadj.data(), G.adj.data(), J.G->color.data());
+      return;
+    }
+    std::vector<int64_t> xa(nv + 1);
+    for (int64_t v = 0; v <= nv; ++v) xa[v] = G.xadj[J.v0 + v] - G.xadj[J.v0];
+    std::vector<int32_t> ad(G.adj.begin() + G.xadj[J.v0], G.adj.begin() + G.xadj[J.v1]);
+    for (int32_t &u : ad) u -= (int32_t)J.v0;
+    ncol[j] = dsatur(nv, xa.data(), ad.data(), J.G->color.data() + J.v0);
+  };
+  if (total < (int64_t(1) << 20) || jobs.size() == 1) {
+    for (size_t j = 0; j < jobs.size(); ++j) run(j);
+  } else {
+    std::vector<size_t> order(jobs.size());
+    for (size_t j = 0; j < jobs.size(); ++j) order[j] = j;
+    std::sort(order.begin(), order.end(), [&](size_t a, size_t b) {
+      return jobs[a].G->xadj[jobs[a].v1] - jobs[a].G->xadj[jobs[a].v0] >
+             jobs[b].G->xadj[jobs[b].v1] - jobs[b].G->xadj[jobs[b].v0];
+    });
+    std::atomic<size_t> next{0};
+    const int nth = std::max(1, std::min<int>((int)jobs.size(),
+                                              (int)std::thread::hardware_concurrency()));
+    std::vector<std::thread> th;
+    for (int t = 0; t < nth; ++t)
+      th.emplace_back([&] {
+        for (size_t q = next++; q < order.size(); q = next++) run(order[q]);
+      });
+    for (auto &t : th) t.join();
+  }
+  for (size_t j = 0; j < jobs.size(); ++j)
+    jobs[j].G->ncolors = std::max(jobs[j].G->ncolors, ncol[j]);
+  for (Graph &G : T.graphs) G.colored = true;
   return HM_OK;
   API_END
 }
@@ -1000,7 +1213,7 @@ hm_status hm_kernel_apply(hm_tree *tree, int kernel, int64_t ncols, int dtype, c
   const bool f32 = dtype == HM_F32;
   const int64_t n = tree->t.n;
   if (order == HM_ORDER_TREE) {
-    launch_kapply(kernel, tree->t.dim, n, D.pts.as<double>(), ncols, f32, X, ldx, Y, ldy, s);
+    kernel_apply_tree(tree->t, kernel, ncols, f32, X, ldx, Y, ldy, s);
     LAUNCH_CHECK();
     return HM_OK;
   }
@@ -1009,7 +1222,7 @@ hm_status hm_kernel_apply(hm_tree *tree, int kernel, int64_t ncols, int dtype, c
   tx.alloc((size_t)n * std::max<int64_t>(ncols, 1) * es);
   ty.alloc((size_t)n * std::max<int64_t>(ncols, 1) * es);
   launch_permute_rows(n, ncols, D.perm.as<int64_t>(), false, f32, X, ldx, tx.p, n, s);
-  launch_kapply(kernel, tree->t.dim, n, D.pts.as<double>(), ncols, f32, tx.p, n, ty.p, n, s);
+  kernel_apply_tree(tree->t, kernel, ncols, f32, tx.p, n, ty.p, n, s);
   launch_permute_rows(n, ncols, D.perm.as<int64_t>(), true, f32, ty.p, n, Y, ldy, s);
   LAUNCH_CHECK();
   HIP_TRY(hipStreamSynchronize(s));
@@ -1107,7 +1320,8 @@ hm_status hm_test_matrix(const hm_tree *tree, int level, int pass, int32_t r, ui
   DBuf dact;
   upload(dact, act, s);
   launch_testmat(tree->t.n, D.rowbox[level].as<int32_t>(), dact.as<uint8_t>(), G.ncolors, r,
-                 level, pass, seed, dtype == HM_F32, out, ld, (int64_t)G.ncolors * r, s);
+                 level, pass, seed, D.inst_off.as<int64_t>(), tree->t.ninst(), dtype == HM_F32,
+                 out, ld, (int64_t)G.ncolors * r, s);
   LAUNCH_CHECK();
   HIP_TRY(hipStreamSynchronize(s));
   return HM_OK;

@@ -51,9 +51,16 @@ struct Tree {
   std::vector<int64_t> perm;      // tree position -> original index
   std::vector<Level> lev;
   std::vector<Graph> graphs;      // one per level + the leaf graph last
+  // A forest holds independent instances side by side: instance i owns rows
+  // [inst_off[i], inst_off[i+1]) in both orders, its boxes come before those
+  // of instance i+1 at every level, and gvoff[g][i] is its first vertex in
+  // graph g.  A single tree is a forest of one instance.
+  std::vector<int64_t> inst_off;
+  std::vector<std::vector<int64_t>> gvoff;
   std::shared_ptr<DeviceTree> dev;
   std::vector<std::shared_ptr<void>> keep;  // objects whose lifetime is the tree's
   int nlev() const { return (int)lev.size(); }
+  int ninst() const { return inst_off.empty() ? 1 : (int)inst_off.size() - 1; }
   int L() const { return nlev() - 1; }
   Graph &leaf_graph() { return graphs.back(); }
   const Graph &leaf_graph() const { return graphs.back(); }
@@ -63,6 +70,12 @@ struct Tree {
 
 hm_status build_tree(const double *pts, int64_t n, int dim, int leaf, int kind, int adm,
                      Tree &T);
+// Independent trees over consecutive point ranges (counts[i] points each),
+// merged level by level; shallower trees carry their leaves down to the
+// deepest level, so level l of the forest is the union of the instances'
+// level-l partitions.
+hm_status build_forest(const double *pts, const int64_t *counts, int ninst, int dim, int leaf,
+                       int kind, int adm, Tree &F);
 int32_t dsatur(int64_t nv, const int64_t *xadj, const int32_t *adj, int32_t *color);
 
 }  // namespace hm

@@ -77,10 +77,16 @@ __device__ __forceinline__ float kval32(float r2) {
   return rsqrtf(r2);
 }
 
-template <typename T, int NT, int KER, int DIM>
+// SEG = false: the whole operator, grid (row blocks, column tiles).
+// SEG = true: block-diagonal (forest) form, a 1-D grid over (item, column
+// tile) pairs, column tile fastest; all indices below are relative to the
+// item's instance (rows, depth and point coordinates start at its base row),
+// and n stays the stride of the point coordinates.
+template <typename T, int NT, int KER, int DIM, bool SEG>
 __global__ void __launch_bounds__(256)
-kapply_kernel(int64_t n, const double *__restrict__ pts, int64_t ncols, const T *__restrict__ X,
-              int64_t ldx, T *__restrict__ Y, int64_t ldy) {
+kapply_kernel(int64_t n, const double *__restrict__ pts_all, int64_t ncols,
+              const T *__restrict__ X_all, int64_t ldx, T *__restrict__ Y_all, int64_t ldy,
+              const KItem *__restrict__ items, int64_t split) {
   constexpr int BN = 16 * NT;
   constexpr int LDT = BN + 2;
   __shared__ T Xs[2][BK][LDT];
@@ -89,19 +95,47 @@ kapply_kernel(int64_t n, const double *__restrict__ pts, int64_t ncols, const T 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int64_t row_blk = (int64_t)blockIdx.x * 64;
-  const int64_t col0 = (int64_t)blockIdx.y * BN;
+  int64_t row_blk, col0, base = 0, nloc = n;
+  bool live = true;
+  if constexpr (SEG) {
+    const int64_t nct = (ncols + BN - 1) / BN;
+    const KItem it = items[blockIdx.x / nct];
+    col0 = (int64_t)(blockIdx.x % nct) * BN;
+    row_blk = it.rblk;
+    base = it.base;
+    nloc = it.nloc;
+    live = col0 < it.width || (split >= 0 && col0 + BN > split && col0 < split + it.width);
+  } else {
+    row_blk = (int64_t)blockIdx.x * 64;
+    col0 = (int64_t)blockIdx.y * BN;
+  }
+  const double *__restrict__ pts = pts_all + base;
+  const T *__restrict__ X = X_all + base;
+  T *__restrict__ Y = Y_all + base;
   const int64_t my_row = row_blk + wave * 16 + (lane & 15);
   const int kq = lane >> 4;  // depth index of this lane inside an MFMA step
 
   double pr[DIM];
 #pragma unroll
-  for (int d = 0; d < DIM; ++d) pr[d] = my_row < n ? pts[(int64_t)d * n + my_row] : 0.0;
+  for (int d = 0; d < DIM; ++d) pr[d] = my_row < nloc ? pts[(int64_t)d * n + my_row] : 0.0;
 
   typedef typename std::conditional<sizeof(T) == 8, d4, f4>::type acc_t;
   acc_t acc[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) acc[t] = (acc_t){0, 0, 0, 0};
+  // FP32: the matrix core accumulates one chunk of KCH points at a time;
+  // chunk sums are added into (sum, cmp) with Kahan's compensated
+  // summation, so the rounding error of the accumulation stays near that of
+  // a single chunk instead of growing with N (plain FP32 accumulation over
+  // N = 32768 points loses about 1e-4 of a row's magnitude)
+  constexpr int NS = sizeof(T) == 4 ? NT : 1;
+  constexpr int KCH = 4;  // k-blocks per chunk (64 points)
+  f4 sum[NS], cmp[NS];
+#pragma unroll
+  for (int t = 0; t < NS; ++t) {
+    sum[t] = (f4){0, 0, 0, 0};
+    cmp[t] = (f4){0, 0, 0, 0};
+  }
 
   // X k-block and point coordinates: fetched into registers one block ahead
   // (global latency overlaps the MFMA work), written to LDS after compute.
@@ -118,11 +152,11 @@ kapply_kernel(int64_t n, const double *__restrict__ pts, int64_t ncols, const T 
       const int e = tid + 256 * q;
       const int kr = e % BK, cc = e / BK;
       const int64_t gk = k0 + kr, gc = col0 + cc;
-      xr[q] = X[(gc < ncols ? gc : ncols - 1) * ldx + (gk < n ? gk : n - 1)];
+      xr[q] = X[(gc < ncols ? gc : ncols - 1) * ldx + (gk < nloc ? gk : nloc - 1)];
     }
     if (tid < BK * DIM) {
       const int64_t gk = k0 + tid % BK;
-      pk = pts[(int64_t)(tid / BK) * n + (gk < n ? gk : n - 1)];
+      pk = pts[(int64_t)(tid / BK) * n + (gk < nloc ? gk : nloc - 1)];
     }
   };
   auto commit = [&](int buf) {
@@ -134,7 +168,8 @@ kapply_kernel(int64_t n, const double *__restrict__ pts, int64_t ncols, const T 
     if (tid < BK * DIM) Ps[buf][tid / BK][tid % BK] = pk;
   };
 
-  const int64_t nk = (n + BK - 1) / BK;
+  // a dead tile (zero columns of X) skips the contraction and stores zeros
+  const int64_t nk = live ? (nloc + BK - 1) / BK : 0;
   fetch(0);
   commit(0);
   __syncthreads();
@@ -154,11 +189,11 @@ kapply_kernel(int64_t n, const double *__restrict__ pts, int64_t ncols, const T 
         const double df = pr[d] - Ps[buf][d][kl];
         r2 += df * df;
       }
-      const bool live = kb * BK + kl < n;
+      const bool in = kb * BK + kl < nloc;
       if constexpr (sizeof(T) == 8)
-        av[s4] = live ? kval64<KER>(r2) : 0.0;
+        av[s4] = in ? kval64<KER>(r2) : 0.0;
       else
-        av[s4] = live ? kval32<KER>((float)r2) : 0.0f;
+        av[s4] = in ? kval32<KER>((float)r2) : 0.0f;
     }
 #pragma unroll
     for (int s4 = 0; s4 < KS; ++s4) {
@@ -170,6 +205,21 @@ kapply_kernel(int64_t n, const double *__restrict__ pts, int64_t ncols, const T 
           acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s4], b, acc[t], 0, 0, 0);
         else
           acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s4], b, acc[t], 0, 0, 0);
+      }
+    }
+    if constexpr (sizeof(T) == 4) {
+      if ((kb % KCH) == KCH - 1 || kb + 1 == nk) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const float y = acc[t][i] - cmp[t][i];
+            const float u = sum[t][i] + y;
+            cmp[t][i] = (u - sum[t][i]) - y;
+            sum[t][i] = u;
+          }
+          acc[t] = (acc_t){0, 0, 0, 0};
+        }
       }
     }
     if (kb + 1 < nk) commit(buf ^ 1);
@@ -186,72 +236,111 @@ kapply_kernel(int64_t n, const double *__restrict__ pts, int64_t ncols, const T 
     for (int i = 0; i < 4; ++i) {
       const int rin = sizeof(T) == 8 ? 4 * i + kq : 4 * kq + i;
       const int64_t rr = row_blk + wave * 16 + rin;
-      if (rr < n) Y[c * ldy + rr] = (T)acc[t][i];
+      if constexpr (sizeof(T) == 8) {
+        if (rr < nloc) Y[c * ldy + rr] = acc[t][i];
+      } else {
+        if (rr < nloc) Y[c * ldy + rr] = sum[t][i];
+      }
     }
   }
 }
 
 template <typename T, int NT, int KER, int DIM>
 void launch_nt(int64_t n, const double *pts, int64_t ncols, const T *X, int64_t ldx, T *Y,
-               int64_t ldy, hipStream_t s) {
+               int64_t ldy, int32_t nitems, const KItem *items, int64_t split, hipStream_t s) {
   const int64_t bn = 16 * NT;
-  dim3 g((unsigned)((n + 63) / 64), (unsigned)((ncols + bn - 1) / bn));
-  kapply_kernel<T, NT, KER, DIM><<<g, 256, 0, s>>>(n, pts, ncols, X, ldx, Y, ldy);
+  const int64_t nct = (ncols + bn - 1) / bn;
+  if (items) {
+    kapply_kernel<T, NT, KER, DIM, true><<<(unsigned)(nitems * nct), 256, 0, s>>>(
+        n, pts, ncols, X, ldx, Y, ldy, items, split);
+  } else {
+    dim3 g((unsigned)((n + 63) / 64), (unsigned)nct);
+    kapply_kernel<T, NT, KER, DIM, false><<<g, 256, 0, s>>>(n, pts, ncols, X, ldx, Y, ldy,
+                                                             nullptr, -1);
+  }
 }
 
 template <typename T, int KER, int DIM>
-void launch_dim(int64_t n, const double *pts, int64_t ncols, const T *X, int64_t ldx, T *Y,
-                int64_t ldy, hipStream_t s) {
-  // columns in 16-wide fragments, at most 16 fragments per workgroup; pick
-  // the narrowest instantiated tile that covers an even split
-  const int64_t frags = (ncols + 15) / 16;
-  const int64_t tiles = (frags + 15) / 16;
-  const int64_t need = (frags + tiles - 1) / tiles;
-  if (need <= 2)
-    launch_nt<T, 2, KER, DIM>(n, pts, ncols, X, ldx, Y, ldy, s);
-  else if (need <= 4)
-    launch_nt<T, 4, KER, DIM>(n, pts, ncols, X, ldx, Y, ldy, s);
-  else if (need <= 6)
-    launch_nt<T, 6, KER, DIM>(n, pts, ncols, X, ldx, Y, ldy, s);
-  else if (need <= 8)
-    launch_nt<T, 8, KER, DIM>(n, pts, ncols, X, ldx, Y, ldy, s);
-  else if (need <= 10)
-    launch_nt<T, 10, KER, DIM>(n, pts, ncols, X, ldx, Y, ldy, s);
-  else if (need <= 12)
-    launch_nt<T, 12, KER, DIM>(n, pts, ncols, X, ldx, Y, ldy, s);
-  else if (need <= 14)
-    launch_nt<T, 14, KER, DIM>(n, pts, ncols, X, ldx, Y, ldy, s);
-  else
-    launch_nt<T, 16, KER, DIM>(n, pts, ncols, X, ldx, Y, ldy, s);
+void launch_dim(int nt, int64_t n, const double *pts, int64_t ncols, const T *X, int64_t ldx,
+                T *Y, int64_t ldy, int32_t nitems, const KItem *items, int64_t split,
+                hipStream_t s) {
+#define HM_KAPPLY_NT(V)                                                              \
+  case V:                                                                           \
+    launch_nt<T, V, KER, DIM>(n, pts, ncols, X, ldx, Y, ldy, nitems, items, split, s); \
+    break;
+  switch (nt) {
+    HM_KAPPLY_NT(2)
+    HM_KAPPLY_NT(4)
+    HM_KAPPLY_NT(6)
+    HM_KAPPLY_NT(8)
+    HM_KAPPLY_NT(10)
+    HM_KAPPLY_NT(12)
+    HM_KAPPLY_NT(14)
+    default:
+      launch_nt<T, 16, KER, DIM>(n, pts, ncols, X, ldx, Y, ldy, nitems, items, split, s);
+  }
+#undef HM_KAPPLY_NT
 }
 
 template <typename T, int KER>
-void launch_ker(int dim, int64_t n, const double *pts, int64_t ncols, const T *X, int64_t ldx,
-                T *Y, int64_t ldy, hipStream_t s) {
+void launch_ker(int nt, int dim, int64_t n, const double *pts, int64_t ncols, const T *X,
+                int64_t ldx, T *Y, int64_t ldy, int32_t nitems, const KItem *items,
+                int64_t split, hipStream_t s) {
   if (dim == 1)
-    launch_dim<T, KER, 1>(n, pts, ncols, X, ldx, Y, ldy, s);
+    launch_dim<T, KER, 1>(nt, n, pts, ncols, X, ldx, Y, ldy, nitems, items, split, s);
   else if (dim == 2)
-    launch_dim<T, KER, 2>(n, pts, ncols, X, ldx, Y, ldy, s);
+    launch_dim<T, KER, 2>(nt, n, pts, ncols, X, ldx, Y, ldy, nitems, items, split, s);
   else
-    launch_dim<T, KER, 3>(n, pts, ncols, X, ldx, Y, ldy, s);
+    launch_dim<T, KER, 3>(nt, n, pts, ncols, X, ldx, Y, ldy, nitems, items, split, s);
+}
+
+void launch_any(int kernel, int nt, int dim, int64_t n, const double *pts, int64_t ncols,
+                bool f32, const void *X, int64_t ldx, void *Y, int64_t ldy, int32_t nitems,
+                const KItem *items, int64_t split, hipStream_t s) {
+  if (nt <= 0) nt = kapply_default_nt(ncols, f32);
+  if (f32) {
+    if (kernel == 0)
+      launch_ker<float, 0>(nt, dim, n, pts, ncols, (const float *)X, ldx, (float *)Y, ldy, nitems,
+                           items, split, s);
+    else
+      launch_ker<float, 1>(nt, dim, n, pts, ncols, (const float *)X, ldx, (float *)Y, ldy, nitems,
+                           items, split, s);
+  } else {
+    if (kernel == 0)
+      launch_ker<double, 0>(nt, dim, n, pts, ncols, (const double *)X, ldx, (double *)Y, ldy,
+                            nitems, items, split, s);
+    else
+      launch_ker<double, 1>(nt, dim, n, pts, ncols, (const double *)X, ldx, (double *)Y, ldy,
+                            nitems, items, split, s);
+  }
 }
 
 }  // namespace
 
+// Columns in 16-wide fragments, at most 16 fragments per workgroup (8 in
+// FP32, whose compensated sums hold three accumulator sets: beyond 8 the
+// register file drops the occupancy to one wave per SIMD): the narrowest
+// instantiated tile that covers an even split of the fragments.
+int kapply_default_nt(int64_t ncols, bool f32) {
+  const int64_t cap = f32 ? 8 : 16;
+  const int64_t frags = (ncols + 15) / 16;
+  const int64_t tiles = (frags + cap - 1) / cap;
+  const int64_t need = (frags + tiles - 1) / tiles;
+  const int64_t nt = need < 2 ? 2 : (need + 1) / 2 * 2;
+  return (int)(nt > cap ? cap : nt);
+}
+
 void launch_kapply(int kernel, int dim, int64_t n, const double *pts, int64_t ncols, bool f32,
                    const void *X, int64_t ldx, void *Y, int64_t ldy, hipStream_t s) {
   if (n <= 0 || ncols <= 0) return;
-  if (f32) {
-    if (kernel == 0)
-      launch_ker<float, 0>(dim, n, pts, ncols, (const float *)X, ldx, (float *)Y, ldy, s);
-    else
-      launch_ker<float, 1>(dim, n, pts, ncols, (const float *)X, ldx, (float *)Y, ldy, s);
-  } else {
-    if (kernel == 0)
-      launch_ker<double, 0>(dim, n, pts, ncols, (const double *)X, ldx, (double *)Y, ldy, s);
-    else
-      launch_ker<double, 1>(dim, n, pts, ncols, (const double *)X, ldx, (double *)Y, ldy, s);
-  }
+  launch_any(kernel, 0, dim, n, pts, ncols, f32, X, ldx, Y, ldy, 0, nullptr, -1, s);
+}
+
+void launch_kapply_forest(int kernel, int dim, int64_t n, const double *pts, int32_t nitems,
+                          const KItem *items, int64_t ncols, int64_t split, int nt, bool f32,
+                          const void *X, int64_t ldx, void *Y, int64_t ldy, hipStream_t s) {
+  if (n <= 0 || ncols <= 0 || nitems <= 0) return;
+  launch_any(kernel, nt, dim, n, pts, ncols, f32, X, ldx, Y, ldy, nitems, items, split, s);
 }
 
 }  // namespace hm

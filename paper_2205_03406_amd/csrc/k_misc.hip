@@ -12,8 +12,9 @@ __global__ void __launch_bounds__(256) testmat_kernel(int64_t n, const int32_t *
                                                       const uint8_t *__restrict__ active,
                                                       int32_t ncolors, int32_t r, int32_t level,
                                                       int32_t pass, uint32_t k0, uint32_t k1,
-                                                      T *__restrict__ out, int64_t ld,
-                                                      int64_t ncols_pad) {
+                                                      const int64_t *__restrict__ inst_off,
+                                                      int32_t ninst, T *__restrict__ out,
+                                                      int64_t ld, int64_t ncols_pad) {
   // one thread per (row, column pair); consecutive threads walk rows
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -24,8 +25,26 @@ __global__ void __launch_bounds__(256) testmat_kernel(int64_t n, const int32_t *
   double z0 = 0.0, z1 = 0.0;
   bool in0 = c < ncolors;
   if (in0 && active[(int64_t)rowbox[i] * ncolors + c]) {
-    dev::U4 ctr{(uint32_t)i, (uint32_t)jj, (uint32_t)c, (uint32_t)(4 * level + pass)};
-    dev::normal_pair(dev::philox10(ctr, k0, k1), z0, z1);
+    // forest: the row's instance (binary search over the row offsets)
+    // supplies the key seed + instance and the row count restarts at 0
+    int64_t row = i;
+    uint32_t q0 = k0, q1 = k1;
+    if (ninst > 1) {
+      int lo = 0, hi = ninst;
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (inst_off[mid] <= i)
+          lo = mid;
+        else
+          hi = mid;
+      }
+      row = i - inst_off[lo];
+      const uint64_t key = ((((uint64_t)k1) << 32) | k0) + (uint64_t)lo;
+      q0 = (uint32_t)key;
+      q1 = (uint32_t)(key >> 32);
+    }
+    dev::U4 ctr{(uint32_t)row, (uint32_t)jj, (uint32_t)c, (uint32_t)(4 * level + pass)};
+    dev::normal_pair(dev::philox10(ctr, q0, q1), z0, z1);
   }
   // the pair (2jj, 2jj+1) lives in color block c; when r is odd the second
   // value of the last pair is dropped and the next block starts
@@ -129,8 +148,9 @@ inline dim3 grid_rows(int64_t n, int64_t ycols) {
 }  // namespace
 
 void launch_testmat(int64_t n, const int32_t *rowbox, const uint8_t *active, int32_t ncolors,
-                    int32_t r, int32_t level, int32_t pass, uint64_t seed, bool f32, void *out,
-                    int64_t ld, int64_t ncols_pad, hipStream_t s) {
+                    int32_t r, int32_t level, int32_t pass, uint64_t seed,
+                    const int64_t *inst_off, int32_t ninst, bool f32, void *out, int64_t ld,
+                    int64_t ncols_pad, hipStream_t s) {
   if (n <= 0) return;
   const int64_t npairs = (int64_t)ncolors * ((r + 1) / 2);
   const uint32_t k0 = (uint32_t)(seed & 0xFFFFFFFFu), k1 = (uint32_t)(seed >> 32);
@@ -138,10 +158,10 @@ void launch_testmat(int64_t n, const int32_t *rowbox, const uint8_t *active, int
     dim3 g((unsigned)((n + 255) / 256), (unsigned)npairs);
     if (f32)
       testmat_kernel<float><<<g, 256, 0, s>>>(n, rowbox, active, ncolors, r, level, pass, k0, k1,
-                                              (float *)out, ld, ncols_pad);
+                                              inst_off, ninst, (float *)out, ld, ncols_pad);
     else
       testmat_kernel<double><<<g, 256, 0, s>>>(n, rowbox, active, ncolors, r, level, pass, k0,
-                                               k1, (double *)out, ld, ncols_pad);
+                                               k1, inst_off, ninst, (double *)out, ld, ncols_pad);
   }
   const int64_t c0 = (int64_t)ncolors * r;
   if (ncols_pad > c0) {

@@ -20,12 +20,35 @@ namespace {
 
 using dev::wave_sum;
 
+// ------------------------------------------------------------------ block norms
+// out[j] = scale * ||S(rows, cols) of job j||_F (FP64 accumulation).
+template <typename T>
+__global__ void __launch_bounds__(256)
+block_norm_kernel(const QrJob *__restrict__ jobs, int32_t r, double scale,
+                  const T *__restrict__ S, int64_t lds, double *__restrict__ out) {
+  __shared__ double part[4];
+  const QrJob job = jobs[blockIdx.x];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const T *A = S + job.col0 * lds + job.row0;
+  double s2 = 0.0;
+  for (int c = wave; c < r; c += 4)
+    for (int i = lane; i < job.m; i += 64) {
+      const double v = (double)A[(int64_t)c * lds + i];
+      s2 += v * v;
+    }
+  s2 = wave_sum(s2);
+  if (lane == 0) part[wave] = s2;
+  __syncthreads();
+  if (tid == 0) out[blockIdx.x] = scale * sqrt(part[0] + part[1] + part[2] + part[3]);
+}
+
 // ------------------------------------------------------------------ pivqr
 template <typename T>
 __global__ void __launch_bounds__(256)
 pivqr_kernel(const QrJob *__restrict__ jobs, int32_t r, int32_t rank_fixed, double tol,
-             int32_t cap, const T *__restrict__ S, int64_t lds, double *__restrict__ Wk,
-             double *__restrict__ U, int32_t *__restrict__ ranks, int32_t *__restrict__ sat) {
+             int32_t cap, const double *__restrict__ floor_abs, const T *__restrict__ S,
+             int64_t lds, double *__restrict__ Wk, double *__restrict__ U,
+             int32_t *__restrict__ ranks, int32_t *__restrict__ sat) {
   __shared__ double nrm2[64];
   __shared__ int piv[64];
   __shared__ double tau[64];
@@ -39,6 +62,9 @@ pivqr_kernel(const QrJob *__restrict__ jobs, int32_t r, int32_t rank_fixed, doub
   const int kmax_here = m < r ? m : r;
   const int kcap = rank_fixed > 0 ? (rank_fixed < kmax_here ? rank_fixed : kmax_here)
                                   : (cap < kmax_here ? cap : kmax_here);
+  // absolute floor under the relative threshold (the rounding noise of a
+  // reduced-precision sample), 0 when none
+  const double fl = floor_abs ? floor_abs[blockIdx.x] : 0.0;
 
   // copy to the FP64 workspace and take squared column norms
   for (int c = wave; c < r; c += 4) {
@@ -82,7 +108,7 @@ pivqr_kernel(const QrJob *__restrict__ jobs, int32_t r, int32_t rank_fixed, doub
         if (j == 0) bcast[1] = nrm;
         const double ref = j == 0 ? nrm : bcast[1];
         int stop = !(nrm > 0.0);
-        if (rank_fixed <= 0 && !(nrm > tol * ref)) stop = 1;
+        if (rank_fixed <= 0 && !(nrm > fmax(tol * ref, fl))) stop = 1;
         stop_s = stop;
         if (!stop) {
           const double alpha = x[j];
@@ -124,7 +150,7 @@ pivqr_kernel(const QrJob *__restrict__ jobs, int32_t r, int32_t rank_fixed, doub
   if (rank_fixed <= 0 && rank == kcap && kcap < kmax_here) {
     double mx = 0.0;
     for (int c = kcap; c < r; ++c) mx = nrm2[c] > mx ? nrm2[c] : mx;
-    if (sqrt(mx) > tol * r00) saturated = 1;
+    if (sqrt(mx) > fmax(tol * r00, fl)) saturated = 1;
   }
 
   // explicit basis: U = H_0 ... H_{rank-1} [I; 0], written column-major (ld = m)
@@ -343,15 +369,24 @@ coupling_kernel(const CoreJob *__restrict__ jobs, int32_t r, int32_t kmax,
 }  // namespace
 
 void launch_pivqr(int32_t njobs, const QrJob *jobs, int32_t r, int32_t rank_fixed, double tol,
-                  int32_t cap, bool f32, const void *S, int64_t lds, double *Wk, double *U,
-                  int32_t *ranks, int32_t *sat, hipStream_t s) {
+                  int32_t cap, const double *floor_abs, bool f32, const void *S, int64_t lds,
+                  double *Wk, double *U, int32_t *ranks, int32_t *sat, hipStream_t s) {
   if (njobs <= 0) return;
   if (f32)
-    pivqr_kernel<float><<<njobs, 256, 0, s>>>(jobs, r, rank_fixed, tol, cap, (const float *)S, lds,
-                                              Wk, U, ranks, sat);
+    pivqr_kernel<float><<<njobs, 256, 0, s>>>(jobs, r, rank_fixed, tol, cap, floor_abs,
+                                              (const float *)S, lds, Wk, U, ranks, sat);
   else
-    pivqr_kernel<double><<<njobs, 256, 0, s>>>(jobs, r, rank_fixed, tol, cap, (const double *)S,
-                                               lds, Wk, U, ranks, sat);
+    pivqr_kernel<double><<<njobs, 256, 0, s>>>(jobs, r, rank_fixed, tol, cap, floor_abs,
+                                               (const double *)S, lds, Wk, U, ranks, sat);
+}
+
+void launch_block_norms(int32_t njobs, const QrJob *jobs, int32_t r, double scale, bool f32,
+                        const void *S, int64_t lds, double *out, hipStream_t s) {
+  if (njobs <= 0) return;
+  if (f32)
+    block_norm_kernel<float><<<njobs, 256, 0, s>>>(jobs, r, scale, (const float *)S, lds, out);
+  else
+    block_norm_kernel<double><<<njobs, 256, 0, s>>>(jobs, r, scale, (const double *)S, lds, out);
 }
 
 void launch_core(int32_t njobs, const CoreJob *jobs, int32_t r, bool f32, const void *Psi,

@@ -9,9 +9,12 @@ namespace hm {
 // ---- test matrices and data movement (k_misc.hip)
 // Colored Gaussian test matrix of one level/pass: out (n x ncolors*r, ld)
 // in tree order; row i of color block c is nonzero iff active[rowbox[i]*ncol + c].
+// Forest (ninst > 1): row i of instance q (inst_off[q] <= i < inst_off[q+1],
+// device array) draws with key seed + q and row number i - inst_off[q].
 void launch_testmat(int64_t n, const int32_t *rowbox, const uint8_t *active, int32_t ncolors,
-                    int32_t r, int32_t level, int32_t pass, uint64_t seed, bool f32, void *out,
-                    int64_t ld, int64_t ncols_pad, hipStream_t s);
+                    int32_t r, int32_t level, int32_t pass, uint64_t seed,
+                    const int64_t *inst_off, int32_t ninst, bool f32, void *out, int64_t ld,
+                    int64_t ncols_pad, hipStream_t s);
 // Identity blocks of the leaf pass: out zeroed (n x ncols_pad), then
 // out[start[b] + t, color*m + t] = 1 for each (b, color) item, t < size(b).
 void launch_leaf_identity(int64_t n, int32_t nitems, const int32_t *item_box,
@@ -40,6 +43,26 @@ void launch_check_finite(int64_t n, int64_t ncols, bool f32, const void *Y, int6
 // tree order), 0 where p_i == p_j.  kernel: 0 = log, 1 = 1/r.
 void launch_kapply(int kernel, int dim, int64_t n, const double *pts, int64_t ncols, bool f32,
                    const void *X, int64_t ldx, void *Y, int64_t ldy, hipStream_t s);
+// Block-diagonal form for a forest: one work item per 64-row block of one
+// instance.  Rows [base, base + nloc) of Y are K_inst X(base : base+nloc, :)
+// where K_inst only couples points of the instance.  Columns outside
+// [0, width) and [split, split + width) (split < 0: no second range) are
+// known to be zero in the instance's rows of X: their tiles are not
+// computed, and Y there is written 0.  Items are launched in the given
+// order (put the long instances first).  nt: column fragments per
+// workgroup (0 = chosen from ncols).
+struct KItem {
+  int64_t base;   // first row of the instance
+  int32_t nloc;   // rows of the instance
+  int32_t rblk;   // first row of the block, relative to base
+  int32_t width;  // live columns of the instance
+  int32_t pad;
+};
+void launch_kapply_forest(int kernel, int dim, int64_t n, const double *pts, int32_t nitems,
+                          const KItem *items, int64_t ncols, int64_t split, int nt, bool f32,
+                          const void *X, int64_t ldx, void *Y, int64_t ldy, hipStream_t s);
+// Column fragments per workgroup the plain launch picks for ncols.
+int kapply_default_nt(int64_t ncols, bool f32);
 // Dense Y = op(A) X, FP64.
 void launch_dense_gemm(int64_t n, const double *A, int64_t lda, bool trans, int64_t ncols,
                        const double *X, int64_t ldx, double *Y, int64_t ldy, hipStream_t s);
@@ -112,9 +135,14 @@ struct QrJob {
 // Column-pivoted Householder QR of S (m x r) in place, truncated by rank /
 // tolerance, and the explicit basis Q[:, 0:k] written to U.  ranks[j] = k,
 // sat[j] = 1 when the tolerance was not met within `cap` columns.
+// floor_abs (device, njobs, or NULL): tolerance mode stops at the first
+// |R_jj| <= max(tol |R_00|, floor_abs[job]).
 void launch_pivqr(int32_t njobs, const QrJob *jobs, int32_t r, int32_t rank_fixed, double tol,
-                  int32_t cap, bool f32, const void *S, int64_t lds, double *Wk, double *U,
-                  int32_t *ranks, int32_t *sat, hipStream_t s);
+                  int32_t cap, const double *floor_abs, bool f32, const void *S, int64_t lds,
+                  double *Wk, double *U, int32_t *ranks, int32_t *sat, hipStream_t s);
+// out[j] = scale * Frobenius norm of job j's block S(row0 : row0+m, col0 : col0+r).
+void launch_block_norms(int32_t njobs, const QrJob *jobs, int32_t r, double scale, bool f32,
+                        const void *S, int64_t lds, double *out, hipStream_t s);
 // C_p = G2^T S_U (r x r) for every pair, into core (np x r x r).
 struct CoreJob {
   int64_t arow0;   // rows of alpha in Psi / Y

@@ -10,6 +10,7 @@
 // (a box's neighbors are among the children of its parent's neighbors), so
 // the cost is O(N log N + boxes * 6^d + edges) rather than quadratic.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -459,6 +460,106 @@ hm_status build_tree(const double *pts, int64_t n, int dim, int leaf, int kind, 
     for (auto &t : th) t.join();
   }
   lap("graphs");
+  T.inst_off = {0, n};
+  T.gvoff.clear();
+  for (const Graph &G : T.graphs) T.gvoff.push_back({0, G.nv()});
+  return HM_OK;
+}
+
+hm_status build_forest(const double *pts, const int64_t *counts, int ninst, int dim, int leaf,
+                       int kind, int adm, Tree &F) {
+  std::vector<Tree> parts(ninst);
+  std::vector<int64_t> off(ninst + 1, 0);
+  for (int i = 0; i < ninst; ++i) off[i + 1] = off[i] + counts[i];
+  std::vector<hm_status> rc(ninst, HM_OK);
+  {
+    // instances are independent: a pool of host threads takes them in turn
+    const int nth = std::max(1, std::min<int>(ninst, (int)std::thread::hardware_concurrency()));
+    std::vector<std::thread> th;
+    std::atomic<int> next{0};
+    for (int t = 0; t < nth; ++t)
+      th.emplace_back([&] {
+        for (int i = next++; i < ninst; i = next++)
+          rc[i] = build_tree(pts + off[i] * dim, counts[i], dim, leaf, kind, adm, parts[i]);
+      });
+    for (auto &t : th) t.join();
+  }
+  for (int i = 0; i < ninst; ++i)
+    if (rc[i] != HM_OK) return rc[i];
+  int nlev = 0;
+  for (const Tree &P : parts) nlev = std::max(nlev, P.nlev());
+  F = Tree();
+  F.n = off[ninst];
+  F.dim = dim;
+  F.kind = kind;
+  F.adm = adm;
+  F.leaf = leaf;
+  F.pts.assign(pts, pts + F.n * dim);
+  F.inst_off = off;
+  F.perm.resize(F.n);
+  for (int i = 0; i < ninst; ++i)
+    for (int64_t t = 0; t < counts[i]; ++t) F.perm[off[i] + t] = parts[i].perm[t] + off[i];
+  // boxes of instance i at forest level l: its own level min(l, L_i)
+  std::vector<std::vector<int32_t>> boff(nlev, std::vector<int32_t>(ninst + 1, 0));
+  F.lev.resize(nlev);
+  for (int l = 0; l < nlev; ++l) {
+    Level &Lv = F.lev[l];
+    Lv.nei_ptr.push_back(0);
+    Lv.int_ptr.push_back(0);
+    for (int i = 0; i < ninst; ++i) {
+      const Tree &P = parts[i];
+      const int sl = std::min(l, P.L());
+      const bool carried = l > P.L();
+      const Level &S = P.lev[sl];
+      const int32_t b0 = boff[l][i];
+      boff[l][i + 1] = b0 + S.nbox();
+      for (int b = 0; b < S.nbox(); ++b) {
+        Lv.start.push_back(S.start[b] + off[i]);
+        Lv.parent.push_back(l == 0 ? -1 : (carried ? b : S.parent[b]) + boff[l - 1][i]);
+        for (int d = 0; d < 3; ++d) Lv.org.push_back(S.org[3 * b + d]);
+        Lv.blev.push_back(S.blev[b]);
+        for (int t = S.nei_ptr[b]; t < S.nei_ptr[b + 1]; ++t) Lv.nei.push_back(S.nei[t] + b0);
+        Lv.nei_ptr.push_back((int32_t)Lv.nei.size());
+        if (!carried)
+          for (int t = S.int_ptr[b]; t < S.int_ptr[b + 1]; ++t) Lv.intl.push_back(S.intl[t] + b0);
+        Lv.int_ptr.push_back((int32_t)Lv.intl.size());
+      }
+    }
+    Lv.start.push_back(F.n);
+  }
+  // graphs: disjoint unions, instance-major vertex numbering
+  F.graphs.resize(nlev + 1);
+  F.gvoff.assign(nlev + 1, std::vector<int64_t>(ninst + 1, 0));
+  for (int g = 0; g <= nlev; ++g) {
+    Graph &G = F.graphs[g];
+    G.xadj.push_back(0);
+    int32_t cls0 = 0;
+    const int bl = g < nlev ? g : nlev - 1;  // box level of the graph's ids
+    for (int i = 0; i < ninst; ++i) {
+      const Tree &P = parts[i];
+      static const Graph empty;
+      const Graph &S = g == nlev ? P.leaf_graph() : (g <= P.L() ? P.graphs[g] : empty);
+      const int64_t v0 = G.nv();
+      F.gvoff[g][i] = v0;
+      const int32_t b0 = boff[bl][i];
+      int32_t cmax = -1;
+      for (int64_t v = 0; v < S.nv(); ++v) {
+        G.vbox.push_back(S.vbox[v] + b0);
+        G.vclass.push_back(S.vclass[v] + cls0);
+        cmax = std::max(cmax, S.vclass[v]);
+        for (int64_t t = S.xadj[v]; t < S.xadj[v + 1]; ++t)
+          G.adj.push_back((int32_t)(S.adj[t] + v0));
+        G.xadj.push_back((int64_t)G.adj.size());
+      }
+      cls0 += cmax + 1;
+      for (size_t q = 0; q < S.pa.size(); ++q) {
+        G.pa.push_back(S.pa[q] + b0);
+        G.pb.push_back(S.pb[q] + b0);
+        G.pv.push_back((int32_t)(S.pv[q] + v0));
+      }
+    }
+    F.gvoff[g][ninst] = G.nv();
+  }
   return HM_OK;
 }
 

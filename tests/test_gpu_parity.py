@@ -15,6 +15,7 @@ import pytest
 import workloads
 import oracle
 from synth import exact_h1
+from devutil import to_dev, to_host, dense_of
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -26,21 +27,6 @@ def hm():
         pytest.skip("no GPU")
     import paper_2205_03406_amd as m
     return m
-
-
-def to_dev(X, dtype=None):
-    X = np.asarray(X)
-    if X.ndim == 1:
-        X = X.reshape(-1, 1)
-    t = torch.from_numpy(np.ascontiguousarray(X.T)).to("cuda")
-    if dtype is not None:
-        t = t.to(dtype)
-    return t.t()
-
-
-def to_host(t):
-    torch.cuda.synchronize()
-    return t.double().cpu().numpy()
 
 
 def test_device_properties(hm):
@@ -152,15 +138,6 @@ def _block_parity(T, O, Hg, Ho, A, rel=1e-8):
         assert np.linalg.norm(D - D2) <= rel * np.linalg.norm(D2) + floor
 
 
-def _dense_of(hm, H, n):
-    I = hm.colmajor(n, n)
-    I.zero_()
-    I.diagonal().fill_(1.0)
-    Y = hm.colmajor(n, n)
-    H.matvec(I, Y, order=hm.HM_ORDER_ORIGINAL)
-    return to_host(Y)
-
-
 @pytest.mark.parametrize("case", ["strong2d", "curve", "hodlr", "strong3d"])
 def test_exact_recovery_dense_blackbox(hm, case):
     if case == "strong2d":
@@ -178,7 +155,7 @@ def test_exact_recovery_dense_blackbox(hm, case):
     bb = hm.dense_blackbox(Ad)
     H = hm.compress(T, bb, rank=4, r=10, seed=77)
     n = O.n
-    D = _dense_of(hm, H, n)
+    D = dense_of(hm, H, n)
     assert np.linalg.norm(D - A) <= 1e-11 * np.linalg.norm(A)
     Ho = oracle.compress(O, oracle.DenseBlackBox(A), 10, k=4, seed=77)
     _block_parity(T, O, H, Ho, A, rel=1e-10)
@@ -188,7 +165,7 @@ def test_exact_recovery_dense_blackbox(hm, case):
     assert st["cols_A"] == 10 * sum(chis) + T.graph(-1).ncolors * O.leaf_max()
     # tolerance mode finds the exact ranks
     Ht = hm.compress(T, bb, tol=1e-9, r=14, seed=78)
-    assert np.linalg.norm(_dense_of(hm, Ht, n) - A) <= 1e-10 * np.linalg.norm(A)
+    assert np.linalg.norm(dense_of(hm, Ht, n) - A) <= 1e-10 * np.linalg.norm(A)
     assert Ht.stats()["max_rank"] <= 4
 
 
@@ -203,7 +180,7 @@ def test_hodlr_config_parity(hm):
     A = oracle.kernel_matrix(inst.points, inst.points, inst.kernel)
     Ho = oracle.compress(O, oracle.DenseBlackBox(A), inst.r, k=inst.rank, seed=inst.seed)
     _block_parity(T, O, H, Ho, A)
-    D = _dense_of(hm, H, O.n)
+    D = dense_of(hm, H, O.n)
     assert np.linalg.norm(D - A) <= 1e-8 * np.linalg.norm(A)
 
 
@@ -217,7 +194,7 @@ def test_curve_tolerance_parity(hm, n, r):
     A = oracle.kernel_matrix(inst.points, inst.points, inst.kernel)
     Ho = oracle.compress(O, oracle.DenseBlackBox(A), r, tol=inst.tol, seed=inst.seed)
     _block_parity(T, O, H, Ho, A, rel=10 * inst.tol)
-    D = _dense_of(hm, H, O.n)
+    D = dense_of(hm, H, O.n)
     assert np.linalg.norm(D - A) <= inst.tol * np.linalg.norm(A)
     assert H.stats()["saturated"] == 0
 
@@ -231,7 +208,7 @@ def test_sphere_tolerance_parity(hm):
     A = oracle.kernel_matrix(inst.points, inst.points, inst.kernel)
     Ho = oracle.compress(O, oracle.DenseBlackBox(A), inst.r, tol=inst.tol, seed=inst.seed)
     _block_parity(T, O, H, Ho, A, rel=10 * inst.tol)
-    D = _dense_of(hm, H, O.n)
+    D = dense_of(hm, H, O.n)
     assert np.linalg.norm(D - A) <= 5 * inst.tol * np.linalg.norm(A)
 
 
@@ -264,8 +241,8 @@ def test_mixed_precision_against_fp64(hm):
     bb = T.kernel_blackbox(inst.kernel)
     H64 = hm.compress(T, bb, tol=1e-8, r=24, seed=inst.seed)
     H32 = hm.compress(T, bb, tol=1e-6, r=24, seed=inst.seed, prec=hm.HM_PREC_MIXED)
-    D64 = _dense_of(hm, H64, T.n)
-    D32 = _dense_of(hm, H32, T.n)
+    D64 = dense_of(hm, H64, T.n)
+    D32 = dense_of(hm, H32, T.n)
     A = oracle.kernel_matrix(inst.points, inst.points, inst.kernel)
     e = np.linalg.norm(D32 - D64) / np.linalg.norm(D64)
     print("mixed vs fp64:", e, "mixed vs dense:", np.linalg.norm(D32 - A) / np.linalg.norm(A))
