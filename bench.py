@@ -29,6 +29,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "peel GFLOP/s + compressions/s at rel err 1e-5 vs plain FP64; p50/p99 ms"
 PEAK_FP64_MFMA = 78.6e12
+PEAK_FP32_MFMA = 157.3e12
 R_COLS = 24
 
 
@@ -40,6 +41,8 @@ def parse():
     ap.add_argument("--n", type=int, default=16384)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-steps", type=int, default=3)
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run this many steps, no extras (for profilers)")
     ap.add_argument("--pmc-probe", action="store_true",
@@ -100,6 +103,64 @@ def run_path(hm, torch, inst, prec, tol, steps, warmup, x, y):
     total = time.perf_counter() - t_all0
     return dict(times=times, total=total, flops=flops, bb_ms=bb_ms, bb_flops=bb_flops,
                 launches=launches, H=H, T=T, stats=st)
+
+
+def batched_step(hm, insts, prec):
+    F = hm.Tree([i.points for i in insts], insts[0].leaf, insts[0].tree, insts[0].adm).color()
+    H = hm.compress(F, F.kernel_blackbox(insts[0].kernel), tol=insts[0].tol, r=insts[0].r,
+                    seed=insts[0].seed, prec=prec, timing=True)
+    return F, H
+
+
+def run_batched(hm, torch, steps):
+    """64 independent ellipse problems (N log-uniform in [2048, 32768]) as one
+    forest: FP32 bulk + FP64 QR, tol 1e-6.  One step = build the 64 trees,
+    merge, color, compress; `value` counts each instance's own algorithmic
+    work."""
+    import workloads
+    insts = workloads.batched_ellipses()
+    ntot = sum(i.points.shape[0] for i in insts)
+    batched_step(hm, insts, hm.HM_PREC_MIXED)          # warm-up
+    torch.cuda.synchronize()
+    times, flops, bb_ms, bb_flops = [], 0.0, 0.0, 0.0
+    t_all = time.perf_counter()
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        F, H = batched_step(hm, insts, hm.HM_PREC_MIXED)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        st = H.stats()
+        flops += algorithmic_flops(st)
+        bb_ms += st["ms_blackbox"]
+        bb_flops += st["flops_blackbox"]
+    total = time.perf_counter() - t_all
+    # error of the mixed result against the FP64 compression of the forest
+    F64, H64 = batched_step(hm, insts, hm.HM_PREC_F64)
+    X = hm.colmajor(ntot, 2)
+    X.copy_(torch.from_numpy(np.random.default_rng(8).standard_normal((ntot, 2))))
+    Y32, Y64 = hm.colmajor(ntot, 2), hm.colmajor(ntot, 2)
+    H.matvec(X, Y32)
+    H64.matvec(X, Y64)
+    torch.cuda.synchronize()
+    a, b = Y64.cpu().numpy(), Y32.cpu().numpy()
+    lat = np.array(times) * 1e3
+    ach = bb_flops / (bb_ms / 1e3)
+    return {
+        "workload": "64_ellipses_log_N2048-32768_leaf64_strong_tol1e-6_r%d_mixed" % insts[0].r,
+        "instances": len(insts), "points": ntot, "steps": steps,
+        "value": round(flops / total / 1e9, 2), "unit": "GFLOP/s",
+        "compressions_per_s": round(len(insts) * steps / total, 3),
+        "ms_per_step": round(1e3 * total / steps, 3),
+        "p50_ms": round(float(np.percentile(lat, 50)), 3),
+        "p99_ms": round(float(np.percentile(lat, 99)), 3),
+        "rel_err_vs_fp64": float(np.linalg.norm(a - b) / np.linalg.norm(a)),
+        "max_rank": st["max_rank"], "saturated": st["saturated"],
+        "stage_ms": {k: round(st[k], 3) for k in ("ms_blackbox", "ms_peel", "ms_qr", "ms_solve",
+                                                  "ms_other", "ms_total")},
+        "kapply": {"kernel": "kapply_kernel<float> (forest items)", "bound": "mfma",
+                   "achieved": round(ach / 1e12, 3), "peak": PEAK_FP32_MFMA / 1e12,
+                   "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_MFMA, 4)},
+    }
 
 
 def main():
@@ -213,6 +274,9 @@ def main():
             "rel_err_vs_fp64": float(np.linalg.norm(Ymx - Y64) / np.linalg.norm(Y64)),
             "kapply_tflops": round(rmx["bb_flops"] / (rmx["bb_ms"] / 1e3) / 1e12, 3),
         }
+
+    if not args.no_batched:
+        out["batched"] = run_batched(hm, torch, args.batched_steps)
 
     if not args.no_cpu_baseline:
         # the oracle, untuned, on one full compression of the same workload

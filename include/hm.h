@@ -163,6 +163,15 @@ hm_status hm_tree_set_colors(hm_tree *tree, int level, const int32_t *color);
 /* The stored coloring (owned by the tree). */
 hm_status hm_tree_colors(const hm_tree *tree, int level, int32_t *ncolors, const int32_t **color);
 
+/* Decisions of the kernel-apply autotuner so far, one line per launch shape
+ * (precision, kernel, dimension, columns, log2 of the point count, forest
+ * form -> column-tile width, best and default times).  The first launch of
+ * a shape times every tile width on the real operands (each computes the
+ * same values bit for bit) and keeps the fastest; HM_AUTOTUNE=0 disables
+ * tuning, HM_TUNE_FILE names a file that keeps decisions across processes.
+ * The string is owned by the calling thread and valid until its next call. */
+const char *hm_autotune_table(void);
+
 /* ------------------------------------------------------------------ black box
  * The black box computes Y = A X (transpose = 0) or Y = A* X (transpose = 1)
  * for a device block X of ncols columns, enqueued on `stream`.

@@ -35,7 +35,7 @@ EXPORTED = [
     "hm_dense_blackbox", "hm_dense_blackbox_free", "hm_compress", "hm_hmatrix_free",
     "hm_matvec", "hm_test_matrix", "hm_philox4x32_10", "hm_hmatrix_stats",
     "hm_hmatrix_export_level", "hm_hmatrix_export_near", "hm_build_forest",
-    "hm_tree_instances",
+    "hm_tree_instances", "hm_autotune_table",
 ]
 
 
@@ -80,6 +80,15 @@ class Stats(C.Structure):
 
 
 def _load():
+    # One HIP runtime per process: torch ships its own libamdhip64 (needed
+    # by file name), libhm needs it by soname.  Loaded first, libhm would
+    # pull in /opt/rocm's runtime and torch a second one, each with its own
+    # HSA runtime on the same device; with torch loaded first the loader
+    # reuses torch's runtime for libhm.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(_SO):
         raise ImportError("libhm.so is not built (run __graft_entry__.build() or "
                           "python -m paper_2205_03406_amd.build)")
@@ -87,6 +96,8 @@ def _load():
     P, I, I64, D = C.c_void_p, C.c_int, C.c_int64, C.c_double
     pp = C.POINTER(C.c_void_p)
     lib.hm_last_error.restype = C.c_char_p
+    lib.hm_autotune_table.restype = C.c_char_p
+    lib.hm_autotune_table.argtypes = []
     sigs = {
         "hm_build_tree": [P, I64, I, I, I, I, pp],
         "hm_build_forest": [P, P, C.c_int32, I, I, I, I, pp],
@@ -309,6 +320,11 @@ class Tree:
     def test_matrix(self, level, pas, r, seed, out, stream=None):
         po, ld, nc, dt = _colmajor(out, "out")
         _check(_lib.hm_test_matrix(self.h, level, pas, r, seed, dt, po, ld, _stream(stream)))
+
+
+def autotune_table():
+    """The kernel-apply autotuner's decisions so far (one line per shape)."""
+    return _lib.hm_autotune_table().decode()
 
 
 def color(xadj, adj):

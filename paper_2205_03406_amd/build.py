@@ -1,6 +1,6 @@
 """Build libhm.so (HIP for gfx950 + host C++) in-tree.
 
-    python -m paper_2205_03406_amd.build
+    python paper_2205_03406_amd/build.py   (or __graft_entry__.build())
 
 Every HIP source is compiled with hipcc for gfx950 with packed FP32 ops
 disabled; the host-only tree code with g++ and FP contraction off (its
@@ -19,7 +19,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhm.so")
 
-HIP_SOURCES = ["k_misc.hip", "k_kapply.hip", "k_lowrank.hip", "k_qr.hip", "engine.hip"]
+HIP_SOURCES = ["k_misc.hip", "k_kapply.hip", "k_lowrank.hip", "k_qr.hip", "autotune.hip",
+               "engine.hip"]
 CXX_SOURCES = ["tree.cpp"]
 ARCH = os.environ.get("HM_OFFLOAD_ARCH", "gfx950")
 

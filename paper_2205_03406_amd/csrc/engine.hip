@@ -177,11 +177,18 @@ struct KernelBB {
 void kernel_apply_tree(const Tree &T, int kernel, int64_t ncols, bool f32, const void *X,
                        int64_t ldx, void *Y, int64_t ldy, hipStream_t s) {
   const DeviceTree &D = *T.dev;
-  if (T.ninst() > 1)
-    launch_kapply_forest(kernel, T.dim, T.n, D.pts.as<double>(), D.nkitems, D.kitems.as<KItem>(),
-                         ncols, -1, 0, f32, X, ldx, Y, ldy, s);
-  else
-    launch_kapply(kernel, T.dim, T.n, D.pts.as<double>(), ncols, f32, X, ldx, Y, ldy, s);
+  const bool forest = T.ninst() > 1;
+  autotune_kapply(KapplyShape{f32, kernel, T.dim, ncols, T.n, forest},
+                  [&](int nt) {
+                    if (forest)
+                      launch_kapply_forest(kernel, T.dim, T.n, D.pts.as<double>(), D.nkitems,
+                                           D.kitems.as<KItem>(), ncols, -1, nt, f32, X, ldx, Y,
+                                           ldy, s);
+                    else
+                      launch_kapply(kernel, T.dim, T.n, D.pts.as<double>(), ncols, nt, f32, X,
+                                    ldx, Y, ldy, s);
+                  },
+                  s);
 }
 
 int kernel_bb_apply(void *ctx, int /*transpose*/, int64_t n, int64_t ncols, int dtype,
@@ -696,9 +703,13 @@ hm_status compress_impl(Tree &T, const hm_blackbox &bb, const hm_compress_opts &
     LAUNCH_CHECK();
     ev.mark(1);
     if (direct) {
-      launch_kapply_forest(kbb->kernel, T.dim, n, D.pts.as<double>(), jobs_of[li].nkit,
-                           jobs_of[li].kit.as<KItem>(), 2 * cpad, cpad, 0, mixed, Om, n, Yl, n,
-                           s);
+      autotune_kapply(KapplyShape{mixed, kbb->kernel, T.dim, 2 * cpad, n, true},
+                      [&](int nt) {
+                        launch_kapply_forest(kbb->kernel, T.dim, n, D.pts.as<double>(),
+                                             jobs_of[li].nkit, jobs_of[li].kit.as<KItem>(),
+                                             2 * cpad, cpad, nt, mixed, Om, n, Yl, n, s);
+                      },
+                      s);
       LAUNCH_CHECK();
     } else if (bb.symmetric) {
       call_blackbox(bb, 0, n, 2 * cpad, mixed, Om, n, Yl, n, D, tmpx, tmpy, s);
@@ -788,8 +799,13 @@ hm_status compress_impl(Tree &T, const hm_blackbox &bb, const hm_compress_opts &
     LAUNCH_CHECK();
     ev.mark(1);
     if (direct) {
-      launch_kapply_forest(kbb->kernel, T.dim, n, D.pts.as<double>(), (int32_t)kit.size(),
-                           dkit.as<KItem>(), leaf_cols, -1, 0, mixed, Xb.p, n, Yb.p, n, s);
+      autotune_kapply(KapplyShape{mixed, kbb->kernel, T.dim, leaf_cols, n, true},
+                      [&](int nt) {
+                        launch_kapply_forest(kbb->kernel, T.dim, n, D.pts.as<double>(),
+                                             (int32_t)kit.size(), dkit.as<KItem>(), leaf_cols,
+                                             -1, nt, mixed, Xb.p, n, Yb.p, n, s);
+                      },
+                      s);
       LAUNCH_CHECK();
     } else {
       call_blackbox(bb, 0, n, leaf_cols, mixed, Xb.p, n, Yb.p, n, D, tmpx, tmpy, s);
@@ -947,6 +963,12 @@ using namespace hm;
 extern "C" {
 
 const char *hm_last_error(void) { return g_last_error.c_str(); }
+
+const char *hm_autotune_table(void) {
+  static thread_local std::string snap;
+  snap = autotune_report();
+  return snap.c_str();
+}
 
 hm_status hm_build_tree(const double *points, int64_t n, int dim, int leaf_size, int tree_kind,
                         int adm, hm_tree **out) {

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <cstdint>
+#include <functional>
 #include <memory>
 #include <string>
 #include <vector>
@@ -77,6 +78,20 @@ hm_status build_tree(const double *pts, int64_t n, int dim, int leaf, int kind, 
 hm_status build_forest(const double *pts, const int64_t *counts, int ninst, int dim, int leaf,
                        int kind, int adm, Tree &F);
 int32_t dsatur(int64_t nv, const int64_t *xadj, const int32_t *adj, int32_t *color);
+
+// ------------------------------------------------------------------ autotuner
+struct KapplyShape {
+  bool f32;
+  int kernel, dim;
+  int64_t ncols, n;
+  bool forest;
+};
+// Column-tile width of a kernel-apply launch: timed over the candidates on
+// the first launch of a shape, then cached.  launch(nt) enqueues one launch
+// on `stream` (hipStream_t); on return the output holds the product.
+int autotune_kapply(const KapplyShape &shape, const std::function<void(int)> &launch,
+                    void *stream);
+std::string autotune_report();
 
 }  // namespace hm
 

@@ -24,6 +24,9 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int BK = 16;   // k-block (points) staged per LDS buffer
+#ifndef HM_KAPPLY_PAD
+#define HM_KAPPLY_PAD 2      // LDS row padding of the X k-block (elements)
+#endif
 
 // Natural logarithm of a positive finite x, written from the series
 //   x = 2^e m,  m in [1/sqrt2, sqrt2),  log m = 2 atanh(s) = 2 s sum_k s^(2k)/(2k+1),
@@ -72,9 +75,10 @@ __device__ __forceinline__ double kval64(double r2) {
 
 template <int KER>
 __device__ __forceinline__ float kval32(float r2) {
-  if (!(r2 > 0.0f)) return 0.0f;
-  if (KER == 0) return 0.34657359027997264f * __log2f(r2);  // 0.5 ln(2) log2(r2)
-  return rsqrtf(r2);
+  const float safe = r2 > 0.0f ? r2 : 1.0f;
+  const float v = KER == 0 ? 0.34657359027997264f * __log2f(safe)  // 0.5 ln(2) log2(r2)
+                           : rsqrtf(safe);
+  return r2 > 0.0f ? v : 0.0f;
 }
 
 // SEG = false: the whole operator, grid (row blocks, column tiles).
@@ -88,7 +92,7 @@ kapply_kernel(int64_t n, const double *__restrict__ pts_all, int64_t ncols,
               const T *__restrict__ X_all, int64_t ldx, T *__restrict__ Y_all, int64_t ldy,
               const KItem *__restrict__ items, int64_t split) {
   constexpr int BN = 16 * NT;
-  constexpr int LDT = BN + 2;
+  constexpr int LDT = BN + HM_KAPPLY_PAD;
   __shared__ T Xs[2][BK][LDT];
   __shared__ double Ps[2][DIM][BK];
 
@@ -123,13 +127,14 @@ kapply_kernel(int64_t n, const double *__restrict__ pts_all, int64_t ncols,
   acc_t acc[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) acc[t] = (acc_t){0, 0, 0, 0};
-  // FP32: the matrix core accumulates one chunk of KCH points at a time;
-  // chunk sums are added into (sum, cmp) with Kahan's compensated
-  // summation, so the rounding error of the accumulation stays near that of
-  // a single chunk instead of growing with N (plain FP32 accumulation over
-  // N = 32768 points loses about 1e-4 of a row's magnitude)
+  // FP32: the matrix core accumulates one chunk of KCH k-blocks (64
+  // points) into a fresh accumulator; chunk sums are added into (sum, cmp)
+  // with Kahan's compensated summation, so the rounding error of the
+  // accumulation stays near that of one chunk instead of growing with N
+  // (plain FP32 accumulation over N = 32768 points loses about 1e-4 of a
+  // row's magnitude)
   constexpr int NS = sizeof(T) == 4 ? NT : 1;
-  constexpr int KCH = 4;  // k-blocks per chunk (64 points)
+  constexpr int KCH = 4;
   f4 sum[NS], cmp[NS];
 #pragma unroll
   for (int t = 0; t < NS; ++t) {
@@ -170,60 +175,92 @@ kapply_kernel(int64_t n, const double *__restrict__ pts_all, int64_t ncols,
 
   // a dead tile (zero columns of X) skips the contraction and stores zeros
   const int64_t nk = live ? (nloc + BK - 1) / BK : 0;
-  fetch(0);
-  commit(0);
-  __syncthreads();
-  for (int64_t kb = 0; kb < nk; ++kb) {
-    const int buf = (int)(kb & 1);
+  constexpr int KS = BK / 4;  // MFMA depth steps per k-block
+
+  // One k-block into the accumulators c.  The B fragments of the first
+  // depth step and the block's coordinates are read from LDS before the
+  // kernel values are computed, and each later step's fragments are read
+  // while the previous step's MFMAs run, so LDS latency hides under VALU
+  // and matrix work.  The KS kernel evaluations are straight-line code (no
+  // per-lane branches) so their dependency chains interleave; depths
+  // beyond the instance are zeroed on the tail block only (a wave-uniform
+  // branch).
+  auto kblock = [&](int64_t kb, int buf, acc_t *c) {
     if (kb + 1 < nk) fetch((kb + 1) * BK);
-    // the block's kernel values first (independent, good ILP), then its
-    // 4 * NT MFMAs; a depth beyond n gets the value 0
-    constexpr int KS = BK / 4;
+    T bq[2][NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) bq[0][t] = Xs[buf][kq][t * 16 + (lane & 15)];
+    double pk4[KS][DIM];
+#pragma unroll
+    for (int s4 = 0; s4 < KS; ++s4)
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) pk4[s4][d] = Ps[buf][d][4 * s4 + kq];
+    // keep the reads above the VALU work (the scheduler would otherwise
+    // sink each read next to its use and expose the LDS latency)
+    __builtin_amdgcn_sched_barrier(0);
     T av[KS];
 #pragma unroll
     for (int s4 = 0; s4 < KS; ++s4) {
-      const int kl = 4 * s4 + kq;
       double r2 = 0.0;
 #pragma unroll
       for (int d = 0; d < DIM; ++d) {
-        const double df = pr[d] - Ps[buf][d][kl];
+        const double df = pr[d] - pk4[s4][d];
         r2 += df * df;
       }
-      const bool in = kb * BK + kl < nloc;
       if constexpr (sizeof(T) == 8)
-        av[s4] = in ? kval64<KER>(r2) : 0.0;
+        av[s4] = kval64<KER>(r2);
       else
-        av[s4] = in ? kval32<KER>((float)r2) : 0.0f;
+        av[s4] = kval32<KER>((float)r2);
+    }
+    if ((kb + 1) * BK > nloc) {
+#pragma unroll
+      for (int s4 = 0; s4 < KS; ++s4)
+        if (kb * BK + 4 * s4 + kq >= nloc) av[s4] = (T)0;
     }
 #pragma unroll
     for (int s4 = 0; s4 < KS; ++s4) {
-      const int kl = 4 * s4 + kq;
+      if (s4 + 1 < KS) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+          bq[(s4 + 1) & 1][t] = Xs[buf][4 * (s4 + 1) + kq][t * 16 + (lane & 15)];
+      }
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
-        const T b = Xs[buf][kl][t * 16 + (lane & 15)];
         if constexpr (sizeof(T) == 8)
-          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s4], b, acc[t], 0, 0, 0);
+          c[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s4], bq[s4 & 1][t], c[t], 0, 0, 0);
         else
-          acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s4], b, acc[t], 0, 0, 0);
-      }
-    }
-    if constexpr (sizeof(T) == 4) {
-      if ((kb % KCH) == KCH - 1 || kb + 1 == nk) {
-#pragma unroll
-        for (int t = 0; t < NT; ++t) {
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const float y = acc[t][i] - cmp[t][i];
-            const float u = sum[t][i] + y;
-            cmp[t][i] = (u - sum[t][i]) - y;
-            sum[t][i] = u;
-          }
-          acc[t] = (acc_t){0, 0, 0, 0};
-        }
+          c[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s4], bq[s4 & 1][t], c[t], 0, 0, 0);
       }
     }
     if (kb + 1 < nk) commit(buf ^ 1);
     __syncthreads();
+  };
+
+  fetch(0);
+  commit(0);
+  __syncthreads();
+  if constexpr (sizeof(T) == 8) {
+    for (int64_t kb = 0; kb < nk; ++kb) kblock(kb, (int)(kb & 1), acc);
+  } else {
+    for (int64_t kc = 0; kc < nk; kc += KCH) {
+      acc_t c[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) c[t] = (acc_t){0, 0, 0, 0};
+#pragma unroll
+      for (int u = 0; u < KCH; ++u)
+        if (kc + u < nk) kblock(kc + u, u & 1, c);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const float y = c[t][i] - cmp[t][i];
+          const float u = sum[t][i] + y;
+          cmp[t][i] = (u - sum[t][i]) - y;
+          sum[t][i] = u;
+        }
+      }
+    }
   }
   // D layout of the 16x16 tiles, column l%16 for lane l:
   //   FP32 16x16x4: item i -> row 4*(l/16) + i
@@ -330,10 +367,10 @@ int kapply_default_nt(int64_t ncols, bool f32) {
   return (int)(nt > cap ? cap : nt);
 }
 
-void launch_kapply(int kernel, int dim, int64_t n, const double *pts, int64_t ncols, bool f32,
-                   const void *X, int64_t ldx, void *Y, int64_t ldy, hipStream_t s) {
+void launch_kapply(int kernel, int dim, int64_t n, const double *pts, int64_t ncols, int nt,
+                   bool f32, const void *X, int64_t ldx, void *Y, int64_t ldy, hipStream_t s) {
   if (n <= 0 || ncols <= 0) return;
-  launch_any(kernel, 0, dim, n, pts, ncols, f32, X, ldx, Y, ldy, 0, nullptr, -1, s);
+  launch_any(kernel, nt, dim, n, pts, ncols, f32, X, ldx, Y, ldy, 0, nullptr, -1, s);
 }
 
 void launch_kapply_forest(int kernel, int dim, int64_t n, const double *pts, int32_t nitems,

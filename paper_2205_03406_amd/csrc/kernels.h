@@ -41,8 +41,10 @@ void launch_check_finite(int64_t n, int64_t ncols, bool f32, const void *Y, int6
 // ---- black-box applies (k_kapply.hip, k_lowrank.hip)
 // Y = K X with K(i,j) = kernel(p_i, p_j) generated on the fly (points SoA,
 // tree order), 0 where p_i == p_j.  kernel: 0 = log, 1 = 1/r.
-void launch_kapply(int kernel, int dim, int64_t n, const double *pts, int64_t ncols, bool f32,
-                   const void *X, int64_t ldx, void *Y, int64_t ldy, hipStream_t s);
+// nt: column fragments (16 columns each) per workgroup, even, 2..16; 0 =
+// kapply_default_nt.  Every nt computes the same values bit for bit.
+void launch_kapply(int kernel, int dim, int64_t n, const double *pts, int64_t ncols, int nt,
+                   bool f32, const void *X, int64_t ldx, void *Y, int64_t ldy, hipStream_t s);
 // Block-diagonal form for a forest: one work item per 64-row block of one
 // instance.  Rows [base, base + nloc) of Y are K_inst X(base : base+nloc, :)
 // where K_inst only couples points of the instance.  Columns outside

@@ -145,3 +145,18 @@ def test_errors_are_reported():
     # a valid caller coloring (all distinct) is accepted
     T.set_colors(3, np.arange(G.nv, dtype=np.int32))
     assert T.graph(3).ncolors == G.nv
+
+
+def test_single_hip_runtime_per_process():
+    """Importing the binding, then torch, must leave one HIP runtime (and one
+    HSA runtime) mapped: two copies would manage the same device apart."""
+    import subprocess
+    import sys
+    code = ("import paper_2205_03406_amd, torch\n"
+            "m = open('/proc/self/maps').read().splitlines()\n"
+            "print(len({l.split()[-1] for l in m if 'libamdhip64' in l}),"
+            " len({l.split()[-1] for l in m if 'libhsa-runtime64' in l}))\n")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True,
+                         timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.split() == ["1", "1"], out.stdout
