@@ -43,6 +43,10 @@ def parse():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=3)
+    ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--served-requests", type=int, default=80)
+    ap.add_argument("--served-loads", default="0.8",
+                    help="comma-separated offered loads (fractions of the FP64 capacity)")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run this many steps, no extras (for profilers)")
     ap.add_argument("--pmc-probe", action="store_true",
@@ -77,6 +81,10 @@ def kapply_traffic_bytes():
         if line.startswith("kapply source sha256 (first 16 hex):"):
             h = line.split(":")[1].strip()
     return val if (val is not None and h == want) else None
+
+
+def _progress(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
 def algorithmic_flops(st):
@@ -163,6 +171,122 @@ def run_batched(hm, torch, steps):
     }
 
 
+# ---------------------------------------------------------------- serving
+SERVE_RESIDENTS = [("curve", 4096), ("curve", 8192), ("curve", 16384), ("curve", 32768),
+                   ("sphere", 4096), ("sphere", 8192), ("sphere", 16384), ("sphere", 32768)]
+
+
+def _serve_points(geom, n, seed):
+    import workloads
+    return workloads.star_curve(n) if geom == "curve" else workloads.sphere(n, seed)
+
+
+def _submit_compress(srv, hm, geom, n, seed, prec):
+    pts = _serve_points(geom, n, seed)
+    if geom == "curve":
+        return srv.submit_compress(pts, 64, kernel="log", tol=1e-6, r=24, prec=prec, seed=seed)
+    return srv.submit_compress(pts, 128, kernel="inv_r", tol=1e-6, r=32, prec=prec, seed=seed)
+
+
+def _serve_once(hm, trace, xs, mixed, nslots, rate_scale):
+    """Replay `trace` (arrival times scaled by rate_scale; 0 = all at once) on
+    a fresh server holding the 8 resident H-matrices; returns per-request
+    latencies (s) by class and the makespan."""
+    prec = hm.HM_PREC_MIXED if mixed else hm.HM_PREC_F64
+    srv = hm.Server(nslots=nslots)
+    res = [_submit_compress(srv, hm, g, n, 900 + i, prec) for i, (g, n) in enumerate(SERVE_RESIDENTS)]
+    got = 0
+    while got < len(res):
+        got += len(srv.poll(wait_ms=1000))
+    kinds, lat = {}, {"compress": [], "matvec": []}
+    pending = 0
+    t0 = srv.info()["now"]
+    i = 0
+    fails = 0
+
+    def collect(wait_ms):
+        nonlocal pending, fails
+        for c in srv.poll(wait_ms=wait_ms):
+            k = kinds.pop(c["id"])
+            if c["status"] != 0:
+                fails += 1
+            lat[k].append(c["t_end"] - c["t_submit"])
+            if k == "compress":
+                srv.release(c["hmatrix"])
+            pending -= 1
+
+    while i < len(trace):
+        due = t0 + trace[i].t_arrival * rate_scale
+        now = srv.info()["now"]
+        if now < due:
+            collect(int(min(50.0, (due - now) * 1e3)) if pending else 0)
+            if not pending:
+                time.sleep(max(0.0, min(0.05, due - srv.info()["now"])))
+            continue
+        q = trace[i]
+        if q.kind == "compress":
+            rid = _submit_compress(srv, hm, q.geometry, q.n, q.seed, prec)
+        else:
+            rid = srv.submit_matvec(res[q.target], xs[mixed][q.target][:q.nrhs].T)
+        kinds[rid] = q.kind
+        pending += 1
+        i += 1
+    while pending:
+        collect(1000)
+    t_end = srv.info()["now"]
+    srv.close()
+    return lat, t_end - t0, fails
+
+
+def run_served(hm, count, loads):
+    """Served mix: Poisson arrivals, 1 in 10 a compression (star curve or
+    sphere, N log-uniform in [4096, 65536], tol 1e-6), the rest applies with
+    1..64 right-hand sides on one of 8 resident H-matrices.  Baseline: the
+    plain FP64 path, one request at a time in arrival order (one slot).
+    Served: the mixed form with FP32 right-hand sides, 4 slots, admission by
+    device memory.  The arrival rate is the given fraction of the FP64
+    path's capacity (requests/s it completes back to back)."""
+    import workloads
+    trace = workloads.serve_trace(count, 1.0, seed=5, n_resident=len(SERVE_RESIDENTS))
+    # right-hand sides: one (n, 64) block per resident, sliced per request
+    rng = np.random.default_rng(7)
+    pool = [rng.standard_normal((64, n)) for _, n in SERVE_RESIDENTS]  # column-major (n, 64)
+    xs = {False: pool, True: [x.astype(np.float32) for x in pool]}
+    # capacity of the FP64 path: the whole trace back to back on one slot
+    # (this pass also settles the kernel-apply autotuner on the trace's
+    # FP64 shapes; a back-to-back pass of the mixed form does the same for
+    # its shapes, so neither timed run pays first-use tuning)
+    _, makespan, _ = _serve_once(hm, trace, xs, False, 1, 0.0)
+    capacity = count / makespan
+    _progress("served mix: FP64 back-to-back pass %.1f s (%.2f requests/s)" % (makespan, capacity))
+    _, span, _ = _serve_once(hm, trace, xs, True, 4, 0.0)
+    _progress("served mix: mixed back-to-back pass %.1f s" % span)
+    out = {"requests": count, "compress_share": round(sum(q.kind == "compress" for q in trace) / count, 3),
+           "fp64_capacity_req_per_s": round(capacity, 3), "loads": {}}
+
+    def summary(lat, span, fails):
+        allv = np.array(lat["compress"] + lat["matvec"]) * 1e3
+        d = {"throughput_req_per_s": round(count / span, 3), "failed": fails,
+             "p50_ms": round(float(np.percentile(allv, 50)), 3),
+             "p99_ms": round(float(np.percentile(allv, 99)), 3)}
+        for k in ("compress", "matvec"):
+            v = np.array(lat[k]) * 1e3
+            d[k] = {"n": len(v), "p50_ms": round(float(np.percentile(v, 50)), 3),
+                    "p99_ms": round(float(np.percentile(v, 99)), 3)}
+        return d
+
+    for load in loads:
+        rate = load * capacity
+        scale = 1.0 / rate  # the trace was drawn at 1 request/s
+        base = summary(*_serve_once(hm, trace, xs, False, 1, scale))
+        _progress("served mix: load %.2f FP64 one-at-a-time done" % load)
+        served = summary(*_serve_once(hm, trace, xs, True, 4, scale))
+        _progress("served mix: load %.2f served done" % load)
+        out["loads"][str(load)] = {"rate_req_per_s": round(rate, 3), "fp64_fifo": base,
+                                   "served_mixed_4slots": served}
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -200,6 +324,7 @@ def main():
         return
 
     r64 = run_path(hm, torch, inst, hm.HM_PREC_F64, inst.tol, args.steps, args.warmup, x, y)
+    _progress("FP64 path done")
     st = r64["stats"]
     ms = 1e3 * r64["total"] / args.steps
     value = r64["flops"] / r64["total"] / 1e9
@@ -277,6 +402,11 @@ def main():
 
     if not args.no_batched:
         out["batched"] = run_batched(hm, torch, args.batched_steps)
+        _progress("batched done")
+
+    if not args.no_served:
+        out["served"] = run_served(hm, args.served_requests,
+                                   [float(x) for x in args.served_loads.split(",")])
 
     if not args.no_cpu_baseline:
         # the oracle, untuned, on one full compression of the same workload

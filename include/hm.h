@@ -295,6 +295,65 @@ hm_status hm_hmatrix_export_level(const hm_hmatrix *H, int level, int64_t *npair
 hm_status hm_hmatrix_export_near(const hm_hmatrix *H, int64_t *npairs, int32_t *pair_a,
                                  int32_t *pair_b, int64_t *size, double *D);
 
+/* ------------------------------------------------------------------ serving
+ * A request loop on one GPU that keeps compressed H-matrices resident and
+ * runs compressions and applies of different sizes side by side
+ * (continuous batching).  nslots host workers, each with its own stream,
+ * take pending requests in arrival order; a request starts as soon as a
+ * worker is free and its device-memory footprint fits beside the resident
+ * H-matrices and the work in flight (an apply also waits for its
+ * H-matrix; a compression also waits while compress_slots others run).  Results do not depend on what else runs: every request
+ * computes exactly what the same call made alone computes.
+ *
+ * Ownership: the server owns the H-matrices it makes (freed by
+ * hm_server_release or hm_server_free).  Calls are thread-safe. */
+typedef struct hm_server hm_server;
+
+typedef struct {
+  int64_t hbm_budget;     /* device bytes for residents + work in flight (<= 0: 90% of free) */
+  int32_t nslots;         /* requests on the GPU at once, 1..64 */
+  int32_t compress_slots; /* of which compressions, at most (<= 0: 1) */
+} hm_server_opts;
+
+typedef struct {
+  int64_t id;       /* request id returned by the submit call */
+  int32_t kind;     /* 0 compression, 1 apply */
+  int32_t status;   /* hm_status of the request */
+  int64_t hmatrix;  /* compression: id of the H-matrix it made (its request id);
+                       apply: the H-matrix it used */
+  double t_submit, t_admit, t_start, t_end; /* seconds on the server's clock */
+  int64_t bytes;    /* device bytes reserved for the request */
+} hm_completion;
+
+hm_status hm_server_create(const hm_server_opts *opts, hm_server **out);
+/* Stops taking requests, waits for the running ones, frees every resident
+ * H-matrix; pending requests are dropped. */
+void hm_server_free(hm_server *srv);
+/* Queue a compression: hm_build_tree(points, ...), hm_tree_color, the
+ * built-in kernel black box `kernel`, hm_compress(opts).  points (host) are
+ * copied.  The H-matrix id is the request id. */
+hm_status hm_server_submit_compress(hm_server *srv, const double *points, int64_t n, int dim,
+                                    int leaf_size, int tree_kind, int adm, int kernel,
+                                    const hm_compress_opts *opts, int64_t *request_id);
+/* Queue Y = H X for a resident (or queued) H-matrix: X, Y host, n x nrhs
+ * column-major (ld = n), original point order, dtype HM_F64 or HM_F32.  X is
+ * copied before the call returns; Y must stay valid until the completion is
+ * returned by hm_server_poll. */
+hm_status hm_server_submit_matvec(hm_server *srv, int64_t hmatrix, int64_t nrhs, int dtype,
+                                  const void *X, void *Y, int64_t *request_id);
+/* Up to max completions in completion order; waits up to wait_ms (0: no
+ * wait, < 0: until one completes) when none is ready. */
+hm_status hm_server_poll(hm_server *srv, int32_t max, int32_t wait_ms, hm_completion *out,
+                         int32_t *count);
+/* Borrow a resident H-matrix (valid until it is released). */
+hm_status hm_server_hmatrix(hm_server *srv, int64_t hmatrix, const hm_hmatrix **H);
+/* Evict a resident H-matrix (once its running applies finish). */
+hm_status hm_server_release(hm_server *srv, int64_t hmatrix);
+/* Server clock (seconds since creation), device bytes in use and budget,
+ * pending and running requests, resident H-matrices; any may be NULL. */
+hm_status hm_server_info(hm_server *srv, double *now, int64_t *in_use, int64_t *budget,
+                         int32_t *pending, int32_t *running, int32_t *residents);
+
 #ifdef __cplusplus
 }
 #endif

@@ -20,6 +20,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "libhm.so")
 
 HM_OK = 0
+HM_E_ARG, HM_E_NOMEM, HM_E_DEVICE, HM_E_CALLBACK = -1, -2, -3, -4
+HM_E_NUMERIC, HM_E_STATE, HM_E_SATURATED = -5, -6, -7
 HM_TREE_GEOMETRIC, HM_TREE_INDEX_BINARY = 0, 1
 HM_ADM_STRONG, HM_ADM_WEAK = 0, 1
 HM_F64, HM_F32 = 0, 1
@@ -35,7 +37,9 @@ EXPORTED = [
     "hm_dense_blackbox", "hm_dense_blackbox_free", "hm_compress", "hm_hmatrix_free",
     "hm_matvec", "hm_test_matrix", "hm_philox4x32_10", "hm_hmatrix_stats",
     "hm_hmatrix_export_level", "hm_hmatrix_export_near", "hm_build_forest",
-    "hm_tree_instances", "hm_autotune_table",
+    "hm_tree_instances", "hm_autotune_table", "hm_server_create", "hm_server_free",
+    "hm_server_submit_compress", "hm_server_submit_matvec", "hm_server_poll", "hm_server_hmatrix",
+    "hm_server_release", "hm_server_info",
 ]
 
 
@@ -77,6 +81,17 @@ class Stats(C.Structure):
             v = getattr(self, name)
             d[name] = list(v) if name == "colors" else v
         return d
+
+
+class ServerOpts(C.Structure):
+    _fields_ = [("hbm_budget", C.c_int64), ("nslots", C.c_int32),
+                ("compress_slots", C.c_int32)]
+
+
+class Completion(C.Structure):
+    _fields_ = [("id", C.c_int64), ("kind", C.c_int32), ("status", C.c_int32),
+                ("hmatrix", C.c_int64), ("t_submit", C.c_double), ("t_admit", C.c_double),
+                ("t_start", C.c_double), ("t_end", C.c_double), ("bytes", C.c_int64)]
 
 
 def _load():
@@ -124,11 +139,19 @@ def _load():
         "hm_hmatrix_stats": [P, C.POINTER(Stats)],
         "hm_hmatrix_export_level": [P, I, P, P, P, P, P, P, P, P, P, P, P],
         "hm_hmatrix_export_near": [P, P, P, P, P, P],
+        "hm_server_create": [C.POINTER(ServerOpts), pp],
+        "hm_server_free": [P],
+        "hm_server_submit_compress": [P, P, I64, I, I, I, I, I, C.POINTER(Opts), P],
+        "hm_server_submit_matvec": [P, I64, I64, I, P, P, P],
+        "hm_server_poll": [P, C.c_int32, C.c_int32, P, P],
+        "hm_server_hmatrix": [P, I64, pp],
+        "hm_server_release": [P, I64],
+        "hm_server_info": [P, P, P, P, P, P, P],
     }
     for name, args in sigs.items():
         f = getattr(lib, name)
         f.argtypes = args
-        if name in ("hm_tree_free", "hm_hmatrix_free", "hm_dense_blackbox_free"):
+        if name in ("hm_tree_free", "hm_hmatrix_free", "hm_dense_blackbox_free", "hm_server_free"):
             f.restype = None
         else:
             f.restype = C.c_int
@@ -421,6 +444,99 @@ class HMatrix:
             out.append((int(pa[q]), int(pb[q]), D[o:o + ma * mb].reshape(mb, ma).T))
             o += ma * mb
         return out
+
+
+class _Borrowed(HMatrix):
+    """An H-matrix owned by a server (not freed here)."""
+
+    def __del__(self):
+        self.h = None
+
+
+class Server:
+    """hm_server: a request loop on one GPU with resident H-matrices.
+
+    submit_* return request ids; a compression's H-matrix id is its request
+    id.  Apply inputs and outputs are host arrays (n, nrhs); the output array
+    of each apply is kept here until its completion is polled."""
+
+    def __init__(self, nslots=4, hbm_budget=0, compress_slots=1):
+        o = ServerOpts(hbm_budget=hbm_budget, nslots=nslots, compress_slots=compress_slots)
+        h = C.c_void_p()
+        _check(_lib.hm_server_create(C.byref(o), C.byref(h)))
+        self.h = h
+        self._out = {}
+        self._n = {}
+
+    def close(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.hm_server_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def submit_compress(self, points, leaf, kind="geometric", adm="strong", kernel="log", rank=0,
+                        tol=0.0, r=0, p=10, prec=HM_PREC_F64, seed=0):
+        pts = np.ascontiguousarray(points, np.float64)
+        if pts.ndim == 1:
+            pts = pts.reshape(-1, 1)
+        o = Opts(rank=rank, tol=tol, oversample=p, r=r, prec=prec, flags=0, seed=seed)
+        rid = C.c_int64()
+        _check(_lib.hm_server_submit_compress(
+            self.h, _ptr(pts), pts.shape[0], pts.shape[1], leaf,
+            HM_TREE_INDEX_BINARY if kind == "index_binary" else HM_TREE_GEOMETRIC,
+            HM_ADM_WEAK if adm == "weak" else HM_ADM_STRONG,
+            HM_KERNEL_INV_R if kernel == "inv_r" else HM_KERNEL_LOG, C.byref(o), C.byref(rid)))
+        self._n[rid.value] = pts.shape[0]
+        return rid.value
+
+    def submit_matvec(self, hmatrix, X):
+        X = np.asarray(X)
+        if X.ndim == 1:
+            X = X.reshape(-1, 1)
+        if X.dtype not in (np.float32, np.float64):
+            raise ValueError("X must be float32 or float64")
+        n, nrhs = X.shape
+        if self._n.get(hmatrix) not in (None, n):
+            raise ValueError("X has %d rows, the H-matrix %d" % (n, self._n[hmatrix]))
+        Xc = np.ascontiguousarray(X.T)            # column-major n x nrhs
+        Y = np.empty((nrhs, n), X.dtype)          # column-major n x nrhs
+        rid = C.c_int64()
+        _check(_lib.hm_server_submit_matvec(self.h, hmatrix, nrhs,
+                                            HM_F32 if X.dtype == np.float32 else HM_F64,
+                                            _ptr(Xc), _ptr(Y), C.byref(rid)))
+        self._out[rid.value] = Y
+        return rid.value
+
+    def poll(self, max_count=256, wait_ms=0):
+        buf = (Completion * max_count)()
+        k = C.c_int32()
+        _check(_lib.hm_server_poll(self.h, max_count, wait_ms, buf, C.byref(k)))
+        out = []
+        for c in buf[:k.value]:
+            d = {name: getattr(c, name) for name, _ in Completion._fields_}
+            Y = self._out.pop(c.id, None)
+            if Y is not None:
+                d["Y"] = Y.T                          # (n, nrhs) view
+            out.append(d)
+        return out
+
+    def hmatrix(self, hmatrix):
+        h = C.c_void_p()
+        _check(_lib.hm_server_hmatrix(self.h, hmatrix, C.byref(h)))
+        return _Borrowed(h, None)
+
+    def release(self, hmatrix):
+        _check(_lib.hm_server_release(self.h, hmatrix))
+
+    def info(self):
+        now, use, bud = C.c_double(), C.c_int64(), C.c_int64()
+        pend, run, res = C.c_int32(), C.c_int32(), C.c_int32()
+        _check(_lib.hm_server_info(self.h, C.byref(now), C.byref(use), C.byref(bud),
+                                   C.byref(pend), C.byref(run), C.byref(res)))
+        return dict(now=now.value, in_use=use.value, budget=bud.value, pending=pend.value,
+                    running=run.value, residents=res.value)
 
 
 def compress(tree: Tree, bb: BlackBox, rank=0, tol=0.0, r=0, p=10, prec=HM_PREC_F64, seed=0,

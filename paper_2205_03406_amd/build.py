@@ -20,7 +20,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhm.so")
 
 HIP_SOURCES = ["k_misc.hip", "k_kapply.hip", "k_lowrank.hip", "k_qr.hip", "autotune.hip",
-               "engine.hip"]
+               "engine.hip", "server.hip"]
 CXX_SOURCES = ["tree.cpp"]
 ARCH = os.environ.get("HM_OFFLOAD_ARCH", "gfx950")
 

@@ -5,13 +5,14 @@
 // registers (occupancy) and the dead columns of the last tile; the best
 // value depends on the column count, the precision and the point count, and
 // is not monotonic in any of them.  The first launch of each shape times
-// every candidate on the real operands and keeps the fastest; every
-// candidate computes the same values bit for bit, so the output of the
-// timing runs is the result.  Decisions live for the process, and in the
+// every candidate on a prefix of the real work (256 row blocks or forest
+// items) and keeps the fastest, then runs it on the whole; every candidate
+// computes the same values bit for bit.  Decisions live for the process, and in the
 // file named by HM_TUNE_FILE when it is set (one decision per line).
-// HM_AUTOTUNE=0 turns tuning off (the fixed rule of kapply_default_nt).
+// HM_AUTOTUNE=0 turns tuning off (the cost rule of kapply_default_nt).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -72,13 +73,13 @@ void append_file(const std::tuple<int, int, int, int64_t, int, int> &k, const En
 
 }  // namespace
 
-int autotune_kapply(const KapplyShape &shape, const std::function<void(int)> &launch,
-                    void *stream) {
+int autotune_kapply(const KapplyShape &shape,
+                    const std::function<void(int, int64_t)> &launch, void *stream) {
   hipStream_t s = (hipStream_t)stream;
-  const int def = kapply_default_nt(shape.ncols, shape.f32);
+  const int def = kapply_default_nt(shape.ncols, shape.f32, shape.units);
   const char *env = std::getenv("HM_AUTOTUNE");
   if (env && std::strcmp(env, "0") == 0) {
-    launch(def);
+    launch(def, 0);
     return def;
   }
   const auto key = key_of(shape);
@@ -87,7 +88,7 @@ int autotune_kapply(const KapplyShape &shape, const std::function<void(int)> &la
     if (!g_loaded) load_file();
     auto it = g_table.find(key);
     if (it != g_table.end()) {
-      launch(it->second.nt);
+      launch(it->second.nt, 0);
       return it->second.nt;
     }
   }
@@ -95,22 +96,25 @@ int autotune_kapply(const KapplyShape &shape, const std::function<void(int)> &la
   // warms the caches
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) {
-    launch(def);
+    launch(def, 0);
     return def;
   }
   if (hipEventCreate(&e1) != hipSuccess) {
     (void)hipEventDestroy(e0);
-    launch(def);
+    launch(def, 0);
     return def;
   }
-  launch(def);
+  // candidates are timed on a prefix of the work (every candidate computes
+  // the same values; the full launch with the winner follows)
+  const int64_t sub = shape.units > 0 ? std::min<int64_t>(shape.units, 256) : 0;
+  launch(def, sub);
   int best = def;
   float best_ms = 1e30f, def_ms = 1e30f;
   const int cands[] = {2, 4, 6, 8, 10, 12, 14, 16};
   for (int nt : cands) {
     if (nt > 2 && (int64_t)16 * (nt - 2) >= shape.ncols) break;  // wider than all columns
     (void)hipEventRecord(e0, s);
-    launch(nt);
+    launch(nt, sub);
     (void)hipEventRecord(e1, s);
     if (hipEventSynchronize(e1) != hipSuccess) break;
     float ms = 0;
@@ -123,6 +127,7 @@ int autotune_kapply(const KapplyShape &shape, const std::function<void(int)> &la
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  launch(best, 0);
   Entry e{best, best_ms, def_ms};
   {
     std::lock_guard<std::mutex> lk(g_mu);

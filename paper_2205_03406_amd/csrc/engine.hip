@@ -56,13 +56,20 @@ hm_status fail(hm_status code, const std::string &msg) {
   } while (0)
 
 // ------------------------------------------------------------------ device buffers
+// Device buffer.  alloc(): plain hipMalloc / hipFree, for objects that
+// outlive the call that makes them (trees, H-matrices).  temp(): stream-
+// ordered hipMallocAsync / hipFreeAsync on the stream of the work that uses
+// it, so the scratch of one compression is freed without waiting on work
+// that other streams (other requests) have in flight.
 struct DBuf {
   void *p = nullptr;
   size_t bytes = 0;
+  hipStream_t st = nullptr;
+  bool async = false;
   DBuf() = default;
   DBuf(const DBuf &) = delete;
   DBuf &operator=(const DBuf &) = delete;
-  DBuf(DBuf &&o) noexcept : p(o.p), bytes(o.bytes) {
+  DBuf(DBuf &&o) noexcept : p(o.p), bytes(o.bytes), st(o.st), async(o.async) {
     o.p = nullptr;
     o.bytes = 0;
   }
@@ -70,6 +77,8 @@ struct DBuf {
     release();
     p = o.p;
     bytes = o.bytes;
+    st = o.st;
+    async = o.async;
     o.p = nullptr;
     o.bytes = 0;
     return *this;
@@ -84,9 +93,22 @@ struct DBuf {
       throw Error{HM_E_NOMEM, "device allocation of " + std::to_string(b) + " bytes failed"};
     }
     bytes = b;
+    async = false;
+  }
+  void temp(size_t b, hipStream_t s) {
+    release();
+    if (b == 0) b = 64;
+    if (hipMallocAsync(&p, b, s) != hipSuccess) {
+      p = nullptr;
+      (void)hipGetLastError();
+      throw Error{HM_E_NOMEM, "device allocation of " + std::to_string(b) + " bytes failed"};
+    }
+    bytes = b;
+    st = s;
+    async = true;
   }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) (void)(async ? hipFreeAsync(p, st) : hipFree(p));
     p = nullptr;
     bytes = 0;
   }
@@ -99,6 +121,14 @@ struct DBuf {
 template <class T>
 void upload(DBuf &d, const std::vector<T> &v, hipStream_t s) {
   d.alloc(v.size() * sizeof(T));
+  if (!v.empty())
+    HIP_TRY(hipMemcpyAsync(d.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+}
+
+// upload into stream-ordered scratch (see DBuf::temp)
+template <class T>
+void upload_temp(DBuf &d, const std::vector<T> &v, hipStream_t s) {
+  d.temp(v.size() * sizeof(T), s);
   if (!v.empty())
     HIP_TRY(hipMemcpyAsync(d.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
 }
@@ -178,15 +208,17 @@ void kernel_apply_tree(const Tree &T, int kernel, int64_t ncols, bool f32, const
                        int64_t ldx, void *Y, int64_t ldy, hipStream_t s) {
   const DeviceTree &D = *T.dev;
   const bool forest = T.ninst() > 1;
-  autotune_kapply(KapplyShape{f32, kernel, T.dim, ncols, T.n, forest},
-                  [&](int nt) {
+  const int64_t units = forest ? D.nkitems : (T.n + 63) / 64;
+  autotune_kapply(KapplyShape{f32, kernel, T.dim, ncols, T.n, forest, units},
+                  [&](int nt, int64_t part) {
                     if (forest)
-                      launch_kapply_forest(kernel, T.dim, T.n, D.pts.as<double>(), D.nkitems,
+                      launch_kapply_forest(kernel, T.dim, T.n, D.pts.as<double>(),
+                                           part > 0 ? (int32_t)part : D.nkitems,
                                            D.kitems.as<KItem>(), ncols, -1, nt, f32, X, ldx, Y,
                                            ldy, s);
                     else
                       launch_kapply(kernel, T.dim, T.n, D.pts.as<double>(), ncols, nt, f32, X,
-                                    ldx, Y, ldy, s);
+                                    ldx, Y, ldy, s, part * 64);
                   },
                   s);
 }
@@ -447,8 +479,8 @@ hm_status call_blackbox(const hm_blackbox &bb, int transpose, int64_t n, int64_t
     return HM_OK;
   }
   const size_t need = (size_t)n * ncols * es;
-  if (tmpx.bytes < need) tmpx.alloc(need);
-  if (tmpy.bytes < need) tmpy.alloc(need);
+  if (tmpx.bytes < need) tmpx.temp(need, s);
+  if (tmpy.bytes < need) tmpy.temp(need, s);
   launch_permute_rows(n, ncols, D.perm.as<int64_t>(), true, f32, X, ldx, tmpx.p, n, s);
   LAUNCH_CHECK();
   const int rc = bb.apply(bb.ctx, transpose, n, ncols, dtype, tmpx.p, n, tmpy.p, n, (void *)s);
@@ -590,10 +622,10 @@ hm_status compress_impl(Tree &T, const hm_blackbox &bb, const hm_compress_opts &
   const int64_t leaf_cols = pad16((int64_t)GL.ncolors * mw);
   const int64_t wcols = std::max<int64_t>(2 * cmax, leaf_cols);
   DBuf Xb, Yb, tmpx, tmpy, Tb, work, core, scratch, jobs, sat, flag;
-  Xb.alloc((size_t)n * wcols * es);
-  Yb.alloc((size_t)n * wcols * es);
+  Xb.temp((size_t)n * wcols * es, s);
+  Yb.temp((size_t)n * wcols * es, s);
   const int64_t tcap = tscratch_elems(*H, wcols);
-  Tb.alloc((size_t)tcap * es);
+  Tb.temp((size_t)tcap * es, s);
   int64_t wmax = 0, cmax_np = 0;
   for (size_t li = 0; li < H->lv.size(); ++li) {
     const hm_hmatrix::Lv &L = H->lv[li];
@@ -604,18 +636,18 @@ hm_status compress_impl(Tree &T, const hm_blackbox &bb, const hm_compress_opts &
     wmax = std::max(wmax, rows * r);
     cmax_np = std::max(cmax_np, L.np);
   }
-  work.alloc((size_t)std::max<int64_t>(wmax, 1) * 8);
-  core.alloc((size_t)std::max<int64_t>(cmax_np, 1) * r * r * 8);
-  scratch.alloc((size_t)std::max<int64_t>(cmax_np, 1) * r * r * 8);
-  sat.alloc((size_t)std::max<int64_t>(2 * np_total, 1) * 4);
+  work.temp((size_t)std::max<int64_t>(wmax, 1) * 8, s);
+  core.temp((size_t)std::max<int64_t>(cmax_np, 1) * r * r * 8, s);
+  scratch.temp((size_t)std::max<int64_t>(cmax_np, 1) * r * r * 8, s);
+  sat.temp((size_t)std::max<int64_t>(2 * np_total, 1) * 4, s);
   launch_fill(sat.p, std::max<int64_t>(2 * np_total, 1), true, 0.0, s);
-  flag.alloc(64);
+  flag.temp(64, s);
   launch_fill(flag.p, 1, true, 0.0, s);
   // mixed path: per-block noise floors of the FP32 samples (see below)
   DBuf floor_u, floor_v;
   if (mixed) {
-    floor_u.alloc((size_t)std::max<int64_t>(cmax_np, 1) * 8);
-    floor_v.alloc((size_t)std::max<int64_t>(cmax_np, 1) * 8);
+    floor_u.temp((size_t)std::max<int64_t>(cmax_np, 1) * 8, s);
+    floor_v.temp((size_t)std::max<int64_t>(cmax_np, 1) * 8, s);
   }
   LAUNCH_CHECK();
 
@@ -672,13 +704,13 @@ hm_status compress_impl(Tree &T, const hm_blackbox &bb, const hm_compress_opts &
       std::vector<int32_t> w = inst_colors(L.level);
       for (int32_t &x : w) x *= r;
       std::vector<KItem> kit = forest_items(T, w);
-      upload(jobs_of[li].kit, kit, s);
+      upload_temp(jobs_of[li].kit, kit, s);
       jobs_of[li].nkit = (int32_t)kit.size();
     }
-    upload(jobs_of[li].act, act, s);
-    upload(jobs_of[li].ju, ju, s);
-    upload(jobs_of[li].jv, jv, s);
-    upload(jobs_of[li].jc, jc, s);
+    upload_temp(jobs_of[li].act, act, s);
+    upload_temp(jobs_of[li].ju, ju, s);
+    upload_temp(jobs_of[li].jv, jv, s);
+    upload_temp(jobs_of[li].jc, jc, s);
     HIP_TRY(hipStreamSynchronize(s));  // the host vectors die here
   }
 
@@ -703,11 +735,12 @@ hm_status compress_impl(Tree &T, const hm_blackbox &bb, const hm_compress_opts &
     LAUNCH_CHECK();
     ev.mark(1);
     if (direct) {
-      autotune_kapply(KapplyShape{mixed, kbb->kernel, T.dim, 2 * cpad, n, true},
-                      [&](int nt) {
+      autotune_kapply(KapplyShape{mixed, kbb->kernel, T.dim, 2 * cpad, n, true, jobs_of[li].nkit},
+                      [&](int nt, int64_t part) {
                         launch_kapply_forest(kbb->kernel, T.dim, n, D.pts.as<double>(),
-                                             jobs_of[li].nkit, jobs_of[li].kit.as<KItem>(),
-                                             2 * cpad, cpad, nt, mixed, Om, n, Yl, n, s);
+                                             part > 0 ? (int32_t)part : jobs_of[li].nkit,
+                                             jobs_of[li].kit.as<KItem>(), 2 * cpad, cpad, nt,
+                                             mixed, Om, n, Yl, n, s);
                       },
                       s);
       LAUNCH_CHECK();
@@ -784,14 +817,14 @@ hm_status compress_impl(Tree &T, const hm_blackbox &bb, const hm_compress_opts &
     }
     // one item per (box, color) is enough; duplicates write the same ones
     DBuf dib, dic, dkit;
-    upload(dib, ib, s);
-    upload(dic, ic, s);
+    upload_temp(dib, ib, s);
+    upload_temp(dic, ic, s);
     std::vector<KItem> kit;
     if (direct) {
       std::vector<int32_t> w = inst_colors(T.nlev());
       for (int32_t &x : w) x *= mw;
       kit = forest_items(T, w);
-      upload(dkit, kit, s);
+      upload_temp(dkit, kit, s);
     }
     ev.mark(0);
     launch_leaf_identity(n, (int32_t)ib.size(), dib.as<int32_t>(), dic.as<int32_t>(),
@@ -799,11 +832,13 @@ hm_status compress_impl(Tree &T, const hm_blackbox &bb, const hm_compress_opts &
     LAUNCH_CHECK();
     ev.mark(1);
     if (direct) {
-      autotune_kapply(KapplyShape{mixed, kbb->kernel, T.dim, leaf_cols, n, true},
-                      [&](int nt) {
+      autotune_kapply(KapplyShape{mixed, kbb->kernel, T.dim, leaf_cols, n, true,
+                                  (int64_t)kit.size()},
+                      [&](int nt, int64_t part) {
                         launch_kapply_forest(kbb->kernel, T.dim, n, D.pts.as<double>(),
-                                             (int32_t)kit.size(), dkit.as<KItem>(), leaf_cols,
-                                             -1, nt, mixed, Xb.p, n, Yb.p, n, s);
+                                             part > 0 ? (int32_t)part : (int32_t)kit.size(),
+                                             dkit.as<KItem>(), leaf_cols, -1, nt, mixed, Xb.p, n,
+                                             Yb.p, n, s);
                       },
                       s);
       LAUNCH_CHECK();
@@ -825,11 +860,11 @@ hm_status compress_impl(Tree &T, const hm_blackbox &bb, const hm_compress_opts &
       c0[q] = (int64_t)GL.color[GL.pv[q]] * mw;
     }
     DBuf dr0, dc0, dma, dmb, doff;
-    upload(dr0, r0, s);
-    upload(dc0, c0, s);
-    upload(dma, ma, s);
-    upload(dmb, mb, s);
-    upload(doff, H->offD, s);
+    upload_temp(dr0, r0, s);
+    upload_temp(dc0, c0, s);
+    upload_temp(dma, ma, s);
+    upload_temp(dmb, mb, s);
+    upload_temp(doff, H->offD, s);
     launch_extract_near((int32_t)GL.pa.size(), dr0.as<int64_t>(), dma.as<int32_t>(),
                         dc0.as<int64_t>(), dmb.as<int32_t>(), doff.as<int64_t>(), mixed, Yb.p, n,
                         H->D.as<double>(), s);
@@ -843,10 +878,12 @@ hm_status compress_impl(Tree &T, const hm_blackbox &bb, const hm_compress_opts &
   std::vector<int32_t> hsat(2 * np_total);
   int32_t hflag = 0;
   if (np_total) {
-    HIP_TRY(hipMemcpy(H->h_ranks.data(), H->ranks.p, 2 * np_total * 4, hipMemcpyDeviceToHost));
-    HIP_TRY(hipMemcpy(hsat.data(), sat.p, 2 * np_total * 4, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpyAsync(H->h_ranks.data(), H->ranks.p, 2 * np_total * 4,
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(hsat.data(), sat.p, 2 * np_total * 4, hipMemcpyDeviceToHost, s));
   }
-  HIP_TRY(hipMemcpy(&hflag, flag.p, 4, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpyAsync(&hflag, flag.p, 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
   if (hflag) return fail(HM_E_NUMERIC, "NaN or Inf in the black-box samples");
 
   // ---------------- statistics
@@ -941,6 +978,69 @@ hm_status compress_impl(Tree &T, const hm_blackbox &bb, const hm_compress_opts &
 }
 
 }  // namespace
+
+// Device bytes an H-matrix holds (factor pools, near blocks, apply plans).
+int64_t hmatrix_device_bytes(const hm_hmatrix *H) {
+  int64_t b = H->perm.bytes + H->U.bytes + H->V.bytes + H->W.bytes + H->B.bytes + H->Vf.bytes +
+              H->Wf.bytes + H->D.bytes + H->ranks.bytes + H->nchunks.bytes + H->nentries.bytes;
+  for (const hm_hmatrix::Orient *O : {&H->oA, &H->oT}) {
+    b += O->items.bytes + O->ppairs.bytes;
+    for (const DBuf &d : O->chunks) b += d.bytes;
+    for (const DBuf &d : O->entries) b += d.bytes;
+  }
+  return b;
+}
+
+// Peak device bytes of one compression of T (factor pools at the largest
+// rank, sample and scratch buffers, plans), from the same sizes
+// compress_impl allocates; an admission estimate (plans are approximated).
+int64_t compress_footprint(const Tree &T, const hm_compress_opts &o) {
+  const int p = o.oversample > 0 ? o.oversample : 10;
+  const int kfix = o.rank > 0 ? o.rank : 0;
+  const int r = o.r > 0 ? o.r : (kfix > 0 ? kfix + p : 0);
+  if (r <= 0) return 0;
+  const int64_t kmax = kfix > 0 ? std::min(kfix, r) : r - p;
+  const int64_t es = o.prec == HM_PREC_MIXED ? 4 : 8;
+  const int64_t n = T.n;
+  int64_t szU = 0, szV = 0, np = 0, cmax = 0, wmax = 0, cmax_np = 0, slots = 0;
+  for (int l = 1; l < T.nlev(); ++l) {
+    const Graph &G = T.graphs[l];
+    if (G.pa.empty()) continue;
+    const Level &Lv = T.lev[l];
+    int64_t rows = 0;
+    for (size_t q = 0; q < G.pa.size(); ++q) {
+      const int64_t ma = Lv.start[G.pa[q] + 1] - Lv.start[G.pa[q]];
+      const int64_t mb = Lv.start[G.pb[q] + 1] - Lv.start[G.pb[q]];
+      szU += ma * kmax;
+      szV += mb * kmax;
+      rows += ma + mb;
+      slots += (std::max(ma, mb) + 255) / 256;
+    }
+    np += (int64_t)G.pa.size();
+    cmax = std::max<int64_t>(cmax, pad16((int64_t)G.ncolors * r));
+    wmax = std::max(wmax, rows * r);
+    cmax_np = std::max<int64_t>(cmax_np, (int64_t)G.pa.size());
+  }
+  const Graph &GL = T.leaf_graph();
+  int64_t szD = 0;
+  for (size_t q = 0; q < GL.pa.size(); ++q)
+    szD += T.box_size(T.L(), GL.pa[q]) * T.box_size(T.L(), GL.pb[q]);
+  const int64_t leaf_cols = pad16((int64_t)GL.ncolors * T.leaf_width());
+  const int64_t wcols = std::max<int64_t>(2 * cmax, leaf_cols);
+  const int64_t pools = szU * (8 + 8 + 4) + szV * (8 + 4) + np * kmax * kmax * 8 + szD * 8 +
+                        np * 8 + n * 8;
+  const int64_t tcap = std::min<int64_t>(slots * kmax * wcols, int64_t(64) << 20);
+  const int64_t scratch = 2 * n * wcols * es + tcap * es + wmax * 8 + 2 * cmax_np * r * r * 8 +
+                          np * 8 + cmax_np * 16;
+  const int64_t plans = 64 * np + 4096;
+  return pools + scratch + plans;
+}
+
+// Device bytes of one hm_matvec call (scratch and order conversion).
+int64_t matvec_footprint(const hm_hmatrix *H, int64_t nrhs, int dtype) {
+  const int64_t es = dtype == HM_F32 ? 4 : 8;
+  return tscratch_elems(*H, nrhs) * es + 2 * H->n * nrhs * es;
+}
 
 }  // namespace hm
 

@@ -79,18 +79,26 @@ hm_status build_forest(const double *pts, const int64_t *counts, int ninst, int 
                        int kind, int adm, Tree &F);
 int32_t dsatur(int64_t nv, const int64_t *xadj, const int32_t *adj, int32_t *color);
 
+// ------------------------------------------------------------------ sizes
+int64_t hmatrix_device_bytes(const hm_hmatrix *H);
+int64_t compress_footprint(const Tree &T, const hm_compress_opts &o);
+int64_t matvec_footprint(const hm_hmatrix *H, int64_t nrhs, int dtype);
+
 // ------------------------------------------------------------------ autotuner
 struct KapplyShape {
   bool f32;
   int kernel, dim;
   int64_t ncols, n;
   bool forest;
+  int64_t units;  // work units of a launch (row blocks, or forest items)
 };
 // Column-tile width of a kernel-apply launch: timed over the candidates on
-// the first launch of a shape, then cached.  launch(nt) enqueues one launch
-// on `stream` (hipStream_t); on return the output holds the product.
-int autotune_kapply(const KapplyShape &shape, const std::function<void(int)> &launch,
-                    void *stream);
+// the first launch of a shape (each on a prefix of the work units), then
+// cached.  launch(nt, units) enqueues one launch of the first `units` work
+// units (0: all) on `stream` (hipStream_t); on return the output holds the
+// full product.
+int autotune_kapply(const KapplyShape &shape,
+                    const std::function<void(int, int64_t)> &launch, void *stream);
 std::string autotune_report();
 
 }  // namespace hm

@@ -11,6 +11,7 @@
 // the matching point coordinates are staged through LDS, double-buffered.
 // The contraction over all N points is the whole cost: 2 N^2 ncols flops
 // against N*ncols*8 bytes of X per row block, far above the FP64 ridge.
+#include <algorithm>
 #include <type_traits>
 
 #include "device_common.h"
@@ -291,7 +292,9 @@ void launch_nt(int64_t n, const double *pts, int64_t ncols, const T *X, int64_t 
     kapply_kernel<T, NT, KER, DIM, true><<<(unsigned)(nitems * nct), 256, 0, s>>>(
         n, pts, ncols, X, ldx, Y, ldy, items, split);
   } else {
-    dim3 g((unsigned)((n + 63) / 64), (unsigned)nct);
+    // nitems > 0: only the first nitems row blocks (a partial launch)
+    const int64_t nb = (n + 63) / 64;
+    dim3 g((unsigned)(nitems > 0 && nitems < nb ? nitems : nb), (unsigned)nct);
     kapply_kernel<T, NT, KER, DIM, false><<<g, 256, 0, s>>>(n, pts, ncols, X, ldx, Y, ldy,
                                                              nullptr, -1);
   }
@@ -334,7 +337,7 @@ void launch_ker(int nt, int dim, int64_t n, const double *pts, int64_t ncols, co
 void launch_any(int kernel, int nt, int dim, int64_t n, const double *pts, int64_t ncols,
                 bool f32, const void *X, int64_t ldx, void *Y, int64_t ldy, int32_t nitems,
                 const KItem *items, int64_t split, hipStream_t s) {
-  if (nt <= 0) nt = kapply_default_nt(ncols, f32);
+  if (nt <= 0) nt = kapply_default_nt(ncols, f32, nitems > 0 ? nitems : (n + 63) / 64);
   if (f32) {
     if (kernel == 0)
       launch_ker<float, 0>(nt, dim, n, pts, ncols, (const float *)X, ldx, (float *)Y, ldy, nitems,
@@ -354,23 +357,36 @@ void launch_any(int kernel, int nt, int dim, int64_t n, const double *pts, int64
 
 }  // namespace
 
-// Columns in 16-wide fragments, at most 16 fragments per workgroup (8 in
-// FP32, whose compensated sums hold three accumulator sets: beyond 8 the
-// register file drops the occupancy to one wave per SIMD): the narrowest
-// instantiated tile that covers an even split of the fragments.
-int kapply_default_nt(int64_t ncols, bool f32) {
-  const int64_t cap = f32 ? 8 : 16;
+// Tile width without timing: columns come in 16-wide fragments; a tile of
+// nt fragments evaluates the kernel once for its nt fragments of MFMA work,
+// which costs about as much as two more fragments, so a launch costs about
+// tiles * (nt + 2); a grid of fewer than two workgroups per CU (512) leaves
+// CUs idle and is charged for it.  nt is capped where the accumulators
+// would drop the occupancy to one wave per SIMD (FP64: 12, FP32 with its
+// compensated sums: 10).
+int kapply_default_nt(int64_t ncols, bool f32, int64_t units) {
+  const int cap = f32 ? 10 : 12;
   const int64_t frags = (ncols + 15) / 16;
-  const int64_t tiles = (frags + cap - 1) / cap;
-  const int64_t need = (frags + tiles - 1) / tiles;
-  const int64_t nt = need < 2 ? 2 : (need + 1) / 2 * 2;
-  return (int)(nt > cap ? cap : nt);
+  int best = 2;
+  double best_cost = 1e300;
+  for (int nt = 2; nt <= cap; nt += 2) {
+    const int64_t tiles = (frags + nt - 1) / nt;
+    const double fill = std::min(1.0, (double)(std::max<int64_t>(units, 1) * tiles) / 512.0);
+    const double cost = (double)tiles * (nt + 2) / fill;
+    if (cost <= best_cost) {
+      best_cost = cost;
+      best = nt;
+    }
+  }
+  return best;
 }
 
 void launch_kapply(int kernel, int dim, int64_t n, const double *pts, int64_t ncols, int nt,
-                   bool f32, const void *X, int64_t ldx, void *Y, int64_t ldy, hipStream_t s) {
+                   bool f32, const void *X, int64_t ldx, void *Y, int64_t ldy, hipStream_t s,
+                   int64_t rows) {
   if (n <= 0 || ncols <= 0) return;
-  launch_any(kernel, nt, dim, n, pts, ncols, f32, X, ldx, Y, ldy, 0, nullptr, -1, s);
+  const int32_t nblk = rows > 0 ? (int32_t)((std::min(rows, n) + 63) / 64) : 0;
+  launch_any(kernel, nt, dim, n, pts, ncols, f32, X, ldx, Y, ldy, nblk, nullptr, -1, s);
 }
 
 void launch_kapply_forest(int kernel, int dim, int64_t n, const double *pts, int32_t nitems,

@@ -43,8 +43,10 @@ void launch_check_finite(int64_t n, int64_t ncols, bool f32, const void *Y, int6
 // tree order), 0 where p_i == p_j.  kernel: 0 = log, 1 = 1/r.
 // nt: column fragments (16 columns each) per workgroup, even, 2..16; 0 =
 // kapply_default_nt.  Every nt computes the same values bit for bit.
+// rows > 0: compute only Y rows [0, rows) (a partial launch for timing).
 void launch_kapply(int kernel, int dim, int64_t n, const double *pts, int64_t ncols, int nt,
-                   bool f32, const void *X, int64_t ldx, void *Y, int64_t ldy, hipStream_t s);
+                   bool f32, const void *X, int64_t ldx, void *Y, int64_t ldy, hipStream_t s,
+                   int64_t rows = 0);
 // Block-diagonal form for a forest: one work item per 64-row block of one
 // instance.  Rows [base, base + nloc) of Y are K_inst X(base : base+nloc, :)
 // where K_inst only couples points of the instance.  Columns outside
@@ -63,8 +65,9 @@ struct KItem {
 void launch_kapply_forest(int kernel, int dim, int64_t n, const double *pts, int32_t nitems,
                           const KItem *items, int64_t ncols, int64_t split, int nt, bool f32,
                           const void *X, int64_t ldx, void *Y, int64_t ldy, hipStream_t s);
-// Column fragments per workgroup the plain launch picks for ncols.
-int kapply_default_nt(int64_t ncols, bool f32);
+// Column fragments per workgroup chosen without timing, for ncols columns
+// over `units` row blocks (or forest items).
+int kapply_default_nt(int64_t ncols, bool f32, int64_t units);
 // Dense Y = op(A) X, FP64.
 void launch_dense_gemm(int64_t n, const double *A, int64_t lda, bool trans, int64_t ncols,
                        const double *X, int64_t ldx, double *Y, int64_t ldy, hipStream_t s);
