@@ -49,6 +49,8 @@ def parse():
                     help="comma-separated offered loads (fractions of the FP64 capacity)")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run this many steps, no extras (for profilers)")
+    ap.add_argument("--profile-workload", default="star", choices=["star", "batched"],
+                    help="with --profile-steps: which workload the steps run")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="with --profile-steps: add a 1 GiB device copy that calibrates "
                          "the FETCH_SIZE / WRITE_SIZE counters")
@@ -309,8 +311,13 @@ def main():
     y = hm.colmajor(n, 1)
 
     if args.profile_steps:
-        for _ in range(args.profile_steps):
-            step(hm, inst, inst.kernel, x, y, hm.HM_PREC_F64, inst.tol)
+        if args.profile_workload == "batched":
+            insts = workloads.batched_ellipses()
+            for _ in range(args.profile_steps):
+                batched_step(hm, insts, hm.HM_PREC_MIXED)
+        else:
+            for _ in range(args.profile_steps):
+                step(hm, inst, inst.kernel, x, y, hm.HM_PREC_F64, inst.tol)
         torch.cuda.synchronize()
         if args.pmc_probe:
             # calibration for the HBM byte counters: one plain device copy of
