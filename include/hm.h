@@ -217,7 +217,10 @@ void hm_dense_blackbox_free(hm_blackbox *bb);
  *
  * qr(., k) is column-pivoted Householder QR truncated to k columns; in
  * tolerance mode k = first j with |R_jj| <= tol |R_00|, capped at r - p
- * (each cap hit is counted as saturation in hm_stats).
+ * (each cap hit is counted as saturation in hm_stats; opts->max_retries and
+ * HM_FLAG_STRICT say what happens then).  In the mixed form the threshold
+ * has a floor at the FP32 rounding level of the raw sample block:
+ * max(tol |R_00|, 8 u32 ||block||_F / sqrt(r)).
  *
  * Test-matrix entries: Philox4x32-10 keyed by seed, counter (tree row,
  * column/2, color, 4*level + pass), two 53-bit uniforms, Box-Muller.  In a
@@ -237,9 +240,16 @@ typedef struct {
   int32_t r;          /* columns per test matrix (0: rank + oversample) */
   int32_t prec;       /* HM_PREC_F64, or HM_PREC_MIXED: black box and peel in FP32,
                          QR and coupling solves in FP64 */
-  int32_t flags;      /* bit 0: record stage times (adds device syncs) */
+  int32_t flags;      /* HM_FLAG_TIMING: record stage times (HIP events);
+                         HM_FLAG_STRICT: fail with HM_E_SATURATED when a block
+                         still reaches the cap r - p after the retries */
   uint64_t seed;
+  int32_t max_retries; /* tolerance mode: recompress with r + 8 (at most 64) while
+                          some block reaches the cap, at most this many times */
+  int32_t reserved;
 } hm_compress_opts;
+#define HM_FLAG_TIMING 1
+#define HM_FLAG_STRICT 2
 
 hm_status hm_compress(hm_tree *tree, const hm_blackbox *bb, const hm_compress_opts *opts,
                       void *stream, hm_hmatrix **out);
@@ -274,6 +284,8 @@ typedef struct {
   int64_t nnear;             /* leaf neighbor pairs */
   int64_t saturated;         /* rank caps hit */
   int64_t nfloats;           /* stored values (U, B, V at their ranks, near blocks) */
+  int32_t retries;           /* recompressions with a larger r (max_retries) */
+  int32_t pad_;
   double flops_blackbox;     /* 2 N^2 per black-box column */
   double flops_peel;         /* level-truncated products subtracted */
   double flops_qr;           /* pivoted QR + basis formation */

@@ -61,7 +61,7 @@ class BlackBox(C.Structure):
 class Opts(C.Structure):
     _fields_ = [("rank", C.c_int32), ("tol", C.c_double), ("oversample", C.c_int32),
                 ("r", C.c_int32), ("prec", C.c_int32), ("flags", C.c_int32),
-                ("seed", C.c_uint64)]
+                ("seed", C.c_uint64), ("max_retries", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -69,7 +69,8 @@ class Stats(C.Structure):
                 ("cols_A", C.c_int64), ("cols_At", C.c_int64), ("colors", C.c_int32 * 32),
                 ("leaf_colors", C.c_int32), ("leaf_width", C.c_int32), ("max_rank", C.c_int32),
                 ("npairs", C.c_int64), ("nnear", C.c_int64), ("saturated", C.c_int64),
-                ("nfloats", C.c_int64), ("flops_blackbox", C.c_double),
+                ("nfloats", C.c_int64), ("retries", C.c_int32), ("pad_", C.c_int32),
+                ("flops_blackbox", C.c_double),
                 ("flops_peel", C.c_double), ("flops_qr", C.c_double),
                 ("flops_solve", C.c_double), ("ms_total", C.c_double),
                 ("ms_blackbox", C.c_double), ("ms_peel", C.c_double), ("ms_qr", C.c_double),
@@ -539,9 +540,14 @@ class Server:
                     running=run.value, residents=res.value)
 
 
+HM_FLAG_TIMING, HM_FLAG_STRICT = 1, 2
+
+
 def compress(tree: Tree, bb: BlackBox, rank=0, tol=0.0, r=0, p=10, prec=HM_PREC_F64, seed=0,
-             timing=False, stream=None) -> HMatrix:
-    o = Opts(rank=rank, tol=tol, oversample=p, r=r, prec=prec, flags=1 if timing else 0, seed=seed)
+             timing=False, stream=None, max_retries=0, strict=False) -> HMatrix:
+    o = Opts(rank=rank, tol=tol, oversample=p, r=r, prec=prec,
+             flags=(HM_FLAG_TIMING if timing else 0) | (HM_FLAG_STRICT if strict else 0),
+             seed=seed, max_retries=max_retries, reserved=0)
     h = C.c_void_p()
     _check(_lib.hm_compress(tree.h, C.byref(bb), C.byref(o), _stream(stream), C.byref(h)))
     return HMatrix(h, tree)

@@ -1376,7 +1376,29 @@ hm_status hm_compress(hm_tree *tree, const hm_blackbox *bb, const hm_compress_op
                       void *stream, hm_hmatrix **out) {
   API_BEGIN
   if (!tree || !bb || !opts || !out) return fail(HM_E_ARG, "hm_compress: null argument");
-  return compress_impl(tree->t, *bb, *opts, (hipStream_t)stream, out);
+  if (opts->max_retries < 0) return fail(HM_E_ARG, "hm_compress: max_retries < 0");
+  // tolerance mode: a block whose rank reached r - p may be truncated above
+  // the tolerance; retry with 8 more columns per test matrix, then report
+  hm_compress_opts o = *opts;
+  for (int attempt = 0;; ++attempt) {
+    hm_hmatrix *H = nullptr;
+    const hm_status st = compress_impl(tree->t, *bb, o, (hipStream_t)stream, &H);
+    if (st != HM_OK) return st;
+    const bool sat = o.rank <= 0 && H->stats.saturated > 0;
+    const int r_used = H->stats.r;
+    if (!sat || attempt >= o.max_retries || r_used + 8 > 64) {
+      if (sat && (o.flags & HM_FLAG_STRICT)) {
+        delete H;
+        return fail(HM_E_SATURATED, "tolerance not reached within r - p columns");
+      }
+      H->stats.retries = attempt;
+      *out = H;
+      return HM_OK;
+    }
+    delete H;
+    o.r = r_used + 8;
+  }
+  API_END
   API_END
 }
 

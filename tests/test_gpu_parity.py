@@ -293,3 +293,28 @@ def test_full_size_sphere_sampled_rows(hm):
     err = np.linalg.norm(got[rows] - want) / np.linalg.norm(want)
     print("sampled-row error", err)
     assert err <= 10 * inst.tol
+
+
+def test_saturation_retry_and_strict(hm):
+    """Tolerance mode with too few columns: blocks reach the cap r - p.
+    max_retries recompresses with r + 8 until no block does; HM_FLAG_STRICT
+    turns a remaining saturation into HM_E_SATURATED."""
+    inst = workloads.config(2, n=3000)
+    T = hm.Tree(inst.points, inst.leaf, inst.tree, inst.adm).color()
+    bb = T.kernel_blackbox(inst.kernel)
+    H0 = hm.compress(T, bb, tol=inst.tol, r=16, seed=inst.seed)
+    assert H0.stats()["saturated"] > 0 and H0.stats()["retries"] == 0
+    H = hm.compress(T, bb, tol=inst.tol, r=16, seed=inst.seed, max_retries=4)
+    st = H.stats()
+    print("retries", st["retries"], "r", st["r"], "max rank", st["max_rank"])
+    assert st["saturated"] == 0 and st["retries"] >= 1 and st["r"] == 16 + 8 * st["retries"]
+    # the retried result is the compression at the final r
+    H2 = hm.compress(T, bb, tol=inst.tol, r=st["r"], seed=inst.seed)
+    X = np.random.default_rng(3).standard_normal((T.n, 2))
+    a, b = hm.colmajor(T.n, 2), hm.colmajor(T.n, 2)
+    H.matvec(to_dev(X), a)
+    H2.matvec(to_dev(X), b)
+    assert np.array_equal(to_host(a), to_host(b))
+    with pytest.raises(hm.HMError) as e:
+        hm.compress(T, bb, tol=inst.tol, r=16, seed=inst.seed, strict=True)
+    assert e.value.code == hm.HM_E_SATURATED
