@@ -1399,7 +1399,6 @@ hm_status hm_compress(hm_tree *tree, const hm_blackbox *bb, const hm_compress_op
     o.r = r_used + 8;
   }
   API_END
-  API_END
 }
 
 void hm_hmatrix_free(hm_hmatrix *H) { delete H; }
