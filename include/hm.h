@@ -255,6 +255,26 @@ hm_status hm_compress(hm_tree *tree, const hm_blackbox *bb, const hm_compress_op
                       void *stream, hm_hmatrix **out);
 void hm_hmatrix_free(hm_hmatrix *H);
 
+/* Plans: compress the same tree with the same black box and options many
+ * times (for instance a black box whose device data change between calls),
+ * with the whole device pipeline captured once into a HIP graph.
+ * hm_compress_plan runs one compression eagerly on `stream` (which also
+ * settles the kernel-apply autotuner), then captures the same launches on a
+ * stream of its own and instantiates the graph.  hm_plan_execute replays it
+ * on `stream` (the black box is applied again, the test matrices are the
+ * same draws) and reads the ranks back; the result replaces the plan's
+ * H-matrix, which hm_plan_hmatrix borrows (valid until the next execution or
+ * hm_plan_free).  The black box must only enqueue device work on the stream
+ * it is given (the built-in kernel and dense black boxes do); retries
+ * (max_retries) do not apply.  graph_nodes (or NULL) receives the node
+ * count of the captured graph. */
+typedef struct hm_plan hm_plan;
+hm_status hm_compress_plan(hm_tree *tree, const hm_blackbox *bb, const hm_compress_opts *opts,
+                           void *stream, hm_plan **out);
+hm_status hm_plan_execute(hm_plan *plan, void *stream);
+hm_status hm_plan_hmatrix(const hm_plan *plan, const hm_hmatrix **H, int64_t *graph_nodes);
+void hm_plan_free(hm_plan *plan);
+
 /* hm_matvec: Y = H X (the H^1 apply: all admissible blocks U B V* plus the
  * leaf neighbor blocks).  X, Y device, n x nrhs, dtype HM_F64 or HM_F32,
  * rows in `order`.  Enqueued on stream. */

@@ -39,7 +39,8 @@ EXPORTED = [
     "hm_hmatrix_export_level", "hm_hmatrix_export_near", "hm_build_forest",
     "hm_tree_instances", "hm_autotune_table", "hm_server_create", "hm_server_free",
     "hm_server_submit_compress", "hm_server_submit_matvec", "hm_server_poll", "hm_server_hmatrix",
-    "hm_server_release", "hm_server_info",
+    "hm_server_release", "hm_server_info", "hm_compress_plan", "hm_plan_execute",
+    "hm_plan_hmatrix", "hm_plan_free",
 ]
 
 
@@ -140,6 +141,10 @@ def _load():
         "hm_hmatrix_stats": [P, C.POINTER(Stats)],
         "hm_hmatrix_export_level": [P, I, P, P, P, P, P, P, P, P, P, P, P],
         "hm_hmatrix_export_near": [P, P, P, P, P, P],
+        "hm_compress_plan": [P, C.POINTER(BlackBox), C.POINTER(Opts), P, pp],
+        "hm_plan_execute": [P, P],
+        "hm_plan_hmatrix": [P, pp, P],
+        "hm_plan_free": [P],
         "hm_server_create": [C.POINTER(ServerOpts), pp],
         "hm_server_free": [P],
         "hm_server_submit_compress": [P, P, I64, I, I, I, I, I, C.POINTER(Opts), P],
@@ -152,7 +157,8 @@ def _load():
     for name, args in sigs.items():
         f = getattr(lib, name)
         f.argtypes = args
-        if name in ("hm_tree_free", "hm_hmatrix_free", "hm_dense_blackbox_free", "hm_server_free"):
+        if name in ("hm_tree_free", "hm_hmatrix_free", "hm_dense_blackbox_free", "hm_server_free",
+                    "hm_plan_free"):
             f.restype = None
         else:
             f.restype = C.c_int
@@ -344,6 +350,41 @@ class Tree:
     def test_matrix(self, level, pas, r, seed, out, stream=None):
         po, ld, nc, dt = _colmajor(out, "out")
         _check(_lib.hm_test_matrix(self.h, level, pas, r, seed, dt, po, ld, _stream(stream)))
+
+
+class Plan:
+    """hm_compress_plan: a compression captured into a HIP graph and replayed
+    by execute(); hmatrix() borrows the latest result."""
+
+    def __init__(self, tree, bb, rank=0, tol=0.0, r=0, p=10, prec=HM_PREC_F64, seed=0,
+                 stream=None):
+        o = Opts(rank=rank, tol=tol, oversample=p, r=r, prec=prec, flags=0, seed=seed,
+                 max_retries=0, reserved=0)
+        h = C.c_void_p()
+        _check(_lib.hm_compress_plan(tree.h, C.byref(bb), C.byref(o), _stream(stream),
+                                     C.byref(h)))
+        self.h = h
+        self.tree = tree
+        self._bb = bb
+
+    def execute(self, stream=None):
+        _check(_lib.hm_plan_execute(self.h, _stream(stream)))
+
+    def hmatrix(self):
+        hh = C.c_void_p()
+        _check(_lib.hm_plan_hmatrix(self.h, C.byref(hh), None))
+        return _Borrowed(hh, self.tree)
+
+    @property
+    def graph_nodes(self):
+        k = C.c_int64()
+        _check(_lib.hm_plan_hmatrix(self.h, None, C.byref(k)))
+        return k.value
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.hm_plan_free(self.h)
+            self.h = None
 
 
 def autotune_table():

@@ -497,49 +497,105 @@ double qr_flops(int64_t m, int64_t r, int64_t k) {
   return f;
 }
 
-hm_status compress_impl(Tree &T, const hm_blackbox &bb, const hm_compress_opts &o,
-                        hipStream_t s, hm_hmatrix **out) {
+// One compression.  setup() plans every launch and allocates every buffer;
+// record() enqueues the whole device pipeline on a stream with no host round
+// trip and no allocation, so once the autotuner has seen its shapes it can
+// be captured into a HIP graph and replayed; finalize() reads the ranks
+// back and fills the statistics.
+struct Compression {
+  Tree &T;
+  hm_blackbox bb;
+  hm_compress_opts o;
+  bool persistent = false;  // buffers outlive the call (a plan): plain allocations
+  int p = 10, kfix = 0, r = 0;
+  int32_t kmax = 0;
+  bool mixed = false;
+  size_t es = 8;
+  int64_t n = 0;
+  DeviceTree *D = nullptr;
+  std::unique_ptr<hm_hmatrix> H;
+  std::vector<int> levels;
+  int64_t np_total = 0, szU = 0, szV = 0, szB = 0, szD = 0;
+  int32_t mw = 0;
+  int64_t cmax = 0, leaf_cols = 0, wcols = 0, tcap = 0, cmax_np = 0;
+  DBuf Xb, Yb, tmpx, tmpy, Tb, work, core, scratch, sat, flag, floor_u, floor_v;
+  struct LevelJobs {
+    DBuf act, ju, jv, jc, kit;
+    int32_t nkit = 0;
+  };
+  std::vector<LevelJobs> jobs_of;
+  int ni = 1;
+  KernelBB *kbb = nullptr;
+  bool direct = false;
+  DBuf dib, dic, dkit, dr0, dc0, dma, dmb, doff;  // leaf pass lists
+  int32_t nib = 0, nkit_leaf = 0;
+  int64_t cols_A = 0, cols_At = 0;
+
+  Compression(Tree &t, const hm_blackbox &b, const hm_compress_opts &opt)
+      : T(t), bb(b), o(opt) {}
+
+  void buf(DBuf &d, size_t bytes, hipStream_t s) {
+    if (persistent)
+      d.alloc(bytes);
+    else
+      d.temp(bytes, s);
+  }
+  template <class V>
+  void put(DBuf &d, const std::vector<V> &v, hipStream_t s) {
+    if (persistent)
+      upload(d, v, s);
+    else
+      upload_temp(d, v, s);
+  }
+  // live colors of each instance in graph g
+  std::vector<int32_t> inst_colors(int g) const {
+    std::vector<int32_t> w(ni, 0);
+    const Graph &Gg = T.graphs[g];
+    for (int i = 0; i < ni; ++i)
+      for (int64_t v = T.gvoff[g][i]; v < T.gvoff[g][i + 1]; ++v)
+        w[i] = std::max(w[i], Gg.color[v] + 1);
+    return w;
+  }
+  hm_status setup(hipStream_t s);
+  void record(hipStream_t s, Events &ev);
+  hm_status finalize(hipStream_t s, Events &ev,
+                     std::chrono::steady_clock::time_point t_host0);
+};
+
+hm_status Compression::setup(hipStream_t s) {
   // ---------------- options
   if (T.n <= 0) return fail(HM_E_ARG, "empty tree");
   for (const Graph &G : T.graphs)
     if (!G.colored && G.nv() > 0) return fail(HM_E_STATE, "tree is not colored (hm_tree_color)");
-  const int p = o.oversample > 0 ? o.oversample : 10;
-  const int kfix = o.rank > 0 ? o.rank : 0;
+  p = o.oversample > 0 ? o.oversample : 10;
+  kfix = o.rank > 0 ? o.rank : 0;
   if (kfix == 0 && !(o.tol > 0)) return fail(HM_E_ARG, "need rank > 0 or tol > 0");
-  const int r = o.r > 0 ? o.r : (kfix > 0 ? kfix + p : 0);
+  r = o.r > 0 ? o.r : (kfix > 0 ? kfix + p : 0);
   if (r <= 0) return fail(HM_E_ARG, "tolerance mode needs r > 0");
   if (r > 64) return fail(HM_E_ARG, "r must be <= 64");
   if (kfix == 0 && r - p < 1) return fail(HM_E_ARG, "r - p must be >= 1 in tolerance mode");
-  const bool mixed = o.prec == HM_PREC_MIXED;
+  mixed = o.prec == HM_PREC_MIXED;
   if (mixed && !(bb.dtypes & (1 << HM_F32))) return fail(HM_E_ARG, "black box has no FP32 apply");
   if (!mixed && !(bb.dtypes & (1 << HM_F64))) return fail(HM_E_ARG, "black box has no FP64 apply");
   if (!bb.apply) return fail(HM_E_ARG, "black box without apply");
-  const int32_t kmax = kfix > 0 ? std::min(kfix, r) : r - p;
-  const size_t es = mixed ? 4 : 8;
-  const int64_t n = T.n;
+  kmax = kfix > 0 ? std::min(kfix, r) : r - p;
+  es = mixed ? 4 : 8;
+  n = T.n;
 
-  DeviceTree &D = device_tree(T, s);
-  auto H = std::make_unique<hm_hmatrix>();
+  D = &device_tree(T, s);
+  H = std::make_unique<hm_hmatrix>();
   HIP_TRY(hipGetDevice(&H->device));
   H->n = n;
   H->nlev = T.nlev();
   H->r = r;
   H->kmax = kmax;
   for (const Level &Lv : T.lev) H->start.push_back(Lv.start);
-  {
-    H->perm.alloc(n * sizeof(int64_t));
-    HIP_TRY(hipMemcpyAsync(H->perm.p, D.perm.p, n * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
-  }
-  Events ev;
-  ev.on = (o.flags & 1) != 0;
-  ev.s = s;
-  auto t_host0 = std::chrono::steady_clock::now();
+  H->perm.alloc(n * sizeof(int64_t));
+  HIP_TRY(hipMemcpyAsync(H->perm.p, D->perm.p, n * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
 
   // ---------------- layout of the factor pools
-  std::vector<int> levels;
   for (int l = 1; l < T.nlev(); ++l)
     if (!T.graphs[l].pa.empty()) levels.push_back(l);
-  int64_t np_total = 0, szU = 0, szV = 0, szB = 0;
   for (int l : levels) {
     const Graph &G = T.graphs[l];
     const Level &Lv = T.lev[l];
@@ -572,17 +628,11 @@ hm_status compress_impl(Tree &T, const hm_blackbox &bb, const hm_compress_opts &
   H->Wf.alloc(szU * 4);
   H->Vf.alloc(szV * 4);
   H->ranks.alloc(2 * np_total * sizeof(int32_t));
-  launch_fill(H->W.p, szU, false, 0.0, s);
-  launch_fill(H->V.p, szV, false, 0.0, s);
-  launch_fill(H->ranks.p, np_total, true, 0.0, s);  // int32 zeros share the float bit pattern
-  launch_fill((char *)H->ranks.p + np_total * 4, np_total, true, 0.0, s);
-  LAUNCH_CHECK();
   build_apply_plans(*H, T, s);
 
   // leaf neighbor blocks
   const Graph &GL = T.leaf_graph();
   const Level &LL = T.lev[T.L()];
-  int64_t szD = 0;
   {
     std::vector<ExpandChunk> ch;
     std::vector<NearEntry> en;
@@ -616,17 +666,15 @@ hm_status compress_impl(Tree &T, const hm_blackbox &bb, const hm_compress_opts &
   }
 
   // ---------------- working buffers
-  int64_t cmax = 0;
   for (int l : levels) cmax = std::max<int64_t>(cmax, pad16((int64_t)T.graphs[l].ncolors * r));
-  const int32_t mw = T.leaf_width();
-  const int64_t leaf_cols = pad16((int64_t)GL.ncolors * mw);
-  const int64_t wcols = std::max<int64_t>(2 * cmax, leaf_cols);
-  DBuf Xb, Yb, tmpx, tmpy, Tb, work, core, scratch, jobs, sat, flag;
-  Xb.temp((size_t)n * wcols * es, s);
-  Yb.temp((size_t)n * wcols * es, s);
-  const int64_t tcap = tscratch_elems(*H, wcols);
-  Tb.temp((size_t)tcap * es, s);
-  int64_t wmax = 0, cmax_np = 0;
+  mw = T.leaf_width();
+  leaf_cols = pad16((int64_t)GL.ncolors * mw);
+  wcols = std::max<int64_t>(2 * cmax, leaf_cols);
+  buf(Xb, (size_t)n * wcols * es, s);
+  buf(Yb, (size_t)n * wcols * es, s);
+  tcap = tscratch_elems(*H, wcols);
+  buf(Tb, (size_t)tcap * es, s);
+  int64_t wmax = 0;
   for (size_t li = 0; li < H->lv.size(); ++li) {
     const hm_hmatrix::Lv &L = H->lv[li];
     const Level &Lv = T.lev[L.level];
@@ -636,43 +684,33 @@ hm_status compress_impl(Tree &T, const hm_blackbox &bb, const hm_compress_opts &
     wmax = std::max(wmax, rows * r);
     cmax_np = std::max(cmax_np, L.np);
   }
-  work.temp((size_t)std::max<int64_t>(wmax, 1) * 8, s);
-  core.temp((size_t)std::max<int64_t>(cmax_np, 1) * r * r * 8, s);
-  scratch.temp((size_t)std::max<int64_t>(cmax_np, 1) * r * r * 8, s);
-  sat.temp((size_t)std::max<int64_t>(2 * np_total, 1) * 4, s);
-  launch_fill(sat.p, std::max<int64_t>(2 * np_total, 1), true, 0.0, s);
-  flag.temp(64, s);
-  launch_fill(flag.p, 1, true, 0.0, s);
-  // mixed path: per-block noise floors of the FP32 samples (see below)
-  DBuf floor_u, floor_v;
+  buf(work, (size_t)std::max<int64_t>(wmax, 1) * 8, s);
+  buf(core, (size_t)std::max<int64_t>(cmax_np, 1) * r * r * 8, s);
+  buf(scratch, (size_t)std::max<int64_t>(cmax_np, 1) * r * r * 8, s);
+  buf(sat, (size_t)std::max<int64_t>(2 * np_total, 1) * 4, s);
+  buf(flag, 64, s);
+  // mixed path: per-block noise floors of the FP32 samples (see record)
   if (mixed) {
-    floor_u.temp((size_t)std::max<int64_t>(cmax_np, 1) * 8, s);
-    floor_v.temp((size_t)std::max<int64_t>(cmax_np, 1) * 8, s);
+    buf(floor_u, (size_t)std::max<int64_t>(cmax_np, 1) * 8, s);
+    buf(floor_v, (size_t)std::max<int64_t>(cmax_np, 1) * 8, s);
   }
-  LAUNCH_CHECK();
+  // a black box in the original point order works through two permuted
+  // copies of the samples
+  if (bb.order != HM_ORDER_TREE) {
+    buf(tmpx, (size_t)n * wcols * es, s);
+    buf(tmpy, (size_t)n * wcols * es, s);
+  }
 
-  // ---------------- forest: live columns of each instance per level
-  const int ni = T.ninst();
-  auto inst_colors = [&](int g) {
-    std::vector<int32_t> w(ni, 0);
-    const Graph &Gg = T.graphs[g];
-    for (int i = 0; i < ni; ++i)
-      for (int64_t v = T.gvoff[g][i]; v < T.gvoff[g][i + 1]; ++v)
-        w[i] = std::max(w[i], Gg.color[v] + 1);
-    return w;
-  };
-  // the library's own kernel black box on this forest is called directly
-  // with the per-instance live widths: colors an instance does not use are
-  // zero columns in its rows, and their tiles are skipped
-  KernelBB *kbb = bb.apply == kernel_bb_apply ? (KernelBB *)bb.ctx : nullptr;
-  const bool direct = kbb && kbb->tree == &T && ni > 1;
+  // ---------------- forest: the library's own kernel black box on this
+  // forest is called directly with the per-instance live widths: colors an
+  // instance does not use are zero columns in its rows, and their tiles are
+  // skipped
+  ni = T.ninst();
+  kbb = bb.apply == kernel_bb_apply ? (KernelBB *)bb.ctx : nullptr;
+  direct = kbb && kbb->tree == &T && ni > 1;
 
   // ---------------- every job list of every level, uploaded once up front
-  struct LevelJobs {
-    DBuf act, ju, jv, jc, kit;
-    int32_t nkit = 0;
-  };
-  std::vector<LevelJobs> jobs_of(H->lv.size());
+  jobs_of.resize(H->lv.size());
   for (size_t li = 0; li < H->lv.size(); ++li) {
     hm_hmatrix::Lv &L = H->lv[li];
     const Graph &G = T.graphs[L.level];
@@ -704,17 +742,64 @@ hm_status compress_impl(Tree &T, const hm_blackbox &bb, const hm_compress_opts &
       std::vector<int32_t> w = inst_colors(L.level);
       for (int32_t &x : w) x *= r;
       std::vector<KItem> kit = forest_items(T, w);
-      upload_temp(jobs_of[li].kit, kit, s);
+      put(jobs_of[li].kit, kit, s);
       jobs_of[li].nkit = (int32_t)kit.size();
     }
-    upload_temp(jobs_of[li].act, act, s);
-    upload_temp(jobs_of[li].ju, ju, s);
-    upload_temp(jobs_of[li].jv, jv, s);
-    upload_temp(jobs_of[li].jc, jc, s);
+    put(jobs_of[li].act, act, s);
+    put(jobs_of[li].ju, ju, s);
+    put(jobs_of[li].jv, jv, s);
+    put(jobs_of[li].jc, jc, s);
     HIP_TRY(hipStreamSynchronize(s));  // the host vectors die here
   }
 
-  int64_t cols_A = 0, cols_At = 0;
+  // ---------------- leaf pass lists
+  {
+    std::vector<int32_t> ib, ic;
+    for (int64_t v = 0; v < GL.nv(); ++v) {
+      ib.push_back(GL.vbox[v]);
+      ic.push_back(GL.color[v]);
+    }
+    // one item per (box, color) is enough; duplicates write the same ones
+    put(dib, ib, s);
+    put(dic, ic, s);
+    nib = (int32_t)ib.size();
+    std::vector<KItem> kit;
+    if (direct) {
+      std::vector<int32_t> w = inst_colors(T.nlev());
+      for (int32_t &x : w) x *= mw;
+      kit = forest_items(T, w);
+      put(dkit, kit, s);
+    }
+    nkit_leaf = (int32_t)kit.size();
+    std::vector<int64_t> r0(GL.pa.size()), c0(GL.pa.size());
+    std::vector<int32_t> ma(GL.pa.size()), mb(GL.pa.size());
+    for (size_t q = 0; q < GL.pa.size(); ++q) {
+      r0[q] = LL.start[GL.pa[q]];
+      ma[q] = (int32_t)T.box_size(T.L(), GL.pa[q]);
+      mb[q] = (int32_t)T.box_size(T.L(), GL.pb[q]);
+      c0[q] = (int64_t)GL.color[GL.pv[q]] * mw;
+    }
+    put(dr0, r0, s);
+    put(dc0, c0, s);
+    put(dma, ma, s);
+    put(dmb, mb, s);
+    put(doff, H->offD, s);
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  return HM_OK;
+}
+
+void Compression::record(hipStream_t s, Events &ev) {
+  const DeviceTree &Dv = *D;
+  const Graph &GL = T.leaf_graph();
+  // state every run starts from (fill kernels, no memset: capturable)
+  launch_fill(H->W.p, szU, false, 0.0, s);
+  launch_fill(H->V.p, szV, false, 0.0, s);
+  launch_fill(H->ranks.p, 2 * np_total, true, 0.0, s);  // int32 zeros share the float bit pattern
+  launch_fill(sat.p, std::max<int64_t>(2 * np_total, 1), true, 0.0, s);
+  launch_fill(flag.p, 1, true, 0.0, s);
+  LAUNCH_CHECK();
+  cols_A = cols_At = 0;
   // ---------------- the level loop (no host round trips)
   for (size_t li = 0; li < H->lv.size(); ++li) {
     hm_hmatrix::Lv &L = H->lv[li];
@@ -728,16 +813,16 @@ hm_status compress_impl(Tree &T, const hm_blackbox &bb, const hm_compress_opts &
     void *Zl = (char *)Yb.p + (size_t)cpad * n * es;
     DBuf &dact = jobs_of[li].act;
     ev.mark(0);
-    launch_testmat(n, D.rowbox[l].as<int32_t>(), dact.as<uint8_t>(), G.ncolors, r, l, 0, o.seed,
-                   D.inst_off.as<int64_t>(), ni, mixed, Om, n, cpad, s);
-    launch_testmat(n, D.rowbox[l].as<int32_t>(), dact.as<uint8_t>(), G.ncolors, r, l, 1, o.seed,
-                   D.inst_off.as<int64_t>(), ni, mixed, Ps, n, cpad, s);
+    launch_testmat(n, Dv.rowbox[l].as<int32_t>(), dact.as<uint8_t>(), G.ncolors, r, l, 0, o.seed,
+                   Dv.inst_off.as<int64_t>(), ni, mixed, Om, n, cpad, s);
+    launch_testmat(n, Dv.rowbox[l].as<int32_t>(), dact.as<uint8_t>(), G.ncolors, r, l, 1, o.seed,
+                   Dv.inst_off.as<int64_t>(), ni, mixed, Ps, n, cpad, s);
     LAUNCH_CHECK();
     ev.mark(1);
     if (direct) {
       autotune_kapply(KapplyShape{mixed, kbb->kernel, T.dim, 2 * cpad, n, true, jobs_of[li].nkit},
                       [&](int nt, int64_t part) {
-                        launch_kapply_forest(kbb->kernel, T.dim, n, D.pts.as<double>(),
+                        launch_kapply_forest(kbb->kernel, T.dim, n, Dv.pts.as<double>(),
                                              part > 0 ? (int32_t)part : jobs_of[li].nkit,
                                              jobs_of[li].kit.as<KItem>(), 2 * cpad, cpad, nt,
                                              mixed, Om, n, Yl, n, s);
@@ -745,10 +830,10 @@ hm_status compress_impl(Tree &T, const hm_blackbox &bb, const hm_compress_opts &
                       s);
       LAUNCH_CHECK();
     } else if (bb.symmetric) {
-      call_blackbox(bb, 0, n, 2 * cpad, mixed, Om, n, Yl, n, D, tmpx, tmpy, s);
+      call_blackbox(bb, 0, n, 2 * cpad, mixed, Om, n, Yl, n, Dv, tmpx, tmpy, s);
     } else {
-      call_blackbox(bb, 0, n, cpad, mixed, Om, n, Yl, n, D, tmpx, tmpy, s);
-      call_blackbox(bb, 1, n, cpad, mixed, Ps, n, Zl, n, D, tmpx, tmpy, s);
+      call_blackbox(bb, 0, n, cpad, mixed, Om, n, Yl, n, Dv, tmpx, tmpy, s);
+      call_blackbox(bb, 1, n, cpad, mixed, Ps, n, Zl, n, Dv, tmpx, tmpy, s);
     }
     cols_A += c;
     cols_At += c;
@@ -809,70 +894,42 @@ hm_status compress_impl(Tree &T, const hm_blackbox &bb, const hm_compress_opts &
   }
 
   // ---------------- leaf pass
-  {
-    std::vector<int32_t> ib, ic;
-    for (int64_t v = 0; v < GL.nv(); ++v) {
-      ib.push_back(GL.vbox[v]);
-      ic.push_back(GL.color[v]);
-    }
-    // one item per (box, color) is enough; duplicates write the same ones
-    DBuf dib, dic, dkit;
-    upload_temp(dib, ib, s);
-    upload_temp(dic, ic, s);
-    std::vector<KItem> kit;
-    if (direct) {
-      std::vector<int32_t> w = inst_colors(T.nlev());
-      for (int32_t &x : w) x *= mw;
-      kit = forest_items(T, w);
-      upload_temp(dkit, kit, s);
-    }
-    ev.mark(0);
-    launch_leaf_identity(n, (int32_t)ib.size(), dib.as<int32_t>(), dic.as<int32_t>(),
-                         D.start[T.L()].as<int64_t>(), mw, mixed, Xb.p, n, leaf_cols, s);
+  ev.mark(0);
+  launch_leaf_identity(n, nib, dib.as<int32_t>(), dic.as<int32_t>(),
+                       Dv.start[T.L()].as<int64_t>(), mw, mixed, Xb.p, n, leaf_cols, s);
+  LAUNCH_CHECK();
+  ev.mark(1);
+  if (direct) {
+    autotune_kapply(KapplyShape{mixed, kbb->kernel, T.dim, leaf_cols, n, true,
+                                (int64_t)nkit_leaf},
+                    [&](int nt, int64_t part) {
+                      launch_kapply_forest(kbb->kernel, T.dim, n, Dv.pts.as<double>(),
+                                           part > 0 ? (int32_t)part : nkit_leaf,
+                                           dkit.as<KItem>(), leaf_cols, -1, nt, mixed, Xb.p, n,
+                                           Yb.p, n, s);
+                    },
+                    s);
     LAUNCH_CHECK();
-    ev.mark(1);
-    if (direct) {
-      autotune_kapply(KapplyShape{mixed, kbb->kernel, T.dim, leaf_cols, n, true,
-                                  (int64_t)kit.size()},
-                      [&](int nt, int64_t part) {
-                        launch_kapply_forest(kbb->kernel, T.dim, n, D.pts.as<double>(),
-                                             part > 0 ? (int32_t)part : (int32_t)kit.size(),
-                                             dkit.as<KItem>(), leaf_cols, -1, nt, mixed, Xb.p, n,
-                                             Yb.p, n, s);
-                      },
-                      s);
-      LAUNCH_CHECK();
-    } else {
-      call_blackbox(bb, 0, n, leaf_cols, mixed, Xb.p, n, Yb.p, n, D, tmpx, tmpy, s);
-    }
-    cols_A += (int64_t)GL.ncolors * mw;
-    ev.mark(2);
-    apply_levels(*H, H->lv.size(), false, mixed, Xb.p, n, leaf_cols, Yb.p, n, -1.0, Tb.p, tcap, s);
-    launch_check_finite(n, leaf_cols, mixed, Yb.p, n, flag.as<int32_t>(), s);
-    LAUNCH_CHECK();
-    ev.mark(3);
-    std::vector<int64_t> r0(GL.pa.size()), c0(GL.pa.size());
-    std::vector<int32_t> ma(GL.pa.size()), mb(GL.pa.size());
-    for (size_t q = 0; q < GL.pa.size(); ++q) {
-      r0[q] = LL.start[GL.pa[q]];
-      ma[q] = (int32_t)T.box_size(T.L(), GL.pa[q]);
-      mb[q] = (int32_t)T.box_size(T.L(), GL.pb[q]);
-      c0[q] = (int64_t)GL.color[GL.pv[q]] * mw;
-    }
-    DBuf dr0, dc0, dma, dmb, doff;
-    upload_temp(dr0, r0, s);
-    upload_temp(dc0, c0, s);
-    upload_temp(dma, ma, s);
-    upload_temp(dmb, mb, s);
-    upload_temp(doff, H->offD, s);
-    launch_extract_near((int32_t)GL.pa.size(), dr0.as<int64_t>(), dma.as<int32_t>(),
-                        dc0.as<int64_t>(), dmb.as<int32_t>(), doff.as<int64_t>(), mixed, Yb.p, n,
-                        H->D.as<double>(), s);
-    LAUNCH_CHECK();
-    ev.mark(5);
-    HIP_TRY(hipStreamSynchronize(s));
+  } else {
+    call_blackbox(bb, 0, n, leaf_cols, mixed, Xb.p, n, Yb.p, n, Dv, tmpx, tmpy, s);
   }
+  cols_A += (int64_t)GL.ncolors * mw;
+  ev.mark(2);
+  apply_levels(*H, H->lv.size(), false, mixed, Xb.p, n, leaf_cols, Yb.p, n, -1.0, Tb.p, tcap, s);
+  launch_check_finite(n, leaf_cols, mixed, Yb.p, n, flag.as<int32_t>(), s);
+  LAUNCH_CHECK();
+  ev.mark(3);
+  launch_extract_near((int32_t)GL.pa.size(), dr0.as<int64_t>(), dma.as<int32_t>(),
+                      dc0.as<int64_t>(), dmb.as<int32_t>(), doff.as<int64_t>(), mixed, Yb.p, n,
+                      H->D.as<double>(), s);
+  LAUNCH_CHECK();
+  ev.mark(5);
+}
 
+hm_status Compression::finalize(hipStream_t s, Events &ev,
+                                std::chrono::steady_clock::time_point t_host0) {
+  const Graph &GL = T.leaf_graph();
+  const Level &LL = T.lev[T.L()];
   // ---------------- results back on the host
   H->h_ranks.resize(2 * np_total);
   std::vector<int32_t> hsat(2 * np_total);
@@ -973,7 +1030,22 @@ hm_status compress_impl(Tree &T, const hm_blackbox &bb, const hm_compress_opts &
     st.ms_other = acc[0] + acc[5];
   }
   st.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_host0).count();
-  *out = H.release();
+  return HM_OK;
+}
+
+hm_status compress_impl(Tree &T, const hm_blackbox &bb, const hm_compress_opts &o,
+                        hipStream_t s, hm_hmatrix **out) {
+  auto t_host0 = std::chrono::steady_clock::now();
+  Compression C(T, bb, o);
+  hm_status st = C.setup(s);
+  if (st != HM_OK) return st;
+  Events ev;
+  ev.on = (o.flags & HM_FLAG_TIMING) != 0;
+  ev.s = s;
+  C.record(s, ev);
+  st = C.finalize(s, ev, t_host0);
+  if (st != HM_OK) return st;
+  *out = C.H.release();
   return HM_OK;
 }
 
@@ -1043,6 +1115,23 @@ int64_t matvec_footprint(const hm_hmatrix *H, int64_t nrhs, int dtype) {
 }
 
 }  // namespace hm
+
+// ------------------------------------------------------------------ plans
+// A compression whose device pipeline is captured once into a HIP graph and
+// replayed: every execution draws the same test matrices, applies the black
+// box again and recovers a new H-matrix into the same buffers.
+struct hm_plan {
+  std::unique_ptr<hm::Compression> C;
+  hipStream_t cs = nullptr;  // capture stream (the null stream cannot be captured)
+  hipGraph_t g = nullptr;
+  hipGraphExec_t ge = nullptr;
+  int64_t nodes = 0;
+  ~hm_plan() {
+    if (ge) (void)hipGraphExecDestroy(ge);
+    if (g) (void)hipGraphDestroy(g);
+    if (cs) (void)hipStreamDestroy(cs);
+  }
+};
 
 // ================================================================== C ABI
 using namespace hm;
@@ -1402,6 +1491,71 @@ hm_status hm_compress(hm_tree *tree, const hm_blackbox *bb, const hm_compress_op
 }
 
 void hm_hmatrix_free(hm_hmatrix *H) { delete H; }
+
+hm_status hm_compress_plan(hm_tree *tree, const hm_blackbox *bb, const hm_compress_opts *opts,
+                           void *stream, hm_plan **out) {
+  API_BEGIN
+  if (!tree || !bb || !opts || !out) return fail(HM_E_ARG, "hm_compress_plan: null argument");
+  hipStream_t s = (hipStream_t)stream;
+  auto P = std::make_unique<hm_plan>();
+  P->C = std::make_unique<Compression>(tree->t, *bb, *opts);
+  P->C->persistent = true;
+  P->C->o.flags &= ~HM_FLAG_TIMING;
+  hm_status st = P->C->setup(s);
+  if (st != HM_OK) return st;
+  // one eager run validates the pipeline and settles the autotuner, so the
+  // captured launches are exactly the ones an eager compression makes
+  Events ev;
+  ev.s = s;
+  P->C->record(s, ev);
+  st = P->C->finalize(s, ev, std::chrono::steady_clock::now());
+  if (st != HM_OK) return st;
+  HIP_TRY(hipStreamCreateWithFlags(&P->cs, hipStreamNonBlocking));
+  HIP_TRY(hipStreamBeginCapture(P->cs, hipStreamCaptureModeThreadLocal));
+  try {
+    ev.s = P->cs;
+    P->C->record(P->cs, ev);
+  } catch (...) {
+    hipGraph_t bad = nullptr;
+    (void)hipStreamEndCapture(P->cs, &bad);
+    if (bad) (void)hipGraphDestroy(bad);
+    (void)hipGetLastError();
+    throw;
+  }
+  if (hipStreamEndCapture(P->cs, &P->g) != hipSuccess || !P->g) {
+    (void)hipGetLastError();
+    return fail(HM_E_DEVICE, "hm_compress_plan: the pipeline could not be captured "
+                             "(the black box must only enqueue work on the given stream)");
+  }
+  HIP_TRY(hipGraphInstantiate(&P->ge, P->g, nullptr, nullptr, 0));
+  size_t nn = 0;
+  (void)hipGraphGetNodes(P->g, nullptr, &nn);
+  P->nodes = (int64_t)nn;
+  *out = P.release();
+  return HM_OK;
+  API_END
+}
+
+hm_status hm_plan_execute(hm_plan *plan, void *stream) {
+  API_BEGIN
+  if (!plan) return fail(HM_E_ARG, "null plan");
+  hipStream_t s = (hipStream_t)stream;
+  const auto t0 = std::chrono::steady_clock::now();
+  HIP_TRY(hipGraphLaunch(plan->ge, s));
+  Events ev;
+  ev.s = s;
+  return plan->C->finalize(s, ev, t0);
+  API_END
+}
+
+hm_status hm_plan_hmatrix(const hm_plan *plan, const hm_hmatrix **H, int64_t *graph_nodes) {
+  if (!plan) return fail(HM_E_ARG, "null plan");
+  if (H) *H = plan->C->H.get();
+  if (graph_nodes) *graph_nodes = plan->nodes;
+  return HM_OK;
+}
+
+void hm_plan_free(hm_plan *plan) { delete plan; }
 
 hm_status hm_matvec(const hm_hmatrix *H, int64_t nrhs, int dtype, const void *X, int64_t ldx,
                     void *Y, int64_t ldy, int order, void *stream) {
