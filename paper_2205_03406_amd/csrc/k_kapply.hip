@@ -24,7 +24,16 @@ namespace {
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-constexpr int BK = 16;   // k-block (points) staged per LDS buffer
+// k-block (points per LDS stage): 16 in FP64 (49.7 TFLOP/s against 44.8 at
+// 32 on the log kernel, N = 16384, 576 columns), 32 in FP32 (92.8 against
+// 83.0 at 16 and 87.2 at 64: half the barriers per point, still two
+// workgroups per CU)
+#ifndef HM_KAPPLY_BK32
+#define HM_KAPPLY_BK32 32
+#endif
+#ifndef HM_KAPPLY_BK64
+#define HM_KAPPLY_BK64 16
+#endif
 #ifndef HM_KAPPLY_PAD
 #define HM_KAPPLY_PAD 2      // LDS row padding of the X k-block (elements)
 #endif
@@ -92,6 +101,7 @@ __global__ void __launch_bounds__(256)
 kapply_kernel(int64_t n, const double *__restrict__ pts_all, int64_t ncols,
               const T *__restrict__ X_all, int64_t ldx, T *__restrict__ Y_all, int64_t ldy,
               const KItem *__restrict__ items, int64_t split) {
+  constexpr int BK = sizeof(T) == 4 ? HM_KAPPLY_BK32 : HM_KAPPLY_BK64;  // points per LDS buffer
   constexpr int BN = 16 * NT;
   constexpr int LDT = BN + HM_KAPPLY_PAD;
   __shared__ T Xs[2][BK][LDT];
@@ -135,7 +145,7 @@ kapply_kernel(int64_t n, const double *__restrict__ pts_all, int64_t ncols,
   // (plain FP32 accumulation over N = 32768 points loses about 1e-4 of a
   // row's magnitude)
   constexpr int NS = sizeof(T) == 4 ? NT : 1;
-  constexpr int KCH = 4;
+  constexpr int KCH = 64 / BK;  // k-blocks per 64-point chunk
   f4 sum[NS], cmp[NS];
 #pragma unroll
   for (int t = 0; t < NS; ++t) {
@@ -363,9 +373,9 @@ void launch_any(int kernel, int nt, int dim, int64_t n, const double *pts, int64
 // tiles * (nt + 2); a grid of fewer than two workgroups per CU (512) leaves
 // CUs idle and is charged for it.  nt is capped where the accumulators
 // would drop the occupancy to one wave per SIMD (FP64: 12, FP32 with its
-// compensated sums: 10).
+// compensated sums and 32-point k-blocks: 6).
 int kapply_default_nt(int64_t ncols, bool f32, int64_t units) {
-  const int cap = f32 ? 10 : 12;
+  const int cap = f32 ? 6 : 12;
   const int64_t frags = (ncols + 15) / 16;
   int best = 2;
   double best_cost = 1e300;
