@@ -10,10 +10,14 @@ library never does, and the two share no code.
 * ``numeric.py`` (numpy/scipy, FP64): counter-based Gaussian test matrices,
   the dense kernel black box, compression (alg:h1_pseudocode with the
   per-pair recovery of alg:compress_double_random), hmatvec, error measures.
+* ``uniform.py``: uniform H^1 compression (per-box bases, two stages).
 """
 from .comb import OTree, dsatur, build as build_comb  # noqa: F401
 from .numeric import (  # noqa: F401
     philox4x32_10, gaussian_block, test_matrix, leaf_test_matrix,
     KernelBlackBox, DenseBlackBox, CountingBlackBox, compress, HMatrix,
     rel_fro_error_dense, probe_error, kernel_matrix,
+)
+from .uniform import (  # noqa: F401
+    UniformGraph, uniform_test_matrix, compress_uniform, uniform_floats,
 )

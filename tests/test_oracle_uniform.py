@@ -1,0 +1,168 @@
+"""Pins of the uniform H^1 oracle (section "Uniform H^1 matrix compression")
+against what the paper and the mathematics fix."""
+import itertools
+import json
+import os
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import (OTree, UniformGraph, uniform_test_matrix, compress_uniform, uniform_floats,
+                    compress, DenseBlackBox, CountingBlackBox, KernelBlackBox, kernel_matrix)
+from oracle.uniform import mixing_matrix
+from oracle.numeric import gaussian_block
+from synth import exact_uniform_h1, exact_h1
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _fixture():
+    return json.load(open(os.path.join(HERE, "golden", "worked_example_1d.json")))
+
+
+def _worked_tree():
+    # the paper's depth-3 example on a grid over [0, 1]: 64 points, 8 per leaf
+    return OTree(workloads.grid_1d(64), 8)
+
+
+def test_uniform_graph_of_the_worked_example():
+    """fig:graph_strong_1d_lvl3_unif: the 8 level-3 boxes (paper ids 8..15),
+    22 edges, and the figure's five color classes are a valid coloring."""
+    fx = _fixture()["graph_uniform_level3"]
+    T = _worked_tree()
+    UG = UniformGraph(T, 3)
+    assert list(UG.vbox) == list(range(8))
+    got = {tuple(sorted((int(UG.vbox[u]) + 8, int(UG.vbox[v]) + 8)))
+           for u in range(UG.nv) for v in UG.adj[UG.xadj[u]:UG.xadj[u + 1]]}
+    want = {tuple(sorted((int(a), int(b)))) for a, b in fx["edges"]}
+    assert got == want and len(want) == 22
+    fill = {int(k): v["fill"] for k, v in fx["vertices"].items()}
+    for a, b in want:
+        assert fill[a] != fill[b]
+    # DSatur needs no more colors than the figure's five, and no coloring
+    # of this graph uses fewer than the clique number
+    assert UG.ncolors <= len(set(fill.values()))
+    clique = max(len(c) for c in (s for n in range(2, 9) for s in itertools.combinations(range(8), n))
+                 if all(tuple(sorted((a + 8, b + 8))) in want for a, b in itertools.combinations(c, 2)))
+    assert UG.ncolors >= clique
+
+
+def test_uniform_test_matrices_of_the_worked_example():
+    """The printed stage-1 test matrices: with the figure's coloring, each
+    column block is Gaussian exactly on the union of the interaction lists of
+    its vertices (boxes marked * are zero: no vertex of that color constrains
+    them) and zero elsewhere."""
+    fx = _fixture()["graph_uniform_level3"]
+    T = _worked_tree()
+    UG = UniformGraph(T, 3)
+    order = ["red", "cyan", "magenta", "green", "blue"]
+    # the printed matrices Omega_1..Omega_5 in the paper's order
+    printed = [{10, 11, 15}, {11, 12}, {8, 12, 13}, {8, 9, 13}, {10, 14, 15}]
+    fill = {int(k): v["fill"] for k, v in fx["vertices"].items()}
+    # match each printed block to a color class by its active set
+    classes = {}
+    for c in set(fill.values()):
+        boxes = [b for b, f in fill.items() if f == c]
+        classes[c] = set(int(x) + 8 for b in boxes for x in T.interaction(3, b - 8))
+    assert sorted(map(sorted, classes.values())) == sorted(map(sorted, printed))
+    colors = np.array([order.index(fill[b + 8]) for b in UG.vbox])
+    Om = uniform_test_matrix(T, 3, UG, seed=9, r=4, colors=colors)
+    for c, name in enumerate(order):
+        for b in range(8):
+            s0, s1 = T.box_range(3, b)
+            blk = Om[s0:s1, 4 * c:4 * c + 4]
+            assert (np.abs(blk).sum() > 0) == ((b + 8) in classes[name])
+
+
+@pytest.mark.parametrize("case", ["strong1d", "strong2d", "strong3d", "hodlr"])
+def test_uniform_recovers_exact_uniform_matrices(case):
+    """A uniform H^1 matrix of rank k is recovered to rounding error, in
+    fixed-rank and tolerance mode; planted errors (Gaussian Psi instead of
+    the bases, no peel) break this."""
+    if case == "strong1d":
+        T = OTree(workloads.random_points(512, 1, 3), 16)
+    elif case == "strong2d":
+        T = OTree(workloads.random_points(700, 2, 4), 16)
+    elif case == "strong3d":
+        T = OTree(workloads.random_points(900, 3, 5), 24)
+    else:
+        T = OTree(workloads.uniform_line(512, 3), 32, "index_binary", "weak")
+    k = 4
+    A = exact_uniform_h1(T, k, seed=8)
+    H = compress_uniform(T, DenseBlackBox(A), r=k + 10, k=k, seed=2)
+    err = np.linalg.norm(H.dense() - A) / np.linalg.norm(A)
+    assert err <= 1e-12, err
+    Ht = compress_uniform(T, DenseBlackBox(A), r=k + 10, tol=1e-11, seed=2)
+    assert np.linalg.norm(Ht.dense() - A) <= 1e-10 * np.linalg.norm(A)
+    assert Ht.saturated == 0
+    # bases are per box: every pair of a level uses its row box's U
+    for l, blocks in H.lowrank.items():
+        for a, b, U, B, V in blocks:
+            assert U is H.ubasis[l][a] and V is H.vbasis[l][b]
+
+
+def test_uniform_is_not_exact_on_nonuniform_matrices():
+    """Control: per-pair bases (non-uniform H^1) of rank k generally need
+    rank > k per box, so uniform compression at rank k is far off while the
+    non-uniform method is exact."""
+    T = OTree(workloads.random_points(700, 2, 4), 16)
+    A = exact_h1(T, 3, seed=6)
+    Hn = compress(T, DenseBlackBox(A), r=13, k=3, seed=2)
+    Hu = compress_uniform(T, DenseBlackBox(A), r=13, k=3, seed=2)
+    en = np.linalg.norm(Hn.dense() - A) / np.linalg.norm(A)
+    eu = np.linalg.norm(Hu.dense() - A) / np.linalg.norm(A)
+    assert en <= 1e-12 and eu > 1e-3
+
+
+def test_uniform_matvec_counts_and_accuracy_on_a_kernel():
+    """Stage 1 sends ncolors_u * r columns through A, stage 2 ncolors * kmax
+    through A*, the leaf pass ncolors_leaf * m; on the star-curve log kernel
+    the result reaches the tolerance with fewer stored values than the
+    non-uniform form."""
+    pts = workloads.star_curve(1500)
+    T = OTree(pts, 32)
+    A = kernel_matrix(pts, pts, "log")
+    bb = CountingBlackBox(DenseBlackBox(A))
+    H, graphs = compress_uniform(T, bb, r=24, tol=1e-8, seed=4, return_graphs=True)
+    kmax = 24 - 10
+    want_A = sum(graphs[l].ncolors * 24 for l in T.sampled_levels()) + \
+        T.leaf_graph.ncolors * T.leaf_max()
+    want_At = sum(T.graphs[l].ncolors * kmax for l in T.sampled_levels())
+    assert bb.cols_A == want_A and bb.cols_At == want_At
+    err = np.linalg.norm(H.dense() - A) / np.linalg.norm(A)
+    assert err <= 1e-7, err          # tol 1e-8 per block
+    Hn = compress(T, DenseBlackBox(A), 24, tol=1e-8, seed=4)
+    print("uniform floats", uniform_floats(H), "non-uniform", Hn.floats(), "err", err)
+    assert uniform_floats(H) < Hn.floats()
+    assert H.saturated == 0
+
+
+def test_uniform_colors_bounded_by_5_to_the_d():
+    """fig:unifh1activations: on a uniform grid the shifted pattern (color =
+    box coordinates mod 5 in each dimension) is a valid coloring of the
+    stage-1 graph, so at most 5^d colors are needed."""
+    g = (np.arange(32) + 0.5) / 32
+    pts = np.stack(np.meshgrid(g, g), -1).reshape(-1, 2)
+    T = OTree(pts, 16)
+    for l in T.sampled_levels():
+        UG = UniformGraph(T, l)
+        xy = T.org[l][UG.vbox, :2] >> (21 - l)
+        pat = (xy[:, 0] % 5) * 5 + (xy[:, 1] % 5)
+        for u in range(UG.nv):
+            for v in UG.adj[UG.xadj[u]:UG.xadj[u + 1]]:
+                assert pat[u] != pat[v]
+        assert len(set(pat.tolist())) <= 25
+        print("level", l, "DSatur colors", UG.ncolors, "pattern colors", len(set(pat.tolist())))
+
+
+def test_mixing_matrices_are_the_generator_draws():
+    """Gamma_a rows are the Philox/Box-Muller normals of the stated counter;
+    distinct boxes get independent matrices."""
+    G1 = mixing_matrix(5, 3, 128, 6)
+    for i in range(6):
+        assert np.array_equal(G1[i], gaussian_block(5, 3, 3, i, [128], 6)[0])
+    G2 = mixing_matrix(5, 3, 192, 6)
+    assert np.abs(G1 - G2).max() > 0.1
+    big = mixing_matrix(5, 2, 0, 40)
+    assert abs(big.mean()) < 0.1 and abs(big.std() - 1) < 0.1
