@@ -145,6 +145,18 @@ hm_status hm_incompat_graph(const hm_tree *tree, int level, int64_t *nv, int64_t
                             int64_t *npairs, const int32_t **pair_a, const int32_t **pair_b,
                             const int32_t **pair_v);
 
+/* hm_uniform_graph: the stage-1 constraint incompatibility graph of uniform
+ * H^1 compression at `level` (section on uniform H^1 compression,
+ * eq:unifh1constraints), built and DSatur-colored on first use.  One vertex
+ * per box a with a non-empty interaction list (boxes ascending): the test
+ * matrix must be a Gaussian block on every box of a's interaction list and
+ * vanish on a's neighbors; a and b are adjacent when a box active for one is
+ * a neighbor of the other.  Outputs point into memory owned by the tree:
+ * xadj (nv+1), adj (nadj, ascending), vbox (nv), color (nv). */
+hm_status hm_uniform_graph(hm_tree *tree, int level, int64_t *nv, int64_t *nadj,
+                           const int64_t **xadj, const int32_t **adj, const int32_t **vbox,
+                           int32_t *ncolors, const int32_t **color);
+
 /* hm_color: DSatur greedy coloring (alg:dsatur) of a CSR graph.  The next
  * vertex is the uncolored one with the largest saturation (number of
  * distinct colors among its neighbors), ties by larger degree, then lower

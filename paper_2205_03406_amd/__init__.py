@@ -40,7 +40,7 @@ EXPORTED = [
     "hm_tree_instances", "hm_autotune_table", "hm_server_create", "hm_server_free",
     "hm_server_submit_compress", "hm_server_submit_matvec", "hm_server_poll", "hm_server_hmatrix",
     "hm_server_release", "hm_server_info", "hm_compress_plan", "hm_plan_execute",
-    "hm_plan_hmatrix", "hm_plan_free",
+    "hm_plan_hmatrix", "hm_plan_free", "hm_uniform_graph",
 ]
 
 
@@ -141,6 +141,7 @@ def _load():
         "hm_hmatrix_stats": [P, C.POINTER(Stats)],
         "hm_hmatrix_export_level": [P, I, P, P, P, P, P, P, P, P, P, P, P],
         "hm_hmatrix_export_near": [P, P, P, P, P, P],
+        "hm_uniform_graph": [P, I, P, P, pp, pp, pp, P, pp],
         "hm_compress_plan": [P, C.POINTER(BlackBox), C.POINTER(Opts), P, pp],
         "hm_plan_execute": [P, P],
         "hm_plan_hmatrix": [P, pp, P],
@@ -327,6 +328,23 @@ class Tree:
     def color(self):
         _check(_lib.hm_tree_color(self.h))
         return self
+
+    def uniform_graph(self, level):
+        """Stage-1 graph of uniform H^1 compression at `level` (hm_uniform_graph):
+        (vbox, xadj, adj, color, ncolors)."""
+        nv, nadj, nc = C.c_int64(), C.c_int64(), C.c_int32()
+        xadj, adj, vbox, col = (C.c_void_p() for _ in range(4))
+        _check(_lib.hm_uniform_graph(self.h, level, C.byref(nv), C.byref(nadj), C.byref(xadj),
+                                     C.byref(adj), C.byref(vbox), C.byref(nc), C.byref(col)))
+
+        def arr(p, n, t):
+            if n == 0 or not p.value:
+                return np.zeros(0, t)
+            return np.ctypeslib.as_array(C.cast(p, C.POINTER(np.ctypeslib.as_ctypes_type(t))),
+                                         shape=(n,)).copy()
+        x = arr(xadj, nv.value + 1, np.int64) if nv.value else np.zeros(1, np.int64)
+        return (arr(vbox, nv.value, np.int32), x, arr(adj, nadj.value, np.int32),
+                arr(col, nv.value, np.int32), nc.value)
 
     def set_colors(self, level, colors):
         c = np.ascontiguousarray(colors, np.int32)

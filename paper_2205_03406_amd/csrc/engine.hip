@@ -1285,6 +1285,24 @@ hm_status hm_incompat_graph(const hm_tree *tree, int level, int64_t *nv, int64_t
   return HM_OK;
 }
 
+hm_status hm_uniform_graph(hm_tree *tree, int level, int64_t *nv, int64_t *nadj,
+                           const int64_t **xadj, const int32_t **adj, const int32_t **vbox,
+                           int32_t *ncolors, const int32_t **color) {
+  API_BEGIN
+  if (!tree || level < 0 || level >= tree->t.nlev()) return fail(HM_E_ARG, "bad level");
+  build_uniform_graphs(tree->t);
+  const Graph &G = tree->t.ugraphs[level];
+  if (nv) *nv = G.nv();
+  if (nadj) *nadj = (int64_t)G.adj.size();
+  if (xadj) *xadj = G.xadj.data();
+  if (adj) *adj = G.adj.data();
+  if (vbox) *vbox = G.vbox.data();
+  if (ncolors) *ncolors = G.ncolors;
+  if (color) *color = G.color.data();
+  return HM_OK;
+  API_END
+}
+
 hm_status hm_color(int64_t nv, const int64_t *xadj, const int32_t *adj, int32_t *color,
                    int32_t *ncolors) {
   API_BEGIN

@@ -58,6 +58,10 @@ struct Tree {
   // graph g.  A single tree is a forest of one instance.
   std::vector<int64_t> inst_off;
   std::vector<std::vector<int64_t>> gvoff;
+  // uniform H^1 stage-1 graphs, one per level (vertices = boxes with a
+  // non-empty interaction list), built and colored on first use
+  std::vector<Graph> ugraphs;
+  bool uniform_built = false;
   std::shared_ptr<DeviceTree> dev;
   std::vector<std::shared_ptr<void>> keep;  // objects whose lifetime is the tree's
   int nlev() const { return (int)lev.size(); }
@@ -77,6 +81,11 @@ hm_status build_tree(const double *pts, int64_t n, int dim, int leaf, int kind, 
 // level-l partitions.
 hm_status build_forest(const double *pts, const int64_t *counts, int ninst, int dim, int leaf,
                        int kind, int adm, Tree &F);
+// Builds and colors T.ugraphs (section on uniform H^1 compression,
+// eq:unifh1constraints): box a wants Gaussian blocks on its interaction list
+// and zeros on its neighbors; a and b conflict when a box active for one is
+// a neighbor of the other.  Idempotent; not thread-safe on one tree.
+void build_uniform_graphs(Tree &T);
 int32_t dsatur(int64_t nv, const int64_t *xadj, const int32_t *adj, int32_t *color);
 
 // ------------------------------------------------------------------ sizes

@@ -563,6 +563,62 @@ hm_status build_forest(const double *pts, const int64_t *counts, int ninst, int 
   return HM_OK;
 }
 
+void build_uniform_graphs(Tree &T) {
+  if (T.uniform_built) return;
+  T.ugraphs.assign(T.nlev(), Graph());
+  for (int l = 0; l < T.nlev(); ++l) {
+    const Level &Lv = T.lev[l];
+    Graph &G = T.ugraphs[l];
+    const int nb = Lv.nbox();
+    std::vector<int32_t> vid(nb, -1);
+    for (int a = 0; a < nb; ++a)
+      if (Lv.int_ptr[a + 1] > Lv.int_ptr[a]) {
+        vid[a] = (int32_t)G.vbox.size();
+        G.vbox.push_back(a);
+        G.vclass.push_back(0);
+      }
+    // conflicts of a: a neighbor of a box in a's interaction list, or a box
+    // in the interaction list of one of a's neighbors (neighbor and
+    // interaction relations are symmetric)
+    std::vector<uint8_t> mark(nb, 0);
+    std::vector<int32_t> cand;
+    G.xadj.assign(1, 0);
+    for (int32_t a : G.vbox) {
+      cand.clear();
+      for (int t = Lv.int_ptr[a]; t < Lv.int_ptr[a + 1]; ++t) {
+        const int b = Lv.intl[t];
+        for (int u = Lv.nei_ptr[b]; u < Lv.nei_ptr[b + 1]; ++u) {
+          const int c = Lv.nei[u];
+          if (c != a && vid[c] >= 0 && !mark[c]) {
+            mark[c] = 1;
+            cand.push_back(c);
+          }
+        }
+      }
+      for (int t = Lv.nei_ptr[a]; t < Lv.nei_ptr[a + 1]; ++t) {
+        const int b = Lv.nei[t];
+        for (int u = Lv.int_ptr[b]; u < Lv.int_ptr[b + 1]; ++u) {
+          const int c = Lv.intl[u];
+          if (c != a && vid[c] >= 0 && !mark[c]) {
+            mark[c] = 1;
+            cand.push_back(c);
+          }
+        }
+      }
+      std::sort(cand.begin(), cand.end());
+      for (int32_t c : cand) {
+        mark[c] = 0;
+        G.adj.push_back(vid[c]);
+      }
+      G.xadj.push_back((int64_t)G.adj.size());
+    }
+    G.color.assign(G.nv(), 0);
+    G.ncolors = dsatur(G.nv(), G.xadj.data(), G.adj.data(), G.color.data());
+    G.colored = true;
+  }
+  T.uniform_built = true;
+}
+
 // DSatur.  Vertices are ranked once by (degree descending, id ascending); the
 // uncolored vertices of each saturation value sit in a bitset over ranks, so
 // the next vertex is the lowest set rank of the highest non-empty saturation.

@@ -160,3 +160,27 @@ def test_single_hip_runtime_per_process():
                          timeout=300)
     assert out.returncode == 0, out.stderr
     assert out.stdout.split() == ["1", "1"], out.stdout
+
+
+@pytest.mark.parametrize("case", ["worked", "curve", "sphere", "hodlr"])
+def test_uniform_graphs_match_oracle(case):
+    """Stage-1 graphs of uniform H^1 (vertices, adjacency, DSatur colors)
+    equal the oracle's, level by level."""
+    from oracle import UniformGraph
+    if case == "worked":
+        args = (workloads.grid_1d(64), 8, "geometric", "strong")
+    elif case == "curve":
+        args = (workloads.star_curve(3000), 32, "geometric", "strong")
+    elif case == "sphere":
+        args = (workloads.sphere(3000, 4), 64, "geometric", "strong")
+    else:
+        args = (workloads.uniform_line(1024, 1), 64, "index_binary", "weak")
+    O = OTree(*args)
+    T = hm.Tree(*args)
+    for l in range(O.nlev):
+        UG = UniformGraph(O, l)
+        vbox, xadj, adj, col, nc = T.uniform_graph(l)
+        assert np.array_equal(vbox, UG.vbox), l
+        assert np.array_equal(xadj, UG.xadj), l
+        assert np.array_equal(adj, UG.adj), l
+        assert np.array_equal(col, UG.color) and nc == UG.ncolors, l
