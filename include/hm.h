@@ -258,10 +258,31 @@ typedef struct {
   uint64_t seed;
   int32_t max_retries; /* tolerance mode: recompress with r + 8 (at most 64) while
                           some block reaches the cap, at most this many times */
-  int32_t reserved;
+  int32_t format;      /* HM_FORMAT_H1, or HM_FORMAT_UNIFORM_H1 (below) */
 } hm_compress_opts;
 #define HM_FLAG_TIMING 1
 #define HM_FLAG_STRICT 2
+/* format = HM_FORMAT_UNIFORM_H1: uniform H^1 compression (section on
+ * uniform H^1 compression), one column basis U_a and one row basis V_b per
+ * box, shared by all admissible pairs: A(I_a, I_b) ~ U_a B_ab V_b*.  Per
+ * sampled level, coarsest first:
+ *   stage 1: test matrices from the coloring of hm_uniform_graph (pass 2 of
+ *     the generator): a Gaussian block on every box of a's interaction list,
+ *     zero on a's neighbors; Y = (A - A^(l)) Omega; U_a = qr(Y(I_a, block), k)
+ *     with the rules (cap r - p, saturation, mixed floor) of hm_compress.
+ *   stage 2: Psi = the level's pair-graph test matrix with U_a (k_a of kmax
+ *     columns) in place of the Gaussian block on box a; Z = (A - A^(l))* Psi;
+ *     V_b = qr(sum over a in int(b) of Z(I_b, block of (b, a)) Gamma_a, k),
+ *     Gamma_a a kmax x kmax Gaussian (pass 3, counter (first tree row of a,
+ *     column/2, row of Gamma, 4*level + 3)); rank at most kmax, no cap; in
+ *     the mixed form its floor is 8 u32 ||sum of the raw blocks||_F / sqrt(kmax).
+ *   B_ab = Z(I_b, block of (b, a))[:, :k_a]* V_b.
+ * kmax = rank (fixed rank) or r - p.  The leaf pass is that of hm_compress.
+ * The result applies, exports and serves like any H-matrix (the per-pair
+ * factors hold copies of the shared bases); hm_stats.nfloats counts each
+ * basis once. */
+#define HM_FORMAT_H1 0
+#define HM_FORMAT_UNIFORM_H1 1
 
 hm_status hm_compress(hm_tree *tree, const hm_blackbox *bb, const hm_compress_opts *opts,
                       void *stream, hm_hmatrix **out);
@@ -293,8 +314,9 @@ void hm_plan_free(hm_plan *plan);
 hm_status hm_matvec(const hm_hmatrix *H, int64_t nrhs, int dtype, const void *X, int64_t ldx,
                     void *Y, int64_t ldy, int order, void *stream);
 
-/* Device test matrix of one level and pass (0 = Omega, 1 = Psi) exactly as
- * hm_compress draws it: out (device, n x ncolors*r, ld) in tree order. */
+/* Device test matrix of one level and pass (0 = Omega, 1 = Psi, 2 = stage 1
+ * of the uniform format, colored by hm_uniform_graph) exactly as hm_compress
+ * draws it: out (device, n x ncolors*r, ld) in tree order. */
 hm_status hm_test_matrix(const hm_tree *tree, int level, int pass, int32_t r, uint64_t seed,
                          int dtype, void *out, int64_t ld, void *stream);
 /* Raw Philox4x32-10: ctr (device, 4*count u32, counter i at 4i..4i+3),
@@ -308,7 +330,8 @@ typedef struct {
   int64_t n;
   int64_t cols_A;            /* black-box columns through A */
   int64_t cols_At;           /* ... and through A* */
-  int32_t colors[32];        /* colors per level (0: level not sampled) */
+  int32_t colors[32];        /* colors per level (0: level not sampled); uniform
+                                format: colors of the stage-2 (pair) graph */
   int32_t leaf_colors;
   int32_t leaf_width;        /* m: columns per leaf color */
   int32_t max_rank;
@@ -317,7 +340,8 @@ typedef struct {
   int64_t saturated;         /* rank caps hit */
   int64_t nfloats;           /* stored values (U, B, V at their ranks, near blocks) */
   int32_t retries;           /* recompressions with a larger r (max_retries) */
-  int32_t pad_;
+  int32_t format;            /* HM_FORMAT_* of the compression */
+  int32_t ucolors[32];       /* uniform format: stage-1 colors per level */
   double flops_blackbox;     /* 2 N^2 per black-box column */
   double flops_peel;         /* level-truncated products subtracted */
   double flops_qr;           /* pivoted QR + basis formation */

@@ -26,6 +26,7 @@ HM_TREE_GEOMETRIC, HM_TREE_INDEX_BINARY = 0, 1
 HM_ADM_STRONG, HM_ADM_WEAK = 0, 1
 HM_F64, HM_F32 = 0, 1
 HM_PREC_F64, HM_PREC_MIXED = 0, 1
+HM_FORMAT_H1, HM_FORMAT_UNIFORM_H1 = 0, 1
 HM_KERNEL_LOG, HM_KERNEL_INV_R = 0, 1
 HM_ORDER_ORIGINAL, HM_ORDER_TREE = 0, 1
 HM_LIST_NEIGHBOR, HM_LIST_INTERACTION = 0, 1
@@ -62,7 +63,7 @@ class BlackBox(C.Structure):
 class Opts(C.Structure):
     _fields_ = [("rank", C.c_int32), ("tol", C.c_double), ("oversample", C.c_int32),
                 ("r", C.c_int32), ("prec", C.c_int32), ("flags", C.c_int32),
-                ("seed", C.c_uint64), ("max_retries", C.c_int32), ("reserved", C.c_int32)]
+                ("seed", C.c_uint64), ("max_retries", C.c_int32), ("format", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -70,7 +71,8 @@ class Stats(C.Structure):
                 ("cols_A", C.c_int64), ("cols_At", C.c_int64), ("colors", C.c_int32 * 32),
                 ("leaf_colors", C.c_int32), ("leaf_width", C.c_int32), ("max_rank", C.c_int32),
                 ("npairs", C.c_int64), ("nnear", C.c_int64), ("saturated", C.c_int64),
-                ("nfloats", C.c_int64), ("retries", C.c_int32), ("pad_", C.c_int32),
+                ("nfloats", C.c_int64), ("retries", C.c_int32), ("format", C.c_int32),
+                ("ucolors", C.c_int32 * 32),
                 ("flops_blackbox", C.c_double),
                 ("flops_peel", C.c_double), ("flops_qr", C.c_double),
                 ("flops_solve", C.c_double), ("ms_total", C.c_double),
@@ -81,7 +83,7 @@ class Stats(C.Structure):
         d = {}
         for name, _ in self._fields_:
             v = getattr(self, name)
-            d[name] = list(v) if name == "colors" else v
+            d[name] = list(v) if name in ("colors", "ucolors") else v
         return d
 
 
@@ -375,9 +377,9 @@ class Plan:
     by execute(); hmatrix() borrows the latest result."""
 
     def __init__(self, tree, bb, rank=0, tol=0.0, r=0, p=10, prec=HM_PREC_F64, seed=0,
-                 stream=None):
+                 stream=None, uniform=False):
         o = Opts(rank=rank, tol=tol, oversample=p, r=r, prec=prec, flags=0, seed=seed,
-                 max_retries=0, reserved=0)
+                 max_retries=0, format=HM_FORMAT_UNIFORM_H1 if uniform else HM_FORMAT_H1)
         h = C.c_void_p()
         _check(_lib.hm_compress_plan(tree.h, C.byref(bb), C.byref(o), _stream(stream),
                                      C.byref(h)))
@@ -537,11 +539,12 @@ class Server:
         self.close()
 
     def submit_compress(self, points, leaf, kind="geometric", adm="strong", kernel="log", rank=0,
-                        tol=0.0, r=0, p=10, prec=HM_PREC_F64, seed=0):
+                        tol=0.0, r=0, p=10, prec=HM_PREC_F64, seed=0, uniform=False):
         pts = np.ascontiguousarray(points, np.float64)
         if pts.ndim == 1:
             pts = pts.reshape(-1, 1)
-        o = Opts(rank=rank, tol=tol, oversample=p, r=r, prec=prec, flags=0, seed=seed)
+        o = Opts(rank=rank, tol=tol, oversample=p, r=r, prec=prec, flags=0, seed=seed,
+                 format=HM_FORMAT_UNIFORM_H1 if uniform else HM_FORMAT_H1)
         rid = C.c_int64()
         _check(_lib.hm_server_submit_compress(
             self.h, _ptr(pts), pts.shape[0], pts.shape[1], leaf,
@@ -603,10 +606,12 @@ HM_FLAG_TIMING, HM_FLAG_STRICT = 1, 2
 
 
 def compress(tree: Tree, bb: BlackBox, rank=0, tol=0.0, r=0, p=10, prec=HM_PREC_F64, seed=0,
-             timing=False, stream=None, max_retries=0, strict=False) -> HMatrix:
+             timing=False, stream=None, max_retries=0, strict=False, uniform=False) -> HMatrix:
+    """hm_compress; uniform=True selects the uniform H^1 format."""
     o = Opts(rank=rank, tol=tol, oversample=p, r=r, prec=prec,
              flags=(HM_FLAG_TIMING if timing else 0) | (HM_FLAG_STRICT if strict else 0),
-             seed=seed, max_retries=max_retries, reserved=0)
+             seed=seed, max_retries=max_retries,
+             format=HM_FORMAT_UNIFORM_H1 if uniform else HM_FORMAT_H1)
     h = C.c_void_p()
     _check(_lib.hm_compress(tree.h, C.byref(bb), C.byref(o), _stream(stream), C.byref(h)))
     return HMatrix(h, tree)

@@ -19,7 +19,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhm.so")
 
-HIP_SOURCES = ["k_misc.hip", "k_kapply.hip", "k_lowrank.hip", "k_qr.hip", "autotune.hip",
+HIP_SOURCES = ["k_misc.hip", "k_kapply.hip", "k_lowrank.hip", "k_qr.hip", "k_uniform.hip",
+               "autotune.hip",
                "engine.hip", "server.hip"]
 CXX_SOURCES = ["tree.cpp"]
 ARCH = os.environ.get("HM_OFFLOAD_ARCH", "gfx950")

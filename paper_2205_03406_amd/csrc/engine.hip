@@ -283,6 +283,17 @@ struct hm_hmatrix {
   int32_t nnch = 0;
   int64_t max_np = 0;
   Orient oA, oT;
+  // uniform format: the shared bases, one per box with a non-empty
+  // interaction list (ubox[li], ascending), U_a in UB and V_a in VB at
+  // uoff[li][v] (m x kmax, ld = m); brank [0, nvtot) U ranks, [nvtot, 2 nvtot)
+  // V ranks, level li's vertices from uv0[li]
+  int32_t format = HM_FORMAT_H1;
+  hm::DBuf UB, VB, brank;
+  std::vector<std::vector<int32_t>> ubox;
+  std::vector<std::vector<int64_t>> uoff;
+  std::vector<int64_t> uv0;
+  int64_t nvtot = 0;
+  std::vector<int32_t> h_brank;
   hm_stats stats{};
 };
 
@@ -530,6 +541,29 @@ struct Compression {
   DBuf dib, dic, dkit, dr0, dc0, dma, dmb, doff;  // leaf pass lists
   int32_t nib = 0, nkit_leaf = 0;
   int64_t cols_A = 0, cols_At = 0;
+  // uniform format (see hm_compress_opts.format)
+  bool uniform = false;
+  struct UniformJobs {
+    DBuf act;          // stage-1 active (box, color) flags
+    DBuf ju;           // stage-1 QR jobs, one per vertex
+    DBuf slot;         // stage-2 (box, color) -> vertex + 1
+    DBuf uoff;         // basis offsets per vertex
+    DBuf mix, terms;   // combination jobs (row chunks) and their terms
+    DBuf jv;           // row-basis QR jobs on S
+    DBuf uc;           // per-pair coupling jobs
+    DBuf kit1, kit2;   // forest kernel-apply items of the two stages
+    int32_t nv = 0, nmix = 0, nkit1 = 0, nkit2 = 0;
+  };
+  std::vector<UniformJobs> ujobs_of;
+  DBuf Sb, usat;
+  void setup_uniform(hipStream_t s);
+  void record_uniform_level(size_t li, hipStream_t s, Events &ev);
+  void fp32_copies(size_t li, hipStream_t s);
+  int inst_of_row(int64_t row) const {
+    if (ni <= 1) return 0;
+    return (int)(std::upper_bound(T.inst_off.begin(), T.inst_off.end(), row) -
+                 T.inst_off.begin()) - 1;
+  }
 
   Compression(Tree &t, const hm_blackbox &b, const hm_compress_opts &opt)
       : T(t), bb(b), o(opt) {}
@@ -578,9 +612,13 @@ hm_status Compression::setup(hipStream_t s) {
   if (mixed && !(bb.dtypes & (1 << HM_F32))) return fail(HM_E_ARG, "black box has no FP32 apply");
   if (!mixed && !(bb.dtypes & (1 << HM_F64))) return fail(HM_E_ARG, "black box has no FP64 apply");
   if (!bb.apply) return fail(HM_E_ARG, "black box without apply");
+  if (o.format != HM_FORMAT_H1 && o.format != HM_FORMAT_UNIFORM_H1)
+    return fail(HM_E_ARG, "unknown format");
+  uniform = o.format == HM_FORMAT_UNIFORM_H1;
   kmax = kfix > 0 ? std::min(kfix, r) : r - p;
   es = mixed ? 4 : 8;
   n = T.n;
+  if (uniform) build_uniform_graphs(T);
 
   D = &device_tree(T, s);
   H = std::make_unique<hm_hmatrix>();
@@ -670,6 +708,13 @@ hm_status Compression::setup(hipStream_t s) {
   mw = T.leaf_width();
   leaf_cols = pad16((int64_t)GL.ncolors * mw);
   wcols = std::max<int64_t>(2 * cmax, leaf_cols);
+  if (uniform) {
+    // the two stages run one after the other through the same buffers
+    wcols = leaf_cols;
+    for (int l : levels)
+      wcols = std::max({wcols, pad16((int64_t)T.ugraphs[l].ncolors * r),
+                        pad16((int64_t)T.graphs[l].ncolors * kmax)});
+  }
   buf(Xb, (size_t)n * wcols * es, s);
   buf(Yb, (size_t)n * wcols * es, s);
   tcap = tscratch_elems(*H, wcols);
@@ -710,8 +755,9 @@ hm_status Compression::setup(hipStream_t s) {
   direct = kbb && kbb->tree == &T && ni > 1;
 
   // ---------------- every job list of every level, uploaded once up front
+  if (uniform) setup_uniform(s);
   jobs_of.resize(H->lv.size());
-  for (size_t li = 0; li < H->lv.size(); ++li) {
+  for (size_t li = 0; !uniform && li < H->lv.size(); ++li) {
     hm_hmatrix::Lv &L = H->lv[li];
     const Graph &G = T.graphs[L.level];
     const Level &Lv = T.lev[L.level];
@@ -789,6 +835,227 @@ hm_status Compression::setup(hipStream_t s) {
   return HM_OK;
 }
 
+// Bases, job lists and buffers of the uniform format (one vertex per box
+// with a non-empty interaction list; the same boxes are the row and the
+// column boxes of the level's pairs).
+void Compression::setup_uniform(hipStream_t s) {
+  H->format = HM_FORMAT_UNIFORM_H1;
+  const size_t nlv = H->lv.size();
+  int64_t szb = 0;
+  H->ubox.resize(nlv);
+  H->uoff.resize(nlv);
+  H->uv0.resize(nlv);
+  for (size_t li = 0; li < nlv; ++li) {
+    const int l = H->lv[li].level;
+    const Graph &UG = T.ugraphs[l];
+    H->uv0[li] = H->nvtot;
+    H->ubox[li] = UG.vbox;
+    for (int64_t v = 0; v < UG.nv(); ++v) {
+      H->uoff[li].push_back(szb);
+      szb += T.box_size(l, UG.vbox[v]) * kmax;
+    }
+    H->nvtot += UG.nv();
+  }
+  H->UB.alloc((size_t)std::max<int64_t>(szb, 1) * 8);
+  H->VB.alloc((size_t)std::max<int64_t>(szb, 1) * 8);
+  H->brank.alloc((size_t)std::max<int64_t>(2 * H->nvtot, 1) * 4);
+  buf(Sb, (size_t)n * kmax * 8, s);
+  buf(usat, (size_t)std::max<int64_t>(2 * H->nvtot, 1) * 4, s);
+
+  ujobs_of.resize(nlv);
+  for (size_t li = 0; li < nlv; ++li) {
+    const hm_hmatrix::Lv &L = H->lv[li];
+    const int l = L.level;
+    const Graph &G = T.graphs[l], &UG = T.ugraphs[l];
+    const Level &Lv = T.lev[l];
+    const int nb = Lv.nbox();
+    UniformJobs &J = ujobs_of[li];
+    J.nv = (int32_t)UG.nv();
+    std::vector<int32_t> vid(nb, -1);
+    for (int64_t v = 0; v < UG.nv(); ++v) vid[UG.vbox[v]] = (int32_t)v;
+    // stage 1: active flags and QR jobs
+    std::vector<uint8_t> act((size_t)nb * std::max(UG.ncolors, 1), 0);
+    std::vector<QrJob> ju(UG.nv()), jv(UG.nv());
+    int64_t wofs = 0;
+    for (int64_t v = 0; v < UG.nv(); ++v) {
+      const int a = UG.vbox[v], c = UG.color[v];
+      for (int32_t t = Lv.int_ptr[a]; t < Lv.int_ptr[a + 1]; ++t)
+        act[(size_t)Lv.intl[t] * UG.ncolors + c] = 1;
+      const int32_t m = (int32_t)T.box_size(l, a);
+      ju[v] = QrJob{Lv.start[a], (int64_t)c * r, H->uoff[li][v], wofs, m, 0};
+      jv[v] = QrJob{Lv.start[a], 0, H->uoff[li][v], wofs, m, 0};
+      wofs += (int64_t)m * r;
+    }
+    // stage 2: the pair graph's (box, color) slots hold the box's basis
+    std::vector<int32_t> slot((size_t)nb * std::max(G.ncolors, 1), 0);
+    for (int64_t v = 0; v < G.nv(); ++v) {
+      const int a = G.vbox[v];
+      if (vid[a] < 0) throw Error{HM_E_STATE, "pair-graph box without a uniform basis"};
+      slot[(size_t)a * G.ncolors + G.color[v]] = vid[a] + 1;
+    }
+    std::unordered_map<int64_t, int64_t> pidx;
+    pidx.reserve(L.np * 2);
+    for (int64_t q = 0; q < L.np; ++q) pidx[(int64_t)L.pa[q] * nb + L.pb[q]] = q;
+    auto color_of = [&](int a, int b) {  // color of the pair (a, b)'s vertex
+      return (int64_t)G.color[G.pv[pidx.at((int64_t)a * nb + b)]];
+    };
+    // combination jobs: 256-row chunks of every vertex box b, terms over a in int(b)
+    std::vector<MixJob> mix;
+    std::vector<MixTerm> terms;
+    for (int64_t v = 0; v < UG.nv(); ++v) {
+      const int b = UG.vbox[v];
+      const int32_t t0 = (int32_t)terms.size();
+      for (int32_t t = Lv.int_ptr[b]; t < Lv.int_ptr[b + 1]; ++t) {
+        const int a = Lv.intl[t];
+        const int inst = inst_of_row(Lv.start[a]);
+        const int64_t base = ni > 1 ? T.inst_off[inst] : 0;
+        terms.push_back(MixTerm{color_of(b, a) * kmax, (uint32_t)(Lv.start[a] - base),
+                                (uint32_t)inst});
+      }
+      const int32_t t1 = (int32_t)terms.size();
+      const int64_t m = T.box_size(l, b);
+      for (int64_t r0 = 0; r0 < m; r0 += 256)
+        mix.push_back(MixJob{Lv.start[b] + r0, (int32_t)std::min<int64_t>(256, m - r0), t0, t1, 0});
+    }
+    // per-pair coupling jobs
+    std::vector<UCJob> uc(L.np);
+    for (int64_t q = 0; q < L.np; ++q) {
+      const int a = L.pa[q], b = L.pb[q];
+      uc[q] = UCJob{Lv.start[b], color_of(b, a) * kmax, H->uoff[li][vid[a]], H->uoff[li][vid[b]],
+                    L.offU[q], L.offV[q], L.offW[q], L.offB[q],
+                    (int32_t)T.box_size(l, a), (int32_t)T.box_size(l, b), vid[a], vid[b],
+                    (int32_t)(L.g0 + q), (int32_t)(np_total + L.g0 + q)};
+    }
+    if (direct) {
+      std::vector<int32_t> wu(ni, 0);
+      for (int64_t v = 0; v < UG.nv(); ++v) {
+        const int i = inst_of_row(Lv.start[UG.vbox[v]]);
+        wu[i] = std::max(wu[i], UG.color[v] + 1);
+      }
+      for (int32_t &x : wu) x *= r;
+      std::vector<KItem> k1 = forest_items(T, wu);
+      std::vector<int32_t> w2 = inst_colors(l);
+      for (int32_t &x : w2) x *= kmax;
+      std::vector<KItem> k2 = forest_items(T, w2);
+      put(J.kit1, k1, s);
+      put(J.kit2, k2, s);
+      J.nkit1 = (int32_t)k1.size();
+      J.nkit2 = (int32_t)k2.size();
+    }
+    J.nmix = (int32_t)mix.size();
+    put(J.act, act, s);
+    put(J.ju, ju, s);
+    put(J.jv, jv, s);
+    put(J.slot, slot, s);
+    put(J.uoff, H->uoff[li], s);
+    put(J.mix, mix, s);
+    put(J.terms, terms, s);
+    put(J.uc, uc, s);
+    HIP_TRY(hipStreamSynchronize(s));  // the host vectors die here
+  }
+}
+
+// One uniform level: stage 1 (column bases), stage 2 (row bases, couplings).
+void Compression::record_uniform_level(size_t li, hipStream_t s, Events &ev) {
+  const DeviceTree &Dv = *D;
+  hm_hmatrix::Lv &L = H->lv[li];
+  const int l = L.level;
+  const Graph &G = T.graphs[l], &UG = T.ugraphs[l];
+  UniformJobs &J = ujobs_of[li];
+  const int64_t v0 = H->uv0[li];
+  int32_t *urank = H->brank.as<int32_t>() + v0;
+  int32_t *vrank = H->brank.as<int32_t>() + H->nvtot + v0;
+  const int64_t c1 = (int64_t)UG.ncolors * r, c1pad = pad16(c1);
+  const int64_t c2 = (int64_t)G.ncolors * kmax, c2pad = pad16(c2);
+  void *X = Xb.p, *Y = Yb.p;
+  // black box on the first `cols` columns of X into Y (A, or A* when trans)
+  auto apply_bb = [&](int trans, int64_t cols, const DBuf &kit, int32_t nkit) {
+    if (direct) {
+      autotune_kapply(KapplyShape{mixed, kbb->kernel, T.dim, cols, n, true, nkit},
+                      [&](int nt, int64_t part) {
+                        launch_kapply_forest(kbb->kernel, T.dim, n, Dv.pts.as<double>(),
+                                             part > 0 ? (int32_t)part : nkit, kit.as<KItem>(),
+                                             cols, -1, nt, mixed, X, n, Y, n, s);
+                      },
+                      s);
+      LAUNCH_CHECK();
+    } else {
+      call_blackbox(bb, bb.symmetric ? 0 : trans, n, cols, mixed, X, n, Y, n, Dv, tmpx, tmpy, s);
+    }
+  };
+  constexpr double kNoiseGamma = 8.0;  // see the mixed floor of record()
+  // ---------------- stage 1: Y = (A - A^(l)) Omega, U_a = qr(Y(I_a, block))
+  ev.mark(0);
+  launch_testmat(n, Dv.rowbox[l].as<int32_t>(), J.act.as<uint8_t>(), UG.ncolors, r, l, 2, o.seed,
+                 Dv.inst_off.as<int64_t>(), ni, mixed, X, n, c1pad, s);
+  LAUNCH_CHECK();
+  ev.mark(1);
+  apply_bb(0, c1pad, J.kit1, J.nkit1);
+  cols_A += c1;
+  if (mixed) {
+    launch_block_norms(J.nv, J.ju.as<QrJob>(), r, kNoiseGamma * 0x1p-24 / std::sqrt((double)r),
+                       true, Y, n, floor_u.as<double>(), s);
+    LAUNCH_CHECK();
+  }
+  ev.mark(2);
+  apply_levels(*H, li, false, mixed, X, n, c1pad, Y, n, -1.0, Tb.p, tcap, s);
+  launch_check_finite(n, c1pad, mixed, Y, n, flag.as<int32_t>(), s);
+  LAUNCH_CHECK();
+  ev.mark(3);
+  launch_pivqr(J.nv, J.ju.as<QrJob>(), r, kfix, o.tol, kfix > 0 ? kfix : r - p,
+               mixed ? floor_u.as<double>() : nullptr, mixed, Y, n, work.as<double>(),
+               H->UB.as<double>(), urank, usat.as<int32_t>() + v0, s);
+  LAUNCH_CHECK();
+  // ---------------- stage 2: Z = (A - A^(l))* Psi(U), V_b = qr(sum_a Z_ba Gamma_a)
+  ev.mark(0);
+  launch_basis_testmat(n, Dv.rowbox[l].as<int32_t>(), Dv.start[l].as<int64_t>(),
+                       J.slot.as<int32_t>(), G.ncolors, kmax, H->UB.as<double>(),
+                       J.uoff.as<int64_t>(), urank, mixed, X, n, c2pad, s);
+  LAUNCH_CHECK();
+  ev.mark(1);
+  apply_bb(1, c2pad, J.kit2, J.nkit2);
+  cols_At += c2;
+  if (mixed) {
+    // floor from the combination of the raw (unpeeled) blocks
+    launch_mix_sum(J.nmix, J.mix.as<MixJob>(), J.terms.as<MixTerm>(), kmax, l, o.seed, true, Y,
+                   n, Sb.as<double>(), n, s);
+    launch_block_norms(J.nv, J.jv.as<QrJob>(), kmax,
+                       kNoiseGamma * 0x1p-24 / std::sqrt((double)kmax), false, Sb.p, n,
+                       floor_v.as<double>(), s);
+    LAUNCH_CHECK();
+  }
+  ev.mark(2);
+  apply_levels(*H, li, true, mixed, X, n, c2pad, Y, n, -1.0, Tb.p, tcap, s);
+  launch_check_finite(n, c2pad, mixed, Y, n, flag.as<int32_t>(), s);
+  LAUNCH_CHECK();
+  ev.mark(3);
+  launch_mix_sum(J.nmix, J.mix.as<MixJob>(), J.terms.as<MixTerm>(), kmax, l, o.seed, mixed, Y, n,
+                 Sb.as<double>(), n, s);
+  launch_pivqr(J.nv, J.jv.as<QrJob>(), kmax, kfix, o.tol, kmax,
+               mixed ? floor_v.as<double>() : nullptr, false, Sb.p, n, work.as<double>(),
+               H->VB.as<double>(), vrank, usat.as<int32_t>() + H->nvtot + v0, s);
+  LAUNCH_CHECK();
+  ev.mark(4);
+  launch_ucoupling((int32_t)L.np, J.uc.as<UCJob>(), kmax, mixed, Y, n, H->UB.as<double>(),
+                   H->VB.as<double>(), urank, vrank, H->U.as<double>(), H->V.as<double>(),
+                   H->B.as<double>(), H->W.as<double>(), H->ranks.as<int32_t>(), s);
+  LAUNCH_CHECK();
+}
+
+// FP32 copies of level li's apply factors
+void Compression::fp32_copies(size_t li, hipStream_t s) {
+  const hm_hmatrix::Lv &L = H->lv[li];
+  const int64_t u0 = L.offU.empty() ? 0 : L.offU[0];
+  const int64_t u1 = li + 1 < H->lv.size() ? H->lv[li + 1].offU[0] : szU;
+  const int64_t v0 = L.offV.empty() ? 0 : L.offV[0];
+  const int64_t v1 = li + 1 < H->lv.size() ? H->lv[li + 1].offV[0] : szV;
+  launch_convert(u1 - u0, 1, false, H->W.as<double>() + u0, u1 - u0, H->Wf.as<float>() + u0,
+                 u1 - u0, s);
+  launch_convert(v1 - v0, 1, false, H->V.as<double>() + v0, v1 - v0, H->Vf.as<float>() + v0,
+                 v1 - v0, s);
+  LAUNCH_CHECK();
+}
+
 void Compression::record(hipStream_t s, Events &ev) {
   const DeviceTree &Dv = *D;
   const Graph &GL = T.leaf_graph();
@@ -801,8 +1068,15 @@ void Compression::record(hipStream_t s, Events &ev) {
   LAUNCH_CHECK();
   cols_A = cols_At = 0;
   // ---------------- the level loop (no host round trips)
+  if (uniform) launch_fill(usat.p, std::max<int64_t>(2 * H->nvtot, 1), true, 0.0, s);
   for (size_t li = 0; li < H->lv.size(); ++li) {
     hm_hmatrix::Lv &L = H->lv[li];
+    if (uniform) {
+      record_uniform_level(li, s, ev);
+      fp32_copies(li, s);
+      ev.mark(5);
+      continue;
+    }
     const int l = L.level;
     const Graph &G = T.graphs[l];
     const int64_t c = (int64_t)G.ncolors * r;
@@ -878,18 +1152,7 @@ void Compression::record(hipStream_t s, Events &ev) {
                     core.as<double>(), scratch.as<double>(), H->B.as<double>(),
                     H->W.as<double>(), s);
     LAUNCH_CHECK();
-    // FP32 copies of this level's apply factors
-    {
-      const int64_t u0 = L.offU.empty() ? 0 : L.offU[0];
-      const int64_t u1 = li + 1 < H->lv.size() ? H->lv[li + 1].offU[0] : szU;
-      const int64_t v0 = L.offV.empty() ? 0 : L.offV[0];
-      const int64_t v1 = li + 1 < H->lv.size() ? H->lv[li + 1].offV[0] : szV;
-      launch_convert(u1 - u0, 1, false, H->W.as<double>() + u0, u1 - u0, H->Wf.as<float>() + u0,
-                     u1 - u0, s);
-      launch_convert(v1 - v0, 1, false, H->V.as<double>() + v0, v1 - v0, H->Vf.as<float>() + v0,
-                     v1 - v0, s);
-      LAUNCH_CHECK();
-    }
+    fp32_copies(li, s);
     ev.mark(5);
   }
 
@@ -940,6 +1203,14 @@ hm_status Compression::finalize(hipStream_t s, Events &ev,
     HIP_TRY(hipMemcpyAsync(hsat.data(), sat.p, 2 * np_total * 4, hipMemcpyDeviceToHost, s));
   }
   HIP_TRY(hipMemcpyAsync(&hflag, flag.p, 4, hipMemcpyDeviceToHost, s));
+  std::vector<int32_t> husat;
+  if (uniform && H->nvtot) {
+    H->h_brank.resize(2 * H->nvtot);
+    husat.resize(2 * H->nvtot);
+    HIP_TRY(hipMemcpyAsync(H->h_brank.data(), H->brank.p, 2 * H->nvtot * 4,
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(husat.data(), usat.p, 2 * H->nvtot * 4, hipMemcpyDeviceToHost, s));
+  }
   HIP_TRY(hipStreamSynchronize(s));
   if (hflag) return fail(HM_E_NUMERIC, "NaN or Inf in the black-box samples");
 
@@ -961,10 +1232,6 @@ hm_status Compression::finalize(hipStream_t s, Events &ev,
   int64_t nfloats = szD;
   // algorithmic work is counted per instance: instance i applies its own
   // operator to its own live columns and peels its own factors
-  auto inst_of_row = [&](int64_t row) {
-    return (int)(std::upper_bound(T.inst_off.begin(), T.inst_off.end(), row) -
-                 T.inst_off.begin()) - 1;
-  };
   // apply_cost[li][i]: flops per column of instance i's level-li factors
   std::vector<std::vector<double>> apply_cost_of(H->lv.size(), std::vector<double>(ni, 0.0));
   for (size_t li = 0; li < H->lv.size(); ++li) {
@@ -977,23 +1244,54 @@ hm_status Compression::finalize(hipStream_t s, Events &ev,
       const int ku = H->h_ranks[L.g0 + q], kv = H->h_ranks[np_total + L.g0 + q];
       st.max_rank = std::max(st.max_rank, std::max(ku, kv));
       st.saturated += hsat[L.g0 + q] + hsat[np_total + L.g0 + q];
-      nfloats += ma * ku + (int64_t)ku * kv + mb * kv;
       apply_cost[ni > 1 ? inst_of_row(Lv.start[L.pa[q]]) : 0] += 2.0 * kv * (ma + mb);
+      if (uniform) {
+        // coupling B = Z_blk^T V_b and W = U_a B; bases counted per box below
+        nfloats += (int64_t)ku * kv;
+        fsolve += 2.0 * mb * ku * kv + 2.0 * ma * ku * kv;
+        continue;
+      }
+      nfloats += ma * ku + (int64_t)ku * kv + mb * kv;
       fqr += qr_flops(ma, r, ku) + qr_flops(mb, r, kv);
       fsolve += 2.0 * ma * r * r + 2.0 * ma * r * ku + 2.0 * mb * r * kv + 4.0 * r * ku * ku +
                 4.0 * r * kv * kv + 2.0 * r * r * (ku + kv) + 2.0 * ma * ku * kv;
+    }
+    if (uniform) {
+      st.format = HM_FORMAT_UNIFORM_H1;
+      if (L.level < 32) st.ucolors[L.level] = T.ugraphs[L.level].ncolors;
+      const int64_t v0 = H->uv0[li];
+      for (size_t v = 0; v < H->ubox[li].size(); ++v) {
+        const int a = H->ubox[li][v];
+        const int64_t m = Lv.start[a + 1] - Lv.start[a];
+        const int ku = H->h_brank[v0 + v], kv = H->h_brank[H->nvtot + v0 + v];
+        st.saturated += husat[v0 + v];
+        nfloats += m * (ku + kv);
+        fqr += qr_flops(m, r, ku) + qr_flops(m, kmax, kv);
+        // the combination sum_a Z_ba Gamma_a
+        fsolve += 2.0 * m * kmax * kmax * (T.lev[L.level].int_ptr[a + 1] - T.lev[L.level].int_ptr[a]);
+      }
     }
   }
   double fbb = 0;
   {
     std::vector<double> prev(ni, 0.0);
     for (size_t li = 0; li < H->lv.size(); ++li) {
-      const std::vector<int32_t> w = inst_colors(H->lv[li].level);
+      const int l = H->lv[li].level;
+      const std::vector<int32_t> w = inst_colors(l);
+      std::vector<int32_t> wu(ni, 0);
+      if (uniform) {
+        const Graph &UG = T.ugraphs[l];
+        for (int64_t v = 0; v < UG.nv(); ++v) {
+          const int i = inst_of_row(T.lev[l].start[UG.vbox[v]]);
+          wu[i] = std::max(wu[i], UG.color[v] + 1);
+        }
+      }
       for (int i = 0; i < ni; ++i) {
-        const double c = (double)w[i] * r;
+        // columns of the Y and Z passes
+        const double c = uniform ? (double)wu[i] * r + (double)w[i] * kmax : 2.0 * w[i] * r;
         const double ni_rows = (double)(T.inst_off[i + 1] - T.inst_off[i]);
-        fpeel += 2.0 * c * prev[i];  // Y and Z passes
-        fbb += 2.0 * ni_rows * ni_rows * 2.0 * c;
+        fpeel += c * prev[i];
+        fbb += 2.0 * ni_rows * ni_rows * c;
       }
       for (int i = 0; i < ni; ++i) prev[i] += apply_cost_of[li][i];
     }
@@ -1054,7 +1352,8 @@ hm_status compress_impl(Tree &T, const hm_blackbox &bb, const hm_compress_opts &
 // Device bytes an H-matrix holds (factor pools, near blocks, apply plans).
 int64_t hmatrix_device_bytes(const hm_hmatrix *H) {
   int64_t b = H->perm.bytes + H->U.bytes + H->V.bytes + H->W.bytes + H->B.bytes + H->Vf.bytes +
-              H->Wf.bytes + H->D.bytes + H->ranks.bytes + H->nchunks.bytes + H->nentries.bytes;
+              H->Wf.bytes + H->D.bytes + H->ranks.bytes + H->nchunks.bytes + H->nentries.bytes +
+              H->UB.bytes + H->VB.bytes + H->brank.bytes;
   for (const hm_hmatrix::Orient *O : {&H->oA, &H->oT}) {
     b += O->items.bytes + O->ppairs.bytes;
     for (const DBuf &d : O->chunks) b += d.bytes;
@@ -1105,7 +1404,15 @@ int64_t compress_footprint(const Tree &T, const hm_compress_opts &o) {
   const int64_t scratch = 2 * n * wcols * es + tcap * es + wmax * 8 + 2 * cmax_np * r * r * 8 +
                           np * 8 + cmax_np * 16;
   const int64_t plans = 64 * np + 4096;
-  return pools + scratch + plans;
+  int64_t uni = 0;
+  if (o.format == HM_FORMAT_UNIFORM_H1) {
+    // shared bases (each level's boxes cover at most n rows, U and V) and
+    // the combination buffer
+    for (int l = 1; l < T.nlev(); ++l)
+      if (!T.graphs[l].pa.empty()) uni += 2 * n * kmax * 8;
+    uni += n * kmax * 8;
+  }
+  return pools + scratch + plans + uni;
 }
 
 // Device bytes of one hm_matvec call (scratch and order conversion).
@@ -1624,14 +1931,25 @@ hm_status hm_test_matrix(const hm_tree *tree, int level, int pass, int32_t r, ui
                          int dtype, void *out, int64_t ld, void *stream) {
   API_BEGIN
   if (!tree || !out || level < 0 || level >= tree->t.nlev() || r <= 0 || ld < tree->t.n ||
-      (pass != 0 && pass != 1) || (dtype != HM_F64 && dtype != HM_F32))
+      pass < 0 || pass > 2 || (dtype != HM_F64 && dtype != HM_F32))
     return fail(HM_E_ARG, "hm_test_matrix: bad argument");
-  const Graph &G = tree->t.graphs[level];
+  Tree &T = const_cast<Tree &>(tree->t);
+  if (pass == 2) build_uniform_graphs(T);
+  const Graph &G = pass == 2 ? T.ugraphs[level] : T.graphs[level];
   if (!G.colored && G.nv() > 0) return fail(HM_E_STATE, "graph not colored");
   hipStream_t s = (hipStream_t)stream;
-  DeviceTree &D = device_tree(const_cast<Tree &>(tree->t), s);
-  std::vector<uint8_t> act((size_t)tree->t.lev[level].nbox() * std::max(G.ncolors, 1), 0);
-  for (int64_t v = 0; v < G.nv(); ++v) act[(size_t)G.vbox[v] * G.ncolors + G.color[v]] = 1;
+  DeviceTree &D = device_tree(T, s);
+  const Level &Lv = T.lev[level];
+  std::vector<uint8_t> act((size_t)Lv.nbox() * std::max(G.ncolors, 1), 0);
+  for (int64_t v = 0; v < G.nv(); ++v) {
+    if (pass == 2) {  // uniform stage 1: Gaussian on the vertex box's interaction list
+      const int a = G.vbox[v];
+      for (int32_t t = Lv.int_ptr[a]; t < Lv.int_ptr[a + 1]; ++t)
+        act[(size_t)Lv.intl[t] * G.ncolors + G.color[v]] = 1;
+    } else {
+      act[(size_t)G.vbox[v] * G.ncolors + G.color[v]] = 1;
+    }
+  }
   DBuf dact;
   upload(dact, act, s);
   launch_testmat(tree->t.n, D.rowbox[level].as<int32_t>(), dact.as<uint8_t>(), G.ncolors, r,

@@ -84,7 +84,7 @@ hm_status build_forest(const double *pts, const int64_t *counts, int ninst, int 
 // Builds and colors T.ugraphs (section on uniform H^1 compression,
 // eq:unifh1constraints): box a wants Gaussian blocks on its interaction list
 // and zeros on its neighbors; a and b conflict when a box active for one is
-// a neighbor of the other.  Idempotent; not thread-safe on one tree.
+// a neighbor of the other.  Idempotent and serialized (one builder at a time).
 void build_uniform_graphs(Tree &T);
 int32_t dsatur(int64_t nv, const int64_t *xadj, const int32_t *adj, int32_t *color);
 

@@ -366,7 +366,59 @@ coupling_kernel(const CoreJob *__restrict__ jobs, int32_t r, int32_t kmax,
   }
 }
 
+// ------------------------------------------------------------------ uniform coupling
+// Per pair (a, b): ranks, copies of the shared bases into the pair's slots,
+// B = Z(I_b, block of (b, a))[:, :ku]^T V_b (slot ld = kmax) and W = U_a B.
+template <typename T>
+__global__ void __launch_bounds__(256)
+ucoupling_kernel(const UCJob *__restrict__ jobs, int32_t kmax, const T *__restrict__ Z,
+                 int64_t ldz, const double *__restrict__ UB, const double *__restrict__ VB,
+                 const int32_t *__restrict__ urank, const int32_t *__restrict__ vrank,
+                 double *__restrict__ U, double *__restrict__ V, double *__restrict__ B,
+                 double *__restrict__ Wout, int32_t *__restrict__ ranks) {
+  extern __shared__ double smem[];  // tn_gemm staging, 33 * 2 kmax doubles
+  const UCJob job = jobs[blockIdx.x];
+  const int ku = urank[job.ua], kv = vrank[job.vb];
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    ranks[job.pu] = ku;
+    ranks[job.pv] = kv;
+  }
+  const double *Ua = UB + job.uboff;
+  const double *Vb = VB + job.vboff;
+  for (int64_t e = tid; e < (int64_t)job.ma * ku; e += 256) U[job.uslot + e] = Ua[e];
+  for (int64_t e = tid; e < (int64_t)job.mb * kv; e += 256) V[job.vslot + e] = Vb[e];
+  double *Bs = B + job.bslot;
+  for (int e = tid; e < kmax * kmax; e += 256) Bs[e] = 0.0;
+  __syncthreads();
+  if (ku == 0 || kv == 0) return;
+  tn_gemm(job.mb, ku, kv, Z + job.zcol0 * ldz + job.zrow0, ldz, Vb, (int64_t)job.mb, Bs, kmax,
+          smem);
+  double *W = Wout + job.wslot;
+  for (int i = tid; i < job.ma; i += 256) {
+    for (int c = 0; c < kv; ++c) {
+      double s = 0.0;
+      for (int t = 0; t < ku; ++t) s += Ua[(int64_t)t * job.ma + i] * Bs[t + c * kmax];
+      W[(int64_t)c * job.ma + i] = s;
+    }
+  }
+}
+
 }  // namespace
+
+void launch_ucoupling(int32_t njobs, const UCJob *jobs, int32_t kmax, bool f32, const void *Z,
+                      int64_t ldz, const double *UB, const double *VB, const int32_t *urank,
+                      const int32_t *vrank, double *U, double *V, double *B, double *W,
+                      int32_t *ranks, hipStream_t s) {
+  if (njobs <= 0) return;
+  const size_t sh = sizeof(double) * (33 * 2 * (size_t)kmax);
+  if (f32)
+    ucoupling_kernel<float><<<njobs, 256, sh, s>>>(jobs, kmax, (const float *)Z, ldz, UB, VB,
+                                                   urank, vrank, U, V, B, W, ranks);
+  else
+    ucoupling_kernel<double><<<njobs, 256, sh, s>>>(jobs, kmax, (const double *)Z, ldz, UB, VB,
+                                                    urank, vrank, U, V, B, W, ranks);
+}
 
 void launch_pivqr(int32_t njobs, const QrJob *jobs, int32_t r, int32_t rank_fixed, double tol,
                   int32_t cap, const double *floor_abs, bool f32, const void *S, int64_t lds,

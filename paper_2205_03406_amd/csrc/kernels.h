@@ -166,4 +166,46 @@ void launch_coupling(int32_t njobs, const CoreJob *jobs, int32_t r, int32_t kmax
                      const double *U, const double *V, const int32_t *ranks, const double *core,
                      double *scratch, double *B, double *W, hipStream_t s);
 
+// ---- uniform H^1 (k_uniform.hip, k_qr.hip)
+// Stage-2 test matrix assembled from the stage-1 column bases: out (n x
+// ncols_pad, ld) with out[i, c*kmax + j] = U_u(i - start[b], j) for the row's
+// box b at this level when u = slot[b*ncolors + c] - 1 >= 0 and j < urank[u]
+// (U_u at UB + uoff[u], m_b x kmax, ld = m_b), else 0.
+void launch_basis_testmat(int64_t n, const int32_t *rowbox, const int64_t *box_start,
+                          const int32_t *slot, int32_t ncolors, int32_t kmax, const double *UB,
+                          const int64_t *uoff, const int32_t *urank, bool f32, void *out,
+                          int64_t ld, int64_t ncols_pad, hipStream_t s);
+// One chunk (<= 256 rows) of box b's combination S_b = sum_t Z(rows, term t
+// block) Gamma_t over the terms [t0, t1).
+struct MixJob {
+  int64_t row0;
+  int32_t m;
+  int32_t t0, t1;
+  int32_t pad;
+};
+// Gamma_t (kmax x kmax): entry (i, j) is the Gaussian of counter (grow, j/2, i,
+// 4*level + 3) under key seed + inst (the test-matrix generator).
+struct MixTerm {
+  int64_t zcol0;   // first column of the term's block in Z
+  uint32_t grow;   // first tree row (instance-local) of the other box
+  uint32_t inst;   // instance of the pair
+};
+void launch_mix_sum(int32_t njobs, const MixJob *jobs, const MixTerm *terms, int32_t kmax,
+                    int32_t level, uint64_t seed, bool f32, const void *Z, int64_t ldz, double *S,
+                    int64_t lds, hipStream_t s);
+// Per admissible pair (a, b) of a uniform level: B = Z(I_b, block of (b, a))[:, :k_a]^T V_b,
+// W = U_a B, and the per-pair copies of U_a and V_b with their ranks.
+struct UCJob {
+  int64_t zrow0, zcol0;        // rows of b, block of the pair (b, a) in Z
+  int64_t uboff, vboff;        // U_a in UB (ma x kmax), V_b in VB (mb x kmax)
+  int64_t uslot, vslot, wslot, bslot;
+  int32_t ma, mb;
+  int32_t ua, vb;              // basis indexes into urank / vrank
+  int32_t pu, pv;              // rank slots of the pair
+};
+void launch_ucoupling(int32_t njobs, const UCJob *jobs, int32_t kmax, bool f32, const void *Z,
+                      int64_t ldz, const double *UB, const double *VB, const int32_t *urank,
+                      const int32_t *vrank, double *U, double *V, double *B, double *W,
+                      int32_t *ranks, hipStream_t s);
+
 }  // namespace hm

@@ -17,6 +17,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <set>
 #include <thread>
 #include <tuple>
@@ -564,6 +565,8 @@ hm_status build_forest(const double *pts, const int64_t *counts, int ninst, int 
 }
 
 void build_uniform_graphs(Tree &T) {
+  static std::mutex mu;
+  std::lock_guard<std::mutex> lk(mu);
   if (T.uniform_built) return;
   T.ugraphs.assign(T.nlev(), Graph());
   for (int l = 0; l < T.nlev(); ++l) {

@@ -1,0 +1,216 @@
+"""Uniform H^1 compression on the GPU (hm_compress with HM_FORMAT_UNIFORM_H1)
+against the oracle's compress_uniform.
+
+Bars (FP64 path): stage-1 test matrices within 8 ulps of the oracle's
+Gaussians with the same zero pattern; exact uniform H^1 matrices recovered
+to 1e-11 relative, and every block equal to the oracle's within 1e-10 of the
+block norm; kernel matrices: every block within 10 tol of the block norm of
+the oracle's (plus 1e-12 ||A||), the whole operator within the error the
+oracle reaches there; the shared bases identical (bit for bit) in every pair
+that uses them.  Mixed form: within 1e-5 of the FP64 form.  Forests: every
+instance equal to its own compression with key seed + i within 1e-10.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from synth import exact_uniform_h1
+from devutil import to_dev, to_host, dense_of
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2205_03406_amd as m
+    return m
+
+
+TREES = {
+    "strong2d": lambda: (workloads.random_points(700, 2, 11), 16, "geometric", "strong"),
+    "strong3d": lambda: (workloads.random_points(900, 3, 12), 24, "geometric", "strong"),
+    "curve": lambda: (workloads.star_curve(900), 20, "geometric", "strong"),
+    "hodlr": lambda: (workloads.uniform_line(512, 3), 32, "index_binary", "weak"),
+    "grid": lambda: (workloads.grid_1d(64), 8, "geometric", "strong"),
+}
+
+
+def _blocks(Hg, O):
+    return {l: Hg.export_level(l) for l in O.sampled_levels()}
+
+
+def _check_shared_bases(blocks):
+    for l, bl in blocks.items():
+        U, V = {}, {}
+        for a, b, Ua, B, Vb in bl:
+            if a in U:
+                assert np.array_equal(U[a], Ua), (l, a)
+            U[a] = Ua
+            if b in V:
+                assert np.array_equal(V[b], Vb), (l, b)
+            V[b] = Vb
+
+
+def _parity(O, blocks, Ho, A, rel):
+    floor = 1e-12 * np.linalg.norm(A)
+    perm = O.perm
+    worst = 0.0
+    for l, g in blocks.items():
+        o = Ho.lowrank[l]
+        assert len(g) == len(o)
+        for (a, b, U, B, V), (a2, b2, U2, B2, V2) in zip(g, o):
+            assert (a, b) == (a2, b2)
+            a0, a1 = O.box_range(l, a)
+            b0, b1 = O.box_range(l, b)
+            nb = np.linalg.norm(A[np.ix_(perm[a0:a1], perm[b0:b1])])
+            d = np.linalg.norm(U @ B @ V.T - U2 @ B2 @ V2.T)
+            worst = max(worst, d / max(nb, 1e-300))
+            assert d <= rel * nb + floor, (l, a, b, d, nb)
+            if U.shape[1]:
+                assert np.allclose(U.T @ U, np.eye(U.shape[1]), atol=1e-12)
+            if V.shape[1]:
+                assert np.allclose(V.T @ V, np.eye(V.shape[1]), atol=1e-12)
+    return worst
+
+
+@pytest.mark.parametrize("name", ["strong2d", "curve", "grid"])
+def test_uniform_test_matrices(hm, name):
+    pts, leaf, kind, adm = TREES[name]()
+    T = hm.Tree(pts, leaf, kind, adm).color()
+    O = oracle.OTree(pts, leaf, kind, adm)
+    for r in (6, 7):
+        for l in O.sampled_levels():
+            UG = oracle.UniformGraph(O, l)
+            want = oracle.uniform_test_matrix(O, l, UG, 99, r)
+            out = hm.colmajor(T.n, want.shape[1])
+            T.test_matrix(l, 2, r, 99, out)
+            got = to_host(out)
+            assert np.array_equal(got == 0, want == 0), (l, r)
+            nz = want != 0
+            assert np.max(np.abs(got[nz] - want[nz]) / np.abs(want[nz])) < 8 * 2.2e-16 * 4
+
+
+@pytest.mark.parametrize("name", ["strong2d", "strong3d", "curve", "hodlr"])
+def test_uniform_exact_recovery(hm, name):
+    args = TREES[name]()
+    O = oracle.OTree(*args)
+    T = hm.Tree(*args).color()
+    A = exact_uniform_h1(O, 4, seed=5)
+    bb = hm.dense_blackbox(to_dev(A))
+    H = hm.compress(T, bb, rank=4, r=10, seed=77, uniform=True)
+    D = dense_of(hm, H, O.n)
+    assert np.linalg.norm(D - A) <= 1e-11 * np.linalg.norm(A)
+    Ho = oracle.compress_uniform(O, oracle.DenseBlackBox(A), 10, k=4, seed=77)
+    blocks = _blocks(H, O)
+    _check_shared_bases(blocks)
+    _parity(O, blocks, Ho, A, rel=1e-10)
+    gn = H.export_near()
+    for (a, b, Dn), (a2, b2, D2) in zip(gn, Ho.near):
+        assert (a, b) == (a2, b2)
+        assert np.linalg.norm(Dn - D2) <= 1e-10 * np.linalg.norm(D2) + 1e-12 * np.linalg.norm(A)
+    st = H.stats()
+    assert st["format"] == hm.HM_FORMAT_UNIFORM_H1
+    ucol = [oracle.UniformGraph(O, l).ncolors for l in O.sampled_levels()]
+    chis = [T.graph(l).ncolors for l in O.sampled_levels()]
+    assert [st["ucolors"][l] for l in O.sampled_levels()] == ucol
+    assert st["cols_A"] == 10 * sum(ucol) + T.graph(-1).ncolors * O.leaf_max()
+    assert st["cols_At"] == 4 * sum(chis)
+    assert st["nfloats"] == oracle.uniform_floats(Ho)
+    # tolerance mode finds the exact ranks
+    Ht = hm.compress(T, bb, tol=1e-9, r=14, seed=78, uniform=True)
+    assert np.linalg.norm(dense_of(hm, Ht, O.n) - A) <= 1e-10 * np.linalg.norm(A)
+    assert Ht.stats()["max_rank"] <= 4
+
+
+@pytest.mark.parametrize("n,tol,r", [(1500, 1e-8, 24), (3000, 1e-6, 24)])
+def test_uniform_kernel_parity(hm, n, tol, r):
+    inst = workloads.config(1, n=n)
+    O = oracle.OTree(inst.points, inst.leaf, inst.tree, inst.adm)
+    T = hm.Tree(inst.points, inst.leaf, inst.tree, inst.adm).color()
+    A = oracle.kernel_matrix(inst.points, inst.points, inst.kernel)
+    H = hm.compress(T, T.kernel_blackbox(inst.kernel), tol=tol, r=r, seed=inst.seed, uniform=True)
+    Ho = oracle.compress_uniform(O, oracle.DenseBlackBox(A), r, tol=tol, seed=inst.seed)
+    blocks = _blocks(H, O)
+    _check_shared_bases(blocks)
+    worst = _parity(O, blocks, Ho, A, rel=10 * tol)
+    D = dense_of(hm, H, O.n)
+    err = np.linalg.norm(D - A) / np.linalg.norm(A)
+    err_o = np.linalg.norm(Ho.dense() - A) / np.linalg.norm(A)
+    st = H.stats()
+    Hn = hm.compress(T, T.kernel_blackbox(inst.kernel), tol=tol, r=r, seed=inst.seed)
+    print("uniform: err %.2e (oracle %.2e), worst block diff %.1e, floats %d (oracle %d, "
+          "non-uniform %d)" % (err, err_o, worst, st["nfloats"], oracle.uniform_floats(Ho),
+                               Hn.stats()["nfloats"]))
+    assert err <= max(2 * err_o, tol)
+    assert abs(st["nfloats"] - oracle.uniform_floats(Ho)) <= 0.01 * oracle.uniform_floats(Ho)
+    assert st["nfloats"] < Hn.stats()["nfloats"]
+    assert st["saturated"] == 0
+
+
+def test_uniform_mixed_matches_f64(hm):
+    inst = workloads.config(1, n=4096)
+    T = hm.Tree(inst.points, inst.leaf, inst.tree, inst.adm).color()
+    bb = T.kernel_blackbox(inst.kernel)
+    H64 = hm.compress(T, bb, tol=1e-6, r=24, seed=5, uniform=True)
+    H32 = hm.compress(T, bb, tol=1e-6, r=24, seed=5, uniform=True, prec=hm.HM_PREC_MIXED)
+    X = np.random.default_rng(0).standard_normal((T.n, 4))
+    Y64, Y32 = hm.colmajor(T.n, 4), hm.colmajor(T.n, 4)
+    H64.matvec(to_dev(X), Y64)
+    H32.matvec(to_dev(X), Y32)
+    a, b = to_host(Y64), to_host(Y32)
+    d = np.linalg.norm(a - b) / np.linalg.norm(a)
+    print("mixed vs FP64 uniform: %.2e; ranks %d vs %d" % (d, H32.stats()["max_rank"],
+                                                          H64.stats()["max_rank"]))
+    assert d <= 1e-5
+    assert H32.stats()["saturated"] == 0
+
+
+def test_uniform_forest_matches_instances(hm):
+    parts = [workloads.ellipse(n, a, b) for n, a, b in [(2500, 1.4, 0.6), (900, 1.0, 1.0),
+                                                        (1700, 0.7, 1.9), (100, 1.0, 0.5)]]
+    F = hm.Tree(parts, 64).color()
+    off = F.instances()
+    seed = 31
+    for prec in (hm.HM_PREC_F64, hm.HM_PREC_MIXED):
+        Hf = hm.compress(F, F.kernel_blackbox("log"), tol=1e-6, r=24, seed=seed, prec=prec,
+                         uniform=True)
+        X = np.random.default_rng(1).standard_normal((F.n, 3))
+        Yf = hm.colmajor(F.n, 3)
+        Hf.matvec(to_dev(X), Yf, order=hm.HM_ORDER_TREE)
+        got = to_host(Yf)
+        for i, p in enumerate(parts):
+            T = hm.Tree(p, 64).color()
+            Hi = hm.compress(T, T.kernel_blackbox("log"), tol=1e-6, r=24, seed=seed + i,
+                             prec=prec, uniform=True)
+            Yi = hm.colmajor(T.n, 3)
+            Hi.matvec(to_dev(X[off[i]:off[i + 1]]), Yi, order=hm.HM_ORDER_TREE)
+            want = to_host(Yi)
+            d = np.linalg.norm(got[off[i]:off[i + 1]] - want) / np.linalg.norm(want)
+            assert d <= 1e-10, (prec, i, d)
+
+
+def test_uniform_plan_replays(hm):
+    inst = workloads.config(1, n=3000)
+    T = hm.Tree(inst.points, inst.leaf, inst.tree, inst.adm).color()
+    bb = T.kernel_blackbox("log")
+    He = hm.compress(T, bb, tol=1e-8, r=24, seed=7, uniform=True)
+    X = np.random.default_rng(1).standard_normal((T.n, 3))
+    Y = hm.colmajor(T.n, 3)
+    He.matvec(to_dev(X), Y)
+    want = to_host(Y)
+    P = hm.Plan(T, bb, tol=1e-8, r=24, seed=7, uniform=True)
+    for k in range(3):
+        Z = hm.colmajor(T.n, 5)
+        Z.normal_()
+        W = hm.colmajor(T.n, 5)
+        T.kernel_apply("log", Z, W)
+        torch.cuda.synchronize()
+        P.execute()
+        Y2 = hm.colmajor(T.n, 3)
+        P.hmatrix().matvec(to_dev(X), Y2)
+        assert np.array_equal(to_host(Y2), want), k
+        assert P.hmatrix().stats()["nfloats"] == He.stats()["nfloats"]
