@@ -42,6 +42,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-uniform", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=3)
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--served-requests", type=int, default=80)
@@ -49,7 +50,7 @@ def parse():
                     help="comma-separated offered loads (fractions of the FP64 capacity)")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run this many steps, no extras (for profilers)")
-    ap.add_argument("--profile-workload", default="star", choices=["star", "batched"],
+    ap.add_argument("--profile-workload", default="star", choices=["star", "batched", "uniform"],
                     help="with --profile-steps: which workload the steps run")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="with --profile-steps: add a 1 GiB device copy that calibrates "
@@ -57,10 +58,11 @@ def parse():
     return ap.parse_args()
 
 
-def step(hm, inst, bb_kernel, x, y, prec, tol):
+def step(hm, inst, bb_kernel, x, y, prec, tol, uniform=False):
     T = hm.Tree(inst.points, inst.leaf, inst.tree, inst.adm).color()
     bb = T.kernel_blackbox(bb_kernel)
-    H = hm.compress(T, bb, tol=tol, r=R_COLS, seed=inst.seed, prec=prec, timing=True)
+    H = hm.compress(T, bb, tol=tol, r=R_COLS, seed=inst.seed, prec=prec, timing=True,
+                    uniform=uniform)
     H.matvec(x, y)
     return T, H
 
@@ -93,23 +95,25 @@ def algorithmic_flops(st):
     return st["flops_blackbox"] + st["flops_peel"] + st["flops_qr"] + st["flops_solve"]
 
 
-def run_path(hm, torch, inst, prec, tol, steps, warmup, x, y):
+def run_path(hm, torch, inst, prec, tol, steps, warmup, x, y, uniform=False):
     for _ in range(warmup):
-        step(hm, inst, inst.kernel, x, y, prec, tol)
+        step(hm, inst, inst.kernel, x, y, prec, tol, uniform)
     torch.cuda.synchronize()
     times, flops, bb_ms, bb_flops, launches = [], 0.0, 0.0, 0.0, 0
     H = None
     t_all0 = time.perf_counter()
     for _ in range(steps):
         t0 = time.perf_counter()
-        T, H = step(hm, inst, inst.kernel, x, y, prec, tol)
+        T, H = step(hm, inst, inst.kernel, x, y, prec, tol, uniform)
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t0)
         st = H.stats()
         flops += algorithmic_flops(st)
         bb_ms += st["ms_blackbox"]
         bb_flops += st["flops_blackbox"]
-        launches += sum(1 for c in st["colors"] if c) + 1
+        # one black-box launch per sampled level (two in the uniform format)
+        # and the leaf pass
+        launches += (2 if uniform else 1) * sum(1 for c in st["colors"] if c) + 1
     total = time.perf_counter() - t_all0
     return dict(times=times, total=total, flops=flops, bb_ms=bb_ms, bb_flops=bb_flops,
                 launches=launches, H=H, T=T, stats=st)
@@ -338,7 +342,8 @@ def main():
                 batched_step(hm, insts, hm.HM_PREC_MIXED)
         else:
             for _ in range(args.profile_steps):
-                step(hm, inst, inst.kernel, x, y, hm.HM_PREC_F64, inst.tol)
+                step(hm, inst, inst.kernel, x, y, hm.HM_PREC_F64, inst.tol,
+                     uniform=args.profile_workload == "uniform")
         torch.cuda.synchronize()
         if args.pmc_probe:
             # calibration for the HBM byte counters: one plain device copy of
@@ -427,6 +432,34 @@ def main():
             "rel_err_vs_fp64": float(np.linalg.norm(Ymx - Y64) / np.linalg.norm(Y64)),
             "kapply_tflops": round(rmx["bb_flops"] / (rmx["bb_ms"] / 1e3) / 1e12, 3),
         }
+
+    if not args.no_uniform:
+        # uniform H^1 format on the same workload and tolerance (FP64)
+        run = run_path(hm, torch, inst, hm.HM_PREC_F64, inst.tol, args.steps, args.warmup, x, y,
+                       uniform=True)
+        su = run["stats"]
+        Yd3 = hm.colmajor(n, 4)
+        run["H"].matvec(Xd, Yd3)
+        torch.cuda.synchronize()
+        Yu = Yd3.cpu().numpy()
+        out["uniform"] = {
+            "value": round(run["flops"] / run["total"] / 1e9, 2),
+            "compressions_per_s": round(args.steps / run["total"], 3),
+            "ms_per_step": round(1e3 * run["total"] / args.steps, 3),
+            "p50_ms": round(float(np.percentile(np.array(run["times"]) * 1e3, 50)), 3),
+            "floats_per_dof": round(su["nfloats"] / n, 2),
+            "stage1_colors_per_level": [c for c in su["ucolors"] if c],
+            "cols_A": su["cols_A"],
+            "cols_At": su["cols_At"],
+            "max_rank": su["max_rank"],
+            "saturated": su["saturated"],
+            "rel_err_vs_dense_sampled_rows": float(np.linalg.norm(Yu[rows] - want) /
+                                                   np.linalg.norm(want)),
+            "kapply_tflops": round(run["bb_flops"] / (run["bb_ms"] / 1e3) / 1e12, 3),
+            "stage_ms": {k: round(su[k], 3) for k in ("ms_blackbox", "ms_peel", "ms_qr",
+                                                      "ms_solve", "ms_other", "ms_total")},
+        }
+        _progress("uniform done")
 
     if not args.no_batched:
         out["batched"] = run_batched(hm, torch, args.batched_steps)
