@@ -43,6 +43,7 @@ def parse():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-uniform", action="store_true")
+    ap.add_argument("--no-product", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=3)
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--served-requests", type=int, default=80)
@@ -117,6 +118,53 @@ def run_path(hm, torch, inst, prec, tol, steps, warmup, x, y, uniform=False):
     total = time.perf_counter() - t_all0
     return dict(times=times, total=total, flops=flops, bb_ms=bb_ms, bb_flops=bb_flops,
                 launches=launches, H=H, T=T, stats=st)
+
+
+def run_product(hm, torch, inst, H, steps, warmup):
+    """Compression of the product H H of the headline compressed operator
+    with itself, given only through its applies (two H-matrix applies per
+    black-box call): the black box is fast, so peel, QR and couplings carry
+    the time.  One step = one compression on the existing tree."""
+    T = H.tree
+    bh = H.blackbox(hm.HM_ORDER_TREE)
+    P = hm.product_blackbox(bh, bh)
+
+    def once():
+        return hm.compress(T, P, tol=inst.tol, r=R_COLS, seed=inst.seed + 1, timing=True)
+
+    for _ in range(warmup):
+        once()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    net_flops = net_ms = bb_ms = 0.0
+    for _ in range(steps):
+        HP = once()
+        st = HP.stats()
+        net_flops += st["flops_peel"] + st["flops_qr"] + st["flops_solve"]
+        net_ms += st["ms_total"] - st["ms_blackbox"]
+        bb_ms += st["ms_blackbox"]
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    n = T.n
+    X = hm.colmajor(n, 4)
+    X.copy_(torch.from_numpy(np.random.default_rng(8).standard_normal((n, 4))))
+    Y, Z, W = hm.colmajor(n, 4), hm.colmajor(n, 4), hm.colmajor(n, 4)
+    HP.matvec(X, Y)
+    H.matvec(X, Z)
+    H.matvec(Z, W)
+    torch.cuda.synchronize()
+    err = float(torch.linalg.norm(Y - W) / torch.linalg.norm(W))
+    return {"workload": "product_of_star_curve_operator_with_itself_N%d_tol%g_r%d"
+                        % (n, inst.tol, R_COLS),
+            "compressions_per_s": round(steps / total, 3),
+            "ms_per_step": round(1e3 * total / steps, 3),
+            "blackbox_share": round(bb_ms / (bb_ms + net_ms), 3),
+            "net_gflops": round(net_flops / (net_ms / 1e3) / 1e9, 2),
+            "max_rank": st["max_rank"], "saturated": st["saturated"],
+            "floats_per_dof": round(st["nfloats"] / n, 2),
+            "rel_err_vs_applied_product": err,
+            "stage_ms": {k: round(st[k], 3) for k in ("ms_blackbox", "ms_peel", "ms_qr",
+                                                      "ms_solve", "ms_other", "ms_total")}}
 
 
 def batched_step(hm, insts, prec):
@@ -460,6 +508,10 @@ def main():
                                                       "ms_solve", "ms_other", "ms_total")},
         }
         _progress("uniform done")
+
+    if not args.no_product:
+        out["product"] = run_product(hm, torch, inst, H, args.steps, args.warmup)
+        _progress("product done")
 
     if not args.no_batched:
         out["batched"] = run_batched(hm, torch, args.batched_steps)

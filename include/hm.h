@@ -218,6 +218,26 @@ hm_status hm_kernel_apply(hm_tree *tree, int kernel, int64_t ncols, int dtype, c
 hm_status hm_dense_blackbox(const double *A, int64_t n, int64_t lda, int order, hm_blackbox *out);
 void hm_dense_blackbox_free(hm_blackbox *bb);
 
+/* Black boxes built from compressed operators, for compressing products and
+ * compositions whose factors have fast applies (the operator-multiplication
+ * experiment of the experiments section; any black box with a fast apply
+ * fits the problem statement of the introduction).
+ * hm_hmatrix_blackbox: Y = H X, and Y = H* X for the adjoint (hm_matvec_op).
+ *   FP64 and FP32.  H is borrowed (must outlive every use).  order =
+ *   HM_ORDER_TREE is valid only when the compression runs on the tree H was
+ *   built on (rows in that tree's order); HM_ORDER_ORIGINAL always is.
+ * hm_product_blackbox: Y = A (B X), adjoint Y = B* (A* X), through a
+ *   stream-ordered n x ncols intermediate.  A and B are copied (their ctx
+ *   objects must outlive the product); both must take the same order; the
+ *   product supports the dtypes both support and is symmetric when A and B
+ *   are the same symmetric box.
+ * hm_blackbox_free releases the ctx of a dense, H-matrix or product black
+ * box (not of its factors); it ignores the kernel black box, which belongs
+ * to its tree. */
+hm_status hm_hmatrix_blackbox(const hm_hmatrix *H, int order, hm_blackbox *out);
+hm_status hm_product_blackbox(const hm_blackbox *A, const hm_blackbox *B, hm_blackbox *out);
+void hm_blackbox_free(hm_blackbox *bb);
+
 /* ------------------------------------------------------------------ compression
  * hm_compress: alg:h1_pseudocode.  For each sampled level (coarsest first):
  * draw the colored Gaussian test matrices Omega, Psi (one N x r block per
@@ -313,6 +333,10 @@ void hm_plan_free(hm_plan *plan);
  * rows in `order`.  Enqueued on stream. */
 hm_status hm_matvec(const hm_hmatrix *H, int64_t nrhs, int dtype, const void *X, int64_t ldx,
                     void *Y, int64_t ldy, int order, void *stream);
+/* hm_matvec_op: hm_matvec (trans = 0) or the adjoint Y = H* X (trans = 1:
+ * every admissible block V B* U*, the leaf blocks transposed). */
+hm_status hm_matvec_op(const hm_hmatrix *H, int trans, int64_t nrhs, int dtype, const void *X,
+                       int64_t ldx, void *Y, int64_t ldy, int order, void *stream);
 
 /* Device test matrix of one level and pass (0 = Omega, 1 = Psi, 2 = stage 1
  * of the uniform format, colored by hm_uniform_graph) exactly as hm_compress

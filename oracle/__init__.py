@@ -11,6 +11,7 @@ library never does, and the two share no code.
   the dense kernel black box, compression (alg:h1_pseudocode with the
   per-pair recovery of alg:compress_double_random), hmatvec, error measures.
 * ``uniform.py``: uniform H^1 compression (per-box bases, two stages).
+* ``product.py``: compressed operators and their products as black boxes.
 """
 from .comb import OTree, dsatur, build as build_comb  # noqa: F401
 from .numeric import (  # noqa: F401
@@ -21,3 +22,4 @@ from .numeric import (  # noqa: F401
 from .uniform import (  # noqa: F401
     UniformGraph, uniform_test_matrix, compress_uniform, uniform_floats,
 )
+from .product import HMatrixBlackBox, ProductBlackBox, assemble  # noqa: F401

@@ -41,7 +41,8 @@ EXPORTED = [
     "hm_tree_instances", "hm_autotune_table", "hm_server_create", "hm_server_free",
     "hm_server_submit_compress", "hm_server_submit_matvec", "hm_server_poll", "hm_server_hmatrix",
     "hm_server_release", "hm_server_info", "hm_compress_plan", "hm_plan_execute",
-    "hm_plan_hmatrix", "hm_plan_free", "hm_uniform_graph",
+    "hm_plan_hmatrix", "hm_plan_free", "hm_uniform_graph", "hm_matvec_op",
+    "hm_hmatrix_blackbox", "hm_product_blackbox", "hm_blackbox_free",
 ]
 
 
@@ -138,6 +139,10 @@ def _load():
         "hm_compress": [P, C.POINTER(BlackBox), C.POINTER(Opts), P, pp],
         "hm_hmatrix_free": [P],
         "hm_matvec": [P, I64, I, P, I64, P, I64, I, P],
+        "hm_matvec_op": [P, I, I64, I, P, I64, P, I64, I, P],
+        "hm_hmatrix_blackbox": [P, I, C.POINTER(BlackBox)],
+        "hm_product_blackbox": [C.POINTER(BlackBox), C.POINTER(BlackBox), C.POINTER(BlackBox)],
+        "hm_blackbox_free": [C.POINTER(BlackBox)],
         "hm_test_matrix": [P, I, I, C.c_int32, C.c_uint64, I, P, I64, P],
         "hm_philox4x32_10": [P, I64, C.c_uint32, C.c_uint32, P, P],
         "hm_hmatrix_stats": [P, C.POINTER(Stats)],
@@ -161,7 +166,7 @@ def _load():
         f = getattr(lib, name)
         f.argtypes = args
         if name in ("hm_tree_free", "hm_hmatrix_free", "hm_dense_blackbox_free", "hm_server_free",
-                    "hm_plan_free"):
+                    "hm_plan_free", "hm_blackbox_free"):
             f.restype = None
         else:
             f.restype = C.c_int
@@ -435,6 +440,22 @@ def dense_blackbox(A, order=HM_ORDER_ORIGINAL):
     return bb
 
 
+def _own_ctx(bb):
+    """Release the black box's ctx (hm_blackbox_free) when bb is collected."""
+    import weakref
+    copy = BlackBox(bb.apply, bb.ctx, bb.order, bb.symmetric, bb.dtypes)
+    weakref.finalize(bb, lambda c=copy: _lib.hm_blackbox_free(C.byref(c)))
+
+
+def product_blackbox(A, B):
+    """The black box Y = A (B X) (hm_product_blackbox); keeps A and B alive."""
+    bb = BlackBox()
+    _check(_lib.hm_product_blackbox(C.byref(A), C.byref(B), C.byref(bb)))
+    bb._keep = (A, B)
+    _own_ctx(bb)
+    return bb
+
+
 def philox(ctr, key0, key1, out, stream=None):
     _check(_lib.hm_philox4x32_10(C.c_void_p(ctr.data_ptr()), ctr.numel() // 4, key0, key1,
                                  C.c_void_p(out.data_ptr()), _stream(stream)))
@@ -455,12 +476,22 @@ class HMatrix:
         _check(_lib.hm_hmatrix_stats(self.h, C.byref(s)))
         return s.as_dict()
 
-    def matvec(self, X, Y, order=HM_ORDER_ORIGINAL, stream=None):
+    def matvec(self, X, Y, order=HM_ORDER_ORIGINAL, stream=None, trans=False):
+        """Y = H X, or H* X with trans=True (hm_matvec_op)."""
         px, ldx, nc, dt = _colmajor(X, "X")
         py, ldy, nc2, dt2 = _colmajor(Y, "Y")
         if nc != nc2 or dt != dt2:
             raise ValueError("X and Y shapes/dtypes differ")
-        _check(_lib.hm_matvec(self.h, nc, dt, px, ldx, py, ldy, order, _stream(stream)))
+        _check(_lib.hm_matvec_op(self.h, 1 if trans else 0, nc, dt, px, ldx, py, ldy, order,
+                                 _stream(stream)))
+
+    def blackbox(self, order=HM_ORDER_ORIGINAL):
+        """This operator as a black box (hm_hmatrix_blackbox); keeps self alive."""
+        bb = BlackBox()
+        _check(_lib.hm_hmatrix_blackbox(self.h, order, C.byref(bb)))
+        bb._keep = self
+        _own_ctx(bb)
+        return bb
 
     def export_level(self, level):
         """List of (a, b, U, B, V) in pair order (host float64 arrays)."""

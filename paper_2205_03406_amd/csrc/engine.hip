@@ -280,6 +280,7 @@ struct hm_hmatrix {
   std::vector<int32_t> na, nb;
   std::vector<int64_t> offD;
   hm::DBuf nchunks, nentries;
+  hm::DBuf nchunksT, nentriesT;   // same chunks, entries of the adjoint
   int32_t nnch = 0;
   int64_t max_np = 0;
   Orient oA, oT;
@@ -461,6 +462,92 @@ int64_t tscratch_elems(const hm_hmatrix &H, int64_t ncols) {
   int64_t cap = int64_t(64) << 20;
   int64_t minimum = slots * H.kmax * 64;
   return std::max<int64_t>(std::min(need, cap), std::max<int64_t>(minimum, 64));
+}
+
+// Y = H X or H* X (rows in `order`); stream-ordered scratch.
+void matvec_impl(const hm_hmatrix &H, bool trans, int64_t nrhs, bool f32, const void *X,
+                 int64_t ldx, void *Y, int64_t ldy, int order, hipStream_t s) {
+  const size_t es = f32 ? 4 : 8;
+  const int64_t n = H.n;
+  const int64_t tcap = tscratch_elems(H, nrhs);
+  void *Tb = nullptr, *xt = nullptr, *yt = nullptr;
+  HIP_TRY(hipMallocAsync(&Tb, (size_t)tcap * es, s));
+  const bool orig = order != HM_ORDER_TREE;
+  const void *Xt = X;
+  void *Yt = Y;
+  int64_t ldxt = ldx, ldyt = ldy;
+  if (orig) {
+    HIP_TRY(hipMallocAsync(&xt, (size_t)n * nrhs * es, s));
+    HIP_TRY(hipMallocAsync(&yt, (size_t)n * nrhs * es, s));
+    launch_permute_rows(n, nrhs, H.perm.as<int64_t>(), false, f32, X, ldx, xt, n, s);
+    Xt = xt;
+    Yt = yt;
+    ldxt = ldyt = n;
+    launch_fill(yt, n * nrhs, f32, 0.0, s);
+  } else {
+    for (int64_t c = 0; c < nrhs; ++c) launch_fill((char *)Y + c * ldy * es, n, f32, 0.0, s);
+  }
+  LAUNCH_CHECK();
+  apply_levels(H, H.lv.size(), trans, f32, Xt, ldxt, nrhs, Yt, ldyt, 1.0, Tb, tcap, s);
+  launch_near_apply(H.nnch, (trans ? H.nchunksT : H.nchunks).as<ExpandChunk>(),
+                    (trans ? H.nentriesT : H.nentries).as<NearEntry>(), f32, H.D.p, Xt, ldxt,
+                    nrhs, Yt, ldyt, s);
+  LAUNCH_CHECK();
+  if (orig) {
+    launch_permute_rows(n, nrhs, H.perm.as<int64_t>(), true, f32, yt, n, Y, ldy, s);
+    LAUNCH_CHECK();
+    HIP_TRY(hipFreeAsync(xt, s));
+    HIP_TRY(hipFreeAsync(yt, s));
+  }
+  HIP_TRY(hipFreeAsync(Tb, s));
+}
+
+// ------------------------------------------------------------------ operator black boxes
+// A compressed operator as a black box (hm_matvec / its adjoint).
+struct HMatrixBB {
+  const hm_hmatrix *H;
+  int order;
+};
+
+int hmatrix_bb_apply(void *ctx, int transpose, int64_t n, int64_t ncols, int dtype, const void *X,
+                     int64_t ldx, void *Y, int64_t ldy, void *stream) {
+  HMatrixBB *b = (HMatrixBB *)ctx;
+  if (!b || !b->H || n != b->H->n || (dtype != HM_F64 && dtype != HM_F32)) return 1;
+  if (ncols <= 0) return 0;
+  try {
+    matvec_impl(*b->H, transpose != 0, ncols, dtype == HM_F32, X, ldx, Y, ldy, b->order,
+                (hipStream_t)stream);
+  } catch (const Error &e) {
+    set_error(e.msg);
+    return 2;
+  }
+  return 0;
+}
+
+// The product A B of two black boxes: Y = A (B X), Y = B* (A* X) for the
+// adjoint, through a stream-ordered intermediate.
+struct ProductBB {
+  hm_blackbox A, B;
+};
+
+int product_bb_apply(void *ctx, int transpose, int64_t n, int64_t ncols, int dtype, const void *X,
+                     int64_t ldx, void *Y, int64_t ldy, void *stream) {
+  ProductBB *p = (ProductBB *)ctx;
+  if (!p) return 1;
+  if (ncols <= 0) return 0;
+  hipStream_t s = (hipStream_t)stream;
+  const size_t es = dtype == HM_F32 ? 4 : 8;
+  void *tmp = nullptr;
+  if (hipMallocAsync(&tmp, (size_t)n * ncols * es, s) != hipSuccess) {
+    (void)hipGetLastError();
+    return 3;
+  }
+  const hm_blackbox &first = transpose ? p->A : p->B;
+  const hm_blackbox &second = transpose ? p->B : p->A;
+  int rc = first.apply(first.ctx, transpose, n, ncols, dtype, X, ldx, tmp, n, stream);
+  if (rc == 0) rc = second.apply(second.ctx, transpose, n, ncols, dtype, tmp, n, Y, ldy, stream);
+  (void)hipFreeAsync(tmp, s);
+  return rc;
 }
 
 struct Events {
@@ -699,6 +786,28 @@ hm_status Compression::setup(hipStream_t s) {
     upload(H->nchunks, ch, s);
     upload(H->nentries, en, s);
     H->nnch = (int32_t)ch.size();
+    // the adjoint's near field: block (a, b) of H* is D_(b,a)^T (neighbor
+    // pairs come in both orders)
+    std::unordered_map<int64_t, size_t> qidx;
+    qidx.reserve(GL.pa.size() * 2);
+    for (size_t q = 0; q < GL.pa.size(); ++q) qidx[(int64_t)GL.pa[q] * LL.nbox() + GL.pb[q]] = q;
+    std::vector<NearEntry> enT;
+    for (ExpandChunk &c : ch) {
+      const int32_t first = (int32_t)enT.size();
+      for (int32_t e = c.first; e < c.last; ++e) {
+        const size_t q = (size_t)(std::upper_bound(H->offD.begin(), H->offD.end(), en[e].dslot) -
+                                  H->offD.begin()) - 1;  // the entry's pair (a, b)
+        const int a = GL.pa[q], b = GL.pb[q];
+        const auto it = qidx.find((int64_t)b * LL.nbox() + a);
+        if (it == qidx.end()) throw Error{HM_E_STATE, "neighbor pairs are not symmetric"};
+        const int32_t mb = (int32_t)T.box_size(T.L(), b);
+        enT.push_back(NearEntry{H->offD[it->second], LL.start[b], mb, mb, en[e].off, 1});
+      }
+      c.first = first;
+      c.last = (int32_t)enT.size();
+    }
+    upload(H->nchunksT, ch, s);
+    upload(H->nentriesT, enT, s);
     H->D.alloc(szD * 8);
     HIP_TRY(hipStreamSynchronize(s));
   }
@@ -1353,7 +1462,7 @@ hm_status compress_impl(Tree &T, const hm_blackbox &bb, const hm_compress_opts &
 int64_t hmatrix_device_bytes(const hm_hmatrix *H) {
   int64_t b = H->perm.bytes + H->U.bytes + H->V.bytes + H->W.bytes + H->B.bytes + H->Vf.bytes +
               H->Wf.bytes + H->D.bytes + H->ranks.bytes + H->nchunks.bytes + H->nentries.bytes +
-              H->UB.bytes + H->VB.bytes + H->brank.bytes;
+              H->nchunksT.bytes + H->nentriesT.bytes + H->UB.bytes + H->VB.bytes + H->brank.bytes;
   for (const hm_hmatrix::Orient *O : {&H->oA, &H->oT}) {
     b += O->items.bytes + O->ppairs.bytes;
     for (const DBuf &d : O->chunks) b += d.bytes;
@@ -1778,6 +1887,48 @@ hm_status hm_dense_blackbox(const double *A, int64_t n, int64_t lda, int order, 
   return HM_OK;
 }
 
+hm_status hm_hmatrix_blackbox(const hm_hmatrix *H, int order, hm_blackbox *out) {
+  if (!H || !out) return fail(HM_E_ARG, "hm_hmatrix_blackbox: bad argument");
+  HMatrixBB *b = new (std::nothrow) HMatrixBB{H, order == HM_ORDER_TREE ? HM_ORDER_TREE
+                                                                       : HM_ORDER_ORIGINAL};
+  if (!b) return fail(HM_E_NOMEM, "host allocation failed");
+  out->apply = hmatrix_bb_apply;
+  out->ctx = b;
+  out->order = b->order;
+  out->symmetric = 0;
+  out->dtypes = (1 << HM_F64) | (1 << HM_F32);
+  return HM_OK;
+}
+
+hm_status hm_product_blackbox(const hm_blackbox *A, const hm_blackbox *B, hm_blackbox *out) {
+  if (!A || !B || !out || !A->apply || !B->apply)
+    return fail(HM_E_ARG, "hm_product_blackbox: bad argument");
+  if (A->order != B->order) return fail(HM_E_ARG, "the two black boxes take different orders");
+  if (!(A->dtypes & B->dtypes)) return fail(HM_E_ARG, "the two black boxes share no dtype");
+  ProductBB *p = new (std::nothrow) ProductBB{*A, *B};
+  if (!p) return fail(HM_E_NOMEM, "host allocation failed");
+  out->apply = product_bb_apply;
+  out->ctx = p;
+  out->order = A->order;
+  // (A A)* = A A when A* = A
+  out->symmetric = A->symmetric && B->symmetric && A->apply == B->apply && A->ctx == B->ctx;
+  out->dtypes = A->dtypes & B->dtypes;
+  return HM_OK;
+}
+
+void hm_blackbox_free(hm_blackbox *bb) {
+  if (!bb) return;
+  if (bb->apply == hmatrix_bb_apply)
+    delete (HMatrixBB *)bb->ctx;
+  else if (bb->apply == product_bb_apply)
+    delete (ProductBB *)bb->ctx;
+  else if (bb->apply == dense_bb_apply)
+    delete (DenseBB *)bb->ctx;
+  else
+    return;  // the kernel black box belongs to its tree
+  bb->ctx = nullptr;
+}
+
 void hm_dense_blackbox_free(hm_blackbox *bb) {
   if (bb && bb->apply == dense_bb_apply) {
     delete (DenseBB *)bb->ctx;
@@ -1884,45 +2035,17 @@ void hm_plan_free(hm_plan *plan) { delete plan; }
 
 hm_status hm_matvec(const hm_hmatrix *H, int64_t nrhs, int dtype, const void *X, int64_t ldx,
                     void *Y, int64_t ldy, int order, void *stream) {
+  return hm_matvec_op(H, 0, nrhs, dtype, X, ldx, Y, ldy, order, stream);
+}
+
+hm_status hm_matvec_op(const hm_hmatrix *H, int trans, int64_t nrhs, int dtype, const void *X,
+                       int64_t ldx, void *Y, int64_t ldy, int order, void *stream) {
   API_BEGIN
   if (!H || !X || !Y || nrhs < 0 || ldx < H->n || ldy < H->n)
     return fail(HM_E_ARG, "hm_matvec: bad argument");
   if (dtype != HM_F64 && dtype != HM_F32) return fail(HM_E_ARG, "bad dtype");
   if (nrhs == 0) return HM_OK;
-  hipStream_t s = (hipStream_t)stream;
-  const bool f32 = dtype == HM_F32;
-  const size_t es = f32 ? 4 : 8;
-  const int64_t n = H->n;
-  const int64_t tcap = tscratch_elems(*H, nrhs);
-  void *Tb = nullptr, *xt = nullptr, *yt = nullptr;
-  HIP_TRY(hipMallocAsync(&Tb, (size_t)tcap * es, s));
-  const bool orig = order != HM_ORDER_TREE;
-  const void *Xt = X;
-  void *Yt = Y;
-  int64_t ldxt = ldx, ldyt = ldy;
-  if (orig) {
-    HIP_TRY(hipMallocAsync(&xt, (size_t)n * nrhs * es, s));
-    HIP_TRY(hipMallocAsync(&yt, (size_t)n * nrhs * es, s));
-    launch_permute_rows(n, nrhs, H->perm.as<int64_t>(), false, f32, X, ldx, xt, n, s);
-    Xt = xt;
-    Yt = yt;
-    ldxt = ldyt = n;
-    launch_fill(yt, n * nrhs, f32, 0.0, s);
-  } else {
-    for (int64_t c = 0; c < nrhs; ++c) launch_fill((char *)Y + c * ldy * es, n, f32, 0.0, s);
-  }
-  LAUNCH_CHECK();
-  apply_levels(*H, H->lv.size(), false, f32, Xt, ldxt, nrhs, Yt, ldyt, 1.0, Tb, tcap, s);
-  launch_near_apply(H->nnch, H->nchunks.as<ExpandChunk>(), H->nentries.as<NearEntry>(), f32,
-                    H->D.p, Xt, ldxt, nrhs, Yt, ldyt, s);
-  LAUNCH_CHECK();
-  if (orig) {
-    launch_permute_rows(n, nrhs, H->perm.as<int64_t>(), true, f32, yt, n, Y, ldy, s);
-    LAUNCH_CHECK();
-    HIP_TRY(hipFreeAsync(xt, s));
-    HIP_TRY(hipFreeAsync(yt, s));
-  }
-  HIP_TRY(hipFreeAsync(Tb, s));
+  matvec_impl(*H, trans != 0, nrhs, dtype == HM_F32, X, ldx, Y, ldy, order, (hipStream_t)stream);
   return HM_OK;
   API_END
 }

@@ -268,7 +268,9 @@ near_kernel(const ExpandChunk *__restrict__ chunks, const NearEntry *__restrict_
       for (int e = tid; e < KC * 64; e += 256) {
         const int rr = e % 64, kk = e / 64;
         Ds[kk][rr] = (rr < ch.nrows && k0 + kk < en.mb)
-                         ? (T)Dp[(int64_t)(k0 + kk) * en.ma + en.off + rr] : (T)0;
+                         ? (T)(en.trans ? Dp[(int64_t)(en.off + rr) * en.ma + k0 + kk]
+                                        : Dp[(int64_t)(k0 + kk) * en.ma + en.off + rr])
+                         : (T)0;
         const int kt = e % KC, cc = e / KC;
         const int64_t gc = c0 + cc;
         Xs[kt][cc] = (k0 + kt < en.mb && gc < ncols) ? X[gc * ldx + en.xrow0 + k0 + kt] : (T)0;

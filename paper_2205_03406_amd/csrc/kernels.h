@@ -120,9 +120,10 @@ struct NearEntry {
   int64_t dslot;   // element offset of D_q (ld = ma)
   int64_t xrow0;   // first row of the column box in X
   int32_t ma;      // leading dimension
-  int32_t mb;      // columns of D_q
-  int32_t off;     // row offset of the chunk inside D_q
-  int32_t pad;
+  int32_t mb;      // columns of the operator block
+  int32_t off;     // row offset of the chunk inside the operator block
+  int32_t trans;   // 1: the operator block is D_q^T (the adjoint's near field);
+                   // element (i, k) = D_q[(off + i) * ma + k]
 };
 void launch_near_apply(int32_t nchunks, const ExpandChunk *chunks, const NearEntry *entries,
                        bool f32, const void *D, const void *X, int64_t ldx, int64_t ncols,
