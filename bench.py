@@ -51,7 +51,7 @@ def parse():
                     help="comma-separated offered loads (fractions of the FP64 capacity)")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run this many steps, no extras (for profilers)")
-    ap.add_argument("--profile-workload", default="star", choices=["star", "batched", "uniform"],
+    ap.add_argument("--profile-workload", default="star", choices=["star", "batched", "uniform", "product"],
                     help="with --profile-steps: which workload the steps run")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="with --profile-steps: add a 1 GiB device copy that calibrates "
@@ -388,6 +388,9 @@ def main():
             insts = workloads.batched_ellipses()
             for _ in range(args.profile_steps):
                 batched_step(hm, insts, hm.HM_PREC_MIXED)
+        elif args.profile_workload == "product":
+            _, H = step(hm, inst, inst.kernel, x, y, hm.HM_PREC_F64, inst.tol)
+            run_product(hm, torch, inst, H, args.profile_steps, 0)
         else:
             for _ in range(args.profile_steps):
                 step(hm, inst, inst.kernel, x, y, hm.HM_PREC_F64, inst.tol,

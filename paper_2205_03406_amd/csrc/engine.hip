@@ -260,6 +260,8 @@ struct hm_hmatrix {
   // Apply plan of one orientation (A, or A* with the roles of U and V swapped)
   struct Orient {
     hm::DBuf items, ppairs;              // projection work, levels in order
+    hm::DBuf red;                        // pairs split over several segments
+    std::vector<int32_t> red_upto;       // [li]: reduce items of the first li levels
     std::vector<int32_t> items_upto;     // [li]: items of the first li levels
     std::vector<int32_t> slots_upto;     // [li]: partial slots of the first li levels
     std::vector<hm::DBuf> chunks, entries;  // [li]: expand plan of the first li levels
@@ -282,6 +284,7 @@ struct hm_hmatrix {
   hm::DBuf nchunks, nentries;
   hm::DBuf nchunksT, nentriesT;   // same chunks, entries of the adjoint
   int32_t nnch = 0;
+  bool near_covers = false;        // the near chunks cover every row once
   int64_t max_np = 0;
   Orient oA, oT;
   // uniform format: the shared bases, one per box with a non-empty
@@ -318,6 +321,8 @@ void build_apply_plans(hm_hmatrix &H, const Tree &T, hipStream_t s) {
     hm_hmatrix::Orient &O = trans ? H.oT : H.oA;
     std::vector<ProjItem> items;
     std::vector<ProjPair> pps;
+    std::vector<ReduceItem> reds;
+    O.red_upto.assign(1, 0);
     O.items_upto.assign(1, 0);
     O.slots_upto.assign(1, 0);
     std::vector<std::vector<int32_t>> slot_base(nlv), nseg(nlv);
@@ -333,8 +338,10 @@ void build_apply_plans(hm_hmatrix &H, const Tree &T, hipStream_t s) {
         const int64_t m = Lev.start[colbox[p] + 1] - Lev.start[colbox[p]];
         nseg[li][p] = (int32_t)((m + kSeg - 1) / kSeg);
         slot_base[li][p] = slots;
+        if (nseg[li][p] > 1) reds.push_back(ReduceItem{slots, nseg[li][p]});
         slots += nseg[li][p];
       }
+      O.red_upto.push_back((int32_t)reds.size());
       std::vector<int64_t> order(L.np);
       for (int64_t p = 0; p < L.np; ++p) order[p] = p;
       std::stable_sort(order.begin(), order.end(),
@@ -361,6 +368,7 @@ void build_apply_plans(hm_hmatrix &H, const Tree &T, hipStream_t s) {
     }
     upload(O.items, items, s);
     upload(O.ppairs, pps, s);
+    upload(O.red, reds, s);
     HIP_TRY(hipStreamSynchronize(s));
     // expand plans
     O.chunks.clear();
@@ -445,10 +453,12 @@ void apply_levels(const hm_hmatrix &H, size_t li_end, bool trans, bool f32, cons
     launch_lr_project(nitems, O.items.as<ProjItem>(), O.ppairs.as<ProjPair>(), H.kmax, tstride,
                       H.ranks.as<int32_t>(), f32, Rp, (const char *)X + c0 * ldx * es, ldx, w, T,
                       s);
+    // partials of pairs split over segments summed once, not per output chunk
+    launch_lr_reduce(O.red_upto[li_end], O.red.as<ReduceItem>(), tstride, tstride, f32, T, s);
     LAUNCH_CHECK();
     launch_lr_expand(O.nch[li_end], O.chunks[li_end].as<ExpandChunk>(),
                      O.entries[li_end].as<ExpandEntry>(), H.kmax, tstride, H.ranks.as<int32_t>(),
-                     f32, Lp, T, w, sign, (char *)Y + c0 * ldy * es, ldy, s);
+                     f32, Lp, T, w, sign, (char *)Y + c0 * ldy * es, ldy, true, s);
     LAUNCH_CHECK();
   }
 }
@@ -483,15 +493,14 @@ void matvec_impl(const hm_hmatrix &H, bool trans, int64_t nrhs, bool f32, const 
     Xt = xt;
     Yt = yt;
     ldxt = ldyt = n;
-    launch_fill(yt, n * nrhs, f32, 0.0, s);
-  } else {
-    for (int64_t c = 0; c < nrhs; ++c) launch_fill((char *)Y + c * ldy * es, n, f32, 0.0, s);
   }
-  LAUNCH_CHECK();
-  apply_levels(H, H.lv.size(), trans, f32, Xt, ldxt, nrhs, Yt, ldyt, 1.0, Tb, tcap, s);
+  // the near field writes Y first when it covers every row, else Y starts at 0
+  if (!H.near_covers) launch_fill_cols(Yt, n, nrhs, ldyt, f32, s);
   launch_near_apply(H.nnch, (trans ? H.nchunksT : H.nchunks).as<ExpandChunk>(),
                     (trans ? H.nentriesT : H.nentries).as<NearEntry>(), f32, H.D.p, Xt, ldxt,
-                    nrhs, Yt, ldyt, s);
+                    nrhs, Yt, ldyt, H.near_covers, s);
+  LAUNCH_CHECK();
+  apply_levels(H, H.lv.size(), trans, f32, Xt, ldxt, nrhs, Yt, ldyt, 1.0, Tb, tcap, s);
   LAUNCH_CHECK();
   if (orig) {
     launch_permute_rows(n, nrhs, H.perm.as<int64_t>(), true, f32, yt, n, Y, ldy, s);
@@ -759,8 +768,12 @@ hm_status Compression::setup(hipStream_t s) {
   const Graph &GL = T.leaf_graph();
   const Level &LL = T.lev[T.L()];
   {
+    // the near kernel takes at most kNearCols columns per entry: wider
+    // neighbor boxes are split into column pieces
+    constexpr int32_t kNearCols = 128;
     std::vector<ExpandChunk> ch;
     std::vector<NearEntry> en;
+    std::vector<size_t> eq;  // pair of each entry
     H->na = GL.pa;
     H->nb = GL.pb;
     for (size_t q = 0; q < GL.pa.size(); ++q) {
@@ -775,9 +788,14 @@ hm_status Compression::setup(hipStream_t s) {
       const int32_t m = (int32_t)T.box_size(T.L(), a);
       for (int32_t off = 0; off < m; off += 64) {
         ExpandChunk c{LL.start[a] + off, std::min<int32_t>(64, m - off), (int32_t)en.size(), 0, 0};
-        for (size_t q = i; q < j; ++q)
-          en.push_back(NearEntry{H->offD[q], LL.start[GL.pb[q]], m,
-                                 (int32_t)T.box_size(T.L(), GL.pb[q]), off, 0});
+        for (size_t q = i; q < j; ++q) {
+          const int32_t mb = (int32_t)T.box_size(T.L(), GL.pb[q]);
+          for (int32_t k0 = 0; k0 < mb; k0 += kNearCols) {
+            en.push_back(NearEntry{H->offD[q] + (int64_t)k0 * m, LL.start[GL.pb[q]] + k0, m,
+                                   std::min(kNearCols, mb - k0), off, 0});
+            eq.push_back(q);
+          }
+        }
         c.last = (int32_t)en.size();
         ch.push_back(c);
       }
@@ -795,19 +813,25 @@ hm_status Compression::setup(hipStream_t s) {
     for (ExpandChunk &c : ch) {
       const int32_t first = (int32_t)enT.size();
       for (int32_t e = c.first; e < c.last; ++e) {
-        const size_t q = (size_t)(std::upper_bound(H->offD.begin(), H->offD.end(), en[e].dslot) -
-                                  H->offD.begin()) - 1;  // the entry's pair (a, b)
+        const size_t q = eq[e];  // the entry's pair (a, b)
         const int a = GL.pa[q], b = GL.pb[q];
         const auto it = qidx.find((int64_t)b * LL.nbox() + a);
         if (it == qidx.end()) throw Error{HM_E_STATE, "neighbor pairs are not symmetric"};
         const int32_t mb = (int32_t)T.box_size(T.L(), b);
-        enT.push_back(NearEntry{H->offD[it->second], LL.start[b], mb, mb, en[e].off, 1});
+        const int32_t k0 = (int32_t)(en[e].xrow0 - LL.start[b]);  // column piece of b
+        enT.push_back(NearEntry{H->offD[it->second] + k0, LL.start[b] + k0, mb, en[e].mb,
+                                en[e].off, 1});
       }
       c.first = first;
       c.last = (int32_t)enT.size();
     }
     upload(H->nchunksT, ch, s);
     upload(H->nentriesT, enT, s);
+    // every row has a near block (a box is its own neighbor): the near
+    // field can open an apply by writing Y
+    int64_t covered = 0;
+    for (const ExpandChunk &c : ch) covered += c.nrows;
+    H->near_covers = covered == T.n;
     H->D.alloc(szD * 8);
     HIP_TRY(hipStreamSynchronize(s));
   }
@@ -1464,7 +1488,7 @@ int64_t hmatrix_device_bytes(const hm_hmatrix *H) {
               H->Wf.bytes + H->D.bytes + H->ranks.bytes + H->nchunks.bytes + H->nentries.bytes +
               H->nchunksT.bytes + H->nentriesT.bytes + H->UB.bytes + H->VB.bytes + H->brank.bytes;
   for (const hm_hmatrix::Orient *O : {&H->oA, &H->oT}) {
-    b += O->items.bytes + O->ppairs.bytes;
+    b += O->items.bytes + O->ppairs.bytes + O->red.bytes;
     for (const DBuf &d : O->chunks) b += d.bytes;
     for (const DBuf &d : O->entries) b += d.bytes;
   }

@@ -9,6 +9,8 @@
 // result is deterministic (no atomics) and each Y element is written once
 // per call.  Tiles are 64 rows x 64 columns, K staged through LDS in chunks
 // of 32; FP64 (or FP32 in the mixed path) on the vector ALUs.
+#include <algorithm>
+
 #include "device_common.h"
 #include "kernels.h"
 
@@ -140,7 +142,7 @@ __global__ void __launch_bounds__(256, 2)
 lr_expand_kernel(const ExpandChunk *__restrict__ chunks, const ExpandEntry *__restrict__ entries,
                  int32_t kmax, int64_t tstride, const int32_t *__restrict__ ranks,
                  const T *__restrict__ L, const T *__restrict__ Tin, int64_t ncols, T sign,
-                 T *__restrict__ Y, int64_t ldy) {
+                 T *__restrict__ Y, int64_t ldy, int reduced) {
   __shared__ T As[KC][64 + 1];   // [depth][row]
   __shared__ T Bs[KC][TC + 1];   // [depth][col]
   __shared__ int64_t e_l[EMAX];
@@ -164,7 +166,7 @@ lr_expand_kernel(const ExpandChunk *__restrict__ chunks, const ExpandEntry *__re
       e_mq[tid] = en.mq;
       e_k[tid] = ranks[en.kidx];
       e_ts[tid] = en.tslot;
-      e_ns[tid] = en.nseg;
+      e_ns[tid] = reduced ? 1 : en.nseg;  // reduced: the partials are summed in the first slot
     }
     __syncthreads();
     if (tid == 0) {
@@ -247,51 +249,139 @@ lr_expand_kernel(const ExpandChunk *__restrict__ chunks, const ExpandEntry *__re
   }
 }
 
+// Near field on the matrix cores, laid out like the expansion: the entries
+// of a chunk (neighbor boxes, at most 128 columns each) form one contraction
+// of depth sum_e mb_e, staged 32 deep through LDS; a depth -> (entry,
+// column) table is built per pass of up to NEMAX entries.  overwrite: the
+// chunk's rows of Y are written instead of accumulated (the first term of an
+// apply, so Y needs no clearing).
+constexpr int NEMAX = 32;
+constexpr int NKTAB = NEMAX * 128;
+
 template <typename T>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, 2)
 near_kernel(const ExpandChunk *__restrict__ chunks, const NearEntry *__restrict__ entries,
             const double *__restrict__ D, const T *__restrict__ X, int64_t ldx, int64_t ncols,
-            T *__restrict__ Y, int64_t ldy) {
-  __shared__ T Ds[KC][64 + 1];   // [kk][row]
-  __shared__ T Xs[KC][TC + 1];   // [kk][col]
+            T *__restrict__ Y, int64_t ldy, int overwrite) {
+  __shared__ T As[KC][64 + 1];   // [depth][row]
+  __shared__ T Bs[KC][TC + 1];   // [depth][col]
+  __shared__ int64_t e_d[NEMAX], e_x[NEMAX];
+  __shared__ int32_t e_ma[NEMAX], e_mb[NEMAX], e_tr[NEMAX], e_ko[NEMAX + 1];
+  __shared__ int16_t d_e[NKTAB];
+  __shared__ uint8_t d_k[NKTAB];
+  typedef typename Acc<T>::type acc_t;
   const ExpandChunk ch = chunks[blockIdx.x];
   const int64_t c0 = (int64_t)blockIdx.y * TC;
-  const int tid = threadIdx.x;
-  const int col = tid & 63, g = tid >> 6;
-  T acc[16];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  acc_t acc[4];
 #pragma unroll
-  for (int q = 0; q < 16; ++q) acc[q] = 0;
-  for (int ei = ch.first; ei < ch.last; ++ei) {
-    const NearEntry en = entries[ei];
-    const double *Dp = D + en.dslot;
-    for (int k0 = 0; k0 < en.mb; k0 += KC) {
-      for (int e = tid; e < KC * 64; e += 256) {
-        const int rr = e % 64, kk = e / 64;
-        Ds[kk][rr] = (rr < ch.nrows && k0 + kk < en.mb)
-                         ? (T)(en.trans ? Dp[(int64_t)(en.off + rr) * en.ma + k0 + kk]
-                                        : Dp[(int64_t)(k0 + kk) * en.ma + en.off + rr])
-                         : (T)0;
-        const int kt = e % KC, cc = e / KC;
-        const int64_t gc = c0 + cc;
-        Xs[kt][cc] = (k0 + kt < en.mb && gc < ncols) ? X[gc * ldx + en.xrow0 + k0 + kt] : (T)0;
+  for (int t = 0; t < 4; ++t) acc[t] = (acc_t){0, 0, 0, 0};
+
+  for (int e0 = ch.first; e0 < ch.last; e0 += NEMAX) {
+    const int ne = min(NEMAX, ch.last - e0);
+    __syncthreads();
+    if (tid < ne) {
+      const NearEntry en = entries[e0 + tid];
+      // element (row i, column k) of the block: D[e_d + k ma + i], or
+      // D[e_d + i ma + k] for a transposed entry
+      e_d[tid] = en.dslot + (en.trans ? (int64_t)en.off * en.ma : (int64_t)en.off);
+      e_x[tid] = en.xrow0;
+      e_ma[tid] = en.ma;
+      e_mb[tid] = en.mb;
+      e_tr[tid] = en.trans;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int a = 0;
+      for (int i = 0; i < ne; ++i) {
+        e_ko[i] = a;
+        a += e_mb[i];
+      }
+      e_ko[ne] = a;
+    }
+    __syncthreads();
+    if (tid < ne)
+      for (int kk = 0; kk < e_mb[tid]; ++kk) {
+        d_e[e_ko[tid] + kk] = (int16_t)tid;
+        d_k[e_ko[tid] + kk] = (uint8_t)kk;
+      }
+    __syncthreads();
+    const int ktot = e_ko[ne];
+    T av[8], bv[8];
+    auto fetch = [&](int k0) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int e = tid + 256 * q;
+        {
+          const int rr = e % 64, kk = e / 64;   // D (row, depth)
+          const int d = k0 + kk;
+          T v = 0;
+          if (d < ktot && rr < ch.nrows) {
+            const int j = d_e[d];
+            const int k = d_k[d];
+            v = (T)(e_tr[j] ? D[e_d[j] + (int64_t)rr * e_ma[j] + k]
+                            : D[e_d[j] + (int64_t)k * e_ma[j] + rr]);
+          }
+          av[q] = v;
+        }
+        {
+          const int kt = e % KC, cc = e / KC;   // X (depth, column)
+          const int d = k0 + kt;
+          const int64_t gc = c0 + cc;
+          T v = 0;
+          if (d < ktot && gc < ncols) v = X[gc * ldx + e_x[d_e[d]] + d_k[d]];
+          bv[q] = v;
+        }
+      }
+    };
+    if (ktot > 0) fetch(0);
+    for (int k0 = 0; k0 < ktot; k0 += KC) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int e = tid + 256 * q;
+        As[e / 64][e % 64] = av[q];
+        Bs[e % KC][e / KC] = bv[q];
       }
       __syncthreads();
-#pragma unroll 4
-      for (int kk = 0; kk < KC; ++kk) {
-        const T xv = Xs[kk][col];
+      if (k0 + KC < ktot) fetch(k0 + KC);
 #pragma unroll
-        for (int q = 0; q < 16; ++q) acc[q] += Ds[kk][g + 4 * q] * xv;
+      for (int ks = 0; ks < KC; ks += 4) {
+        const T a = As[ks + (lane >> 4)][16 * wave + (lane & 15)];
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          Acc<T>::step(a, Bs[ks + (lane >> 4)][16 * t + (lane & 15)], acc[t]);
       }
       __syncthreads();
     }
   }
-  const int64_t gc = c0 + col;
-  if (gc < ncols) {
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int rr = g + 4 * q;
-      if (rr < ch.nrows) Y[gc * ldy + ch.row0 + rr] += acc[q];
+  for (int t = 0; t < 4; ++t) {
+    const int64_t gc = c0 + 16 * t + (lane & 15);
+    if (gc >= ncols) continue;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int rr = 16 * wave + Acc<T>::row(i, lane);
+      if (rr < ch.nrows) {
+        T *y = Y + gc * ldy + ch.row0 + rr;
+        *y = overwrite ? acc[t][i] : *y + acc[t][i];
+      }
     }
+  }
+}
+
+// Partial projections of a pair split over several row segments, summed
+// into the first segment's slot: T[s0] = T[s0] + T[s0 + 1] + ... (in order).
+template <typename T>
+__global__ void __launch_bounds__(256)
+lr_reduce_kernel(const ReduceItem *__restrict__ items, int64_t tstride, int64_t elems,
+                 T *__restrict__ Tb) {
+  const ReduceItem it = items[blockIdx.y];
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < elems;
+       e += (int64_t)gridDim.x * 256) {
+    T *p = Tb + (int64_t)it.slot * tstride + e;
+    T v = p[0];
+    for (int sg = 1; sg < it.nseg; ++sg) v += p[(int64_t)sg * tstride];
+    p[0] = v;
   }
 }
 
@@ -366,30 +456,40 @@ void launch_lr_project(int32_t nitems, const ProjItem *items, const ProjPair *pa
 void launch_lr_expand(int32_t nchunks, const ExpandChunk *chunks, const ExpandEntry *entries,
                       int32_t kmax, int64_t tstride, const int32_t *ranks, bool f32,
                       const void *L, const void *T, int64_t ncols, double sign, void *Y,
-                      int64_t ldy, hipStream_t s) {
+                      int64_t ldy, bool reduced, hipStream_t s) {
   if (nchunks <= 0 || ncols <= 0) return;
   dim3 g(nchunks, col_tiles(ncols));
   if (f32)
     lr_expand_kernel<float><<<g, 256, 0, s>>>(chunks, entries, kmax, tstride, ranks,
                                               (const float *)L, (const float *)T, ncols,
-                                              (float)sign, (float *)Y, ldy);
+                                              (float)sign, (float *)Y, ldy, reduced ? 1 : 0);
   else
     lr_expand_kernel<double><<<g, 256, 0, s>>>(chunks, entries, kmax, tstride, ranks,
                                                (const double *)L, (const double *)T, ncols, sign,
-                                               (double *)Y, ldy);
+                                               (double *)Y, ldy, reduced ? 1 : 0);
+}
+
+void launch_lr_reduce(int32_t nitems, const ReduceItem *items, int64_t tstride, int64_t elems,
+                      bool f32, void *T, hipStream_t s) {
+  if (nitems <= 0 || elems <= 0) return;
+  dim3 g((unsigned)std::min<int64_t>((elems + 255) / 256, 64), (unsigned)nitems);
+  if (f32)
+    lr_reduce_kernel<float><<<g, 256, 0, s>>>(items, tstride, elems, (float *)T);
+  else
+    lr_reduce_kernel<double><<<g, 256, 0, s>>>(items, tstride, elems, (double *)T);
 }
 
 void launch_near_apply(int32_t nchunks, const ExpandChunk *chunks, const NearEntry *entries,
                        bool f32, const void *D, const void *X, int64_t ldx, int64_t ncols,
-                       void *Y, int64_t ldy, hipStream_t s) {
+                       void *Y, int64_t ldy, bool overwrite, hipStream_t s) {
   if (nchunks <= 0 || ncols <= 0) return;
   dim3 g(nchunks, col_tiles(ncols));
   if (f32)
     near_kernel<float><<<g, 256, 0, s>>>(chunks, entries, (const double *)D, (const float *)X, ldx,
-                                         ncols, (float *)Y, ldy);
+                                         ncols, (float *)Y, ldy, overwrite ? 1 : 0);
   else
     near_kernel<double><<<g, 256, 0, s>>>(chunks, entries, (const double *)D, (const double *)X,
-                                          ldx, ncols, (double *)Y, ldy);
+                                          ldx, ncols, (double *)Y, ldy, overwrite ? 1 : 0);
 }
 
 void launch_dense_gemm(int64_t n, const double *A, int64_t lda, bool trans, int64_t ncols,

@@ -183,6 +183,15 @@ void launch_fill(void *p, int64_t count, bool f32, double value, hipStream_t s) 
     fill_kernel<double><<<(unsigned)blocks, 256, 0, s>>>((double *)p, count, value);
 }
 
+void launch_fill_cols(void *p, int64_t n, int64_t ncols, int64_t ld, bool f32, hipStream_t s) {
+  if (n <= 0 || ncols <= 0) return;
+  dim3 g = grid_rows(n, ncols);
+  if (f32)
+    zero_cols<float><<<g, 256, 0, s>>>(n, 0, ncols, (float *)p, ld);
+  else
+    zero_cols<double><<<g, 256, 0, s>>>(n, 0, ncols, (double *)p, ld);
+}
+
 void launch_leaf_identity(int64_t n, int32_t nitems, const int32_t *item_box,
                           const int32_t *item_color, const int64_t *box_start, int32_t m,
                           bool f32, void *out, int64_t ld, int64_t ncols_pad, hipStream_t s) {

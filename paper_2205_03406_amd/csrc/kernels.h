@@ -21,6 +21,8 @@ void launch_leaf_identity(int64_t n, int32_t nitems, const int32_t *item_box,
                           const int32_t *item_color, const int64_t *box_start, int32_t m,
                           bool f32, void *out, int64_t ld, int64_t ncols_pad, hipStream_t s);
 void launch_fill(void *p, int64_t count, bool f32, double value, hipStream_t s);
+// zeros in an n x ncols column-major block (leading dimension ld), one launch
+void launch_fill_cols(void *p, int64_t n, int64_t ncols, int64_t ld, bool f32, hipStream_t s);
 // Row permutation of a column-major block: dst[i, :] = src[idx[i], :] (gather)
 // or dst[idx[i], :] = src[i, :] (scatter).
 void launch_permute_rows(int64_t n, int64_t ncols, const int64_t *idx, bool scatter, bool f32,
@@ -111,23 +113,33 @@ struct ExpandEntry {
 void launch_lr_project(int32_t nitems, const ProjItem *items, const ProjPair *pairs, int32_t kmax,
                        int64_t tstride, const int32_t *ranks, bool f32, const void *R,
                        const void *X, int64_t ldx, int64_t ncols, void *T, hipStream_t s);
+// reduced: every entry's partials were already summed into its first slot
+// (launch_lr_reduce), so only that slot is read.
 void launch_lr_expand(int32_t nchunks, const ExpandChunk *chunks, const ExpandEntry *entries,
                       int32_t kmax, int64_t tstride, const int32_t *ranks, bool f32,
                       const void *L, const void *T, int64_t ncols, double sign, void *Y,
-                      int64_t ldy, hipStream_t s);
+                      int64_t ldy, bool reduced, hipStream_t s);
+// T[slot] += T[slot + 1] + ... + T[slot + nseg - 1] (elems values per slot,
+// slot s at T + s * tstride), one item per pair split over several segments.
+struct ReduceItem {
+  int32_t slot, nseg;
+};
+void launch_lr_reduce(int32_t nitems, const ReduceItem *items, int64_t tstride, int64_t elems,
+                      bool f32, void *T, hipStream_t s);
 // Near field: Y[rows] += sum D_q(off: off+nrows, 0:mb) X[b0 : b0+mb, :]
 struct NearEntry {
   int64_t dslot;   // element offset of D_q (ld = ma)
   int64_t xrow0;   // first row of the column box in X
   int32_t ma;      // leading dimension
-  int32_t mb;      // columns of the operator block
+  int32_t mb;      // columns of the operator block (at most 128)
   int32_t off;     // row offset of the chunk inside the operator block
   int32_t trans;   // 1: the operator block is D_q^T (the adjoint's near field);
                    // element (i, k) = D_q[(off + i) * ma + k]
 };
+// overwrite: Y's chunk rows are set rather than accumulated.
 void launch_near_apply(int32_t nchunks, const ExpandChunk *chunks, const NearEntry *entries,
                        bool f32, const void *D, const void *X, int64_t ldx, int64_t ncols,
-                       void *Y, int64_t ldy, hipStream_t s);
+                       void *Y, int64_t ldy, bool overwrite, hipStream_t s);
 
 // ---- per-pair recovery (k_qr.hip)
 struct QrJob {
