@@ -12,6 +12,7 @@ library never does, and the two share no code.
   per-pair recovery of alg:compress_double_random), hmatvec, error measures.
 * ``uniform.py``: uniform H^1 compression (per-box bases, two stages).
 * ``product.py``: compressed operators and their products as black boxes.
+* ``h2.py``: H^2 compression (nested bases) and its upward / downward apply.
 """
 from .comb import OTree, dsatur, build as build_comb  # noqa: F401
 from .numeric import (  # noqa: F401
@@ -23,3 +24,4 @@ from .uniform import (  # noqa: F401
     UniformGraph, uniform_test_matrix, compress_uniform, uniform_floats,
 )
 from .product import HMatrixBlackBox, ProductBlackBox, assemble  # noqa: F401
+from .h2 import H2Matrix, compress_h2, augment_gaussian, svd_basis  # noqa: F401
