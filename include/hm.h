@@ -278,7 +278,7 @@ typedef struct {
   uint64_t seed;
   int32_t max_retries; /* tolerance mode: recompress with r + 8 (at most 64) while
                           some block reaches the cap, at most this many times */
-  int32_t format;      /* HM_FORMAT_H1, or HM_FORMAT_UNIFORM_H1 (below) */
+  int32_t format;      /* HM_FORMAT_H1, HM_FORMAT_UNIFORM_H1 or HM_FORMAT_H2 (below) */
 } hm_compress_opts;
 #define HM_FLAG_TIMING 1
 #define HM_FLAG_STRICT 2
@@ -301,8 +301,25 @@ typedef struct {
  * The result applies, exports and serves like any H-matrix (the per-pair
  * factors hold copies of the shared bases); hm_stats.nfloats counts each
  * basis once. */
+/* format = HM_FORMAT_H2: H^2 compression (section on H^2 compression,
+ * alg:h2_pseudocode): the uniform stages with three changes.  Every box of
+ * the sampled levels whose far field is not empty (an interaction list, or
+ * a parent with a basis) gets bases, from the SVD of its sample augmented
+ * with its parent's:  U_a = svd(Y(I_a, block) + U_tau(rows of a) S_tau G, k)
+ * (G: k_tau x r Gaussian, counter (first tree row of a, column/2, 2^31 + row
+ * of G, 4*level + 2)), and V_b likewise from the combination of the uniform
+ * form (G: k_tau x kmax, 4*level + 3); singular vectors are signed so that
+ * their largest entry is positive.  After each level, the previous level's
+ * bases become transfers U_a* U_tau(rows of a) (eq:nested_basis), and every
+ * coarser level's bases are rebuilt from the finest ones through the
+ * transfers, so the level-truncated matrix peeled from the next samples
+ * and the final operator are the nested ones.  The sampled levels must be
+ * consecutive (HM_E_ARG otherwise).  hm_stats.nfloats counts the finest
+ * level's bases, the transfers, the couplings and the leaf blocks; the
+ * device copy keeps the implied bases of every level for the applies. */
 #define HM_FORMAT_H1 0
 #define HM_FORMAT_UNIFORM_H1 1
+#define HM_FORMAT_H2 2
 
 hm_status hm_compress(hm_tree *tree, const hm_blackbox *bb, const hm_compress_opts *opts,
                       void *stream, hm_hmatrix **out);

@@ -34,6 +34,7 @@ Readings (listed in the design notes):
   first sampled level to the last one;
 * rank rules as in the uniform compression: U by qr(., k)'s rule (cap
   r - p, saturation) on the singular values, V up to kmax with no cap;
+  singular vectors are signed so that their largest entry is positive;
 * B_ab = Z(I_b, block of (b, a))[:, :k_a]* V_b as in the uniform form;
   A^(l)'s near blocks are not part of the level-truncated product (the
   near field is only known after the leaf pass), so the final line of
@@ -68,6 +69,10 @@ def svd_basis(S, k, tol, cap):
     if kmax == 0:
         return np.zeros((m, 0)), np.zeros(0), False
     U, s, _ = np.linalg.svd(S, full_matrices=False)
+    # sign convention: the entry of largest magnitude of every singular
+    # vector is positive (the first one on ties)
+    idx = np.argmax(np.abs(U), axis=0)
+    U = U * np.where(U[idx, np.arange(U.shape[1])] < 0, -1.0, 1.0)
     if k > 0:
         kk = min(k, kmax)
         return U[:, :kk], s[:kk], False

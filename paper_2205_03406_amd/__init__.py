@@ -26,7 +26,13 @@ HM_TREE_GEOMETRIC, HM_TREE_INDEX_BINARY = 0, 1
 HM_ADM_STRONG, HM_ADM_WEAK = 0, 1
 HM_F64, HM_F32 = 0, 1
 HM_PREC_F64, HM_PREC_MIXED = 0, 1
-HM_FORMAT_H1, HM_FORMAT_UNIFORM_H1 = 0, 1
+HM_FORMAT_H1, HM_FORMAT_UNIFORM_H1, HM_FORMAT_H2 = 0, 1, 2
+
+
+def _format(uniform, h2):
+    if uniform and h2:
+        raise ValueError("choose one of uniform and h2")
+    return HM_FORMAT_H2 if h2 else (HM_FORMAT_UNIFORM_H1 if uniform else HM_FORMAT_H1)
 HM_KERNEL_LOG, HM_KERNEL_INV_R = 0, 1
 HM_ORDER_ORIGINAL, HM_ORDER_TREE = 0, 1
 HM_LIST_NEIGHBOR, HM_LIST_INTERACTION = 0, 1
@@ -382,9 +388,9 @@ class Plan:
     by execute(); hmatrix() borrows the latest result."""
 
     def __init__(self, tree, bb, rank=0, tol=0.0, r=0, p=10, prec=HM_PREC_F64, seed=0,
-                 stream=None, uniform=False):
+                 stream=None, uniform=False, h2=False):
         o = Opts(rank=rank, tol=tol, oversample=p, r=r, prec=prec, flags=0, seed=seed,
-                 max_retries=0, format=HM_FORMAT_UNIFORM_H1 if uniform else HM_FORMAT_H1)
+                 max_retries=0, format=_format(uniform, h2))
         h = C.c_void_p()
         _check(_lib.hm_compress_plan(tree.h, C.byref(bb), C.byref(o), _stream(stream),
                                      C.byref(h)))
@@ -570,12 +576,13 @@ class Server:
         self.close()
 
     def submit_compress(self, points, leaf, kind="geometric", adm="strong", kernel="log", rank=0,
-                        tol=0.0, r=0, p=10, prec=HM_PREC_F64, seed=0, uniform=False):
+                        tol=0.0, r=0, p=10, prec=HM_PREC_F64, seed=0, uniform=False,
+                        h2=False):
         pts = np.ascontiguousarray(points, np.float64)
         if pts.ndim == 1:
             pts = pts.reshape(-1, 1)
         o = Opts(rank=rank, tol=tol, oversample=p, r=r, prec=prec, flags=0, seed=seed,
-                 format=HM_FORMAT_UNIFORM_H1 if uniform else HM_FORMAT_H1)
+                 format=_format(uniform, h2))
         rid = C.c_int64()
         _check(_lib.hm_server_submit_compress(
             self.h, _ptr(pts), pts.shape[0], pts.shape[1], leaf,
@@ -637,12 +644,13 @@ HM_FLAG_TIMING, HM_FLAG_STRICT = 1, 2
 
 
 def compress(tree: Tree, bb: BlackBox, rank=0, tol=0.0, r=0, p=10, prec=HM_PREC_F64, seed=0,
-             timing=False, stream=None, max_retries=0, strict=False, uniform=False) -> HMatrix:
-    """hm_compress; uniform=True selects the uniform H^1 format."""
+             timing=False, stream=None, max_retries=0, strict=False, uniform=False,
+             h2=False) -> HMatrix:
+    """hm_compress; uniform=True selects the uniform H^1 format, h2=True the
+    H^2 format."""
     o = Opts(rank=rank, tol=tol, oversample=p, r=r, prec=prec,
              flags=(HM_FLAG_TIMING if timing else 0) | (HM_FLAG_STRICT if strict else 0),
-             seed=seed, max_retries=max_retries,
-             format=HM_FORMAT_UNIFORM_H1 if uniform else HM_FORMAT_H1)
+             seed=seed, max_retries=max_retries, format=_format(uniform, h2))
     h = C.c_void_p()
     _check(_lib.hm_compress(tree.h, C.byref(bb), C.byref(o), _stream(stream), C.byref(h)))
     return HMatrix(h, tree)

@@ -293,6 +293,9 @@ struct hm_hmatrix {
   // V ranks, level li's vertices from uv0[li]
   int32_t format = HM_FORMAT_H1;
   hm::DBuf UB, VB, brank;
+  // H^2: singular values (kmax per box) and transfers (kmax x kmax per box,
+  // to its parent); UB / VB hold the bases implied by the nesting
+  hm::DBuf SU, SV, TU, TV;
   std::vector<std::vector<int32_t>> ubox;
   std::vector<std::vector<int64_t>> uoff;
   std::vector<int64_t> uv0;
@@ -648,12 +651,18 @@ struct Compression {
     DBuf jv;           // row-basis QR jobs on S
     DBuf uc;           // per-pair coupling jobs
     DBuf kit1, kit2;   // forest kernel-apply items of the two stages
-    int32_t nv = 0, nmix = 0, nkit1 = 0, nkit2 = 0;
+    // H^2: norm jobs of the raw samples (mixed floors), augmentation jobs of
+    // the two stages, transfers and nesting of the previous level into this one
+    DBuf jn, jvn, augu, augv, tr, nest;
+    int32_t nv = 0, nmix = 0, nkit1 = 0, nkit2 = 0, naug = 0, ntr = 0, nnest = 0;
   };
   std::vector<UniformJobs> ujobs_of;
   DBuf Sb, usat;
+  bool h2 = false;  // H^2: uniform stages with augmented SVD bases, nested
   void setup_uniform(hipStream_t s);
   void record_uniform_level(size_t li, hipStream_t s, Events &ev);
+  void setup_h2(hipStream_t s);
+  void record_h2_level(size_t li, hipStream_t s, Events &ev);
   void fp32_copies(size_t li, hipStream_t s);
   int inst_of_row(int64_t row) const {
     if (ni <= 1) return 0;
@@ -708,9 +717,10 @@ hm_status Compression::setup(hipStream_t s) {
   if (mixed && !(bb.dtypes & (1 << HM_F32))) return fail(HM_E_ARG, "black box has no FP32 apply");
   if (!mixed && !(bb.dtypes & (1 << HM_F64))) return fail(HM_E_ARG, "black box has no FP64 apply");
   if (!bb.apply) return fail(HM_E_ARG, "black box without apply");
-  if (o.format != HM_FORMAT_H1 && o.format != HM_FORMAT_UNIFORM_H1)
+  if (o.format != HM_FORMAT_H1 && o.format != HM_FORMAT_UNIFORM_H1 && o.format != HM_FORMAT_H2)
     return fail(HM_E_ARG, "unknown format");
-  uniform = o.format == HM_FORMAT_UNIFORM_H1;
+  uniform = o.format == HM_FORMAT_UNIFORM_H1 || o.format == HM_FORMAT_H2;
+  h2 = o.format == HM_FORMAT_H2;
   kmax = kfix > 0 ? std::min(kfix, r) : r - p;
   es = mixed ? 4 : 8;
   n = T.n;
@@ -888,7 +898,13 @@ hm_status Compression::setup(hipStream_t s) {
   direct = kbb && kbb->tree == &T && ni > 1;
 
   // ---------------- every job list of every level, uploaded once up front
-  if (uniform) setup_uniform(s);
+  if (h2) {
+    // the SVD workspace holds every basis box of a level (at most n rows) x r
+    if ((int64_t)work.bytes < n * r * 8) buf(work, (size_t)n * r * 8, s);
+    setup_h2(s);
+  } else if (uniform) {
+    setup_uniform(s);
+  }
   jobs_of.resize(H->lv.size());
   for (size_t li = 0; !uniform && li < H->lv.size(); ++li) {
     hm_hmatrix::Lv &L = H->lv[li];
@@ -1088,6 +1104,339 @@ void Compression::setup_uniform(hipStream_t s) {
   }
 }
 
+// H^2: bases on every level of the sampled range for each box whose far
+// field is not empty (an interaction list, or a parent with a basis); the
+// parent's long basis augments the samples, transfer matrices nest each
+// level into the next, and after every level the bases of all coarser
+// levels are rebuilt from the finest ones through the transfers, with
+// their pairs' apply factors, so the per-pair apply of the level-truncated
+// matrix is the nested (H^2) one.
+void Compression::setup_h2(hipStream_t s) {
+  H->format = HM_FORMAT_H2;
+  const size_t nlv = H->lv.size();
+  for (size_t li = 1; li < nlv; ++li)
+    if (H->lv[li].level != H->lv[li - 1].level + 1)
+      throw Error{HM_E_ARG, "H2 format: a level between the first and the last sampled level "
+                            "has no admissible pair"};
+  // each instance's last sampled level: its boxes inherit bases only up to
+  // it (a forest carries a shallow instance's leaves further down, and the
+  // instance compressed alone has no bases there)
+  std::vector<int> inst_last(ni, -1);
+  for (size_t li = 0; li < nlv; ++li) {
+    const hm_hmatrix::Lv &L = H->lv[li];
+    for (int64_t q = 0; q < L.np; ++q) {
+      const int i = inst_of_row(T.lev[L.level].start[L.pa[q]]);
+      inst_last[i] = std::max(inst_last[i], L.level);
+    }
+  }
+  int64_t szb = 0;
+  H->ubox.resize(nlv);
+  H->uoff.resize(nlv);
+  H->uv0.resize(nlv);
+  std::vector<std::vector<int32_t>> vid(nlv);
+  for (size_t li = 0; li < nlv; ++li) {
+    const int l = H->lv[li].level;
+    const Level &Lv = T.lev[l];
+    vid[li].assign(Lv.nbox(), -1);
+    H->uv0[li] = H->nvtot;
+    for (int a = 0; a < Lv.nbox(); ++a) {
+      const bool inherit = li > 0 && vid[li - 1][Lv.parent[a]] >= 0 &&
+                           l <= inst_last[inst_of_row(Lv.start[a])];
+      if (Lv.int_ptr[a + 1] > Lv.int_ptr[a] || inherit) {
+        vid[li][a] = (int32_t)H->ubox[li].size();
+        H->ubox[li].push_back(a);
+        H->uoff[li].push_back(szb);
+        szb += T.box_size(l, a) * kmax;
+      }
+    }
+    H->nvtot += (int64_t)H->ubox[li].size();
+  }
+  const int64_t nb = H->nvtot;
+  H->UB.alloc((size_t)std::max<int64_t>(szb, 1) * 8);
+  H->VB.alloc((size_t)std::max<int64_t>(szb, 1) * 8);
+  H->brank.alloc((size_t)std::max<int64_t>(2 * nb, 1) * 4);
+  H->SU.alloc((size_t)std::max<int64_t>(nb * kmax, 1) * 8);
+  H->SV.alloc((size_t)std::max<int64_t>(nb * kmax, 1) * 8);
+  H->TU.alloc((size_t)std::max<int64_t>(nb * kmax * kmax, 1) * 8);
+  H->TV.alloc((size_t)std::max<int64_t>(nb * kmax * kmax, 1) * 8);
+  buf(Sb, (size_t)n * r * 8, s);
+  buf(usat, (size_t)std::max<int64_t>(2 * nb, 1) * 4, s);
+  if (mixed) {
+    const size_t nbl = [&] {
+      size_t x = 1;
+      for (const auto &u : H->ubox) x = std::max(x, u.size());
+      return x;
+    }();
+    buf(floor_u, nbl * 8, s);
+    buf(floor_v, nbl * 8, s);
+  }
+
+  ujobs_of.resize(nlv);
+  for (size_t li = 0; li < nlv; ++li) {
+    const hm_hmatrix::Lv &L = H->lv[li];
+    const int l = L.level;
+    const Graph &G = T.graphs[l], &UG = T.ugraphs[l];
+    const Level &Lv = T.lev[l];
+    const int nbx = Lv.nbox();
+    UniformJobs &J = ujobs_of[li];
+    const std::vector<int32_t> &hb = H->ubox[li];
+    J.nv = (int32_t)hb.size();
+    const int64_t v0 = H->uv0[li];
+    std::vector<int32_t> ucol(nbx, -1);  // stage-1 color of a vertex box
+    for (int64_t v = 0; v < UG.nv(); ++v) ucol[UG.vbox[v]] = UG.color[v];
+    std::vector<uint8_t> act((size_t)nbx * std::max(UG.ncolors, 1), 0);
+    for (int64_t v = 0; v < UG.nv(); ++v)
+      for (int32_t t = Lv.int_ptr[UG.vbox[v]]; t < Lv.int_ptr[UG.vbox[v] + 1]; ++t)
+        act[(size_t)Lv.intl[t] * UG.ncolors + UG.color[v]] = 1;
+    std::vector<QrJob> jn(hb.size()), jvn(hb.size()), jsu(hb.size()), jsv(hb.size());
+    std::vector<AugJob> au, av;
+    int64_t wofs = 0;
+    for (size_t v = 0; v < hb.size(); ++v) {
+      const int a = hb[v];
+      const int32_t m = (int32_t)T.box_size(l, a);
+      const bool vert = ucol[a] >= 0;
+      jn[v] = QrJob{Lv.start[a], vert ? (int64_t)ucol[a] * r : 0, 0, 0, vert ? m : 0, 0};
+      jvn[v] = QrJob{Lv.start[a], 0, 0, 0, vert ? m : 0, 0};
+      jsu[v] = QrJob{Lv.start[a], 0, H->uoff[li][v], wofs, m, 0};
+      jsv[v] = jsu[v];
+      wofs += (int64_t)m * r;
+      const int inst = inst_of_row(Lv.start[a]);
+      const int64_t base = ni > 1 ? T.inst_off[inst] : 0;
+      int32_t pi = -1;
+      int64_t poff = -1, pstart = 0;
+      int32_t pld = 0;
+      if (li > 0) {
+        const int tau = Lv.parent[a];
+        const int32_t tv = vid[li - 1][tau];
+        if (tv >= 0) {
+          pi = (int32_t)(H->uv0[li - 1] + tv);
+          pstart = T.lev[l - 1].start[tau];
+          poff = H->uoff[li - 1][tv] + (Lv.start[a] - pstart);
+          pld = (int32_t)T.box_size(l - 1, tau);
+        }
+      }
+      for (int64_t c0 = 0; c0 < m; c0 += 256) {
+        const int32_t cm = (int32_t)std::min<int64_t>(256, m - c0);
+        au.push_back(AugJob{Lv.start[a] + c0, vert ? (int64_t)ucol[a] * r : -1,
+                            poff >= 0 ? poff + c0 : -1, cm, pld, pi,
+                            (uint32_t)(Lv.start[a] - base), (uint32_t)inst, 0});
+        av.push_back(AugJob{Lv.start[a] + c0, vert ? 0 : -1, poff >= 0 ? poff + c0 : -1, cm, pld,
+                            pi, (uint32_t)(Lv.start[a] - base), (uint32_t)inst, 0});
+      }
+    }
+    std::vector<int32_t> slot((size_t)nbx * std::max(G.ncolors, 1), 0);
+    for (int64_t v = 0; v < G.nv(); ++v) {
+      const int a = G.vbox[v];
+      if (vid[li][a] < 0) throw Error{HM_E_STATE, "pair-graph box without a basis"};
+      slot[(size_t)a * G.ncolors + G.color[v]] = vid[li][a] + 1;
+    }
+    std::unordered_map<int64_t, int64_t> pidx;
+    pidx.reserve(L.np * 2);
+    for (int64_t q = 0; q < L.np; ++q) pidx[(int64_t)L.pa[q] * nbx + L.pb[q]] = q;
+    auto color_of = [&](int a, int b) {
+      return (int64_t)G.color[G.pv[pidx.at((int64_t)a * nbx + b)]];
+    };
+    std::vector<MixJob> mix;
+    std::vector<MixTerm> terms;
+    for (int b : hb) {
+      if (Lv.int_ptr[b + 1] == Lv.int_ptr[b]) continue;
+      const int32_t t0 = (int32_t)terms.size();
+      for (int32_t t = Lv.int_ptr[b]; t < Lv.int_ptr[b + 1]; ++t) {
+        const int a = Lv.intl[t];
+        const int inst = inst_of_row(Lv.start[a]);
+        const int64_t base = ni > 1 ? T.inst_off[inst] : 0;
+        terms.push_back(MixTerm{color_of(b, a) * kmax, (uint32_t)(Lv.start[a] - base),
+                                (uint32_t)inst});
+      }
+      const int32_t t1 = (int32_t)terms.size();
+      const int64_t m = T.box_size(l, b);
+      for (int64_t r0 = 0; r0 < m; r0 += 256)
+        mix.push_back(MixJob{Lv.start[b] + r0, (int32_t)std::min<int64_t>(256, m - r0), t0, t1, 0});
+    }
+    std::vector<UCJob> uc(L.np);
+    for (int64_t q = 0; q < L.np; ++q) {
+      const int a = L.pa[q], b = L.pb[q];
+      uc[q] = UCJob{Lv.start[b], color_of(b, a) * kmax, H->uoff[li][vid[li][a]],
+                    H->uoff[li][vid[li][b]], L.offU[q], L.offV[q], L.offW[q], L.offB[q],
+                    (int32_t)T.box_size(l, a), (int32_t)T.box_size(l, b), vid[li][a], vid[li][b],
+                    (int32_t)(L.g0 + q), (int32_t)(np_total + L.g0 + q)};
+    }
+    // transfers and nesting of the previous level into this one
+    std::vector<TransferJob> tr;
+    std::vector<NestJob> ne;
+    if (li > 0) {
+      for (size_t v = 0; v < hb.size(); ++v) {
+        const int a = hb[v];
+        const int tau = Lv.parent[a];
+        const int32_t tv = vid[li - 1][tau];
+        if (tv < 0) continue;
+        const int64_t ga = v0 + (int64_t)v, gt = H->uv0[li - 1] + tv;
+        const int64_t rowin = Lv.start[a] - T.lev[l - 1].start[tau];
+        const int32_t ma = (int32_t)T.box_size(l, a), mt = (int32_t)T.box_size(l - 1, tau);
+        tr.push_back(TransferJob{H->uoff[li][v], H->uoff[li - 1][tv] + rowin,
+                                 ga * kmax * kmax, ma, mt, (int32_t)ga, (int32_t)gt});
+        for (int64_t c0 = 0; c0 < ma; c0 += 256)
+          ne.push_back(NestJob{H->uoff[li - 1][tv] + rowin + c0, H->uoff[li][v] + c0,
+                               ga * kmax * kmax, (int32_t)std::min<int64_t>(256, ma - c0), mt,
+                               ma, (int32_t)ga, (int32_t)gt, 0});
+      }
+    }
+    if (direct) {
+      std::vector<int32_t> wu(ni, 0);
+      for (int64_t v = 0; v < UG.nv(); ++v) {
+        const int i = inst_of_row(Lv.start[UG.vbox[v]]);
+        wu[i] = std::max(wu[i], UG.color[v] + 1);
+      }
+      for (int32_t &x : wu) x *= r;
+      std::vector<KItem> k1 = forest_items(T, wu);
+      std::vector<int32_t> w2 = inst_colors(l);
+      for (int32_t &x : w2) x *= kmax;
+      std::vector<KItem> k2 = forest_items(T, w2);
+      put(J.kit1, k1, s);
+      put(J.kit2, k2, s);
+      J.nkit1 = (int32_t)k1.size();
+      J.nkit2 = (int32_t)k2.size();
+    }
+    J.nmix = (int32_t)mix.size();
+    J.naug = (int32_t)au.size();
+    J.ntr = (int32_t)tr.size();
+    J.nnest = (int32_t)ne.size();
+    put(J.act, act, s);
+    put(J.ju, jsu, s);
+    put(J.jv, jsv, s);
+    put(J.jn, jn, s);
+    put(J.jvn, jvn, s);
+    put(J.augu, au, s);
+    put(J.augv, av, s);
+    put(J.slot, slot, s);
+    put(J.uoff, H->uoff[li], s);
+    put(J.mix, mix, s);
+    put(J.terms, terms, s);
+    put(J.uc, uc, s);
+    put(J.tr, tr, s);
+    put(J.nest, ne, s);
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+}
+
+void Compression::record_h2_level(size_t li, hipStream_t s, Events &ev) {
+  const DeviceTree &Dv = *D;
+  hm_hmatrix::Lv &L = H->lv[li];
+  const int l = L.level;
+  const Graph &G = T.graphs[l], &UG = T.ugraphs[l];
+  UniformJobs &J = ujobs_of[li];
+  const int64_t v0 = H->uv0[li], nb = H->nvtot;
+  int32_t *rk = H->brank.as<int32_t>();
+  const int64_t c1 = (int64_t)UG.ncolors * r, c1pad = pad16(c1);
+  const int64_t c2 = (int64_t)G.ncolors * kmax, c2pad = pad16(c2);
+  void *X = Xb.p, *Y = Yb.p;
+  auto apply_bb = [&](int trans, int64_t cols, const DBuf &kit, int32_t nkit) {
+    if (direct) {
+      autotune_kapply(KapplyShape{mixed, kbb->kernel, T.dim, cols, n, true, nkit},
+                      [&](int nt, int64_t part) {
+                        launch_kapply_forest(kbb->kernel, T.dim, n, Dv.pts.as<double>(),
+                                             part > 0 ? (int32_t)part : nkit, kit.as<KItem>(),
+                                             cols, -1, nt, mixed, X, n, Y, n, s);
+                      },
+                      s);
+      LAUNCH_CHECK();
+    } else {
+      call_blackbox(bb, bb.symmetric ? 0 : trans, n, cols, mixed, X, n, Y, n, Dv, tmpx, tmpy, s);
+    }
+  };
+  constexpr double kNoiseGamma = 8.0;
+  // ---------------- stage 1: augmented samples, SVD column bases
+  if (UG.nv() > 0) {
+    ev.mark(0);
+    launch_testmat(n, Dv.rowbox[l].as<int32_t>(), J.act.as<uint8_t>(), UG.ncolors, r, l, 2,
+                   o.seed, Dv.inst_off.as<int64_t>(), ni, mixed, X, n, c1pad, s);
+    LAUNCH_CHECK();
+    ev.mark(1);
+    apply_bb(0, c1pad, J.kit1, J.nkit1);
+    cols_A += c1;
+    if (mixed) {
+      launch_block_norms(J.nv, J.jn.as<QrJob>(), r, kNoiseGamma * 0x1p-24 / std::sqrt((double)r),
+                         true, Y, n, floor_u.as<double>(), s);
+      LAUNCH_CHECK();
+    }
+    ev.mark(2);
+    apply_levels(*H, li, false, mixed, X, n, c1pad, Y, n, -1.0, Tb.p, tcap, s);
+    launch_check_finite(n, c1pad, mixed, Y, n, flag.as<int32_t>(), s);
+    LAUNCH_CHECK();
+  }
+  ev.mark(3);
+  launch_h2_sample(J.naug, J.augu.as<AugJob>(), r, l, 2, o.seed, mixed, Y, n, H->UB.as<double>(),
+                   rk, H->SU.as<double>(), kmax, Sb.as<double>(), n, s);
+  launch_svd_basis(J.nv, J.ju.as<QrJob>(), r, kfix, o.tol, kfix > 0 ? kfix : r - p,
+                   mixed ? floor_u.as<double>() : nullptr, Sb.as<double>(), n, work.as<double>(),
+                   H->UB.as<double>(), H->SU.as<double>() + v0 * kmax, kmax, rk + v0,
+                   usat.as<int32_t>() + v0, s);
+  LAUNCH_CHECK();
+  // ---------------- stage 2: Z, combinations, augmented SVD row bases
+  if (G.nv() > 0) {
+    ev.mark(0);
+    launch_basis_testmat(n, Dv.rowbox[l].as<int32_t>(), Dv.start[l].as<int64_t>(),
+                         J.slot.as<int32_t>(), G.ncolors, kmax, H->UB.as<double>(),
+                         J.uoff.as<int64_t>(), rk + v0, mixed, X, n, c2pad, s);
+    LAUNCH_CHECK();
+    ev.mark(1);
+    apply_bb(1, c2pad, J.kit2, J.nkit2);
+    cols_At += c2;
+    if (mixed) {
+      launch_mix_sum(J.nmix, J.mix.as<MixJob>(), J.terms.as<MixTerm>(), kmax, l, o.seed, true, Y,
+                     n, Sb.as<double>(), n, s);
+      launch_block_norms(J.nv, J.jvn.as<QrJob>(), kmax,
+                         kNoiseGamma * 0x1p-24 / std::sqrt((double)kmax), false, Sb.p, n,
+                         floor_v.as<double>(), s);
+      LAUNCH_CHECK();
+    }
+    ev.mark(2);
+    apply_levels(*H, li, true, mixed, X, n, c2pad, Y, n, -1.0, Tb.p, tcap, s);
+    launch_check_finite(n, c2pad, mixed, Y, n, flag.as<int32_t>(), s);
+    LAUNCH_CHECK();
+  }
+  ev.mark(3);
+  launch_mix_sum(J.nmix, J.mix.as<MixJob>(), J.terms.as<MixTerm>(), kmax, l, o.seed, mixed, Y, n,
+                 Sb.as<double>(), n, s);
+  launch_h2_sample(J.naug, J.augv.as<AugJob>(), kmax, l, 3, o.seed, false, Sb.p, n,
+                   H->VB.as<double>(), rk + nb, H->SV.as<double>(), kmax, Sb.as<double>(), n, s);
+  launch_svd_basis(J.nv, J.jv.as<QrJob>(), kmax, kfix, o.tol, kmax,
+                   mixed ? floor_v.as<double>() : nullptr, Sb.as<double>(), n, work.as<double>(),
+                   H->VB.as<double>(), H->SV.as<double>() + v0 * kmax, kmax, rk + nb + v0,
+                   usat.as<int32_t>() + nb + v0, s);
+  LAUNCH_CHECK();
+  ev.mark(4);
+  launch_ucoupling((int32_t)L.np, J.uc.as<UCJob>(), kmax, mixed, Y, n, H->UB.as<double>(),
+                   H->VB.as<double>(), rk + v0, rk + nb + v0, H->U.as<double>(),
+                   H->V.as<double>(), H->B.as<double>(), H->W.as<double>(),
+                   H->ranks.as<int32_t>(), true, s);
+  LAUNCH_CHECK();
+  // ---------------- nest the previous level, rebuild the coarser bases
+  if (li > 0) {
+    const UniformJobs &Jc = J;
+    launch_transfer(Jc.ntr, Jc.tr.as<TransferJob>(), kmax, H->UB.as<double>(), rk,
+                    H->TU.as<double>(), s);
+    launch_transfer(Jc.ntr, Jc.tr.as<TransferJob>(), kmax, H->VB.as<double>(), rk + nb,
+                    H->TV.as<double>(), s);
+    LAUNCH_CHECK();
+    for (size_t lj = li; lj-- > 0;) {
+      // level lj's bases from level lj + 1's through the transfers of lj + 1's boxes
+      const UniformJobs &Jn = ujobs_of[lj + 1];
+      launch_nest(Jn.nnest, Jn.nest.as<NestJob>(), kmax, H->UB.as<double>(), H->TU.as<double>(),
+                  rk, H->UB.as<double>(), s);
+      launch_nest(Jn.nnest, Jn.nest.as<NestJob>(), kmax, H->VB.as<double>(), H->TV.as<double>(),
+                  rk + nb, H->VB.as<double>(), s);
+      const int64_t w0 = H->uv0[lj];
+      launch_ucoupling((int32_t)H->lv[lj].np, ujobs_of[lj].uc.as<UCJob>(), kmax, mixed, Y, n,
+                       H->UB.as<double>(), H->VB.as<double>(), rk + w0, rk + nb + w0,
+                       H->U.as<double>(), H->V.as<double>(), H->B.as<double>(),
+                       H->W.as<double>(), H->ranks.as<int32_t>(), false, s);
+      LAUNCH_CHECK();
+      fp32_copies(lj, s);
+    }
+  }
+}
+
 // One uniform level: stage 1 (column bases), stage 2 (row bases, couplings).
 void Compression::record_uniform_level(size_t li, hipStream_t s, Events &ev) {
   const DeviceTree &Dv = *D;
@@ -1171,7 +1520,7 @@ void Compression::record_uniform_level(size_t li, hipStream_t s, Events &ev) {
   ev.mark(4);
   launch_ucoupling((int32_t)L.np, J.uc.as<UCJob>(), kmax, mixed, Y, n, H->UB.as<double>(),
                    H->VB.as<double>(), urank, vrank, H->U.as<double>(), H->V.as<double>(),
-                   H->B.as<double>(), H->W.as<double>(), H->ranks.as<int32_t>(), s);
+                   H->B.as<double>(), H->W.as<double>(), H->ranks.as<int32_t>(), true, s);
   LAUNCH_CHECK();
 }
 
@@ -1205,7 +1554,10 @@ void Compression::record(hipStream_t s, Events &ev) {
   for (size_t li = 0; li < H->lv.size(); ++li) {
     hm_hmatrix::Lv &L = H->lv[li];
     if (uniform) {
-      record_uniform_level(li, s, ev);
+      if (h2)
+        record_h2_level(li, s, ev);
+      else
+        record_uniform_level(li, s, ev);
       fp32_copies(li, s);
       ev.mark(5);
       continue;
@@ -1390,16 +1742,42 @@ hm_status Compression::finalize(hipStream_t s, Events &ev,
                 4.0 * r * kv * kv + 2.0 * r * r * (ku + kv) + 2.0 * ma * ku * kv;
     }
     if (uniform) {
-      st.format = HM_FORMAT_UNIFORM_H1;
+      st.format = h2 ? HM_FORMAT_H2 : HM_FORMAT_UNIFORM_H1;
       if (L.level < 32) st.ucolors[L.level] = T.ugraphs[L.level].ncolors;
       const int64_t v0 = H->uv0[li];
+      // H^2: basis index of each box of the previous level (transfers), and
+      // the boxes with a basis on the next level below them (a box without
+      // one keeps its long bases)
+      std::vector<int32_t> pv;
+      if (h2 && li > 0) {
+        pv.assign(T.lev[H->lv[li - 1].level].nbox(), -1);
+        for (size_t v = 0; v < H->ubox[li - 1].size(); ++v) pv[H->ubox[li - 1][v]] = (int32_t)v;
+      }
+      std::vector<uint8_t> parent_of_basis(Lv.nbox(), 0);
+      if (h2 && li + 1 < H->lv.size()) {
+        const Level &Ln = T.lev[H->lv[li + 1].level];
+        for (int c : H->ubox[li + 1]) parent_of_basis[Ln.parent[c]] = 1;
+      }
       for (size_t v = 0; v < H->ubox[li].size(); ++v) {
         const int a = H->ubox[li][v];
         const int64_t m = Lv.start[a + 1] - Lv.start[a];
         const int ku = H->h_brank[v0 + v], kv = H->h_brank[H->nvtot + v0 + v];
         st.saturated += husat[v0 + v];
-        nfloats += m * (ku + kv);
-        fqr += qr_flops(m, r, ku) + qr_flops(m, kmax, kv);
+        if (!h2 || !parent_of_basis[a]) nfloats += m * (ku + kv);
+        if (h2 && li > 0 && pv[Lv.parent[a]] >= 0) {
+          const int64_t g = H->uv0[li - 1] + pv[Lv.parent[a]];
+          nfloats += (int64_t)ku * H->h_brank[g] + (int64_t)kv * H->h_brank[H->nvtot + g];
+          // transfers, and the nested bases rebuilt on every coarser level
+          fsolve += 2.0 * m * (ku * H->h_brank[g] + kv * H->h_brank[H->nvtot + g]) *
+                    (1.0 + (double)(H->lv.size() - li));
+        }
+        if (h2) {
+          // QR, Jacobi sweeps (about 10), basis formation; the augmentation
+          fqr += 2.0 * qr_flops(m, r, r) + 20.0 * r * r * r;
+          fsolve += 4.0 * m * kmax * r;
+        } else {
+          fqr += qr_flops(m, r, ku) + qr_flops(m, kmax, kv);
+        }
         // the combination sum_a Z_ba Gamma_a
         fsolve += 2.0 * m * kmax * kmax * (T.lev[L.level].int_ptr[a + 1] - T.lev[L.level].int_ptr[a]);
       }
@@ -1486,7 +1864,8 @@ hm_status compress_impl(Tree &T, const hm_blackbox &bb, const hm_compress_opts &
 int64_t hmatrix_device_bytes(const hm_hmatrix *H) {
   int64_t b = H->perm.bytes + H->U.bytes + H->V.bytes + H->W.bytes + H->B.bytes + H->Vf.bytes +
               H->Wf.bytes + H->D.bytes + H->ranks.bytes + H->nchunks.bytes + H->nentries.bytes +
-              H->nchunksT.bytes + H->nentriesT.bytes + H->UB.bytes + H->VB.bytes + H->brank.bytes;
+              H->nchunksT.bytes + H->nentriesT.bytes + H->UB.bytes + H->VB.bytes + H->brank.bytes +
+              H->SU.bytes + H->SV.bytes + H->TU.bytes + H->TV.bytes;
   for (const hm_hmatrix::Orient *O : {&H->oA, &H->oT}) {
     b += O->items.bytes + O->ppairs.bytes + O->red.bytes;
     for (const DBuf &d : O->chunks) b += d.bytes;
@@ -1538,7 +1917,13 @@ int64_t compress_footprint(const Tree &T, const hm_compress_opts &o) {
                           np * 8 + cmax_np * 16;
   const int64_t plans = 64 * np + 4096;
   int64_t uni = 0;
-  if (o.format == HM_FORMAT_UNIFORM_H1) {
+  if (o.format == HM_FORMAT_H2) {
+    // every box of the sampled range may hold a basis: bases, singular
+    // values, transfers; the augmented sample buffer
+    for (int l = 1; l < T.nlev(); ++l)
+      if (!T.graphs[l].pa.empty()) uni += 2 * n * kmax * 8 + 2 * T.lev[l].nbox() * (kmax + kmax * kmax) * 8;
+    uni += n * r * 8 * 2;
+  } else if (o.format == HM_FORMAT_UNIFORM_H1) {
     // shared bases (each level's boxes cover at most n rows, U and V) and
     // the combination buffer
     for (int l = 1; l < T.nlev(); ++l)

@@ -375,7 +375,7 @@ ucoupling_kernel(const UCJob *__restrict__ jobs, int32_t kmax, const T *__restri
                  int64_t ldz, const double *__restrict__ UB, const double *__restrict__ VB,
                  const int32_t *__restrict__ urank, const int32_t *__restrict__ vrank,
                  double *__restrict__ U, double *__restrict__ V, double *__restrict__ B,
-                 double *__restrict__ Wout, int32_t *__restrict__ ranks) {
+                 double *__restrict__ Wout, int32_t *__restrict__ ranks, int recompute) {
   extern __shared__ double smem[];  // tn_gemm staging, 33 * 2 kmax doubles
   const UCJob job = jobs[blockIdx.x];
   const int ku = urank[job.ua], kv = vrank[job.vb];
@@ -389,11 +389,15 @@ ucoupling_kernel(const UCJob *__restrict__ jobs, int32_t kmax, const T *__restri
   for (int64_t e = tid; e < (int64_t)job.ma * ku; e += 256) U[job.uslot + e] = Ua[e];
   for (int64_t e = tid; e < (int64_t)job.mb * kv; e += 256) V[job.vslot + e] = Vb[e];
   double *Bs = B + job.bslot;
-  for (int e = tid; e < kmax * kmax; e += 256) Bs[e] = 0.0;
-  __syncthreads();
-  if (ku == 0 || kv == 0) return;
-  tn_gemm(job.mb, ku, kv, Z + job.zcol0 * ldz + job.zrow0, ldz, Vb, (int64_t)job.mb, Bs, kmax,
-          smem);
+  if (recompute) {
+    for (int e = tid; e < kmax * kmax; e += 256) Bs[e] = 0.0;
+    __syncthreads();
+    if (ku == 0 || kv == 0) return;
+    tn_gemm(job.mb, ku, kv, Z + job.zcol0 * ldz + job.zrow0, ldz, Vb, (int64_t)job.mb, Bs, kmax,
+            smem);
+  } else if (ku == 0 || kv == 0) {
+    return;
+  }
   double *W = Wout + job.wslot;
   for (int i = tid; i < job.ma; i += 256) {
     for (int c = 0; c < kv; ++c) {
@@ -404,20 +408,253 @@ ucoupling_kernel(const UCJob *__restrict__ jobs, int32_t kmax, const T *__restri
   }
 }
 
+// ------------------------------------------------------------------ SVD bases
+// Left singular vectors of a sample block S (m x c, c <= 64) in FP64:
+// Householder QR of S in the workspace (no pivoting), one-sided Jacobi
+// (Hestenes) on the columns of R in LDS until no pair is rotated, singular
+// values = the column norms, sorted descending; U = Q [R V / sigma ; 0]
+// truncated to the rank (fixed, or the values above max(tol sigma_0,
+// floor), at most cap), each column signed so that its largest entry is
+// positive (the first on ties).  Singular values go to sigma (kmax per job).
+__global__ void __launch_bounds__(256)
+svd_basis_kernel(const QrJob *__restrict__ jobs, int32_t c, int32_t rank_fixed, double tol,
+                 int32_t cap, const double *__restrict__ floor_abs, const double *__restrict__ S,
+                 int64_t lds, double *__restrict__ Wk, double *__restrict__ U,
+                 double *__restrict__ sigma, int32_t kmax, int32_t *__restrict__ ranks,
+                 int32_t *__restrict__ sat) {
+  __shared__ double Rs[64][65];  // [column][row]
+  __shared__ double tau[64];
+  __shared__ double sg[64];
+  __shared__ int ord[64];
+  __shared__ double bc[2];
+  __shared__ int flag, kk_s, sat_s;
+  const QrJob job = jobs[blockIdx.x];
+  const int m = job.m;
+  const int kq = m < c ? m : c;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double *W = Wk + job.wslot;  // m x c, ld = m
+  for (int j = wave; j < c; j += 4)
+    for (int i = lane; i < m; i += 64)
+      W[(int64_t)j * m + i] = S[(job.col0 + j) * lds + job.row0 + i];
+  __syncthreads();
+  // Householder QR: R in the upper triangle, reflector tails below it
+  for (int j = 0; j < kq; ++j) {
+    double *x = W + (int64_t)j * m;
+    if (wave == 0) {
+      double s2 = 0.0;
+      for (int i = j + lane; i < m; i += 64) s2 += x[i] * x[i];
+      s2 = wave_sum(s2);
+      if (lane == 0) {
+        const double nrm = sqrt(s2);
+        const double alpha = x[j];
+        if (nrm > 0.0) {
+          const double beta = alpha >= 0.0 ? -nrm : nrm;
+          tau[j] = (beta - alpha) / beta;
+          bc[0] = 1.0 / (alpha - beta);
+          x[j] = beta;
+        } else {
+          tau[j] = 0.0;
+          bc[0] = 0.0;
+        }
+      }
+    }
+    __syncthreads();
+    const double sc = bc[0];
+    for (int i = j + 1 + tid; i < m; i += 256) x[i] *= sc;
+    __syncthreads();
+    const double tj = tau[j];
+    for (int cc = j + 1 + wave; cc < c; cc += 4) {
+      double *y = W + (int64_t)cc * m;
+      double w = 0.0;
+      for (int i = j + 1 + lane; i < m; i += 64) w += x[i] * y[i];
+      w = wave_sum(w) + y[j];
+      const double f = tj * w;
+      for (int i = j + 1 + lane; i < m; i += 64) y[i] -= f * x[i];
+      if (lane == 0) y[j] -= f;
+    }
+    __syncthreads();
+  }
+  // R (kq x c, upper trapezoidal) into LDS, zero elsewhere
+  for (int e = tid; e < 64 * 64; e += 256) {
+    const int i = e % 64, j = e / 64;
+    Rs[j][i] = (j < c && i < kq && i <= j) ? W[(int64_t)j * m + i] : 0.0;
+  }
+  __syncthreads();
+  // one-sided Jacobi over round-robin pairings, 8 threads per pair
+  const int ce = c + (c & 1);
+  const int pk = tid >> 3, l8 = tid & 7;
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    if (tid == 0) flag = 0;
+    __syncthreads();
+    for (int rr = 0; rr < ce - 1; ++rr) {
+      if (pk < ce / 2) {
+        const int p = (rr + pk) % (ce - 1);
+        const int q = pk == 0 ? ce - 1 : (rr - pk + ce - 1) % (ce - 1);
+        if (p < c && q < c) {
+          double al = 0.0, be = 0.0, ga = 0.0;
+          for (int i = l8; i < kq; i += 8) {
+            const double u = Rs[p][i], v = Rs[q][i];
+            al += u * u;
+            be += v * v;
+            ga += u * v;
+          }
+#pragma unroll
+          for (int off = 4; off > 0; off >>= 1) {
+            al += __shfl_xor(al, off, 8);
+            be += __shfl_xor(be, off, 8);
+            ga += __shfl_xor(ga, off, 8);
+          }
+          if (ga != 0.0 && fabs(ga) > 1e-15 * sqrt(al * be)) {
+            const double zeta = (be - al) / (2.0 * ga);
+            const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+            const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+            for (int i = l8; i < kq; i += 8) {
+              const double u = Rs[p][i], v = Rs[q][i];
+              Rs[p][i] = cs * u - sn * v;
+              Rs[q][i] = sn * u + cs * v;
+            }
+            if (l8 == 0) flag = 1;
+          }
+        }
+      }
+      __syncthreads();
+    }
+    const int again = flag;
+    __syncthreads();
+    if (again == 0) break;
+  }
+  if (tid < c) {
+    double s2 = 0.0;
+    for (int i = 0; i < kq; ++i) s2 += Rs[tid][i] * Rs[tid][i];
+    sg[tid] = sqrt(s2);
+  }
+  __syncthreads();
+  if (tid < c) {
+    int rk = 0;
+    for (int i = 0; i < c; ++i) rk += (sg[i] > sg[tid] || (sg[i] == sg[tid] && i < tid)) ? 1 : 0;
+    ord[rk] = tid;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    const double s0 = sg[ord[0]];
+    int kk, st = 0;
+    if (!(s0 > 0.0)) {
+      kk = 0;
+    } else if (rank_fixed > 0) {
+      kk = rank_fixed < kq ? rank_fixed : kq;
+    } else {
+      const double thr = fmax(tol * s0, floor_abs ? floor_abs[blockIdx.x] : 0.0);
+      int cnt = 0;
+      while (cnt < kq && sg[ord[cnt]] > thr) ++cnt;
+      st = cnt > cap ? 1 : 0;
+      kk = cnt < cap ? cnt : cap;
+    }
+    kk_s = kk;
+    sat_s = st;
+  }
+  __syncthreads();
+  const int kk = kk_s;
+  // U = Q [R V / sigma; 0]: the left singular vectors of R, then the reflectors
+  double *Uo = U + job.uslot;
+  for (int j = wave; j < kk; j += 4) {
+    const int col = ord[j];
+    const double inv = 1.0 / sg[col];
+    for (int i = lane; i < m; i += 64) Uo[(int64_t)j * m + i] = i < kq ? Rs[col][i] * inv : 0.0;
+  }
+  __syncthreads();
+  for (int j = kq - 1; j >= 0; --j) {
+    const double *x = W + (int64_t)j * m;
+    const double tj = tau[j];
+    for (int cc = wave; cc < kk; cc += 4) {
+      double *y = Uo + (int64_t)cc * m;
+      double w = 0.0;
+      for (int i = j + 1 + lane; i < m; i += 64) w += x[i] * y[i];
+      w = wave_sum(w) + y[j];
+      const double f = tj * w;
+      for (int i = j + 1 + lane; i < m; i += 64) y[i] -= f * x[i];
+      if (lane == 0) y[j] -= f;
+    }
+    __syncthreads();
+  }
+  // sign: the largest entry of every column positive (first on ties)
+  for (int cc = wave; cc < kk; cc += 4) {
+    double *y = Uo + (int64_t)cc * m;
+    double best = -1.0;
+    int bi = 0;
+    for (int i = lane; i < m; i += 64) {
+      const double a = fabs(y[i]);
+      if (a > best) {
+        best = a;
+        bi = i;
+      }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ob = __shfl_xor(best, off, 64);
+      const int oi = __shfl_xor(bi, off, 64);
+      if (ob > best || (ob == best && oi < bi)) {
+        best = ob;
+        bi = oi;
+      }
+    }
+    if (y[bi] < 0.0)
+      for (int i = lane; i < m; i += 64) y[i] = -y[i];
+  }
+  if (tid < kmax) sigma[(int64_t)blockIdx.x * kmax + tid] = tid < kk ? sg[ord[tid]] : 0.0;
+  if (tid == 0) {
+    ranks[blockIdx.x] = kk;
+    sat[blockIdx.x] = sat_s;
+  }
+}
+
+// Transfer (short basis) of one child a of tau: out (k_a x k_tau, ld kmax)
+// = U_a* U_tau(rows of a, :).
+__global__ void __launch_bounds__(256)
+transfer_kernel(const TransferJob *__restrict__ jobs, int32_t kmax, const double *__restrict__ UB,
+                const int32_t *__restrict__ rank, double *__restrict__ out) {
+  extern __shared__ double smem[];
+  const TransferJob job = jobs[blockIdx.x];
+  const int kc = rank[job.cidx], kp = rank[job.pidx];
+  double *o = out + job.out_off;
+  for (int e = threadIdx.x; e < kmax * kmax; e += 256) o[e] = 0.0;
+  __syncthreads();
+  if (kc == 0 || kp == 0) return;
+  tn_gemm(job.mc, kc, kp, UB + job.child_off, (int64_t)job.mc, UB + job.par_off,
+          (int64_t)job.ldp, o, kmax, smem);
+}
+
 }  // namespace
 
 void launch_ucoupling(int32_t njobs, const UCJob *jobs, int32_t kmax, bool f32, const void *Z,
                       int64_t ldz, const double *UB, const double *VB, const int32_t *urank,
                       const int32_t *vrank, double *U, double *V, double *B, double *W,
-                      int32_t *ranks, hipStream_t s) {
+                      int32_t *ranks, bool recompute, hipStream_t s) {
   if (njobs <= 0) return;
   const size_t sh = sizeof(double) * (33 * 2 * (size_t)kmax);
   if (f32)
     ucoupling_kernel<float><<<njobs, 256, sh, s>>>(jobs, kmax, (const float *)Z, ldz, UB, VB,
-                                                   urank, vrank, U, V, B, W, ranks);
+                                                   urank, vrank, U, V, B, W, ranks,
+                                                   recompute ? 1 : 0);
   else
     ucoupling_kernel<double><<<njobs, 256, sh, s>>>(jobs, kmax, (const double *)Z, ldz, UB, VB,
-                                                    urank, vrank, U, V, B, W, ranks);
+                                                    urank, vrank, U, V, B, W, ranks,
+                                                    recompute ? 1 : 0);
+}
+
+void launch_svd_basis(int32_t njobs, const QrJob *jobs, int32_t c, int32_t rank_fixed, double tol,
+                      int32_t cap, const double *floor_abs, const double *S, int64_t lds,
+                      double *Wk, double *U, double *sigma, int32_t kmax, int32_t *ranks,
+                      int32_t *sat, hipStream_t s) {
+  if (njobs <= 0 || c <= 0 || c > 64 || kmax > 64) return;
+  svd_basis_kernel<<<njobs, 256, 0, s>>>(jobs, c, rank_fixed, tol, cap, floor_abs, S, lds, Wk, U,
+                                         sigma, kmax, ranks, sat);
+}
+
+void launch_transfer(int32_t njobs, const TransferJob *jobs, int32_t kmax, const double *UB,
+                     const int32_t *rank, double *out, hipStream_t s) {
+  if (njobs <= 0) return;
+  const size_t sh = sizeof(double) * (33 * 2 * (size_t)kmax);
+  transfer_kernel<<<njobs, 256, sh, s>>>(jobs, kmax, UB, rank, out);
 }
 
 void launch_pivqr(int32_t njobs, const QrJob *jobs, int32_t r, int32_t rank_fixed, double tol,

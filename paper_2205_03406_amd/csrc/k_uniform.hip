@@ -1,7 +1,9 @@
-// Uniform H^1 kernels (section on uniform H^1 compression): the stage-2
-// test matrix assembled from the stage-1 column bases, and the randomized
-// combination of a box's sample blocks whose basis is the box's row basis.
-// Both are HBM-bound and coalesced along the column-major row index.
+// Uniform H^1 and H^2 kernels (sections on uniform H^1 and on H^2
+// compression): the stage-2 test matrix assembled from the stage-1 column
+// bases, the randomized combination of a box's sample blocks whose basis is
+// the box's row basis, the parent augmentation of H^2 samples and the
+// nesting of bases through transfer matrices.  All are row-parallel (one
+// row per thread, coalesced along the column-major row index).
 #include "device_common.h"
 #include "kernels.h"
 
@@ -78,7 +80,109 @@ mix_sum_kernel(const MixJob *__restrict__ jobs, const MixTerm *__restrict__ term
   }
 }
 
+// Augmented sample of one chunk of a box (one row per thread, ncols FP64
+// accumulators); the parent term's G, scaled by the parent's singular
+// values, is drawn into LDS by the whole workgroup.
+template <typename T>
+__global__ void __launch_bounds__(256)
+h2_sample_kernel(const AugJob *__restrict__ jobs, int32_t ncols, int32_t level, int32_t pass,
+                 uint64_t seed, const T *__restrict__ src, int64_t lds,
+                 const double *__restrict__ UBp, const int32_t *__restrict__ prank,
+                 const double *__restrict__ psigma, int32_t kmax, double *__restrict__ dst,
+                 int64_t ldd) {
+  __shared__ double G[64 * 64];
+  const AugJob job = jobs[blockIdx.x];
+  const int tid = threadIdx.x;
+  const int kp = job.par_off >= 0 ? prank[job.par_idx] : 0;
+  const int npair = (ncols + 1) / 2;
+  const uint64_t key = seed + (uint64_t)job.inst;
+  for (int e = tid; e < kp * npair; e += 256) {
+    const int i = e / npair, jj = e % npair;
+    dev::U4 ctr{job.grow, (uint32_t)jj, 0x80000000u + (uint32_t)i, (uint32_t)(4 * level + pass)};
+    double z0, z1;
+    dev::normal_pair(dev::philox10(ctr, (uint32_t)key, (uint32_t)(key >> 32)), z0, z1);
+    const double sgm = psigma[(int64_t)job.par_idx * kmax + i];
+    G[i * 64 + 2 * jj] = sgm * z0;
+    if (2 * jj + 1 < ncols) G[i * 64 + 2 * jj + 1] = sgm * z1;
+  }
+  __syncthreads();
+  if (tid >= job.m) return;
+  double acc[64];
+#pragma unroll
+  for (int j = 0; j < 64; ++j) acc[j] = 0.0;
+  if (job.src_col0 >= 0) {
+    const T *sr = src + job.src_col0 * lds + job.row0 + tid;
+#pragma unroll
+    for (int j = 0; j < 64; ++j)
+      if (j < ncols) acc[j] = (double)sr[(int64_t)j * lds];
+  }
+  if (kp > 0) {
+    const double *pr = UBp + job.par_off + tid;
+    for (int i = 0; i < kp; ++i) {
+      const double u = pr[(int64_t)i * job.par_ld];
+#pragma unroll
+      for (int j = 0; j < 64; ++j)
+        if (j < ncols) acc[j] += u * G[i * 64 + j];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 64; ++j)
+    if (j < ncols) dst[(int64_t)j * ldd + job.row0 + tid] = acc[j];
+}
+
+// One chunk of nested rows: out(row, 0:kp) = U_a(row, 0:kc) Tr (one row per thread).
+__global__ void __launch_bounds__(256)
+nest_kernel(const NestJob *__restrict__ jobs, int32_t kmax, const double *__restrict__ UBin,
+            const double *__restrict__ Tr, const int32_t *__restrict__ rank,
+            double *__restrict__ UBout) {
+  __shared__ double Ts[64 * 64];
+  const NestJob job = jobs[blockIdx.x];
+  const int tid = threadIdx.x;
+  const int kc = rank[job.cidx], kp = rank[job.pidx];
+  for (int e = tid; e < kc * kp; e += 256) {
+    const int i = e % kc, j = e / kc;
+    Ts[i * 64 + j] = Tr[job.t_off + (int64_t)j * kmax + i];
+  }
+  __syncthreads();
+  if (tid >= job.m) return;
+  double acc[64];
+#pragma unroll
+  for (int j = 0; j < 64; ++j) acc[j] = 0.0;
+  const double *ur = UBin + job.in_off + tid;
+  for (int i = 0; i < kc; ++i) {
+    const double u = ur[(int64_t)i * job.ldi];
+#pragma unroll
+    for (int j = 0; j < 64; ++j)
+      if (j < kp) acc[j] += u * Ts[i * 64 + j];
+  }
+  double *o = UBout + job.out_off + tid;
+#pragma unroll
+  for (int j = 0; j < 64; ++j)
+    if (j < kp) o[(int64_t)j * job.ldo] = acc[j];
+}
+
 }  // namespace
+
+void launch_h2_sample(int32_t njobs, const AugJob *jobs, int32_t ncols, int32_t level,
+                      int32_t pass, uint64_t seed, bool src_f32, const void *src, int64_t lds,
+                      const double *UBp, const int32_t *prank, const double *psigma,
+                      int32_t kmax, double *dst, int64_t ldd, hipStream_t s) {
+  if (njobs <= 0 || ncols <= 0 || ncols > 64 || kmax > 64) return;
+  if (src_f32)
+    h2_sample_kernel<float><<<njobs, 256, 0, s>>>(jobs, ncols, level, pass, seed,
+                                                  (const float *)src, lds, UBp, prank, psigma,
+                                                  kmax, dst, ldd);
+  else
+    h2_sample_kernel<double><<<njobs, 256, 0, s>>>(jobs, ncols, level, pass, seed,
+                                                   (const double *)src, lds, UBp, prank, psigma,
+                                                   kmax, dst, ldd);
+}
+
+void launch_nest(int32_t njobs, const NestJob *jobs, int32_t kmax, const double *UBin,
+                 const double *Tr, const int32_t *rank, double *UBout, hipStream_t s) {
+  if (njobs <= 0 || kmax <= 0 || kmax > 64) return;
+  nest_kernel<<<njobs, 256, 0, s>>>(jobs, kmax, UBin, Tr, rank, UBout);
+}
 
 void launch_basis_testmat(int64_t n, const int32_t *rowbox, const int64_t *box_start,
                           const int32_t *slot, int32_t ncolors, int32_t kmax, const double *UB,

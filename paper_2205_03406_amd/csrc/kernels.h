@@ -216,9 +216,61 @@ struct UCJob {
   int32_t ua, vb;              // basis indexes into urank / vrank
   int32_t pu, pv;              // rank slots of the pair
 };
+// recompute = false: keep the stored B (bases replaced by nested ones:
+// copies and W = U_a B only).
 void launch_ucoupling(int32_t njobs, const UCJob *jobs, int32_t kmax, bool f32, const void *Z,
                       int64_t ldz, const double *UB, const double *VB, const int32_t *urank,
                       const int32_t *vrank, double *U, double *V, double *B, double *W,
-                      int32_t *ranks, hipStream_t s);
+                      int32_t *ranks, bool recompute, hipStream_t s);
+
+// ---- H^2 (k_qr.hip, k_uniform.hip)
+// Left singular vectors of each job's sample S(row0 : row0+m, col0 : col0+c)
+// (FP64, c <= 64) into U + uslot (m x k, ld m), k by the fixed rank or by
+// max(tol sigma_0, floor_abs[job]) capped at cap (sat[job] = 1 when more
+// values exceed it); the job's singular values into sigma + job * kmax.
+// Workspace Wk + wslot: m x c.
+void launch_svd_basis(int32_t njobs, const QrJob *jobs, int32_t c, int32_t rank_fixed, double tol,
+                      int32_t cap, const double *floor_abs, const double *S, int64_t lds,
+                      double *Wk, double *U, double *sigma, int32_t kmax, int32_t *ranks,
+                      int32_t *sat, hipStream_t s);
+struct TransferJob {
+  int64_t child_off;   // U_a in UB (mc x k_a, ld mc)
+  int64_t par_off;     // first row of a inside U_tau in UB (ld ldp)
+  int64_t out_off;     // transfer slot (kmax x kmax, ld kmax)
+  int32_t mc, ldp;
+  int32_t cidx, pidx;  // rank indexes of a and tau
+};
+void launch_transfer(int32_t njobs, const TransferJob *jobs, int32_t kmax, const double *UB,
+                     const int32_t *rank, double *out, hipStream_t s);
+// Augmented samples, one job per chunk (<= 256 rows) of a box:
+// dst(rows, 0:ncols) = src(rows, src_col0 : src_col0+ncols) (or 0 when
+// src_col0 < 0) + P(rows, 0:kp) diag(sigma_p) G, P = the parent basis rows
+// at UBp + par_off (ld par_ld; none when par_off < 0), kp = prank[par_idx],
+// G (kp x ncols) from counter (grow, j/2, 2^31 + i, 4*level + pass) under key
+// seed + inst.
+struct AugJob {
+  int64_t row0;
+  int64_t src_col0;
+  int64_t par_off;
+  int32_t m, par_ld, par_idx;
+  uint32_t grow, inst;
+  int32_t pad;
+};
+void launch_h2_sample(int32_t njobs, const AugJob *jobs, int32_t ncols, int32_t level,
+                      int32_t pass, uint64_t seed, bool src_f32, const void *src, int64_t lds,
+                      const double *UBp, const int32_t *prank, const double *psigma,
+                      int32_t kmax, double *dst, int64_t ldd, hipStream_t s);
+// Nested bases: out rows (a chunk of child a inside tau) = U_a(chunk) Tr_a,
+// Tr_a the transfer (k_a x k_tau, ld kmax).
+struct NestJob {
+  int64_t out_off;     // first output row in UB (ld ldo)
+  int64_t in_off;      // first input row of U_a in UB (ld ldi)
+  int64_t t_off;       // transfer slot
+  int32_t m, ldo, ldi;
+  int32_t cidx, pidx;  // rank indexes of a and tau
+  int32_t pad;
+};
+void launch_nest(int32_t njobs, const NestJob *jobs, int32_t kmax, const double *UBin,
+                 const double *Tr, const int32_t *rank, double *UBout, hipStream_t s);
 
 }  // namespace hm

@@ -1,0 +1,171 @@
+"""H^2 compression on the GPU (hm_compress with HM_FORMAT_H2) against the
+oracle's compress_h2.
+
+Bars (FP64): exact H^2 matrices recovered to 1e-11 relative, every block
+(through the nested bases) equal to the oracle's within 1e-10 of the block
+norm, the finest level's bases equal to the oracle's singular vectors
+within 1e-9 (same signs: the largest entry positive), float and matvec
+counts equal to the oracle's; kernel matrices: blocks within 10 tol of the
+block norm of the oracle's (plus 1e-12 ||A||), error within twice the
+oracle's (or 20 tol), storage below the uniform H^1 form.  Mixed within
+1e-5 of FP64; a forest equal to its instances alone within 1e-10; plan
+replays equal to eager.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from synth import exact_h2
+from devutil import to_dev, to_host, dense_of
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2205_03406_amd as m
+    return m
+
+
+TREES = {
+    "strong2d": lambda: (workloads.random_points(700, 2, 11), 16, "geometric", "strong"),
+    "strong3d": lambda: (workloads.random_points(900, 3, 12), 24, "geometric", "strong"),
+    "curve": lambda: (workloads.star_curve(900), 20, "geometric", "strong"),
+    "hodlr": lambda: (workloads.uniform_line(512, 3), 32, "index_binary", "weak"),
+}
+
+
+def _parity(O, H, Ho, A, rel):
+    floor = 1e-12 * np.linalg.norm(A)
+    Ue, Ve = Ho.effective_bases()
+    perm = O.perm
+    worst = 0.0
+    for l in Ho.levels:
+        g = H.export_level(l)
+        o = Ho.B[l]
+        assert len(g) == len(o)
+        for (a, b, U, B, V), (a2, b2, B2) in zip(g, o):
+            assert (a, b) == (a2, b2)
+            a0, a1 = O.box_range(l, a)
+            b0, b1 = O.box_range(l, b)
+            nb = np.linalg.norm(A[np.ix_(perm[a0:a1], perm[b0:b1])])
+            d = np.linalg.norm(U @ B @ V.T - Ue[l][a] @ B2 @ Ve[l][b].T)
+            worst = max(worst, d / max(nb, 1e-300))
+            assert d <= rel * nb + floor, (l, a, b, d, nb)
+    return worst
+
+
+@pytest.mark.parametrize("name", ["strong2d", "strong3d", "curve", "hodlr"])
+def test_h2_exact_recovery(hm, name):
+    args = TREES[name]()
+    O = oracle.OTree(*args)
+    T = hm.Tree(*args).color()
+    A = exact_h2(O, 4, seed=5)
+    bb = hm.dense_blackbox(to_dev(A))
+    H = hm.compress(T, bb, rank=4, r=10, seed=77, h2=True)
+    D = dense_of(hm, H, O.n)
+    assert np.linalg.norm(D - A) <= 1e-11 * np.linalg.norm(A)
+    Ho = oracle.compress_h2(O, oracle.DenseBlackBox(A), 10, k=4, seed=77)
+    _parity(O, H, Ho, A, rel=1e-10)
+    # the finest level's bases are the oracle's singular vectors, signs included
+    f = Ho.levels[-1]
+    seen = set()
+    for a, b, U, B, V in H.export_level(f):
+        if a in seen:
+            continue
+        seen.add(a)
+        assert U.shape == Ho.Ulong[a].shape
+        assert np.max(np.abs(U - Ho.Ulong[a])) <= 1e-9, (a, np.max(np.abs(U - Ho.Ulong[a])))
+    st = H.stats()
+    assert st["format"] == hm.HM_FORMAT_H2
+    assert st["nfloats"] == Ho.floats()
+    assert (st["cols_A"], st["cols_At"]) == (Ho.cols_A, Ho.cols_At)
+    Ht = hm.compress(T, bb, tol=1e-9, r=14, seed=78, h2=True)
+    assert np.linalg.norm(dense_of(hm, Ht, O.n) - A) <= 1e-10 * np.linalg.norm(A)
+
+
+@pytest.mark.parametrize("n,tol", [(1500, 1e-8), (3000, 1e-6)])
+def test_h2_kernel_parity(hm, n, tol):
+    inst = workloads.config(1, n=n)
+    O = oracle.OTree(inst.points, inst.leaf, inst.tree, inst.adm)
+    T = hm.Tree(inst.points, inst.leaf, inst.tree, inst.adm).color()
+    A = oracle.kernel_matrix(inst.points, inst.points, inst.kernel)
+    H = hm.compress(T, T.kernel_blackbox(inst.kernel), tol=tol, r=24, seed=inst.seed, h2=True)
+    Ho = oracle.compress_h2(O, oracle.DenseBlackBox(A), 24, tol=tol, seed=inst.seed)
+    worst = _parity(O, H, Ho, A, rel=10 * tol)
+    D = dense_of(hm, H, O.n)
+    err = np.linalg.norm(D - A) / np.linalg.norm(A)
+    err_o = np.linalg.norm(Ho.dense() - A) / np.linalg.norm(A)
+    st = H.stats()
+    Hu = hm.compress(T, T.kernel_blackbox(inst.kernel), tol=tol, r=24, seed=inst.seed,
+                     uniform=True)
+    print("h2: err %.2e (oracle %.2e), worst block diff %.1e, floats %d (oracle %d, uniform %d)"
+          % (err, err_o, worst, st["nfloats"], Ho.floats(), Hu.stats()["nfloats"]))
+    assert err <= max(2 * err_o, 20 * tol)
+    assert abs(st["nfloats"] - Ho.floats()) <= 0.01 * Ho.floats()
+    assert st["nfloats"] < Hu.stats()["nfloats"]
+    assert st["saturated"] == 0
+
+
+def test_h2_mixed_matches_f64(hm):
+    inst = workloads.config(1, n=4096)
+    T = hm.Tree(inst.points, inst.leaf, inst.tree, inst.adm).color()
+    bb = T.kernel_blackbox(inst.kernel)
+    H64 = hm.compress(T, bb, tol=1e-6, r=24, seed=5, h2=True)
+    H32 = hm.compress(T, bb, tol=1e-6, r=24, seed=5, h2=True, prec=hm.HM_PREC_MIXED)
+    X = np.random.default_rng(0).standard_normal((T.n, 4))
+    a, b = hm.colmajor(T.n, 4), hm.colmajor(T.n, 4)
+    H64.matvec(to_dev(X), a)
+    H32.matvec(to_dev(X), b)
+    a, b = to_host(a), to_host(b)
+    d = np.linalg.norm(a - b) / np.linalg.norm(a)
+    print("mixed vs FP64 H2: %.2e" % d)
+    assert d <= 1e-5
+    assert H32.stats()["saturated"] == 0
+
+
+def test_h2_forest_matches_instances(hm):
+    parts = [workloads.ellipse(n, a, b) for n, a, b in [(2500, 1.4, 0.6), (900, 1.0, 1.0),
+                                                        (1700, 0.7, 1.9)]]
+    F = hm.Tree(parts, 64).color()
+    off = F.instances()
+    seed = 31
+    Hf = hm.compress(F, F.kernel_blackbox("log"), tol=1e-6, r=24, seed=seed, h2=True)
+    X = np.random.default_rng(1).standard_normal((F.n, 3))
+    Yf = hm.colmajor(F.n, 3)
+    Hf.matvec(to_dev(X), Yf, order=hm.HM_ORDER_TREE)
+    got = to_host(Yf)
+    for i, p in enumerate(parts):
+        T = hm.Tree(p, 64).color()
+        Hi = hm.compress(T, T.kernel_blackbox("log"), tol=1e-6, r=24, seed=seed + i, h2=True)
+        Yi = hm.colmajor(T.n, 3)
+        Hi.matvec(to_dev(X[off[i]:off[i + 1]]), Yi, order=hm.HM_ORDER_TREE)
+        want = to_host(Yi)
+        d = np.linalg.norm(got[off[i]:off[i + 1]] - want) / np.linalg.norm(want)
+        assert d <= 1e-10, (i, d)
+
+
+def test_h2_plan_replays(hm):
+    inst = workloads.config(1, n=3000)
+    T = hm.Tree(inst.points, inst.leaf, inst.tree, inst.adm).color()
+    bb = T.kernel_blackbox("log")
+    He = hm.compress(T, bb, tol=1e-8, r=24, seed=7, h2=True)
+    X = np.random.default_rng(1).standard_normal((T.n, 3))
+    Y = hm.colmajor(T.n, 3)
+    He.matvec(to_dev(X), Y)
+    want = to_host(Y)
+    P = hm.Plan(T, bb, tol=1e-8, r=24, seed=7, h2=True)
+    for k in range(3):
+        Z = hm.colmajor(T.n, 5)
+        Z.normal_()
+        W = hm.colmajor(T.n, 5)
+        T.kernel_apply("log", Z, W)
+        torch.cuda.synchronize()
+        P.execute()
+        Y2 = hm.colmajor(T.n, 3)
+        P.hmatrix().matvec(to_dev(X), Y2)
+        assert np.array_equal(to_host(Y2), want), k
