@@ -31,6 +31,7 @@ METRIC = "peel GFLOP/s + compressions/s at rel err 1e-5 vs plain FP64; p50/p99 m
 PEAK_FP64_MFMA = 78.6e12
 PEAK_FP32_MFMA = 157.3e12
 R_COLS = 24
+H2_RANK = R_COLS - 10   # fixed rank of the H^2 line (r - p)
 
 
 def parse():
@@ -44,6 +45,7 @@ def parse():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-uniform", action="store_true")
     ap.add_argument("--no-product", action="store_true")
+    ap.add_argument("--no-h2", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=3)
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--served-requests", type=int, default=80)
@@ -51,7 +53,7 @@ def parse():
                     help="comma-separated offered loads (fractions of the FP64 capacity)")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run this many steps, no extras (for profilers)")
-    ap.add_argument("--profile-workload", default="star", choices=["star", "batched", "uniform", "product"],
+    ap.add_argument("--profile-workload", default="star", choices=["star", "batched", "uniform", "product", "h2"],
                     help="with --profile-steps: which workload the steps run")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="with --profile-steps: add a 1 GiB device copy that calibrates "
@@ -59,11 +61,11 @@ def parse():
     return ap.parse_args()
 
 
-def step(hm, inst, bb_kernel, x, y, prec, tol, uniform=False):
+def step(hm, inst, bb_kernel, x, y, prec, tol, uniform=False, h2=False, rank=0):
     T = hm.Tree(inst.points, inst.leaf, inst.tree, inst.adm).color()
     bb = T.kernel_blackbox(bb_kernel)
-    H = hm.compress(T, bb, tol=tol, r=R_COLS, seed=inst.seed, prec=prec, timing=True,
-                    uniform=uniform)
+    H = hm.compress(T, bb, rank=rank, tol=0.0 if rank else tol, r=R_COLS, seed=inst.seed,
+                    prec=prec, timing=True, uniform=uniform, h2=h2)
     H.matvec(x, y)
     return T, H
 
@@ -96,16 +98,16 @@ def algorithmic_flops(st):
     return st["flops_blackbox"] + st["flops_peel"] + st["flops_qr"] + st["flops_solve"]
 
 
-def run_path(hm, torch, inst, prec, tol, steps, warmup, x, y, uniform=False):
+def run_path(hm, torch, inst, prec, tol, steps, warmup, x, y, uniform=False, h2=False, rank=0):
     for _ in range(warmup):
-        step(hm, inst, inst.kernel, x, y, prec, tol, uniform)
+        step(hm, inst, inst.kernel, x, y, prec, tol, uniform, h2, rank)
     torch.cuda.synchronize()
     times, flops, bb_ms, bb_flops, launches = [], 0.0, 0.0, 0.0, 0
     H = None
     t_all0 = time.perf_counter()
     for _ in range(steps):
         t0 = time.perf_counter()
-        T, H = step(hm, inst, inst.kernel, x, y, prec, tol, uniform)
+        T, H = step(hm, inst, inst.kernel, x, y, prec, tol, uniform, h2, rank)
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t0)
         st = H.stats()
@@ -114,7 +116,7 @@ def run_path(hm, torch, inst, prec, tol, steps, warmup, x, y, uniform=False):
         bb_flops += st["flops_blackbox"]
         # one black-box launch per sampled level (two in the uniform format)
         # and the leaf pass
-        launches += (2 if uniform else 1) * sum(1 for c in st["colors"] if c) + 1
+        launches += (2 if uniform or h2 else 1) * sum(1 for c in st["colors"] if c) + 1
     total = time.perf_counter() - t_all0
     return dict(times=times, total=total, flops=flops, bb_ms=bb_ms, bb_flops=bb_flops,
                 launches=launches, H=H, T=T, stats=st)
@@ -394,7 +396,9 @@ def main():
         else:
             for _ in range(args.profile_steps):
                 step(hm, inst, inst.kernel, x, y, hm.HM_PREC_F64, inst.tol,
-                     uniform=args.profile_workload == "uniform")
+                     uniform=args.profile_workload == "uniform",
+                     h2=args.profile_workload == "h2",
+                     rank=H2_RANK if args.profile_workload == "h2" else 0)
         torch.cuda.synchronize()
         if args.pmc_probe:
             # calibration for the HBM byte counters: one plain device copy of
@@ -511,6 +515,33 @@ def main():
                                                       "ms_solve", "ms_other", "ms_total")},
         }
         _progress("uniform done")
+
+    if not args.no_h2:
+        # H^2 format (nested bases) on the same workload at the fixed rank
+        # r - p (the truncation of augmented samples by a tolerance compounds
+        # over the levels)
+        run = run_path(hm, torch, inst, hm.HM_PREC_F64, inst.tol, args.steps, args.warmup, x, y,
+                       h2=True, rank=H2_RANK)
+        s2 = run["stats"]
+        Yd4 = hm.colmajor(n, 4)
+        run["H"].matvec(Xd, Yd4)
+        torch.cuda.synchronize()
+        Yh = Yd4.cpu().numpy()
+        out["h2"] = {
+            "value": round(run["flops"] / run["total"] / 1e9, 2),
+            "compressions_per_s": round(args.steps / run["total"], 3),
+            "ms_per_step": round(1e3 * run["total"] / args.steps, 3),
+            "p50_ms": round(float(np.percentile(np.array(run["times"]) * 1e3, 50)), 3),
+            "rank": H2_RANK,
+            "floats_per_dof": round(s2["nfloats"] / n, 2),
+            "max_rank": s2["max_rank"],
+            "saturated": s2["saturated"],
+            "rel_err_vs_dense_sampled_rows": float(np.linalg.norm(Yh[rows] - want) /
+                                                   np.linalg.norm(want)),
+            "stage_ms": {k: round(s2[k], 3) for k in ("ms_blackbox", "ms_peel", "ms_qr",
+                                                      "ms_solve", "ms_other", "ms_total")},
+        }
+        _progress("h2 done")
 
     if not args.no_product:
         out["product"] = run_product(hm, torch, inst, H, args.steps, args.warmup)

@@ -480,9 +480,14 @@ svd_basis_kernel(const QrJob *__restrict__ jobs, int32_t c, int32_t rank_fixed, 
     Rs[j][i] = (j < c && i < kq && i <= j) ? W[(int64_t)j * m + i] : 0.0;
   }
   __syncthreads();
-  // one-sided Jacobi over round-robin pairings, 8 threads per pair
+  // one-sided Jacobi over round-robin pairings; tpp threads per pair (the
+  // most that 256 threads give every pair, a power of two from 8 to 32).
+  // A pair is rotated while |p.q| > 2e-14 |p| |q|: rounding keeps smaller
+  // products from vanishing, and the singular vectors are then orthogonal
+  // to that level.
   const int ce = c + (c & 1);
-  const int pk = tid >> 3, l8 = tid & 7;
+  const int tpp = ce <= 16 ? 32 : (ce <= 32 ? 16 : 8);
+  const int pk = tid / tpp, lt = tid % tpp;
   for (int sweep = 0; sweep < 40; ++sweep) {
     if (tid == 0) flag = 0;
     __syncthreads();
@@ -490,31 +495,29 @@ svd_basis_kernel(const QrJob *__restrict__ jobs, int32_t c, int32_t rank_fixed, 
       if (pk < ce / 2) {
         const int p = (rr + pk) % (ce - 1);
         const int q = pk == 0 ? ce - 1 : (rr - pk + ce - 1) % (ce - 1);
-        if (p < c && q < c) {
-          double al = 0.0, be = 0.0, ga = 0.0;
-          for (int i = l8; i < kq; i += 8) {
+        double al = 0.0, be = 0.0, ga = 0.0;
+        if (p < c && q < c)
+          for (int i = lt; i < kq; i += tpp) {
             const double u = Rs[p][i], v = Rs[q][i];
             al += u * u;
             be += v * v;
             ga += u * v;
           }
-#pragma unroll
-          for (int off = 4; off > 0; off >>= 1) {
-            al += __shfl_xor(al, off, 8);
-            be += __shfl_xor(be, off, 8);
-            ga += __shfl_xor(ga, off, 8);
+        for (int off = tpp >> 1; off > 0; off >>= 1) {
+          al += __shfl_xor(al, off, tpp);
+          be += __shfl_xor(be, off, tpp);
+          ga += __shfl_xor(ga, off, tpp);
+        }
+        if (p < c && q < c && ga != 0.0 && fabs(ga) > 2e-14 * sqrt(al * be)) {
+          const double zeta = (be - al) / (2.0 * ga);
+          const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+          for (int i = lt; i < kq; i += tpp) {
+            const double u = Rs[p][i], v = Rs[q][i];
+            Rs[p][i] = cs * u - sn * v;
+            Rs[q][i] = sn * u + cs * v;
           }
-          if (ga != 0.0 && fabs(ga) > 1e-15 * sqrt(al * be)) {
-            const double zeta = (be - al) / (2.0 * ga);
-            const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-            const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
-            for (int i = l8; i < kq; i += 8) {
-              const double u = Rs[p][i], v = Rs[q][i];
-              Rs[p][i] = cs * u - sn * v;
-              Rs[q][i] = sn * u + cs * v;
-            }
-            if (l8 == 0) flag = 1;
-          }
+          if (lt == 0) flag = 1;
         }
       }
       __syncthreads();

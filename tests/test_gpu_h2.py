@@ -169,3 +169,21 @@ def test_h2_plan_replays(hm):
         Y2 = hm.colmajor(T.n, 3)
         P.hmatrix().matvec(to_dev(X), Y2)
         assert np.array_equal(to_host(Y2), want), k
+
+
+def test_h2_kernel_fixed_rank_parity(hm):
+    """Fixed rank (the setting of the paper's experiments): blocks against
+    the oracle's within 1e-8 of the block norm, error within twice the
+    oracle's."""
+    inst = workloads.config(1, n=3000)
+    O = oracle.OTree(inst.points, inst.leaf, inst.tree, inst.adm)
+    T = hm.Tree(inst.points, inst.leaf, inst.tree, inst.adm).color()
+    A = oracle.kernel_matrix(inst.points, inst.points, inst.kernel)
+    H = hm.compress(T, T.kernel_blackbox(inst.kernel), rank=14, r=24, seed=inst.seed, h2=True)
+    Ho = oracle.compress_h2(O, oracle.DenseBlackBox(A), 24, k=14, seed=inst.seed)
+    worst = _parity(O, H, Ho, A, rel=1e-8)
+    err = np.linalg.norm(dense_of(hm, H, O.n) - A) / np.linalg.norm(A)
+    err_o = np.linalg.norm(Ho.dense() - A) / np.linalg.norm(A)
+    print("h2 fixed rank: err %.2e (oracle %.2e), worst block diff %.1e" % (err, err_o, worst))
+    assert err <= 2 * err_o + 1e-12
+    assert H.stats()["nfloats"] == Ho.floats()
