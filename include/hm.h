@@ -66,10 +66,12 @@ const char *hm_last_error(void);
  * graphs of every level (def:incompatibility_graph, eq:h1constraints) and of
  * the leaf level (section on extracting inadmissible blocks).
  *
- *   points     host, n x dim row-major FP64, copied (1 <= dim <= 3)
+ *   points     host, n x dim row-major FP64, copied (1 <= dim <= 8; the
+ *              kernel black box and kernel apply take dim <= 3)
  *   leaf_size  m >= 1
  *   tree_kind  HM_TREE_GEOMETRIC: root = bounding cube of the points, integer
- *              cell c = min(2^21-1, floor(((x-lo)/s) 2^21)), tree order =
+ *              cell c = min(2^b-1, floor(((x-lo)/s) 2^b)) with b = 21 bits for
+ *              dim <= 3 and floor(63/dim) above (at most b levels), tree order =
  *              stable sort by the interleaved cell bits (x lowest); a box that
  *              stops splitting is carried unchanged to finer levels.
  *              HM_TREE_INDEX_BINARY: points stably sorted by x, ranges halved
@@ -114,7 +116,8 @@ hm_status hm_tree_info(const hm_tree *tree, int32_t *nlevels, int64_t *n, int32_
 hm_status hm_tree_perm(const hm_tree *tree, int64_t *perm);
 /* box ranges of one level: start (host, nbox+1; box b holds tree positions
  * [start[b], start[b+1])), parent (host, nbox; box id at level-1, -1 at
- * level 0), org (host, 3*nbox; integer cube origin in 2^-21 root units),
+ * level 0), org (host, max(3, dim)*nbox; integer cube origin in 2^-b root
+ * units, b as for hm_build_tree),
  * blev (host, nbox; level whose cube size the box has).  Any output may be
  * NULL; nbox is always written. */
 hm_status hm_tree_level(const hm_tree *tree, int level, int32_t *nbox, int64_t *start,

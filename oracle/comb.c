@@ -19,7 +19,9 @@
  *
  * Readings where the paper is silent (all listed in the design notes):
  *   - root cube = bounding cube of the points (the paper assumes [0,1]^d);
- *     integer coordinates c = min(2^21-1, floor(((x-lo)/s) * 2^21));
+ *     integer coordinates c = min(2^b-1, floor(((x-lo)/s) * 2^b)) with
+ *     b = 21 bits for d <= 3 and floor(63 / d) for 4 <= d <= 8 (the key of
+ *     all d coordinates fits 64 bits; at most b levels);
  *   - a box that stops splitting is carried unchanged to every finer level,
  *     so each level partitions all N points;
  *   - box ids at a level are ranks of their first point in tree order;
@@ -34,7 +36,6 @@
 #include <string.h>
 #include <math.h>
 
-#define KEYBITS 21
 
 typedef struct {
   int nv;
@@ -47,6 +48,8 @@ typedef struct {
 
 typedef struct {
   int n, dim, nlev, weak;
+  int kb;          /* key bits per coordinate: 21 for dim <= 3, 63 / dim above */
+  int os;          /* origin entries per box: max(3, dim) */
   int64_t *perm;
   int *nbox;
   int64_t **start;
@@ -95,17 +98,18 @@ static void v32_push(vec32 *a, int x) {
 }
 
 /* ------------------------------------------------------------ the tree */
-static uint32_t coord_of(double x, double lo, double s) {
+static uint32_t coord_of(double x, double lo, double s, int kb) {
   double t = (x - lo) / s;
-  t = t * 2097152.0; /* 2^21 */
+  t = t * ldexp(1.0, kb); /* 2^kb */
   double f = floor(t);
-  uint32_t c = (f >= 2097151.0) ? 2097151u : (uint32_t)f;
+  const double top = ldexp(1.0, kb) - 1.0;
+  uint32_t c = (f >= top) ? (uint32_t)top : (uint32_t)f;
   return c;
 }
 
-static uint64_t interleave(const uint32_t *c, int dim) {
+static uint64_t interleave(const uint32_t *c, int dim, int kb) {
   uint64_t key = 0;
-  for (int b = 0; b < KEYBITS; ++b)
+  for (int b = 0; b < kb; ++b)
     for (int d = 0; d < dim; ++d)
       if ((c[d] >> b) & 1u) key |= (uint64_t)1 << (b * dim + d);
   return key;
@@ -135,7 +139,8 @@ static void push_level(otree *T, lvl_t *L, int64_t n) {
 }
 
 static void build_geometric(otree *T, const double *pts, int64_t n, int dim, int m) {
-  double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+  const int kb = T->kb, os = T->os;
+  double lo[8] = {0}, hi[8] = {0};
   for (int d = 0; d < dim; ++d) { lo[d] = pts[d]; hi[d] = pts[d]; }
   for (int64_t i = 0; i < n; ++i)
     for (int d = 0; d < dim; ++d) {
@@ -149,8 +154,8 @@ static void build_geometric(otree *T, const double *pts, int64_t n, int dim, int
   uint32_t *c = (uint32_t *)malloc(n * dim * sizeof(uint32_t));
   kv_t *kv = (kv_t *)malloc(n * sizeof(kv_t));
   for (int64_t i = 0; i < n; ++i) {
-    for (int d = 0; d < dim; ++d) c[i * dim + d] = coord_of(pts[i * dim + d], lo[d], s);
-    kv[i].key = interleave(&c[i * dim], dim);
+    for (int d = 0; d < dim; ++d) c[i * dim + d] = coord_of(pts[i * dim + d], lo[d], s, kb);
+    kv[i].key = interleave(&c[i * dim], dim, kb);
     kv[i].idx = i;
   }
   qsort(kv, n, sizeof(kv_t), kv_cmp);
@@ -163,10 +168,10 @@ static void build_geometric(otree *T, const double *pts, int64_t n, int dim, int
 
   lvl_t L; memset(&L, 0, sizeof(L));
   v64_push(&L.start, 0); v32_push(&L.parent, -1);
-  for (int d = 0; d < 3; ++d) v64_push(&L.org, 0);
+  for (int d = 0; d < T->os; ++d) v64_push(&L.org, 0);
   v32_push(&L.blev, 0);
   push_level(T, &L, n);
-  for (int l = 0; l < KEYBITS; ++l) {
+  for (int l = 0; l < kb; ++l) {
     int nb = T->nbox[l], any = 0;
     for (int b = 0; b < nb; ++b) if (T->start[l][b + 1] - T->start[l][b] > m) any = 1;
     if (!any) break;
@@ -174,11 +179,11 @@ static void build_geometric(otree *T, const double *pts, int64_t n, int dim, int
       int64_t s0 = T->start[l][b], s1 = T->start[l][b + 1];
       if (s1 - s0 <= m) {            /* carried leaf */
         v64_push(&L.start, s0); v32_push(&L.parent, b);
-        for (int d = 0; d < 3; ++d) v64_push(&L.org, T->org[l][b * 3 + d]);
+        for (int d = 0; d < os; ++d) v64_push(&L.org, T->org[l][b * os + d]);
         v32_push(&L.blev, T->blev[l][b]);
         continue;
       }
-      int bit = KEYBITS - 1 - l;   /* the coordinate bit that picks the child */
+      int bit = kb - 1 - l;        /* the coordinate bit that picks the child */
       for (int ch = 0; ch < (1 << dim); ++ch) {
         int64_t first = -1;
         for (int64_t i = s0; i < s1; ++i) {
@@ -188,8 +193,8 @@ static void build_geometric(otree *T, const double *pts, int64_t n, int dim, int
         }
         if (first < 0) continue;     /* empty child omitted */
         v64_push(&L.start, first); v32_push(&L.parent, b);
-        for (int d = 0; d < 3; ++d) {
-          int64_t o = T->org[l][b * 3 + d];
+        for (int d = 0; d < os; ++d) {
+          int64_t o = T->org[l][b * os + d];
           if (d < dim && ((ch >> d) & 1)) o += (int64_t)1 << bit;
           v64_push(&L.org, o);
         }
@@ -209,7 +214,7 @@ static void build_index_binary(otree *T, const double *pts, int64_t n, int dim, 
   free(dv);
   lvl_t L; memset(&L, 0, sizeof(L));
   v64_push(&L.start, 0); v32_push(&L.parent, -1);
-  for (int d = 0; d < 3; ++d) v64_push(&L.org, 0);
+  for (int d = 0; d < T->os; ++d) v64_push(&L.org, 0);
   v32_push(&L.blev, 0);
   push_level(T, &L, n);
   for (int l = 0; l < 62; ++l) {
@@ -219,11 +224,11 @@ static void build_index_binary(otree *T, const double *pts, int64_t n, int dim, 
     for (int b = 0; b < nb; ++b) {
       int64_t s0 = T->start[l][b], s1 = T->start[l][b + 1];
       v64_push(&L.start, s0); v32_push(&L.parent, b);
-      for (int d = 0; d < 3; ++d) v64_push(&L.org, 0);
+      for (int d = 0; d < T->os; ++d) v64_push(&L.org, 0);
       v32_push(&L.blev, (s1 - s0 > m) ? l + 1 : T->blev[l][b]);
       if (s1 - s0 > m) {
         v64_push(&L.start, s0 + (s1 - s0) / 2); v32_push(&L.parent, b);
-        for (int d = 0; d < 3; ++d) v64_push(&L.org, 0);
+        for (int d = 0; d < T->os; ++d) v64_push(&L.org, 0);
         v32_push(&L.blev, l + 1);
       }
     }
@@ -234,9 +239,9 @@ static void build_index_binary(otree *T, const double *pts, int64_t n, int dim, 
 /* closed cubes of boxes a and b at level l touch */
 static int touch(const otree *T, int l, int a, int b) {
   for (int d = 0; d < T->dim; ++d) {
-    int64_t oa = T->org[l][a * 3 + d], ob = T->org[l][b * 3 + d];
-    int64_t sa = (int64_t)1 << (KEYBITS - T->blev[l][a]);
-    int64_t sb = (int64_t)1 << (KEYBITS - T->blev[l][b]);
+    int64_t oa = T->org[l][a * T->os + d], ob = T->org[l][b * T->os + d];
+    int64_t sa = (int64_t)1 << (T->kb - T->blev[l][a]);
+    int64_t sb = (int64_t)1 << (T->kb - T->blev[l][b]);
     if (!(oa <= ob + sb && ob <= oa + sa)) return 0;
   }
   return 1;
@@ -462,6 +467,8 @@ int orc_dsatur(int nv, const int64_t *xadj, const int *adj, int *color) {
 void *orc_build(const double *pts, int64_t n, int dim, int leaf, int index_binary, int weak) {
   otree *T = (otree *)calloc(1, sizeof(otree));
   T->n = (int)n; T->dim = dim; T->weak = weak;
+  T->kb = dim <= 3 ? 21 : 63 / dim;
+  T->os = dim > 3 ? dim : 3;
   T->perm = (int64_t *)malloc((n > 0 ? n : 1) * sizeof(int64_t));
   if (index_binary) build_index_binary(T, pts, n, dim, leaf);
   else build_geometric(T, pts, n, dim, leaf);
@@ -479,7 +486,7 @@ void orc_boxes(void *t, int l, int64_t *start, int *parent, int64_t *org, int *b
   otree *T = (otree *)t; int nb = T->nbox[l];
   memcpy(start, T->start[l], (nb + 1) * sizeof(int64_t));
   memcpy(parent, T->parent[l], nb * sizeof(int));
-  memcpy(org, T->org[l], nb * 3 * sizeof(int64_t));
+  memcpy(org, T->org[l], (size_t)nb * T->os * sizeof(int64_t));
   memcpy(blev, T->blev[l], nb * sizeof(int));
 }
 int orc_list_len(void *t, int l, int which) {

@@ -91,11 +91,15 @@ class OTree:
     """
 
     def __init__(self, points: np.ndarray, leaf: int, kind: str = "geometric", adm: str = "strong"):
+        """points: N x d, 1 <= d <= 8 (2^d-trees; integer cells of 21 bits per
+        coordinate for d <= 3, floor(63 / d) bits above)."""
         lib = _load()
         pts = np.ascontiguousarray(points, np.float64)
         if pts.ndim == 1:
             pts = pts.reshape(-1, 1)
         n, dim = pts.shape
+        if not 1 <= dim <= 8:
+            raise ValueError("points must have 1 to 8 coordinates")
         if kind == "index_binary" and adm != "weak":
             raise ValueError("the index-halving tree is only used with weak admissibility")
         self.n, self.dim, self.leaf, self.kind, self.adm = n, dim, leaf, kind, adm
@@ -111,10 +115,11 @@ class OTree:
             for l in range(self.nlev):
                 nb = lib.orc_nbox(h, l)
                 s = np.zeros(nb + 1, np.int64); p = np.zeros(nb, np.int32)
-                o = np.zeros(nb * 3, np.int64); b = np.zeros(nb, np.int32)
+                os_ = max(3, dim)
+                o = np.zeros(nb * os_, np.int64); b = np.zeros(nb, np.int32)
                 lib.orc_boxes(h, l, s, p, o, b)
                 self.start.append(s); self.parent.append(p)
-                self.org.append(o.reshape(nb, 3)); self.blev.append(b)
+                self.org.append(o.reshape(nb, os_)); self.blev.append(b)
                 lists = []
                 for which in (0, 1):
                     ln = lib.orc_list_len(h, l, which)

@@ -300,10 +300,11 @@ class Tree:
         nb = nb.value
         start = np.zeros(nb + 1, np.int64)
         parent = np.zeros(nb, np.int32)
-        org = np.zeros(3 * nb, np.int64)
+        os_ = max(3, self.dim)
+        org = np.zeros(os_ * nb, np.int64)
         blev = np.zeros(nb, np.int32)
         _check(_lib.hm_tree_level(self.h, l, None, _ptr(start), _ptr(parent), _ptr(org), _ptr(blev)))
-        return start, parent, org.reshape(nb, 3), blev
+        return start, parent, org.reshape(nb, os_), blev
 
     def list(self, l, which):
         nnz = C.c_int64()

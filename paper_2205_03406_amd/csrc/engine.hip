@@ -1987,7 +1987,7 @@ const char *hm_autotune_table(void) {
 hm_status hm_build_tree(const double *points, int64_t n, int dim, int leaf_size, int tree_kind,
                         int adm, hm_tree **out) {
   API_BEGIN
-  if (!points || !out || n <= 0 || dim < 1 || dim > 3 || leaf_size < 1)
+  if (!points || !out || n <= 0 || dim < 1 || dim > 8 || leaf_size < 1)
     return fail(HM_E_ARG, "hm_build_tree: bad argument");
   if (tree_kind != HM_TREE_GEOMETRIC && tree_kind != HM_TREE_INDEX_BINARY)
     return fail(HM_E_ARG, "hm_build_tree: bad tree kind");
@@ -2007,7 +2007,7 @@ hm_status hm_build_tree(const double *points, int64_t n, int dim, int leaf_size,
 hm_status hm_build_forest(const double *points, const int64_t *counts, int32_t ninst, int dim,
                           int leaf_size, int tree_kind, int adm, hm_tree **out) {
   API_BEGIN
-  if (!points || !counts || !out || ninst < 1 || dim < 1 || dim > 3 || leaf_size < 1)
+  if (!points || !counts || !out || ninst < 1 || dim < 1 || dim > 8 || leaf_size < 1)
     return fail(HM_E_ARG, "hm_build_forest: bad argument");
   if (tree_kind != HM_TREE_GEOMETRIC && tree_kind != HM_TREE_INDEX_BINARY)
     return fail(HM_E_ARG, "hm_build_forest: bad tree kind");
@@ -2241,6 +2241,7 @@ hm_status hm_kernel_blackbox(hm_tree *tree, int kernel, hm_blackbox *out) {
   API_BEGIN
   if (!tree || !out) return fail(HM_E_ARG, "null argument");
   if (kernel != HM_KERNEL_LOG && kernel != HM_KERNEL_INV_R) return fail(HM_E_ARG, "bad kernel");
+  if (tree->t.dim > 3) return fail(HM_E_ARG, "the kernel black box takes 1 to 3 dimensions");
   auto k = std::make_shared<KernelBB>();
   k->tree = &tree->t;
   k->kernel = kernel;
@@ -2262,6 +2263,7 @@ hm_status hm_kernel_apply(hm_tree *tree, int kernel, int64_t ncols, int dtype, c
     return fail(HM_E_ARG, "hm_kernel_apply: bad argument");
   if (kernel != HM_KERNEL_LOG && kernel != HM_KERNEL_INV_R) return fail(HM_E_ARG, "bad kernel");
   if (dtype != HM_F64 && dtype != HM_F32) return fail(HM_E_ARG, "bad dtype");
+  if (tree->t.dim > 3) return fail(HM_E_ARG, "the kernel apply takes 1 to 3 dimensions");
   hipStream_t s = (hipStream_t)stream;
   DeviceTree &D = device_tree(tree->t, s);
   const bool f32 = dtype == HM_F32;

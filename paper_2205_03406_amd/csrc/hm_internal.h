@@ -24,7 +24,7 @@ struct Error {
 struct Level {
   std::vector<int64_t> start;    // nbox + 1
   std::vector<int32_t> parent;   // nbox
-  std::vector<int64_t> org;      // 3 * nbox
+  std::vector<int64_t> org;      // ostride * nbox (integer cube origins)
   std::vector<int32_t> blev;     // nbox
   std::vector<int32_t> nei_ptr, nei;
   std::vector<int32_t> int_ptr, intl;
@@ -48,6 +48,8 @@ struct DeviceTree;  // device copies, defined in the engine
 struct Tree {
   int64_t n = 0;
   int dim = 0, kind = 0, adm = 0, leaf = 0;
+  int kbits = 21;    // integer cell bits per coordinate (21 for d <= 3, 63 / d above)
+  int ostride = 3;   // origin entries per box: max(3, dim)
   std::vector<double> pts;        // original order, n x dim row-major
   std::vector<int64_t> perm;      // tree position -> original index
   std::vector<Level> lev;

@@ -29,13 +29,20 @@ namespace hm {
 
 namespace {
 
-constexpr int kBits = 21;
-constexpr uint32_t kMaxCell = (1u << kBits) - 1;
+// Key bits per coordinate: 21 for d <= 3, floor(63 / d) for 4 <= d <= 8, so
+// that the interleaved key of all coordinates fits 64 bits.
+int key_bits(int dim) { return dim <= 3 ? 21 : 63 / dim; }
 
-// Spread the low 21 bits of v so that bit i lands at bit i*stride
-// (shift-and-mask interleave, stride 1, 2 or 3).
-uint64_t spread(uint32_t v, int stride) {
-  uint64_t x = v & kMaxCell;
+// Spread the low kb bits of v so that bit i lands at bit i*stride
+// (shift-and-mask interleave for strides 1, 2 and 3 with 21 bits, a bit
+// loop for wider strides).
+uint64_t spread(uint32_t v, int stride, int kb) {
+  uint64_t x = v & ((1u << kb) - 1);
+  if (stride > 3) {
+    uint64_t y = 0;
+    for (int b = 0; b < kb; ++b) y |= ((x >> b) & 1u) << (b * stride);
+    return y;
+  }
   if (stride == 2) {
     x = (x | (x << 16)) & 0x0000FFFF0000FFFFull;
     x = (x | (x << 8)) & 0x00FF00FF00FF00FFull;
@@ -52,12 +59,13 @@ uint64_t spread(uint32_t v, int stride) {
   return x;
 }
 
-// Integer cell of one coordinate: floor(((x - lo) / s) * 2^21), clamped.
+// Integer cell of one coordinate: floor(((x - lo) / s) * 2^kb), clamped.
 // x >= lo, so the quotient is non-negative and truncation is the floor; the
 // division and the (exact) power-of-two product are separate roundings.
-uint32_t cell(double x, double lo, double s) {
-  const double t = ((x - lo) / s) * 2097152.0;
-  if (t >= double(kMaxCell)) return kMaxCell;
+uint32_t cell(double x, double lo, double s, int kb) {
+  const uint32_t top = (1u << kb) - 1;
+  const double t = ((x - lo) / s) * std::ldexp(1.0, kb);
+  if (t >= double(top)) return top;
   return uint32_t(t);
 }
 
@@ -83,7 +91,8 @@ struct Builder {
   void geometric(const double *pts) {
     const int64_t n = T.n;
     const int dim = T.dim;
-    double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    const int kb = T.kbits, os = T.ostride;
+    double lo[8] = {0}, hi[8] = {0};
     for (int d = 0; d < dim; ++d) lo[d] = hi[d] = pts[d];
     for (int64_t i = 1; i < n; ++i)
       for (int d = 0; d < dim; ++d) {
@@ -98,9 +107,9 @@ struct Builder {
     for (int64_t i = 0; i < n; ++i) {
       uint64_t k = 0;
       for (int d = 0; d < dim; ++d) {
-        uint32_t c = cell(pts[i * dim + d], lo[d], s);
+        uint32_t c = cell(pts[i * dim + d], lo[d], s, kb);
         cells[i * dim + d] = c;
-        k |= spread(c, dim) << d;
+        k |= spread(c, dim, kb) << d;
       }
       key[i] = {k, i};
     }
@@ -115,24 +124,24 @@ struct Builder {
     Level root;
     root.start = {0, n};
     root.parent = {-1};
-    root.org = {0, 0, 0};
+    root.org.assign(T.ostride, 0);
     root.blev = {0};
     T.lev.push_back(std::move(root));
     const int m = T.leaf;
-    for (int l = 0; l < kBits; ++l) {
+    for (int l = 0; l < kb; ++l) {
       const Level &P = T.lev[l];
       bool split_any = false;
       for (int b = 0; b < P.nbox(); ++b)
         if (P.start[b + 1] - P.start[b] > m) split_any = true;
       if (!split_any) break;
       Level C;
-      const int shift = (kBits - 1 - l) * dim;  // key bits below the child digit
+      const int shift = (kb - 1 - l) * dim;  // key bits below the child digit
       for (int b = 0; b < P.nbox(); ++b) {
         int64_t s0 = P.start[b], s1 = P.start[b + 1];
         if (s1 - s0 <= m) {  // leaf: carried to the next level unchanged
           C.start.push_back(s0);
           C.parent.push_back(b);
-          for (int d = 0; d < 3; ++d) C.org.push_back(P.org[3 * b + d]);
+          for (int d = 0; d < os; ++d) C.org.push_back(P.org[os * b + d]);
           C.blev.push_back(P.blev[b]);
           continue;
         }
@@ -145,9 +154,9 @@ struct Builder {
           int digit = int(pre & ((uint64_t(1) << dim) - 1));
           C.start.push_back(i);
           C.parent.push_back(b);
-          for (int d = 0; d < 3; ++d) {
-            int64_t o = P.org[3 * b + d];
-            if (d < dim && ((digit >> d) & 1)) o += int64_t(1) << (kBits - 1 - l);
+          for (int d = 0; d < os; ++d) {
+            int64_t o = P.org[os * b + d];
+            if (d < dim && ((digit >> d) & 1)) o += int64_t(1) << (kb - 1 - l);
             C.org.push_back(o);
           }
           C.blev.push_back(l + 1);
@@ -169,7 +178,7 @@ struct Builder {
     Level root;
     root.start = {0, n};
     root.parent = {-1};
-    root.org = {0, 0, 0};
+    root.org.assign(T.ostride, 0);
     root.blev = {0};
     T.lev.push_back(std::move(root));
     const int m = T.leaf;
@@ -192,7 +201,7 @@ struct Builder {
           C.blev.push_back(l + 1);
         }
       }
-      C.org.assign(3 * C.parent.size(), 0);
+      C.org.assign((size_t)T.ostride * C.parent.size(), 0);
       C.start.push_back(n);
       T.lev.push_back(std::move(C));
     }
@@ -200,9 +209,10 @@ struct Builder {
 
   bool touching(const Level &Lv, int a, int b) const {
     for (int d = 0; d < T.dim; ++d) {
-      int64_t oa = Lv.org[3 * a + d], ob = Lv.org[3 * b + d];
-      int64_t ea = oa + (int64_t(1) << (kBits - Lv.blev[a]));
-      int64_t eb = ob + (int64_t(1) << (kBits - Lv.blev[b]));
+      const int os = T.ostride;
+      int64_t oa = Lv.org[os * a + d], ob = Lv.org[os * b + d];
+      int64_t ea = oa + (int64_t(1) << (T.kbits - Lv.blev[a]));
+      int64_t eb = ob + (int64_t(1) << (T.kbits - Lv.blev[b]));
       if (ob > ea || oa > eb) return false;
     }
     return true;
@@ -422,6 +432,8 @@ hm_status build_tree(const double *pts, int64_t n, int dim, int leaf, int kind, 
   T = Tree();
   T.n = n;
   T.dim = dim;
+  T.kbits = key_bits(dim);
+  T.ostride = std::max(3, dim);
   T.kind = kind;
   T.adm = adm;
   T.leaf = leaf;
@@ -492,6 +504,8 @@ hm_status build_forest(const double *pts, const int64_t *counts, int ninst, int 
   F = Tree();
   F.n = off[ninst];
   F.dim = dim;
+  F.kbits = key_bits(dim);
+  F.ostride = std::max(3, dim);
   F.kind = kind;
   F.adm = adm;
   F.leaf = leaf;
@@ -517,7 +531,7 @@ hm_status build_forest(const double *pts, const int64_t *counts, int ninst, int 
       for (int b = 0; b < S.nbox(); ++b) {
         Lv.start.push_back(S.start[b] + off[i]);
         Lv.parent.push_back(l == 0 ? -1 : (carried ? b : S.parent[b]) + boff[l - 1][i]);
-        for (int d = 0; d < 3; ++d) Lv.org.push_back(S.org[3 * b + d]);
+        for (int d = 0; d < F.ostride; ++d) Lv.org.push_back(S.org[F.ostride * b + d]);
         Lv.blev.push_back(S.blev[b]);
         for (int t = S.nei_ptr[b]; t < S.nei_ptr[b + 1]; ++t) Lv.nei.push_back(S.nei[t] + b0);
         Lv.nei_ptr.push_back((int32_t)Lv.nei.size());

@@ -184,3 +184,10 @@ def test_uniform_graphs_match_oracle(case):
         assert np.array_equal(xadj, UG.xadj), l
         assert np.array_equal(adj, UG.adj), l
         assert np.array_equal(col, UG.color) and nc == UG.ncolors, l
+
+
+@pytest.mark.parametrize("dim,noise", [(4, 0.0), (4, 0.05), (6, 0.01), (8, 0.0), (8, 0.005)])
+def test_noisy_lines_in_more_dimensions(dim, noise):
+    """Trees of d > 3 (2^d children, floor(63 / d) key bits): tree order,
+    boxes, lists, graphs and colors equal to the oracle's."""
+    compare(workloads.noisy_line(3000, dim, noise), 32)

@@ -61,6 +61,18 @@ def random_points(n: int, dim: int, seed: int) -> np.ndarray:
     return np.ascontiguousarray(rng.uniform(0.0, 1.0, size=(n, dim)))
 
 
+def noisy_line(n: int, dim: int, noise: float, seed: int = 6) -> np.ndarray:
+    """n points equispaced along a randomly oriented line through the center
+    of [0, 1]^dim (the longest such segment inside the cube), plus Gaussian
+    noise of standard deviation `noise` on every coordinate."""
+    rng = np.random.default_rng(seed)
+    u = rng.standard_normal(dim)
+    u /= np.linalg.norm(u)
+    half = 0.5 / np.max(np.abs(u))
+    t = np.linspace(-half, half, n)
+    return 0.5 + t[:, None] * u[None, :] + noise * rng.standard_normal((n, dim))
+
+
 def gaussian_rhs(n: int, nrhs: int, seed: int, dtype=np.float64) -> np.ndarray:
     """Column-major-friendly right-hand sides: returned as (nrhs, n) C order,
     i.e. the transpose of an N x nrhs column-major matrix."""
