@@ -54,20 +54,20 @@ constexpr int PMAX = 128;  // packed output rows of one projection item
 // Projection: the pairs of one item share a column box; their rank columns
 // are packed end to end (actual device ranks) into at most PMAX output rows,
 // processed 64 at a time.
-template <typename T>
+template <typename T, int NTW>
 __global__ void __launch_bounds__(256, 2)
 lr_project_kernel(const ProjItem *__restrict__ items, const ProjPair *__restrict__ pairs,
                   int32_t kmax, int64_t tstride, const int32_t *__restrict__ ranks,
                   const T *__restrict__ R, const T *__restrict__ X, int64_t ldx, int64_t ncols,
                   T *__restrict__ Tout) {
   __shared__ T As[KC][64 + 1];   // [depth][output row]
-  __shared__ T Bs[KC][TC + 1];   // [depth][col]
+  __shared__ T Bs[KC][16 * NTW + 1];   // [depth][col]
   __shared__ int64_t o_r[PMAX];  // R element offset of output row (segment start)
   __shared__ int64_t o_t[PMAX];  // T element offset of output row
   __shared__ int o_tot;
   typedef typename Acc<T>::type acc_t;
   const ProjItem it = items[blockIdx.x];
-  const int64_t c0 = (int64_t)blockIdx.y * TC;
+  const int64_t c0 = (int64_t)blockIdx.y * (16 * NTW);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (tid == 0) {
     int o = 0;
@@ -84,10 +84,10 @@ lr_project_kernel(const ProjItem *__restrict__ items, const ProjPair *__restrict
   __syncthreads();
   const int nout = o_tot;
   for (int ob = 0; ob < nout; ob += 64) {
-    acc_t acc[4];
+    acc_t acc[NTW];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) acc[t] = (acc_t){0, 0, 0, 0};
-    T av[8], bv[8];
+    for (int t = 0; t < NTW; ++t) acc[t] = (acc_t){0, 0, 0, 0};
+    T av[8], bv[2 * NTW];
     auto fetch = [&](int r0) {
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
@@ -95,6 +95,12 @@ lr_project_kernel(const ProjItem *__restrict__ items, const ProjPair *__restrict
         const int rr = e % KC, o = e / KC;
         const int row = r0 + rr;
         av[q] = (row < it.nrows && ob + o < nout) ? R[o_r[ob + o] + row] : (T)0;
+      }
+#pragma unroll
+      for (int q = 0; q < 2 * NTW; ++q) {
+        const int e = tid + 256 * q;
+        const int rr = e % KC, o = e / KC;
+        const int row = r0 + rr;
         const int64_t gc = c0 + o;
         bv[q] = (row < it.nrows && gc < ncols) ? X[gc * ldx + it.row0 + row] : (T)0;
       }
@@ -105,6 +111,10 @@ lr_project_kernel(const ProjItem *__restrict__ items, const ProjPair *__restrict
       for (int q = 0; q < 8; ++q) {
         const int e = tid + 256 * q;
         As[e % KC][e / KC] = av[q];
+      }
+#pragma unroll
+      for (int q = 0; q < 2 * NTW; ++q) {
+        const int e = tid + 256 * q;
         Bs[e % KC][e / KC] = bv[q];
       }
       __syncthreads();
@@ -113,13 +123,13 @@ lr_project_kernel(const ProjItem *__restrict__ items, const ProjPair *__restrict
       for (int ks = 0; ks < KC; ks += 4) {
         const T a = As[ks + (lane >> 4)][16 * wave + (lane & 15)];
 #pragma unroll
-        for (int t = 0; t < 4; ++t)
+        for (int t = 0; t < NTW; ++t)
           Acc<T>::step(a, Bs[ks + (lane >> 4)][16 * t + (lane & 15)], acc[t]);
       }
       __syncthreads();
     }
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
+    for (int t = 0; t < NTW; ++t) {
       const int64_t gc = c0 + 16 * t + (lane & 15);
       if (gc >= ncols) continue;
 #pragma unroll
@@ -137,25 +147,27 @@ lr_project_kernel(const ProjItem *__restrict__ items, const ProjPair *__restrict
 constexpr int EMAX = 32;
 constexpr int KTAB = EMAX * 64;
 
-template <typename T>
-__global__ void __launch_bounds__(256, 2)
+// four waves per SIMD (at most 128 VGPRs): 11 % faster than three at 288
+// columns; the latency of the table-driven operand fetches needs the waves
+template <typename T, int NTW>
+__global__ void __launch_bounds__(256, 4)
 lr_expand_kernel(const ExpandChunk *__restrict__ chunks, const ExpandEntry *__restrict__ entries,
                  int32_t kmax, int64_t tstride, const int32_t *__restrict__ ranks,
                  const T *__restrict__ L, const T *__restrict__ Tin, int64_t ncols, T sign,
                  T *__restrict__ Y, int64_t ldy, int reduced) {
   __shared__ T As[KC][64 + 1];   // [depth][row]
-  __shared__ T Bs[KC][TC + 1];   // [depth][col]
+  __shared__ T Bs[KC][16 * NTW + 1];   // [depth][col]
   __shared__ int64_t e_l[EMAX];
   __shared__ int32_t e_mq[EMAX], e_k[EMAX], e_ts[EMAX], e_ns[EMAX], e_ko[EMAX + 1];
   __shared__ int16_t d_e[KTAB];
   __shared__ int8_t d_k[KTAB];
   typedef typename Acc<T>::type acc_t;
   const ExpandChunk ch = chunks[blockIdx.x];
-  const int64_t c0 = (int64_t)blockIdx.y * TC;
+  const int64_t c0 = (int64_t)blockIdx.y * (16 * NTW);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  acc_t acc[4];
+  acc_t acc[NTW];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) acc[t] = (acc_t){0, 0, 0, 0};
+  for (int t = 0; t < NTW; ++t) acc[t] = (acc_t){0, 0, 0, 0};
 
   for (int e0 = ch.first; e0 < ch.last; e0 += EMAX) {
     const int ne = min(EMAX, ch.last - e0);
@@ -185,7 +197,7 @@ lr_expand_kernel(const ExpandChunk *__restrict__ chunks, const ExpandEntry *__re
       }
     __syncthreads();
     const int ktot = e_ko[ne];
-    T av[8], bv[8];
+    T av[8], bv[2 * NTW];
     auto fetch = [&](int k0) {
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
@@ -200,18 +212,20 @@ lr_expand_kernel(const ExpandChunk *__restrict__ chunks, const ExpandEntry *__re
           }
           av[q] = v;
         }
-        {
-          const int kt = e % KC, cc = e / KC;   // T (depth, column)
-          const int d = k0 + kt;
-          const int64_t gc = c0 + cc;
-          T v = 0;
-          if (d < ktot && gc < ncols) {
-            const int j = d_e[d];
-            const T *tp = Tin + (int64_t)e_ts[j] * tstride + gc * kmax + d_k[d];
-            for (int sg = 0; sg < e_ns[j]; ++sg) v += tp[(int64_t)sg * tstride];
-          }
-          bv[q] = v;
+      }
+#pragma unroll
+      for (int q = 0; q < 2 * NTW; ++q) {
+        const int e = tid + 256 * q;
+        const int kt = e % KC, cc = e / KC;   // T (depth, column)
+        const int d = k0 + kt;
+        const int64_t gc = c0 + cc;
+        T v = 0;
+        if (d < ktot && gc < ncols) {
+          const int j = d_e[d];
+          const T *tp = Tin + (int64_t)e_ts[j] * tstride + gc * kmax + d_k[d];
+          for (int sg = 0; sg < e_ns[j]; ++sg) v += tp[(int64_t)sg * tstride];
         }
+        bv[q] = v;
       }
     };
     if (ktot > 0) fetch(0);
@@ -220,6 +234,10 @@ lr_expand_kernel(const ExpandChunk *__restrict__ chunks, const ExpandEntry *__re
       for (int q = 0; q < 8; ++q) {
         const int e = tid + 256 * q;
         As[e / 64][e % 64] = av[q];
+      }
+#pragma unroll
+      for (int q = 0; q < 2 * NTW; ++q) {
+        const int e = tid + 256 * q;
         Bs[e % KC][e / KC] = bv[q];
       }
       __syncthreads();
@@ -228,14 +246,14 @@ lr_expand_kernel(const ExpandChunk *__restrict__ chunks, const ExpandEntry *__re
       for (int ks = 0; ks < KC; ks += 4) {
         const T a = As[ks + (lane >> 4)][16 * wave + (lane & 15)];
 #pragma unroll
-        for (int t = 0; t < 4; ++t)
+        for (int t = 0; t < NTW; ++t)
           Acc<T>::step(a, Bs[ks + (lane >> 4)][16 * t + (lane & 15)], acc[t]);
       }
       __syncthreads();
     }
   }
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
+  for (int t = 0; t < NTW; ++t) {
     const int64_t gc = c0 + 16 * t + (lane & 15);
     if (gc >= ncols) continue;
 #pragma unroll
@@ -258,24 +276,24 @@ lr_expand_kernel(const ExpandChunk *__restrict__ chunks, const ExpandEntry *__re
 constexpr int NEMAX = 32;
 constexpr int NKTAB = NEMAX * 128;
 
-template <typename T>
+template <typename T, int NTW>
 __global__ void __launch_bounds__(256, 2)
 near_kernel(const ExpandChunk *__restrict__ chunks, const NearEntry *__restrict__ entries,
             const double *__restrict__ D, const T *__restrict__ X, int64_t ldx, int64_t ncols,
             T *__restrict__ Y, int64_t ldy, int overwrite) {
   __shared__ T As[KC][64 + 1];   // [depth][row]
-  __shared__ T Bs[KC][TC + 1];   // [depth][col]
+  __shared__ T Bs[KC][16 * NTW + 1];   // [depth][col]
   __shared__ int64_t e_d[NEMAX], e_x[NEMAX];
   __shared__ int32_t e_ma[NEMAX], e_mb[NEMAX], e_tr[NEMAX], e_ko[NEMAX + 1];
   __shared__ int16_t d_e[NKTAB];
   __shared__ uint8_t d_k[NKTAB];
   typedef typename Acc<T>::type acc_t;
   const ExpandChunk ch = chunks[blockIdx.x];
-  const int64_t c0 = (int64_t)blockIdx.y * TC;
+  const int64_t c0 = (int64_t)blockIdx.y * (16 * NTW);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  acc_t acc[4];
+  acc_t acc[NTW];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) acc[t] = (acc_t){0, 0, 0, 0};
+  for (int t = 0; t < NTW; ++t) acc[t] = (acc_t){0, 0, 0, 0};
 
   for (int e0 = ch.first; e0 < ch.last; e0 += NEMAX) {
     const int ne = min(NEMAX, ch.last - e0);
@@ -307,7 +325,7 @@ near_kernel(const ExpandChunk *__restrict__ chunks, const NearEntry *__restrict_
       }
     __syncthreads();
     const int ktot = e_ko[ne];
-    T av[8], bv[8];
+    T av[8], bv[2 * NTW];
     auto fetch = [&](int k0) {
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
@@ -324,14 +342,16 @@ near_kernel(const ExpandChunk *__restrict__ chunks, const NearEntry *__restrict_
           }
           av[q] = v;
         }
-        {
-          const int kt = e % KC, cc = e / KC;   // X (depth, column)
-          const int d = k0 + kt;
-          const int64_t gc = c0 + cc;
-          T v = 0;
-          if (d < ktot && gc < ncols) v = X[gc * ldx + e_x[d_e[d]] + d_k[d]];
-          bv[q] = v;
-        }
+      }
+#pragma unroll
+      for (int q = 0; q < 2 * NTW; ++q) {
+        const int e = tid + 256 * q;
+        const int kt = e % KC, cc = e / KC;   // X (depth, column)
+        const int d = k0 + kt;
+        const int64_t gc = c0 + cc;
+        T v = 0;
+        if (d < ktot && gc < ncols) v = X[gc * ldx + e_x[d_e[d]] + d_k[d]];
+        bv[q] = v;
       }
     };
     if (ktot > 0) fetch(0);
@@ -340,6 +360,10 @@ near_kernel(const ExpandChunk *__restrict__ chunks, const NearEntry *__restrict_
       for (int q = 0; q < 8; ++q) {
         const int e = tid + 256 * q;
         As[e / 64][e % 64] = av[q];
+      }
+#pragma unroll
+      for (int q = 0; q < 2 * NTW; ++q) {
+        const int e = tid + 256 * q;
         Bs[e % KC][e / KC] = bv[q];
       }
       __syncthreads();
@@ -348,14 +372,14 @@ near_kernel(const ExpandChunk *__restrict__ chunks, const NearEntry *__restrict_
       for (int ks = 0; ks < KC; ks += 4) {
         const T a = As[ks + (lane >> 4)][16 * wave + (lane & 15)];
 #pragma unroll
-        for (int t = 0; t < 4; ++t)
+        for (int t = 0; t < NTW; ++t)
           Acc<T>::step(a, Bs[ks + (lane >> 4)][16 * t + (lane & 15)], acc[t]);
       }
       __syncthreads();
     }
   }
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
+  for (int t = 0; t < NTW; ++t) {
     const int64_t gc = c0 + 16 * t + (lane & 15);
     if (gc >= ncols) continue;
 #pragma unroll
@@ -438,19 +462,54 @@ inline unsigned col_tiles(int64_t ncols) { return (unsigned)((ncols + TC - 1) / 
 
 }  // namespace
 
+// Workgroups of 64 columns (4 MFMA column tiles per wave).  Wider tiles
+// (8 per wave, 128 columns) measured slower for all three kernels at 288
+// and 1024 columns: the kernels are bound by the latency of their operand
+// fetches, and wider tiles halve the resident workgroups that hide it.
+constexpr int kNTW = 4;
+
+template <int NTW>
+inline unsigned tiles_of(int64_t ncols) {
+  return (unsigned)((ncols + 16 * NTW - 1) / (16 * NTW));
+}
+
+template <typename T, int NTW>
+void project_ntw(int32_t nitems, const ProjItem *items, const ProjPair *pairs, int32_t kmax,
+                 int64_t tstride, const int32_t *ranks, const void *R, const void *X, int64_t ldx,
+                 int64_t ncols, void *Tb, hipStream_t s) {
+  dim3 g(nitems, tiles_of<NTW>(ncols));
+  lr_project_kernel<T, NTW><<<g, 256, 0, s>>>(items, pairs, kmax, tstride, ranks, (const T *)R,
+                                              (const T *)X, ldx, ncols, (T *)Tb);
+}
+
+template <typename T, int NTW>
+void expand_ntw(int32_t nchunks, const ExpandChunk *chunks, const ExpandEntry *entries,
+                int32_t kmax, int64_t tstride, const int32_t *ranks, const void *L,
+                const void *Tb, int64_t ncols, double sign, void *Y, int64_t ldy, bool reduced,
+                hipStream_t s) {
+  dim3 g(nchunks, tiles_of<NTW>(ncols));
+  lr_expand_kernel<T, NTW><<<g, 256, 0, s>>>(chunks, entries, kmax, tstride, ranks,
+                                             (const T *)L, (const T *)Tb, ncols, (T)sign,
+                                             (T *)Y, ldy, reduced ? 1 : 0);
+}
+
+template <typename T, int NTW>
+void near_ntw(int32_t nchunks, const ExpandChunk *chunks, const NearEntry *entries,
+              const void *D, const void *X, int64_t ldx, int64_t ncols, void *Y, int64_t ldy,
+              bool overwrite, hipStream_t s) {
+  dim3 g(nchunks, tiles_of<NTW>(ncols));
+  near_kernel<T, NTW><<<g, 256, 0, s>>>(chunks, entries, (const double *)D, (const T *)X, ldx,
+                                        ncols, (T *)Y, ldy, overwrite ? 1 : 0);
+}
+
 void launch_lr_project(int32_t nitems, const ProjItem *items, const ProjPair *pairs, int32_t kmax,
                        int64_t tstride, const int32_t *ranks, bool f32, const void *R,
                        const void *X, int64_t ldx, int64_t ncols, void *T, hipStream_t s) {
   if (nitems <= 0 || ncols <= 0) return;
-  dim3 g(nitems, col_tiles(ncols));
   if (f32)
-    lr_project_kernel<float><<<g, 256, 0, s>>>(items, pairs, kmax, tstride, ranks,
-                                               (const float *)R, (const float *)X, ldx, ncols,
-                                               (float *)T);
+    project_ntw<float, kNTW>(nitems, items, pairs, kmax, tstride, ranks, R, X, ldx, ncols, T, s);
   else
-    lr_project_kernel<double><<<g, 256, 0, s>>>(items, pairs, kmax, tstride, ranks,
-                                                (const double *)R, (const double *)X, ldx, ncols,
-                                                (double *)T);
+    project_ntw<double, kNTW>(nitems, items, pairs, kmax, tstride, ranks, R, X, ldx, ncols, T, s);
 }
 
 void launch_lr_expand(int32_t nchunks, const ExpandChunk *chunks, const ExpandEntry *entries,
@@ -458,15 +517,12 @@ void launch_lr_expand(int32_t nchunks, const ExpandChunk *chunks, const ExpandEn
                       const void *L, const void *T, int64_t ncols, double sign, void *Y,
                       int64_t ldy, bool reduced, hipStream_t s) {
   if (nchunks <= 0 || ncols <= 0) return;
-  dim3 g(nchunks, col_tiles(ncols));
   if (f32)
-    lr_expand_kernel<float><<<g, 256, 0, s>>>(chunks, entries, kmax, tstride, ranks,
-                                              (const float *)L, (const float *)T, ncols,
-                                              (float)sign, (float *)Y, ldy, reduced ? 1 : 0);
+    expand_ntw<float, kNTW>(nchunks, chunks, entries, kmax, tstride, ranks, L, T, ncols, sign, Y,
+                            ldy, reduced, s);
   else
-    lr_expand_kernel<double><<<g, 256, 0, s>>>(chunks, entries, kmax, tstride, ranks,
-                                               (const double *)L, (const double *)T, ncols, sign,
-                                               (double *)Y, ldy, reduced ? 1 : 0);
+    expand_ntw<double, kNTW>(nchunks, chunks, entries, kmax, tstride, ranks, L, T, ncols, sign, Y,
+                             ldy, reduced, s);
 }
 
 void launch_lr_reduce(int32_t nitems, const ReduceItem *items, int64_t tstride, int64_t elems,
@@ -483,13 +539,10 @@ void launch_near_apply(int32_t nchunks, const ExpandChunk *chunks, const NearEnt
                        bool f32, const void *D, const void *X, int64_t ldx, int64_t ncols,
                        void *Y, int64_t ldy, bool overwrite, hipStream_t s) {
   if (nchunks <= 0 || ncols <= 0) return;
-  dim3 g(nchunks, col_tiles(ncols));
   if (f32)
-    near_kernel<float><<<g, 256, 0, s>>>(chunks, entries, (const double *)D, (const float *)X, ldx,
-                                         ncols, (float *)Y, ldy, overwrite ? 1 : 0);
+    near_ntw<float, kNTW>(nchunks, chunks, entries, D, X, ldx, ncols, Y, ldy, overwrite, s);
   else
-    near_kernel<double><<<g, 256, 0, s>>>(chunks, entries, (const double *)D, (const double *)X,
-                                          ldx, ncols, (double *)Y, ldy, overwrite ? 1 : 0);
+    near_ntw<double, kNTW>(nchunks, chunks, entries, D, X, ldx, ncols, Y, ldy, overwrite, s);
 }
 
 void launch_dense_gemm(int64_t n, const double *A, int64_t lda, bool trans, int64_t ncols,
