@@ -53,7 +53,7 @@ def parse():
                     help="comma-separated offered loads (fractions of the FP64 capacity)")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run this many steps, no extras (for profilers)")
-    ap.add_argument("--profile-workload", default="star", choices=["star", "batched", "uniform", "product", "h2"],
+    ap.add_argument("--profile-workload", default="star", choices=["star", "mixed", "batched", "uniform", "product", "h2"],
                     help="with --profile-steps: which workload the steps run")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="with --profile-steps: add a 1 GiB device copy that calibrates "
@@ -394,8 +394,10 @@ def main():
             _, H = step(hm, inst, inst.kernel, x, y, hm.HM_PREC_F64, inst.tol)
             run_product(hm, torch, inst, H, args.profile_steps, 0)
         else:
+            prec = hm.HM_PREC_MIXED if args.profile_workload == "mixed" else hm.HM_PREC_F64
+            tol = 1e-6 if args.profile_workload == "mixed" else inst.tol
             for _ in range(args.profile_steps):
-                step(hm, inst, inst.kernel, x, y, hm.HM_PREC_F64, inst.tol,
+                step(hm, inst, inst.kernel, x, y, prec, tol,
                      uniform=args.profile_workload == "uniform",
                      h2=args.profile_workload == "h2",
                      rank=H2_RANK if args.profile_workload == "h2" else 0)

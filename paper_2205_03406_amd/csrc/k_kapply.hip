@@ -162,13 +162,21 @@ kapply_kernel(int64_t n, const double *__restrict__ pts_all, int64_t ncols,
   // kernel value of a depth beyond n is set to zero, and columns beyond
   // ncols are never stored, so nothing needs masking and the loads stay in
   // flight across the MFMA work of the current block.
+  // Element q of a thread is X(k0 + tid % BK, col0 + tid / BK + q * 256 / BK)
+  // (256 is a multiple of BK): the row is clamped once per fetch, each column
+  // in 32 bits, and the address is one 32 x 32 -> 64-bit multiply-add
+  // (column counts and leading dimensions are below 2^31).  Computed in
+  // place, so no per-element offsets stay live across the k loop.
+  static_assert(256 % BK == 0, "a thread's elements share one row");
+  const int ldx32 = (int)ldx, nc32 = (int)ncols;
   auto fetch = [&](int64_t k0) {
+    const int64_t gk = k0 + tid % BK;
+    const T *__restrict__ xk = X + (gk < nloc ? gk : nloc - 1);
+    const int cb = (int)col0 + tid / BK;
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-      const int e = tid + 256 * q;
-      const int kr = e % BK, cc = e / BK;
-      const int64_t gk = k0 + kr, gc = col0 + cc;
-      xr[q] = X[(gc < ncols ? gc : ncols - 1) * ldx + (gk < nloc ? gk : nloc - 1)];
+      const int gc = cb + q * (256 / BK);
+      xr[q] = xk[(int64_t)(gc < nc32 ? gc : nc32 - 1) * ldx32];
     }
     if (tid < BK * DIM) {
       const int64_t gk = k0 + tid % BK;
