@@ -296,6 +296,16 @@ struct hm_hmatrix {
   // H^2: singular values (kmax per box) and transfers (kmax x kmax per box,
   // to its parent); UB / VB hold the bases implied by the nesting
   hm::DBuf SU, SV, TU, TV;
+  // H^2 apply plan: boxes with long bases (whole, and 64-row chunks), per
+  // level the upward sums (transfers of the children) and the downward sums
+  // (couplings and the parent term) of the operator and of its adjoint
+  struct H2Apply {
+    hm::DBuf leaf, chunk;
+    int32_t nleaf = 0, nchunk = 0;
+    std::vector<hm::DBuf> up_j, up_t, dn_j, dn_t, dnt_j, dnt_t;
+    std::vector<int32_t> nup, ndn;
+    bool ready = false;
+  } h2a;
   std::vector<std::vector<int32_t>> ubox;
   std::vector<std::vector<int64_t>> uoff;
   std::vector<int64_t> uv0;
@@ -477,6 +487,46 @@ int64_t tscratch_elems(const hm_hmatrix &H, int64_t ncols) {
   return std::max<int64_t>(std::min(need, cap), std::max<int64_t>(minimum, 64));
 }
 
+// The H^2 part of Y += H X (or H* X) through the nested representation
+// (alg:apply_h2_level_truncated): outgoing expansions of the boxes with
+// long bases, upward pass, couplings and downward pass, expansion.
+// Expansions in stream-ordered scratch, at most 256 columns at a time.
+void h2_apply(const hm_hmatrix &H, bool trans, bool f32, const void *X, int64_t ldx,
+              int64_t ncols, void *Y, int64_t ldy, hipStream_t s) {
+  const hm_hmatrix::H2Apply &P = H.h2a;
+  const int32_t kmax = H.kmax;
+  const int64_t nb = H.nvtot;
+  const int32_t *Ur = H.brank.as<int32_t>(), *Vr = Ur + nb;
+  const int32_t *ro = trans ? Vr : Ur, *ri = trans ? Ur : Vr;  // incoming / outgoing ranks
+  const double *Bout = trans ? H.UB.as<double>() : H.VB.as<double>();  // applied to x
+  const double *Bin = trans ? H.VB.as<double>() : H.UB.as<double>();   // expands into y
+  const double *Tup = trans ? H.TU.as<double>() : H.TV.as<double>();
+  const double *Tdn = trans ? H.TV.as<double>() : H.TU.as<double>();
+  const size_t es = f32 ? 4 : 8;
+  const int64_t cw = std::min<int64_t>(ncols, 256);
+  double *QH = nullptr, *UH = nullptr;
+  HIP_TRY(hipMallocAsync((void **)&QH, (size_t)std::max<int64_t>(nb * kmax * cw, 1) * 8, s));
+  HIP_TRY(hipMallocAsync((void **)&UH, (size_t)std::max<int64_t>(nb * kmax * cw, 1) * 8, s));
+  const size_t nlv = H.lv.size();
+  for (int64_t c0 = 0; c0 < ncols; c0 += cw) {
+    const int64_t w = std::min(cw, ncols - c0);
+    const char *Xc = (const char *)X + c0 * ldx * es;
+    char *Yc = (char *)Y + c0 * ldy * es;
+    launch_h2_project(P.nleaf, P.leaf.as<H2Leaf>(), kmax, ri, Bout, f32, Xc, ldx, w, QH, w, s);
+    for (size_t li = nlv; li-- > 0;)
+      launch_h2_sum(P.nup[li], P.up_j[li].as<H2Sum>(), P.up_t[li].as<H2Term>(), kmax, ri, ri,
+                    Tup, Tup, QH, QH, QH, w, w, s);
+    for (size_t li = 0; li < nlv; ++li)
+      launch_h2_sum(P.ndn[li], (trans ? P.dnt_j[li] : P.dn_j[li]).as<H2Sum>(),
+                    (trans ? P.dnt_t[li] : P.dn_t[li]).as<H2Term>(), kmax, ro, ri,
+                    H.B.as<double>(), Tdn, QH, UH, UH, w, w, s);
+    launch_h2_expand(P.nchunk, P.chunk.as<H2Leaf>(), kmax, ro, Bin, UH, w, f32, w, Yc, ldy, s);
+    LAUNCH_CHECK();
+  }
+  HIP_TRY(hipFreeAsync(QH, s));
+  HIP_TRY(hipFreeAsync(UH, s));
+}
+
 // Y = H X or H* X (rows in `order`); stream-ordered scratch.
 void matvec_impl(const hm_hmatrix &H, bool trans, int64_t nrhs, bool f32, const void *X,
                  int64_t ldx, void *Y, int64_t ldy, int order, hipStream_t s) {
@@ -503,7 +553,10 @@ void matvec_impl(const hm_hmatrix &H, bool trans, int64_t nrhs, bool f32, const 
                     (trans ? H.nentriesT : H.nentries).as<NearEntry>(), f32, H.D.p, Xt, ldxt,
                     nrhs, Yt, ldyt, H.near_covers, s);
   LAUNCH_CHECK();
-  apply_levels(H, H.lv.size(), trans, f32, Xt, ldxt, nrhs, Yt, ldyt, 1.0, Tb, tcap, s);
+  if (H.format == HM_FORMAT_H2 && H.h2a.ready)
+    h2_apply(H, trans, f32, Xt, ldxt, nrhs, Yt, ldyt, s);
+  else
+    apply_levels(H, H.lv.size(), trans, f32, Xt, ldxt, nrhs, Yt, ldyt, 1.0, Tb, tcap, s);
   LAUNCH_CHECK();
   if (orig) {
     launch_permute_rows(n, nrhs, H.perm.as<int64_t>(), true, f32, yt, n, Y, ldy, s);
@@ -662,6 +715,7 @@ struct Compression {
   void setup_uniform(hipStream_t s);
   void record_uniform_level(size_t li, hipStream_t s, Events &ev);
   void setup_h2(hipStream_t s);
+  void build_h2_apply(const std::vector<std::vector<int32_t>> &vid, hipStream_t s);
   void record_h2_level(size_t li, hipStream_t s, Events &ev);
   void fp32_copies(size_t li, hipStream_t s);
   int inst_of_row(int64_t row) const {
@@ -1317,6 +1371,92 @@ void Compression::setup_h2(hipStream_t s) {
     put(J.nest, ne, s);
     HIP_TRY(hipStreamSynchronize(s));
   }
+  build_h2_apply(vid, s);
+}
+
+// The H^2 apply plan (alg:apply_h2_level_truncated) from the basis boxes.
+void Compression::build_h2_apply(const std::vector<std::vector<int32_t>> &vid, hipStream_t s) {
+  hm_hmatrix::H2Apply &P = H->h2a;
+  const size_t nlv = H->lv.size();
+  const int64_t km2 = (int64_t)kmax * kmax;
+  std::vector<H2Leaf> leaf, chunk;
+  P.up_j.resize(nlv);
+  P.up_t.resize(nlv);
+  P.dn_j.resize(nlv);
+  P.dn_t.resize(nlv);
+  P.dnt_j.resize(nlv);
+  P.dnt_t.resize(nlv);
+  P.nup.assign(nlv, 0);
+  P.ndn.assign(nlv, 0);
+  for (size_t li = 0; li < nlv; ++li) {
+    const hm_hmatrix::Lv &L = H->lv[li];
+    const int l = L.level;
+    const Level &Lv = T.lev[l];
+    const std::vector<int32_t> &hb = H->ubox[li];
+    const int64_t v0 = H->uv0[li];
+    // children with bases of each basis box
+    std::vector<std::vector<int32_t>> kids(hb.size());
+    if (li + 1 < nlv) {
+      const Level &Ln = T.lev[H->lv[li + 1].level];
+      for (size_t c = 0; c < H->ubox[li + 1].size(); ++c) {
+        const int a = H->ubox[li + 1][c];
+        const int32_t pv = vid[li][Ln.parent[a]];
+        if (pv >= 0) kids[pv].push_back((int32_t)(H->uv0[li + 1] + c));
+      }
+    }
+    std::unordered_map<int64_t, int64_t> pidx;
+    pidx.reserve(L.np * 2);
+    for (int64_t q = 0; q < L.np; ++q) pidx[(int64_t)L.pa[q] * Lv.nbox() + L.pb[q]] = q;
+    std::vector<H2Sum> uj, dj, dtj;
+    std::vector<H2Term> ut, dt, dtt;
+    for (size_t v = 0; v < hb.size(); ++v) {
+      const int a = hb[v];
+      const int32_t g = (int32_t)(v0 + v);
+      if (kids[v].empty()) {
+        const int32_t m = (int32_t)T.box_size(l, a);
+        leaf.push_back(H2Leaf{Lv.start[a], H->uoff[li][v], m, g, 0, 0});
+        for (int32_t r0 = 0; r0 < m; r0 += 64)
+          chunk.push_back(H2Leaf{Lv.start[a], H->uoff[li][v], m, g, r0, 0});
+      } else {
+        const int32_t t0 = (int32_t)ut.size();
+        for (int32_t c : kids[v]) ut.push_back(H2Term{c * km2, c, 0, 1});
+        uj.push_back(H2Sum{g, t0, (int32_t)ut.size(), 0});
+      }
+      // downward: couplings of the level, then the parent's incoming expansion
+      const int32_t d0 = (int32_t)dt.size(), e0 = (int32_t)dtt.size();
+      for (int32_t t = Lv.int_ptr[a]; t < Lv.int_ptr[a + 1]; ++t) {
+        const int b = Lv.intl[t];
+        const int32_t gb = (int32_t)(v0 + vid[li][b]);
+        dt.push_back(H2Term{L.offB[pidx.at((int64_t)a * Lv.nbox() + b)], gb, 0, 0});
+        dtt.push_back(H2Term{L.offB[pidx.at((int64_t)b * Lv.nbox() + a)], gb, 0, 1});
+      }
+      if (li > 0) {
+        const int32_t pv = vid[li - 1][Lv.parent[a]];
+        if (pv >= 0) {
+          const int32_t gp = (int32_t)(H->uv0[li - 1] + pv);
+          dt.push_back(H2Term{(int64_t)g * km2, gp, 1, 0});
+          dtt.push_back(H2Term{(int64_t)g * km2, gp, 1, 0});
+        }
+      }
+      dj.push_back(H2Sum{g, d0, (int32_t)dt.size(), 0});
+      dtj.push_back(H2Sum{g, e0, (int32_t)dtt.size(), 0});
+    }
+    upload(P.up_j[li], uj, s);
+    upload(P.up_t[li], ut, s);
+    upload(P.dn_j[li], dj, s);
+    upload(P.dn_t[li], dt, s);
+    upload(P.dnt_j[li], dtj, s);
+    upload(P.dnt_t[li], dtt, s);
+    P.nup[li] = (int32_t)uj.size();
+    P.ndn[li] = (int32_t)dj.size();
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  upload(P.leaf, leaf, s);
+  upload(P.chunk, chunk, s);
+  P.nleaf = (int32_t)leaf.size();
+  P.nchunk = (int32_t)chunk.size();
+  HIP_TRY(hipStreamSynchronize(s));
+  P.ready = true;
 }
 
 void Compression::record_h2_level(size_t li, hipStream_t s, Events &ev) {
@@ -1865,7 +2005,11 @@ int64_t hmatrix_device_bytes(const hm_hmatrix *H) {
   int64_t b = H->perm.bytes + H->U.bytes + H->V.bytes + H->W.bytes + H->B.bytes + H->Vf.bytes +
               H->Wf.bytes + H->D.bytes + H->ranks.bytes + H->nchunks.bytes + H->nentries.bytes +
               H->nchunksT.bytes + H->nentriesT.bytes + H->UB.bytes + H->VB.bytes + H->brank.bytes +
-              H->SU.bytes + H->SV.bytes + H->TU.bytes + H->TV.bytes;
+              H->SU.bytes + H->SV.bytes + H->TU.bytes + H->TV.bytes + H->h2a.leaf.bytes +
+              H->h2a.chunk.bytes;
+  for (const auto *v : {&H->h2a.up_j, &H->h2a.up_t, &H->h2a.dn_j, &H->h2a.dn_t, &H->h2a.dnt_j,
+                        &H->h2a.dnt_t})
+    for (const DBuf &d : *v) b += d.bytes;
   for (const hm_hmatrix::Orient *O : {&H->oA, &H->oT}) {
     b += O->items.bytes + O->ppairs.bytes + O->red.bytes;
     for (const DBuf &d : O->chunks) b += d.bytes;

@@ -273,4 +273,38 @@ struct NestJob {
 void launch_nest(int32_t njobs, const NestJob *jobs, int32_t kmax, const double *UBin,
                  const double *Tr, const int32_t *rank, double *UBout, hipStream_t s);
 
+// ---- H^2 apply (k_h2apply.hip).  Expansions QH / UH: FP64, kmax x ncols per
+// basis box g at + g * kmax * ldq (ld kmax).
+// A box holding long bases (or a 64-row chunk of it, for the expansion).
+struct H2Leaf {
+  int64_t row0;   // first row of the box
+  int64_t boff;   // its basis in UB / VB (m x kmax, ld m)
+  int32_t m;      // rows of the box
+  int32_t g;      // global basis index (ranks, expansions)
+  int32_t r0;     // first row of the chunk inside the box (expansion)
+  int32_t pad;
+};
+// QH[g] = V_g* X(rows of g), one job per box with long bases.
+void launch_h2_project(int32_t njobs, const H2Leaf *jobs, int32_t kmax, const int32_t *rank,
+                       const double *VB, bool f32, const void *X, int64_t ldx, int64_t ncols,
+                       double *QH, int64_t ldq, hipStream_t s);
+// OUT[g] = sum over the job's terms of M (x IN[src], or x PAR[src] for a parent term).
+struct H2Sum {
+  int32_t g, t0, t1, pad;
+};
+struct H2Term {
+  int64_t moff;    // matrix in Mpool (or Mpar for a parent term), kmax x kmax
+  int32_t src;     // global basis index of the input expansion
+  int16_t parent;  // 1: Mpar and PAR, ranks from rank_o
+  int16_t trans;   // 1: the matrix is applied transposed
+};
+void launch_h2_sum(int32_t njobs, const H2Sum *jobs, const H2Term *terms, int32_t kmax,
+                   const int32_t *rank_o, const int32_t *rank_i, const double *Mpool,
+                   const double *Mpar, const double *IN, const double *PAR, double *OUT,
+                   int64_t ldq, int64_t ncols, hipStream_t s);
+// Y(rows of the chunk) += U_g UH[g], one job per 64-row chunk of a box with long bases.
+void launch_h2_expand(int32_t njobs, const H2Leaf *jobs, int32_t kmax, const int32_t *rank,
+                      const double *UB, const double *UH, int64_t ldq, bool f32, int64_t ncols,
+                      void *Y, int64_t ldy, hipStream_t s);
+
 }  // namespace hm

@@ -187,3 +187,30 @@ def test_h2_kernel_fixed_rank_parity(hm):
     print("h2 fixed rank: err %.2e (oracle %.2e), worst block diff %.1e" % (err, err_o, worst))
     assert err <= 2 * err_o + 1e-12
     assert H.stats()["nfloats"] == Ho.floats()
+
+
+def test_h2_apply_matches_oracle_passes(hm):
+    """The device apply through the nested representation (upward pass,
+    couplings, downward pass) against the oracle's, forward and adjoint,
+    FP64 and FP32 right-hand sides."""
+    inst = workloads.config(1, n=3000)
+    O = oracle.OTree(inst.points, inst.leaf, inst.tree, inst.adm)
+    T = hm.Tree(inst.points, inst.leaf, inst.tree, inst.adm).color()
+    A = oracle.kernel_matrix(inst.points, inst.points, inst.kernel)
+    H = hm.compress(T, T.kernel_blackbox(inst.kernel), rank=14, r=24, seed=inst.seed, h2=True)
+    Ho = oracle.compress_h2(O, oracle.DenseBlackBox(A), 24, k=14, seed=inst.seed)
+    perm = O.perm
+    for nrhs in (1, 5, 300):
+        X = np.random.default_rng(nrhs).standard_normal((O.n, nrhs))
+        want = Ho.matvec(X)
+        Y = hm.colmajor(O.n, nrhs)
+        H.matvec(to_dev(X), Y)
+        assert np.linalg.norm(to_host(Y) - want) <= 1e-9 * np.linalg.norm(want), nrhs
+        wt = np.empty_like(X)
+        wt[perm] = Ho.apply(X[perm], transpose=True)
+        Yt = hm.colmajor(O.n, nrhs)
+        H.matvec(to_dev(X), Yt, trans=True)
+        assert np.linalg.norm(to_host(Yt) - wt) <= 1e-9 * np.linalg.norm(wt), nrhs
+        Y32 = hm.colmajor(O.n, nrhs, dtype=torch.float32)
+        H.matvec(to_dev(X, torch.float32), Y32)
+        assert np.linalg.norm(to_host(Y32) - want) <= 1e-5 * np.linalg.norm(want), nrhs
