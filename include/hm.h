@@ -349,12 +349,17 @@ hm_status hm_plan_hmatrix(const hm_plan *plan, const hm_hmatrix **H, int64_t *gr
 void hm_plan_free(hm_plan *plan);
 
 /* hm_matvec: Y = H X (the H^1 apply: all admissible blocks U B V* plus the
- * leaf neighbor blocks).  X, Y device, n x nrhs, dtype HM_F64 or HM_F32,
- * rows in `order`.  Enqueued on stream. */
+ * leaf neighbor blocks; an H^2 matrix applies through its nested form,
+ * alg:apply_h2_level_truncated: outgoing expansions, upward pass through the
+ * transfers, couplings and downward pass, expansion).  X, Y device,
+ * n x nrhs, dtype HM_F64 or HM_F32, rows in `order`.  Enqueued on stream;
+ * scratch from the stream-ordered allocator. */
 hm_status hm_matvec(const hm_hmatrix *H, int64_t nrhs, int dtype, const void *X, int64_t ldx,
                     void *Y, int64_t ldy, int order, void *stream);
 /* hm_matvec_op: hm_matvec (trans = 0) or the adjoint Y = H* X (trans = 1:
- * every admissible block V B* U*, the leaf blocks transposed). */
+ * every admissible block V B* U*, the leaf blocks transposed; for H^2 the
+ * passes with the two basis families swapped and the couplings
+ * transposed). */
 hm_status hm_matvec_op(const hm_hmatrix *H, int trans, int64_t nrhs, int dtype, const void *X,
                        int64_t ldx, void *Y, int64_t ldy, int order, void *stream);
 
