@@ -411,9 +411,10 @@ ucoupling_kernel(const UCJob *__restrict__ jobs, int32_t kmax, const T *__restri
 // ------------------------------------------------------------------ SVD bases
 // Left singular vectors of a sample block S (m x c, c <= 64) in FP64:
 // Householder QR of S in the workspace (no pivoting), one-sided Jacobi
-// (Hestenes) on the columns of R in LDS until no pair is rotated, singular
-// values = the column norms, sorted descending; U = Q [R V / sigma ; 0]
-// truncated to the rank (fixed, or the values above max(tol sigma_0,
+// (Hestenes) on the columns of R* in LDS until no pair is rotated, with the
+// rotations accumulated in J; singular values = the column norms, sorted
+// descending; U = Q [J ; 0] (the columns of J in that order) truncated to
+// the rank (fixed, or the values above max(tol sigma_0,
 // floor), at most cap), each column signed so that its largest entry is
 // positive (the first on ties).  Singular values go to sigma (kmax per job).
 __global__ void __launch_bounds__(256)
@@ -422,7 +423,8 @@ svd_basis_kernel(const QrJob *__restrict__ jobs, int32_t c, int32_t rank_fixed, 
                  int64_t lds, double *__restrict__ Wk, double *__restrict__ U,
                  double *__restrict__ sigma, int32_t kmax, int32_t *__restrict__ ranks,
                  int32_t *__restrict__ sat) {
-  __shared__ double Rs[64][65];  // [column][row]
+  __shared__ double Rs[64][65];  // R*: [column][row]
+  __shared__ double Js[64][65];  // rotations: [column][row]
   __shared__ double tau[64];
   __shared__ double sg[64];
   __shared__ int ord[64];
@@ -474,18 +476,22 @@ svd_basis_kernel(const QrJob *__restrict__ jobs, int32_t c, int32_t rank_fixed, 
     }
     __syncthreads();
   }
-  // R (kq x c, upper trapezoidal) into LDS, zero elsewhere
+  // R* (c x kq: column j is row j of R) into LDS, zero elsewhere; J = I
   for (int e = tid; e < 64 * 64; e += 256) {
     const int i = e % 64, j = e / 64;
-    Rs[j][i] = (j < c && i < kq && i <= j) ? W[(int64_t)j * m + i] : 0.0;
+    Rs[j][i] = (j < kq && i < c && i >= j) ? W[(int64_t)i * m + j] : 0.0;
+    Js[j][i] = i == j ? 1.0 : 0.0;
   }
   __syncthreads();
-  // one-sided Jacobi over round-robin pairings; tpp threads per pair (the
-  // most that 256 threads give every pair, a power of two from 8 to 32).
-  // A pair is rotated while |p.q| > 2e-14 |p| |q|: rounding keeps smaller
-  // products from vanishing, and the singular vectors are then orthogonal
-  // to that level.
-  const int ce = c + (c & 1);
+  // One-sided Jacobi on R* over round-robin pairings of its kq columns,
+  // accumulating the rotations in J: R* J = X Sigma, so R = J Sigma X* and
+  // the left singular vectors of R are the columns of J (no division by
+  // sigma).  R* converges in far fewer sweeps than R (about 8 against 13 to
+  // 20 on kernel samples, and R itself stalls when m < c).  tpp threads per
+  // pair (the most that 256 threads give every pair, a power of two from 8
+  // to 32).  A pair is rotated while |p.q| > 2e-14 |p| |q|: rounding keeps
+  // smaller products from vanishing.
+  const int ce = kq + (kq & 1);
   const int tpp = ce <= 16 ? 32 : (ce <= 32 ? 16 : 8);
   const int pk = tid / tpp, lt = tid % tpp;
   for (int sweep = 0; sweep < 40; ++sweep) {
@@ -496,8 +502,8 @@ svd_basis_kernel(const QrJob *__restrict__ jobs, int32_t c, int32_t rank_fixed, 
         const int p = (rr + pk) % (ce - 1);
         const int q = pk == 0 ? ce - 1 : (rr - pk + ce - 1) % (ce - 1);
         double al = 0.0, be = 0.0, ga = 0.0;
-        if (p < c && q < c)
-          for (int i = lt; i < kq; i += tpp) {
+        if (p < kq && q < kq)
+          for (int i = lt; i < c; i += tpp) {
             const double u = Rs[p][i], v = Rs[q][i];
             al += u * u;
             be += v * v;
@@ -508,14 +514,21 @@ svd_basis_kernel(const QrJob *__restrict__ jobs, int32_t c, int32_t rank_fixed, 
           be += __shfl_xor(be, off, tpp);
           ga += __shfl_xor(ga, off, tpp);
         }
-        if (p < c && q < c && ga != 0.0 && fabs(ga) > 2e-14 * sqrt(al * be)) {
+        if (p < kq && q < kq && ga != 0.0 && fabs(ga) > 2e-14 * sqrt(al * be)) {
           const double zeta = (be - al) / (2.0 * ga);
-          const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double t = fabs(zeta) > 1e100
+                               ? 0.5 / zeta
+                               : (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
-          for (int i = lt; i < kq; i += tpp) {
+          for (int i = lt; i < c; i += tpp) {
             const double u = Rs[p][i], v = Rs[q][i];
             Rs[p][i] = cs * u - sn * v;
             Rs[q][i] = sn * u + cs * v;
+          }
+          for (int i = lt; i < kq; i += tpp) {
+            const double u = Js[p][i], v = Js[q][i];
+            Js[p][i] = cs * u - sn * v;
+            Js[q][i] = sn * u + cs * v;
           }
           if (lt == 0) flag = 1;
         }
@@ -526,20 +539,20 @@ svd_basis_kernel(const QrJob *__restrict__ jobs, int32_t c, int32_t rank_fixed, 
     __syncthreads();
     if (again == 0) break;
   }
-  if (tid < c) {
+  if (tid < kq) {
     double s2 = 0.0;
-    for (int i = 0; i < kq; ++i) s2 += Rs[tid][i] * Rs[tid][i];
+    for (int i = 0; i < c; ++i) s2 += Rs[tid][i] * Rs[tid][i];
     sg[tid] = sqrt(s2);
   }
   __syncthreads();
-  if (tid < c) {
+  if (tid < kq) {
     int rk = 0;
-    for (int i = 0; i < c; ++i) rk += (sg[i] > sg[tid] || (sg[i] == sg[tid] && i < tid)) ? 1 : 0;
+    for (int i = 0; i < kq; ++i) rk += (sg[i] > sg[tid] || (sg[i] == sg[tid] && i < tid)) ? 1 : 0;
     ord[rk] = tid;
   }
   __syncthreads();
   if (tid == 0) {
-    const double s0 = sg[ord[0]];
+    const double s0 = kq > 0 ? sg[ord[0]] : 0.0;
     int kk, st = 0;
     if (!(s0 > 0.0)) {
       kk = 0;
@@ -557,12 +570,11 @@ svd_basis_kernel(const QrJob *__restrict__ jobs, int32_t c, int32_t rank_fixed, 
   }
   __syncthreads();
   const int kk = kk_s;
-  // U = Q [R V / sigma; 0]: the left singular vectors of R, then the reflectors
+  // U = Q [J(:, order); 0]: the left singular vectors of R, then the reflectors
   double *Uo = U + job.uslot;
   for (int j = wave; j < kk; j += 4) {
     const int col = ord[j];
-    const double inv = 1.0 / sg[col];
-    for (int i = lane; i < m; i += 64) Uo[(int64_t)j * m + i] = i < kq ? Rs[col][i] * inv : 0.0;
+    for (int i = lane; i < m; i += 64) Uo[(int64_t)j * m + i] = i < kq ? Js[col][i] : 0.0;
   }
   __syncthreads();
   for (int j = kq - 1; j >= 0; --j) {
