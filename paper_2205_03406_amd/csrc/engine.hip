@@ -21,6 +21,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <unordered_map>
@@ -56,8 +57,65 @@ hm_status fail(hm_status code, const std::string &msg) {
   } while (0)
 
 // ------------------------------------------------------------------ device buffers
+// Device blocks of H-matrices kept for reuse, per device: hipMalloc maps
+// pages eagerly (about 10 us per MB) and freeing costs 20 us to 0.3 ms per
+// buffer, milliseconds per compression for the few dozen buffers (a few
+// hundred MB) an H-matrix holds.  A block comes back only once the device
+// is idle (the H-matrix destructor synchronizes, and a block replaced while
+// a compression runs waits for the device first), so a block taken from
+// the cache has no work in flight.  At most 2 GiB per device is kept; the
+// cache is emptied when hipMalloc fails.
+struct BlockCache {
+  std::mutex mu;
+  std::multimap<size_t, void *> free[64];  // block size -> block
+  size_t held[64] = {};
+};
+BlockCache &block_cache() {
+  static BlockCache c;
+  return c;
+}
+constexpr size_t kCacheMax = size_t(2) << 30;
+// a cached block of at least b bytes and at most 2b + 1 MB (its size in b),
+// or nullptr
+void *cache_take(int dev, size_t &b) {
+  BlockCache &c = block_cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  auto it = c.free[dev].lower_bound(b);
+  if (it == c.free[dev].end() || it->first > 2 * b + (size_t(1) << 20)) return nullptr;
+  b = it->first;
+  void *p = it->second;
+  c.held[dev] -= b;
+  c.free[dev].erase(it);
+  return p;
+}
+void cache_put(int dev, void *p, size_t b) {
+  BlockCache &c = block_cache();
+  {
+    std::lock_guard<std::mutex> lk(c.mu);
+    if (c.held[dev] + b <= kCacheMax) {
+      c.free[dev].emplace(b, p);
+      c.held[dev] += b;
+      return;
+    }
+  }
+  (void)hipFree(p);
+}
+void cache_drop(int dev) {
+  BlockCache &c = block_cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  for (auto &e : c.free[dev]) (void)hipFree(e.second);
+  c.free[dev].clear();
+  c.held[dev] = 0;
+}
+// set while an H-matrix's members are destroyed after the device was synchronized
+inline bool &release_synced() {
+  thread_local bool f = false;
+  return f;
+}
+
 // Device buffer.  alloc(): plain hipMalloc / hipFree, for objects that
-// outlive the call that makes them (trees, H-matrices).  temp(): stream-
+// outlive the call that makes them (trees).  cached(): the block cache above,
+// for the buffers of H-matrices.  temp(): stream-
 // ordered hipMallocAsync / hipFreeAsync on the stream of the work that uses
 // it, so the scratch of one compression is freed without waiting on work
 // that other streams (other requests) have in flight.
@@ -66,12 +124,18 @@ struct DBuf {
   size_t bytes = 0;
   hipStream_t st = nullptr;
   bool async = false;
+  bool in_cache = false;  // from the block cache (cap bytes, device dev)
+  size_t cap = 0;
+  int dev = 0;
   DBuf() = default;
   DBuf(const DBuf &) = delete;
   DBuf &operator=(const DBuf &) = delete;
-  DBuf(DBuf &&o) noexcept : p(o.p), bytes(o.bytes), st(o.st), async(o.async) {
+  DBuf(DBuf &&o) noexcept
+      : p(o.p), bytes(o.bytes), st(o.st), async(o.async), in_cache(o.in_cache), cap(o.cap),
+        dev(o.dev) {
     o.p = nullptr;
     o.bytes = 0;
+    o.in_cache = false;
   }
   DBuf &operator=(DBuf &&o) noexcept {
     release();
@@ -79,8 +143,12 @@ struct DBuf {
     bytes = o.bytes;
     st = o.st;
     async = o.async;
+    in_cache = o.in_cache;
+    cap = o.cap;
+    dev = o.dev;
     o.p = nullptr;
     o.bytes = 0;
+    o.in_cache = false;
     return *this;
   }
   ~DBuf() { release(); }
@@ -95,6 +163,33 @@ struct DBuf {
     bytes = b;
     async = false;
   }
+  void cached(size_t b) {
+    release();
+    if (b == 0) b = 64;
+    b = (b + 255) / 256 * 256;
+    if (hipGetDevice(&dev) != hipSuccess) {
+      (void)hipGetLastError();
+      throw Error{HM_E_DEVICE, "hipGetDevice failed"};
+    }
+    size_t blk = b;
+    p = cache_take(dev, blk);
+    if (!p) {
+      if (hipMalloc(&p, b) != hipSuccess) {
+        (void)hipGetLastError();
+        cache_drop(dev);
+        if (hipMalloc(&p, b) != hipSuccess) {
+          p = nullptr;
+          (void)hipGetLastError();
+          throw Error{HM_E_NOMEM, "device allocation of " + std::to_string(b) + " bytes failed"};
+        }
+      }
+      blk = b;
+    }
+    bytes = b;
+    cap = blk;
+    async = false;
+    in_cache = true;
+  }
   void temp(size_t b, hipStream_t s) {
     release();
     if (b == 0) b = 64;
@@ -108,9 +203,15 @@ struct DBuf {
     async = true;
   }
   void release() {
-    if (p) (void)(async ? hipFreeAsync(p, st) : hipFree(p));
+    if (p && in_cache) {
+      if (!release_synced()) (void)hipDeviceSynchronize();
+      cache_put(dev, p, cap);
+    } else if (p) {
+      (void)(async ? hipFreeAsync(p, st) : hipFree(p));
+    }
     p = nullptr;
     bytes = 0;
+    in_cache = false;
   }
   template <class T>
   T *as() const {
@@ -121,6 +222,14 @@ struct DBuf {
 template <class T>
 void upload(DBuf &d, const std::vector<T> &v, hipStream_t s) {
   d.alloc(v.size() * sizeof(T));
+  if (!v.empty())
+    HIP_TRY(hipMemcpyAsync(d.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+}
+
+// upload into a cached block (the buffers of H-matrices)
+template <class T>
+void upload_cached(DBuf &d, const std::vector<T> &v, hipStream_t s) {
+  d.cached(v.size() * sizeof(T));
   if (!v.empty())
     HIP_TRY(hipMemcpyAsync(d.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
 }
@@ -250,6 +359,16 @@ int dense_bb_apply(void *ctx, int transpose, int64_t n, int64_t ncols, int dtype
 
 // ------------------------------------------------------------------ the H-matrix
 struct hm_hmatrix {
+  // first member, so destroyed last: ends the synchronized release of the
+  // others and restores the caller's device
+  struct ReleaseScope {
+    int cur = -1;  // the caller's device while the members are released
+    ~ReleaseScope() {
+      hm::release_synced() = false;
+      int d = -1;
+      if (cur >= 0 && hipGetDevice(&d) == hipSuccess && d != cur) (void)hipSetDevice(cur);
+    }
+  } release_scope_;
   struct Lv {
     int level = 0;
     int64_t np = 0;   // pairs
@@ -312,6 +431,16 @@ struct hm_hmatrix {
   int64_t nvtot = 0;
   std::vector<int32_t> h_brank;
   hm_stats stats{};
+  // Buffers return to the block cache once the device is idle (as hipFree
+  // would wait): synchronize here, the members are released after this body
+  // with release_synced() set, and the first member (destroyed last) clears it.
+  ~hm_hmatrix() {
+    (void)hipGetDevice(&release_scope_.cur);
+    if (device != release_scope_.cur) (void)hipSetDevice(device);
+    (void)hipDeviceSynchronize();
+    (void)hipGetLastError();
+    hm::release_synced() = true;
+  }
 };
 
 namespace hm {
@@ -379,9 +508,9 @@ void build_apply_plans(hm_hmatrix &H, const Tree &T, hipStream_t s) {
       O.items_upto.push_back((int32_t)items.size());
       O.slots_upto.push_back(slots);
     }
-    upload(O.items, items, s);
-    upload(O.ppairs, pps, s);
-    upload(O.red, reds, s);
+    upload_cached(O.items, items, s);
+    upload_cached(O.ppairs, pps, s);
+    upload_cached(O.red, reds, s);
     HIP_TRY(hipStreamSynchronize(s));
     // expand plans
     O.chunks.clear();
@@ -436,8 +565,8 @@ void build_apply_plans(hm_hmatrix &H, const Tree &T, hipStream_t s) {
           if (c.last > c.first) ch.push_back(c);
         }
       }
-      upload(O.chunks[le], ch, s);
-      upload(O.entries[le], en, s);
+      upload_cached(O.chunks[le], ch, s);
+      upload_cached(O.entries[le], en, s);
       O.nch[le] = (int32_t)ch.size();
       HIP_TRY(hipStreamSynchronize(s));
     }
@@ -788,7 +917,7 @@ hm_status Compression::setup(hipStream_t s) {
   H->r = r;
   H->kmax = kmax;
   for (const Level &Lv : T.lev) H->start.push_back(Lv.start);
-  H->perm.alloc(n * sizeof(int64_t));
+  H->perm.cached(n * sizeof(int64_t));
   HIP_TRY(hipMemcpyAsync(H->perm.p, D->perm.p, n * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
 
   // ---------------- layout of the factor pools
@@ -819,13 +948,13 @@ hm_status Compression::setup(hipStream_t s) {
     H->lv.push_back(std::move(L));
   }
   H->np_total = np_total;
-  H->U.alloc(szU * 8);
-  H->W.alloc(szU * 8);
-  H->V.alloc(szV * 8);
-  H->B.alloc(szB * 8);
-  H->Wf.alloc(szU * 4);
-  H->Vf.alloc(szV * 4);
-  H->ranks.alloc(2 * np_total * sizeof(int32_t));
+  H->U.cached(szU * 8);
+  H->W.cached(szU * 8);
+  H->V.cached(szV * 8);
+  H->B.cached(szB * 8);
+  H->Wf.cached(szU * 4);
+  H->Vf.cached(szV * 4);
+  H->ranks.cached(2 * np_total * sizeof(int32_t));
   build_apply_plans(*H, T, s);
 
   // leaf neighbor blocks
@@ -865,8 +994,8 @@ hm_status Compression::setup(hipStream_t s) {
       }
       i = j;
     }
-    upload(H->nchunks, ch, s);
-    upload(H->nentries, en, s);
+    upload_cached(H->nchunks, ch, s);
+    upload_cached(H->nentries, en, s);
     H->nnch = (int32_t)ch.size();
     // the adjoint's near field: block (a, b) of H* is D_(b,a)^T (neighbor
     // pairs come in both orders)
@@ -889,14 +1018,14 @@ hm_status Compression::setup(hipStream_t s) {
       c.first = first;
       c.last = (int32_t)enT.size();
     }
-    upload(H->nchunksT, ch, s);
-    upload(H->nentriesT, enT, s);
+    upload_cached(H->nchunksT, ch, s);
+    upload_cached(H->nentriesT, enT, s);
     // every row has a near block (a box is its own neighbor): the near
     // field can open an apply by writing Y
     int64_t covered = 0;
     for (const ExpandChunk &c : ch) covered += c.nrows;
     H->near_covers = covered == T.n;
-    H->D.alloc(szD * 8);
+    H->D.cached(szD * 8);
     HIP_TRY(hipStreamSynchronize(s));
   }
 
@@ -1059,9 +1188,9 @@ void Compression::setup_uniform(hipStream_t s) {
     }
     H->nvtot += UG.nv();
   }
-  H->UB.alloc((size_t)std::max<int64_t>(szb, 1) * 8);
-  H->VB.alloc((size_t)std::max<int64_t>(szb, 1) * 8);
-  H->brank.alloc((size_t)std::max<int64_t>(2 * H->nvtot, 1) * 4);
+  H->UB.cached((size_t)std::max<int64_t>(szb, 1) * 8);
+  H->VB.cached((size_t)std::max<int64_t>(szb, 1) * 8);
+  H->brank.cached((size_t)std::max<int64_t>(2 * H->nvtot, 1) * 4);
   buf(Sb, (size_t)n * kmax * 8, s);
   buf(usat, (size_t)std::max<int64_t>(2 * H->nvtot, 1) * 4, s);
 
@@ -1206,13 +1335,13 @@ void Compression::setup_h2(hipStream_t s) {
     H->nvtot += (int64_t)H->ubox[li].size();
   }
   const int64_t nb = H->nvtot;
-  H->UB.alloc((size_t)std::max<int64_t>(szb, 1) * 8);
-  H->VB.alloc((size_t)std::max<int64_t>(szb, 1) * 8);
-  H->brank.alloc((size_t)std::max<int64_t>(2 * nb, 1) * 4);
-  H->SU.alloc((size_t)std::max<int64_t>(nb * kmax, 1) * 8);
-  H->SV.alloc((size_t)std::max<int64_t>(nb * kmax, 1) * 8);
-  H->TU.alloc((size_t)std::max<int64_t>(nb * kmax * kmax, 1) * 8);
-  H->TV.alloc((size_t)std::max<int64_t>(nb * kmax * kmax, 1) * 8);
+  H->UB.cached((size_t)std::max<int64_t>(szb, 1) * 8);
+  H->VB.cached((size_t)std::max<int64_t>(szb, 1) * 8);
+  H->brank.cached((size_t)std::max<int64_t>(2 * nb, 1) * 4);
+  H->SU.cached((size_t)std::max<int64_t>(nb * kmax, 1) * 8);
+  H->SV.cached((size_t)std::max<int64_t>(nb * kmax, 1) * 8);
+  H->TU.cached((size_t)std::max<int64_t>(nb * kmax * kmax, 1) * 8);
+  H->TV.cached((size_t)std::max<int64_t>(nb * kmax * kmax, 1) * 8);
   buf(Sb, (size_t)n * r * 8, s);
   buf(usat, (size_t)std::max<int64_t>(2 * nb, 1) * 4, s);
   if (mixed) {
@@ -1441,18 +1570,18 @@ void Compression::build_h2_apply(const std::vector<std::vector<int32_t>> &vid, h
       dj.push_back(H2Sum{g, d0, (int32_t)dt.size(), 0});
       dtj.push_back(H2Sum{g, e0, (int32_t)dtt.size(), 0});
     }
-    upload(P.up_j[li], uj, s);
-    upload(P.up_t[li], ut, s);
-    upload(P.dn_j[li], dj, s);
-    upload(P.dn_t[li], dt, s);
-    upload(P.dnt_j[li], dtj, s);
-    upload(P.dnt_t[li], dtt, s);
+    upload_cached(P.up_j[li], uj, s);
+    upload_cached(P.up_t[li], ut, s);
+    upload_cached(P.dn_j[li], dj, s);
+    upload_cached(P.dn_t[li], dt, s);
+    upload_cached(P.dnt_j[li], dtj, s);
+    upload_cached(P.dnt_t[li], dtt, s);
     P.nup[li] = (int32_t)uj.size();
     P.ndn[li] = (int32_t)dj.size();
     HIP_TRY(hipStreamSynchronize(s));
   }
-  upload(P.leaf, leaf, s);
-  upload(P.chunk, chunk, s);
+  upload_cached(P.leaf, leaf, s);
+  upload_cached(P.chunk, chunk, s);
   P.nleaf = (int32_t)leaf.size();
   P.nchunk = (int32_t)chunk.size();
   HIP_TRY(hipStreamSynchronize(s));
