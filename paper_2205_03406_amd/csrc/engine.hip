@@ -112,6 +112,26 @@ inline bool &release_synced() {
   thread_local bool f = false;
   return f;
 }
+// Declared as the first member of an owner of cached blocks (so destroyed
+// last): the owner's destructor body calls begin(), which makes the owner's
+// device current, waits until it is idle and lets the members that follow
+// go back to the cache without waiting again; this member then ends that
+// and restores the caller's device.
+struct SyncedRelease {
+  int cur = -1;
+  void begin(int device) {
+    (void)hipGetDevice(&cur);
+    if (device >= 0 && device != cur) (void)hipSetDevice(device);
+    (void)hipDeviceSynchronize();
+    (void)hipGetLastError();
+    release_synced() = true;
+  }
+  ~SyncedRelease() {
+    release_synced() = false;
+    int d = -1;
+    if (cur >= 0 && hipGetDevice(&d) == hipSuccess && d != cur) (void)hipSetDevice(cur);
+  }
+};
 
 // Device buffer.  alloc(): plain hipMalloc / hipFree, for objects that
 // outlive the call that makes them (trees).  cached(): the block cache above,
@@ -246,7 +266,9 @@ inline int64_t pad16(int64_t x) { return (x + 15) / 16 * 16; }
 
 // ------------------------------------------------------------------ device tree
 struct DeviceTree {
+  SyncedRelease rel;  // first: destroyed last
   int device = -1;
+  ~DeviceTree() { rel.begin(device); }
   DBuf pts;                    // dim x n, tree order
   DBuf perm;                   // n (tree -> original)
   std::vector<DBuf> rowbox;    // per level: box of every row
@@ -283,8 +305,8 @@ DeviceTree &device_tree(Tree &T, hipStream_t s) {
   std::vector<double> soa((size_t)T.dim * T.n);
   for (int64_t i = 0; i < T.n; ++i)
     for (int d = 0; d < T.dim; ++d) soa[(size_t)d * T.n + i] = T.pts[T.perm[i] * T.dim + d];
-  upload(D->pts, soa, s);
-  upload(D->perm, T.perm, s);
+  upload_cached(D->pts, soa, s);
+  upload_cached(D->perm, T.perm, s);
   D->rowbox.resize(T.nlev());
   D->start.resize(T.nlev());
   for (int l = 0; l < T.nlev(); ++l) {
@@ -292,13 +314,13 @@ DeviceTree &device_tree(Tree &T, hipStream_t s) {
     const Level &Lv = T.lev[l];
     for (int b = 0; b < Lv.nbox(); ++b)
       for (int64_t i = Lv.start[b]; i < Lv.start[b + 1]; ++i) rb[i] = b;
-    upload(D->rowbox[l], rb, s);
-    upload(D->start[l], Lv.start, s);
+    upload_cached(D->rowbox[l], rb, s);
+    upload_cached(D->start[l], Lv.start, s);
   }
-  upload(D->inst_off, T.inst_off.empty() ? std::vector<int64_t>{0, T.n} : T.inst_off, s);
+  upload_cached(D->inst_off, T.inst_off.empty() ? std::vector<int64_t>{0, T.n} : T.inst_off, s);
   if (T.ninst() > 1) {
     std::vector<KItem> it = forest_items(T, std::vector<int32_t>(T.ninst(), INT32_MAX));
-    upload(D->kitems, it, s);
+    upload_cached(D->kitems, it, s);
     D->nkitems = (int32_t)it.size();
   }
   HIP_TRY(hipStreamSynchronize(s));
@@ -359,16 +381,7 @@ int dense_bb_apply(void *ctx, int transpose, int64_t n, int64_t ncols, int dtype
 
 // ------------------------------------------------------------------ the H-matrix
 struct hm_hmatrix {
-  // first member, so destroyed last: ends the synchronized release of the
-  // others and restores the caller's device
-  struct ReleaseScope {
-    int cur = -1;  // the caller's device while the members are released
-    ~ReleaseScope() {
-      hm::release_synced() = false;
-      int d = -1;
-      if (cur >= 0 && hipGetDevice(&d) == hipSuccess && d != cur) (void)hipSetDevice(cur);
-    }
-  } release_scope_;
+  hm::SyncedRelease rel;  // first: destroyed last
   struct Lv {
     int level = 0;
     int64_t np = 0;   // pairs
@@ -431,16 +444,8 @@ struct hm_hmatrix {
   int64_t nvtot = 0;
   std::vector<int32_t> h_brank;
   hm_stats stats{};
-  // Buffers return to the block cache once the device is idle (as hipFree
-  // would wait): synchronize here, the members are released after this body
-  // with release_synced() set, and the first member (destroyed last) clears it.
-  ~hm_hmatrix() {
-    (void)hipGetDevice(&release_scope_.cur);
-    if (device != release_scope_.cur) (void)hipSetDevice(device);
-    (void)hipDeviceSynchronize();
-    (void)hipGetLastError();
-    hm::release_synced() = true;
-  }
+  // the buffers return to the block cache once the device is idle
+  ~hm_hmatrix() { rel.begin(device); }
 };
 
 namespace hm {
