@@ -126,6 +126,12 @@ struct SyncedRelease {
     (void)hipGetLastError();
     release_synced() = true;
   }
+  // the same for buffers used on stream s only
+  void begin_stream(hipStream_t s) {
+    (void)hipStreamSynchronize(s);
+    (void)hipGetLastError();
+    release_synced() = true;
+  }
   ~SyncedRelease() {
     release_synced() = false;
     int d = -1;
@@ -145,14 +151,15 @@ struct DBuf {
   hipStream_t st = nullptr;
   bool async = false;
   bool in_cache = false;  // from the block cache (cap bytes, device dev)
+  bool stream_owned = false;  // returns once st is idle (else the device)
   size_t cap = 0;
   int dev = 0;
   DBuf() = default;
   DBuf(const DBuf &) = delete;
   DBuf &operator=(const DBuf &) = delete;
   DBuf(DBuf &&o) noexcept
-      : p(o.p), bytes(o.bytes), st(o.st), async(o.async), in_cache(o.in_cache), cap(o.cap),
-        dev(o.dev) {
+      : p(o.p), bytes(o.bytes), st(o.st), async(o.async), in_cache(o.in_cache),
+        stream_owned(o.stream_owned), cap(o.cap), dev(o.dev) {
     o.p = nullptr;
     o.bytes = 0;
     o.in_cache = false;
@@ -164,6 +171,7 @@ struct DBuf {
     st = o.st;
     async = o.async;
     in_cache = o.in_cache;
+    stream_owned = o.stream_owned;
     cap = o.cap;
     dev = o.dev;
     o.p = nullptr;
@@ -182,6 +190,13 @@ struct DBuf {
     }
     bytes = b;
     async = false;
+  }
+  // a cached block used on stream s only: it returns once s is idle, so
+  // work of other streams is not waited on
+  void scratch(size_t b, hipStream_t s) {
+    cached(b);
+    st = s;
+    stream_owned = true;
   }
   void cached(size_t b) {
     release();
@@ -224,7 +239,7 @@ struct DBuf {
   }
   void release() {
     if (p && in_cache) {
-      if (!release_synced()) (void)hipDeviceSynchronize();
+      if (!release_synced()) (void)(stream_owned ? hipStreamSynchronize(st) : hipDeviceSynchronize());
       cache_put(dev, p, cap);
     } else if (p) {
       (void)(async ? hipFreeAsync(p, st) : hipFree(p));
@@ -232,6 +247,7 @@ struct DBuf {
     p = nullptr;
     bytes = 0;
     in_cache = false;
+    stream_owned = false;
   }
   template <class T>
   T *as() const {
@@ -254,13 +270,6 @@ void upload_cached(DBuf &d, const std::vector<T> &v, hipStream_t s) {
     HIP_TRY(hipMemcpyAsync(d.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
 }
 
-// upload into stream-ordered scratch (see DBuf::temp)
-template <class T>
-void upload_temp(DBuf &d, const std::vector<T> &v, hipStream_t s) {
-  d.temp(v.size() * sizeof(T), s);
-  if (!v.empty())
-    HIP_TRY(hipMemcpyAsync(d.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
-}
 
 inline int64_t pad16(int64_t x) { return (x + 15) / 16 * 16; }
 
@@ -800,6 +809,9 @@ double qr_flops(int64_t m, int64_t r, int64_t k) {
 // be captured into a HIP graph and replayed; finalize() reads the ranks
 // back and fills the statistics.
 struct Compression {
+  SyncedRelease rel;           // first: destroyed last
+  hipStream_t home = nullptr;  // the stream of the setup and the level work
+  ~Compression() { rel.begin_stream(home); }
   Tree &T;
   hm_blackbox bb;
   hm_compress_opts o;
@@ -861,18 +873,24 @@ struct Compression {
   Compression(Tree &t, const hm_blackbox &b, const hm_compress_opts &opt)
       : T(t), bb(b), o(opt) {}
 
+  // scratch of one compression: cached blocks owned by its stream (the
+  // compression waits for the stream before it ends), plain allocations for
+  // a plan, whose captured launches keep them
   void buf(DBuf &d, size_t bytes, hipStream_t s) {
     if (persistent)
       d.alloc(bytes);
     else
-      d.temp(bytes, s);
+      d.scratch(bytes, s);
   }
   template <class V>
   void put(DBuf &d, const std::vector<V> &v, hipStream_t s) {
-    if (persistent)
+    if (persistent) {
       upload(d, v, s);
-    else
-      upload_temp(d, v, s);
+    } else {
+      d.scratch(v.size() * sizeof(V), s);
+      if (!v.empty())
+        HIP_TRY(hipMemcpyAsync(d.p, v.data(), v.size() * sizeof(V), hipMemcpyHostToDevice, s));
+    }
   }
   // live colors of each instance in graph g
   std::vector<int32_t> inst_colors(int g) const {
@@ -890,6 +908,7 @@ struct Compression {
 };
 
 hm_status Compression::setup(hipStream_t s) {
+  home = s;
   // ---------------- options
   if (T.n <= 0) return fail(HM_E_ARG, "empty tree");
   for (const Graph &G : T.graphs)
