@@ -443,6 +443,11 @@ struct hm_hmatrix {
   struct H2Apply {
     hm::DBuf leaf, chunk;
     int32_t nleaf = 0, nchunk = 0;
+    // [li]: boxes projected and expanded by the operator of the first li
+    // levels (the level-truncated product of the peel): the boxes of level
+    // li - 1 and the coarser ones without children holding bases
+    std::vector<hm::DBuf> tleaf, tchunk;
+    std::vector<int32_t> ntleaf, ntchunk;
     std::vector<hm::DBuf> up_j, up_t, dn_j, dn_t, dnt_j, dnt_t;
     std::vector<int32_t> nup, ndn;
     bool ready = false;
@@ -630,13 +635,21 @@ int64_t tscratch_elems(const hm_hmatrix &H, int64_t ncols) {
   return std::max<int64_t>(std::min(need, cap), std::max<int64_t>(minimum, 64));
 }
 
-// The H^2 part of Y += H X (or H* X) through the nested representation
+// The H^2 part of Y += sign H X (or H* X) through the nested representation
 // (alg:apply_h2_level_truncated): outgoing expansions of the boxes with
-// long bases, upward pass, couplings and downward pass, expansion.
-// Expansions in stream-ordered scratch, at most 256 columns at a time.
-void h2_apply(const hm_hmatrix &H, bool trans, bool f32, const void *X, int64_t ldx,
-              int64_t ncols, void *Y, int64_t ldy, hipStream_t s) {
+// long bases, upward pass, couplings and downward pass, expansion.  With
+// le < the number of levels, the operator of the first le levels (the
+// level-truncated product of the peel): its long bases are those of level
+// le - 1 and of the coarser boxes without children holding bases.
+// Expansions in QH / UH (nvtot x kmax x qcols each) when given, else in
+// stream-ordered scratch; at most 256 columns at a time.
+void h2_apply(const hm_hmatrix &H, size_t le, bool trans, bool f32, const void *X, int64_t ldx,
+              int64_t ncols, void *Y, int64_t ldy, double sign, double *qh, double *uh,
+              int64_t qcols, hipStream_t s) {
   const hm_hmatrix::H2Apply &P = H.h2a;
+  const size_t nlv = H.lv.size();
+  if (le == 0 || ncols <= 0) return;
+  if (le > nlv) le = nlv;
   const int32_t kmax = H.kmax;
   const int64_t nb = H.nvtot;
   const int32_t *Ur = H.brank.as<int32_t>(), *Vr = Ur + nb;
@@ -645,29 +658,40 @@ void h2_apply(const hm_hmatrix &H, bool trans, bool f32, const void *X, int64_t 
   const double *Bin = trans ? H.VB.as<double>() : H.UB.as<double>();   // expands into y
   const double *Tup = trans ? H.TU.as<double>() : H.TV.as<double>();
   const double *Tdn = trans ? H.TV.as<double>() : H.TU.as<double>();
+  const bool full = le == nlv;
+  const H2Leaf *leaf = (full ? P.leaf : P.tleaf[le]).as<H2Leaf>();
+  const H2Leaf *chunk = (full ? P.chunk : P.tchunk[le]).as<H2Leaf>();
+  const int32_t nleaf = full ? P.nleaf : P.ntleaf[le];
+  const int32_t nchunk = full ? P.nchunk : P.ntchunk[le];
   const size_t es = f32 ? 4 : 8;
-  const int64_t cw = std::min<int64_t>(ncols, 256);
-  double *QH = nullptr, *UH = nullptr;
-  HIP_TRY(hipMallocAsync((void **)&QH, (size_t)std::max<int64_t>(nb * kmax * cw, 1) * 8, s));
-  HIP_TRY(hipMallocAsync((void **)&UH, (size_t)std::max<int64_t>(nb * kmax * cw, 1) * 8, s));
-  const size_t nlv = H.lv.size();
+  const bool own = qh == nullptr;
+  const int64_t cw = own ? std::min<int64_t>(ncols, 256) : std::min<int64_t>(ncols, qcols);
+  if (cw < 1) throw Error{HM_E_NOMEM, "H2 expansion scratch too small"};
+  double *QH = qh, *UH = uh;
+  if (own) {
+    HIP_TRY(hipMallocAsync((void **)&QH, (size_t)std::max<int64_t>(nb * kmax * cw, 1) * 8, s));
+    HIP_TRY(hipMallocAsync((void **)&UH, (size_t)std::max<int64_t>(nb * kmax * cw, 1) * 8, s));
+  }
   for (int64_t c0 = 0; c0 < ncols; c0 += cw) {
     const int64_t w = std::min(cw, ncols - c0);
     const char *Xc = (const char *)X + c0 * ldx * es;
     char *Yc = (char *)Y + c0 * ldy * es;
-    launch_h2_project(P.nleaf, P.leaf.as<H2Leaf>(), kmax, ri, Bout, f32, Xc, ldx, w, QH, w, s);
-    for (size_t li = nlv; li-- > 0;)
+    launch_h2_project(nleaf, leaf, kmax, ri, Bout, f32, Xc, ldx, w, QH, w, s);
+    // upward: level li from its children on li + 1 (< le)
+    for (size_t li = le - 1; li-- > 0;)
       launch_h2_sum(P.nup[li], P.up_j[li].as<H2Sum>(), P.up_t[li].as<H2Term>(), kmax, ri, ri,
                     Tup, Tup, QH, QH, QH, w, w, s);
-    for (size_t li = 0; li < nlv; ++li)
+    for (size_t li = 0; li < le; ++li)
       launch_h2_sum(P.ndn[li], (trans ? P.dnt_j[li] : P.dn_j[li]).as<H2Sum>(),
                     (trans ? P.dnt_t[li] : P.dn_t[li]).as<H2Term>(), kmax, ro, ri,
                     H.B.as<double>(), Tdn, QH, UH, UH, w, w, s);
-    launch_h2_expand(P.nchunk, P.chunk.as<H2Leaf>(), kmax, ro, Bin, UH, w, f32, w, Yc, ldy, s);
+    launch_h2_expand(nchunk, chunk, kmax, ro, Bin, UH, w, f32, w, Yc, ldy, sign, s);
     LAUNCH_CHECK();
   }
-  HIP_TRY(hipFreeAsync(QH, s));
-  HIP_TRY(hipFreeAsync(UH, s));
+  if (own) {
+    HIP_TRY(hipFreeAsync(QH, s));
+    HIP_TRY(hipFreeAsync(UH, s));
+  }
 }
 
 // Y = H X or H* X (rows in `order`); stream-ordered scratch.
@@ -697,7 +721,7 @@ void matvec_impl(const hm_hmatrix &H, bool trans, int64_t nrhs, bool f32, const 
                     nrhs, Yt, ldyt, H.near_covers, s);
   LAUNCH_CHECK();
   if (H.format == HM_FORMAT_H2 && H.h2a.ready)
-    h2_apply(H, trans, f32, Xt, ldxt, nrhs, Yt, ldyt, s);
+    h2_apply(H, H.lv.size(), trans, f32, Xt, ldxt, nrhs, Yt, ldyt, 1.0, nullptr, nullptr, 0, s);
   else
     apply_levels(H, H.lv.size(), trans, f32, Xt, ldxt, nrhs, Yt, ldyt, 1.0, Tb, tcap, s);
   LAUNCH_CHECK();
@@ -857,6 +881,8 @@ struct Compression {
   };
   std::vector<UniformJobs> ujobs_of;
   DBuf Sb, usat;
+  DBuf h2q, h2u;       // H^2: expansions of the level-truncated products
+  int64_t h2cols = 0;  // columns they hold
   bool h2 = false;  // H^2: uniform stages with augmented SVD bases, nested
   void setup_uniform(hipStream_t s);
   void record_uniform_level(size_t li, hipStream_t s, Events &ev);
@@ -1366,6 +1392,11 @@ void Compression::setup_h2(hipStream_t s) {
   H->SV.cached((size_t)std::max<int64_t>(nb * kmax, 1) * 8);
   H->TU.cached((size_t)std::max<int64_t>(nb * kmax * kmax, 1) * 8);
   H->TV.cached((size_t)std::max<int64_t>(nb * kmax * kmax, 1) * 8);
+  // expansion scratch of the peel's level-truncated products, at most 64 MB each
+  h2cols = std::min<int64_t>(256, std::max<int64_t>(16, (int64_t(64) << 20) /
+                                                            std::max<int64_t>(nb * kmax * 8, 1)));
+  buf(h2q, (size_t)std::max<int64_t>(nb * kmax * h2cols, 1) * 8, s);
+  buf(h2u, (size_t)std::max<int64_t>(nb * kmax * h2cols, 1) * 8, s);
   buf(Sb, (size_t)n * r * 8, s);
   buf(usat, (size_t)std::max<int64_t>(2 * nb, 1) * 4, s);
   if (mixed) {
@@ -1533,6 +1564,9 @@ void Compression::build_h2_apply(const std::vector<std::vector<int32_t>> &vid, h
   const size_t nlv = H->lv.size();
   const int64_t km2 = (int64_t)kmax * kmax;
   std::vector<H2Leaf> leaf, chunk;
+  // per level: every basis box as a leaf record, and whether it has children with bases
+  std::vector<std::vector<H2Leaf>> all_of(nlv);
+  std::vector<std::vector<uint8_t>> haskids(nlv);
   P.up_j.resize(nlv);
   P.up_t.resize(nlv);
   P.dn_j.resize(nlv);
@@ -1562,15 +1596,18 @@ void Compression::build_h2_apply(const std::vector<std::vector<int32_t>> &vid, h
     for (int64_t q = 0; q < L.np; ++q) pidx[(int64_t)L.pa[q] * Lv.nbox() + L.pb[q]] = q;
     std::vector<H2Sum> uj, dj, dtj;
     std::vector<H2Term> ut, dt, dtt;
+    haskids[li].assign(hb.size(), 0);
     for (size_t v = 0; v < hb.size(); ++v) {
       const int a = hb[v];
       const int32_t g = (int32_t)(v0 + v);
+      all_of[li].push_back(H2Leaf{Lv.start[a], H->uoff[li][v], (int32_t)T.box_size(l, a), g, 0, 0});
       if (kids[v].empty()) {
         const int32_t m = (int32_t)T.box_size(l, a);
         leaf.push_back(H2Leaf{Lv.start[a], H->uoff[li][v], m, g, 0, 0});
         for (int32_t r0 = 0; r0 < m; r0 += 64)
           chunk.push_back(H2Leaf{Lv.start[a], H->uoff[li][v], m, g, r0, 0});
       } else {
+        haskids[li][v] = 1;
         const int32_t t0 = (int32_t)ut.size();
         for (int32_t c : kids[v]) ut.push_back(H2Term{c * km2, c, 0, 1});
         uj.push_back(H2Sum{g, t0, (int32_t)ut.size(), 0});
@@ -1608,6 +1645,26 @@ void Compression::build_h2_apply(const std::vector<std::vector<int32_t>> &vid, h
   upload_cached(P.chunk, chunk, s);
   P.nleaf = (int32_t)leaf.size();
   P.nchunk = (int32_t)chunk.size();
+  // the level-truncated operators of the peel (first li levels, li < nlv)
+  P.tleaf.resize(nlv);
+  P.tchunk.resize(nlv);
+  P.ntleaf.assign(nlv, 0);
+  P.ntchunk.assign(nlv, 0);
+  for (size_t le = 1; le < nlv; ++le) {
+    std::vector<H2Leaf> tl, tc;
+    for (size_t li = 0; li < le; ++li)
+      for (size_t v = 0; v < all_of[li].size(); ++v) {
+        if (li + 1 < le && haskids[li][v]) continue;
+        const H2Leaf &b = all_of[li][v];
+        tl.push_back(b);
+        for (int32_t r0 = 0; r0 < b.m; r0 += 64)
+          tc.push_back(H2Leaf{b.row0, b.boff, b.m, b.g, r0, 0});
+      }
+    upload_cached(P.tleaf[le], tl, s);
+    upload_cached(P.tchunk[le], tc, s);
+    P.ntleaf[le] = (int32_t)tl.size();
+    P.ntchunk[le] = (int32_t)tc.size();
+  }
   HIP_TRY(hipStreamSynchronize(s));
   P.ready = true;
 }
@@ -1653,7 +1710,8 @@ void Compression::record_h2_level(size_t li, hipStream_t s, Events &ev) {
       LAUNCH_CHECK();
     }
     ev.mark(2);
-    apply_levels(*H, li, false, mixed, X, n, c1pad, Y, n, -1.0, Tb.p, tcap, s);
+    h2_apply(*H, li, false, mixed, X, n, c1pad, Y, n, -1.0, h2q.as<double>(), h2u.as<double>(),
+             h2cols, s);
     launch_check_finite(n, c1pad, mixed, Y, n, flag.as<int32_t>(), s);
     LAUNCH_CHECK();
   }
@@ -1684,7 +1742,8 @@ void Compression::record_h2_level(size_t li, hipStream_t s, Events &ev) {
       LAUNCH_CHECK();
     }
     ev.mark(2);
-    apply_levels(*H, li, true, mixed, X, n, c2pad, Y, n, -1.0, Tb.p, tcap, s);
+    h2_apply(*H, li, true, mixed, X, n, c2pad, Y, n, -1.0, h2q.as<double>(), h2u.as<double>(),
+             h2cols, s);
     launch_check_finite(n, c2pad, mixed, Y, n, flag.as<int32_t>(), s);
     LAUNCH_CHECK();
   }
@@ -1956,7 +2015,12 @@ void Compression::record(hipStream_t s, Events &ev) {
   }
   cols_A += (int64_t)GL.ncolors * mw;
   ev.mark(2);
-  apply_levels(*H, H->lv.size(), false, mixed, Xb.p, n, leaf_cols, Yb.p, n, -1.0, Tb.p, tcap, s);
+  if (h2)
+    h2_apply(*H, H->lv.size(), false, mixed, Xb.p, n, leaf_cols, Yb.p, n, -1.0, h2q.as<double>(),
+             h2u.as<double>(), h2cols, s);
+  else
+    apply_levels(*H, H->lv.size(), false, mixed, Xb.p, n, leaf_cols, Yb.p, n, -1.0, Tb.p, tcap,
+                 s);
   launch_check_finite(n, leaf_cols, mixed, Yb.p, n, flag.as<int32_t>(), s);
   LAUNCH_CHECK();
   ev.mark(3);

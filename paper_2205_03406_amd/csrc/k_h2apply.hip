@@ -189,14 +189,14 @@ h2_sum_kernel(const H2Sum *__restrict__ jobs, const H2Term *__restrict__ terms, 
   }
 }
 
-// y(row0 + r, c) += sum_j U_a(r, j) u_a(j, c) for one 64-row chunk of a
+// y(row0 + r, c) += sign sum_j U_a(r, j) u_a(j, c) for one 64-row chunk of a
 // box: lanes along the rows (coalesced read-modify-write of y), thread
 // (row r, group cg) owns columns cg + 4 q.
 template <typename T>
 __global__ void __launch_bounds__(256)
 h2_expand_kernel(const H2Leaf *__restrict__ jobs, int32_t kmax, const int32_t *__restrict__ rank,
                  const double *__restrict__ UB, const double *__restrict__ UH, int64_t ldq,
-                 int64_t ncols, T *__restrict__ Y, int64_t ldy) {
+                 int64_t ncols, T *__restrict__ Y, int64_t ldy, double sign) {
   extern __shared__ double sm[];
   double *Us = sm;              // [j][row], ld 65
   double *Hs = sm + kmax * 65;  // [j][column], ld HC + 1
@@ -231,7 +231,7 @@ h2_expand_kernel(const H2Leaf *__restrict__ jobs, int32_t kmax, const int32_t *_
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
     const int c = cg + 4 * q;
-    if (c < wc) y[(c0 + c) * ldy] = (T)((double)y[(c0 + c) * ldy] + acc[q]);
+    if (c < wc) y[(c0 + c) * ldy] = (T)((double)y[(c0 + c) * ldy] + sign * acc[q]);
   }
 }
 
@@ -307,17 +307,17 @@ void launch_h2_sum(int32_t njobs, const H2Sum *jobs, const H2Term *terms, int32_
 
 void launch_h2_expand(int32_t njobs, const H2Leaf *jobs, int32_t kmax, const int32_t *rank,
                       const double *UB, const double *UH, int64_t ldq, bool f32, int64_t ncols,
-                      void *Y, int64_t ldy, hipStream_t s) {
+                      void *Y, int64_t ldy, double sign, hipStream_t s) {
   if (njobs <= 0 || ncols <= 0 || kmax <= 0) return;
   if (kmax > 64) throw std::runtime_error("h2 apply: rank above 64");
   dim3 g(njobs, (unsigned)((ncols + HC - 1) / HC));
   const size_t lds = (size_t)(kmax * 65 + kmax * (HC + 1)) * sizeof(double);
   if (f32)
     h2_expand_kernel<float><<<g, 256, lds, s>>>(jobs, kmax, rank, UB, UH, ldq, ncols, (float *)Y,
-                                                ldy);
+                                                ldy, sign);
   else
     h2_expand_kernel<double><<<g, 256, lds, s>>>(jobs, kmax, rank, UB, UH, ldq, ncols,
-                                                 (double *)Y, ldy);
+                                                 (double *)Y, ldy, sign);
 }
 
 }  // namespace hm

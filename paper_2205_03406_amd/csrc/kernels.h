@@ -305,6 +305,6 @@ void launch_h2_sum(int32_t njobs, const H2Sum *jobs, const H2Term *terms, int32_
 // Y(rows of the chunk) += U_g UH[g], one job per 64-row chunk of a box with long bases.
 void launch_h2_expand(int32_t njobs, const H2Leaf *jobs, int32_t kmax, const int32_t *rank,
                       const double *UB, const double *UH, int64_t ldq, bool f32, int64_t ncols,
-                      void *Y, int64_t ldy, hipStream_t s);
+                      void *Y, int64_t ldy, double sign, hipStream_t s);
 
 }  // namespace hm
