@@ -2300,6 +2300,11 @@ int64_t matvec_footprint(const hm_hmatrix *H, int64_t nrhs, int dtype) {
   return tscratch_elems(*H, nrhs) * es + 2 * H->n * nrhs * es;
 }
 
+// Frees the idle blocks the block cache keeps for device dev.
+void trim_block_cache(int dev) {
+  if (dev >= 0 && dev < 64) cache_drop(dev);
+}
+
 }  // namespace hm
 
 // ------------------------------------------------------------------ plans

@@ -292,6 +292,8 @@ hm_status hm_server_create(const hm_server_opts *opts, hm_server **out) {
     S->compress_slots = opts->compress_slots > 0 ? std::min(opts->compress_slots, opts->nslots)
                                                  : 1;
     if (S->budget <= 0) {
+      // idle cached blocks count as free memory here
+      hm::trim_block_cache(S->device);
       size_t fr = 0, tot = 0;
       if (hipMemGetInfo(&fr, &tot) != hipSuccess) return fail(HM_E_DEVICE, "hipMemGetInfo failed");
       S->budget = (int64_t)(0.9 * (double)fr);
