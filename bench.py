@@ -226,7 +226,7 @@ def run_batched(hm, torch, steps):
     plan.hmatrix().matvec(X, Yr)
     torch.cuda.synchronize()
     replay_equal = bool(np.array_equal(Yr.cpu().numpy(), b))
-    return {
+    res = {
         "workload": "64_ellipses_log_N2048-32768_leaf64_strong_tol1e-6_r%d_mixed" % insts[0].r,
         "instances": len(insts), "points": ntot, "steps": steps,
         "value": round(flops / total / 1e9, 2), "unit": "GFLOP/s",
@@ -246,6 +246,10 @@ def run_batched(hm, torch, steps):
                    "achieved": round(ach / 1e12, 3), "peak": PEAK_FP32_MFMA / 1e12,
                    "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_MFMA, 4)},
     }
+    ceil32 = hm.mfma_rate(hm.HM_F32)
+    res["kapply"]["mfma_sustained"] = round(ceil32, 2)
+    res["kapply"]["frac_of_sustained"] = round(ach / 1e12 / ceil32, 4)
+    return res
 
 
 # ---------------------------------------------------------------- serving
@@ -457,6 +461,11 @@ def main():
                        "traffic": kapply_traffic_bytes(),
                        "avg_launch_ms": round(r64["bb_ms"] / r64["launches"], 4),
                        "flops_per_launch": r64["bb_flops"] / r64["launches"]}
+    # what the matrix cores of this part sustain for the same instruction
+    # (independent chains, no memory traffic), measured outside the timed steps
+    ceil64 = hm.mfma_rate(hm.HM_F64)
+    out["roofline"]["mfma_sustained"] = round(ceil64, 2)
+    out["roofline"]["frac_of_sustained"] = round(ach / 1e12 / ceil64, 4)
 
     # accuracy of the FP64 result on sampled rows (outside the timed region)
     import oracle

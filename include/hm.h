@@ -368,6 +368,15 @@ hm_status hm_matvec_op(const hm_hmatrix *H, int trans, int64_t nrhs, int dtype, 
  * draws it: out (device, n x ncolors*r, ld) in tree order. */
 hm_status hm_test_matrix(const hm_tree *tree, int level, int pass, int32_t r, uint64_t seed,
                          int dtype, void *out, int64_t ld, void *stream);
+/* Calibration of the kernel apply's roofline: the sustained TFLOP/s of the
+ * 16x16x4 matrix-core instruction the kernel apply issues in dtype (HM_F64:
+ * v_mfma_f64_16x16x4f64, HM_F32: v_mfma_f32_16x16x4f32), measured on the
+ * current device with independent accumulator chains and no memory traffic
+ * (best of 1, 2 and 4 workgroups per compute unit, 4 and 8 chains per wave;
+ * about a second of device time).  tflops (host) written on success;
+ * HM_E_ARG for a bad dtype or null pointer, HM_E_DEVICE on a failed launch.
+ * Synchronizes the stream. */
+hm_status hm_mfma_rate(int dtype, void *stream, double *tflops);
 /* Raw Philox4x32-10: ctr (device, 4*count u32, counter i at 4i..4i+3),
  * out (device, 4*count u32). */
 hm_status hm_philox4x32_10(const uint32_t *ctr, int64_t count, uint32_t key0, uint32_t key1,

@@ -48,7 +48,7 @@ EXPORTED = [
     "hm_server_submit_compress", "hm_server_submit_matvec", "hm_server_poll", "hm_server_hmatrix",
     "hm_server_release", "hm_server_info", "hm_compress_plan", "hm_plan_execute",
     "hm_plan_hmatrix", "hm_plan_free", "hm_uniform_graph", "hm_matvec_op",
-    "hm_hmatrix_blackbox", "hm_product_blackbox", "hm_blackbox_free",
+    "hm_hmatrix_blackbox", "hm_product_blackbox", "hm_blackbox_free", "hm_mfma_rate",
 ]
 
 
@@ -422,6 +422,14 @@ class Plan:
 def autotune_table():
     """The kernel-apply autotuner's decisions so far (one line per shape)."""
     return _lib.hm_autotune_table().decode()
+
+
+def mfma_rate(dtype=HM_F64, stream=None):
+    """hm_mfma_rate: sustained TFLOP/s of the kernel apply's matrix-core
+    instruction on the current device (independent chains, no memory)."""
+    v = C.c_double(0.0)
+    _check(_lib.hm_mfma_rate(dtype, _stream(stream), C.byref(v)))
+    return v.value
 
 
 def color(xadj, adj):

@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhm.so")
 
-HIP_SOURCES = ["k_misc.hip", "k_kapply.hip", "k_lowrank.hip", "k_qr.hip", "k_uniform.hip", "k_h2apply.hip",
+HIP_SOURCES = ["k_misc.hip", "k_kapply.hip", "k_lowrank.hip", "k_qr.hip", "k_uniform.hip", "k_h2apply.hip", "k_probe.hip",
                "autotune.hip",
                "engine.hip", "server.hip"]
 CXX_SOURCES = ["tree.cpp"]

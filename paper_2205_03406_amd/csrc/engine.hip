@@ -2622,6 +2622,21 @@ hm_status hm_kernel_blackbox(hm_tree *tree, int kernel, hm_blackbox *out) {
   API_END
 }
 
+hm_status hm_mfma_rate(int dtype, void *stream, double *tflops) {
+  API_BEGIN
+  if (!tflops || (dtype != HM_F64 && dtype != HM_F32)) return fail(HM_E_ARG, "hm_mfma_rate: bad argument");
+  int dev = 0, cus = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  try {
+    *tflops = hm::measure_mfma_rate(dtype == HM_F32, cus, (hipStream_t)stream);
+  } catch (const std::runtime_error &e) {
+    return fail(HM_E_DEVICE, e.what());
+  }
+  return HM_OK;
+  API_END
+}
+
 hm_status hm_kernel_apply(hm_tree *tree, int kernel, int64_t ncols, int dtype, const void *X,
                           int64_t ldx, void *Y, int64_t ldy, int order, void *stream) {
   API_BEGIN

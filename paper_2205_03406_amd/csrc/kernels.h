@@ -307,4 +307,9 @@ void launch_h2_expand(int32_t njobs, const H2Leaf *jobs, int32_t kmax, const int
                       const double *UB, const double *UH, int64_t ldq, bool f32, int64_t ncols,
                       void *Y, int64_t ldy, double sign, hipStream_t s);
 
+// Sustained TFLOP/s of the 16x16x4 matrix-core instruction of the kernel
+// apply (FP32 or FP64), independent chains, no memory traffic; cus = the
+// device's compute units.
+double measure_mfma_rate(bool f32, int cus, hipStream_t s);
+
 }  // namespace hm
