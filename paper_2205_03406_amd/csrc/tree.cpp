@@ -461,12 +461,12 @@ hm_status build_tree(const double *pts, int64_t n, int dim, int leaf, int kind, 
   {
     std::vector<std::thread> th;
     for (int l = 0; l < T.nlev(); ++l) {
-      if (T.lev[l].nbox() > 1024)
+      if (T.lev[l].nbox() > 128)
         th.emplace_back([&B, &T, l] { B.level_graph(l, T.graphs[l]); });
       else
         B.level_graph(l, T.graphs[l]);
     }
-    if (T.lev[T.L()].nbox() > 1024)
+    if (T.lev[T.L()].nbox() > 128)
       th.emplace_back([&B, &T] { B.leaf_graph(T.graphs.back()); });
     else
       B.leaf_graph(T.graphs.back());
