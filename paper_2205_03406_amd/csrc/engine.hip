@@ -1758,12 +1758,17 @@ void Compression::record_h2_level(size_t li, hipStream_t s, Events &ev) {
                    usat.as<int32_t>() + nb + v0, s);
   LAUNCH_CHECK();
   ev.mark(4);
+  // couplings and the pair copies of the bases (the exported blocks); the
+  // products W = U B only serve the per-pair apply plan, which H^2 does not use
   launch_ucoupling((int32_t)L.np, J.uc.as<UCJob>(), kmax, mixed, Y, n, H->UB.as<double>(),
                    H->VB.as<double>(), rk + v0, rk + nb + v0, H->U.as<double>(),
-                   H->V.as<double>(), H->B.as<double>(), H->W.as<double>(),
-                   H->ranks.as<int32_t>(), true, s);
+                   H->V.as<double>(), H->B.as<double>(), nullptr, H->ranks.as<int32_t>(), true,
+                   s);
   LAUNCH_CHECK();
-  // ---------------- nest the previous level, rebuild the coarser bases
+  // ---------------- nest the previous level; after the last level rebuild the
+  // bases the nesting implies on every coarser level (for export: the peel and
+  // the apply read only long bases and transfers, and a transfer is taken
+  // from the parent's basis as computed, before any rebuild)
   if (li > 0) {
     const UniformJobs &Jc = J;
     launch_transfer(Jc.ntr, Jc.tr.as<TransferJob>(), kmax, H->UB.as<double>(), rk,
@@ -1771,7 +1776,7 @@ void Compression::record_h2_level(size_t li, hipStream_t s, Events &ev) {
     launch_transfer(Jc.ntr, Jc.tr.as<TransferJob>(), kmax, H->VB.as<double>(), rk + nb,
                     H->TV.as<double>(), s);
     LAUNCH_CHECK();
-    for (size_t lj = li; lj-- > 0;) {
+    for (size_t lj = li + 1 == H->lv.size() ? li : 0; lj-- > 0;) {
       // level lj's bases from level lj + 1's through the transfers of lj + 1's boxes
       const UniformJobs &Jn = ujobs_of[lj + 1];
       launch_nest(Jn.nnest, Jn.nest.as<NestJob>(), kmax, H->UB.as<double>(), H->TU.as<double>(),
@@ -1781,10 +1786,9 @@ void Compression::record_h2_level(size_t li, hipStream_t s, Events &ev) {
       const int64_t w0 = H->uv0[lj];
       launch_ucoupling((int32_t)H->lv[lj].np, ujobs_of[lj].uc.as<UCJob>(), kmax, mixed, Y, n,
                        H->UB.as<double>(), H->VB.as<double>(), rk + w0, rk + nb + w0,
-                       H->U.as<double>(), H->V.as<double>(), H->B.as<double>(),
-                       H->W.as<double>(), H->ranks.as<int32_t>(), false, s);
+                       H->U.as<double>(), H->V.as<double>(), H->B.as<double>(), nullptr,
+                       H->ranks.as<int32_t>(), false, s);
       LAUNCH_CHECK();
-      fp32_copies(lj, s);
     }
   }
 }
@@ -1906,11 +1910,12 @@ void Compression::record(hipStream_t s, Events &ev) {
   for (size_t li = 0; li < H->lv.size(); ++li) {
     hm_hmatrix::Lv &L = H->lv[li];
     if (uniform) {
-      if (h2)
+      if (h2) {
         record_h2_level(li, s, ev);
-      else
+      } else {
         record_uniform_level(li, s, ev);
-      fp32_copies(li, s);
+        fp32_copies(li, s);
+      }
       ev.mark(5);
       continue;
     }

@@ -368,7 +368,8 @@ coupling_kernel(const CoreJob *__restrict__ jobs, int32_t r, int32_t kmax,
 
 // ------------------------------------------------------------------ uniform coupling
 // Per pair (a, b): ranks, copies of the shared bases into the pair's slots,
-// B = Z(I_b, block of (b, a))[:, :ku]^T V_b (slot ld = kmax) and W = U_a B.
+// B = Z(I_b, block of (b, a))[:, :ku]^T V_b (slot ld = kmax) and, when Wout
+// is given, W = U_a B.
 template <typename T>
 __global__ void __launch_bounds__(256)
 ucoupling_kernel(const UCJob *__restrict__ jobs, int32_t kmax, const T *__restrict__ Z,
@@ -398,6 +399,7 @@ ucoupling_kernel(const UCJob *__restrict__ jobs, int32_t kmax, const T *__restri
   } else if (ku == 0 || kv == 0) {
     return;
   }
+  if (!Wout) return;
   double *W = Wout + job.wslot;
   for (int i = tid; i < job.ma; i += 256) {
     for (int c = 0; c < kv; ++c) {
