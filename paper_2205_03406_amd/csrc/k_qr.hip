@@ -20,6 +20,51 @@ namespace {
 
 using dev::wave_sum;
 
+// ------------------------------------------------------------------ lane loops
+// A lane's share of a column operation over rows i0, i0 + 64, ... < m, four
+// rows in flight at a time (independent partial sums, every load of a group
+// issued before its results are used or stored): a loop with one row per
+// step waits on each load in turn, and these blocks run to thousands of rows.
+__device__ __forceinline__ double lane_dot(const double *x, const double *y, int i0, int m) {
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int i = i0;
+  for (; i + 192 < m; i += 256) {
+    const double x0 = x[i], x1 = x[i + 64], x2 = x[i + 128], x3 = x[i + 192];
+    const double y0 = y[i], y1 = y[i + 64], y2 = y[i + 128], y3 = y[i + 192];
+    a0 += x0 * y0;
+    a1 += x1 * y1;
+    a2 += x2 * y2;
+    a3 += x3 * y3;
+  }
+  for (; i < m; i += 64) a0 += x[i] * y[i];
+  return (a0 + a1) + (a2 + a3);
+}
+
+// y(i) -= f x(i) over the lane's rows; returns the lane's sum of the new y(i)^2
+__device__ __forceinline__ double lane_axpy(double *y, const double *x, double f, int i0, int m) {
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int i = i0;
+  for (; i + 192 < m; i += 256) {
+    const double x0 = x[i], x1 = x[i + 64], x2 = x[i + 128], x3 = x[i + 192];
+    const double y0 = y[i], y1 = y[i + 64], y2 = y[i + 128], y3 = y[i + 192];
+    const double v0 = y0 - f * x0, v1 = y1 - f * x1, v2 = y2 - f * x2, v3 = y3 - f * x3;
+    y[i] = v0;
+    y[i + 64] = v1;
+    y[i + 128] = v2;
+    y[i + 192] = v3;
+    s0 += v0 * v0;
+    s1 += v1 * v1;
+    s2 += v2 * v2;
+    s3 += v3 * v3;
+  }
+  for (; i < m; i += 64) {
+    const double v = y[i] - f * x[i];
+    y[i] = v;
+    s0 += v * v;
+  }
+  return (s0 + s1) + (s2 + s3);
+}
+
 // ------------------------------------------------------------------ block norms
 // out[j] = scale * ||S(rows, cols) of job j||_F (FP64 accumulation).
 template <typename T>
@@ -100,8 +145,7 @@ pivqr_kernel(const QrJob *__restrict__ jobs, int32_t r, int32_t rank_fixed, doub
     const int pc = piv[j];
     double *x = W + (int64_t)pc * m;
     if (wave == 0) {
-      double s2 = 0.0;
-      for (int i = j + lane; i < m; i += 64) s2 += x[i] * x[i];
+      double s2 = lane_dot(x, x, j + lane, m);
       s2 = wave_sum(s2);
       if (lane == 0) {
         const double nrm = sqrt(s2);
@@ -129,17 +173,11 @@ pivqr_kernel(const QrJob *__restrict__ jobs, int32_t r, int32_t rank_fixed, doub
     const double tj = tau[j];
     for (int c = j + 1 + wave; c < r; c += 4) {
       double *y = W + (int64_t)piv[c] * m;
-      double w = 0.0;
-      for (int i = j + 1 + lane; i < m; i += 64) w += x[i] * y[i];
+      double w = lane_dot(x, y, j + 1 + lane, m);
       w = wave_sum(w) + y[j];
       const double f = tj * w;
       if (lane == 0) y[j] -= f;
-      double s2 = 0.0;
-      for (int i = j + 1 + lane; i < m; i += 64) {
-        const double v = y[i] - f * x[i];
-        y[i] = v;
-        s2 += v * v;
-      }
+      double s2 = lane_axpy(y, x, f, j + 1 + lane, m);
       s2 = wave_sum(s2);
       if (lane == 0) nrm2[c] = s2;
     }
@@ -163,11 +201,10 @@ pivqr_kernel(const QrJob *__restrict__ jobs, int32_t r, int32_t rank_fixed, doub
     const double tj = tau[j];
     for (int c = j + wave; c < rank; c += 4) {
       double *y = Uo + (int64_t)c * m;
-      double w = 0.0;
-      for (int i = j + 1 + lane; i < m; i += 64) w += x[i] * y[i];
+      double w = lane_dot(x, y, j + 1 + lane, m);
       w = wave_sum(w) + y[j];
       const double f = tj * w;
-      for (int i = j + 1 + lane; i < m; i += 64) y[i] -= f * x[i];
+      (void)lane_axpy(y, x, f, j + 1 + lane, m);
       if (lane == 0) y[j] -= f;
     }
     __syncthreads();
@@ -445,8 +482,7 @@ svd_basis_kernel(const QrJob *__restrict__ jobs, int32_t c, int32_t rank_fixed, 
   for (int j = 0; j < kq; ++j) {
     double *x = W + (int64_t)j * m;
     if (wave == 0) {
-      double s2 = 0.0;
-      for (int i = j + lane; i < m; i += 64) s2 += x[i] * x[i];
+      double s2 = lane_dot(x, x, j + lane, m);
       s2 = wave_sum(s2);
       if (lane == 0) {
         const double nrm = sqrt(s2);
@@ -469,11 +505,10 @@ svd_basis_kernel(const QrJob *__restrict__ jobs, int32_t c, int32_t rank_fixed, 
     const double tj = tau[j];
     for (int cc = j + 1 + wave; cc < c; cc += 4) {
       double *y = W + (int64_t)cc * m;
-      double w = 0.0;
-      for (int i = j + 1 + lane; i < m; i += 64) w += x[i] * y[i];
+      double w = lane_dot(x, y, j + 1 + lane, m);
       w = wave_sum(w) + y[j];
       const double f = tj * w;
-      for (int i = j + 1 + lane; i < m; i += 64) y[i] -= f * x[i];
+      (void)lane_axpy(y, x, f, j + 1 + lane, m);
       if (lane == 0) y[j] -= f;
     }
     __syncthreads();
@@ -584,11 +619,10 @@ svd_basis_kernel(const QrJob *__restrict__ jobs, int32_t c, int32_t rank_fixed, 
     const double tj = tau[j];
     for (int cc = wave; cc < kk; cc += 4) {
       double *y = Uo + (int64_t)cc * m;
-      double w = 0.0;
-      for (int i = j + 1 + lane; i < m; i += 64) w += x[i] * y[i];
+      double w = lane_dot(x, y, j + 1 + lane, m);
       w = wave_sum(w) + y[j];
       const double f = tj * w;
-      for (int i = j + 1 + lane; i < m; i += 64) y[i] -= f * x[i];
+      (void)lane_axpy(y, x, f, j + 1 + lane, m);
       if (lane == 0) y[j] -= f;
     }
     __syncthreads();
