@@ -998,12 +998,14 @@ hm_status Compression::setup(hipStream_t s) {
     H->lv.push_back(std::move(L));
   }
   H->np_total = np_total;
+  // H^2 applies through its passes: no per-pair products W = U B, no FP32
+  // copies (the pair copies of U and V remain, for export)
   H->U.cached(szU * 8);
-  H->W.cached(szU * 8);
+  H->W.cached(h2 ? 0 : szU * 8);
   H->V.cached(szV * 8);
   H->B.cached(szB * 8);
-  H->Wf.cached(szU * 4);
-  H->Vf.cached(szV * 4);
+  H->Wf.cached(h2 ? 0 : szU * 4);
+  H->Vf.cached(h2 ? 0 : szV * 4);
   H->ranks.cached(2 * np_total * sizeof(int32_t));
   build_apply_plans(*H, T, s);
 
@@ -1898,7 +1900,7 @@ void Compression::record(hipStream_t s, Events &ev) {
   const DeviceTree &Dv = *D;
   const Graph &GL = T.leaf_graph();
   // state every run starts from (fill kernels, no memset: capturable)
-  launch_fill(H->W.p, szU, false, 0.0, s);
+  if (!h2) launch_fill(H->W.p, szU, false, 0.0, s);
   launch_fill(H->V.p, szV, false, 0.0, s);
   launch_fill(H->ranks.p, 2 * np_total, true, 0.0, s);  // int32 zeros share the float bit pattern
   launch_fill(sat.p, std::max<int64_t>(2 * np_total, 1), true, 0.0, s);
