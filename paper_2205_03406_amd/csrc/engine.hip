@@ -598,6 +598,8 @@ void apply_levels(const hm_hmatrix &H, size_t li_end, bool trans, bool f32, cons
                   int64_t tcap, hipStream_t s) {
   if (li_end == 0 || ncols <= 0) return;
   const hm_hmatrix::Orient &O = trans ? H.oT : H.oA;
+  if (O.items_upto.size() <= li_end)
+    throw Error{HM_E_STATE, "no per-pair apply plan for these levels"};
   const int32_t nitems = O.items_upto[li_end];
   const int64_t nslots = O.slots_upto[li_end];
   if (nitems == 0 || O.nch[li_end] == 0) return;
@@ -1007,7 +1009,7 @@ hm_status Compression::setup(hipStream_t s) {
   H->Wf.cached(h2 ? 0 : szU * 4);
   H->Vf.cached(h2 ? 0 : szV * 4);
   H->ranks.cached(2 * np_total * sizeof(int32_t));
-  build_apply_plans(*H, T, s);
+  if (!h2) build_apply_plans(*H, T, s);  // H^2 applies through its passes
 
   // leaf neighbor blocks
   const Graph &GL = T.leaf_graph();
