@@ -1000,11 +1000,11 @@ hm_status Compression::setup(hipStream_t s) {
     H->lv.push_back(std::move(L));
   }
   H->np_total = np_total;
-  // H^2 applies through its passes: no per-pair products W = U B, no FP32
-  // copies (the pair copies of U and V remain, for export)
-  H->U.cached(szU * 8);
+  // H^2 applies through its passes: no per-pair copies of the bases, no
+  // products W = U B, no FP32 copies (export reads the bases themselves)
+  H->U.cached(h2 ? 0 : szU * 8);
   H->W.cached(h2 ? 0 : szU * 8);
-  H->V.cached(szV * 8);
+  H->V.cached(h2 ? 0 : szV * 8);
   H->B.cached(szB * 8);
   H->Wf.cached(h2 ? 0 : szU * 4);
   H->Vf.cached(h2 ? 0 : szV * 4);
@@ -1415,7 +1415,7 @@ void Compression::setup_h2(hipStream_t s) {
 
   ujobs_of.resize(nlv);
   for (size_t li = 0; li < nlv; ++li) {
-    const hm_hmatrix::Lv &L = H->lv[li];
+    hm_hmatrix::Lv &L = H->lv[li];  // offU, offV point into the box bases (no pair copies)
     const int l = L.level;
     const Graph &G = T.graphs[l], &UG = T.ugraphs[l];
     const Level &Lv = T.lev[l];
@@ -1502,6 +1502,9 @@ void Compression::setup_h2(hipStream_t s) {
                     H->uoff[li][vid[li][b]], L.offU[q], L.offV[q], L.offW[q], L.offB[q],
                     (int32_t)T.box_size(l, a), (int32_t)T.box_size(l, b), vid[li][a], vid[li][b],
                     (int32_t)(L.g0 + q), (int32_t)(np_total + L.g0 + q)};
+      // no pair copies: a pair's bases are read where the boxes keep them
+      L.offU[q] = H->uoff[li][vid[li][a]];
+      L.offV[q] = H->uoff[li][vid[li][b]];
     }
     // transfers and nesting of the previous level into this one
     std::vector<TransferJob> tr;
@@ -1765,9 +1768,8 @@ void Compression::record_h2_level(size_t li, hipStream_t s, Events &ev) {
   // couplings and the pair copies of the bases (the exported blocks); the
   // products W = U B only serve the per-pair apply plan, which H^2 does not use
   launch_ucoupling((int32_t)L.np, J.uc.as<UCJob>(), kmax, mixed, Y, n, H->UB.as<double>(),
-                   H->VB.as<double>(), rk + v0, rk + nb + v0, H->U.as<double>(),
-                   H->V.as<double>(), H->B.as<double>(), nullptr, H->ranks.as<int32_t>(), true,
-                   s);
+                   H->VB.as<double>(), rk + v0, rk + nb + v0, nullptr, nullptr,
+                   H->B.as<double>(), nullptr, H->ranks.as<int32_t>(), true, s);
   LAUNCH_CHECK();
   // ---------------- nest the previous level; after the last level rebuild the
   // bases the nesting implies on every coarser level (for export: the peel and
@@ -1787,11 +1789,6 @@ void Compression::record_h2_level(size_t li, hipStream_t s, Events &ev) {
                   rk, H->UB.as<double>(), s);
       launch_nest(Jn.nnest, Jn.nest.as<NestJob>(), kmax, H->VB.as<double>(), H->TV.as<double>(),
                   rk + nb, H->VB.as<double>(), s);
-      const int64_t w0 = H->uv0[lj];
-      launch_ucoupling((int32_t)H->lv[lj].np, ujobs_of[lj].uc.as<UCJob>(), kmax, mixed, Y, n,
-                       H->UB.as<double>(), H->VB.as<double>(), rk + w0, rk + nb + w0,
-                       H->U.as<double>(), H->V.as<double>(), H->B.as<double>(), nullptr,
-                       H->ranks.as<int32_t>(), false, s);
       LAUNCH_CHECK();
     }
   }
@@ -1903,7 +1900,7 @@ void Compression::record(hipStream_t s, Events &ev) {
   const Graph &GL = T.leaf_graph();
   // state every run starts from (fill kernels, no memset: capturable)
   if (!h2) launch_fill(H->W.p, szU, false, 0.0, s);
-  launch_fill(H->V.p, szV, false, 0.0, s);
+  if (!h2) launch_fill(H->V.p, szV, false, 0.0, s);
   launch_fill(H->ranks.p, 2 * np_total, true, 0.0, s);  // int32 zeros share the float bit pattern
   launch_fill(sat.p, std::max<int64_t>(2 * np_total, 1), true, 0.0, s);
   launch_fill(flag.p, 1, true, 0.0, s);
@@ -2943,10 +2940,14 @@ hm_status hm_hmatrix_export_level(const hm_hmatrix *H, int level, int64_t *npair
       const int ku = H->h_ranks[L->g0 + q], kv = H->h_ranks[H->np_total + L->g0 + q];
       const int64_t ma = st[L->pa[q] + 1] - st[L->pa[q]];
       const int64_t mb = st[L->pb[q] + 1] - st[L->pb[q]];
+      // H^2 keeps no pair copies: the boxes' bases (m x kmax, ld m) hold them
+      const bool boxes = H->format == HM_FORMAT_H2;
       if (U && ku)
-        HIP_TRY(hipMemcpy(U + ou, H->U.as<double>() + L->offU[q], ma * ku * 8, hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(U + ou, (boxes ? H->UB : H->U).as<double>() + L->offU[q], ma * ku * 8,
+                          hipMemcpyDeviceToHost));
       if (V && kv)
-        HIP_TRY(hipMemcpy(V + ov, H->V.as<double>() + L->offV[q], mb * kv * 8, hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(V + ov, (boxes ? H->VB : H->V).as<double>() + L->offV[q], mb * kv * 8,
+                          hipMemcpyDeviceToHost));
       if (B && ku && kv) {
         HIP_TRY(hipMemcpy(bt.data(), H->B.as<double>() + L->offB[q], bt.size() * 8,
                           hipMemcpyDeviceToHost));

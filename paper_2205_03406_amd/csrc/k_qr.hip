@@ -404,9 +404,9 @@ coupling_kernel(const CoreJob *__restrict__ jobs, int32_t r, int32_t kmax,
 }
 
 // ------------------------------------------------------------------ uniform coupling
-// Per pair (a, b): ranks, copies of the shared bases into the pair's slots,
-// B = Z(I_b, block of (b, a))[:, :ku]^T V_b (slot ld = kmax) and, when Wout
-// is given, W = U_a B.
+// Per pair (a, b): ranks, copies of the shared bases into the pair's slots
+// (when U and V are given), B = Z(I_b, block of (b, a))[:, :ku]^T V_b
+// (slot ld = kmax) and, when Wout is given, W = U_a B.
 template <typename T>
 __global__ void __launch_bounds__(256)
 ucoupling_kernel(const UCJob *__restrict__ jobs, int32_t kmax, const T *__restrict__ Z,
@@ -424,8 +424,10 @@ ucoupling_kernel(const UCJob *__restrict__ jobs, int32_t kmax, const T *__restri
   }
   const double *Ua = UB + job.uboff;
   const double *Vb = VB + job.vboff;
-  for (int64_t e = tid; e < (int64_t)job.ma * ku; e += 256) U[job.uslot + e] = Ua[e];
-  for (int64_t e = tid; e < (int64_t)job.mb * kv; e += 256) V[job.vslot + e] = Vb[e];
+  if (U)
+    for (int64_t e = tid; e < (int64_t)job.ma * ku; e += 256) U[job.uslot + e] = Ua[e];
+  if (V)
+    for (int64_t e = tid; e < (int64_t)job.mb * kv; e += 256) V[job.vslot + e] = Vb[e];
   double *Bs = B + job.bslot;
   if (recompute) {
     for (int e = tid; e < kmax * kmax; e += 256) Bs[e] = 0.0;
