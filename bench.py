@@ -449,6 +449,7 @@ def main():
         "max_rank": st["max_rank"],
         "saturated": st["saturated"],
         "floats_per_dof": round(st["nfloats"] / n, 2),
+        "device_mb": round(st["device_bytes"] / 2**20, 1),
         "stage_ms": {k: round(st[k], 3) for k in ("ms_blackbox", "ms_peel", "ms_qr", "ms_solve",
                                                   "ms_other", "ms_total")},
     }
@@ -514,6 +515,7 @@ def main():
             "ms_per_step": round(1e3 * run["total"] / args.steps, 3),
             "p50_ms": round(float(np.percentile(np.array(run["times"]) * 1e3, 50)), 3),
             "floats_per_dof": round(su["nfloats"] / n, 2),
+            "device_mb": round(su["device_bytes"] / 2**20, 1),
             "stage1_colors_per_level": [c for c in su["ucolors"] if c],
             "cols_A": su["cols_A"],
             "cols_At": su["cols_At"],
@@ -545,6 +547,7 @@ def main():
             "p50_ms": round(float(np.percentile(np.array(run["times"]) * 1e3, 50)), 3),
             "rank": H2_RANK,
             "floats_per_dof": round(s2["nfloats"] / n, 2),
+            "device_mb": round(s2["device_bytes"] / 2**20, 1),
             "max_rank": s2["max_rank"],
             "saturated": s2["saturated"],
             "rel_err_vs_dense_sampled_rows": float(np.linalg.norm(Yh[rows] - want) /

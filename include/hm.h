@@ -405,6 +405,7 @@ typedef struct {
   double flops_qr;           /* pivoted QR + basis formation */
   double flops_solve;        /* coupling solves */
   double ms_total, ms_blackbox, ms_peel, ms_qr, ms_solve, ms_other; /* flags bit 0 */
+  int64_t device_bytes;      /* device memory the H-matrix holds (factors, plans) */
 } hm_stats;
 hm_status hm_hmatrix_stats(const hm_hmatrix *H, hm_stats *out);
 

@@ -84,7 +84,8 @@ class Stats(C.Structure):
                 ("flops_peel", C.c_double), ("flops_qr", C.c_double),
                 ("flops_solve", C.c_double), ("ms_total", C.c_double),
                 ("ms_blackbox", C.c_double), ("ms_peel", C.c_double), ("ms_qr", C.c_double),
-                ("ms_solve", C.c_double), ("ms_other", C.c_double)]
+                ("ms_solve", C.c_double), ("ms_other", C.c_double),
+                ("device_bytes", C.c_int64)]
 
     def as_dict(self):
         d = {}

@@ -2895,6 +2895,7 @@ hm_status hm_philox4x32_10(const uint32_t *ctr, int64_t count, uint32_t key0, ui
 hm_status hm_hmatrix_stats(const hm_hmatrix *H, hm_stats *out) {
   if (!H || !out) return fail(HM_E_ARG, "null argument");
   *out = H->stats;
+  out->device_bytes = hm::hmatrix_device_bytes(H);
   return HM_OK;
 }
 

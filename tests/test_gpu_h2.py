@@ -109,6 +109,10 @@ def test_h2_kernel_parity(hm, n, tol):
     assert abs(st["nfloats"] - Ho.floats()) <= 0.01 * Ho.floats()
     assert st["nfloats"] < Hu.stats()["nfloats"]
     assert st["saturated"] == 0
+    # device memory: no per-pair copies, products or plans beside the nested form
+    print("device MB: h2 %.1f, uniform %.1f" % (st["device_bytes"] / 2**20,
+                                                Hu.stats()["device_bytes"] / 2**20))
+    assert 0 < st["device_bytes"] < Hu.stats()["device_bytes"]
 
 
 def test_h2_mixed_matches_f64(hm):
