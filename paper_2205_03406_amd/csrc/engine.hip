@@ -647,7 +647,7 @@ int64_t tscratch_elems(const hm_hmatrix &H, int64_t ncols) {
 // stream-ordered scratch; at most 256 columns at a time.
 void h2_apply(const hm_hmatrix &H, size_t le, bool trans, bool f32, const void *X, int64_t ldx,
               int64_t ncols, void *Y, int64_t ldy, double sign, double *qh, double *uh,
-              int64_t qcols, hipStream_t s) {
+              double *part, int64_t qcols, hipStream_t s) {
   const hm_hmatrix::H2Apply &P = H.h2a;
   const size_t nlv = H.lv.size();
   if (le == 0 || ncols <= 0) return;
@@ -669,16 +669,19 @@ void h2_apply(const hm_hmatrix &H, size_t le, bool trans, bool f32, const void *
   const bool own = qh == nullptr;
   const int64_t cw = own ? std::min<int64_t>(ncols, 256) : std::min<int64_t>(ncols, qcols);
   if (cw < 1) throw Error{HM_E_NOMEM, "H2 expansion scratch too small"};
-  double *QH = qh, *UH = uh;
+  double *QH = qh, *UH = uh, *PT = part;
   if (own) {
     HIP_TRY(hipMallocAsync((void **)&QH, (size_t)std::max<int64_t>(nb * kmax * cw, 1) * 8, s));
     HIP_TRY(hipMallocAsync((void **)&UH, (size_t)std::max<int64_t>(nb * kmax * cw, 1) * 8, s));
+    HIP_TRY(hipMallocAsync((void **)&PT,
+                           (size_t)std::max<int64_t>((int64_t)nchunk * kmax * cw, 1) * 8, s));
   }
   for (int64_t c0 = 0; c0 < ncols; c0 += cw) {
     const int64_t w = std::min(cw, ncols - c0);
     const char *Xc = (const char *)X + c0 * ldx * es;
     char *Yc = (char *)Y + c0 * ldy * es;
-    launch_h2_project(nleaf, leaf, kmax, ri, Bout, f32, Xc, ldx, w, QH, w, s);
+    launch_h2_project(nchunk, chunk, kmax, ri, Bout, f32, Xc, ldx, w, PT, w, s);
+    launch_h2_reduce(nleaf, leaf, kmax, PT, QH, w, w, s);
     // upward: level li from its children on li + 1 (< le)
     for (size_t li = le - 1; li-- > 0;)
       launch_h2_sum(P.nup[li], P.up_j[li].as<H2Sum>(), P.up_t[li].as<H2Term>(), kmax, ri, ri,
@@ -693,6 +696,7 @@ void h2_apply(const hm_hmatrix &H, size_t le, bool trans, bool f32, const void *
   if (own) {
     HIP_TRY(hipFreeAsync(QH, s));
     HIP_TRY(hipFreeAsync(UH, s));
+    HIP_TRY(hipFreeAsync(PT, s));
   }
 }
 
@@ -723,7 +727,8 @@ void matvec_impl(const hm_hmatrix &H, bool trans, int64_t nrhs, bool f32, const 
                     nrhs, Yt, ldyt, H.near_covers, s);
   LAUNCH_CHECK();
   if (H.format == HM_FORMAT_H2 && H.h2a.ready)
-    h2_apply(H, H.lv.size(), trans, f32, Xt, ldxt, nrhs, Yt, ldyt, 1.0, nullptr, nullptr, 0, s);
+    h2_apply(H, H.lv.size(), trans, f32, Xt, ldxt, nrhs, Yt, ldyt, 1.0, nullptr, nullptr, nullptr,
+             0, s);
   else
     apply_levels(H, H.lv.size(), trans, f32, Xt, ldxt, nrhs, Yt, ldyt, 1.0, Tb, tcap, s);
   LAUNCH_CHECK();
@@ -883,7 +888,7 @@ struct Compression {
   };
   std::vector<UniformJobs> ujobs_of;
   DBuf Sb, usat;
-  DBuf h2q, h2u;       // H^2: expansions of the level-truncated products
+  DBuf h2q, h2u, h2p;  // H^2: expansions of the level-truncated products, chunk partials
   int64_t h2cols = 0;  // columns they hold
   bool h2 = false;  // H^2: uniform stages with augmented SVD bases, nested
   void setup_uniform(hipStream_t s);
@@ -1563,6 +1568,10 @@ void Compression::setup_h2(hipStream_t s) {
     HIP_TRY(hipStreamSynchronize(s));
   }
   build_h2_apply(vid, s);
+  // chunk partials of the outgoing expansions, for the largest chunk list
+  int64_t maxc = H->h2a.nchunk;
+  for (int32_t c : H->h2a.ntchunk) maxc = std::max<int64_t>(maxc, c);
+  buf(h2p, (size_t)std::max<int64_t>(maxc * kmax * h2cols, 1) * 8, s);
 }
 
 // The H^2 apply plan (alg:apply_h2_level_truncated) from the basis boxes.
@@ -1610,7 +1619,7 @@ void Compression::build_h2_apply(const std::vector<std::vector<int32_t>> &vid, h
       all_of[li].push_back(H2Leaf{Lv.start[a], H->uoff[li][v], (int32_t)T.box_size(l, a), g, 0, 0});
       if (kids[v].empty()) {
         const int32_t m = (int32_t)T.box_size(l, a);
-        leaf.push_back(H2Leaf{Lv.start[a], H->uoff[li][v], m, g, 0, 0});
+        leaf.push_back(H2Leaf{Lv.start[a], H->uoff[li][v], m, g, 0, (int32_t)chunk.size()});
         for (int32_t r0 = 0; r0 < m; r0 += 64)
           chunk.push_back(H2Leaf{Lv.start[a], H->uoff[li][v], m, g, r0, 0});
       } else {
@@ -1662,7 +1671,8 @@ void Compression::build_h2_apply(const std::vector<std::vector<int32_t>> &vid, h
     for (size_t li = 0; li < le; ++li)
       for (size_t v = 0; v < all_of[li].size(); ++v) {
         if (li + 1 < le && haskids[li][v]) continue;
-        const H2Leaf &b = all_of[li][v];
+        H2Leaf b = all_of[li][v];
+        b.c0 = (int32_t)tc.size();
         tl.push_back(b);
         for (int32_t r0 = 0; r0 < b.m; r0 += 64)
           tc.push_back(H2Leaf{b.row0, b.boff, b.m, b.g, r0, 0});
@@ -1718,7 +1728,7 @@ void Compression::record_h2_level(size_t li, hipStream_t s, Events &ev) {
     }
     ev.mark(2);
     h2_apply(*H, li, false, mixed, X, n, c1pad, Y, n, -1.0, h2q.as<double>(), h2u.as<double>(),
-             h2cols, s);
+             h2p.as<double>(), h2cols, s);
     launch_check_finite(n, c1pad, mixed, Y, n, flag.as<int32_t>(), s);
     LAUNCH_CHECK();
   }
@@ -1750,7 +1760,7 @@ void Compression::record_h2_level(size_t li, hipStream_t s, Events &ev) {
     }
     ev.mark(2);
     h2_apply(*H, li, true, mixed, X, n, c2pad, Y, n, -1.0, h2q.as<double>(), h2u.as<double>(),
-             h2cols, s);
+             h2p.as<double>(), h2cols, s);
     launch_check_finite(n, c2pad, mixed, Y, n, flag.as<int32_t>(), s);
     LAUNCH_CHECK();
   }
@@ -2023,7 +2033,7 @@ void Compression::record(hipStream_t s, Events &ev) {
   ev.mark(2);
   if (h2)
     h2_apply(*H, H->lv.size(), false, mixed, Xb.p, n, leaf_cols, Yb.p, n, -1.0, h2q.as<double>(),
-             h2u.as<double>(), h2cols, s);
+             h2u.as<double>(), h2p.as<double>(), h2cols, s);
   else
     apply_levels(*H, H->lv.size(), false, mixed, Xb.p, n, leaf_cols, Yb.p, n, -1.0, Tb.p, tcap,
                  s);

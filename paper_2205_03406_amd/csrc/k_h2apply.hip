@@ -17,15 +17,18 @@ namespace {
 
 constexpr int HC = 64;  // columns per workgroup (projection, expansion)
 
-// q_b(0:k, c) = sum_{i < m} V_b(i, 0:k) x(row0 + i, c): one workgroup per
-// (box, 64-column tile); rows staged 64 at a time through LDS.  Thread
-// (column cc, group ig) accumulates rows j = ig + 4 q (q < NQ, 4 NQ >= kmax)
-// of the expansion; rows past kmax read row kmax - 1 and are dropped.
+// The partial q_b(0:k, c) = sum_i V_b(i, 0:k) x(row0 + i, c) over one
+// 64-row chunk of a box: one workgroup per (chunk, 64-column tile), written
+// to PART at the chunk's index; the chunks of a large box run in parallel
+// (one workgroup walking a box of thousands of rows is latency-bound).
+// Thread (column cc, group ig) accumulates rows j = ig + 4 q (q < NQ,
+// 4 NQ >= kmax) of the expansion; rows past kmax read row kmax - 1 and are
+// dropped.
 template <typename T, int NQ>
 __global__ void __launch_bounds__(256)
 h2_project_kernel(const H2Leaf *__restrict__ jobs, int32_t kmax, const int32_t *__restrict__ rank,
                   const double *__restrict__ VB, const T *__restrict__ X, int64_t ldx,
-                  int64_t ncols, double *__restrict__ QH, int64_t ldq) {
+                  int64_t ncols, double *__restrict__ PART, int64_t ldq) {
   extern __shared__ double sm[];
   const int ldv = kmax + 1;
   double *Xs = sm;                  // [row][column], ld HC + 1
@@ -42,10 +45,10 @@ h2_project_kernel(const H2Leaf *__restrict__ jobs, int32_t kmax, const int32_t *
     acc[q] = 0.0;
     jr[q] = ig + 4 * q < kmax ? ig + 4 * q : kmax - 1;
   }
-  for (int r0 = 0; r0 < job.m; r0 += 64) {
+  {
+    const int r0 = job.r0;
     const int rows = job.m - r0 < 64 ? job.m - r0 : 64;
     const bool rin = cc < rows;
-    if (r0 > 0) __syncthreads();
     const T *xr = X + job.row0 + r0 + cc;
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
@@ -73,12 +76,31 @@ h2_project_kernel(const H2Leaf *__restrict__ jobs, int32_t kmax, const int32_t *
     if (j < kmax) Xs[cc * ldv + j] = j < k ? acc[q] : 0.0;
   }
   __syncthreads();
-  double *o = QH + (int64_t)job.g * kmax * ldq + c0 * kmax;
+  double *o = PART + (int64_t)blockIdx.x * kmax * ldq + c0 * kmax;
   const int64_t left = ncols - c0;
   const int ne = kmax * (int)(left < HC ? left : HC);
   for (int e = tid; e < ne; e += 256) {
     const int c = e / kmax, j = e - c * kmax;
     o[e] = Xs[c * ldv + j];
+  }
+}
+
+// QH[g] = the sum of the partials of box g's chunks, in chunk order
+// (deterministic); one workgroup per (box, 64-column tile).
+__global__ void __launch_bounds__(256)
+h2_reduce_kernel(const H2Leaf *__restrict__ leaf, int32_t kmax, const double *__restrict__ PART,
+                 double *__restrict__ QH, int64_t ldq, int64_t ncols) {
+  const H2Leaf job = leaf[blockIdx.x];
+  const int64_t c0 = (int64_t)blockIdx.y * HC;
+  const int64_t left = ncols - c0;
+  const int ne = kmax * (int)(left < HC ? left : HC);
+  const int nch = (job.m + 63) / 64;
+  const double *p = PART + (int64_t)job.c0 * kmax * ldq + c0 * kmax;
+  double *o = QH + (int64_t)job.g * kmax * ldq + c0 * kmax;
+  for (int e = threadIdx.x; e < ne; e += 256) {
+    double acc = 0.0;
+    for (int t = 0; t < nch; ++t) acc += p[(int64_t)t * kmax * ldq + e];
+    o[e] = acc;
   }
 }
 
@@ -238,13 +260,13 @@ h2_expand_kernel(const H2Leaf *__restrict__ jobs, int32_t kmax, const int32_t *_
 template <typename T>
 void project_nq(dim3 g, size_t lds, hipStream_t s, const H2Leaf *jobs, int32_t kmax,
                 const int32_t *rank, const double *VB, const T *X, int64_t ldx, int64_t ncols,
-                double *QH, int64_t ldq) {
+                double *PART, int64_t ldq) {
   if (kmax <= 16)
-    h2_project_kernel<T, 4><<<g, 256, lds, s>>>(jobs, kmax, rank, VB, X, ldx, ncols, QH, ldq);
+    h2_project_kernel<T, 4><<<g, 256, lds, s>>>(jobs, kmax, rank, VB, X, ldx, ncols, PART, ldq);
   else if (kmax <= 32)
-    h2_project_kernel<T, 8><<<g, 256, lds, s>>>(jobs, kmax, rank, VB, X, ldx, ncols, QH, ldq);
+    h2_project_kernel<T, 8><<<g, 256, lds, s>>>(jobs, kmax, rank, VB, X, ldx, ncols, PART, ldq);
   else
-    h2_project_kernel<T, 16><<<g, 256, lds, s>>>(jobs, kmax, rank, VB, X, ldx, ncols, QH, ldq);
+    h2_project_kernel<T, 16><<<g, 256, lds, s>>>(jobs, kmax, rank, VB, X, ldx, ncols, PART, ldq);
 }
 
 template <int HCT, int NQ>
@@ -258,17 +280,25 @@ void sum_launch(dim3 g, size_t lds, hipStream_t s, const H2Sum *jobs, const H2Te
 
 }  // namespace
 
-void launch_h2_project(int32_t njobs, const H2Leaf *jobs, int32_t kmax, const int32_t *rank,
+void launch_h2_project(int32_t nchunks, const H2Leaf *chunks, int32_t kmax, const int32_t *rank,
                        const double *VB, bool f32, const void *X, int64_t ldx, int64_t ncols,
-                       double *QH, int64_t ldq, hipStream_t s) {
-  if (njobs <= 0 || ncols <= 0 || kmax <= 0) return;
+                       double *PART, int64_t ldq, hipStream_t s) {
+  if (nchunks <= 0 || ncols <= 0 || kmax <= 0) return;
   if (kmax > 64) throw std::runtime_error("h2 apply: rank above 64");
-  dim3 g(njobs, (unsigned)((ncols + HC - 1) / HC));
+  dim3 g(nchunks, (unsigned)((ncols + HC - 1) / HC));
   const size_t lds = (size_t)(64 * (HC + 1) + 64 * (kmax + 1)) * sizeof(double);
   if (f32)
-    project_nq<float>(g, lds, s, jobs, kmax, rank, VB, (const float *)X, ldx, ncols, QH, ldq);
+    project_nq<float>(g, lds, s, chunks, kmax, rank, VB, (const float *)X, ldx, ncols, PART, ldq);
   else
-    project_nq<double>(g, lds, s, jobs, kmax, rank, VB, (const double *)X, ldx, ncols, QH, ldq);
+    project_nq<double>(g, lds, s, chunks, kmax, rank, VB, (const double *)X, ldx, ncols, PART,
+                       ldq);
+}
+
+void launch_h2_reduce(int32_t nleaf, const H2Leaf *leaf, int32_t kmax, const double *PART,
+                      double *QH, int64_t ldq, int64_t ncols, hipStream_t s) {
+  if (nleaf <= 0 || ncols <= 0 || kmax <= 0) return;
+  dim3 g(nleaf, (unsigned)((ncols + HC - 1) / HC));
+  h2_reduce_kernel<<<g, 256, 0, s>>>(leaf, kmax, PART, QH, ldq, ncols);
 }
 
 void launch_h2_sum(int32_t njobs, const H2Sum *jobs, const H2Term *terms, int32_t kmax,

@@ -281,13 +281,18 @@ struct H2Leaf {
   int64_t boff;   // its basis in UB / VB (m x kmax, ld m)
   int32_t m;      // rows of the box
   int32_t g;      // global basis index (ranks, expansions)
-  int32_t r0;     // first row of the chunk inside the box (expansion)
-  int32_t pad;
+  int32_t r0;     // first row of the chunk inside the box
+  int32_t c0;     // box records: index of the box's first chunk record
 };
-// QH[g] = V_g* X(rows of g), one job per box with long bases.
-void launch_h2_project(int32_t njobs, const H2Leaf *jobs, int32_t kmax, const int32_t *rank,
+// Outgoing expansions in two steps: every 64-row chunk (chunk list) its
+// partial V* x into PART (chunk-indexed, kmax x ncols, ld kmax), then every
+// box (leaf list; pad = its first chunk) the sum of its chunks' partials in
+// order into QH.
+void launch_h2_project(int32_t nchunks, const H2Leaf *chunks, int32_t kmax, const int32_t *rank,
                        const double *VB, bool f32, const void *X, int64_t ldx, int64_t ncols,
-                       double *QH, int64_t ldq, hipStream_t s);
+                       double *PART, int64_t ldq, hipStream_t s);
+void launch_h2_reduce(int32_t nleaf, const H2Leaf *leaf, int32_t kmax, const double *PART,
+                      double *QH, int64_t ldq, int64_t ncols, hipStream_t s);
 // OUT[g] = sum over the job's terms of M (x IN[src], or x PAR[src] for a parent term).
 struct H2Sum {
   int32_t g, t0, t1, pad;
