@@ -285,6 +285,12 @@ typedef struct {
 } hm_compress_opts;
 #define HM_FLAG_TIMING 1
 #define HM_FLAG_STRICT 2
+/* HM_FLAG_MIX_GAMMA (uniform H^1 and H^2 only; an extension, not the
+ * paper's rule): form the row-basis sample of box b as
+ * sum_a Z(I_b, block of (b, a)) Gamma_a with Gamma_a a kmax x kmax Gaussian
+ * (pass 3 of the generator, counter (first tree row of a, column/2, row of
+ * Gamma, 4*level + 3)) instead of the plain sum of the blocks. */
+#define HM_FLAG_MIX_GAMMA 4
 /* format = HM_FORMAT_UNIFORM_H1: uniform H^1 compression (section on
  * uniform H^1 compression), one column basis U_a and one row basis V_b per
  * box, shared by all admissible pairs: A(I_a, I_b) ~ U_a B_ab V_b*.  Per
@@ -295,9 +301,9 @@ typedef struct {
  *     with the rules (cap r - p, saturation, mixed floor) of hm_compress.
  *   stage 2: Psi = the level's pair-graph test matrix with U_a (k_a of kmax
  *     columns) in place of the Gaussian block on box a; Z = (A - A^(l))* Psi;
- *     V_b = qr(sum over a in int(b) of Z(I_b, block of (b, a)) Gamma_a, k),
- *     Gamma_a a kmax x kmax Gaussian (pass 3, counter (first tree row of a,
- *     column/2, row of Gamma, 4*level + 3)); rank at most kmax, no cap; in
+ *     V_b = qr(sum over a in int(b) of Z(I_b, block of (b, a)), k)
+ *     (alg:h2_pseudocode, "sum samples and orthonormalize"; HM_FLAG_MIX_GAMMA
+ *     selects the Gaussian-weighted extension); rank at most kmax, no cap; in
  *     the mixed form its floor is 8 u32 ||sum of the raw blocks||_F / sqrt(kmax).
  *   B_ab = Z(I_b, block of (b, a))[:, :k_a]* V_b.
  * kmax = rank (fixed rank) or r - p.  The leaf pass is that of hm_compress.
@@ -310,8 +316,8 @@ typedef struct {
  * a parent with a basis) gets bases, from the SVD of its sample augmented
  * with its parent's:  U_a = svd(Y(I_a, block) + U_tau(rows of a) S_tau G, k)
  * (G: k_tau x r Gaussian, counter (first tree row of a, column/2, 2^31 + row
- * of G, 4*level + 2)), and V_b likewise from the combination of the uniform
- * form (G: k_tau x kmax, 4*level + 3); singular vectors are signed so that
+ * of G, 4*level + 2)), and V_b likewise from the sum of the uniform form
+ * (G: k_tau x kmax, 4*level + 3); singular vectors are signed so that
  * their largest entry is positive.  After each level, the previous level's
  * bases become transfers U_a* U_tau(rows of a) (eq:nested_basis), and every
  * coarser level's bases are rebuilt from the finest ones through the

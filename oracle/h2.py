@@ -15,6 +15,11 @@ same test matrices and Psi) with three changes:
   the least-squares transfers Ushort_tau[a] = U_a* U_tau(I_tau(a), :) and
   the long basis of tau is dropped.
 
+The row bases come from the plain sum of the stage-2 blocks, augmented:
+V_b = svd(sum over a in int(b) of Z(I_b, block of (b, a)) + V_tau(I_tau(b), :)
+S_tau G, k), as alg:h2_pseudocode writes it (combine="gaussian" selects the
+Gamma-weighted combination of the uniform module's extension instead).
+
 The level-truncated matrix A^(l) subtracted while sampling level l is the
 H^2 matrix built so far (every coarser level), applied by the upward pass,
 couplings and downward pass of alg:apply_h2_level_truncated with the long
@@ -46,7 +51,7 @@ from __future__ import annotations
 import numpy as np
 
 from .numeric import gaussian_block, leaf_test_matrix
-from .uniform import UniformGraph, mixing_matrix, uniform_test_matrix
+from .uniform import COMBINE, UniformGraph, mixing_matrix, uniform_test_matrix
 
 AUG_SLOT = 1 << 31
 
@@ -208,9 +213,12 @@ class H2Matrix:
         return n
 
 
-def compress_h2(T, bb, r, k=0, tol=0.0, p=10, seed=0):
+def compress_h2(T, bb, r, k=0, tol=0.0, p=10, seed=0, combine="sum"):
     """H^2 compression of the black box bb (apply / applyT in the original
-    point order), alg:h2_pseudocode."""
+    point order), alg:h2_pseudocode in its H^2 branch.  combine as in
+    compress_uniform ("sum" is the paper's rule)."""
+    if combine not in COMBINE:
+        raise ValueError("combine must be one of %s" % (COMBINE,))
     if r <= 0:
         r = k + p
     kmax = k if k > 0 else r - p
@@ -280,8 +288,11 @@ def compress_h2(T, bb, r, k=0, tol=0.0, p=10, seed=0):
             S = np.zeros((b1 - b0, kmax))
             for a in T.interaction(l, b):
                 cq = int(G.color[G.pair_v[pidx[(b, int(a))]]])
-                S += Z[b0:b1, cq * kmax:(cq + 1) * kmax] @ mixing_matrix(
-                    seed, l, T.box_range(l, int(a))[0], kmax)
+                blk = Z[b0:b1, cq * kmax:(cq + 1) * kmax]
+                if combine == "sum":
+                    S += blk
+                else:
+                    S += blk @ mixing_matrix(seed, l, T.box_range(l, int(a))[0], kmax)
             if has_parent(b):
                 tau = int(par[b])
                 t0 = T.box_range(l - 1, tau)[0]

@@ -15,26 +15,25 @@ Per sampled level, coarsest first:
   replaced by the bases just computed: for the pair (a, b), Psi holds U_a on
   box a and zeros on the other boxes of b's parent's neighborhood, so
   Z = (A - A^(l))* Psi gives Z(I_b, block) = A(I_a, I_b)* U_a.  Then
-  V_b = qr(sum over a in the interaction list of b of Z(I_b, block of (b, a)) Gamma_a)
-  and B_ab = Z(I_b, block)* V_b.
+  V_b = qr(sum over a in the interaction list of b of Z(I_b, block of (b, a)), k)
+  (alg:h2_pseudocode, "sum samples and orthonormalize") and
+  B_ab = Z(I_b, block)* V_b.
 
-Readings (listed in the design notes): the paper forms V_b from the plain
-sum of the blocks A(I_a, I_b)* U_a.  That sum has only max k_a columns and
-mixes column j of every term, so it spans max k_a directions of the block
-column of b while the blocks together can span more (star curve, N = 1500,
-tol 1e-8: error 1.4e-4 against 9e-9 for the side-by-side blocks).  We weight
-each term with a Gaussian kmax x kmax matrix Gamma_a before summing (a
-randomized sample of the side-by-side blocks: 1.3e-8 there), drawn with
-pass number 3 of the counter-based generator, counter (first row of box a,
-column pair, row of Gamma, 4 level + 3).  Exact uniform H^1 matrices are
-recovered either way.  The Psi constraint of pair (a, b) is
+Readings (listed in the design notes): the Psi constraint of pair (a, b) is
 written in the paper with the roles of a and b exchanged; it is the Omega
 constraint set of the non-uniform pair (b, a), so the non-uniform level graph
 and its coloring serve stage 2 unchanged.  Stage-1 draws use pass number 2 of
 the counter-based generator.  Psi blocks are kmax = k (or r - p) columns wide,
-U_a in the first k_a of them.  The rank of V_b follows the rule of qr(., k)
-on the kmax-column sum (at most the largest k_a; saturation is counted in
-stage 1 only).
+U_a in the first k_a of them (zero beyond), so each summed block is
+A(I_a, I_b)* U_a padded with zero columns.  The rank of V_b follows the rule
+of qr(., k) on the kmax-column sum (at most the largest k_a; saturation is
+counted in stage 1 only).
+
+Extension (not the paper's rule, opt-in with combine="gaussian", no parity
+claim against the paper): each term is first multiplied by a Gaussian
+kmax x kmax matrix Gamma_a (pass 3 of the generator, counter (first row of
+box a, column pair, row of Gamma, 4 level + 3)), a randomized sample of the
+side-by-side blocks instead of their sum.
 The leaf pass is the non-uniform one.
 """
 from __future__ import annotations
@@ -47,9 +46,13 @@ from .numeric import (HMatrix, _basis, gaussian_block, leaf_test_matrix)
 PASS_UNIFORM, PASS_MIX = 2, 3
 
 
+COMBINE = ("sum", "gaussian")
+
+
 def mixing_matrix(seed, level, row0, kmax):
-    """Gamma_a (kmax x kmax): row i from the counter (row0, column pair, i,
-    4 level + 3), row0 = the first tree row of box a."""
+    """Gamma_a (kmax x kmax) of the combine="gaussian" extension: row i from
+    the counter (row0, column pair, i, 4 level + 3), row0 = the first tree
+    row of box a."""
     return np.vstack([gaussian_block(seed, level, PASS_MIX, i, [row0], kmax)[0]
                       for i in range(kmax)])
 
@@ -105,11 +108,16 @@ def _qr_rank(S, k, tol):
     return Q
 
 
-def compress_uniform(T, bb, r, k=0, tol=0.0, p=10, seed=0, return_graphs=False):
+def compress_uniform(T, bb, r, k=0, tol=0.0, p=10, seed=0, return_graphs=False, combine="sum"):
     """Uniform H^1 compression of the black box bb (apply / applyT in the
-    original point order).  Returns an HMatrix whose blocks are
-    (a, b, U_a, B_ab, V_b) in the pair order of the level graph, with the
-    per-box bases in H.ubasis[l] / H.vbasis[l]."""
+    original point order), alg:h2_pseudocode in its uniform H^1 branch.
+    Returns an HMatrix whose blocks are (a, b, U_a, B_ab, V_b) in the pair
+    order of the level graph, with the per-box bases in H.ubasis[l] /
+    H.vbasis[l].  combine="sum" (default) forms V_b from the plain sum of
+    the sample blocks as the paper does; "gaussian" is the extension of the
+    module docstring."""
+    if combine not in COMBINE:
+        raise ValueError("combine must be one of %s" % (COMBINE,))
     if r <= 0:
         r = k + p
     kmax = k if k > 0 else r - p
@@ -156,8 +164,11 @@ def compress_uniform(T, bb, r, k=0, tol=0.0, p=10, seed=0, return_graphs=False):
             S = np.zeros((b1 - b0, kmax))
             for a in T.interaction(l, b):
                 cq = int(G.color[G.pair_v[pair_index[(b, int(a))]]])
-                Gam = mixing_matrix(seed, l, T.box_range(l, int(a))[0], kmax)
-                S += Z[b0:b1, cq * kmax:(cq + 1) * kmax] @ Gam
+                blk = Z[b0:b1, cq * kmax:(cq + 1) * kmax]
+                if combine == "sum":
+                    S += blk
+                else:
+                    S += blk @ mixing_matrix(seed, l, T.box_range(l, int(a))[0], kmax)
             V[b] = _qr_rank(S, k, tol)
         blocks = []
         for q in range(len(G.pair_a)):

@@ -650,16 +650,24 @@ class Server:
                     running=run.value, residents=res.value)
 
 
-HM_FLAG_TIMING, HM_FLAG_STRICT = 1, 2
+HM_FLAG_TIMING, HM_FLAG_STRICT, HM_FLAG_MIX_GAMMA = 1, 2, 4
+
+
+def _flags(timing, strict, combine):
+    if combine not in ("sum", "gaussian"):
+        raise ValueError("combine must be 'sum' or 'gaussian'")
+    return ((HM_FLAG_TIMING if timing else 0) | (HM_FLAG_STRICT if strict else 0)
+            | (HM_FLAG_MIX_GAMMA if combine == "gaussian" else 0))
 
 
 def compress(tree: Tree, bb: BlackBox, rank=0, tol=0.0, r=0, p=10, prec=HM_PREC_F64, seed=0,
              timing=False, stream=None, max_retries=0, strict=False, uniform=False,
-             h2=False) -> HMatrix:
+             h2=False, combine="sum") -> HMatrix:
     """hm_compress; uniform=True selects the uniform H^1 format, h2=True the
-    H^2 format."""
+    H^2 format; combine="gaussian" sets HM_FLAG_MIX_GAMMA (their row bases
+    from the Gaussian-weighted combination instead of the plain sum)."""
     o = Opts(rank=rank, tol=tol, oversample=p, r=r, prec=prec,
-             flags=(HM_FLAG_TIMING if timing else 0) | (HM_FLAG_STRICT if strict else 0),
+             flags=_flags(timing, strict, combine),
              seed=seed, max_retries=max_retries, format=_format(uniform, h2))
     h = C.c_void_p()
     _check(_lib.hm_compress(tree.h, C.byref(bb), C.byref(o), _stream(stream), C.byref(h)))

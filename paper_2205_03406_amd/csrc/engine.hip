@@ -1712,6 +1712,7 @@ void Compression::record_h2_level(size_t li, hipStream_t s, Events &ev) {
     }
   };
   constexpr double kNoiseGamma = 8.0;
+  const bool gamma = (o.flags & HM_FLAG_MIX_GAMMA) != 0;  // extension: weighted combination
   // ---------------- stage 1: augmented samples, SVD column bases
   if (UG.nv() > 0) {
     ev.mark(0);
@@ -1751,7 +1752,7 @@ void Compression::record_h2_level(size_t li, hipStream_t s, Events &ev) {
     apply_bb(1, c2pad, J.kit2, J.nkit2);
     cols_At += c2;
     if (mixed) {
-      launch_mix_sum(J.nmix, J.mix.as<MixJob>(), J.terms.as<MixTerm>(), kmax, l, o.seed, true, Y,
+      launch_mix_sum(J.nmix, J.mix.as<MixJob>(), J.terms.as<MixTerm>(), kmax, l, o.seed, gamma, true, Y,
                      n, Sb.as<double>(), n, s);
       launch_block_norms(J.nv, J.jvn.as<QrJob>(), kmax,
                          kNoiseGamma * 0x1p-24 / std::sqrt((double)kmax), false, Sb.p, n,
@@ -1765,7 +1766,7 @@ void Compression::record_h2_level(size_t li, hipStream_t s, Events &ev) {
     LAUNCH_CHECK();
   }
   ev.mark(3);
-  launch_mix_sum(J.nmix, J.mix.as<MixJob>(), J.terms.as<MixTerm>(), kmax, l, o.seed, mixed, Y, n,
+  launch_mix_sum(J.nmix, J.mix.as<MixJob>(), J.terms.as<MixTerm>(), kmax, l, o.seed, gamma, mixed, Y, n,
                  Sb.as<double>(), n, s);
   launch_h2_sample(J.naug, J.augv.as<AugJob>(), kmax, l, 3, o.seed, false, Sb.p, n,
                    H->VB.as<double>(), rk + nb, H->SV.as<double>(), kmax, Sb.as<double>(), n, s);
@@ -1833,6 +1834,7 @@ void Compression::record_uniform_level(size_t li, hipStream_t s, Events &ev) {
     }
   };
   constexpr double kNoiseGamma = 8.0;  // see the mixed floor of record()
+  const bool gamma = (o.flags & HM_FLAG_MIX_GAMMA) != 0;  // extension: weighted combination
   // ---------------- stage 1: Y = (A - A^(l)) Omega, U_a = qr(Y(I_a, block))
   ev.mark(0);
   launch_testmat(n, Dv.rowbox[l].as<int32_t>(), J.act.as<uint8_t>(), UG.ncolors, r, l, 2, o.seed,
@@ -1855,7 +1857,7 @@ void Compression::record_uniform_level(size_t li, hipStream_t s, Events &ev) {
                mixed ? floor_u.as<double>() : nullptr, mixed, Y, n, work.as<double>(),
                H->UB.as<double>(), urank, usat.as<int32_t>() + v0, s);
   LAUNCH_CHECK();
-  // ---------------- stage 2: Z = (A - A^(l))* Psi(U), V_b = qr(sum_a Z_ba Gamma_a)
+  // ---------------- stage 2: Z = (A - A^(l))* Psi(U), V_b = qr(sum_a Z_ba)
   ev.mark(0);
   launch_basis_testmat(n, Dv.rowbox[l].as<int32_t>(), Dv.start[l].as<int64_t>(),
                        J.slot.as<int32_t>(), G.ncolors, kmax, H->UB.as<double>(),
@@ -1866,7 +1868,7 @@ void Compression::record_uniform_level(size_t li, hipStream_t s, Events &ev) {
   cols_At += c2;
   if (mixed) {
     // floor from the combination of the raw (unpeeled) blocks
-    launch_mix_sum(J.nmix, J.mix.as<MixJob>(), J.terms.as<MixTerm>(), kmax, l, o.seed, true, Y,
+    launch_mix_sum(J.nmix, J.mix.as<MixJob>(), J.terms.as<MixTerm>(), kmax, l, o.seed, gamma, true, Y,
                    n, Sb.as<double>(), n, s);
     launch_block_norms(J.nv, J.jv.as<QrJob>(), kmax,
                        kNoiseGamma * 0x1p-24 / std::sqrt((double)kmax), false, Sb.p, n,
@@ -1878,7 +1880,7 @@ void Compression::record_uniform_level(size_t li, hipStream_t s, Events &ev) {
   launch_check_finite(n, c2pad, mixed, Y, n, flag.as<int32_t>(), s);
   LAUNCH_CHECK();
   ev.mark(3);
-  launch_mix_sum(J.nmix, J.mix.as<MixJob>(), J.terms.as<MixTerm>(), kmax, l, o.seed, mixed, Y, n,
+  launch_mix_sum(J.nmix, J.mix.as<MixJob>(), J.terms.as<MixTerm>(), kmax, l, o.seed, gamma, mixed, Y, n,
                  Sb.as<double>(), n, s);
   launch_pivqr(J.nv, J.jv.as<QrJob>(), kmax, kfix, o.tol, kmax,
                mixed ? floor_v.as<double>() : nullptr, false, Sb.p, n, work.as<double>(),

@@ -1,7 +1,8 @@
 // Uniform H^1 and H^2 kernels (sections on uniform H^1 and on H^2
 // compression): the stage-2 test matrix assembled from the stage-1 column
-// bases, the randomized combination of a box's sample blocks whose basis is
-// the box's row basis, the parent augmentation of H^2 samples and the
+// bases, the sum of a box's sample blocks whose basis is the box's row
+// basis (or, as an extension, a Gaussian-weighted combination), the parent
+// augmentation of H^2 samples and the
 // nesting of bases through transfer matrices.  All are row-parallel (one
 // row per thread, coalesced along the column-major row index).
 #include "device_common.h"
@@ -34,10 +35,37 @@ basis_testmat_kernel(int64_t n, const int32_t *__restrict__ rowbox,
   out[col * ld + i] = (T)v;
 }
 
-// One workgroup per job (a chunk of <= 256 rows of one box), one row per
-// thread, kmax accumulators per thread.  Per term, Gamma is drawn into LDS
-// by the whole workgroup (kmax * ceil(kmax/2) Philox draws), then every row
-// takes its kmax x kmax product with the term's Z block.
+// Row-basis sample of a box: the sum of the box's Z blocks over its
+// interaction list (alg:h2_pseudocode, "sum samples"), in term order.  One
+// workgroup per job (a chunk of <= 256 rows of one box), one row per
+// thread, kmax FP64 accumulators per thread.
+template <typename T>
+__global__ void __launch_bounds__(256)
+sum_blocks_kernel(const MixJob *__restrict__ jobs, const MixTerm *__restrict__ terms,
+                  int32_t kmax, const T *__restrict__ Z, int64_t ldz, double *__restrict__ S,
+                  int64_t lds) {
+  const MixJob job = jobs[blockIdx.x];
+  const int tid = threadIdx.x;
+  if (tid >= job.m) return;
+  double acc[64];
+#pragma unroll
+  for (int j = 0; j < 64; ++j) acc[j] = 0.0;
+  for (int t = job.t0; t < job.t1; ++t) {
+    const T *zr = Z + terms[t].zcol0 * ldz + job.row0 + tid;
+#pragma unroll
+    for (int j = 0; j < 64; ++j)
+      if (j < kmax) acc[j] += (double)zr[(int64_t)j * ldz];
+  }
+#pragma unroll
+  for (int j = 0; j < 64; ++j)
+    if (j < kmax) S[(int64_t)j * lds + job.row0 + tid] = acc[j];
+}
+
+// The Gaussian-weighted combination (an extension, HM_FLAG_MIX_GAMMA): each
+// term is multiplied by Gamma_a before the sum.  Same jobs and layout as
+// sum_blocks_kernel.  Per term, Gamma is drawn into LDS by the whole
+// workgroup (kmax * ceil(kmax/2) Philox draws), then every row takes its
+// kmax x kmax product with the term's Z block.
 template <typename T>
 __global__ void __launch_bounds__(256)
 mix_sum_kernel(const MixJob *__restrict__ jobs, const MixTerm *__restrict__ terms, int32_t kmax,
@@ -199,9 +227,18 @@ void launch_basis_testmat(int64_t n, const int32_t *rowbox, const int64_t *box_s
 }
 
 void launch_mix_sum(int32_t njobs, const MixJob *jobs, const MixTerm *terms, int32_t kmax,
-                    int32_t level, uint64_t seed, bool f32, const void *Z, int64_t ldz, double *S,
-                    int64_t lds, hipStream_t s) {
+                    int32_t level, uint64_t seed, bool gamma, bool f32, const void *Z,
+                    int64_t ldz, double *S, int64_t lds, hipStream_t s) {
   if (njobs <= 0 || kmax <= 0 || kmax > 64) return;
+  if (!gamma) {
+    if (f32)
+      sum_blocks_kernel<float><<<njobs, 256, 0, s>>>(jobs, terms, kmax, (const float *)Z, ldz, S,
+                                                     lds);
+    else
+      sum_blocks_kernel<double><<<njobs, 256, 0, s>>>(jobs, terms, kmax, (const double *)Z, ldz,
+                                                      S, lds);
+    return;
+  }
   if (f32)
     mix_sum_kernel<float><<<njobs, 256, 0, s>>>(jobs, terms, kmax, level, seed, (const float *)Z,
                                                 ldz, S, lds);

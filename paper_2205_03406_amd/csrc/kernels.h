@@ -204,8 +204,8 @@ struct MixTerm {
   uint32_t inst;   // instance of the pair
 };
 void launch_mix_sum(int32_t njobs, const MixJob *jobs, const MixTerm *terms, int32_t kmax,
-                    int32_t level, uint64_t seed, bool f32, const void *Z, int64_t ldz, double *S,
-                    int64_t lds, hipStream_t s);
+                    int32_t level, uint64_t seed, bool gamma, bool f32, const void *Z,
+                    int64_t ldz, double *S, int64_t lds, hipStream_t s);
 // Per admissible pair (a, b) of a uniform level: B = Z(I_b, block of (b, a))[:, :k_a]^T V_b,
 // W = U_a B, and the per-pair copies of U_a and V_b with their ranks.
 struct UCJob {

@@ -28,3 +28,41 @@ def dense_of(hm, H, n):
     Y = hm.colmajor(n, n)
     H.matvec(I, Y, order=hm.HM_ORDER_ORIGINAL)
     return to_host(Y)
+
+
+def pair_parity(O, pairs, A_norm_of, rel, mismatch_rel, floor):
+    """Per-block parity of admissible pairs.
+
+    pairs: iterable of (level, a, b, gpu_block, oracle_block, gpu_ranks,
+    oracle_ranks) with the blocks as dense |a| x |b| arrays (U B V*).  Where
+    the GPU and the oracle chose the same ranks the difference must be within
+    rel * ||A(I_a, I_b)||_F + floor; a rank chosen differently (a singular
+    value at the tolerance, decided differently by rounding) is counted and
+    held to mismatch_rel instead.  Returns (worst relative difference where
+    the ranks agree, number of rank mismatches, number of blocks)."""
+    worst = 0.0
+    mism = 0
+    nblk = 0
+    for l, a, b, G, W, rg, ro in pairs:
+        nblk += 1
+        nb = A_norm_of(l, a, b)
+        d = np.linalg.norm(G - W)
+        if tuple(rg) == tuple(ro):
+            worst = max(worst, d / max(nb, 1e-300))
+            assert d <= rel * nb + floor, (l, a, b, d, nb, rg)
+        else:
+            mism += 1
+            assert d <= mismatch_rel * nb + floor, (l, a, b, d, nb, rg, ro)
+    return worst, mism, nblk
+
+
+def block_norms(O, A):
+    """||A(I_a, I_b)||_F for boxes of level l (tree order), from the dense
+    original-order matrix A."""
+    perm = O.perm
+
+    def f(l, a, b):
+        a0, a1 = O.box_range(l, a)
+        b0, b1 = O.box_range(l, b)
+        return np.linalg.norm(A[np.ix_(perm[a0:a1], perm[b0:b1])])
+    return f

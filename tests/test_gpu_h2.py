@@ -1,15 +1,20 @@
 """H^2 compression on the GPU (hm_compress with HM_FORMAT_H2) against the
 oracle's compress_h2.
 
+The row bases follow the paper's rule (plain sum of the stage-2 samples,
+augmented); the Gaussian-weighted extension is checked against the
+oracle's extension.
+
 Bars (FP64): exact H^2 matrices recovered to 1e-11 relative, every block
 (through the nested bases) equal to the oracle's within 1e-10 of the block
 norm, the finest level's bases equal to the oracle's singular vectors
 within 1e-9 (same signs: the largest entry positive), float and matvec
-counts equal to the oracle's; kernel matrices: blocks within 10 tol of the
-block norm of the oracle's (plus 1e-12 ||A||), error within twice the
-oracle's (or 20 tol), storage below the uniform H^1 form.  Mixed within
-1e-5 of FP64; a forest equal to its instances alone within 1e-10; plan
-replays equal to eager.
+counts equal to the oracle's; kernel matrices: blocks within 1e-10 of the
+block norm of the oracle's (plus 1e-12 ||A||) where the ranks agree (rank
+mismatches counted, at most 1 %, held to 10 tol), error equal to the
+oracle's, storage below the uniform H^1 form.  Mixed within 1e-5 of the
+FP64 oracle at fixed rank; a forest equal to its instances alone within
+1e-10; plan replays equal to eager.
 """
 import numpy as np
 import pytest
@@ -17,7 +22,7 @@ import pytest
 import oracle
 import workloads
 from synth import exact_h2
-from devutil import to_dev, to_host, dense_of
+from devutil import to_dev, to_host, dense_of, pair_parity, block_norms
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -39,24 +44,23 @@ TREES = {
 }
 
 
-def _parity(O, H, Ho, A, rel):
-    floor = 1e-12 * np.linalg.norm(A)
+def _parity(O, H, Ho, A, rel, mismatch_rel=None):
+    """Every block through the nested bases against the oracle's
+    (pair_parity).  Returns (worst difference where the ranks agree, rank
+    mismatches, blocks)."""
     Ue, Ve = Ho.effective_bases()
-    perm = O.perm
-    worst = 0.0
-    for l in Ho.levels:
-        g = H.export_level(l)
-        o = Ho.B[l]
-        assert len(g) == len(o)
-        for (a, b, U, B, V), (a2, b2, B2) in zip(g, o):
-            assert (a, b) == (a2, b2)
-            a0, a1 = O.box_range(l, a)
-            b0, b1 = O.box_range(l, b)
-            nb = np.linalg.norm(A[np.ix_(perm[a0:a1], perm[b0:b1])])
-            d = np.linalg.norm(U @ B @ V.T - Ue[l][a] @ B2 @ Ve[l][b].T)
-            worst = max(worst, d / max(nb, 1e-300))
-            assert d <= rel * nb + floor, (l, a, b, d, nb)
-    return worst
+
+    def pairs():
+        for l in Ho.levels:
+            g = H.export_level(l)
+            o = Ho.B[l]
+            assert len(g) == len(o)
+            for (a, b, U, B, V), (a2, b2, B2) in zip(g, o):
+                assert (a, b) == (a2, b2)
+                yield (l, a, b, U @ B @ V.T, Ue[l][a] @ B2 @ Ve[l][b].T, B.shape, B2.shape)
+    return pair_parity(O, pairs(), block_norms(O, A), rel,
+                       rel if mismatch_rel is None else mismatch_rel,
+                       1e-12 * np.linalg.norm(A))
 
 
 @pytest.mark.parametrize("name", ["strong2d", "strong3d", "curve", "hodlr"])
@@ -70,7 +74,7 @@ def test_h2_exact_recovery(hm, name):
     D = dense_of(hm, H, O.n)
     assert np.linalg.norm(D - A) <= 1e-11 * np.linalg.norm(A)
     Ho = oracle.compress_h2(O, oracle.DenseBlackBox(A), 10, k=4, seed=77)
-    _parity(O, H, Ho, A, rel=1e-10)
+    assert _parity(O, H, Ho, A, rel=1e-10)[1] == 0
     # the finest level's bases are the oracle's singular vectors, signs included
     f = Ho.levels[-1]
     seen = set()
@@ -90,22 +94,27 @@ def test_h2_exact_recovery(hm, name):
 
 @pytest.mark.parametrize("n,tol", [(1500, 1e-8), (3000, 1e-6)])
 def test_h2_kernel_parity(hm, n, tol):
+    """Tolerance mode: every block within 1e-10 of the oracle's where the
+    ranks agree (mismatches counted, held to 10 tol), error equal to the
+    oracle's, storage and device memory below the uniform form."""
     inst = workloads.config(1, n=n)
     O = oracle.OTree(inst.points, inst.leaf, inst.tree, inst.adm)
     T = hm.Tree(inst.points, inst.leaf, inst.tree, inst.adm).color()
     A = oracle.kernel_matrix(inst.points, inst.points, inst.kernel)
     H = hm.compress(T, T.kernel_blackbox(inst.kernel), tol=tol, r=24, seed=inst.seed, h2=True)
     Ho = oracle.compress_h2(O, oracle.DenseBlackBox(A), 24, tol=tol, seed=inst.seed)
-    worst = _parity(O, H, Ho, A, rel=10 * tol)
+    worst, mism, nblk = _parity(O, H, Ho, A, rel=1e-10, mismatch_rel=10 * tol)
     D = dense_of(hm, H, O.n)
     err = np.linalg.norm(D - A) / np.linalg.norm(A)
     err_o = np.linalg.norm(Ho.dense() - A) / np.linalg.norm(A)
     st = H.stats()
     Hu = hm.compress(T, T.kernel_blackbox(inst.kernel), tol=tol, r=24, seed=inst.seed,
                      uniform=True)
-    print("h2: err %.2e (oracle %.2e), worst block diff %.1e, floats %d (oracle %d, uniform %d)"
-          % (err, err_o, worst, st["nfloats"], Ho.floats(), Hu.stats()["nfloats"]))
-    assert err <= max(2 * err_o, 20 * tol)
+    print("h2: err %.2e (oracle %.2e), worst block diff %.1e, rank mismatches %d of %d, "
+          "floats %d (oracle %d, uniform %d)"
+          % (err, err_o, worst, mism, nblk, st["nfloats"], Ho.floats(), Hu.stats()["nfloats"]))
+    assert mism <= 0.01 * nblk
+    assert abs(err - err_o) <= 0.05 * err_o + 1e-12
     assert abs(st["nfloats"] - Ho.floats()) <= 0.01 * Ho.floats()
     assert st["nfloats"] < Hu.stats()["nfloats"]
     assert st["saturated"] == 0
@@ -115,21 +124,42 @@ def test_h2_kernel_parity(hm, n, tol):
     assert 0 < st["device_bytes"] < Hu.stats()["device_bytes"]
 
 
-def test_h2_mixed_matches_f64(hm):
+def test_h2_gamma_extension_parity(hm):
+    """The Gaussian-weighted row-basis combination (HM_FLAG_MIX_GAMMA, an
+    extension) against the oracle's combine="gaussian" at fixed rank."""
+    inst = workloads.config(1, n=1500)
+    O = oracle.OTree(inst.points, inst.leaf, inst.tree, inst.adm)
+    T = hm.Tree(inst.points, inst.leaf, inst.tree, inst.adm).color()
+    A = oracle.kernel_matrix(inst.points, inst.points, inst.kernel)
+    H = hm.compress(T, T.kernel_blackbox(inst.kernel), rank=14, r=24, seed=inst.seed, h2=True,
+                    combine="gaussian")
+    Ho = oracle.compress_h2(O, oracle.DenseBlackBox(A), 24, k=14, seed=inst.seed,
+                            combine="gaussian")
+    worst, mism, nblk = _parity(O, H, Ho, A, rel=1e-10)
+    assert mism == 0
+    err = np.linalg.norm(dense_of(hm, H, O.n) - A) / np.linalg.norm(A)
+    err_o = np.linalg.norm(Ho.dense() - A) / np.linalg.norm(A)
+    print("h2 gamma extension: err %.2e (oracle %.2e), worst block diff %.1e" % (err, err_o, worst))
+    assert abs(err - err_o) <= 0.05 * err_o + 1e-12
+
+
+def test_h2_mixed_against_oracle(hm):
+    """Mixed form at the paper's fixed rank against the FP64 oracle's H^2
+    compression of the same inputs: within 1e-5 of it."""
     inst = workloads.config(1, n=4096)
+    O = oracle.OTree(inst.points, inst.leaf, inst.tree, inst.adm)
     T = hm.Tree(inst.points, inst.leaf, inst.tree, inst.adm).color()
     bb = T.kernel_blackbox(inst.kernel)
-    H64 = hm.compress(T, bb, tol=1e-6, r=24, seed=5, h2=True)
-    H32 = hm.compress(T, bb, tol=1e-6, r=24, seed=5, h2=True, prec=hm.HM_PREC_MIXED)
-    X = np.random.default_rng(0).standard_normal((T.n, 4))
-    a, b = hm.colmajor(T.n, 4), hm.colmajor(T.n, 4)
-    H64.matvec(to_dev(X), a)
-    H32.matvec(to_dev(X), b)
-    a, b = to_host(a), to_host(b)
-    d = np.linalg.norm(a - b) / np.linalg.norm(a)
-    print("mixed vs FP64 H2: %.2e" % d)
+    A = oracle.kernel_matrix(inst.points, inst.points, inst.kernel)
+    Ho = oracle.compress_h2(O, oracle.DenseBlackBox(A), 24, k=14, seed=5)
+    H32 = hm.compress(T, bb, rank=14, r=24, seed=5, h2=True, prec=hm.HM_PREC_MIXED)
+    D32, Do = dense_of(hm, H32, T.n), Ho.dense()
+    d = np.linalg.norm(D32 - Do) / np.linalg.norm(Do)
+    e32 = np.linalg.norm(D32 - A) / np.linalg.norm(A)
+    eo = np.linalg.norm(Do - A) / np.linalg.norm(A)
+    print("mixed H2 vs FP64 oracle: %.2e; errors %.2e (oracle %.2e)" % (d, e32, eo))
     assert d <= 1e-5
-    assert H32.stats()["saturated"] == 0
+    assert e32 <= eo + 1e-5
 
 
 def test_h2_forest_matches_instances(hm):
@@ -177,7 +207,7 @@ def test_h2_plan_replays(hm):
 
 def test_h2_kernel_fixed_rank_parity(hm):
     """Fixed rank (the setting of the paper's experiments): blocks against
-    the oracle's within 1e-8 of the block norm, error within twice the
+    the oracle's within 1e-10 of the block norm, error within twice the
     oracle's."""
     inst = workloads.config(1, n=3000)
     O = oracle.OTree(inst.points, inst.leaf, inst.tree, inst.adm)
@@ -185,7 +215,8 @@ def test_h2_kernel_fixed_rank_parity(hm):
     A = oracle.kernel_matrix(inst.points, inst.points, inst.kernel)
     H = hm.compress(T, T.kernel_blackbox(inst.kernel), rank=14, r=24, seed=inst.seed, h2=True)
     Ho = oracle.compress_h2(O, oracle.DenseBlackBox(A), 24, k=14, seed=inst.seed)
-    worst = _parity(O, H, Ho, A, rel=1e-8)
+    worst, mism, _ = _parity(O, H, Ho, A, rel=1e-10)
+    assert mism == 0
     err = np.linalg.norm(dense_of(hm, H, O.n) - A) / np.linalg.norm(A)
     err_o = np.linalg.norm(Ho.dense() - A) / np.linalg.norm(A)
     print("h2 fixed rank: err %.2e (oracle %.2e), worst block diff %.1e" % (err, err_o, worst))

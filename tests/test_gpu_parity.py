@@ -2,12 +2,14 @@
 
 Tolerances (FP64 path): Philox words bit-exact; Gaussians within 8 ulps
 (libm vs device log/sin/cos); kernel apply within 1e-13 relative Frobenius
-(different summation order over N terms); reconstructed blocks within
-1e-8 of the block norm plus a floor of 1e-12 ||A|| (the tolerance the
-compression itself runs at, far above rounding; a pivot chosen differently
-between near-equal column norms moves the basis but not the block).
-Mixed path (FP32 kernel apply and peel): 1e-5 relative Frobenius against the
-FP64 result.
+and, element by element, within 1e-13 of sum_j |A_ij X_j| (the scale of a
+sum's rounding); reconstructed blocks within 1e-10 of the block norm plus a
+floor of 1e-12 ||A|| wherever the GPU and the oracle chose the same ranks (a
+pivot chosen differently between near-equal column norms moves the basis
+but not the block); a rank decided differently at the tolerance is counted
+(at most 1 % of the blocks) and held to 10 tol; the whole operator within
+1e-8 of the oracle's.  Mixed path (FP32 kernel apply and peel): 1e-5
+relative Frobenius against the FP64 oracle.
 """
 import numpy as np
 import pytest
@@ -15,7 +17,7 @@ import pytest
 import workloads
 import oracle
 from synth import exact_h1
-from devutil import to_dev, to_host, dense_of
+from devutil import to_dev, to_host, dense_of, pair_parity, block_norms
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -100,42 +102,54 @@ def test_kernel_apply(hm, dim, kernel, n, ncols):
     X = np.random.default_rng(n).standard_normal((n, ncols))
     A = oracle.kernel_matrix(pts, pts, kernel)
     want = A @ X                               # original order
+    # element-wise scale of a sum's rounding: sum_j |A_ij X_jc|
+    scale = np.abs(A) @ np.abs(X)
     Xd, Yd = to_dev(X), hm.colmajor(n, ncols)
     T.kernel_apply(kernel, Xd, Yd, order=hm.HM_ORDER_ORIGINAL)
     got = to_host(Yd)
     assert np.linalg.norm(got - want) <= 1e-13 * np.linalg.norm(want)
+    assert np.max(np.abs(got - want) / scale) <= 1e-13
     Xt = to_dev(X[perm])                       # tree order
     T.kernel_apply(kernel, Xt, Yd, order=hm.HM_ORDER_TREE)
     assert np.linalg.norm(to_host(Yd) - want[perm]) <= 1e-13 * np.linalg.norm(want)
     X32, Y32 = to_dev(X, torch.float32), hm.colmajor(n, ncols, dtype=torch.float32)
     T.kernel_apply(kernel, X32, Y32, order=hm.HM_ORDER_ORIGINAL)
-    assert np.linalg.norm(to_host(Y32) - want) <= 2e-5 * np.linalg.norm(want)
+    got32 = to_host(Y32)
+    assert np.linalg.norm(got32 - want) <= 2e-5 * np.linalg.norm(want)
+    # FP32 inputs: X rounded to FP32 (u32 per term) plus the FP32 kernel values
+    assert np.max(np.abs(got32 - want) / scale) <= 1e-5
 
 
-def _block_parity(T, O, Hg, Ho, A, rel=1e-8):
+def _block_parity(T, O, Hg, Ho, A, rel=1e-10, mismatch_rel=None):
+    """Every admissible block U B V* and every leaf block against the
+    oracle's: within rel of the block norm where the ranks agree; a rank
+    decided differently (a singular value at the tolerance) is counted and
+    held to mismatch_rel.  Returns (worst, mismatches, blocks)."""
     floor = 1e-12 * np.linalg.norm(A)
-    perm = O.perm
-    for l in O.sampled_levels():
-        g = Hg.export_level(l)
-        o = Ho.lowrank[l]
-        assert len(g) == len(o)
-        for (a, b, U, B, V), (a2, b2, U2, B2, V2) in zip(g, o):
-            assert (a, b) == (a2, b2)
-            a0, a1 = O.box_range(l, a)
-            b0, b1 = O.box_range(l, b)
-            Ab = A[np.ix_(perm[a0:a1], perm[b0:b1])]
-            d = np.linalg.norm(U @ B @ V.T - U2 @ B2 @ V2.T)
-            assert d <= rel * np.linalg.norm(Ab) + floor, (l, a, b, d, np.linalg.norm(Ab))
-            # orthonormal bases
-            if U.shape[1]:
-                assert np.allclose(U.T @ U, np.eye(U.shape[1]), atol=1e-12)
-            if V.shape[1]:
-                assert np.allclose(V.T @ V, np.eye(V.shape[1]), atol=1e-12)
+
+    def pairs():
+        for l in O.sampled_levels():
+            g = Hg.export_level(l)
+            o = Ho.lowrank[l]
+            assert len(g) == len(o)
+            for (a, b, U, B, V), (a2, b2, U2, B2, V2) in zip(g, o):
+                assert (a, b) == (a2, b2)
+                # orthonormal bases
+                if U.shape[1]:
+                    assert np.allclose(U.T @ U, np.eye(U.shape[1]), atol=1e-12)
+                if V.shape[1]:
+                    assert np.allclose(V.T @ V, np.eye(V.shape[1]), atol=1e-12)
+                yield (l, a, b, U @ B @ V.T, U2 @ B2 @ V2.T, (U.shape[1], V.shape[1]),
+                       (U2.shape[1], V2.shape[1]))
+    res = pair_parity(O, pairs(), block_norms(O, A), rel,
+                      rel if mismatch_rel is None else mismatch_rel, floor)
     gn = Hg.export_near()
     assert len(gn) == len(Ho.near)
+    lim = rel if res[1] == 0 else (rel if mismatch_rel is None else mismatch_rel)
     for (a, b, D), (a2, b2, D2) in zip(gn, Ho.near):
         assert (a, b) == (a2, b2)
-        assert np.linalg.norm(D - D2) <= rel * np.linalg.norm(D2) + floor
+        assert np.linalg.norm(D - D2) <= lim * np.linalg.norm(D2) + floor
+    return res
 
 
 @pytest.mark.parametrize("case", ["strong2d", "curve", "hodlr", "strong3d"])
@@ -158,7 +172,7 @@ def test_exact_recovery_dense_blackbox(hm, case):
     D = dense_of(hm, H, n)
     assert np.linalg.norm(D - A) <= 1e-11 * np.linalg.norm(A)
     Ho = oracle.compress(O, oracle.DenseBlackBox(A), 10, k=4, seed=77)
-    _block_parity(T, O, H, Ho, A, rel=1e-10)
+    assert _block_parity(T, O, H, Ho, A, rel=1e-10)[1] == 0
     st = H.stats()
     chis = [T.graph(l).ncolors for l in O.sampled_levels()]
     assert st["cols_At"] == 10 * sum(chis)
@@ -179,7 +193,7 @@ def test_hodlr_config_parity(hm):
     assert (st["cols_A"], st["cols_At"]) == (304, 240)
     A = oracle.kernel_matrix(inst.points, inst.points, inst.kernel)
     Ho = oracle.compress(O, oracle.DenseBlackBox(A), inst.r, k=inst.rank, seed=inst.seed)
-    _block_parity(T, O, H, Ho, A)
+    assert _block_parity(T, O, H, Ho, A)[1] == 0
     D = dense_of(hm, H, O.n)
     assert np.linalg.norm(D - A) <= 1e-8 * np.linalg.norm(A)
 
@@ -193,8 +207,13 @@ def test_curve_tolerance_parity(hm, n, r):
     H = hm.compress(T, bb, tol=inst.tol, r=r, seed=inst.seed)
     A = oracle.kernel_matrix(inst.points, inst.points, inst.kernel)
     Ho = oracle.compress(O, oracle.DenseBlackBox(A), r, tol=inst.tol, seed=inst.seed)
-    _block_parity(T, O, H, Ho, A, rel=10 * inst.tol)
+    worst, mism, nblk = _block_parity(T, O, H, Ho, A, rel=1e-10, mismatch_rel=10 * inst.tol)
     D = dense_of(hm, H, O.n)
+    whole = np.linalg.norm(D - Ho.dense()) / np.linalg.norm(A)
+    print("curve N=%d: worst block diff %.1e, rank mismatches %d of %d, whole %.1e"
+          % (n, worst, mism, nblk, whole))
+    assert mism <= 0.01 * nblk
+    assert whole <= 1e-8
     assert np.linalg.norm(D - A) <= inst.tol * np.linalg.norm(A)
     assert H.stats()["saturated"] == 0
 
@@ -207,8 +226,13 @@ def test_sphere_tolerance_parity(hm):
     H = hm.compress(T, bb, tol=inst.tol, r=inst.r, seed=inst.seed)
     A = oracle.kernel_matrix(inst.points, inst.points, inst.kernel)
     Ho = oracle.compress(O, oracle.DenseBlackBox(A), inst.r, tol=inst.tol, seed=inst.seed)
-    _block_parity(T, O, H, Ho, A, rel=10 * inst.tol)
+    worst, mism, nblk = _block_parity(T, O, H, Ho, A, rel=1e-10, mismatch_rel=10 * inst.tol)
     D = dense_of(hm, H, O.n)
+    whole = np.linalg.norm(D - Ho.dense()) / np.linalg.norm(A)
+    print("sphere N=3000: worst block diff %.1e, rank mismatches %d of %d, whole %.1e"
+          % (worst, mism, nblk, whole))
+    assert mism <= 0.01 * nblk
+    assert whole <= 1e-8
     assert np.linalg.norm(D - A) <= 5 * inst.tol * np.linalg.norm(A)
 
 
@@ -235,18 +259,26 @@ def test_matvec_against_exported_factors(hm):
         assert np.linalg.norm(to_host(Y32) - want) <= 1e-5 * np.linalg.norm(want)
 
 
-def test_mixed_precision_against_fp64(hm):
-    inst = workloads.config(1, n=4096)
+@pytest.mark.parametrize("cfg,n,tol,r", [(1, 4096, 1e-6, 24), (1, 4096, 1e-8, 24),
+                                         (2, 4000, 1e-6, 32)])
+def test_mixed_precision_against_oracle(hm, cfg, n, tol, r):
+    """Mixed form (FP32 kernel apply and peel, FP64 QR and couplings)
+    against the FP64 oracle's compression of the same inputs, tolerance and
+    r: the operators within 1e-5 of each other (relative Frobenius)."""
+    inst = workloads.config(cfg, n=n)
+    O = oracle.OTree(inst.points, inst.leaf, inst.tree, inst.adm)
     T = hm.Tree(inst.points, inst.leaf, inst.tree, inst.adm).color()
     bb = T.kernel_blackbox(inst.kernel)
-    H64 = hm.compress(T, bb, tol=1e-8, r=24, seed=inst.seed)
-    H32 = hm.compress(T, bb, tol=1e-6, r=24, seed=inst.seed, prec=hm.HM_PREC_MIXED)
-    D64 = dense_of(hm, H64, T.n)
-    D32 = dense_of(hm, H32, T.n)
     A = oracle.kernel_matrix(inst.points, inst.points, inst.kernel)
-    e = np.linalg.norm(D32 - D64) / np.linalg.norm(D64)
-    print("mixed vs fp64:", e, "mixed vs dense:", np.linalg.norm(D32 - A) / np.linalg.norm(A))
+    Ho = oracle.compress(O, oracle.DenseBlackBox(A), r, tol=tol, seed=inst.seed)
+    H32 = hm.compress(T, bb, tol=tol, r=r, seed=inst.seed, prec=hm.HM_PREC_MIXED)
+    D32, Do = dense_of(hm, H32, T.n), Ho.dense()
+    e = np.linalg.norm(D32 - Do) / np.linalg.norm(Do)
+    print("mixed vs FP64 oracle (%s, tol %g): %.2e; mixed vs dense %.2e, oracle vs dense %.2e"
+          % (inst.name, tol, e, np.linalg.norm(D32 - A) / np.linalg.norm(A),
+             np.linalg.norm(Do - A) / np.linalg.norm(A)))
     assert e <= 1e-5
+    assert H32.stats()["saturated"] == 0
 
 
 def test_full_size_star_curve_sampled_rows(hm):

@@ -1,14 +1,19 @@
 """Uniform H^1 compression on the GPU (hm_compress with HM_FORMAT_UNIFORM_H1)
 against the oracle's compress_uniform.
 
+The row bases follow the paper's rule (plain sum of the stage-2 samples);
+the Gaussian-weighted extension is checked against the oracle's extension.
+
 Bars (FP64 path): stage-1 test matrices within 8 ulps of the oracle's
 Gaussians with the same zero pattern; exact uniform H^1 matrices recovered
 to 1e-11 relative, and every block equal to the oracle's within 1e-10 of the
-block norm; kernel matrices: every block within 10 tol of the block norm of
-the oracle's (plus 1e-12 ||A||), the whole operator within the error the
-oracle reaches there; the shared bases identical (bit for bit) in every pair
-that uses them.  Mixed form: within 1e-5 of the FP64 form.  Forests: every
-instance equal to its own compression with key seed + i within 1e-10.
+block norm; kernel matrices (tolerance mode and fixed rank): every block
+within 1e-10 of the block norm of the oracle's (plus 1e-12 ||A||) where the
+ranks agree, rank mismatches counted (at most 1 %) and held to 10 tol, the
+whole operator's error equal to the oracle's; the shared bases identical
+(bit for bit) in every pair that uses them.  Mixed form: within 1e-5 of the
+FP64 oracle at fixed rank.  Forests: every instance equal to its own
+compression with key seed + i within 1e-10.
 """
 import numpy as np
 import pytest
@@ -16,7 +21,7 @@ import pytest
 import oracle
 import workloads
 from synth import exact_uniform_h1
-from devutil import to_dev, to_host, dense_of
+from devutil import to_dev, to_host, dense_of, pair_parity, block_norms
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -55,26 +60,25 @@ def _check_shared_bases(blocks):
             V[b] = Vb
 
 
-def _parity(O, blocks, Ho, A, rel):
-    floor = 1e-12 * np.linalg.norm(A)
-    perm = O.perm
-    worst = 0.0
-    for l, g in blocks.items():
-        o = Ho.lowrank[l]
-        assert len(g) == len(o)
-        for (a, b, U, B, V), (a2, b2, U2, B2, V2) in zip(g, o):
-            assert (a, b) == (a2, b2)
-            a0, a1 = O.box_range(l, a)
-            b0, b1 = O.box_range(l, b)
-            nb = np.linalg.norm(A[np.ix_(perm[a0:a1], perm[b0:b1])])
-            d = np.linalg.norm(U @ B @ V.T - U2 @ B2 @ V2.T)
-            worst = max(worst, d / max(nb, 1e-300))
-            assert d <= rel * nb + floor, (l, a, b, d, nb)
-            if U.shape[1]:
-                assert np.allclose(U.T @ U, np.eye(U.shape[1]), atol=1e-12)
-            if V.shape[1]:
-                assert np.allclose(V.T @ V, np.eye(V.shape[1]), atol=1e-12)
-    return worst
+def _parity(O, blocks, Ho, A, rel, mismatch_rel=None):
+    """Every block U B V* against the oracle's (pair_parity); orthonormal
+    bases.  Returns (worst difference where the ranks agree, rank
+    mismatches, blocks)."""
+    def pairs():
+        for l, g in blocks.items():
+            o = Ho.lowrank[l]
+            assert len(g) == len(o)
+            for (a, b, U, B, V), (a2, b2, U2, B2, V2) in zip(g, o):
+                assert (a, b) == (a2, b2)
+                if U.shape[1]:
+                    assert np.allclose(U.T @ U, np.eye(U.shape[1]), atol=1e-12)
+                if V.shape[1]:
+                    assert np.allclose(V.T @ V, np.eye(V.shape[1]), atol=1e-12)
+                yield (l, a, b, U @ B @ V.T, U2 @ B2 @ V2.T, (U.shape[1], V.shape[1]),
+                       (U2.shape[1], V2.shape[1]))
+    return pair_parity(O, pairs(), block_norms(O, A), rel,
+                       rel if mismatch_rel is None else mismatch_rel,
+                       1e-12 * np.linalg.norm(A))
 
 
 @pytest.mark.parametrize("name", ["strong2d", "curve", "grid"])
@@ -107,7 +111,7 @@ def test_uniform_exact_recovery(hm, name):
     Ho = oracle.compress_uniform(O, oracle.DenseBlackBox(A), 10, k=4, seed=77)
     blocks = _blocks(H, O)
     _check_shared_bases(blocks)
-    _parity(O, blocks, Ho, A, rel=1e-10)
+    assert _parity(O, blocks, Ho, A, rel=1e-10)[1] == 0
     gn = H.export_near()
     for (a, b, Dn), (a2, b2, D2) in zip(gn, Ho.near):
         assert (a, b) == (a2, b2)
@@ -126,47 +130,83 @@ def test_uniform_exact_recovery(hm, name):
     assert Ht.stats()["max_rank"] <= 4
 
 
-@pytest.mark.parametrize("n,tol,r", [(1500, 1e-8, 24), (3000, 1e-6, 24)])
-def test_uniform_kernel_parity(hm, n, tol, r):
+@pytest.mark.parametrize("n,tol,k,r", [(1500, 1e-8, 0, 24), (3000, 1e-6, 0, 24),
+                                        (3000, 0.0, 14, 24), (3000, 0.0, 10, 20)])
+def test_uniform_kernel_parity(hm, n, tol, k, r):
+    """Kernel matrices in tolerance mode and at the paper's fixed ranks:
+    every block within 1e-10 of the oracle's where the ranks agree (rank
+    mismatches counted, held to 10 tol), the whole operator's error equal to
+    the oracle's."""
     inst = workloads.config(1, n=n)
     O = oracle.OTree(inst.points, inst.leaf, inst.tree, inst.adm)
     T = hm.Tree(inst.points, inst.leaf, inst.tree, inst.adm).color()
     A = oracle.kernel_matrix(inst.points, inst.points, inst.kernel)
-    H = hm.compress(T, T.kernel_blackbox(inst.kernel), tol=tol, r=r, seed=inst.seed, uniform=True)
-    Ho = oracle.compress_uniform(O, oracle.DenseBlackBox(A), r, tol=tol, seed=inst.seed)
+    H = hm.compress(T, T.kernel_blackbox(inst.kernel), rank=k, tol=tol, r=r, seed=inst.seed,
+                    uniform=True)
+    Ho = oracle.compress_uniform(O, oracle.DenseBlackBox(A), r, k=k, tol=tol, seed=inst.seed)
     blocks = _blocks(H, O)
     _check_shared_bases(blocks)
-    worst = _parity(O, blocks, Ho, A, rel=10 * tol)
+    worst, mism, nblk = _parity(O, blocks, Ho, A, rel=1e-10, mismatch_rel=10 * max(tol, 1e-10))
     D = dense_of(hm, H, O.n)
     err = np.linalg.norm(D - A) / np.linalg.norm(A)
     err_o = np.linalg.norm(Ho.dense() - A) / np.linalg.norm(A)
+    whole = np.linalg.norm(D - Ho.dense()) / np.linalg.norm(A)
     st = H.stats()
-    Hn = hm.compress(T, T.kernel_blackbox(inst.kernel), tol=tol, r=r, seed=inst.seed)
-    print("uniform: err %.2e (oracle %.2e), worst block diff %.1e, floats %d (oracle %d, "
-          "non-uniform %d)" % (err, err_o, worst, st["nfloats"], oracle.uniform_floats(Ho),
-                               Hn.stats()["nfloats"]))
-    assert err <= max(2 * err_o, tol)
+    Hn = hm.compress(T, T.kernel_blackbox(inst.kernel), rank=k, tol=tol, r=r, seed=inst.seed)
+    print("uniform: err %.2e (oracle %.2e), GPU vs oracle %.1e, worst block diff %.1e, "
+          "rank mismatches %d of %d, floats %d (oracle %d, non-uniform %d)"
+          % (err, err_o, whole, worst, mism, nblk, st["nfloats"], oracle.uniform_floats(Ho),
+             Hn.stats()["nfloats"]))
+    assert mism <= 0.01 * nblk
+    assert whole <= 1e-8 or mism > 0
+    assert abs(err - err_o) <= 0.05 * err_o + 1e-12
     assert abs(st["nfloats"] - oracle.uniform_floats(Ho)) <= 0.01 * oracle.uniform_floats(Ho)
     assert st["nfloats"] < Hn.stats()["nfloats"]
     assert st["saturated"] == 0
 
 
-def test_uniform_mixed_matches_f64(hm):
+def test_uniform_gamma_extension_parity(hm):
+    """The Gaussian-weighted row-basis combination (HM_FLAG_MIX_GAMMA, an
+    extension) against the oracle's combine="gaussian": blocks within 1e-10
+    where the ranks agree, and it is more accurate than the paper's sum in
+    tolerance mode (no parity claim against the paper)."""
+    inst = workloads.config(1, n=1500)
+    O = oracle.OTree(inst.points, inst.leaf, inst.tree, inst.adm)
+    T = hm.Tree(inst.points, inst.leaf, inst.tree, inst.adm).color()
+    A = oracle.kernel_matrix(inst.points, inst.points, inst.kernel)
+    H = hm.compress(T, T.kernel_blackbox(inst.kernel), tol=1e-8, r=24, seed=inst.seed,
+                    uniform=True, combine="gaussian")
+    Ho = oracle.compress_uniform(O, oracle.DenseBlackBox(A), 24, tol=1e-8, seed=inst.seed,
+                                 combine="gaussian")
+    worst, mism, nblk = _parity(O, _blocks(H, O), Ho, A, rel=1e-10, mismatch_rel=1e-7)
+    assert mism <= 0.01 * nblk
+    err = np.linalg.norm(dense_of(hm, H, O.n) - A) / np.linalg.norm(A)
+    Hs = hm.compress(T, T.kernel_blackbox(inst.kernel), tol=1e-8, r=24, seed=inst.seed,
+                     uniform=True)
+    err_s = np.linalg.norm(dense_of(hm, Hs, O.n) - A) / np.linalg.norm(A)
+    print("uniform gamma extension: err %.2e, plain sum %.2e, worst block diff %.1e"
+          % (err, err_s, worst))
+    assert err < err_s
+
+
+def test_uniform_mixed_against_oracle(hm):
+    """Mixed form (FP32 kernel apply and peel, FP64 QR and couplings) at
+    the paper's fixed rank against the FP64 oracle's compression of the same
+    inputs: within 1e-5 of it, and as accurate against the kernel matrix."""
     inst = workloads.config(1, n=4096)
+    O = oracle.OTree(inst.points, inst.leaf, inst.tree, inst.adm)
     T = hm.Tree(inst.points, inst.leaf, inst.tree, inst.adm).color()
     bb = T.kernel_blackbox(inst.kernel)
-    H64 = hm.compress(T, bb, tol=1e-6, r=24, seed=5, uniform=True)
-    H32 = hm.compress(T, bb, tol=1e-6, r=24, seed=5, uniform=True, prec=hm.HM_PREC_MIXED)
-    X = np.random.default_rng(0).standard_normal((T.n, 4))
-    Y64, Y32 = hm.colmajor(T.n, 4), hm.colmajor(T.n, 4)
-    H64.matvec(to_dev(X), Y64)
-    H32.matvec(to_dev(X), Y32)
-    a, b = to_host(Y64), to_host(Y32)
-    d = np.linalg.norm(a - b) / np.linalg.norm(a)
-    print("mixed vs FP64 uniform: %.2e; ranks %d vs %d" % (d, H32.stats()["max_rank"],
-                                                          H64.stats()["max_rank"]))
+    A = oracle.kernel_matrix(inst.points, inst.points, inst.kernel)
+    Ho = oracle.compress_uniform(O, oracle.DenseBlackBox(A), 24, k=14, seed=5)
+    H32 = hm.compress(T, bb, rank=14, r=24, seed=5, uniform=True, prec=hm.HM_PREC_MIXED)
+    D32, Do = dense_of(hm, H32, T.n), Ho.dense()
+    d = np.linalg.norm(D32 - Do) / np.linalg.norm(Do)
+    e32 = np.linalg.norm(D32 - A) / np.linalg.norm(A)
+    eo = np.linalg.norm(Do - A) / np.linalg.norm(A)
+    print("mixed uniform vs FP64 oracle: %.2e; errors %.2e (oracle %.2e)" % (d, e32, eo))
     assert d <= 1e-5
-    assert H32.stats()["saturated"] == 0
+    assert e32 <= eo + 1e-5
 
 
 def test_uniform_forest_matches_instances(hm):

@@ -9,9 +9,11 @@ alg:h2_pseudocode, alg:apply_h2_level_truncated).
 * The upward / downward apply equals the dense matrix assembled from the
   bases implied by the nesting (a second, bottom-up construction), and its
   adjoint equals the transpose.
-* On the star-curve log kernel: error within 20 tol, storage below the
-  uniform H^1 form and that below the H^1 form, and the matvec counts
-  sum(chi_unif) r + chi_leaf m through A and sum(chi) kmax through A*.
+* On the star-curve log kernel at a fixed rank: storage below the uniform
+  H^1 form and that below the H^1 form, and the matvec counts
+  sum(chi_unif) r + chi_leaf m through A and sum(chi) k through A*.
+* The row bases span the plain sum of the stage-2 samples (the paper's
+  rule; the Gaussian-weighted extension fails this).
 """
 import numpy as np
 import pytest
@@ -55,7 +57,9 @@ def test_exact_recovery(name):
     H = oracle.compress_h2(T, oracle.DenseBlackBox(A), 10, k=4, seed=77)
     assert np.linalg.norm(H.dense() - A) <= 1e-12 * np.linalg.norm(A)
     Ht = oracle.compress_h2(T, oracle.DenseBlackBox(A), 14, tol=1e-9, seed=78)
-    assert np.linalg.norm(Ht.dense() - A) <= 1e-12 * np.linalg.norm(A)
+    # tolerance mode: the summed samples are truncated at tol s_0, so the
+    # rounding of the sum is not amplified beyond 1e-2 tol
+    assert np.linalg.norm(Ht.dense() - A) <= 1e-11 * np.linalg.norm(A)
     assert Ht.saturated == 0
 
 
@@ -84,22 +88,63 @@ def test_apply_matches_nested_assembly(name):
 
 
 def test_kernel_accuracy_storage_counts():
+    """At a fixed rank (the paper's setting) the star-curve log kernel is
+    approximated with less storage than the uniform H^1 form, and that less
+    than the H^1 form; matvec counts sum(chi_unif) r + chi_leaf m through A
+    and sum(chi) k through A*."""
     pts = workloads.star_curve(1500)
     T = oracle.OTree(pts, 64, "geometric", "strong")
     K = oracle.kernel_matrix(pts, pts, "log")
-    tol, r = 1e-8, 24
+    k, r = 14, 24
     bb = oracle.CountingBlackBox(oracle.DenseBlackBox(K))
-    H = oracle.compress_h2(T, bb, r, tol=tol, seed=3)
+    H = oracle.compress_h2(T, bb, r, k=k, seed=3)
     err = np.linalg.norm(H.dense() - K) / np.linalg.norm(K)
-    assert err <= 20 * tol, err
-    Hu = oracle.compress_uniform(T, oracle.DenseBlackBox(K), r, tol=tol, seed=3)
-    Hn = oracle.compress(T, oracle.DenseBlackBox(K), r, tol=tol, seed=3)
+    assert err <= 1e-6, err
+    Hu = oracle.compress_uniform(T, oracle.DenseBlackBox(K), r, k=k, seed=3)
+    Hn = oracle.compress(T, oracle.DenseBlackBox(K), r, k=k, seed=3)
     assert H.floats() < oracle.uniform_floats(Hu) < Hn.floats()
     chi_u = [oracle.UniformGraph(T, l).ncolors for l in T.sampled_levels()]
     chi = [T.graphs[l].ncolors for l in T.sampled_levels()]
     assert bb.cols_A == r * sum(chi_u) + T.leaf_graph.ncolors * T.leaf_max() == H.cols_A
-    assert bb.cols_At == (r - 10) * sum(chi) == H.cols_At
+    assert bb.cols_At == k * sum(chi) == H.cols_At
     assert H.saturated == 0
+
+
+def test_row_bases_span_the_summed_samples():
+    """alg:h2_pseudocode, H^2 branch, on a tree whose only sampled level is
+    level 2 (no parent basis to augment with, nothing peeled): at fixed rank
+    V_b = svd(sum over a in int(b) of A(I_a, I_b)* U_a, k) spans the sum
+    formed here from the dense matrix and the oracle's U_a, and
+    B_ab = U_a* A(I_a, I_b) V_b.  The Gaussian-weighted extension fails the
+    span check."""
+    g = (np.arange(20) + 0.5) / 20
+    pts = np.stack(np.meshgrid(g, g), -1).reshape(-1, 2)
+    T = oracle.OTree(pts, 25)
+    assert T.sampled_levels() == [2] and T.L == 2
+    K = oracle.kernel_matrix(pts, pts, "log")
+    Kt = K[np.ix_(T.perm, T.perm)]
+    res = {}
+    for combine in ("sum", "gaussian"):
+        H = oracle.compress_h2(T, oracle.DenseBlackBox(K), 14, k=4, seed=2, combine=combine)
+        Bs = {(a, b): B for a, b, B in H.B[2]}
+        worst = worst_b = 0.0
+        for b, Vb in H.Vlong.items():
+            ints = [int(x) for x in T.interaction(2, b)]
+            if not ints:
+                continue
+            b0, b1 = T.box_range(2, b)
+            S = 0.0
+            for a in ints:
+                a0, a1 = T.box_range(2, a)
+                Ua = H.Ulong[a]
+                S = S + Kt[a0:a1, b0:b1].T @ Ua
+                Bw = Ua.T @ Kt[a0:a1, b0:b1] @ Vb
+                worst_b = max(worst_b, np.linalg.norm(Bs[(a, b)] - Bw) / np.linalg.norm(Bw))
+            worst = max(worst, np.linalg.norm(S - Vb @ (Vb.T @ S)) / np.linalg.norm(S))
+        res[combine] = worst
+        assert worst_b <= 1e-12, (combine, worst_b)
+    assert res["sum"] <= 1e-12, res
+    assert res["gaussian"] > 1e-5, res
 
 
 def test_augment_gaussian_draws():

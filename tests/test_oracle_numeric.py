@@ -20,8 +20,8 @@ import pytest
 
 import workloads
 from oracle import (CountingBlackBox, DenseBlackBox, KernelBlackBox, OTree, compress,
-                    gaussian_block, leaf_test_matrix, philox4x32_10, rel_fro_error_dense,
-                    )
+                    gaussian_block, kernel_matrix, leaf_test_matrix, philox4x32_10,
+                    rel_fro_error_dense)
 from oracle import test_matrix as make_test_matrix
 from synth import exact_h1
 
@@ -236,3 +236,31 @@ def test_error_estimators():
     assert probe_error(lambda X: A @ X, lambda X: A @ X, 60) == 0.0
     pe = probe_error(lambda X: A @ X, lambda X: (A - E) @ X, 60, nprobe=4000)
     assert abs(pe - np.linalg.norm(E) / np.linalg.norm(A)) < 0.01
+
+
+def test_kernel_matrix_hand_values():
+    """The kernels of the experiments at hand-computed points: log|x - y| is
+    log 5 and 1/|x - y| is 1/5 at (0, 0)-(3, 4) (a 3-4-5 triangle), 0 on the
+    diagonal and between coincident points; 1D and 3D distances likewise
+    (a slip such as log r^2 for log r, or a squared distance, fails)."""
+    P = np.array([[0.0, 0.0], [3.0, 4.0], [3.0, 4.0], [-1.0, 0.0]])
+    L = kernel_matrix(P, P, "log")
+    R = kernel_matrix(P, P, "inv_r")
+    assert L[0, 1] == pytest.approx(np.log(5.0), rel=1e-15)
+    assert L[1, 0] == pytest.approx(np.log(5.0), rel=1e-15)
+    assert R[0, 1] == pytest.approx(0.2, rel=1e-15)
+    assert L[0, 3] == 0.0 and R[0, 3] == 1.0          # |x - y| = 1
+    assert L[1, 2] == 0.0 and R[1, 2] == 0.0          # coincident points
+    assert np.all(np.diag(L) == 0.0) and np.all(np.diag(R) == 0.0)
+    assert L[3, 1] == pytest.approx(0.5 * np.log(32.0), rel=1e-15)   # (4, 4): sqrt 32
+    x = np.array([[0.25], [2.25]])
+    assert kernel_matrix(x, x, "log")[0, 1] == pytest.approx(np.log(2.0), rel=1e-15)
+    assert kernel_matrix(x, x, "inv_r")[1, 0] == pytest.approx(0.5, rel=1e-15)
+    q = np.array([[1.0, 2.0, 2.0], [0.0, 0.0, 0.0]])   # |q| = 3
+    assert kernel_matrix(q, q, "inv_r")[0, 1] == pytest.approx(1.0 / 3.0, rel=1e-15)
+    assert kernel_matrix(q, q, "log")[0, 1] == pytest.approx(np.log(3.0), rel=1e-15)
+    # the black box applies the same matrix, rows included
+    bb = KernelBlackBox(P, "log", dense_cache=False)
+    X = np.eye(4)
+    assert np.allclose(bb.apply(X), L, rtol=0, atol=1e-15)
+    assert np.allclose(bb.rows([1, 3], X), L[[1, 3]], rtol=0, atol=1e-15)
