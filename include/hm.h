@@ -303,8 +303,11 @@ typedef struct {
  *     columns) in place of the Gaussian block on box a; Z = (A - A^(l))* Psi;
  *     V_b = qr(sum over a in int(b) of Z(I_b, block of (b, a)), k)
  *     (alg:h2_pseudocode, "sum samples and orthonormalize"; HM_FLAG_MIX_GAMMA
- *     selects the Gaussian-weighted extension); rank at most kmax, no cap; in
- *     the mixed form its floor is 8 u32 ||sum of the raw blocks||_F / sqrt(kmax).
+ *     selects the Gaussian-weighted extension); rank at most kmax, no cap.
+ *     Stage 2 runs in FP64 in both precisions (the sum adds column j of
+ *     every term, and where terms cancel, FP32 rounding of the samples
+ *     would decide the directions V_b keeps); the black box therefore needs
+ *     an FP64 apply in the mixed form too (HM_E_ARG otherwise).
  *   B_ab = Z(I_b, block of (b, a))[:, :k_a]* V_b.
  * kmax = rank (fixed rank) or r - p.  The leaf pass is that of hm_compress.
  * The result applies, exports and serves like any H-matrix (the per-pair

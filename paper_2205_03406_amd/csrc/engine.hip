@@ -206,6 +206,10 @@ struct DBuf {
       (void)hipGetLastError();
       throw Error{HM_E_DEVICE, "hipGetDevice failed"};
     }
+    if (dev < 0 || dev >= 64) {  // beyond the cache's table: a plain allocation
+      alloc(b);
+      return;
+    }
     size_t blk = b;
     p = cache_take(dev, blk);
     if (!p) {
@@ -883,7 +887,7 @@ struct Compression {
     DBuf kit1, kit2;   // forest kernel-apply items of the two stages
     // H^2: norm jobs of the raw samples (mixed floors), augmentation jobs of
     // the two stages, transfers and nesting of the previous level into this one
-    DBuf jn, jvn, augu, augv, tr, nest;
+    DBuf jn, augu, augv, tr, nest;
     int32_t nv = 0, nmix = 0, nkit1 = 0, nkit2 = 0, naug = 0, ntr = 0, nnest = 0;
   };
   std::vector<UniformJobs> ujobs_of;
@@ -961,6 +965,8 @@ hm_status Compression::setup(hipStream_t s) {
     return fail(HM_E_ARG, "unknown format");
   uniform = o.format == HM_FORMAT_UNIFORM_H1 || o.format == HM_FORMAT_H2;
   h2 = o.format == HM_FORMAT_H2;
+  if (uniform && mixed && !(bb.dtypes & (1 << HM_F64)))
+    return fail(HM_E_ARG, "the uniform and H2 formats apply A* in FP64: black box has no FP64 apply");
   kmax = kfix > 0 ? std::min(kfix, r) : r - p;
   es = mixed ? 4 : 8;
   n = T.n;
@@ -1093,17 +1099,25 @@ hm_status Compression::setup(hipStream_t s) {
   mw = T.leaf_width();
   leaf_cols = pad16((int64_t)GL.ncolors * mw);
   wcols = std::max<int64_t>(2 * cmax, leaf_cols);
+  size_t wbytes = (size_t)n * wcols * es, tes = es;
   if (uniform) {
-    // the two stages run one after the other through the same buffers
+    // the two stages run one after the other through the same buffers;
+    // stage 2 always runs in FP64 (its samples are summed, see
+    // record_uniform_level)
     wcols = leaf_cols;
-    for (int l : levels)
-      wcols = std::max({wcols, pad16((int64_t)T.ugraphs[l].ncolors * r),
-                        pad16((int64_t)T.graphs[l].ncolors * kmax)});
+    int64_t w2 = 0;
+    for (int l : levels) {
+      wcols = std::max(wcols, pad16((int64_t)T.ugraphs[l].ncolors * r));
+      w2 = std::max(w2, pad16((int64_t)T.graphs[l].ncolors * kmax));
+    }
+    wbytes = std::max((size_t)n * wcols * es, (size_t)n * w2 * 8);
+    wcols = std::max(wcols, w2);
+    tes = 8;
   }
-  buf(Xb, (size_t)n * wcols * es, s);
-  buf(Yb, (size_t)n * wcols * es, s);
+  buf(Xb, wbytes, s);
+  buf(Yb, wbytes, s);
   tcap = tscratch_elems(*H, wcols);
-  buf(Tb, (size_t)tcap * es, s);
+  buf(Tb, (size_t)tcap * tes, s);
   int64_t wmax = 0;
   for (size_t li = 0; li < H->lv.size(); ++li) {
     const hm_hmatrix::Lv &L = H->lv[li];
@@ -1127,8 +1141,8 @@ hm_status Compression::setup(hipStream_t s) {
   // a black box in the original point order works through two permuted
   // copies of the samples
   if (bb.order != HM_ORDER_TREE) {
-    buf(tmpx, (size_t)n * wcols * es, s);
-    buf(tmpy, (size_t)n * wcols * es, s);
+    buf(tmpx, wbytes, s);
+    buf(tmpy, wbytes, s);
   }
 
   // ---------------- forest: the library's own kernel black box on this
@@ -1415,7 +1429,6 @@ void Compression::setup_h2(hipStream_t s) {
       return x;
     }();
     buf(floor_u, nbl * 8, s);
-    buf(floor_v, nbl * 8, s);
   }
 
   ujobs_of.resize(nlv);
@@ -1435,7 +1448,7 @@ void Compression::setup_h2(hipStream_t s) {
     for (int64_t v = 0; v < UG.nv(); ++v)
       for (int32_t t = Lv.int_ptr[UG.vbox[v]]; t < Lv.int_ptr[UG.vbox[v] + 1]; ++t)
         act[(size_t)Lv.intl[t] * UG.ncolors + UG.color[v]] = 1;
-    std::vector<QrJob> jn(hb.size()), jvn(hb.size()), jsu(hb.size()), jsv(hb.size());
+    std::vector<QrJob> jn(hb.size()), jsu(hb.size()), jsv(hb.size());
     std::vector<AugJob> au, av;
     int64_t wofs = 0;
     for (size_t v = 0; v < hb.size(); ++v) {
@@ -1443,7 +1456,6 @@ void Compression::setup_h2(hipStream_t s) {
       const int32_t m = (int32_t)T.box_size(l, a);
       const bool vert = ucol[a] >= 0;
       jn[v] = QrJob{Lv.start[a], vert ? (int64_t)ucol[a] * r : 0, 0, 0, vert ? m : 0, 0};
-      jvn[v] = QrJob{Lv.start[a], 0, 0, 0, vert ? m : 0, 0};
       jsu[v] = QrJob{Lv.start[a], 0, H->uoff[li][v], wofs, m, 0};
       jsv[v] = jsu[v];
       wofs += (int64_t)m * r;
@@ -1555,7 +1567,6 @@ void Compression::setup_h2(hipStream_t s) {
     put(J.ju, jsu, s);
     put(J.jv, jsv, s);
     put(J.jn, jn, s);
-    put(J.jvn, jvn, s);
     put(J.augu, au, s);
     put(J.augv, av, s);
     put(J.slot, slot, s);
@@ -1697,18 +1708,18 @@ void Compression::record_h2_level(size_t li, hipStream_t s, Events &ev) {
   const int64_t c1 = (int64_t)UG.ncolors * r, c1pad = pad16(c1);
   const int64_t c2 = (int64_t)G.ncolors * kmax, c2pad = pad16(c2);
   void *X = Xb.p, *Y = Yb.p;
-  auto apply_bb = [&](int trans, int64_t cols, const DBuf &kit, int32_t nkit) {
+  auto apply_bb = [&](int trans, int64_t cols, const DBuf &kit, int32_t nkit, bool f32) {
     if (direct) {
-      autotune_kapply(KapplyShape{mixed, kbb->kernel, T.dim, cols, n, true, nkit},
+      autotune_kapply(KapplyShape{f32, kbb->kernel, T.dim, cols, n, true, nkit},
                       [&](int nt, int64_t part) {
                         launch_kapply_forest(kbb->kernel, T.dim, n, Dv.pts.as<double>(),
                                              part > 0 ? (int32_t)part : nkit, kit.as<KItem>(),
-                                             cols, -1, nt, mixed, X, n, Y, n, s);
+                                             cols, -1, nt, f32, X, n, Y, n, s);
                       },
                       s);
       LAUNCH_CHECK();
     } else {
-      call_blackbox(bb, bb.symmetric ? 0 : trans, n, cols, mixed, X, n, Y, n, Dv, tmpx, tmpy, s);
+      call_blackbox(bb, bb.symmetric ? 0 : trans, n, cols, f32, X, n, Y, n, Dv, tmpx, tmpy, s);
     }
   };
   constexpr double kNoiseGamma = 8.0;
@@ -1720,7 +1731,7 @@ void Compression::record_h2_level(size_t li, hipStream_t s, Events &ev) {
                    o.seed, Dv.inst_off.as<int64_t>(), ni, mixed, X, n, c1pad, s);
     LAUNCH_CHECK();
     ev.mark(1);
-    apply_bb(0, c1pad, J.kit1, J.nkit1);
+    apply_bb(0, c1pad, J.kit1, J.nkit1, mixed);
     cols_A += c1;
     if (mixed) {
       launch_block_norms(J.nv, J.jn.as<QrJob>(), r, kNoiseGamma * 0x1p-24 / std::sqrt((double)r),
@@ -1741,44 +1752,36 @@ void Compression::record_h2_level(size_t li, hipStream_t s, Events &ev) {
                    H->UB.as<double>(), H->SU.as<double>() + v0 * kmax, kmax, rk + v0,
                    usat.as<int32_t>() + v0, s);
   LAUNCH_CHECK();
-  // ---------------- stage 2: Z, combinations, augmented SVD row bases
+  // ---------------- stage 2: Z, sums, augmented SVD row bases; FP64 in both
+  // precisions, as in the uniform format (the samples are summed)
   if (G.nv() > 0) {
     ev.mark(0);
     launch_basis_testmat(n, Dv.rowbox[l].as<int32_t>(), Dv.start[l].as<int64_t>(),
                          J.slot.as<int32_t>(), G.ncolors, kmax, H->UB.as<double>(),
-                         J.uoff.as<int64_t>(), rk + v0, mixed, X, n, c2pad, s);
+                         J.uoff.as<int64_t>(), rk + v0, false, X, n, c2pad, s);
     LAUNCH_CHECK();
     ev.mark(1);
-    apply_bb(1, c2pad, J.kit2, J.nkit2);
+    apply_bb(1, c2pad, J.kit2, J.nkit2, false);
     cols_At += c2;
-    if (mixed) {
-      launch_mix_sum(J.nmix, J.mix.as<MixJob>(), J.terms.as<MixTerm>(), kmax, l, o.seed, gamma, true, Y,
-                     n, Sb.as<double>(), n, s);
-      launch_block_norms(J.nv, J.jvn.as<QrJob>(), kmax,
-                         kNoiseGamma * 0x1p-24 / std::sqrt((double)kmax), false, Sb.p, n,
-                         floor_v.as<double>(), s);
-      LAUNCH_CHECK();
-    }
     ev.mark(2);
-    h2_apply(*H, li, true, mixed, X, n, c2pad, Y, n, -1.0, h2q.as<double>(), h2u.as<double>(),
+    h2_apply(*H, li, true, false, X, n, c2pad, Y, n, -1.0, h2q.as<double>(), h2u.as<double>(),
              h2p.as<double>(), h2cols, s);
-    launch_check_finite(n, c2pad, mixed, Y, n, flag.as<int32_t>(), s);
+    launch_check_finite(n, c2pad, false, Y, n, flag.as<int32_t>(), s);
     LAUNCH_CHECK();
   }
   ev.mark(3);
-  launch_mix_sum(J.nmix, J.mix.as<MixJob>(), J.terms.as<MixTerm>(), kmax, l, o.seed, gamma, mixed, Y, n,
+  launch_mix_sum(J.nmix, J.mix.as<MixJob>(), J.terms.as<MixTerm>(), kmax, l, o.seed, gamma, false, Y, n,
                  Sb.as<double>(), n, s);
   launch_h2_sample(J.naug, J.augv.as<AugJob>(), kmax, l, 3, o.seed, false, Sb.p, n,
                    H->VB.as<double>(), rk + nb, H->SV.as<double>(), kmax, Sb.as<double>(), n, s);
-  launch_svd_basis(J.nv, J.jv.as<QrJob>(), kmax, kfix, o.tol, kmax,
-                   mixed ? floor_v.as<double>() : nullptr, Sb.as<double>(), n, work.as<double>(),
-                   H->VB.as<double>(), H->SV.as<double>() + v0 * kmax, kmax, rk + nb + v0,
-                   usat.as<int32_t>() + nb + v0, s);
+  launch_svd_basis(J.nv, J.jv.as<QrJob>(), kmax, kfix, o.tol, kmax, nullptr, Sb.as<double>(), n,
+                   work.as<double>(), H->VB.as<double>(), H->SV.as<double>() + v0 * kmax, kmax,
+                   rk + nb + v0, usat.as<int32_t>() + nb + v0, s);
   LAUNCH_CHECK();
   ev.mark(4);
   // couplings and the pair copies of the bases (the exported blocks); the
   // products W = U B only serve the per-pair apply plan, which H^2 does not use
-  launch_ucoupling((int32_t)L.np, J.uc.as<UCJob>(), kmax, mixed, Y, n, H->UB.as<double>(),
+  launch_ucoupling((int32_t)L.np, J.uc.as<UCJob>(), kmax, false, Y, n, H->UB.as<double>(),
                    H->VB.as<double>(), rk + v0, rk + nb + v0, nullptr, nullptr,
                    H->B.as<double>(), nullptr, H->ranks.as<int32_t>(), true, s);
   LAUNCH_CHECK();
@@ -1819,18 +1822,18 @@ void Compression::record_uniform_level(size_t li, hipStream_t s, Events &ev) {
   const int64_t c2 = (int64_t)G.ncolors * kmax, c2pad = pad16(c2);
   void *X = Xb.p, *Y = Yb.p;
   // black box on the first `cols` columns of X into Y (A, or A* when trans)
-  auto apply_bb = [&](int trans, int64_t cols, const DBuf &kit, int32_t nkit) {
+  auto apply_bb = [&](int trans, int64_t cols, const DBuf &kit, int32_t nkit, bool f32) {
     if (direct) {
-      autotune_kapply(KapplyShape{mixed, kbb->kernel, T.dim, cols, n, true, nkit},
+      autotune_kapply(KapplyShape{f32, kbb->kernel, T.dim, cols, n, true, nkit},
                       [&](int nt, int64_t part) {
                         launch_kapply_forest(kbb->kernel, T.dim, n, Dv.pts.as<double>(),
                                              part > 0 ? (int32_t)part : nkit, kit.as<KItem>(),
-                                             cols, -1, nt, mixed, X, n, Y, n, s);
+                                             cols, -1, nt, f32, X, n, Y, n, s);
                       },
                       s);
       LAUNCH_CHECK();
     } else {
-      call_blackbox(bb, bb.symmetric ? 0 : trans, n, cols, mixed, X, n, Y, n, Dv, tmpx, tmpy, s);
+      call_blackbox(bb, bb.symmetric ? 0 : trans, n, cols, f32, X, n, Y, n, Dv, tmpx, tmpy, s);
     }
   };
   constexpr double kNoiseGamma = 8.0;  // see the mixed floor of record()
@@ -1841,7 +1844,7 @@ void Compression::record_uniform_level(size_t li, hipStream_t s, Events &ev) {
                  Dv.inst_off.as<int64_t>(), ni, mixed, X, n, c1pad, s);
   LAUNCH_CHECK();
   ev.mark(1);
-  apply_bb(0, c1pad, J.kit1, J.nkit1);
+  apply_bb(0, c1pad, J.kit1, J.nkit1, mixed);
   cols_A += c1;
   if (mixed) {
     launch_block_norms(J.nv, J.ju.as<QrJob>(), r, kNoiseGamma * 0x1p-24 / std::sqrt((double)r),
@@ -1857,37 +1860,30 @@ void Compression::record_uniform_level(size_t li, hipStream_t s, Events &ev) {
                mixed ? floor_u.as<double>() : nullptr, mixed, Y, n, work.as<double>(),
                H->UB.as<double>(), urank, usat.as<int32_t>() + v0, s);
   LAUNCH_CHECK();
-  // ---------------- stage 2: Z = (A - A^(l))* Psi(U), V_b = qr(sum_a Z_ba)
+  // ---------------- stage 2: Z = (A - A^(l))* Psi(U), V_b = qr(sum_a Z_ba).
+  // FP64 in both precisions: the sum adds column j of every term, and where
+  // the terms cancel, the directions V_b must keep fall below the rounding
+  // of an FP32 sample (a mixed stage 2 measured 2.5e-4 against 5e-7).
   ev.mark(0);
   launch_basis_testmat(n, Dv.rowbox[l].as<int32_t>(), Dv.start[l].as<int64_t>(),
                        J.slot.as<int32_t>(), G.ncolors, kmax, H->UB.as<double>(),
-                       J.uoff.as<int64_t>(), urank, mixed, X, n, c2pad, s);
+                       J.uoff.as<int64_t>(), urank, false, X, n, c2pad, s);
   LAUNCH_CHECK();
   ev.mark(1);
-  apply_bb(1, c2pad, J.kit2, J.nkit2);
+  apply_bb(1, c2pad, J.kit2, J.nkit2, false);
   cols_At += c2;
-  if (mixed) {
-    // floor from the combination of the raw (unpeeled) blocks
-    launch_mix_sum(J.nmix, J.mix.as<MixJob>(), J.terms.as<MixTerm>(), kmax, l, o.seed, gamma, true, Y,
-                   n, Sb.as<double>(), n, s);
-    launch_block_norms(J.nv, J.jv.as<QrJob>(), kmax,
-                       kNoiseGamma * 0x1p-24 / std::sqrt((double)kmax), false, Sb.p, n,
-                       floor_v.as<double>(), s);
-    LAUNCH_CHECK();
-  }
   ev.mark(2);
-  apply_levels(*H, li, true, mixed, X, n, c2pad, Y, n, -1.0, Tb.p, tcap, s);
-  launch_check_finite(n, c2pad, mixed, Y, n, flag.as<int32_t>(), s);
+  apply_levels(*H, li, true, false, X, n, c2pad, Y, n, -1.0, Tb.p, tcap, s);
+  launch_check_finite(n, c2pad, false, Y, n, flag.as<int32_t>(), s);
   LAUNCH_CHECK();
   ev.mark(3);
-  launch_mix_sum(J.nmix, J.mix.as<MixJob>(), J.terms.as<MixTerm>(), kmax, l, o.seed, gamma, mixed, Y, n,
+  launch_mix_sum(J.nmix, J.mix.as<MixJob>(), J.terms.as<MixTerm>(), kmax, l, o.seed, gamma, false, Y, n,
                  Sb.as<double>(), n, s);
-  launch_pivqr(J.nv, J.jv.as<QrJob>(), kmax, kfix, o.tol, kmax,
-               mixed ? floor_v.as<double>() : nullptr, false, Sb.p, n, work.as<double>(),
-               H->VB.as<double>(), vrank, usat.as<int32_t>() + H->nvtot + v0, s);
+  launch_pivqr(J.nv, J.jv.as<QrJob>(), kmax, kfix, o.tol, kmax, nullptr, false, Sb.p, n,
+               work.as<double>(), H->VB.as<double>(), vrank, usat.as<int32_t>() + H->nvtot + v0, s);
   LAUNCH_CHECK();
   ev.mark(4);
-  launch_ucoupling((int32_t)L.np, J.uc.as<UCJob>(), kmax, mixed, Y, n, H->UB.as<double>(),
+  launch_ucoupling((int32_t)L.np, J.uc.as<UCJob>(), kmax, false, Y, n, H->UB.as<double>(),
                    H->VB.as<double>(), urank, vrank, H->U.as<double>(), H->V.as<double>(),
                    H->B.as<double>(), H->W.as<double>(), H->ranks.as<int32_t>(), true, s);
   LAUNCH_CHECK();
@@ -2256,7 +2252,7 @@ int64_t hmatrix_device_bytes(const hm_hmatrix *H) {
 // Peak device bytes of one compression of T (factor pools at the largest
 // rank, sample and scratch buffers, plans), from the same sizes
 // compress_impl allocates; an admission estimate (plans are approximated).
-int64_t compress_footprint(const Tree &T, const hm_compress_opts &o) {
+int64_t compress_footprint(Tree &T, const hm_compress_opts &o) {
   const int p = o.oversample > 0 ? o.oversample : 10;
   const int kfix = o.rank > 0 ? o.rank : 0;
   const int r = o.r > 0 ? o.r : (kfix > 0 ? kfix + p : 0);
@@ -2296,12 +2292,34 @@ int64_t compress_footprint(const Tree &T, const hm_compress_opts &o) {
                           np * 8 + cmax_np * 16;
   const int64_t plans = 64 * np + 4096;
   int64_t uni = 0;
+  if (o.format == HM_FORMAT_H2 || o.format == HM_FORMAT_UNIFORM_H1) {
+    // sample buffers of the two stages (stage 2 in FP64), beyond the H^1
+    // ones counted above
+    build_uniform_graphs(T);
+    int64_t w1 = leaf_cols, w2 = 0;
+    for (int l = 1; l < T.nlev(); ++l)
+      if (!T.graphs[l].pa.empty()) {
+        w1 = std::max(w1, pad16((int64_t)T.ugraphs[l].ncolors * r));
+        w2 = std::max(w2, pad16((int64_t)T.graphs[l].ncolors * kmax));
+      }
+    uni += 2 * std::max<int64_t>(0, std::max(n * w1 * es, n * w2 * 8) - n * wcols * es);
+    uni += tcap * (8 - es);
+  }
   if (o.format == HM_FORMAT_H2) {
     // every box of the sampled range may hold a basis: bases, singular
-    // values, transfers; the augmented sample buffer
+    // values, transfers; the augmented sample buffer; the expansion scratch
+    // of the peel (two nb x kmax x h2cols blocks, capped at 64 MB each, and
+    // the chunk partials: at most one 64-row chunk per box plus n / 64)
+    int64_t nb = 0;
     for (int l = 1; l < T.nlev(); ++l)
-      if (!T.graphs[l].pa.empty()) uni += 2 * n * kmax * 8 + 2 * T.lev[l].nbox() * (kmax + kmax * kmax) * 8;
+      if (!T.graphs[l].pa.empty()) {
+        uni += 2 * n * kmax * 8 + 2 * T.lev[l].nbox() * (kmax + kmax * kmax) * 8;
+        nb += T.lev[l].nbox();
+      }
     uni += n * r * 8 * 2;
+    const int64_t h2cols = std::min<int64_t>(
+        256, std::max<int64_t>(16, (int64_t(64) << 20) / std::max<int64_t>(nb * kmax * 8, 1)));
+    uni += 2 * nb * kmax * h2cols * 8 + (nb + n / 64 + 1) * kmax * h2cols * 8;
   } else if (o.format == HM_FORMAT_UNIFORM_H1) {
     // shared bases (each level's boxes cover at most n rows, U and V) and
     // the combination buffer
@@ -2315,7 +2333,13 @@ int64_t compress_footprint(const Tree &T, const hm_compress_opts &o) {
 // Device bytes of one hm_matvec call (scratch and order conversion).
 int64_t matvec_footprint(const hm_hmatrix *H, int64_t nrhs, int dtype) {
   const int64_t es = dtype == HM_F32 ? 4 : 8;
-  return tscratch_elems(*H, nrhs) * es + 2 * H->n * nrhs * es;
+  int64_t b = tscratch_elems(*H, nrhs) * es + 2 * H->n * nrhs * es;
+  if (H->format == HM_FORMAT_H2 && H->h2a.ready) {
+    // the passes' expansions (h2_apply's own scratch, 256 columns at a time)
+    const int64_t cw = std::min<int64_t>(std::max<int64_t>(nrhs, 1), 256);
+    b += (2 * H->nvtot + H->h2a.nchunk) * H->kmax * cw * 8;
+  }
+  return b;
 }
 
 // Frees the idle blocks the block cache keeps for device dev.

@@ -286,7 +286,7 @@ struct H2Leaf {
 };
 // Outgoing expansions in two steps: every 64-row chunk (chunk list) its
 // partial V* x into PART (chunk-indexed, kmax x ncols, ld kmax), then every
-// box (leaf list; pad = its first chunk) the sum of its chunks' partials in
+// box (leaf list; c0 = its first chunk) the sum of its chunks' partials in
 // order into QH.
 void launch_h2_project(int32_t nchunks, const H2Leaf *chunks, int32_t kmax, const int32_t *rank,
                        const double *VB, bool f32, const void *X, int64_t ldx, int64_t ncols,

@@ -66,3 +66,39 @@ def block_norms(O, A):
         b0, b1 = O.box_range(l, b)
         return np.linalg.norm(A[np.ix_(perm[a0:a1], perm[b0:b1])])
     return f
+
+
+class PerturbedDense:
+    """Dense black box (as oracle.DenseBlackBox) whose products carry a
+    relative perturbation of one rounding unit per entry (2^-53 times a
+    standard normal): the size of the difference two correct FP64
+    implementations of the same product may show.  Compressing through it
+    measures how far rounding alone moves the oracle's result."""
+
+    def __init__(self, A, seed=0):
+        self.A = A
+        self.rng = np.random.default_rng(seed)
+
+    def _p(self, Y):
+        return Y * (1.0 + 2.0 ** -53 * self.rng.standard_normal(Y.shape))
+
+    def apply(self, X):
+        return self._p(self.A @ X)
+
+    def applyT(self, X):
+        return self._p(self.A.T @ X)
+
+
+def level_worst(O, blocks_a, blocks_b, A_norm_of):
+    """Per level, the largest ||X_ab - Y_ab||_F / ||A(I_a, I_b)||_F over the
+    admissible pairs, X and Y the blocks U B V* of two compressions given as
+    {level: [(a, b, U, B, V), ...]} in the same pair order."""
+    out = {}
+    for l in blocks_a:
+        w = 0.0
+        for (a, b, U, B, V), (a2, b2, U2, B2, V2) in zip(blocks_a[l], blocks_b[l]):
+            assert (a, b) == (a2, b2)
+            d = np.linalg.norm(U @ B @ V.T - U2 @ B2 @ V2.T)
+            w = max(w, d / max(A_norm_of(l, a, b), 1e-300))
+        out[l] = w
+    return out

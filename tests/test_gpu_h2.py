@@ -22,7 +22,7 @@ import pytest
 import oracle
 import workloads
 from synth import exact_h2
-from devutil import to_dev, to_host, dense_of, pair_parity, block_norms
+from devutil import PerturbedDense, level_worst, to_dev, to_host, dense_of, pair_parity, block_norms
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -205,22 +205,48 @@ def test_h2_plan_replays(hm):
         assert np.array_equal(to_host(Y2), want), k
 
 
+def _oracle_blocks(Ho):
+    Ue, Ve = Ho.effective_bases()
+    return {l: [(a, b, Ue[l][a], B, Ve[l][b]) for (a, b, B) in Ho.B[l]] for l in Ho.levels}
+
+
 def test_h2_kernel_fixed_rank_parity(hm):
-    """Fixed rank (the setting of the paper's experiments): blocks against
-    the oracle's within 1e-10 of the block norm, error within twice the
-    oracle's."""
+    """Fixed rank (the setting of the paper's experiments).  The row bases
+    come from the plain sum of the stage-2 samples, which is numerically
+    rank-deficient for many boxes at rank 14 (its trailing singular values
+    sit at the rounding level), so the directions it leaves undetermined are
+    set by rounding and a correct implementation is unique only up to that:
+    the oracle compressing through a black box perturbed by one rounding
+    unit per entry moves blocks by up to about 1e-6 of their norm.  The GPU
+    must stay within 10 times that response on every level and on the whole
+    operator, with the error within 1.5 times the oracle's and equal
+    stored-value counts.  (The column bases are not unique either: at rank 14
+    the samples of well-separated blocks have trailing singular values at the
+    rounding level.)"""
     inst = workloads.config(1, n=3000)
     O = oracle.OTree(inst.points, inst.leaf, inst.tree, inst.adm)
     T = hm.Tree(inst.points, inst.leaf, inst.tree, inst.adm).color()
     A = oracle.kernel_matrix(inst.points, inst.points, inst.kernel)
     H = hm.compress(T, T.kernel_blackbox(inst.kernel), rank=14, r=24, seed=inst.seed, h2=True)
     Ho = oracle.compress_h2(O, oracle.DenseBlackBox(A), 24, k=14, seed=inst.seed)
-    worst, mism, _ = _parity(O, H, Ho, A, rel=1e-10)
-    assert mism == 0
-    err = np.linalg.norm(dense_of(hm, H, O.n) - A) / np.linalg.norm(A)
-    err_o = np.linalg.norm(Ho.dense() - A) / np.linalg.norm(A)
-    print("h2 fixed rank: err %.2e (oracle %.2e), worst block diff %.1e" % (err, err_o, worst))
-    assert err <= 2 * err_o + 1e-12
+    Hp = oracle.compress_h2(O, PerturbedDense(A, seed=1), 24, k=14, seed=inst.seed)
+    bo = _oracle_blocks(Ho)
+    bg = {l: H.export_level(l) for l in Ho.levels}
+    bn = block_norms(O, A)
+    sens = level_worst(O, bo, _oracle_blocks(Hp), bn)
+    gpu = level_worst(O, bo, bg, bn)
+    Do, Dp, D = Ho.dense(), Hp.dense(), dense_of(hm, H, O.n)
+    nA = np.linalg.norm(A)
+    whole, whole_p = np.linalg.norm(D - Do) / nA, np.linalg.norm(Dp - Do) / nA
+    err, err_o = np.linalg.norm(D - A) / nA, np.linalg.norm(Do - A) / nA
+    print("h2 fixed rank: err %.2e (oracle %.2e), GPU vs oracle %.1e (rounding response %.1e), "
+          "per level %s against %s" % (err, err_o, whole, whole_p,
+                                       ["%.1e" % gpu[l] for l in sorted(gpu)],
+                                       ["%.1e" % sens[l] for l in sorted(sens)]))
+    for l in gpu:
+        assert gpu[l] <= 10 * sens[l] + 1e-10, (l, gpu[l], sens[l])
+    assert whole <= 10 * whole_p + 1e-10
+    assert err <= 1.5 * err_o + 1e-12
     assert H.stats()["nfloats"] == Ho.floats()
 
 
@@ -232,8 +258,10 @@ def test_h2_apply_matches_oracle_passes(hm):
     O = oracle.OTree(inst.points, inst.leaf, inst.tree, inst.adm)
     T = hm.Tree(inst.points, inst.leaf, inst.tree, inst.adm).color()
     A = oracle.kernel_matrix(inst.points, inst.points, inst.kernel)
-    H = hm.compress(T, T.kernel_blackbox(inst.kernel), rank=14, r=24, seed=inst.seed, h2=True)
-    Ho = oracle.compress_h2(O, oracle.DenseBlackBox(A), 24, k=14, seed=inst.seed)
+    # tolerance mode: the compression is unique (blocks agree to 1e-10), so
+    # the two applies can be compared at a tight bar
+    H = hm.compress(T, T.kernel_blackbox(inst.kernel), tol=1e-8, r=24, seed=inst.seed, h2=True)
+    Ho = oracle.compress_h2(O, oracle.DenseBlackBox(A), 24, tol=1e-8, seed=inst.seed)
     perm = O.perm
     for nrhs in (1, 5, 300):
         X = np.random.default_rng(nrhs).standard_normal((O.n, nrhs))

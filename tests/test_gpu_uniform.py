@@ -7,13 +7,15 @@ the Gaussian-weighted extension is checked against the oracle's extension.
 Bars (FP64 path): stage-1 test matrices within 8 ulps of the oracle's
 Gaussians with the same zero pattern; exact uniform H^1 matrices recovered
 to 1e-11 relative, and every block equal to the oracle's within 1e-10 of the
-block norm; kernel matrices (tolerance mode and fixed rank): every block
-within 1e-10 of the block norm of the oracle's (plus 1e-12 ||A||) where the
-ranks agree, rank mismatches counted (at most 1 %) and held to 10 tol, the
-whole operator's error equal to the oracle's; the shared bases identical
-(bit for bit) in every pair that uses them.  Mixed form: within 1e-5 of the
-FP64 oracle at fixed rank.  Forests: every instance equal to its own
-compression with key seed + i within 1e-10.
+block norm; kernel matrices in tolerance mode: every block within 1e-10 of
+the block norm of the oracle's (plus 1e-12 ||A||) where the ranks agree, rank
+mismatches counted (at most 1 %) and held to 10 tol, the whole operator's
+error equal to the oracle's; at fixed rank (where the plain sum leaves
+directions to rounding) within 10 times the oracle's own response to a
+rounding-level perturbation of its samples; the shared bases identical (bit
+for bit) in every pair that uses them.  Mixed form (stage 2 in FP64):
+within 1e-5 of the FP64 oracle at fixed rank.  Forests: every instance equal
+to its own compression with key seed + i within 1e-10.
 """
 import numpy as np
 import pytest
@@ -21,7 +23,7 @@ import pytest
 import oracle
 import workloads
 from synth import exact_uniform_h1
-from devutil import to_dev, to_host, dense_of, pair_parity, block_norms
+from devutil import PerturbedDense, level_worst, to_dev, to_host, dense_of, pair_parity, block_norms
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -36,7 +38,11 @@ def hm():
 
 
 TREES = {
-    "strong2d": lambda: (workloads.random_points(700, 2, 11), 16, "geometric", "strong"),
+    # a 2D tree whose boxes of a sampled level all hold at least k = 4
+    # points: the paper's plain sum of the stage-2 samples spans at most the
+    # largest k_a directions, so boxes of fewer than k points among a box's
+    # partners can leave its row basis short (pinned on the CPU, test_oracle_uniform)
+    "strong2d": lambda: (workloads.random_points(700, 2, 4), 16, "geometric", "strong"),
     "strong3d": lambda: (workloads.random_points(900, 3, 12), 24, "geometric", "strong"),
     "curve": lambda: (workloads.star_curve(900), 20, "geometric", "strong"),
     "hodlr": lambda: (workloads.uniform_line(512, 3), 32, "index_binary", "weak"),
@@ -130,29 +136,28 @@ def test_uniform_exact_recovery(hm, name):
     assert Ht.stats()["max_rank"] <= 4
 
 
-@pytest.mark.parametrize("n,tol,k,r", [(1500, 1e-8, 0, 24), (3000, 1e-6, 0, 24),
-                                        (3000, 0.0, 14, 24), (3000, 0.0, 10, 20)])
-def test_uniform_kernel_parity(hm, n, tol, k, r):
-    """Kernel matrices in tolerance mode and at the paper's fixed ranks:
-    every block within 1e-10 of the oracle's where the ranks agree (rank
-    mismatches counted, held to 10 tol), the whole operator's error equal to
-    the oracle's."""
+@pytest.mark.parametrize("n,tol", [(1500, 1e-8), (3000, 1e-6)])
+def test_uniform_kernel_parity(hm, n, tol):
+    """Kernel matrices in tolerance mode: every block within 1e-10 of the
+    oracle's where the ranks agree (rank mismatches counted, held to 10 tol),
+    the whole operator within 1e-8 of the oracle's and its error equal to the
+    oracle's."""
+    r = 24
     inst = workloads.config(1, n=n)
     O = oracle.OTree(inst.points, inst.leaf, inst.tree, inst.adm)
     T = hm.Tree(inst.points, inst.leaf, inst.tree, inst.adm).color()
     A = oracle.kernel_matrix(inst.points, inst.points, inst.kernel)
-    H = hm.compress(T, T.kernel_blackbox(inst.kernel), rank=k, tol=tol, r=r, seed=inst.seed,
-                    uniform=True)
-    Ho = oracle.compress_uniform(O, oracle.DenseBlackBox(A), r, k=k, tol=tol, seed=inst.seed)
+    H = hm.compress(T, T.kernel_blackbox(inst.kernel), tol=tol, r=r, seed=inst.seed, uniform=True)
+    Ho = oracle.compress_uniform(O, oracle.DenseBlackBox(A), r, tol=tol, seed=inst.seed)
     blocks = _blocks(H, O)
     _check_shared_bases(blocks)
-    worst, mism, nblk = _parity(O, blocks, Ho, A, rel=1e-10, mismatch_rel=10 * max(tol, 1e-10))
+    worst, mism, nblk = _parity(O, blocks, Ho, A, rel=1e-10, mismatch_rel=10 * tol)
     D = dense_of(hm, H, O.n)
     err = np.linalg.norm(D - A) / np.linalg.norm(A)
     err_o = np.linalg.norm(Ho.dense() - A) / np.linalg.norm(A)
     whole = np.linalg.norm(D - Ho.dense()) / np.linalg.norm(A)
     st = H.stats()
-    Hn = hm.compress(T, T.kernel_blackbox(inst.kernel), rank=k, tol=tol, r=r, seed=inst.seed)
+    Hn = hm.compress(T, T.kernel_blackbox(inst.kernel), tol=tol, r=r, seed=inst.seed)
     print("uniform: err %.2e (oracle %.2e), GPU vs oracle %.1e, worst block diff %.1e, "
           "rank mismatches %d of %d, floats %d (oracle %d, non-uniform %d)"
           % (err, err_o, whole, worst, mism, nblk, st["nfloats"], oracle.uniform_floats(Ho),
@@ -163,6 +168,47 @@ def test_uniform_kernel_parity(hm, n, tol, k, r):
     assert abs(st["nfloats"] - oracle.uniform_floats(Ho)) <= 0.01 * oracle.uniform_floats(Ho)
     assert st["nfloats"] < Hn.stats()["nfloats"]
     assert st["saturated"] == 0
+
+
+@pytest.mark.parametrize("n,k,r", [(3000, 14, 24), (3000, 10, 20)])
+def test_uniform_kernel_fixed_rank_parity(hm, n, k, r):
+    """Fixed ranks (the paper's setting).  The row basis of a box is
+    qr(sum of its stage-2 samples, k), and at these ranks the sum is
+    numerically rank-deficient for many boxes (trailing singular values at
+    the rounding level), so the directions it leaves undetermined are set
+    by rounding: a correct implementation is unique only up to that.  The
+    oracle compressing through a black box perturbed by one rounding unit
+    per entry measures the response; the GPU must stay within 10 times it on
+    every level and on the whole operator, with the error within 1.5 times
+    the oracle's and the same stored-value count.  (The column bases are not
+    unique either: at these ranks the samples of well-separated blocks have
+    trailing singular values at the rounding level.)"""
+    inst = workloads.config(1, n=n)
+    O = oracle.OTree(inst.points, inst.leaf, inst.tree, inst.adm)
+    T = hm.Tree(inst.points, inst.leaf, inst.tree, inst.adm).color()
+    A = oracle.kernel_matrix(inst.points, inst.points, inst.kernel)
+    H = hm.compress(T, T.kernel_blackbox(inst.kernel), rank=k, r=r, seed=inst.seed, uniform=True)
+    Ho = oracle.compress_uniform(O, oracle.DenseBlackBox(A), r, k=k, seed=inst.seed)
+    Hp = oracle.compress_uniform(O, PerturbedDense(A, seed=1), r, k=k, seed=inst.seed)
+    blocks = _blocks(H, O)
+    _check_shared_bases(blocks)
+    bn = block_norms(O, A)
+    sens = level_worst(O, Ho.lowrank, Hp.lowrank, bn)
+    gpu = level_worst(O, Ho.lowrank, blocks, bn)
+    Do, Dp, D = Ho.dense(), Hp.dense(), dense_of(hm, H, O.n)
+    nA = np.linalg.norm(A)
+    whole, whole_p = np.linalg.norm(D - Do) / nA, np.linalg.norm(Dp - Do) / nA
+    err, err_o = np.linalg.norm(D - A) / nA, np.linalg.norm(Do - A) / nA
+    print("uniform rank %d: err %.2e (oracle %.2e), GPU vs oracle %.1e (rounding response %.1e), "
+          "per level %s against %s" % (k, err, err_o, whole, whole_p,
+                                       ["%.1e" % gpu[l] for l in sorted(gpu)],
+                                       ["%.1e" % sens[l] for l in sorted(sens)]))
+    for l in gpu:
+        assert gpu[l] <= 10 * sens[l] + 1e-10, (l, gpu[l], sens[l])
+    assert whole <= 10 * whole_p + 1e-10
+    assert err <= 1.5 * err_o + 1e-12
+    assert H.stats()["nfloats"] == oracle.uniform_floats(Ho)
+    assert H.stats()["saturated"] == 0
 
 
 def test_uniform_gamma_extension_parity(hm):

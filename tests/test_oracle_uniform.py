@@ -102,6 +102,39 @@ def test_uniform_recovers_exact_uniform_matrices(case):
             assert U is H.ubasis[l][a] and V is H.vbasis[l][b]
 
 
+def test_plain_sum_is_short_when_partners_are_smaller_than_k():
+    """A property of the paper's rule V_b = qr(sum_a Z(I_b, block of a), k):
+    the sum has as many columns as the widest term and adds column j of
+    every term together, so where a box's interaction list holds boxes of
+    fewer than k points (their bases have fewer than k columns) the sum can
+    span fewer directions than the blocks of the box column need.  On this
+    2D tree four level-4 boxes hold fewer than 4 points and the exact matrix
+    is not recovered, while a Gaussian-weighted combination (which keeps the
+    terms' directions apart) recovers it; on the tree of the test above
+    (one such box) the plain sum is exact."""
+    T = OTree(workloads.random_points(700, 2, 11), 16)
+    small = [b for b in range(T.nbox(4)) if len(T.interaction(4, b))
+             and T.box_range(4, b)[1] - T.box_range(4, b)[0] < 4]
+    assert len(small) == 4
+    A = exact_uniform_h1(T, 4, seed=5)
+    Hs = compress_uniform(T, DenseBlackBox(A), r=10, k=4, seed=77)
+    Hg = compress_uniform(T, DenseBlackBox(A), r=10, k=4, seed=77, combine="gaussian")
+    es = np.linalg.norm(Hs.dense() - A) / np.linalg.norm(A)
+    eg = np.linalg.norm(Hg.dense() - A) / np.linalg.norm(A)
+    assert es > 1e-5 and eg < 1e-12, (es, eg)
+    # only pairs whose column box has a partner smaller than k fail
+    At = A[np.ix_(T.perm, T.perm)]
+    for l, blocks in Hs.lowrank.items():
+        for a, b, U, B, V in blocks:
+            a0, a1 = T.box_range(l, a)
+            b0, b1 = T.box_range(l, b)
+            e = np.linalg.norm(U @ B @ V.T - At[a0:a1, b0:b1]) / np.linalg.norm(At[a0:a1, b0:b1])
+            if e > 1e-10:
+                sizes = [T.box_range(l, int(c))[1] - T.box_range(l, int(c))[0]
+                         for c in T.interaction(l, b)]
+                assert min(sizes) < 4, (l, a, b, e)
+
+
 def test_uniform_is_not_exact_on_nonuniform_matrices():
     """Control: per-pair bases (non-uniform H^1) of rank k generally need
     rank > k per box, so uniform compression at rank k is far off while the
