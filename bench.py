@@ -1,18 +1,22 @@
-"""Benchmark: H^1 compression of the star-curve log-kernel operator on one GPU.
+"""Benchmark: H^1 compression by colored peeling on one GPU.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 
-Workload (the single-GPU headline configuration): N = 16384 points
-equispaced in angle on r(t) = 1 + 0.3 cos(5t), kernel log|x - y| (diagonal
-0), quadtree with leaves of at most 64 points, strong admissibility,
-relative tolerance 1e-8, p = 10, r = 24 columns per test matrix, graph-colored
-test matrices.  One step = build the tree, color every graph, compress (all
-levels and the leaf pass) and apply the result to one vector.  Inputs are
-synthetic and seeded; they are resident on the GPU before the timed region.
+Headline workload (the largest single-GPU configuration): N = 65536 points
+uniform on the unit sphere (normalised Gaussians, seed 3), kernel 1/|x - y|
+(diagonal 0), adaptive octree with leaves of at most 128 points, strong
+admissibility, relative tolerance 1e-6, p = 10, r = 32 columns per test
+matrix, graph-colored test matrices, FP64.  One step = build the tree, color
+every graph, compress (all levels and the leaf pass) and apply the result to
+one vector.  Inputs are synthetic and seeded; after the host tree they are
+resident on the GPU.
 
 The JSON line reports the FP64 path as `value` (GFLOP/s of the algorithmic
-work: black box + peel + QR + coupling solves); the mixed FP32/FP64 path is
-measured the same way and reported with its error against the FP64 result.
+work: black box + peel + QR + coupling solves) and beside it the net rate
+without the black box, the kernel apply's and the peel's rooflines, the
+spectral error (20 power iterations), the mixed FP32/FP64 form, the other
+configurations (HODLR line, star curve), the uniform and H^2 formats, products,
+the batched form and the served mix.
 """
 from __future__ import annotations
 
@@ -30,22 +34,27 @@ sys.path.insert(0, ROOT)
 METRIC = "peel GFLOP/s + compressions/s at rel err 1e-5 vs plain FP64; p50/p99 ms"
 PEAK_FP64_MFMA = 78.6e12
 PEAK_FP32_MFMA = 157.3e12
-R_COLS = 24
-H2_RANK = R_COLS - 10   # fixed rank of the H^2 line (r - p)
+PEAK_HBM = 8.0e12
+R_COLS = 24            # star-curve lines (the rank rule: largest rank 8 + p <= 24)
+H2_RANK = R_COLS - 10  # fixed rank of the H^2 and fixed-rank uniform lines (r - p)
+CPU_SAMPLE_N = 16384   # sphere points of the oracle's timed sample
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--n", type=int, default=16384)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=65536, help="headline sphere points")
+    ap.add_argument("--sub-steps", type=int, default=10,
+                    help="timed steps of each star-curve, HODLR and format sub-line")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-uniform", action="store_true")
     ap.add_argument("--no-product", action="store_true")
     ap.add_argument("--no-h2", action="store_true")
+    ap.add_argument("--no-configs", action="store_true", help="skip the HODLR and star-curve lines")
     ap.add_argument("--batched-steps", type=int, default=3)
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--served-requests", type=int, default=80)
@@ -53,7 +62,9 @@ def parse():
                     help="comma-separated offered loads (fractions of the FP64 capacity)")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run this many steps, no extras (for profilers)")
-    ap.add_argument("--profile-workload", default="star", choices=["star", "mixed", "batched", "uniform", "product", "h2"],
+    ap.add_argument("--profile-workload", default="sphere",
+                    choices=["sphere", "sphere_mixed", "star", "mixed", "batched", "uniform",
+                             "product", "h2"],
                     help="with --profile-steps: which workload the steps run")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="with --profile-steps: add a 1 GiB device copy that calibrates "
@@ -61,22 +72,22 @@ def parse():
     return ap.parse_args()
 
 
-def step(hm, inst, bb_kernel, x, y, prec, tol, uniform=False, h2=False, rank=0):
+def step(hm, inst, bb_kernel, x, y, prec, tol, uniform=False, h2=False, rank=0, r=None):
     T = hm.Tree(inst.points, inst.leaf, inst.tree, inst.adm).color()
     bb = T.kernel_blackbox(bb_kernel)
-    H = hm.compress(T, bb, rank=rank, tol=0.0 if rank else tol, r=R_COLS, seed=inst.seed,
+    H = hm.compress(T, bb, rank=rank, tol=0.0 if rank else tol, r=r or inst.r, seed=inst.seed,
                     prec=prec, timing=True, uniform=uniform, h2=h2)
     H.matvec(x, y)
     return T, H
 
 
-def kapply_traffic_bytes():
-    """HBM bytes per kernel-apply launch from the committed counter summary
+def kapply_traffic_bytes(summary):
+    """HBM bytes per kernel-apply launch from a committed counter summary
     (FETCH_SIZE and WRITE_SIZE runs, scaled by the copy calibration), or
     None when the kernel source changed since the counters were taken."""
     import hashlib
     try:
-        txt = open(os.path.join(ROOT, "profiles", "kapply_f64_star_curve_N16384_pmc.md")).read()
+        txt = open(os.path.join(ROOT, "profiles", summary)).read()
         src = open(os.path.join(ROOT, "paper_2205_03406_amd", "csrc", "k_kapply.hip"), "rb").read()
     except OSError:
         return None
@@ -98,28 +109,133 @@ def algorithmic_flops(st):
     return st["flops_blackbox"] + st["flops_peel"] + st["flops_qr"] + st["flops_solve"]
 
 
-def run_path(hm, torch, inst, prec, tol, steps, warmup, x, y, uniform=False, h2=False, rank=0):
+def net_flops(st):
+    return st["flops_peel"] + st["flops_qr"] + st["flops_solve"]
+
+
+def run_path(hm, torch, inst, prec, tol, steps, warmup, x, y, uniform=False, h2=False, rank=0,
+             r=None):
+    """warmup + steps timed steps of one workload; accumulates the stage
+    statistics of the timed steps."""
     for _ in range(warmup):
-        step(hm, inst, inst.kernel, x, y, prec, tol, uniform, h2, rank)
+        step(hm, inst, inst.kernel, x, y, prec, tol, uniform, h2, rank, r)
     torch.cuda.synchronize()
-    times, flops, bb_ms, bb_flops, launches = [], 0.0, 0.0, 0.0, 0
-    H = None
+    acc = dict(flops=0.0, bb_ms=0.0, bb_flops=0.0, net_flops=0.0, net_ms=0.0, peel_ms=0.0,
+               peel_flops=0.0, peel_bytes=0.0, launches=0)
+    times = []
+    H = T = st = None
     t_all0 = time.perf_counter()
     for _ in range(steps):
         t0 = time.perf_counter()
-        T, H = step(hm, inst, inst.kernel, x, y, prec, tol, uniform, h2, rank)
+        T, H = step(hm, inst, inst.kernel, x, y, prec, tol, uniform, h2, rank, r)
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t0)
         st = H.stats()
-        flops += algorithmic_flops(st)
-        bb_ms += st["ms_blackbox"]
-        bb_flops += st["flops_blackbox"]
+        acc["flops"] += algorithmic_flops(st)
+        acc["bb_ms"] += st["ms_blackbox"]
+        acc["bb_flops"] += st["flops_blackbox"]
+        acc["net_flops"] += net_flops(st)
+        acc["net_ms"] += st["ms_peel"] + st["ms_qr"] + st["ms_solve"]
+        acc["peel_ms"] += st["ms_peel"]
+        acc["peel_flops"] += st["flops_peel"]
+        acc["peel_bytes"] += st["bytes_peel"]
         # one black-box launch per sampled level (two in the uniform format)
         # and the leaf pass
-        launches += (2 if uniform or h2 else 1) * sum(1 for c in st["colors"] if c) + 1
+        acc["launches"] += (2 if uniform or h2 else 1) * sum(1 for c in st["colors"] if c) + 1
     total = time.perf_counter() - t_all0
-    return dict(times=times, total=total, flops=flops, bb_ms=bb_ms, bb_flops=bb_flops,
-                launches=launches, H=H, T=T, stats=st)
+    return dict(times=times, total=total, H=H, T=T, stats=st, **acc)
+
+
+def line_of(run, steps, n):
+    """Throughput, latency and statistics of one run_path result."""
+    st = run["stats"]
+    lat = np.array(run["times"]) * 1e3
+    return {
+        "value": round(run["flops"] / run["total"] / 1e9, 2), "unit": "GFLOP/s",
+        "compressions_per_s": round(steps / run["total"], 3),
+        "ms_per_step": round(1e3 * run["total"] / steps, 3),
+        "p50_ms": round(float(np.percentile(lat, 50)), 3),
+        "p99_ms": round(float(np.percentile(lat, 99)), 3),
+        "net_gflops": round(run["net_flops"] / (run["net_ms"] / 1e3) / 1e9, 2)
+        if run["net_ms"] > 0 else None,
+        "kapply_tflops": round(run["bb_flops"] / (run["bb_ms"] / 1e3) / 1e12, 3)
+        if run["bb_ms"] > 0 else None,
+        "colors_per_level": [c for c in st["colors"] if c],
+        "leaf_colors": st["leaf_colors"],
+        "cols_A": st["cols_A"], "cols_At": st["cols_At"],
+        "max_rank": st["max_rank"], "saturated": st["saturated"],
+        "floats_per_dof": round(st["nfloats"] / n, 2),
+        "device_mb": round(st["device_bytes"] / 2**20, 1),
+        "stage_ms": {k: round(st[k], 3) for k in ("ms_blackbox", "ms_peel", "ms_qr", "ms_solve",
+                                                  "ms_other", "ms_total")},
+    }
+
+
+def peel_roofline(run, prec_bytes):
+    """Achieved rate of the peel stage (the level-truncated products
+    subtracted, lr_project / lr_reduce / lr_expand and the finiteness check),
+    timed by HIP events around the stage on the compression stream: its
+    algorithmic bytes against HBM and its flops against the matrix cores."""
+    if run["peel_ms"] <= 0:
+        return None
+    sec = run["peel_ms"] / 1e3
+    gbs = run["peel_bytes"] / sec
+    fl = run["peel_flops"] / sec
+    peak = PEAK_FP64_MFMA if prec_bytes == 8 else PEAK_FP32_MFMA
+    return {"kernels": "lr_project_kernel, lr_reduce_kernel, lr_expand_kernel", "bound": "hbm",
+            "achieved": round(gbs / 1e9, 1), "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+            "frac": round(gbs / PEAK_HBM, 4),
+            "flops_achieved_tflops": round(fl / 1e12, 3), "flops_peak_tflops": peak / 1e12,
+            "flops_frac": round(fl / peak, 4),
+            "intensity_flop_per_byte": round(run["peel_flops"] / run["peel_bytes"], 2),
+            "ms_per_compression": round(run["peel_ms"] / max(1, len(run["times"])), 3)}
+
+
+def device_errors(hm, torch, T, H, kernel, dtype=None, nprobe=16, iters=20, seed=12):
+    """Errors of H against the kernel matrix A, both applied on the device
+    (A by the library's FP64 kernel apply, generated on the fly): the probe
+    estimate ||(A - H) G||_F / ||A G||_F over nprobe Gaussian vectors, and
+    the spectral ratio ||A - H||_2 / ||A||_2 from `iters` power iterations
+    on (A - H)* (A - H) and on A* A (A is symmetric for both kernels; H* by
+    the adjoint apply)."""
+    n = T.n
+    rng = np.random.default_rng(seed)
+
+    def dev(M):
+        t = hm.colmajor(n, M.shape[1])
+        t.copy_(torch.from_numpy(M))
+        return t
+
+    def Aop(X):
+        Y = hm.colmajor(n, X.shape[1])
+        T.kernel_apply(kernel, X, Y, order=hm.HM_ORDER_ORIGINAL)
+        return Y
+
+    def Hop(X, trans=False):
+        Y = hm.colmajor(n, X.shape[1])
+        H.matvec(X, Y, trans=trans)
+        return Y
+
+    G = dev(rng.standard_normal((n, nprobe)))
+    AG = Aop(G)
+    probe = float(torch.linalg.norm(AG - Hop(G)) / torch.linalg.norm(AG))
+
+    def power(op, opT):
+        v = dev(rng.standard_normal((n, 1)))
+        v /= torch.linalg.norm(v)
+        s = 0.0
+        for _ in range(iters):
+            u = opT(op(v))
+            s = float(torch.linalg.norm(u))
+            if s == 0.0:
+                return 0.0
+            v = u / s
+        return s ** 0.5
+
+    sd = power(lambda v: Aop(v) - Hop(v), lambda w: Aop(w) - Hop(w, True))
+    sa = power(Aop, Aop)
+    torch.cuda.synchronize()
+    return {"probe_rel_fro": probe, "spectral_rel_power20": sd / sa}
 
 
 def run_product(hm, torch, inst, H, steps, warmup):
@@ -246,9 +362,6 @@ def run_batched(hm, torch, steps):
                    "achieved": round(ach / 1e12, 3), "peak": PEAK_FP32_MFMA / 1e12,
                    "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_MFMA, 4)},
     }
-    ceil32 = hm.mfma_rate(hm.HM_F32)
-    res["kapply"]["mfma_sustained"] = round(ceil32, 2)
-    res["kapply"]["frac_of_sustained"] = round(ach / 1e12 / ceil32, 4)
     return res
 
 
@@ -368,6 +481,14 @@ def run_served(hm, count, loads):
     return out
 
 
+def oracle_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        return max(int(i.get("num_threads", 1)) for i in threadpool_info())
+    except Exception:
+        return int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -383,28 +504,38 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
-    inst = workloads.config(1, n=args.n)
+    inst = workloads.config(2, n=args.n)          # sphere, 1/r, tol 1e-6, r = 32
+    star = workloads.config(1)                    # star curve, log, tol 1e-8, r = 24
+
+    def vecs(m):
+        a = hm.colmajor(m, 1)
+        a.copy_(torch.from_numpy(np.random.default_rng(0).standard_normal((m, 1))))
+        return a, hm.colmajor(m, 1)
+
     n = inst.points.shape[0]
-    x = hm.colmajor(n, 1)
-    x.copy_(torch.from_numpy(np.random.default_rng(0).standard_normal((n, 1))))
-    y = hm.colmajor(n, 1)
+    x, y = vecs(n)
+    ns = star.points.shape[0]
+    xs, ys = vecs(ns)
 
     if args.profile_steps:
-        if args.profile_workload == "batched":
+        w = args.profile_workload
+        if w == "batched":
             insts = workloads.batched_ellipses()
             for _ in range(args.profile_steps):
                 batched_step(hm, insts, hm.HM_PREC_MIXED)
-        elif args.profile_workload == "product":
-            _, H = step(hm, inst, inst.kernel, x, y, hm.HM_PREC_F64, inst.tol)
-            run_product(hm, torch, inst, H, args.profile_steps, 0)
-        else:
-            prec = hm.HM_PREC_MIXED if args.profile_workload == "mixed" else hm.HM_PREC_F64
-            tol = 1e-6 if args.profile_workload == "mixed" else inst.tol
+        elif w == "product":
+            _, H = step(hm, star, star.kernel, xs, ys, hm.HM_PREC_F64, star.tol)
+            run_product(hm, torch, star, H, args.profile_steps, 0)
+        elif w in ("sphere", "sphere_mixed"):
+            prec = hm.HM_PREC_MIXED if w == "sphere_mixed" else hm.HM_PREC_F64
             for _ in range(args.profile_steps):
-                step(hm, inst, inst.kernel, x, y, prec, tol,
-                     uniform=args.profile_workload == "uniform",
-                     h2=args.profile_workload == "h2",
-                     rank=H2_RANK if args.profile_workload == "h2" else 0)
+                step(hm, inst, inst.kernel, x, y, prec, inst.tol)
+        else:
+            prec = hm.HM_PREC_MIXED if w == "mixed" else hm.HM_PREC_F64
+            tol = 1e-6 if w == "mixed" else star.tol
+            for _ in range(args.profile_steps):
+                step(hm, star, star.kernel, xs, ys, prec, tol, uniform=w == "uniform",
+                     h2=w == "h2", rank=H2_RANK if w in ("h2", "uniform") else 0)
         torch.cuda.synchronize()
         if args.pmc_probe:
             # calibration for the HBM byte counters: one plain device copy of
@@ -417,148 +548,110 @@ def main():
         print("profile run done", flush=True)
         return
 
+    # ---------------- headline: the sphere, FP64
     r64 = run_path(hm, torch, inst, hm.HM_PREC_F64, inst.tol, args.steps, args.warmup, x, y)
-    _progress("FP64 path done")
-    st = r64["stats"]
-    ms = 1e3 * r64["total"] / args.steps
-    value = r64["flops"] / r64["total"] / 1e9
-    lat = np.array(r64["times"]) * 1e3
-
+    _progress("headline FP64 path done")
+    line = line_of(r64, args.steps, n)
     out = {
         "metric": METRIC,
-        "value": round(value, 2),
-        "unit": "GFLOP/s",
+        "value": line.pop("value"),
+        "unit": line.pop("unit"),
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms, 3),
+        "ms_per_step": line.pop("ms_per_step"),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "star_curve_log_N%d_leaf64_strong_tol1e-8_r%d" % (n, R_COLS),
+        "config": {"workload": "sphere_inv_r_N%d_leaf128_adaptive_octree_strong_tol1e-6_r%d"
+                               % (n, inst.r),
                    "step": "build_tree+color+compress+hmatvec(1 rhs)"},
-        "compressions_per_s": round(args.steps / r64["total"], 3),
-        "p50_ms": round(float(np.percentile(lat, 50)), 3),
-        "p99_ms": round(float(np.percentile(lat, 99)), 3),
-        "colors_per_level": [c for c in st["colors"] if c],
-        "leaf_colors": st["leaf_colors"],
-        "cols_A": st["cols_A"],
-        "cols_At": st["cols_At"],
-        "max_rank": st["max_rank"],
-        "saturated": st["saturated"],
-        "floats_per_dof": round(st["nfloats"] / n, 2),
-        "device_mb": round(st["device_bytes"] / 2**20, 1),
-        "stage_ms": {k: round(st[k], 3) for k in ("ms_blackbox", "ms_peel", "ms_qr", "ms_solve",
-                                                  "ms_other", "ms_total")},
     }
+    out.update(line)
     # dominant kernel: the on-the-fly kernel apply (FP64 MFMA), timed by HIP
     # events recorded around its launches on the compression stream
     ach = r64["bb_flops"] / (r64["bb_ms"] / 1e3)
-    out["roofline"] = {"kernel": "kapply_kernel<double>", "bound": "mfma",
+    out["roofline"] = {"kernel": "kapply_kernel<double> (1/r)", "bound": "mfma",
                        "achieved": round(ach / 1e12, 3), "peak": PEAK_FP64_MFMA / 1e12,
                        "unit": "TFLOP/s", "frac": round(ach / PEAK_FP64_MFMA, 4),
-                       "traffic": kapply_traffic_bytes(),
+                       "traffic": kapply_traffic_bytes("kapply_f64_sphere_N65536_pmc.md"),
                        "avg_launch_ms": round(r64["bb_ms"] / r64["launches"], 4),
                        "flops_per_launch": r64["bb_flops"] / r64["launches"]}
-    # what the matrix cores of this part sustain for the same instruction
-    # (independent chains, no memory traffic), measured outside the timed steps
-    ceil64 = hm.mfma_rate(hm.HM_F64)
-    out["roofline"]["mfma_sustained"] = round(ceil64, 2)
-    out["roofline"]["frac_of_sustained"] = round(ach / 1e12 / ceil64, 4)
-
-    # accuracy of the FP64 result on sampled rows (outside the timed region)
-    import oracle
+    out["peel_roofline"] = peel_roofline(r64, 8)
     H = r64["H"]
-    X = np.random.default_rng(5).standard_normal((n, 4))
-    Xd = hm.colmajor(n, 4)
-    Xd.copy_(torch.from_numpy(X))
-    Yd = hm.colmajor(n, 4)
-    H.matvec(Xd, Yd)
-    torch.cuda.synchronize()
-    Y64 = Yd.cpu().numpy()
-    rows = np.random.default_rng(6).choice(n, 128, replace=False)
-    kb = oracle.KernelBlackBox(inst.points, inst.kernel, dense_cache=False)
-    want = kb.rows(rows, X)
-    out["rel_err_vs_dense_sampled_rows"] = float(np.linalg.norm(Y64[rows] - want) / np.linalg.norm(want))
+    out["error_vs_kernel"] = device_errors(hm, torch, r64["T"], H, inst.kernel)
+    _progress("headline errors done")
 
     if not args.no_mixed:
-        rmx = run_path(hm, torch, inst, hm.HM_PREC_MIXED, 1e-6, args.steps, args.warmup, x, y)
-        Yd2 = hm.colmajor(n, 4)
-        rmx["H"].matvec(Xd, Yd2)
+        rmx = run_path(hm, torch, inst, hm.HM_PREC_MIXED, inst.tol, args.steps, args.warmup, x, y)
+        G = hm.colmajor(n, 4)
+        G.copy_(torch.from_numpy(np.random.default_rng(5).standard_normal((n, 4))))
+        Y64, Ymx = hm.colmajor(n, 4), hm.colmajor(n, 4)
+        H.matvec(G, Y64)
+        rmx["H"].matvec(G, Ymx)
         torch.cuda.synchronize()
-        Ymx = Yd2.cpu().numpy()
-        out["mixed"] = {
-            "value": round(rmx["flops"] / rmx["total"] / 1e9, 2),
-            "compressions_per_s": round(args.steps / rmx["total"], 3),
-            "ms_per_step": round(1e3 * rmx["total"] / args.steps, 3),
-            "p50_ms": round(float(np.percentile(np.array(rmx["times"]) * 1e3, 50)), 3),
-            "p99_ms": round(float(np.percentile(np.array(rmx["times"]) * 1e3, 99)), 3),
-            "tol": 1e-6,
-            "rel_err_vs_fp64": float(np.linalg.norm(Ymx - Y64) / np.linalg.norm(Y64)),
-            "kapply_tflops": round(rmx["bb_flops"] / (rmx["bb_ms"] / 1e3) / 1e12, 3),
-        }
+        mline = line_of(rmx, args.steps, n)
+        mline["tol"] = inst.tol
+        mline["rel_err_vs_fp64"] = float(torch.linalg.norm(Ymx - Y64) / torch.linalg.norm(Y64))
+        mline["error_vs_kernel"] = device_errors(hm, torch, rmx["T"], rmx["H"], inst.kernel)
+        mline["peel_roofline"] = peel_roofline(rmx, 4)
+        out["mixed"] = mline
+        del rmx
+        _progress("headline mixed path done")
+    del r64
 
-    if not args.no_uniform:
-        # uniform H^1 format on the same workload and tolerance (FP64)
-        run = run_path(hm, torch, inst, hm.HM_PREC_F64, inst.tol, args.steps, args.warmup, x, y,
-                       uniform=True)
-        su = run["stats"]
-        Yd3 = hm.colmajor(n, 4)
-        run["H"].matvec(Xd, Yd3)
+    # ---------------- the other single-compression configurations
+    Hstar = None
+    if not args.no_configs:
+        hod = workloads.config(0)
+        xh, yh = vecs(hod.points.shape[0])
+        rh = run_path(hm, torch, hod, hm.HM_PREC_F64, 0.0, args.sub_steps, 2, xh, yh, rank=hod.rank)
+        hl = line_of(rh, args.sub_steps, hod.points.shape[0])
+        hl["workload"] = "hodlr_line_log_N1024_index_binary_leaf64_weak_k20_r30"
+        hl["error_vs_kernel"] = device_errors(hm, torch, rh["T"], rh["H"], hod.kernel)
+        out["hodlr"] = hl
+        del rh
+        rs = run_path(hm, torch, star, hm.HM_PREC_F64, star.tol, args.sub_steps, 2, xs, ys)
+        sl = line_of(rs, args.sub_steps, ns)
+        sl["workload"] = "star_curve_log_N16384_leaf64_strong_tol1e-8_r%d" % R_COLS
+        sl["error_vs_kernel"] = device_errors(hm, torch, rs["T"], rs["H"], star.kernel)
+        sl["peel_roofline"] = peel_roofline(rs, 8)
+        Hstar = rs["H"]
+        rsm = run_path(hm, torch, star, hm.HM_PREC_MIXED, 1e-6, args.sub_steps, 2, xs, ys)
+        G = hm.colmajor(ns, 4)
+        G.copy_(torch.from_numpy(np.random.default_rng(5).standard_normal((ns, 4))))
+        Y64, Ymx = hm.colmajor(ns, 4), hm.colmajor(ns, 4)
+        Hstar.matvec(G, Y64)
+        rsm["H"].matvec(G, Ymx)
         torch.cuda.synchronize()
-        Yu = Yd3.cpu().numpy()
-        out["uniform"] = {
-            "value": round(run["flops"] / run["total"] / 1e9, 2),
-            "compressions_per_s": round(args.steps / run["total"], 3),
-            "ms_per_step": round(1e3 * run["total"] / args.steps, 3),
-            "p50_ms": round(float(np.percentile(np.array(run["times"]) * 1e3, 50)), 3),
-            "floats_per_dof": round(su["nfloats"] / n, 2),
-            "device_mb": round(su["device_bytes"] / 2**20, 1),
-            "stage1_colors_per_level": [c for c in su["ucolors"] if c],
-            "cols_A": su["cols_A"],
-            "cols_At": su["cols_At"],
-            "max_rank": su["max_rank"],
-            "saturated": su["saturated"],
-            "rel_err_vs_dense_sampled_rows": float(np.linalg.norm(Yu[rows] - want) /
-                                                   np.linalg.norm(want)),
-            "kapply_tflops": round(run["bb_flops"] / (run["bb_ms"] / 1e3) / 1e12, 3),
-            "stage_ms": {k: round(su[k], 3) for k in ("ms_blackbox", "ms_peel", "ms_qr",
-                                                      "ms_solve", "ms_other", "ms_total")},
-        }
-        _progress("uniform done")
+        sml = line_of(rsm, args.sub_steps, ns)
+        sml["tol"] = 1e-6
+        sml["rel_err_vs_fp64"] = float(torch.linalg.norm(Ymx - Y64) / torch.linalg.norm(Y64))
+        sl["mixed"] = sml
+        out["star_curve"] = sl
+        del rsm
+        _progress("HODLR and star-curve lines done")
 
-    if not args.no_h2:
-        # H^2 format (nested bases) on the same workload at the fixed rank
-        # r - p (the truncation of augmented samples by a tolerance compounds
-        # over the levels)
-        run = run_path(hm, torch, inst, hm.HM_PREC_F64, inst.tol, args.steps, args.warmup, x, y,
-                       h2=True, rank=H2_RANK)
-        s2 = run["stats"]
-        Yd4 = hm.colmajor(n, 4)
-        run["H"].matvec(Xd, Yd4)
-        torch.cuda.synchronize()
-        Yh = Yd4.cpu().numpy()
-        out["h2"] = {
-            "value": round(run["flops"] / run["total"] / 1e9, 2),
-            "compressions_per_s": round(args.steps / run["total"], 3),
-            "ms_per_step": round(1e3 * run["total"] / args.steps, 3),
-            "p50_ms": round(float(np.percentile(np.array(run["times"]) * 1e3, 50)), 3),
-            "rank": H2_RANK,
-            "floats_per_dof": round(s2["nfloats"] / n, 2),
-            "device_mb": round(s2["device_bytes"] / 2**20, 1),
-            "max_rank": s2["max_rank"],
-            "saturated": s2["saturated"],
-            "rel_err_vs_dense_sampled_rows": float(np.linalg.norm(Yh[rows] - want) /
-                                                   np.linalg.norm(want)),
-            "stage_ms": {k: round(s2[k], 3) for k in ("ms_blackbox", "ms_peel", "ms_qr",
-                                                      "ms_solve", "ms_other", "ms_total")},
-        }
-        _progress("h2 done")
+    # ---------------- the paper's other formats on the star curve
+    for name, skip, kw in (("uniform", args.no_uniform, dict(uniform=True, rank=H2_RANK)),
+                           ("uniform_tol", args.no_uniform, dict(uniform=True)),
+                           ("h2", args.no_h2, dict(h2=True, rank=H2_RANK))):
+        if skip:
+            continue
+        run = run_path(hm, torch, star, hm.HM_PREC_F64, star.tol, args.sub_steps, 2, xs, ys, **kw)
+        fl = line_of(run, args.sub_steps, ns)
+        fl["rank"] = kw.get("rank", 0)
+        fl["tol"] = 0.0 if kw.get("rank") else star.tol
+        fl["stage1_colors_per_level"] = [c for c in run["stats"]["ucolors"] if c]
+        fl["error_vs_kernel"] = device_errors(hm, torch, run["T"], run["H"], star.kernel)
+        out[name] = fl
+        del run
+        _progress(name + " done")
 
-    if not args.no_product:
-        out["product"] = run_product(hm, torch, inst, H, args.steps, args.warmup)
+    if not args.no_product and Hstar is not None:
+        out["product"] = run_product(hm, torch, star, Hstar, args.sub_steps, 2)
         _progress("product done")
 
     if not args.no_batched:
@@ -567,28 +660,29 @@ def main():
 
     if not args.no_served:
         out["served"] = run_served(hm, args.served_requests,
-                                   [float(x) for x in args.served_loads.split(",")])
+                                   [float(v) for v in args.served_loads.split(",")])
 
     if not args.no_cpu_baseline:
-        # the oracle, untuned, on one full compression of the same workload
+        # the oracle, untuned, on a bounded sample of the headline workload:
+        # the same sphere generator, kernel, leaf, tolerance and r at
+        # CPU_SAMPLE_N points; its algorithmic flops are those the GPU counts
+        # for a compression of the same sample (same tree, colors and r;
+        # ranks agree up to threshold ties)
         import oracle as O
-        try:
-            from threadpoolctl import threadpool_info
-            nthreads = max(int(i.get("num_threads", 1)) for i in threadpool_info())
-        except Exception:
-            nthreads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        samp = workloads.config(2, n=CPU_SAMPLE_N)
+        xc, yc = vecs(CPU_SAMPLE_N)
+        _, Hs = step(hm, samp, samp.kernel, xc, yc, hm.HM_PREC_F64, samp.tol)
+        fl = algorithmic_flops(Hs.stats())
         t0 = time.perf_counter()
-        OT = O.OTree(inst.points, inst.leaf, inst.tree, inst.adm)
-        obb = O.KernelBlackBox(inst.points, inst.kernel)
-        Ho = O.compress(OT, obb, R_COLS, tol=inst.tol, seed=inst.seed)
+        OT = O.OTree(samp.points, samp.leaf, samp.tree, samp.adm)
+        obb = O.KernelBlackBox(samp.points, samp.kernel)
+        O.compress(OT, obb, samp.r, tol=samp.tol, seed=samp.seed)
         tcpu = time.perf_counter() - t0
-        # algorithmic flops of that compression: the GPU run's count (same
-        # tree, colors, r; ranks agree up to threshold ties)
-        out["cpu_baseline"] = {"value": round(algorithmic_flops(st) / tcpu / 1e9, 3),
-                               "unit": "GFLOP/s", "cores": nthreads, "kind": "oracle",
-                               "sample": "one full compression of the benchmark workload "
-                                         "(tree, colors, dense FP64 black box, recovery), %.1f s"
-                                         % tcpu}
+        out["cpu_baseline"] = {"value": round(fl / tcpu / 1e9, 3), "unit": "GFLOP/s",
+                               "cores": oracle_threads(), "kind": "oracle",
+                               "sample": "one full oracle compression (tree, colors, dense FP64 "
+                                         "black box, recovery) of the headline sphere workload "
+                                         "at N=%d, %.1f s" % (CPU_SAMPLE_N, tcpu)}
     print(json.dumps(out), flush=True)
 
 

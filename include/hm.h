@@ -415,6 +415,9 @@ typedef struct {
   double flops_solve;        /* coupling solves */
   double ms_total, ms_blackbox, ms_peel, ms_qr, ms_solve, ms_other; /* flags bit 0 */
   int64_t device_bytes;      /* device memory the H-matrix holds (factors, plans) */
+  double bytes_peel;         /* algorithmic HBM bytes of the peel: per sampled level
+                                (and the leaf pass) the samples read and written once
+                                and the coarser levels' factors read once */
 } hm_stats;
 hm_status hm_hmatrix_stats(const hm_hmatrix *H, hm_stats *out);
 

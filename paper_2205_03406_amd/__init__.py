@@ -85,7 +85,7 @@ class Stats(C.Structure):
                 ("flops_solve", C.c_double), ("ms_total", C.c_double),
                 ("ms_blackbox", C.c_double), ("ms_peel", C.c_double), ("ms_qr", C.c_double),
                 ("ms_solve", C.c_double), ("ms_other", C.c_double),
-                ("device_bytes", C.c_int64)]
+                ("device_bytes", C.c_int64), ("bytes_peel", C.c_double)]
 
     def as_dict(self):
         d = {}

@@ -2154,8 +2154,12 @@ hm_status Compression::finalize(hipStream_t s, Events &ev,
       }
     }
   }
-  double fbb = 0;
+  double fbb = 0, bpeel = 0;
   {
+    // peel bytes: a level with coarser factors reads X and reads and writes
+    // Y once (es bytes per element; the uniform formats' stage 2 in FP64)
+    // and reads every coarser factor once (V and W = U B, prev / 2 elements)
+    const double es1 = mixed ? 4.0 : 8.0;
     std::vector<double> prev(ni, 0.0);
     for (size_t li = 0; li < H->lv.size(); ++li) {
       const int l = H->lv[li].level;
@@ -2174,6 +2178,11 @@ hm_status Compression::finalize(hipStream_t s, Events &ev,
         const double ni_rows = (double)(T.inst_off[i + 1] - T.inst_off[i]);
         fpeel += c * prev[i];
         fbb += 2.0 * ni_rows * ni_rows * c;
+        if (prev[i] > 0) {
+          const double sbytes = uniform ? (double)wu[i] * r * es1 + (double)w[i] * kmax * 8.0
+                                        : c * es1;
+          bpeel += 3.0 * ni_rows * sbytes + (uniform ? es1 + 8.0 : es1) * prev[i] / 2.0;
+        }
       }
       for (int i = 0; i < ni; ++i) prev[i] += apply_cost_of[li][i];
     }
@@ -2189,6 +2198,7 @@ hm_status Compression::finalize(hipStream_t s, Events &ev,
       const double ni_rows = (double)(T.inst_off[i + 1] - T.inst_off[i]);
       fpeel += (double)wl[i] * mwi[i] * prev[i];
       fbb += 2.0 * ni_rows * ni_rows * (double)wl[i] * mwi[i];
+      if (prev[i] > 0) bpeel += 3.0 * ni_rows * (double)wl[i] * mwi[i] * es1 + es1 * prev[i] / 2.0;
     }
   }
   st.nfloats = nfloats;
@@ -2196,6 +2206,7 @@ hm_status Compression::finalize(hipStream_t s, Events &ev,
   st.flops_peel = fpeel;
   st.flops_qr = fqr;
   st.flops_solve = fsolve;
+  st.bytes_peel = bpeel;
   if (ev.on && !ev.marks.empty()) {
     double acc[6] = {0, 0, 0, 0, 0, 0};
     for (size_t i = 0; i + 1 < ev.marks.size(); ++i) {
