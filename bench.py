@@ -182,12 +182,20 @@ def peel_roofline(run, prec_bytes):
     gbs = run["peel_bytes"] / sec
     fl = run["peel_flops"] / sec
     peak = PEAK_FP64_MFMA if prec_bytes == 8 else PEAK_FP32_MFMA
-    return {"kernels": "lr_project_kernel, lr_reduce_kernel, lr_expand_kernel", "bound": "hbm",
-            "achieved": round(gbs / 1e9, 1), "peak": PEAK_HBM / 1e9, "unit": "GB/s",
-            "frac": round(gbs / PEAK_HBM, 4),
-            "flops_achieved_tflops": round(fl / 1e12, 3), "flops_peak_tflops": peak / 1e12,
-            "flops_frac": round(fl / peak, 4),
-            "intensity_flop_per_byte": round(run["peel_flops"] / run["peel_bytes"], 2),
+    ai = run["peel_flops"] / run["peel_bytes"]
+    # the bound is the one the algorithmic intensity selects (ridge = peak
+    # flops / HBM bandwidth); both fractions are reported
+    mfma = ai >= peak / PEAK_HBM
+    return {"kernels": "lr_project_kernel, lr_reduce_kernel, lr_expand_kernel",
+            "bound": "mfma" if mfma else "hbm",
+            "achieved": round(fl / 1e12, 3) if mfma else round(gbs / 1e9, 1),
+            "peak": peak / 1e12 if mfma else PEAK_HBM / 1e9,
+            "unit": "TFLOP/s" if mfma else "GB/s",
+            "frac": round(fl / peak if mfma else gbs / PEAK_HBM, 4),
+            "hbm_gbs": round(gbs / 1e9, 1), "hbm_frac": round(gbs / PEAK_HBM, 4),
+            "flops_tflops": round(fl / 1e12, 3), "flops_frac": round(fl / peak, 4),
+            "intensity_flop_per_byte": round(ai, 2),
+            "algorithmic_bytes_per_compression": run["peel_bytes"] / max(1, len(run["times"])),
             "ms_per_compression": round(run["peel_ms"] / max(1, len(run["times"])), 3)}
 
 
