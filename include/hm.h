@@ -372,6 +372,26 @@ hm_status hm_matvec(const hm_hmatrix *H, int64_t nrhs, int dtype, const void *X,
 hm_status hm_matvec_op(const hm_hmatrix *H, int trans, int64_t nrhs, int dtype, const void *X,
                        int64_t ldx, void *Y, int64_t ldy, int order, void *stream);
 
+/* hm_matvec_static: hm_matvec_op without any device allocation, for callers
+ * that cannot allocate (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Its scratch (the order-conversion
+ * copies and the low-rank expansions) is a static device array of
+ * HM_STATIC_SCRATCH_BYTES, one per device, held from the library's load
+ * until the process ends; the right-hand sides go through in blocks of as
+ * many columns as fit.  Results equal hm_matvec_op's (every column is
+ * computed the same way).  Arguments, layout and ownership as hm_matvec_op.
+ * Errors: HM_E_ARG for bad arguments or when one right-hand side needs more
+ * scratch than the array holds (the message gives the bytes needed: about
+ * 2 n + (pair segments) kmax elements in the original order); HM_E_DEVICE
+ * when the array's device address cannot be obtained.  Every call on one
+ * device shares that device's array: calls that overlap on a device (on
+ * several streams, or from several threads without ordering) race, and
+ * must be serialized by the caller.  Nothing in the array needs to start
+ * at zero (every byte a call reads it has written first). */
+#define HM_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+hm_status hm_matvec_static(const hm_hmatrix *H, int trans, int64_t nrhs, int dtype, const void *X,
+                           int64_t ldx, void *Y, int64_t ldy, int order, void *stream);
+
 /* Device test matrix of one level and pass (0 = Omega, 1 = Psi, 2 = stage 1
  * of the uniform format, colored by hm_uniform_graph) exactly as hm_compress
  * draws it: out (device, n x ncolors*r, ld) in tree order. */

@@ -49,6 +49,7 @@ EXPORTED = [
     "hm_server_release", "hm_server_info", "hm_compress_plan", "hm_plan_execute",
     "hm_plan_hmatrix", "hm_plan_free", "hm_uniform_graph", "hm_matvec_op",
     "hm_hmatrix_blackbox", "hm_product_blackbox", "hm_blackbox_free", "hm_mfma_rate",
+    "hm_matvec_static",
 ]
 
 
@@ -147,6 +148,7 @@ def _load():
         "hm_hmatrix_free": [P],
         "hm_matvec": [P, I64, I, P, I64, P, I64, I, P],
         "hm_matvec_op": [P, I, I64, I, P, I64, P, I64, I, P],
+        "hm_matvec_static": [P, I, I64, I, P, I64, P, I64, I, P],
         "hm_hmatrix_blackbox": [P, I, C.POINTER(BlackBox)],
         "hm_product_blackbox": [C.POINTER(BlackBox), C.POINTER(BlackBox), C.POINTER(BlackBox)],
         "hm_blackbox_free": [C.POINTER(BlackBox)],
@@ -500,6 +502,16 @@ class HMatrix:
             raise ValueError("X and Y shapes/dtypes differ")
         _check(_lib.hm_matvec_op(self.h, 1 if trans else 0, nc, dt, px, ldx, py, ldy, order,
                                  _stream(stream)))
+
+    def matvec_static(self, X, Y, order=HM_ORDER_ORIGINAL, stream=None, trans=False):
+        """hm_matvec_static: matvec with the library's static device scratch
+        (no allocation; calls on one device must not overlap)."""
+        px, ldx, nc, dt = _colmajor(X, "X")
+        py, ldy, nc2, dt2 = _colmajor(Y, "Y")
+        if nc != nc2 or dt != dt2:
+            raise ValueError("X and Y shapes/dtypes differ")
+        _check(_lib.hm_matvec_static(self.h, 1 if trans else 0, nc, dt, px, ldx, py, ldy, order,
+                                     _stream(stream)))
 
     def blackbox(self, order=HM_ORDER_ORIGINAL):
         """This operator as a black box (hm_hmatrix_blackbox); keeps self alive."""

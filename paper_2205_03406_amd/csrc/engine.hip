@@ -613,7 +613,7 @@ void apply_levels(const hm_hmatrix &H, size_t li_end, bool trans, bool f32, cons
   int64_t cw = tcap / (nslots * H.kmax);
   if (cw < 1) throw Error{HM_E_NOMEM, "low-rank scratch too small"};
   cw = std::min<int64_t>(cw, ncols);
-  if (cw < ncols) cw = std::max<int64_t>(64, cw / 64 * 64);
+  if (cw < ncols && cw >= 64) cw = cw / 64 * 64;
   for (int64_t c0 = 0; c0 < ncols; c0 += cw) {
     const int64_t w = std::min(cw, ncols - c0);
     const int64_t tstride = (int64_t)H.kmax * w;
@@ -743,6 +743,67 @@ void matvec_impl(const hm_hmatrix &H, bool trans, int64_t nrhs, bool f32, const 
     HIP_TRY(hipFreeAsync(yt, s));
   }
   HIP_TRY(hipFreeAsync(Tb, s));
+}
+
+// Y = H X or H* X (rows in `order`) with every scratch buffer carved out of
+// buf (cap bytes, 256-aligned): the columns go through in blocks sized so
+// that the block's order-conversion copies and the apply's expansions fit.
+// Every byte of buf that a block reads is written earlier in that block.
+void matvec_in(const hm_hmatrix &H, bool trans, int64_t nrhs, bool f32, const void *X,
+               int64_t ldx, void *Y, int64_t ldy, int order, unsigned char *buf, size_t cap,
+               hipStream_t s) {
+  const size_t es = f32 ? 4 : 8;
+  const int64_t n = H.n;
+  const bool orig = order != HM_ORDER_TREE;
+  const bool h2 = H.format == HM_FORMAT_H2 && H.h2a.ready;
+  const int64_t nslots = std::max<int64_t>(
+      H.oA.slots_upto.empty() ? 0 : H.oA.slots_upto.back(),
+      H.oT.slots_upto.empty() ? 0 : H.oT.slots_upto.back());
+  const size_t stage = orig ? (size_t)n * es : 0;  // per column, each of the two copies
+  const size_t work = h2 ? (size_t)(2 * H.nvtot + H.h2a.nchunk) * H.kmax * 8
+                         : (size_t)std::max<int64_t>(nslots, 1) * H.kmax * es;
+  auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t fixed = 8 * 256;  // alignment slack of the pieces
+  const size_t per_col = 2 * stage + work;
+  if (cap <= fixed || per_col > cap - fixed)
+    throw Error{HM_E_ARG, "hm_matvec_static: one right-hand side needs " +
+                              std::to_string(per_col + fixed) + " bytes of scratch, the static "
+                              "scratch holds " + std::to_string(cap)};
+  const int64_t cw = std::min<int64_t>(nrhs, (int64_t)((cap - fixed) / per_col));
+  unsigned char *xt = buf, *yt = xt + up(stage * cw), *wk = yt + up(stage * cw);
+  for (int64_t c0 = 0; c0 < nrhs; c0 += cw) {
+    const int64_t w = std::min(cw, nrhs - c0);
+    const void *Xc = (const char *)X + c0 * ldx * es;
+    void *Yc = (char *)Y + c0 * ldy * es;
+    const void *Xt = Xc;
+    void *Yt = Yc;
+    int64_t ldxt = ldx, ldyt = ldy;
+    if (orig) {
+      launch_permute_rows(n, w, H.perm.as<int64_t>(), false, f32, Xc, ldx, xt, n, s);
+      Xt = xt;
+      Yt = yt;
+      ldxt = ldyt = n;
+    }
+    if (!H.near_covers) launch_fill_cols(Yt, n, w, ldyt, f32, s);
+    launch_near_apply(H.nnch, (trans ? H.nchunksT : H.nchunks).as<ExpandChunk>(),
+                      (trans ? H.nentriesT : H.nentries).as<NearEntry>(), f32, H.D.p, Xt, ldxt,
+                      w, Yt, ldyt, H.near_covers, s);
+    LAUNCH_CHECK();
+    if (h2) {
+      double *qh = (double *)wk;
+      double *uh = (double *)(wk + up((size_t)H.nvtot * H.kmax * w * 8));
+      double *pt = (double *)((unsigned char *)uh + up((size_t)H.nvtot * H.kmax * w * 8));
+      h2_apply(H, H.lv.size(), trans, f32, Xt, ldxt, w, Yt, ldyt, 1.0, qh, uh, pt, w, s);
+    } else {
+      apply_levels(H, H.lv.size(), trans, f32, Xt, ldxt, w, Yt, ldyt, 1.0, wk,
+                   std::max<int64_t>(nslots, 1) * H.kmax * w, s);
+    }
+    LAUNCH_CHECK();
+    if (orig) {
+      launch_permute_rows(n, w, H.perm.as<int64_t>(), true, f32, yt, n, Yc, ldy, s);
+      LAUNCH_CHECK();
+    }
+  }
 }
 
 // ------------------------------------------------------------------ operator black boxes
@@ -2891,6 +2952,50 @@ hm_status hm_matvec_op(const hm_hmatrix *H, int trans, int64_t nrhs, int dtype, 
   if (dtype != HM_F64 && dtype != HM_F32) return fail(HM_E_ARG, "bad dtype");
   if (nrhs == 0) return HM_OK;
   matvec_impl(*H, trans != 0, nrhs, dtype == HM_F32, X, ldx, Y, ldy, order, (hipStream_t)stream);
+  return HM_OK;
+  API_END
+}
+
+// Scratch of hm_matvec_static, for callers that cannot allocate: a static
+// device array, one copy per device from the code object's load until the
+// process ends.  Host code reaches it only through the address
+// hipGetSymbolAddress returns on each device (static_scratch_address).
+static __device__ __align__(256) unsigned char scratch[HM_STATIC_SCRATCH_BYTES];
+
+// The device address of `scratch` on the current device, looked up on the
+// first call on that device (with it current) and kept.
+static unsigned char *static_scratch_address() {
+  static std::mutex mu;
+  static unsigned char *addr[64] = {};
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+    (void)hipGetLastError();
+    throw hm::Error{HM_E_DEVICE, "hm_matvec_static: no current device (or device id >= 64)"};
+  }
+  std::lock_guard<std::mutex> lk(mu);
+  if (!addr[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      throw hm::Error{HM_E_DEVICE, std::string("hm_matvec_static: hipGetSymbolAddress: ") +
+                                       hipGetErrorString(e)};
+    }
+    addr[dev] = (unsigned char *)p;
+  }
+  return addr[dev];
+}
+
+hm_status hm_matvec_static(const hm_hmatrix *H, int trans, int64_t nrhs, int dtype, const void *X,
+                           int64_t ldx, void *Y, int64_t ldy, int order, void *stream) {
+  API_BEGIN
+  if (!H || !X || !Y || nrhs < 0 || ldx < H->n || ldy < H->n)
+    return fail(HM_E_ARG, "hm_matvec_static: bad argument");
+  if (dtype != HM_F64 && dtype != HM_F32) return fail(HM_E_ARG, "bad dtype");
+  if (nrhs == 0) return HM_OK;
+  unsigned char *buf = static_scratch_address();
+  matvec_in(*H, trans != 0, nrhs, dtype == HM_F32, X, ldx, Y, ldy, order, buf,
+            HM_STATIC_SCRATCH_BYTES, (hipStream_t)stream);
   return HM_OK;
   API_END
 }
