@@ -401,6 +401,10 @@ def _serve_once(hm, trace, xs, mixed, nslots, rate_scale):
     while got < len(res):
         got += len(srv.poll(wait_ms=1000))
     kinds, lat = {}, {"compress": [], "matvec": []}
+    # matvec latency split: waiting (submit -> start on the device stream:
+    # admission, a free worker, memory) and running (start -> end: staging,
+    # the apply and the copies back, sharing the device with the rest)
+    split = {"wait": [], "run": []}
     pending = 0
     t0 = srv.info()["now"]
     i = 0
@@ -415,6 +419,9 @@ def _serve_once(hm, trace, xs, mixed, nslots, rate_scale):
             lat[k].append(c["t_end"] - c["t_submit"])
             if k == "compress":
                 srv.release(c["hmatrix"])
+            else:
+                split["wait"].append(c["t_start"] - c["t_submit"])
+                split["run"].append(c["t_end"] - c["t_start"])
             pending -= 1
 
     while i < len(trace):
@@ -437,7 +444,7 @@ def _serve_once(hm, trace, xs, mixed, nslots, rate_scale):
         collect(1000)
     t_end = srv.info()["now"]
     srv.close()
-    return lat, t_end - t0, fails
+    return lat, t_end - t0, fails, split
 
 
 def run_served(hm, count, loads):
@@ -458,15 +465,15 @@ def run_served(hm, count, loads):
     # (this pass also settles the kernel-apply autotuner on the trace's
     # FP64 shapes; a back-to-back pass of the mixed form does the same for
     # its shapes, so neither timed run pays first-use tuning)
-    _, makespan, _ = _serve_once(hm, trace, xs, False, 1, 0.0)
+    _, makespan, _, _ = _serve_once(hm, trace, xs, False, 1, 0.0)
     capacity = count / makespan
     _progress("served mix: FP64 back-to-back pass %.1f s (%.2f requests/s)" % (makespan, capacity))
-    _, span, _ = _serve_once(hm, trace, xs, True, 4, 0.0)
+    _, span, _, _ = _serve_once(hm, trace, xs, True, 4, 0.0)
     _progress("served mix: mixed back-to-back pass %.1f s" % span)
     out = {"requests": count, "compress_share": round(sum(q.kind == "compress" for q in trace) / count, 3),
            "fp64_capacity_req_per_s": round(capacity, 3), "loads": {}}
 
-    def summary(lat, span, fails):
+    def summary(lat, span, fails, split):
         allv = np.array(lat["compress"] + lat["matvec"]) * 1e3
         d = {"throughput_req_per_s": round(count / span, 3), "failed": fails,
              "p50_ms": round(float(np.percentile(allv, 50)), 3),
@@ -475,6 +482,10 @@ def run_served(hm, count, loads):
             v = np.array(lat[k]) * 1e3
             d[k] = {"n": len(v), "p50_ms": round(float(np.percentile(v, 50)), 3),
                     "p99_ms": round(float(np.percentile(v, 99)), 3)}
+        for k in ("wait", "run"):
+            v = np.array(split[k]) * 1e3
+            d["matvec"][k + "_p50_ms"] = round(float(np.percentile(v, 50)), 3)
+            d["matvec"][k + "_p99_ms"] = round(float(np.percentile(v, 99)), 3)
         return d
 
     for load in loads:

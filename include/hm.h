@@ -241,6 +241,23 @@ hm_status hm_hmatrix_blackbox(const hm_hmatrix *H, int order, hm_blackbox *out);
 hm_status hm_product_blackbox(const hm_blackbox *A, const hm_blackbox *B, hm_blackbox *out);
 void hm_blackbox_free(hm_blackbox *bb);
 
+/* ------------------------------------------------------------------ device memory
+ * hm_allocator: a caller's device allocator (for instance the PyTorch
+ * caching allocator), so that the caller owns every device block the
+ * library uses.  alloc returns a block of at least `bytes` bytes on the
+ * current device for work ordered on `stream` (a hipStream_t; NULL = the
+ * null stream), or NULL when it cannot (the call then fails with
+ * HM_E_NOMEM); free takes back a block alloc returned, with the stream it
+ * was used on.  The library frees a block only once the work that used it
+ * is complete or ordered on that stream (stream-ordered scratch).  Both
+ * functions may be called from any thread the library runs on (the
+ * server's workers included). */
+typedef struct {
+  void *ctx;
+  void *(*alloc)(void *ctx, size_t bytes, void *stream);
+  void (*free)(void *ctx, void *p, void *stream);
+} hm_allocator;
+
 /* ------------------------------------------------------------------ compression
  * hm_compress: alg:h1_pseudocode.  For each sampled level (coarsest first):
  * draw the colored Gaussian test matrices Omega, Psi (one N x r block per
@@ -282,6 +299,18 @@ typedef struct {
   int32_t max_retries; /* tolerance mode: recompress with r + 8 (at most 64) while
                           some block reaches the cap, at most this many times */
   int32_t format;      /* HM_FORMAT_H1, HM_FORMAT_UNIFORM_H1 or HM_FORMAT_H2 (below) */
+  const hm_allocator *allocator; /* NULL: the library allocates (hipMalloc, a block
+                          cache of idle H-matrix blocks, hipMallocAsync scratch).
+                          Else every device block of the call goes through it: the
+                          compression's scratch, the H-matrix (which keeps a copy
+                          of the struct, frees its blocks through it in
+                          hm_hmatrix_free and takes its applies' scratch from it),
+                          and the tree's device copy when this call makes it (the
+                          first call that needs it makes it: a compression, with
+                          its allocator, or hm_kernel_blackbox, hm_kernel_apply,
+                          hm_test_matrix with the library's own; hm_tree_free
+                          frees it there).  ctx must stay valid until all of
+                          those are freed. */
 } hm_compress_opts;
 #define HM_FLAG_TIMING 1
 #define HM_FLAG_STRICT 2
@@ -357,12 +386,16 @@ hm_status hm_plan_execute(hm_plan *plan, void *stream);
 hm_status hm_plan_hmatrix(const hm_plan *plan, const hm_hmatrix **H, int64_t *graph_nodes);
 void hm_plan_free(hm_plan *plan);
 
-/* hm_matvec: Y = H X (the H^1 apply: all admissible blocks U B V* plus the
- * leaf neighbor blocks; an H^2 matrix applies through its nested form,
- * alg:apply_h2_level_truncated: outgoing expansions, upward pass through the
- * transfers, couplings and downward pass, expansion).  X, Y device,
- * n x nrhs, dtype HM_F64 or HM_F32, rows in `order`.  Enqueued on stream;
- * scratch from the stream-ordered allocator. */
+/* hm_matvec: Y = H X, the apply of the H^1 representation (section on
+ * rank-structured matrices: Y = sum over levels and admissible pairs of
+ * U B V* X(I_b) plus the leaf neighbor blocks A(I_a, I_b) X(I_b); an H^2
+ * matrix applies through its nested form, alg:apply_h2_level_truncated:
+ * outgoing expansions, upward pass through the transfers, couplings and
+ * downward pass, expansion).  X, Y device, n x nrhs column-major (ldx, ldy
+ * >= n), dtype HM_F64 or HM_F32, rows in `order`; the caller owns both.
+ * Enqueued on stream; scratch stream-ordered (through the H-matrix's
+ * allocator when it was made with one).  HM_E_ARG for bad arguments,
+ * HM_E_NOMEM when scratch cannot be had. */
 hm_status hm_matvec(const hm_hmatrix *H, int64_t nrhs, int dtype, const void *X, int64_t ldx,
                     void *Y, int64_t ldy, int order, void *stream);
 /* hm_matvec_op: hm_matvec (trans = 0) or the adjoint Y = H* X (trans = 1:
@@ -472,6 +505,8 @@ typedef struct {
   int64_t hbm_budget;     /* device bytes for residents + work in flight (<= 0: 90% of free) */
   int32_t nslots;         /* requests on the GPU at once, 1..64 */
   int32_t compress_slots; /* of which compressions, at most (<= 0: 1) */
+  const hm_allocator *allocator; /* NULL, or the allocator of every device block of
+                          every request (copied; ctx must outlive the server) */
 } hm_server_opts;
 
 typedef struct {

@@ -63,6 +63,12 @@ typedef struct {
 
 /* ---------------------------------------------------------------- sort */
 typedef struct { uint64_t key; int64_t idx; } kv_t;
+/* memcpy of n bytes; nothing for n = 0 (the source of an empty array may be
+ * a null pointer, which memcpy does not accept even for no bytes) */
+static void copy_bytes(void *dst, const void *src, size_t n) {
+  if (n) memcpy(dst, src, n);
+}
+
 static int kv_cmp(const void *a, const void *b) {
   const kv_t *x = (const kv_t *)a, *y = (const kv_t *)b;
   if (x->key < y->key) return -1;
@@ -128,7 +134,7 @@ static void push_level(otree *T, lvl_t *L, int64_t n) {
   int nb = (int)L->start.n;
   T->nbox[l] = nb;
   T->start[l] = (int64_t *)malloc((nb + 1) * sizeof(int64_t));
-  memcpy(T->start[l], L->start.v, nb * sizeof(int64_t));
+  copy_bytes(T->start[l], L->start.v, nb * sizeof(int64_t));
   T->start[l][nb] = n;
   T->parent[l] = L->parent.v; L->parent.v = NULL;
   T->org[l] = L->org.v; L->org.v = NULL;
@@ -359,7 +365,7 @@ static void finish_graph(ograph *G, vtab *V, int nboxes) {
   G->xadj[0] = 0;
   vec32 adj = {0};
   for (int u = 0; u < G->nv; ++u) {
-    qsort(nb[u].v, nb[u].n, sizeof(int), int_cmp);
+    if (nb[u].n > 1) qsort(nb[u].v, nb[u].n, sizeof(int), int_cmp);
     for (int64_t t = 0; t < nb[u].n; ++t)
       if (t == 0 || nb[u].v[t] != nb[u].v[t - 1]) v32_push(&adj, nb[u].v[t]);
     G->xadj[u + 1] = adj.n;
@@ -481,13 +487,13 @@ void *orc_build(const double *pts, int64_t n, int dim, int leaf, int index_binar
 
 int orc_nlev(void *t) { return ((otree *)t)->nlev; }
 int orc_nbox(void *t, int l) { return ((otree *)t)->nbox[l]; }
-void orc_perm(void *t, int64_t *out) { otree *T = (otree *)t; memcpy(out, T->perm, T->n * sizeof(int64_t)); }
+void orc_perm(void *t, int64_t *out) { otree *T = (otree *)t; copy_bytes(out, T->perm, T->n * sizeof(int64_t)); }
 void orc_boxes(void *t, int l, int64_t *start, int *parent, int64_t *org, int *blev) {
   otree *T = (otree *)t; int nb = T->nbox[l];
-  memcpy(start, T->start[l], (nb + 1) * sizeof(int64_t));
-  memcpy(parent, T->parent[l], nb * sizeof(int));
-  memcpy(org, T->org[l], (size_t)nb * T->os * sizeof(int64_t));
-  memcpy(blev, T->blev[l], nb * sizeof(int));
+  copy_bytes(start, T->start[l], (nb + 1) * sizeof(int64_t));
+  copy_bytes(parent, T->parent[l], nb * sizeof(int));
+  copy_bytes(org, T->org[l], (size_t)nb * T->os * sizeof(int64_t));
+  copy_bytes(blev, T->blev[l], nb * sizeof(int));
 }
 int orc_list_len(void *t, int l, int which) {
   otree *T = (otree *)t; int nb = T->nbox[l];
@@ -497,8 +503,8 @@ void orc_list(void *t, int l, int which, int *ptr, int *idx) {
   otree *T = (otree *)t; int nb = T->nbox[l];
   int *p = which == 0 ? T->nei_ptr[l] : T->int_ptr[l];
   int *x = which == 0 ? T->nei[l] : T->intl[l];
-  memcpy(ptr, p, (nb + 1) * sizeof(int));
-  memcpy(idx, x, p[nb] * sizeof(int));
+  copy_bytes(ptr, p, (nb + 1) * sizeof(int));
+  copy_bytes(idx, x, p[nb] * sizeof(int));
 }
 /* g = level for the admissible graph of that level, g = nlev for the leaf graph */
 void orc_graph_sizes(void *t, int g, int *nv, int64_t *nadj, int *nset, int *npairs) {
@@ -508,14 +514,14 @@ void orc_graph_sizes(void *t, int g, int *nv, int64_t *nadj, int *nset, int *npa
 void orc_graph(void *t, int g, int *vbox, int *vset_ptr, int *vset, int64_t *xadj, int *adj,
                int *pair_a, int *pair_b, int *pair_v) {
   ograph *G = &((otree *)t)->graphs[g];
-  memcpy(vbox, G->vbox, G->nv * sizeof(int));
-  memcpy(vset_ptr, G->vset_ptr, (G->nv + 1) * sizeof(int));
-  memcpy(vset, G->vset, G->vset_ptr[G->nv] * sizeof(int));
-  memcpy(xadj, G->xadj, (G->nv + 1) * sizeof(int64_t));
-  memcpy(adj, G->adj, G->xadj[G->nv] * sizeof(int));
-  memcpy(pair_a, G->pair_a, G->npairs * sizeof(int));
-  memcpy(pair_b, G->pair_b, G->npairs * sizeof(int));
-  memcpy(pair_v, G->pair_v, G->npairs * sizeof(int));
+  copy_bytes(vbox, G->vbox, G->nv * sizeof(int));
+  copy_bytes(vset_ptr, G->vset_ptr, (G->nv + 1) * sizeof(int));
+  copy_bytes(vset, G->vset, G->vset_ptr[G->nv] * sizeof(int));
+  copy_bytes(xadj, G->xadj, (G->nv + 1) * sizeof(int64_t));
+  copy_bytes(adj, G->adj, G->xadj[G->nv] * sizeof(int));
+  copy_bytes(pair_a, G->pair_a, G->npairs * sizeof(int));
+  copy_bytes(pair_b, G->pair_b, G->npairs * sizeof(int));
+  copy_bytes(pair_v, G->pair_v, G->npairs * sizeof(int));
 }
 void orc_free(void *t) {
   otree *T = (otree *)t;

@@ -68,10 +68,86 @@ class BlackBox(C.Structure):
                 ("symmetric", C.c_int32), ("dtypes", C.c_int32)]
 
 
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
+class Allocator(C.Structure):
+    """hm_allocator: the caller's device allocator."""
+    _fields_ = [("ctx", C.c_void_p), ("alloc", ALLOC_FN), ("free", FREE_FN)]
+
+
+class TorchAllocator:
+    """An hm_allocator over PyTorch's caching allocator
+    (torch.cuda.caching_allocator_alloc / caching_allocator_delete), so that
+    the library's device blocks belong to torch (they show in
+    torch.cuda.memory_allocated()).  `allocs`, `frees` and `live` (pointer ->
+    bytes) count the blocks taken and returned.  The object must outlive
+    every H-matrix, plan, tree and server that uses it."""
+
+    def __init__(self):
+        import threading
+        import torch
+        self.allocs = 0
+        self.frees = 0
+        self.live = {}
+        self._lock = threading.Lock()
+
+        def _alloc(ctx, nbytes, stream):
+            try:
+                p = torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0))
+            except Exception:
+                return None
+            with self._lock:
+                self.allocs += 1
+                self.live[p] = int(nbytes)
+            return p
+
+        def _free(ctx, p, stream):
+            with self._lock:
+                self.frees += 1
+                self.live.pop(p, None)
+            try:
+                torch.cuda.caching_allocator_delete(p)
+            except Exception:
+                pass  # interpreter shutdown: the process is ending
+
+        self._fa = ALLOC_FN(_alloc)
+        self._ff = FREE_FN(_free)
+        self.struct = Allocator(None, self._fa, self._ff)
+
+    def live_bytes(self):
+        with self._lock:
+            return sum(self.live.values())
+
+
+_TORCH_ALLOC = None
+
+
+def torch_allocator():
+    """The process-wide TorchAllocator (made on first use)."""
+    global _TORCH_ALLOC
+    if _TORCH_ALLOC is None:
+        _TORCH_ALLOC = TorchAllocator()
+    return _TORCH_ALLOC
+
+
+def _allocator(a):
+    """allocator argument -> (TorchAllocator or None, pointer for the opts)."""
+    if a is None:
+        return None, None
+    if isinstance(a, str):
+        if a != "torch":
+            raise ValueError("allocator must be None, 'torch' or a TorchAllocator")
+        a = torch_allocator()
+    return a, C.pointer(a.struct)
+
+
 class Opts(C.Structure):
     _fields_ = [("rank", C.c_int32), ("tol", C.c_double), ("oversample", C.c_int32),
                 ("r", C.c_int32), ("prec", C.c_int32), ("flags", C.c_int32),
-                ("seed", C.c_uint64), ("max_retries", C.c_int32), ("format", C.c_int32)]
+                ("seed", C.c_uint64), ("max_retries", C.c_int32), ("format", C.c_int32),
+                ("allocator", C.POINTER(Allocator))]
 
 
 class Stats(C.Structure):
@@ -98,7 +174,7 @@ class Stats(C.Structure):
 
 class ServerOpts(C.Structure):
     _fields_ = [("hbm_budget", C.c_int64), ("nslots", C.c_int32),
-                ("compress_slots", C.c_int32)]
+                ("compress_slots", C.c_int32), ("allocator", C.POINTER(Allocator))]
 
 
 class Completion(C.Structure):
@@ -278,6 +354,7 @@ class Tree:
         self.nlev = nl.value
         self.L = self.nlev - 1
         self._bbs = []
+        self._allocs = []  # allocators whose blocks the tree's device copy may hold
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:
@@ -392,15 +469,18 @@ class Plan:
     by execute(); hmatrix() borrows the latest result."""
 
     def __init__(self, tree, bb, rank=0, tol=0.0, r=0, p=10, prec=HM_PREC_F64, seed=0,
-                 stream=None, uniform=False, h2=False):
+                 stream=None, uniform=False, h2=False, allocator="torch"):
+        al, ap = _allocator(allocator)
         o = Opts(rank=rank, tol=tol, oversample=p, r=r, prec=prec, flags=0, seed=seed,
-                 max_retries=0, format=_format(uniform, h2))
+                 max_retries=0, format=_format(uniform, h2), allocator=ap)
         h = C.c_void_p()
         _check(_lib.hm_compress_plan(tree.h, C.byref(bb), C.byref(o), _stream(stream),
                                      C.byref(h)))
         self.h = h
         self.tree = tree
         self._bb = bb
+        self._alloc = al
+        tree._allocs.append(al)
 
     def execute(self, stream=None):
         _check(_lib.hm_plan_execute(self.h, _stream(stream)))
@@ -581,11 +661,14 @@ class Server:
     id.  Apply inputs and outputs are host arrays (n, nrhs); the output array
     of each apply is kept here until its completion is polled."""
 
-    def __init__(self, nslots=4, hbm_budget=0, compress_slots=1):
-        o = ServerOpts(hbm_budget=hbm_budget, nslots=nslots, compress_slots=compress_slots)
+    def __init__(self, nslots=4, hbm_budget=0, compress_slots=1, allocator=None):
+        al, ap = _allocator(allocator)
+        o = ServerOpts(hbm_budget=hbm_budget, nslots=nslots, compress_slots=compress_slots,
+                       allocator=ap)
         h = C.c_void_p()
         _check(_lib.hm_server_create(C.byref(o), C.byref(h)))
         self.h = h
+        self._alloc = al
         self._out = {}
         self._n = {}
 
@@ -674,13 +757,19 @@ def _flags(timing, strict, combine):
 
 def compress(tree: Tree, bb: BlackBox, rank=0, tol=0.0, r=0, p=10, prec=HM_PREC_F64, seed=0,
              timing=False, stream=None, max_retries=0, strict=False, uniform=False,
-             h2=False, combine="sum") -> HMatrix:
+             h2=False, combine="sum", allocator="torch") -> HMatrix:
     """hm_compress; uniform=True selects the uniform H^1 format, h2=True the
     H^2 format; combine="gaussian" sets HM_FLAG_MIX_GAMMA (their row bases
-    from the Gaussian-weighted combination instead of the plain sum)."""
+    from the Gaussian-weighted combination instead of the plain sum).
+    allocator: "torch" (the default: every device block from PyTorch's
+    caching allocator), a TorchAllocator, or None (the library's own)."""
+    al, ap = _allocator(allocator)
     o = Opts(rank=rank, tol=tol, oversample=p, r=r, prec=prec,
              flags=_flags(timing, strict, combine),
-             seed=seed, max_retries=max_retries, format=_format(uniform, h2))
+             seed=seed, max_retries=max_retries, format=_format(uniform, h2), allocator=ap)
     h = C.c_void_p()
     _check(_lib.hm_compress(tree.h, C.byref(bb), C.byref(o), _stream(stream), C.byref(h)))
-    return HMatrix(h, tree)
+    tree._allocs.append(al)
+    H = HMatrix(h, tree)
+    H._alloc = al
+    return H

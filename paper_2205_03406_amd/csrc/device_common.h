@@ -65,5 +65,20 @@ __device__ __forceinline__ void normal_pair(U4 r, double &z0, double &z1) {
   z1 = rad * s;
 }
 
+// The work item of this workgroup in a 1-D grid of nitems x ntiles
+// workgroups.  The dispatcher sends linear workgroup ids round robin to the
+// 8 XCDs, each with its own L2; the ids are remapped so that the workgroups
+// of one XCD take a contiguous run of (tile, item) pairs, items fastest:
+// neighbouring items of one column tile (row chunks of one box, segments
+// and pair groups of one column box) then share that XCD's L2.
+__device__ __forceinline__ void xcd_item_tile(int64_t nitems, int64_t ntiles, int64_t &item,
+                                              int64_t &tile) {
+  const int64_t G = nitems * ntiles, b = blockIdx.x;
+  const int64_t q = G / 8, r = G % 8, x = b % 8;
+  const int64_t L = x * q + (x < r ? x : r) + b / 8;
+  tile = L / nitems;
+  item = L % nitems;
+}
+
 }  // namespace dev
 }  // namespace hm

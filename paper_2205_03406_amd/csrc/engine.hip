@@ -139,12 +139,67 @@ struct SyncedRelease {
   }
 };
 
+// The caller's allocator (hm_allocator) in force on this thread: set for
+// the duration of an entry point that was given one (AllocScope); every
+// device allocation made meanwhile goes through it.
+double &kapply_slice_flops() {
+  thread_local double f = 0.0;
+  return f;
+}
+
+const hm_allocator *&alloc_scope() {
+  thread_local const hm_allocator *a = nullptr;
+  return a;
+}
+void *scope_alloc(const hm_allocator &a, size_t b, hipStream_t s) {
+  void *p = a.alloc(a.ctx, b, (void *)s);
+  if (!p) throw Error{HM_E_NOMEM, "allocator returned no block for " + std::to_string(b) + " bytes"};
+  return p;
+}
+// stream-ordered scratch: the allocator in force, else hipMallocAsync
+void *stream_alloc(size_t b, hipStream_t s) {
+  if (b == 0) b = 64;
+  if (const hm_allocator *a = alloc_scope()) return scope_alloc(*a, b, s);
+  void *p = nullptr;
+  if (hipMallocAsync(&p, b, s) != hipSuccess) {
+    (void)hipGetLastError();
+    throw Error{HM_E_NOMEM, "device allocation of " + std::to_string(b) + " bytes failed"};
+  }
+  return p;
+}
+void stream_free(void *p, hipStream_t s) {
+  if (!p) return;
+  if (const hm_allocator *a = alloc_scope())
+    a->free(a->ctx, p, (void *)s);
+  else
+    (void)hipFreeAsync(p, s);
+}
+void *scratch_alloc(size_t bytes, void *stream) { return stream_alloc(bytes, (hipStream_t)stream); }
+void scratch_free(void *p, void *stream) { stream_free(p, (hipStream_t)stream); }
+// a stream-ordered block that goes back when it leaves scope (also on an
+// error); the allocator scope must enclose it
+struct StreamBlock {
+  void *p = nullptr;
+  hipStream_t s = nullptr;
+  StreamBlock() = default;
+  StreamBlock(size_t b, hipStream_t st) : s(st) { p = stream_alloc(b, st); }
+  StreamBlock(const StreamBlock &) = delete;
+  StreamBlock &operator=(const StreamBlock &) = delete;
+  void take(size_t b, hipStream_t st) {
+    s = st;
+    p = stream_alloc(b, st);
+  }
+  ~StreamBlock() { stream_free(p, s); }
+};
+
 // Device buffer.  alloc(): plain hipMalloc / hipFree, for objects that
 // outlive the call that makes them (trees).  cached(): the block cache above,
 // for the buffers of H-matrices.  temp(): stream-
 // ordered hipMallocAsync / hipFreeAsync on the stream of the work that uses
 // it, so the scratch of one compression is freed without waiting on work
-// that other streams (other requests) have in flight.
+// that other streams (other requests) have in flight.  With a caller's
+// allocator in force (alloc_scope) every form takes its block from it
+// instead and returns it there, after the same waits.
 struct DBuf {
   void *p = nullptr;
   size_t bytes = 0;
@@ -154,15 +209,17 @@ struct DBuf {
   bool stream_owned = false;  // returns once st is idle (else the device)
   size_t cap = 0;
   int dev = 0;
+  hm_allocator al{};  // the caller's allocator the block came from (al.free set)
   DBuf() = default;
   DBuf(const DBuf &) = delete;
   DBuf &operator=(const DBuf &) = delete;
   DBuf(DBuf &&o) noexcept
       : p(o.p), bytes(o.bytes), st(o.st), async(o.async), in_cache(o.in_cache),
-        stream_owned(o.stream_owned), cap(o.cap), dev(o.dev) {
+        stream_owned(o.stream_owned), cap(o.cap), dev(o.dev), al(o.al) {
     o.p = nullptr;
     o.bytes = 0;
     o.in_cache = false;
+    o.al = hm_allocator{};
   }
   DBuf &operator=(DBuf &&o) noexcept {
     release();
@@ -174,15 +231,31 @@ struct DBuf {
     stream_owned = o.stream_owned;
     cap = o.cap;
     dev = o.dev;
+    al = o.al;
     o.p = nullptr;
     o.bytes = 0;
     o.in_cache = false;
+    o.al = hm_allocator{};
     return *this;
   }
   ~DBuf() { release(); }
+  // a block from the allocator in force, if any
+  bool from_scope(size_t b, hipStream_t s) {
+    const hm_allocator *a = alloc_scope();
+    if (!a) return false;
+    p = scope_alloc(*a, b, s);
+    al = *a;
+    bytes = b;
+    st = s;
+    return true;
+  }
   void alloc(size_t b) {
     release();
     if (b == 0) b = 64;
+    if (from_scope(b, nullptr)) {
+      async = false;
+      return;
+    }
     if (hipMalloc(&p, b) != hipSuccess) {
       p = nullptr;
       (void)hipGetLastError();
@@ -202,6 +275,10 @@ struct DBuf {
     release();
     if (b == 0) b = 64;
     b = (b + 255) / 256 * 256;
+    if (from_scope(b, nullptr)) {
+      async = false;
+      return;
+    }
     if (hipGetDevice(&dev) != hipSuccess) {
       (void)hipGetLastError();
       throw Error{HM_E_DEVICE, "hipGetDevice failed"};
@@ -232,6 +309,10 @@ struct DBuf {
   void temp(size_t b, hipStream_t s) {
     release();
     if (b == 0) b = 64;
+    if (from_scope(b, s)) {
+      async = true;
+      return;
+    }
     if (hipMallocAsync(&p, b, s) != hipSuccess) {
       p = nullptr;
       (void)hipGetLastError();
@@ -242,7 +323,14 @@ struct DBuf {
     async = true;
   }
   void release() {
-    if (p && in_cache) {
+    if (p && al.free) {
+      // stream-ordered scratch goes back at once (the allocator orders its
+      // reuse on that stream); other blocks once their work is done
+      if (!async && !release_synced())
+        (void)(stream_owned ? hipStreamSynchronize(st) : hipDeviceSynchronize());
+      al.free(al.ctx, p, (void *)st);
+      al = hm_allocator{};
+    } else if (p && in_cache) {
       if (!release_synced()) (void)(stream_owned ? hipStreamSynchronize(st) : hipDeviceSynchronize());
       cache_put(dev, p, cap);
     } else if (p) {
@@ -348,21 +436,38 @@ struct KernelBB {
 };
 
 // Y = K X in tree order; block-diagonal over the instances of a forest.
+// With a slice budget on this thread (kapply_slice_flops) a whole-operator
+// apply runs as consecutive launches of row blocks, each about that many
+// flops.
 void kernel_apply_tree(const Tree &T, int kernel, int64_t ncols, bool f32, const void *X,
                        int64_t ldx, void *Y, int64_t ldy, hipStream_t s) {
   const DeviceTree &D = *T.dev;
   const bool forest = T.ninst() > 1;
   const int64_t units = forest ? D.nkitems : (T.n + 63) / 64;
+  const double slice = kapply_slice_flops();
   autotune_kapply(KapplyShape{f32, kernel, T.dim, ncols, T.n, forest, units},
                   [&](int nt, int64_t part) {
-                    if (forest)
+                    if (forest) {
                       launch_kapply_forest(kernel, T.dim, T.n, D.pts.as<double>(),
                                            part > 0 ? (int32_t)part : D.nkitems,
                                            D.kitems.as<KItem>(), ncols, -1, nt, f32, X, ldx, Y,
                                            ldy, s);
-                    else
+                    } else if (part > 0 || !(slice > 0)) {
                       launch_kapply(kernel, T.dim, T.n, D.pts.as<double>(), ncols, nt, f32, X,
                                     ldx, Y, ldy, s, part * 64);
+                    } else {
+                      // about `slice` flops per launch, and at least 1024
+                      // workgroups (4 per CU) so that a slice fills the device
+                      const double per_blk = 2.0 * (double)T.n * 64.0 * (double)ncols;
+                      const int ntw = nt > 0 ? nt : kapply_default_nt(ncols, f32, units);
+                      const int64_t nct = (ncols + 16 * ntw - 1) / (16 * ntw);
+                      const int64_t blks = std::max<int64_t>(
+                          {(int64_t)1, (int64_t)(slice / std::max(per_blk, 1.0)),
+                           (1024 + nct - 1) / std::max<int64_t>(nct, 1)});
+                      for (int64_t b = 0; b < units; b += blks)
+                        launch_kapply(kernel, T.dim, T.n, D.pts.as<double>(), ncols, nt, f32, X,
+                                      ldx, Y, ldy, s, blks * 64, b * 64);
+                    }
                   },
                   s);
 }
@@ -395,6 +500,7 @@ int dense_bb_apply(void *ctx, int transpose, int64_t n, int64_t ncols, int dtype
 // ------------------------------------------------------------------ the H-matrix
 struct hm_hmatrix {
   hm::SyncedRelease rel;  // first: destroyed last
+  hm_allocator al{};      // the caller's allocator its blocks came from (and its applies' scratch)
   struct Lv {
     int level = 0;
     int64_t np = 0;   // pairs
@@ -630,13 +736,19 @@ void apply_levels(const hm_hmatrix &H, size_t li_end, bool trans, bool f32, cons
   }
 }
 
+// Partial projections of the low-rank products: every slot at full width,
+// capped at 1 G elements (8 GB in FP64).  The products run over the columns
+// in chunks of cap / (slots kmax), and every chunk reads the coarser levels'
+// factors again, so a wide sample (thousands of columns) wants few chunks;
+// the device holds 288 GB.
+constexpr int64_t kTScratchCap = int64_t(1) << 30;
+
 int64_t tscratch_elems(const hm_hmatrix &H, int64_t ncols) {
-  // every partial slot at full width, capped at 64 M elements
   const int64_t slots = std::max<int32_t>(
       H.oA.slots_upto.empty() ? 0 : H.oA.slots_upto.back(),
       H.oT.slots_upto.empty() ? 0 : H.oT.slots_upto.back());
   int64_t need = slots * H.kmax * std::max<int64_t>(ncols, 1);
-  int64_t cap = int64_t(64) << 20;
+  int64_t cap = kTScratchCap;
   int64_t minimum = slots * H.kmax * 64;
   return std::max<int64_t>(std::min(need, cap), std::max<int64_t>(minimum, 64));
 }
@@ -674,11 +786,14 @@ void h2_apply(const hm_hmatrix &H, size_t le, bool trans, bool f32, const void *
   const int64_t cw = own ? std::min<int64_t>(ncols, 256) : std::min<int64_t>(ncols, qcols);
   if (cw < 1) throw Error{HM_E_NOMEM, "H2 expansion scratch too small"};
   double *QH = qh, *UH = uh, *PT = part;
+  StreamBlock oq, ou, op;
   if (own) {
-    HIP_TRY(hipMallocAsync((void **)&QH, (size_t)std::max<int64_t>(nb * kmax * cw, 1) * 8, s));
-    HIP_TRY(hipMallocAsync((void **)&UH, (size_t)std::max<int64_t>(nb * kmax * cw, 1) * 8, s));
-    HIP_TRY(hipMallocAsync((void **)&PT,
-                           (size_t)std::max<int64_t>((int64_t)nchunk * kmax * cw, 1) * 8, s));
+    oq.take((size_t)std::max<int64_t>(nb * kmax * cw, 1) * 8, s);
+    ou.take((size_t)std::max<int64_t>(nb * kmax * cw, 1) * 8, s);
+    op.take((size_t)std::max<int64_t>((int64_t)nchunk * kmax * cw, 1) * 8, s);
+    QH = (double *)oq.p;
+    UH = (double *)ou.p;
+    PT = (double *)op.p;
   }
   for (int64_t c0 = 0; c0 < ncols; c0 += cw) {
     const int64_t w = std::min(cw, ncols - c0);
@@ -697,28 +812,29 @@ void h2_apply(const hm_hmatrix &H, size_t le, bool trans, bool f32, const void *
     launch_h2_expand(nchunk, chunk, kmax, ro, Bin, UH, w, f32, w, Yc, ldy, sign, s);
     LAUNCH_CHECK();
   }
-  if (own) {
-    HIP_TRY(hipFreeAsync(QH, s));
-    HIP_TRY(hipFreeAsync(UH, s));
-    HIP_TRY(hipFreeAsync(PT, s));
-  }
 }
 
 // Y = H X or H* X (rows in `order`); stream-ordered scratch.
 void matvec_impl(const hm_hmatrix &H, bool trans, int64_t nrhs, bool f32, const void *X,
                  int64_t ldx, void *Y, int64_t ldy, int order, hipStream_t s) {
+  // the H-matrix's allocator (if it was made with one) for the scratch
+  AllocScope scope(H.al.alloc ? &H.al : nullptr);
   const size_t es = f32 ? 4 : 8;
   const int64_t n = H.n;
-  const int64_t tcap = tscratch_elems(H, nrhs);
-  void *Tb = nullptr, *xt = nullptr, *yt = nullptr;
-  HIP_TRY(hipMallocAsync(&Tb, (size_t)tcap * es, s));
+  const bool h2 = H.format == HM_FORMAT_H2 && H.h2a.ready;
+  const int64_t tcap = h2 ? 0 : tscratch_elems(H, nrhs);
+  StreamBlock tb, xb, yb;
+  if (!h2) tb.take((size_t)tcap * es, s);
+  void *Tb = tb.p, *xt = nullptr, *yt = nullptr;
   const bool orig = order != HM_ORDER_TREE;
   const void *Xt = X;
   void *Yt = Y;
   int64_t ldxt = ldx, ldyt = ldy;
   if (orig) {
-    HIP_TRY(hipMallocAsync(&xt, (size_t)n * nrhs * es, s));
-    HIP_TRY(hipMallocAsync(&yt, (size_t)n * nrhs * es, s));
+    xb.take((size_t)n * nrhs * es, s);
+    yb.take((size_t)n * nrhs * es, s);
+    xt = xb.p;
+    yt = yb.p;
     launch_permute_rows(n, nrhs, H.perm.as<int64_t>(), false, f32, X, ldx, xt, n, s);
     Xt = xt;
     Yt = yt;
@@ -730,7 +846,7 @@ void matvec_impl(const hm_hmatrix &H, bool trans, int64_t nrhs, bool f32, const 
                     (trans ? H.nentriesT : H.nentries).as<NearEntry>(), f32, H.D.p, Xt, ldxt,
                     nrhs, Yt, ldyt, H.near_covers, s);
   LAUNCH_CHECK();
-  if (H.format == HM_FORMAT_H2 && H.h2a.ready)
+  if (h2)
     h2_apply(H, H.lv.size(), trans, f32, Xt, ldxt, nrhs, Yt, ldyt, 1.0, nullptr, nullptr, nullptr,
              0, s);
   else
@@ -739,10 +855,7 @@ void matvec_impl(const hm_hmatrix &H, bool trans, int64_t nrhs, bool f32, const 
   if (orig) {
     launch_permute_rows(n, nrhs, H.perm.as<int64_t>(), true, f32, yt, n, Y, ldy, s);
     LAUNCH_CHECK();
-    HIP_TRY(hipFreeAsync(xt, s));
-    HIP_TRY(hipFreeAsync(yt, s));
   }
-  HIP_TRY(hipFreeAsync(Tb, s));
 }
 
 // Y = H X or H* X (rows in `order`) with every scratch buffer carved out of
@@ -841,16 +954,19 @@ int product_bb_apply(void *ctx, int transpose, int64_t n, int64_t ncols, int dty
   if (ncols <= 0) return 0;
   hipStream_t s = (hipStream_t)stream;
   const size_t es = dtype == HM_F32 ? 4 : 8;
-  void *tmp = nullptr;
-  if (hipMallocAsync(&tmp, (size_t)n * ncols * es, s) != hipSuccess) {
-    (void)hipGetLastError();
+  StreamBlock tb;
+  try {
+    tb.take((size_t)n * ncols * es, s);
+  } catch (const Error &e) {
+    set_error(e.msg);
     return 3;
   }
+  void *tmp = tb.p;
   const hm_blackbox &first = transpose ? p->A : p->B;
   const hm_blackbox &second = transpose ? p->B : p->A;
   int rc = first.apply(first.ctx, transpose, n, ncols, dtype, X, ldx, tmp, n, stream);
   if (rc == 0) rc = second.apply(second.ctx, transpose, n, ncols, dtype, tmp, n, Y, ldy, stream);
-  (void)hipFreeAsync(tmp, s);
+
   return rc;
 }
 
@@ -926,8 +1042,11 @@ struct Compression {
   DBuf Xb, Yb, tmpx, tmpy, Tb, work, core, scratch, sat, flag, floor_u, floor_v;
   struct LevelJobs {
     DBuf act, ju, jv, jc, kit;
+    DBuf order;  // pairs by block size, largest first (the fused recovery's work list)
     int32_t nkit = 0;
   };
+  DBuf counters;  // one work counter per level of the fused recovery
+  int recover_grid = 1024;
   std::vector<LevelJobs> jobs_of;
   int ni = 1;
   KernelBB *kbb = nullptr;
@@ -968,8 +1087,16 @@ struct Compression {
                  T.inst_off.begin()) - 1;
   }
 
+  hm_allocator al{};  // copy of the caller's allocator (o.allocator points here)
   Compression(Tree &t, const hm_blackbox &b, const hm_compress_opts &opt)
-      : T(t), bb(b), o(opt) {}
+      : T(t), bb(b), o(opt) {
+    if (opt.allocator && opt.allocator->alloc && opt.allocator->free) {
+      al = *opt.allocator;
+      o.allocator = &al;
+    } else {
+      o.allocator = nullptr;
+    }
+  }
 
   // scratch of one compression: cached blocks owned by its stream (the
   // compression waits for the stream before it ends), plain allocations for
@@ -1035,6 +1162,7 @@ hm_status Compression::setup(hipStream_t s) {
 
   D = &device_tree(T, s);
   H = std::make_unique<hm_hmatrix>();
+  if (o.allocator) H->al = al;
   HIP_TRY(hipGetDevice(&H->device));
   H->n = n;
   H->nlev = T.nlev();
@@ -1257,11 +1385,28 @@ hm_status Compression::setup(hipStream_t s) {
       put(jobs_of[li].kit, kit, s);
       jobs_of[li].nkit = (int32_t)kit.size();
     }
+    // the fused recovery takes the largest blocks first, so that the
+    // workgroups finish together
+    std::vector<int32_t> order(L.np);
+    for (int64_t q = 0; q < L.np; ++q) order[q] = (int32_t)q;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+      return ju[x].m + jv[x].m > ju[y].m + jv[y].m;
+    });
     put(jobs_of[li].act, act, s);
     put(jobs_of[li].ju, ju, s);
     put(jobs_of[li].jv, jv, s);
     put(jobs_of[li].jc, jc, s);
+    put(jobs_of[li].order, order, s);
     HIP_TRY(hipStreamSynchronize(s));  // the host vectors die here
+  }
+  if (!uniform) {
+    buf(counters, (size_t)std::max<size_t>(H->lv.size(), 1) * 4, s);
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, H->device) ==
+            hipSuccess &&
+        cus > 0)
+      recover_grid = 4 * cus;
+    (void)hipGetLastError();
   }
 
   // ---------------- leaf pass lists
@@ -1973,6 +2118,7 @@ void Compression::record(hipStream_t s, Events &ev) {
   launch_fill(H->ranks.p, 2 * np_total, true, 0.0, s);  // int32 zeros share the float bit pattern
   launch_fill(sat.p, std::max<int64_t>(2 * np_total, 1), true, 0.0, s);
   launch_fill(flag.p, 1, true, 0.0, s);
+  if (!uniform) launch_fill(counters.p, std::max<int64_t>((int64_t)H->lv.size(), 1), true, 0.0, s);
   LAUNCH_CHECK();
   cols_A = cols_At = 0;
   // ---------------- the level loop (no host round trips)
@@ -2044,26 +2190,39 @@ void Compression::record(hipStream_t s, Events &ev) {
     launch_check_finite(n, 2 * cpad, mixed, Yb.p, n, flag.as<int32_t>(), s);
     LAUNCH_CHECK();
     ev.mark(3);
-    DBuf &dju = jobs_of[li].ju, &djv = jobs_of[li].jv, &djc = jobs_of[li].jc;
-    const int32_t cap = kfix > 0 ? kfix : r - p;
-    launch_core((int32_t)L.np, djc.as<CoreJob>(), r, mixed, Xb.p, n, Yb.p, n, core.as<double>(), s);
-    LAUNCH_CHECK();
-    launch_pivqr((int32_t)L.np, dju.as<QrJob>(), r, kfix, o.tol, cap,
-                 mixed ? floor_u.as<double>() : nullptr, mixed, Yb.p, n,
-                 work.as<double>(), H->U.as<double>(), H->ranks.as<int32_t>() + L.g0,
-                 sat.as<int32_t>() + L.g0, s);
-    LAUNCH_CHECK();
-    launch_pivqr((int32_t)L.np, djv.as<QrJob>(), r, kfix, o.tol, cap,
-                 mixed ? floor_v.as<double>() : nullptr, mixed, Yb.p, n,
-                 work.as<double>(), H->V.as<double>(), H->ranks.as<int32_t>() + np_total + L.g0,
-                 sat.as<int32_t>() + np_total + L.g0, s);
+    // per pair: core, the pivoted QRs of the Y and Z blocks, the coupling
+    // solve and W = U B, in one persistent launch over the level's pairs
+    // (the QR stage's time includes the solves)
+    RecoverArgs ra{};
+    ra.jc = jobs_of[li].jc.as<CoreJob>();
+    ra.ju = jobs_of[li].ju.as<QrJob>();
+    ra.jv = jobs_of[li].jv.as<QrJob>();
+    ra.order = jobs_of[li].order.as<int32_t>();
+    ra.counter = counters.as<int32_t>() + li;
+    ra.njobs = (int32_t)L.np;
+    ra.r = r;
+    ra.kmax = kmax;
+    ra.rank_fixed = kfix;
+    ra.cap = kfix > 0 ? kfix : r - p;
+    ra.tol = o.tol;
+    ra.ld = n;
+    ra.floor_u = mixed ? floor_u.as<double>() : nullptr;
+    ra.floor_v = mixed ? floor_v.as<double>() : nullptr;
+    ra.work = work.as<double>();
+    ra.U = H->U.as<double>();
+    ra.V = H->V.as<double>();
+    ra.core = core.as<double>();
+    ra.scratch = scratch.as<double>();
+    ra.B = H->B.as<double>();
+    ra.W = H->W.as<double>();
+    ra.ranks = H->ranks.as<int32_t>();
+    ra.ranks_u = H->ranks.as<int32_t>() + L.g0;
+    ra.ranks_v = H->ranks.as<int32_t>() + np_total + L.g0;
+    ra.sat_u = sat.as<int32_t>() + L.g0;
+    ra.sat_v = sat.as<int32_t>() + np_total + L.g0;
+    launch_recover(ra, recover_grid, mixed, Xb.p, Xb.p, Yb.p, s);
     LAUNCH_CHECK();
     ev.mark(4);
-    launch_coupling((int32_t)L.np, djc.as<CoreJob>(), r, kmax, mixed, Xb.p, n, Xb.p, n,
-                    H->U.as<double>(), H->V.as<double>(), H->ranks.as<int32_t>(),
-                    core.as<double>(), scratch.as<double>(), H->B.as<double>(),
-                    H->W.as<double>(), s);
-    LAUNCH_CHECK();
     fp32_copies(li, s);
     ev.mark(5);
   }
@@ -2288,6 +2447,7 @@ hm_status Compression::finalize(hipStream_t s, Events &ev,
 hm_status compress_impl(Tree &T, const hm_blackbox &bb, const hm_compress_opts &o,
                         hipStream_t s, hm_hmatrix **out) {
   auto t_host0 = std::chrono::steady_clock::now();
+  AllocScope scope(o.allocator);
   Compression C(T, bb, o);
   hm_status st = C.setup(s);
   if (st != HM_OK) return st;
@@ -2359,7 +2519,8 @@ int64_t compress_footprint(Tree &T, const hm_compress_opts &o) {
   const int64_t wcols = std::max<int64_t>(2 * cmax, leaf_cols);
   const int64_t pools = szU * (8 + 8 + 4) + szV * (8 + 4) + np * kmax * kmax * 8 + szD * 8 +
                         np * 8 + n * 8;
-  const int64_t tcap = std::min<int64_t>(slots * kmax * wcols, int64_t(64) << 20);
+  const int64_t tcap = std::max(std::min<int64_t>(slots * kmax * wcols, kTScratchCap),
+                                slots * kmax * 64);
   const int64_t scratch = 2 * n * wcols * es + tcap * es + wmax * 8 + 2 * cmax_np * r * r * 8 +
                           np * 8 + cmax_np * 16;
   const int64_t plans = 64 * np + 4096;
@@ -2879,6 +3040,7 @@ hm_status hm_compress_plan(hm_tree *tree, const hm_blackbox *bb, const hm_compre
   API_BEGIN
   if (!tree || !bb || !opts || !out) return fail(HM_E_ARG, "hm_compress_plan: null argument");
   hipStream_t s = (hipStream_t)stream;
+  AllocScope scope(opts->allocator);
   auto P = std::make_unique<hm_plan>();
   P->C = std::make_unique<Compression>(tree->t, *bb, *opts);
   P->C->persistent = true;
@@ -2922,6 +3084,7 @@ hm_status hm_plan_execute(hm_plan *plan, void *stream) {
   API_BEGIN
   if (!plan) return fail(HM_E_ARG, "null plan");
   hipStream_t s = (hipStream_t)stream;
+  AllocScope scope(plan->C->o.allocator);
   const auto t0 = std::chrono::steady_clock::now();
   HIP_TRY(hipGraphLaunch(plan->ge, s));
   Events ev;

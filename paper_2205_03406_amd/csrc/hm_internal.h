@@ -20,6 +20,39 @@ struct Error {
   std::string msg;
 };
 
+// ------------------------------------------------------------------ device memory
+// The caller's allocator (hm_allocator) in force on this thread: an entry
+// point that was given one installs it for its duration, and every device
+// allocation made meanwhile (its blocks and scratch) goes through it.
+const hm_allocator *&alloc_scope();
+struct AllocScope {
+  const hm_allocator *prev;
+  // a null or incomplete allocator leaves the one in force
+  explicit AllocScope(const hm_allocator *a) : prev(alloc_scope()) {
+    if (a && a->alloc && a->free) alloc_scope() = a;
+  }
+  ~AllocScope() { alloc_scope() = prev; }
+  AllocScope(const AllocScope &) = delete;
+  AllocScope &operator=(const AllocScope &) = delete;
+};
+// Flops per launch of the built-in kernel apply on this thread (0: whole
+// launches).  The server sets it for its compressions, whose kernel applies
+// then run as row slices of about that much work each, so that work on the
+// other workers' streams (applies) gets the device between slices instead
+// of waiting for a launch of seconds.
+double &kapply_slice_flops();
+struct SliceScope {
+  double prev;
+  explicit SliceScope(double flops) : prev(kapply_slice_flops()) { kapply_slice_flops() = flops; }
+  ~SliceScope() { kapply_slice_flops() = prev; }
+  SliceScope(const SliceScope &) = delete;
+  SliceScope &operator=(const SliceScope &) = delete;
+};
+// stream-ordered device scratch: the allocator in force, else
+// hipMallocAsync / hipFreeAsync (stream: a hipStream_t)
+void *scratch_alloc(size_t bytes, void *stream);
+void scratch_free(void *p, void *stream);
+
 // ------------------------------------------------------------------ tree
 struct Level {
   std::vector<int64_t> start;    // nbox + 1

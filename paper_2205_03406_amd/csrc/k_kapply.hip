@@ -91,16 +91,18 @@ __device__ __forceinline__ float kval32(float r2) {
   return r2 > 0.0f ? v : 0.0f;
 }
 
-// SEG = false: the whole operator, grid (row blocks, column tiles).
+// SEG = false: the whole operator, grid (row blocks, column tiles), the
+// row blocks counted from aux (a slice of the rows: aux = its first block).
 // SEG = true: block-diagonal (forest) form, a 1-D grid over (item, column
 // tile) pairs, column tile fastest; all indices below are relative to the
 // item's instance (rows, depth and point coordinates start at its base row),
-// and n stays the stride of the point coordinates.
+// and n stays the stride of the point coordinates; aux = split (the second
+// live column range, < 0: none).
 template <typename T, int NT, int KER, int DIM, bool SEG>
 __global__ void __launch_bounds__(256)
 kapply_kernel(int64_t n, const double *__restrict__ pts_all, int64_t ncols,
               const T *__restrict__ X_all, int64_t ldx, T *__restrict__ Y_all, int64_t ldy,
-              const KItem *__restrict__ items, int64_t split) {
+              const KItem *__restrict__ items, int64_t aux) {
   constexpr int BK = sizeof(T) == 4 ? HM_KAPPLY_BK32 : HM_KAPPLY_BK64;  // points per LDS buffer
   constexpr int BN = 16 * NT;
   constexpr int LDT = BN + HM_KAPPLY_PAD;
@@ -119,9 +121,9 @@ kapply_kernel(int64_t n, const double *__restrict__ pts_all, int64_t ncols,
     row_blk = it.rblk;
     base = it.base;
     nloc = it.nloc;
-    live = col0 < it.width || (split >= 0 && col0 + BN > split && col0 < split + it.width);
+    live = col0 < it.width || (aux >= 0 && col0 + BN > aux && col0 < aux + it.width);
   } else {
-    row_blk = (int64_t)blockIdx.x * 64;
+    row_blk = ((int64_t)blockIdx.x + aux) * 64;
     col0 = (int64_t)blockIdx.y * BN;
   }
   const double *__restrict__ pts = pts_all + base;
@@ -310,11 +312,14 @@ void launch_nt(int64_t n, const double *pts, int64_t ncols, const T *X, int64_t 
     kapply_kernel<T, NT, KER, DIM, true><<<(unsigned)(nitems * nct), 256, 0, s>>>(
         n, pts, ncols, X, ldx, Y, ldy, items, split);
   } else {
-    // nitems > 0: only the first nitems row blocks (a partial launch)
+    // row blocks [split, split + nitems) (a slice), nitems <= 0: to the end
     const int64_t nb = (n + 63) / 64;
-    dim3 g((unsigned)(nitems > 0 && nitems < nb ? nitems : nb), (unsigned)nct);
+    const int64_t b0 = split > 0 ? split : 0;
+    const int64_t cnt = nitems > 0 ? std::min<int64_t>(nitems, nb - b0) : nb - b0;
+    if (cnt <= 0) return;
+    dim3 g((unsigned)cnt, (unsigned)nct);
     kapply_kernel<T, NT, KER, DIM, false><<<g, 256, 0, s>>>(n, pts, ncols, X, ldx, Y, ldy,
-                                                             nullptr, -1);
+                                                             nullptr, b0);
   }
 }
 
@@ -401,10 +406,12 @@ int kapply_default_nt(int64_t ncols, bool f32, int64_t units) {
 
 void launch_kapply(int kernel, int dim, int64_t n, const double *pts, int64_t ncols, int nt,
                    bool f32, const void *X, int64_t ldx, void *Y, int64_t ldy, hipStream_t s,
-                   int64_t rows) {
-  if (n <= 0 || ncols <= 0) return;
-  const int32_t nblk = rows > 0 ? (int32_t)((std::min(rows, n) + 63) / 64) : 0;
-  launch_any(kernel, nt, dim, n, pts, ncols, f32, X, ldx, Y, ldy, nblk, nullptr, -1, s);
+                   int64_t rows, int64_t row0) {
+  if (n <= 0 || ncols <= 0 || row0 < 0 || row0 >= n) return;
+  // rows of a slice start on a 64-row block
+  const int64_t b0 = row0 / 64;
+  const int32_t nblk = rows > 0 ? (int32_t)((std::min(rows, n - b0 * 64) + 63) / 64) : 0;
+  launch_any(kernel, nt, dim, n, pts, ncols, f32, X, ldx, Y, ldy, nblk, nullptr, b0, s);
 }
 
 void launch_kapply_forest(int kernel, int dim, int64_t n, const double *pts, int32_t nitems,

@@ -10,6 +10,8 @@
 // per call.  Tiles are 64 rows x 64 columns, K staged through LDS in chunks
 // of 32; FP64 (or FP32 in the mixed path) on the vector ALUs.
 #include <algorithm>
+#include <stdexcept>
+#include <string>
 
 #include "device_common.h"
 #include "kernels.h"
@@ -59,15 +61,17 @@ __global__ void __launch_bounds__(256, 2)
 lr_project_kernel(const ProjItem *__restrict__ items, const ProjPair *__restrict__ pairs,
                   int32_t kmax, int64_t tstride, const int32_t *__restrict__ ranks,
                   const T *__restrict__ R, const T *__restrict__ X, int64_t ldx, int64_t ncols,
-                  T *__restrict__ Tout) {
+                  T *__restrict__ Tout, int32_t nitems, int32_t ntiles) {
   __shared__ T As[KC][64 + 1];   // [depth][output row]
   __shared__ T Bs[KC][16 * NTW + 1];   // [depth][col]
   __shared__ int64_t o_r[PMAX];  // R element offset of output row (segment start)
   __shared__ int64_t o_t[PMAX];  // T element offset of output row
   __shared__ int o_tot;
   typedef typename Acc<T>::type acc_t;
-  const ProjItem it = items[blockIdx.x];
-  const int64_t c0 = (int64_t)blockIdx.y * (16 * NTW);
+  int64_t item, tile;
+  dev::xcd_item_tile(nitems, ntiles, item, tile);
+  const ProjItem it = items[item];
+  const int64_t c0 = tile * (16 * NTW);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (tid == 0) {
     int o = 0;
@@ -154,7 +158,7 @@ __global__ void __launch_bounds__(256, 4)
 lr_expand_kernel(const ExpandChunk *__restrict__ chunks, const ExpandEntry *__restrict__ entries,
                  int32_t kmax, int64_t tstride, const int32_t *__restrict__ ranks,
                  const T *__restrict__ L, const T *__restrict__ Tin, int64_t ncols, T sign,
-                 T *__restrict__ Y, int64_t ldy, int reduced) {
+                 T *__restrict__ Y, int64_t ldy, int reduced, int32_t nitems, int32_t ntiles) {
   __shared__ T As[KC][64 + 1];   // [depth][row]
   __shared__ T Bs[KC][16 * NTW + 1];   // [depth][col]
   __shared__ int64_t e_l[EMAX];
@@ -162,8 +166,10 @@ lr_expand_kernel(const ExpandChunk *__restrict__ chunks, const ExpandEntry *__re
   __shared__ int16_t d_e[KTAB];
   __shared__ int8_t d_k[KTAB];
   typedef typename Acc<T>::type acc_t;
-  const ExpandChunk ch = chunks[blockIdx.x];
-  const int64_t c0 = (int64_t)blockIdx.y * (16 * NTW);
+  int64_t item, tile;
+  dev::xcd_item_tile(nitems, ntiles, item, tile);
+  const ExpandChunk ch = chunks[item];
+  const int64_t c0 = tile * (16 * NTW);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   acc_t acc[NTW];
 #pragma unroll
@@ -280,7 +286,7 @@ template <typename T, int NTW>
 __global__ void __launch_bounds__(256, 2)
 near_kernel(const ExpandChunk *__restrict__ chunks, const NearEntry *__restrict__ entries,
             const double *__restrict__ D, const T *__restrict__ X, int64_t ldx, int64_t ncols,
-            T *__restrict__ Y, int64_t ldy, int overwrite) {
+            T *__restrict__ Y, int64_t ldy, int overwrite, int32_t nitems, int32_t ntiles) {
   __shared__ T As[KC][64 + 1];   // [depth][row]
   __shared__ T Bs[KC][16 * NTW + 1];   // [depth][col]
   __shared__ int64_t e_d[NEMAX], e_x[NEMAX];
@@ -288,8 +294,10 @@ near_kernel(const ExpandChunk *__restrict__ chunks, const NearEntry *__restrict_
   __shared__ int16_t d_e[NKTAB];
   __shared__ uint8_t d_k[NKTAB];
   typedef typename Acc<T>::type acc_t;
-  const ExpandChunk ch = chunks[blockIdx.x];
-  const int64_t c0 = (int64_t)blockIdx.y * (16 * NTW);
+  int64_t item, tile;
+  dev::xcd_item_tile(nitems, ntiles, item, tile);
+  const ExpandChunk ch = chunks[item];
+  const int64_t c0 = tile * (16 * NTW);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   acc_t acc[NTW];
 #pragma unroll
@@ -473,13 +481,23 @@ inline unsigned tiles_of(int64_t ncols) {
   return (unsigned)((ncols + 16 * NTW - 1) / (16 * NTW));
 }
 
+// workgroups of a 1-D (item, tile) grid; the work-items of one grid
+// dimension must stay below 2^32
+inline unsigned grid_of(int64_t nitems, unsigned ntiles) {
+  const int64_t g = nitems * (int64_t)ntiles;
+  if (g * 256 >= (int64_t(1) << 32))
+    throw std::runtime_error("low-rank launch of " + std::to_string(g) + " workgroups is too large");
+  return (unsigned)g;
+}
+
 template <typename T, int NTW>
 void project_ntw(int32_t nitems, const ProjItem *items, const ProjPair *pairs, int32_t kmax,
                  int64_t tstride, const int32_t *ranks, const void *R, const void *X, int64_t ldx,
                  int64_t ncols, void *Tb, hipStream_t s) {
-  dim3 g(nitems, tiles_of<NTW>(ncols));
-  lr_project_kernel<T, NTW><<<g, 256, 0, s>>>(items, pairs, kmax, tstride, ranks, (const T *)R,
-                                              (const T *)X, ldx, ncols, (T *)Tb);
+  const unsigned nt = tiles_of<NTW>(ncols);
+  lr_project_kernel<T, NTW><<<grid_of(nitems, nt), 256, 0, s>>>(
+      items, pairs, kmax, tstride, ranks, (const T *)R, (const T *)X, ldx, ncols, (T *)Tb, nitems,
+      (int32_t)nt);
 }
 
 template <typename T, int NTW>
@@ -487,19 +505,20 @@ void expand_ntw(int32_t nchunks, const ExpandChunk *chunks, const ExpandEntry *e
                 int32_t kmax, int64_t tstride, const int32_t *ranks, const void *L,
                 const void *Tb, int64_t ncols, double sign, void *Y, int64_t ldy, bool reduced,
                 hipStream_t s) {
-  dim3 g(nchunks, tiles_of<NTW>(ncols));
-  lr_expand_kernel<T, NTW><<<g, 256, 0, s>>>(chunks, entries, kmax, tstride, ranks,
-                                             (const T *)L, (const T *)Tb, ncols, (T)sign,
-                                             (T *)Y, ldy, reduced ? 1 : 0);
+  const unsigned nt = tiles_of<NTW>(ncols);
+  lr_expand_kernel<T, NTW><<<grid_of(nchunks, nt), 256, 0, s>>>(
+      chunks, entries, kmax, tstride, ranks, (const T *)L, (const T *)Tb, ncols, (T)sign, (T *)Y,
+      ldy, reduced ? 1 : 0, nchunks, (int32_t)nt);
 }
 
 template <typename T, int NTW>
 void near_ntw(int32_t nchunks, const ExpandChunk *chunks, const NearEntry *entries,
               const void *D, const void *X, int64_t ldx, int64_t ncols, void *Y, int64_t ldy,
               bool overwrite, hipStream_t s) {
-  dim3 g(nchunks, tiles_of<NTW>(ncols));
-  near_kernel<T, NTW><<<g, 256, 0, s>>>(chunks, entries, (const double *)D, (const T *)X, ldx,
-                                        ncols, (T *)Y, ldy, overwrite ? 1 : 0);
+  const unsigned nt = tiles_of<NTW>(ncols);
+  near_kernel<T, NTW><<<grid_of(nchunks, nt), 256, 0, s>>>(
+      chunks, entries, (const double *)D, (const T *)X, ldx, ncols, (T *)Y, ldy,
+      overwrite ? 1 : 0, nchunks, (int32_t)nt);
 }
 
 void launch_lr_project(int32_t nitems, const ProjItem *items, const ProjPair *pairs, int32_t kmax,

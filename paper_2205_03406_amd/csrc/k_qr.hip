@@ -11,6 +11,8 @@
 //
 // All of this stays in FP64 in every precision mode.  Reductions over rows
 // are wave-wide shuffles; every column update is owned by one wave.
+#include <algorithm>
+
 #include "device_common.h"
 #include "kernels.h"
 
@@ -88,18 +90,19 @@ block_norm_kernel(const QrJob *__restrict__ jobs, int32_t r, double scale,
 }
 
 // ------------------------------------------------------------------ pivqr
+// One block (job index jx): the body of pivqr_kernel and of the fused
+// recovery kernel.
 template <typename T>
-__global__ void __launch_bounds__(256)
-pivqr_kernel(const QrJob *__restrict__ jobs, int32_t r, int32_t rank_fixed, double tol,
-             int32_t cap, const double *__restrict__ floor_abs, const T *__restrict__ S,
-             int64_t lds, double *__restrict__ Wk, double *__restrict__ U,
-             int32_t *__restrict__ ranks, int32_t *__restrict__ sat) {
+__device__ void pivqr_body(const QrJob &job, int jx, int32_t r, int32_t rank_fixed, double tol,
+                           int32_t cap, const double *__restrict__ floor_abs,
+                           const T *__restrict__ S, int64_t lds, double *__restrict__ Wk,
+                           double *__restrict__ U, int32_t *__restrict__ ranks,
+                           int32_t *__restrict__ sat) {
   __shared__ double nrm2[64];
   __shared__ int piv[64];
   __shared__ double tau[64];
   __shared__ double bcast[4];
   __shared__ int stop_s;
-  const QrJob job = jobs[blockIdx.x];
   const int m = job.m;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const T *A = S + job.col0 * lds + job.row0;
@@ -109,7 +112,7 @@ pivqr_kernel(const QrJob *__restrict__ jobs, int32_t r, int32_t rank_fixed, doub
                                   : (cap < kmax_here ? cap : kmax_here);
   // absolute floor under the relative threshold (the rounding noise of a
   // reduced-precision sample), 0 when none
-  const double fl = floor_abs ? floor_abs[blockIdx.x] : 0.0;
+  const double fl = floor_abs ? floor_abs[jx] : 0.0;
 
   // copy to the FP64 workspace and take squared column norms
   for (int c = wave; c < r; c += 4) {
@@ -210,9 +213,20 @@ pivqr_kernel(const QrJob *__restrict__ jobs, int32_t r, int32_t rank_fixed, doub
     __syncthreads();
   }
   if (tid == 0) {
-    ranks[blockIdx.x] = rank;
-    sat[blockIdx.x] = saturated;
+    ranks[jx] = rank;
+    sat[jx] = saturated;
   }
+  __syncthreads();
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+pivqr_kernel(const QrJob *__restrict__ jobs, int32_t r, int32_t rank_fixed, double tol,
+             int32_t cap, const double *__restrict__ floor_abs, const T *__restrict__ S,
+             int64_t lds, double *__restrict__ Wk, double *__restrict__ U,
+             int32_t *__restrict__ ranks, int32_t *__restrict__ sat) {
+  pivqr_body<T>(jobs[blockIdx.x], blockIdx.x, r, rank_fixed, tol, cap, floor_abs, S, lds, Wk, U,
+                ranks, sat);
 }
 
 // ------------------------------------------------------------------ small dense helpers
@@ -330,27 +344,31 @@ __device__ void lds_backsolve(const double *M, int ld, int k, double *C, int ldc
 
 // ------------------------------------------------------------------ core
 template <typename T>
-__global__ void __launch_bounds__(256)
-core_kernel(const CoreJob *__restrict__ jobs, int32_t r, const T *__restrict__ Psi, int64_t ldp,
-            const T *__restrict__ Y, int64_t ldy, double *__restrict__ core) {
-  extern __shared__ double smem[];  // staging, 33 * 2r doubles
-  const CoreJob job = jobs[blockIdx.x];
+__device__ void core_body(const CoreJob &job, int32_t r, const T *__restrict__ Psi, int64_t ldp,
+                          const T *__restrict__ Y, int64_t ldy, double *__restrict__ core,
+                          double *smem) {
   tn_gemm(job.ma, r, r, Psi + job.vcol0 * ldp + job.arow0, ldp, Y + job.ucol0 * ldy + job.arow0,
           ldy, core + job.cslot, r, smem);
 }
 
-// ------------------------------------------------------------------ coupling
 template <typename T>
 __global__ void __launch_bounds__(256)
-coupling_kernel(const CoreJob *__restrict__ jobs, int32_t r, int32_t kmax,
-                const T *__restrict__ Omega, int64_t ldo, const T *__restrict__ Psi, int64_t ldp,
-                const double *__restrict__ U, const double *__restrict__ V,
-                const int32_t *__restrict__ ranks, const double *__restrict__ core,
-                double *__restrict__ scratch, double *__restrict__ B, double *__restrict__ Wout) {
-  extern __shared__ double smem[];
+core_kernel(const CoreJob *__restrict__ jobs, int32_t r, const T *__restrict__ Psi, int64_t ldp,
+            const T *__restrict__ Y, int64_t ldy, double *__restrict__ core) {
+  extern __shared__ double smem[];  // staging, 33 * 2r doubles
+  core_body<T>(jobs[blockIdx.x], r, Psi, ldp, Y, ldy, core, smem);
+}
+
+// ------------------------------------------------------------------ coupling
+template <typename T>
+__device__ void coupling_body(const CoreJob &job, int32_t r, int32_t kmax,
+                              const T *__restrict__ Omega, int64_t ldo, const T *__restrict__ Psi,
+                              int64_t ldp, const double *__restrict__ U,
+                              const double *__restrict__ V, const int32_t *__restrict__ ranks,
+                              const double *__restrict__ core, double *__restrict__ scratch,
+                              double *__restrict__ B, double *__restrict__ Wout, double *smem) {
   __shared__ double tau[64];
   __shared__ double bc[2];
-  const CoreJob job = jobs[blockIdx.x];
   const int ku = ranks[job.pu], kv = ranks[job.pv];
   const int tid = threadIdx.x;
   double *Bs = B + job.bslot;
@@ -358,6 +376,7 @@ coupling_kernel(const CoreJob *__restrict__ jobs, int32_t r, int32_t kmax,
   if (ku == 0 || kv == 0) {
     // a zero block: B and W stay empty (ranks say so); clear for export
     for (int e = tid; e < kmax * kmax; e += 256) Bs[e] = 0.0;
+    __syncthreads();
     return;
   }
   const int sa = (r * r > 33 * (r + kmax)) ? r * r : 33 * (r + kmax);
@@ -400,6 +419,51 @@ coupling_kernel(const CoreJob *__restrict__ jobs, int32_t r, int32_t kmax,
       for (int t = 0; t < ku; ++t) s += Ua[(int64_t)t * job.ma + i] * A[t * r + c];
       W[(int64_t)c * job.ma + i] = s;
     }
+  }
+  __syncthreads();
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+coupling_kernel(const CoreJob *__restrict__ jobs, int32_t r, int32_t kmax,
+                const T *__restrict__ Omega, int64_t ldo, const T *__restrict__ Psi, int64_t ldp,
+                const double *__restrict__ U, const double *__restrict__ V,
+                const int32_t *__restrict__ ranks, const double *__restrict__ core,
+                double *__restrict__ scratch, double *__restrict__ B, double *__restrict__ Wout) {
+  extern __shared__ double smem[];
+  coupling_body<T>(jobs[blockIdx.x], r, kmax, Omega, ldo, Psi, ldp, U, V, ranks, core, scratch, B,
+                   Wout, smem);
+}
+
+// Fused, persistent recovery of one level: a grid of at most a few
+// workgroups per compute unit, each pulling pairs from the level's work
+// list (largest blocks first) through an atomic counter until the list is
+// exhausted; per pair, in one workgroup, the core C = G2^T Y, the two
+// pivoted QRs (U from the Y block, V from the Z block) and the coupling
+// solve with W = U B.  The same arithmetic as the four separate launches,
+// in one launch per level with no workgroup idle while others finish the
+// large blocks.  The counter must be zero at the launch.
+template <typename T>
+__global__ void __launch_bounds__(256)
+recover_kernel(RecoverArgs a, const T *__restrict__ Om, const T *__restrict__ Ps,
+               const T *__restrict__ Ys) {
+  extern __shared__ double smem[];
+  __shared__ int next;
+  for (;;) {
+    if (threadIdx.x == 0) next = atomicAdd(a.counter, 1);
+    __syncthreads();
+    const int i = next;
+    __syncthreads();
+    if (i >= a.njobs) break;
+    const int q = a.order[i];
+    const CoreJob cj = a.jc[q];
+    core_body<T>(cj, a.r, Ps, a.ld, Ys, a.ld, a.core, smem);
+    pivqr_body<T>(a.ju[q], q, a.r, a.rank_fixed, a.tol, a.cap, a.floor_u, Ys, a.ld, a.work, a.U,
+                  a.ranks_u, a.sat_u);
+    pivqr_body<T>(a.jv[q], q, a.r, a.rank_fixed, a.tol, a.cap, a.floor_v, Ys, a.ld, a.work, a.V,
+                  a.ranks_v, a.sat_v);
+    coupling_body<T>(cj, a.r, a.kmax, Om, a.ld, Ps, a.ld, a.U, a.V, a.ranks, a.core, a.scratch,
+                     a.B, a.W, smem);
   }
 }
 
@@ -741,6 +805,22 @@ void launch_core(int32_t njobs, const CoreJob *jobs, int32_t r, bool f32, const 
   else
     core_kernel<double><<<njobs, 256, sh, s>>>(jobs, r, (const double *)Psi, ldp,
                                                (const double *)Y, ldy, core);
+}
+
+void launch_recover(const RecoverArgs &a, int grid, bool f32, const void *Omega, const void *Psi,
+                    const void *Y, hipStream_t s) {
+  if (a.njobs <= 0) return;
+  const size_t core_sh = 33 * 2 * (size_t)a.r;
+  const size_t sa = ((size_t)a.r * a.r > 33 * (size_t)(a.r + a.kmax)) ? (size_t)a.r * a.r
+                                                                       : 33 * (size_t)(a.r + a.kmax);
+  const size_t sh = sizeof(double) * std::max(core_sh, sa + (size_t)a.r * a.kmax);
+  const unsigned g = (unsigned)std::max(1, std::min(grid, (int)a.njobs));
+  if (f32)
+    recover_kernel<float><<<g, 256, sh, s>>>(a, (const float *)Omega, (const float *)Psi,
+                                             (const float *)Y);
+  else
+    recover_kernel<double><<<g, 256, sh, s>>>(a, (const double *)Omega, (const double *)Psi,
+                                              (const double *)Y);
 }
 
 void launch_coupling(int32_t njobs, const CoreJob *jobs, int32_t r, int32_t kmax, bool f32,

@@ -45,10 +45,11 @@ void launch_check_finite(int64_t n, int64_t ncols, bool f32, const void *Y, int6
 // tree order), 0 where p_i == p_j.  kernel: 0 = log, 1 = 1/r.
 // nt: column fragments (16 columns each) per workgroup, even, 2..16; 0 =
 // kapply_default_nt.  Every nt computes the same values bit for bit.
-// rows > 0: compute only Y rows [0, rows) (a partial launch for timing).
+// rows > 0: compute only Y rows [row0, row0 + rows) (row0 a multiple of
+// 64): a slice of a launch, or a partial launch for timing (row0 = 0).
 void launch_kapply(int kernel, int dim, int64_t n, const double *pts, int64_t ncols, int nt,
                    bool f32, const void *X, int64_t ldx, void *Y, int64_t ldy, hipStream_t s,
-                   int64_t rows = 0);
+                   int64_t rows = 0, int64_t row0 = 0);
 // Block-diagonal form for a forest: one work item per 64-row block of one
 // instance.  Rows [base, base + nloc) of Y are K_inst X(base : base+nloc, :)
 // where K_inst only couples points of the instance.  Columns outside
@@ -171,6 +172,25 @@ struct CoreJob {
   int32_t ma, mb;
   int32_t pu, pv;  // index of the pair's U / V rank
 };
+// The recovery of a whole level in one persistent launch (core, the two
+// pivoted QRs and the coupling of every pair, pairs pulled through
+// *counter in `order`, largest blocks first); the arguments of the four
+// separate launches.  *counter must be 0 at the launch.
+struct RecoverArgs {
+  const CoreJob *jc;
+  const QrJob *ju, *jv;
+  const int32_t *order;
+  int32_t *counter;
+  int32_t njobs, r, kmax, rank_fixed, cap;
+  double tol;
+  int64_t ld;                   // leading dimension of Omega, Psi, Y (= n)
+  const double *floor_u, *floor_v;
+  double *work, *U, *V, *core, *scratch, *B, *W;
+  int32_t *ranks;               // all ranks (coupling: ranks[pu], ranks[pv])
+  int32_t *ranks_u, *ranks_v, *sat_u, *sat_v;  // this level's, indexed by pair
+};
+void launch_recover(const RecoverArgs &a, int grid, bool f32, const void *Omega, const void *Psi,
+                    const void *Y, hipStream_t s);
 void launch_core(int32_t njobs, const CoreJob *jobs, int32_t r, bool f32, const void *Psi,
                  int64_t ldp, const void *Y, int64_t ldy, double *core, hipStream_t s);
 // B = (G2^T U)^+ C (V^T G1)^+ and W = U B for every pair.

@@ -90,6 +90,8 @@ struct Pinned {
 
 struct hm_server {
   int device = 0;
+  hm_allocator al{};  // the caller's allocator (al.alloc null: the library's own)
+  double slice_flops = 4e11;  // kernel-apply slice of a compression (0: whole launches)
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   std::deque<hm::Req *> pending;
@@ -158,6 +160,13 @@ void hm_server::finish(hm::Req *q, hm_status st) {
 
 void hm_server::worker() {
   (void)hipSetDevice(device);
+  // every device block of this worker's requests through the caller's
+  // allocator, when the server was given one
+  hm::AllocScope scope(al.alloc ? &al : nullptr);
+  // compressions' kernel applies in row slices of about 4e11 flops (about
+  // 8 ms of FP64 matrix-core time), so that applies on the other workers'
+  // streams reach the device between slices
+  hm::SliceScope slices(slice_flops);
   hipStream_t s = nullptr;
   if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return;
   hm::Pinned pin;
@@ -245,10 +254,13 @@ void hm_server::worker() {
     void *hp = pin.get(2 * bytes);
     void *dx = nullptr, *dy = nullptr;
     if (!hp) st = hm::fail(HM_E_NOMEM, "pinned staging allocation failed");
-    if (st == HM_OK && (hipMallocAsync(&dx, bytes, s) != hipSuccess ||
-                        hipMallocAsync(&dy, bytes, s) != hipSuccess)) {
-      (void)hipGetLastError();
-      st = hm::fail(HM_E_NOMEM, "device staging allocation failed");
+    if (st == HM_OK) {
+      try {
+        dx = hm::scratch_alloc(bytes, (void *)s);
+        dy = hm::scratch_alloc(bytes, (void *)s);
+      } catch (const hm::Error &) {
+        st = hm::fail(HM_E_NOMEM, "device staging allocation failed");
+      }
     }
     if (st == HM_OK) {
       std::memcpy(hp, q->X.data(), bytes);
@@ -260,8 +272,8 @@ void hm_server::worker() {
     if (st == HM_OK &&
         hipMemcpyAsync((char *)hp + bytes, dy, bytes, hipMemcpyDeviceToHost, s) != hipSuccess)
       st = hm::fail(HM_E_DEVICE, "copy of the result failed");
-    if (dx) (void)hipFreeAsync(dx, s);
-    if (dy) (void)hipFreeAsync(dy, s);
+    hm::scratch_free(dx, (void *)s);
+    hm::scratch_free(dy, (void *)s);
     if (hipStreamSynchronize(s) != hipSuccess && st == HM_OK)
       st = hm::fail(HM_E_DEVICE, "apply failed on the device");
     if (st == HM_OK) std::memcpy(q->Y, (char *)hp + bytes, bytes);
@@ -289,6 +301,7 @@ hm_status hm_server_create(const hm_server_opts *opts, hm_server **out) {
     auto S = std::make_unique<hm_server>();
     if (hipGetDevice(&S->device) != hipSuccess) return fail(HM_E_DEVICE, "no device");
     S->budget = opts->hbm_budget;
+    if (opts->allocator && opts->allocator->alloc && opts->allocator->free) S->al = *opts->allocator;
     S->compress_slots = opts->compress_slots > 0 ? std::min(opts->compress_slots, opts->nslots)
                                                  : 1;
     if (S->budget <= 0) {
@@ -344,6 +357,7 @@ hm_status hm_server_submit_compress(hm_server *S, const double *points, int64_t 
     q->kernel = kernel;
     q->o = *opts;
     q->o.flags = 0;
+    q->o.allocator = nullptr;  // the server's own allocator (if any) applies
     {
       std::lock_guard<std::mutex> lk(S->mu);
       q->id = S->next_id++;
