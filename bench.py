@@ -400,11 +400,16 @@ def _serve_once(hm, trace, xs, mixed, nslots, rate_scale):
     got = 0
     while got < len(res):
         got += len(srv.poll(wait_ms=1000))
-    kinds, lat = {}, {"compress": [], "matvec": []}
-    # matvec latency split: waiting (submit -> start on the device stream:
+    kinds, due_of, lat = {}, {}, {"compress": [], "matvec": []}
+    # latencies from each request's scheduled arrival (a submission that the
+    # loop makes late still counts from its arrival); matvec latency split:
+    # waiting (arrival -> start on the device stream: submission,
     # admission, a free worker, memory) and running (start -> end: staging,
-    # the apply and the copies back, sharing the device with the rest)
-    split = {"wait": [], "run": []}
+    # the apply and the copies back, sharing the device with the rest), and
+    # of the running time the part between the first copy's start and the
+    # last copy's end on the device stream (device events) and the host
+    # time spent enqueueing
+    split = {"wait": [], "run": [], "enqueue": [], "device": []}
     pending = 0
     t0 = srv.info()["now"]
     i = 0
@@ -414,14 +419,17 @@ def _serve_once(hm, trace, xs, mixed, nslots, rate_scale):
         nonlocal pending, fails
         for c in srv.poll(wait_ms=wait_ms):
             k = kinds.pop(c["id"])
+            t_arr = due_of.pop(c["id"])
             if c["status"] != 0:
                 fails += 1
-            lat[k].append(c["t_end"] - c["t_submit"])
+            lat[k].append(c["t_end"] - t_arr)
             if k == "compress":
                 srv.release(c["hmatrix"])
             else:
-                split["wait"].append(c["t_start"] - c["t_submit"])
+                split["wait"].append(c["t_start"] - t_arr)
                 split["run"].append(c["t_end"] - c["t_start"])
+                split["enqueue"].append(c["enqueue_ms"] * 1e-3)
+                split["device"].append(c["device_ms"] * 1e-3)
             pending -= 1
 
     while i < len(trace):
@@ -438,6 +446,7 @@ def _serve_once(hm, trace, xs, mixed, nslots, rate_scale):
         else:
             rid = srv.submit_matvec(res[q.target], xs[mixed][q.target][:q.nrhs].T)
         kinds[rid] = q.kind
+        due_of[rid] = due
         pending += 1
         i += 1
     while pending:
@@ -482,7 +491,7 @@ def run_served(hm, count, loads):
             v = np.array(lat[k]) * 1e3
             d[k] = {"n": len(v), "p50_ms": round(float(np.percentile(v, 50)), 3),
                     "p99_ms": round(float(np.percentile(v, 99)), 3)}
-        for k in ("wait", "run"):
+        for k in ("wait", "run", "enqueue", "device"):
             v = np.array(split[k]) * 1e3
             d["matvec"][k + "_p50_ms"] = round(float(np.percentile(v, 50)), 3)
             d["matvec"][k + "_p99_ms"] = round(float(np.percentile(v, 99)), 3)

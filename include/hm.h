@@ -517,6 +517,12 @@ typedef struct {
                        apply: the H-matrix it used */
   double t_submit, t_admit, t_start, t_end; /* seconds on the server's clock */
   int64_t bytes;    /* device bytes reserved for the request */
+  double device_ms; /* apply: device time between its first and last operation on
+                       its stream (HIP events around the upload, the apply and the
+                       download); 0 for a compression */
+  double enqueue_ms; /* apply: host time from t_start until its last operation was
+                       enqueued (staging into pinned memory and the enqueue calls);
+                       the rest of t_end - t_start is spent waiting for the stream */
 } hm_completion;
 
 hm_status hm_server_create(const hm_server_opts *opts, hm_server **out);

@@ -180,7 +180,8 @@ class ServerOpts(C.Structure):
 class Completion(C.Structure):
     _fields_ = [("id", C.c_int64), ("kind", C.c_int32), ("status", C.c_int32),
                 ("hmatrix", C.c_int64), ("t_submit", C.c_double), ("t_admit", C.c_double),
-                ("t_start", C.c_double), ("t_end", C.c_double), ("bytes", C.c_int64)]
+                ("t_start", C.c_double), ("t_end", C.c_double), ("bytes", C.c_int64),
+                ("device_ms", C.c_double), ("enqueue_ms", C.c_double)]
 
 
 def _load():

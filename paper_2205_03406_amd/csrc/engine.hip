@@ -112,6 +112,13 @@ inline bool &release_synced() {
   thread_local bool f = false;
   return f;
 }
+// set while an owner whose every use its caller has already synchronized
+// is destroyed (free_idle): nothing to wait for, however busy the device's
+// other streams are
+inline bool &release_idle() {
+  thread_local bool f = false;
+  return f;
+}
 // Declared as the first member of an owner of cached blocks (so destroyed
 // last): the owner's destructor body calls begin(), which makes the owner's
 // device current, waits until it is idle and lets the members that follow
@@ -122,14 +129,18 @@ struct SyncedRelease {
   void begin(int device) {
     (void)hipGetDevice(&cur);
     if (device >= 0 && device != cur) (void)hipSetDevice(device);
-    (void)hipDeviceSynchronize();
-    (void)hipGetLastError();
+    if (!release_idle()) {
+      (void)hipDeviceSynchronize();
+      (void)hipGetLastError();
+    }
     release_synced() = true;
   }
   // the same for buffers used on stream s only
   void begin_stream(hipStream_t s) {
-    (void)hipStreamSynchronize(s);
-    (void)hipGetLastError();
+    if (!release_idle()) {
+      (void)hipStreamSynchronize(s);
+      (void)hipGetLastError();
+    }
     release_synced() = true;
   }
   ~SyncedRelease() {
@@ -576,20 +587,29 @@ namespace hm {
 
 namespace {
 
-constexpr int kSeg = 256;  // rows per projection segment
+constexpr int kSeg = 256;  // rows per projection segment of the applies' plans
 
-// Apply plans of both orientations (levels in order).  Projection items
-// group up to 64/kmax pairs that share a column box and cover one segment of
-// it; each pair owns one partial slot per segment.  The expand plan for the
-// first li levels walks 64-row chunks of the finest of them and lists every
-// pair whose row box (at its own level) contains the chunk.
-void build_apply_plans(hm_hmatrix &H, const Tree &T, hipStream_t s) {
+// Low-rank product plans of both orientations (levels in order), into A and
+// At.  Projection items group up to 128/kmax pairs that share a column box
+// and cover one segment of `seg` rows of it (seg <= 0: the whole box); each
+// pair owns one partial slot per segment.  The expand plan for the first li
+// levels walks 64-row chunks of the finest of them and lists every pair
+// whose row box (at its own level) contains the chunk; it is built for
+// every li (prefixes, the peel's level-truncated products) or only for all
+// levels (the applies of the finished matrix).
+//   The applies of a finished H-matrix (few right-hand sides) take segments
+// of 256 rows: parallel work over the rows of the large boxes of the coarse
+// levels, the partials summed once (lr_reduce_kernel).  The peel (thousands
+// of columns, parallel over column tiles) takes whole boxes: no partial
+// slots to write, sum and read back, and fewer slots, so fewer column chunks.
+void build_plans(const hm_hmatrix &H, const Tree &T, int32_t seg, bool prefixes,
+                 hm_hmatrix::Orient &A, hm_hmatrix::Orient &At, hipStream_t s) {
   const int nlv = (int)H.lv.size();
   // pairs of one column box per projection item, at most 128 rank columns
   const int per_group = std::max(1, 128 / std::max(1, (int)H.kmax));
   for (int o = 0; o < 2; ++o) {
     const bool trans = o == 1;
-    hm_hmatrix::Orient &O = trans ? H.oT : H.oA;
+    hm_hmatrix::Orient &O = trans ? At : A;
     std::vector<ProjItem> items;
     std::vector<ProjPair> pps;
     std::vector<ReduceItem> reds;
@@ -607,7 +627,7 @@ void build_apply_plans(hm_hmatrix &H, const Tree &T, hipStream_t s) {
       nseg[li].resize(L.np);
       for (int64_t p = 0; p < L.np; ++p) {
         const int64_t m = Lev.start[colbox[p] + 1] - Lev.start[colbox[p]];
-        nseg[li][p] = (int32_t)((m + kSeg - 1) / kSeg);
+        nseg[li][p] = seg > 0 ? (int32_t)((m + seg - 1) / seg) : 1;
         slot_base[li][p] = slots;
         if (nseg[li][p] > 1) reds.push_back(ReduceItem{slots, nseg[li][p]});
         slots += nseg[li][p];
@@ -623,8 +643,9 @@ void build_apply_plans(hm_hmatrix &H, const Tree &T, hipStream_t s) {
         int64_t j = i;
         while (j < L.np && colbox[order[j]] == cb && j - i < per_group) ++j;
         const int32_t m = (int32_t)(Lev.start[cb + 1] - Lev.start[cb]);
-        for (int32_t sg = 0; sg * kSeg < m; ++sg) {
-          ProjItem it{Lev.start[cb] + (int64_t)sg * kSeg, std::min(kSeg, m - sg * kSeg), sg * kSeg,
+        const int32_t sl = seg > 0 ? seg : std::max(m, 1);
+        for (int32_t sg = 0; sg * sl < m; ++sg) {
+          ProjItem it{Lev.start[cb] + (int64_t)sg * sl, std::min(sl, m - sg * sl), sg * sl,
                       m, (int32_t)(j - i), (int32_t)pps.size(), 0};
           for (int64_t q = i; q < j; ++q) {
             const int64_t p = order[q];
@@ -660,7 +681,8 @@ void build_apply_plans(hm_hmatrix &H, const Tree &T, hipStream_t s) {
       std::vector<int32_t> fill(rb_ptr[li].begin(), rb_ptr[li].end() - 1);
       for (int64_t p = 0; p < L.np; ++p) rb_idx[li][fill[rowbox[p]]++] = (int32_t)p;
     }
-    for (int le = 1; le <= nlv; ++le) {
+    // (a tree with no sampled level has no plan: nlv = 0, no iteration)
+    for (int le = prefixes ? 1 : std::max(nlv, 1); le <= nlv; ++le) {
       const int fl = H.lv[le - 1].level;
       const Level &F = T.lev[fl];
       std::vector<ExpandChunk> ch;
@@ -705,10 +727,11 @@ void build_apply_plans(hm_hmatrix &H, const Tree &T, hipStream_t s) {
 // Y +=/-= (first li_end levels of H) X; T is scratch of tcap elements.
 void apply_levels(const hm_hmatrix &H, size_t li_end, bool trans, bool f32, const void *X,
                   int64_t ldx, int64_t ncols, void *Y, int64_t ldy, double sign, void *T,
-                  int64_t tcap, hipStream_t s) {
+                  int64_t tcap, hipStream_t s, const hm_hmatrix::Orient *plans = nullptr) {
   if (li_end == 0 || ncols <= 0) return;
-  const hm_hmatrix::Orient &O = trans ? H.oT : H.oA;
-  if (O.items_upto.size() <= li_end)
+  // plans: the two orientations' plans to use (the peel's), else the matrix's own
+  const hm_hmatrix::Orient &O = plans ? plans[trans ? 1 : 0] : (trans ? H.oT : H.oA);
+  if (O.items_upto.size() <= li_end || O.chunks.size() <= li_end || O.nch.size() <= li_end)
     throw Error{HM_E_STATE, "no per-pair apply plan for these levels"};
   const int32_t nitems = O.items_upto[li_end];
   const int64_t nslots = O.slots_upto[li_end];
@@ -731,7 +754,7 @@ void apply_levels(const hm_hmatrix &H, size_t li_end, bool trans, bool f32, cons
     LAUNCH_CHECK();
     launch_lr_expand(O.nch[li_end], O.chunks[li_end].as<ExpandChunk>(),
                      O.entries[li_end].as<ExpandEntry>(), H.kmax, tstride, H.ranks.as<int32_t>(),
-                     f32, Lp, T, w, sign, (char *)Y + c0 * ldy * es, ldy, true, s);
+                     f32, Lp, T, w, sign, (char *)Y + c0 * ldy * es, ldy, s);
     LAUNCH_CHECK();
   }
 }
@@ -1046,6 +1069,7 @@ struct Compression {
     int32_t nkit = 0;
   };
   DBuf counters;  // one work counter per level of the fused recovery
+  hm_hmatrix::Orient peel_plans[2];  // the peel's low-rank product plans (A, A*)
   int recover_grid = 1024;
   std::vector<LevelJobs> jobs_of;
   int ni = 1;
@@ -1209,7 +1233,12 @@ hm_status Compression::setup(hipStream_t s) {
   H->Wf.cached(h2 ? 0 : szU * 4);
   H->Vf.cached(h2 ? 0 : szV * 4);
   H->ranks.cached(2 * np_total * sizeof(int32_t));
-  if (!h2) build_apply_plans(*H, T, s);  // H^2 applies through its passes
+  // H^2 applies through its passes.  The matrix keeps the applies' plans;
+  // the peel's (whole boxes, every prefix of levels) live with the compression.
+  if (!h2) {
+    build_plans(*H, T, kSeg, false, H->oA, H->oT, s);
+    build_plans(*H, T, 0, true, peel_plans[0], peel_plans[1], s);
+  }
 
   // leaf neighbor blocks
   const Graph &GL = T.leaf_graph();
@@ -1305,7 +1334,14 @@ hm_status Compression::setup(hipStream_t s) {
   }
   buf(Xb, wbytes, s);
   buf(Yb, wbytes, s);
-  tcap = tscratch_elems(*H, wcols);
+  {
+    // partial projections of the peel: one slot per pair (whole boxes)
+    const int64_t slots = std::max<int64_t>(
+        peel_plans[0].slots_upto.empty() ? 0 : peel_plans[0].slots_upto.back(),
+        peel_plans[1].slots_upto.empty() ? 0 : peel_plans[1].slots_upto.back());
+    const int64_t need = slots * kmax * std::max<int64_t>(wcols, 1);
+    tcap = std::max<int64_t>(std::min(need, kTScratchCap), std::max<int64_t>(slots * kmax * 64, 64));
+  }
   buf(Tb, (size_t)tcap * tes, s);
   int64_t wmax = 0;
   for (size_t li = 0; li < H->lv.size(); ++li) {
@@ -1405,7 +1441,7 @@ hm_status Compression::setup(hipStream_t s) {
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, H->device) ==
             hipSuccess &&
         cus > 0)
-      recover_grid = 4 * cus;
+      recover_grid = 16 * cus;  // as many as fit resident; the rest find the list empty
     (void)hipGetLastError();
   }
 
@@ -2058,7 +2094,7 @@ void Compression::record_uniform_level(size_t li, hipStream_t s, Events &ev) {
     LAUNCH_CHECK();
   }
   ev.mark(2);
-  apply_levels(*H, li, false, mixed, X, n, c1pad, Y, n, -1.0, Tb.p, tcap, s);
+  apply_levels(*H, li, false, mixed, X, n, c1pad, Y, n, -1.0, Tb.p, tcap, s, peel_plans);
   launch_check_finite(n, c1pad, mixed, Y, n, flag.as<int32_t>(), s);
   LAUNCH_CHECK();
   ev.mark(3);
@@ -2079,7 +2115,7 @@ void Compression::record_uniform_level(size_t li, hipStream_t s, Events &ev) {
   apply_bb(1, c2pad, J.kit2, J.nkit2, false);
   cols_At += c2;
   ev.mark(2);
-  apply_levels(*H, li, true, false, X, n, c2pad, Y, n, -1.0, Tb.p, tcap, s);
+  apply_levels(*H, li, true, false, X, n, c2pad, Y, n, -1.0, Tb.p, tcap, s, peel_plans);
   launch_check_finite(n, c2pad, false, Y, n, flag.as<int32_t>(), s);
   LAUNCH_CHECK();
   ev.mark(3);
@@ -2185,8 +2221,8 @@ void Compression::record(hipStream_t s, Events &ev) {
       LAUNCH_CHECK();
     }
     ev.mark(2);
-    apply_levels(*H, li, false, mixed, Om, n, cpad, Yl, n, -1.0, Tb.p, tcap, s);
-    apply_levels(*H, li, true, mixed, Ps, n, cpad, Zl, n, -1.0, Tb.p, tcap, s);
+    apply_levels(*H, li, false, mixed, Om, n, cpad, Yl, n, -1.0, Tb.p, tcap, s, peel_plans);
+    apply_levels(*H, li, true, mixed, Ps, n, cpad, Zl, n, -1.0, Tb.p, tcap, s, peel_plans);
     launch_check_finite(n, 2 * cpad, mixed, Yb.p, n, flag.as<int32_t>(), s);
     LAUNCH_CHECK();
     ev.mark(3);
@@ -2254,7 +2290,7 @@ void Compression::record(hipStream_t s, Events &ev) {
              h2u.as<double>(), h2p.as<double>(), h2cols, s);
   else
     apply_levels(*H, H->lv.size(), false, mixed, Xb.p, n, leaf_cols, Yb.p, n, -1.0, Tb.p, tcap,
-                 s);
+                 s, peel_plans);
   launch_check_finite(n, leaf_cols, mixed, Yb.p, n, flag.as<int32_t>(), s);
   LAUNCH_CHECK();
   ev.mark(3);
@@ -2614,6 +2650,23 @@ using namespace hm;
   catch (const std::exception &e) {                          \
     return fail(HM_E_ARG, e.what());                         \
   }
+
+namespace hm {
+namespace {
+struct IdleRelease {
+  IdleRelease() { release_idle() = true; }
+  ~IdleRelease() { release_idle() = false; }
+};
+}  // namespace
+void free_idle(hm_hmatrix *H) {
+  IdleRelease g;
+  delete H;
+}
+void free_idle(hm_tree *T) {
+  IdleRelease g;
+  delete T;
+}
+}  // namespace hm
 
 extern "C" {
 

@@ -129,6 +129,12 @@ int64_t compress_footprint(Tree &T, const hm_compress_opts &o);
 int64_t matvec_footprint(const hm_hmatrix *H, int64_t nrhs, int dtype);
 // frees the idle device blocks kept for reuse by H-matrices, trees and compressions
 void trim_block_cache(int dev);
+// hm_hmatrix_free / hm_tree_free for an object with no work in flight (its
+// caller synchronized every stream that used it): its blocks go back at
+// once instead of after a device-wide synchronization, which would wait
+// for the work of every other stream (a compression of seconds)
+void free_idle(hm_hmatrix *H);
+void free_idle(hm_tree *T);
 
 // ------------------------------------------------------------------ autotuner
 struct KapplyShape {

@@ -76,10 +76,23 @@ __device__ __forceinline__ double log_pos(double x) {
   return fe * ln2_hi + (fe * ln2_lo + lm);
 }
 
+// 1/sqrt(x) for x > 0 from the hardware estimate y (relative error e0):
+// with e = 1 - x y^2, (1 - e)^(-1/2) = 1 + e/2 + 3e^2/8 + O(e^3), so
+// y (1 + e/2 + 3e^2/8) has relative error O(e0^3), below an ulp.  x = 0
+// gives inf or NaN here; the caller replaces it.
+__device__ __forceinline__ double rsqrt_pos(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  const double e = fma(-x * y, y, 1.0);
+  return fma(y * e, fma(e, 0.375, 0.5), y);
+}
+
 template <int KER>
 __device__ __forceinline__ double kval64(double r2) {
-  const double safe = r2 > 0.0 ? r2 : 1.0;
-  const double v = KER == 0 ? 0.5 * log_pos(safe) : rsqrt(safe);
+  if (KER == 1) {
+    const double v = rsqrt_pos(r2);
+    return r2 > 0.0 ? v : 0.0;
+  }
+  const double v = 0.5 * log_pos(r2 > 0.0 ? r2 : 1.0);
   return r2 > 0.0 ? v : 0.0;
 }
 

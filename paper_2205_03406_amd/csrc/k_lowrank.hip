@@ -55,209 +55,225 @@ constexpr int PMAX = 128;  // packed output rows of one projection item
 
 // Projection: the pairs of one item share a column box; their rank columns
 // are packed end to end (actual device ranks) into at most PMAX output rows,
-// processed 64 at a time.
-template <typename T, int NTW>
+// all of them accumulated in one sweep over the item's rows (NP passes of
+// 64 output rows side by side), so each X tile is fetched once per item.
+// (Walking several column tiles per workgroup, to set the packing up once
+// and keep the prefetch running across tiles, measured slower at 2 and 4
+// tiles: neighbouring workgroups then no longer share X rows in L2.)
+template <typename T, int NTW, int KD>
 __global__ void __launch_bounds__(256, 2)
 lr_project_kernel(const ProjItem *__restrict__ items, const ProjPair *__restrict__ pairs,
                   int32_t kmax, int64_t tstride, const int32_t *__restrict__ ranks,
                   const T *__restrict__ R, const T *__restrict__ X, int64_t ldx, int64_t ncols,
                   T *__restrict__ Tout, int32_t nitems, int32_t ntiles) {
-  __shared__ T As[KC][64 + 1];   // [depth][output row]
-  __shared__ T Bs[KC][16 * NTW + 1];   // [depth][col]
+  constexpr int NP = PMAX / 64;
+  constexpr int QS = 256 / KD;              // output rows / columns per fetch round
+  constexpr int NA = PMAX / QS, NB = 16 * NTW / QS;  // fetch rounds of R and X
+  static_assert(KD % 4 == 0 && 256 % KD == 0 && PMAX % QS == 0 && (16 * NTW) % QS == 0,
+                "fetch layout");
+  __shared__ T As[KD][PMAX + 1];   // [depth][output row]
+  __shared__ T Bs[KD][16 * NTW + 1];   // [depth][col]
   __shared__ int64_t o_r[PMAX];  // R element offset of output row (segment start)
   __shared__ int64_t o_t[PMAX];  // T element offset of output row
-  __shared__ int o_tot;
+  __shared__ int p_k[PMAX], p_o[PMAX + 1];
   typedef typename Acc<T>::type acc_t;
   int64_t item, tile;
   dev::xcd_item_tile(nitems, ntiles, item, tile);
   const ProjItem it = items[item];
   const int64_t c0 = tile * (16 * NTW);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // packing of the pairs' rank columns: ranks read in parallel, offsets by
+  // a short serial scan (at most PMAX pairs), rows filled per pair
+  const int np = it.npairs < PMAX ? it.npairs : PMAX;
+  if (tid < np) p_k[tid] = ranks[pairs[it.first + tid].kidx];
+  __syncthreads();
   if (tid == 0) {
     int o = 0;
-    for (int j = 0; j < it.npairs; ++j) {
-      const ProjPair pp = pairs[it.first + j];
-      const int k = ranks[pp.kidx];
-      for (int kk = 0; kk < k && o < PMAX; ++kk, ++o) {
-        o_r[o] = pp.rslot + it.seg_off + (int64_t)kk * it.m;
-        o_t[o] = (int64_t)pp.tslot * tstride + kk;
-      }
+    for (int j = 0; j < np; ++j) {
+      p_o[j] = o;
+      o = min(o + p_k[j], PMAX);
     }
-    o_tot = o;
+    p_o[np] = o;
   }
   __syncthreads();
-  const int nout = o_tot;
-  for (int ob = 0; ob < nout; ob += 64) {
-    acc_t acc[NTW];
-#pragma unroll
-    for (int t = 0; t < NTW; ++t) acc[t] = (acc_t){0, 0, 0, 0};
-    T av[8], bv[2 * NTW];
-    auto fetch = [&](int r0) {
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int e = tid + 256 * q;
-        const int rr = e % KC, o = e / KC;
-        const int row = r0 + rr;
-        av[q] = (row < it.nrows && ob + o < nout) ? R[o_r[ob + o] + row] : (T)0;
-      }
-#pragma unroll
-      for (int q = 0; q < 2 * NTW; ++q) {
-        const int e = tid + 256 * q;
-        const int rr = e % KC, o = e / KC;
-        const int row = r0 + rr;
-        const int64_t gc = c0 + o;
-        bv[q] = (row < it.nrows && gc < ncols) ? X[gc * ldx + it.row0 + row] : (T)0;
-      }
-    };
-    fetch(0);
-    for (int r0 = 0; r0 < it.nrows; r0 += KC) {
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int e = tid + 256 * q;
-        As[e % KC][e / KC] = av[q];
-      }
-#pragma unroll
-      for (int q = 0; q < 2 * NTW; ++q) {
-        const int e = tid + 256 * q;
-        Bs[e % KC][e / KC] = bv[q];
-      }
-      __syncthreads();
-      if (r0 + KC < it.nrows) fetch(r0 + KC);
-#pragma unroll
-      for (int ks = 0; ks < KC; ks += 4) {
-        const T a = As[ks + (lane >> 4)][16 * wave + (lane & 15)];
-#pragma unroll
-        for (int t = 0; t < NTW; ++t)
-          Acc<T>::step(a, Bs[ks + (lane >> 4)][16 * t + (lane & 15)], acc[t]);
-      }
-      __syncthreads();
+  if (tid < np) {
+    const ProjPair pp = pairs[it.first + tid];
+    for (int o = p_o[tid], kk = 0; o < p_o[tid + 1]; ++o, ++kk) {
+      o_r[o] = pp.rslot + it.seg_off + (int64_t)kk * it.m;
+      o_t[o] = (int64_t)pp.tslot * tstride + kk;
     }
+  }
+  __syncthreads();
+  const int nout = p_o[np];
+  if (nout == 0) return;  // uniform: nothing to project
+  acc_t acc[NP][NTW];
+#pragma unroll
+  for (int p = 0; p < NP; ++p)
+#pragma unroll
+    for (int t = 0; t < NTW; ++t) acc[p][t] = (acc_t){0, 0, 0, 0};
+  // thread operands: row r0 + (tid mod KD) of output rows / columns
+  // tid / KD + QS q
+  T av[NA], bv[NB];
+  auto fetch = [&](int r0) {
+    const int row = r0 + (tid % KD);
+    const bool rv = row < it.nrows;
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      const int o = tid / KD + QS * q;
+      av[q] = (rv && o < nout) ? R[o_r[o] + row] : (T)0;
+    }
+    const T *xr = X + it.row0 + row;
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int64_t gc = c0 + tid / KD + QS * q;
+      bv[q] = (rv && gc < ncols) ? xr[gc * ldx] : (T)0;
+    }
+  };
+  fetch(0);
+  for (int r0 = 0; r0 < it.nrows; r0 += KD) {
+#pragma unroll
+    for (int q = 0; q < NA; ++q) As[tid % KD][tid / KD + QS * q] = av[q];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) Bs[tid % KD][tid / KD + QS * q] = bv[q];
+    __syncthreads();
+    if (r0 + KD < it.nrows) fetch(r0 + KD);
+#pragma unroll
+    for (int ks = 0; ks < KD; ks += 4) {
+      T b[NTW];
+#pragma unroll
+      for (int t = 0; t < NTW; ++t) b[t] = Bs[ks + (lane >> 4)][16 * t + (lane & 15)];
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+        if (64 * p + 16 * wave < nout) {  // uniform across the wave: rows of the pass it holds
+          const T a = As[ks + (lane >> 4)][64 * p + 16 * wave + (lane & 15)];
+#pragma unroll
+          for (int t = 0; t < NTW; ++t) Acc<T>::step(a, b[t], acc[p][t]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
 #pragma unroll
     for (int t = 0; t < NTW; ++t) {
       const int64_t gc = c0 + 16 * t + (lane & 15);
       if (gc >= ncols) continue;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int o = ob + 16 * wave + Acc<T>::row(i, lane);
-        if (o < nout) Tout[o_t[o] + gc * kmax] = acc[t][i];
+        const int o = 64 * p + 16 * wave + Acc<T>::row(i, lane);
+        if (o < nout) Tout[o_t[o] + gc * kmax] = acc[p][t][i];
       }
     }
   }
 }
 
 // Expansion: the entries of a chunk form one contraction of depth
-// sum_e rank_e (actual device ranks, packed end to end); a depth -> (entry,
-// column) table is built per pass of up to EMAX entries.
+// sum_e rank_e (actual device ranks, packed end to end), taken in passes of
+// up to EMAX entries and DMAX depths; per pass a depth -> (L offset, T
+// offset) table in LDS, so that every operand fetch is one table read and
+// one load.  The partial projections of pairs split over segments must be
+// summed into their first slot beforehand (lr_reduce_kernel).
 constexpr int EMAX = 32;
-constexpr int KTAB = EMAX * 64;
+constexpr int DMAX = 384;
 
 // four waves per SIMD (at most 128 VGPRs): 11 % faster than three at 288
-// columns; the latency of the table-driven operand fetches needs the waves
-template <typename T, int NTW>
+// columns; the latency of the operand fetches needs the waves
+template <typename T, int NTW, int KD>
 __global__ void __launch_bounds__(256, 4)
 lr_expand_kernel(const ExpandChunk *__restrict__ chunks, const ExpandEntry *__restrict__ entries,
                  int32_t kmax, int64_t tstride, const int32_t *__restrict__ ranks,
                  const T *__restrict__ L, const T *__restrict__ Tin, int64_t ncols, T sign,
-                 T *__restrict__ Y, int64_t ldy, int reduced, int32_t nitems, int32_t ntiles) {
-  __shared__ T As[KC][64 + 1];   // [depth][row]
-  __shared__ T Bs[KC][16 * NTW + 1];   // [depth][col]
-  __shared__ int64_t e_l[EMAX];
-  __shared__ int32_t e_mq[EMAX], e_k[EMAX], e_ts[EMAX], e_ns[EMAX], e_ko[EMAX + 1];
-  __shared__ int16_t d_e[KTAB];
-  __shared__ int8_t d_k[KTAB];
+                 T *__restrict__ Y, int64_t ldy, int32_t nitems, int32_t ntiles) {
+  constexpr int QS = 256 / KD;  // T columns per fetch round
+  constexpr int NA = KD / 4, NB = 16 * NTW / QS;  // fetch rounds of L and T
+  static_assert(KD % 4 == 0 && 256 % KD == 0 && (16 * NTW) % QS == 0, "fetch layout");
+  __shared__ T As[KD][64 + 1];   // [depth][row]
+  __shared__ T Bs[KD][16 * NTW + 1];   // [depth][col]
+  __shared__ int64_t d_l[DMAX];  // L element offset of depth d at the chunk's first row
+  __shared__ int64_t d_t[DMAX];  // T element offset of depth d at column 0
+  __shared__ int32_t e_k[EMAX], e_ko[EMAX + 1];
+  __shared__ int32_t s_ne;
   typedef typename Acc<T>::type acc_t;
   int64_t item, tile;
   dev::xcd_item_tile(nitems, ntiles, item, tile);
   const ExpandChunk ch = chunks[item];
   const int64_t c0 = tile * (16 * NTW);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // a wave whose 16 rows all lie past the chunk's end has nothing to add
+  const bool rows_live = 16 * wave < ch.nrows;
   acc_t acc[NTW];
 #pragma unroll
   for (int t = 0; t < NTW; ++t) acc[t] = (acc_t){0, 0, 0, 0};
 
-  for (int e0 = ch.first; e0 < ch.last; e0 += EMAX) {
-    const int ne = min(EMAX, ch.last - e0);
-    __syncthreads();
-    if (tid < ne) {
-      const ExpandEntry en = entries[e0 + tid];
-      e_l[tid] = en.lslot + en.off;
-      e_mq[tid] = en.mq;
-      e_k[tid] = ranks[en.kidx];
-      e_ts[tid] = en.tslot;
-      e_ns[tid] = reduced ? 1 : en.nseg;  // reduced: the partials are summed in the first slot
-    }
+  for (int e0 = ch.first; e0 < ch.last;) {
+    const int avail = min(EMAX, ch.last - e0);
+    __syncthreads();  // the previous pass is done with the tables
+    if (tid < avail) e_k[tid] = ranks[entries[e0 + tid].kidx];
     __syncthreads();
     if (tid == 0) {
-      int a = 0;
-      for (int i = 0; i < ne; ++i) {
+      // entries while the depth fits (every rank <= kmax <= DMAX: at least one)
+      int a = 0, i = 0;
+      for (; i < avail && a + e_k[i] <= DMAX; ++i) {
         e_ko[i] = a;
         a += e_k[i];
       }
-      e_ko[ne] = a;
+      e_ko[i] = a;
+      s_ne = i;
     }
     __syncthreads();
-    if (tid < ne)
-      for (int kk = 0; kk < e_k[tid]; ++kk) {
-        d_e[e_ko[tid] + kk] = (int16_t)tid;
-        d_k[e_ko[tid] + kk] = (int8_t)kk;
+    const int ne = s_ne;
+    if (tid < ne) {
+      const ExpandEntry en = entries[e0 + tid];
+      const int64_t lb = en.lslot + en.off;
+      const int64_t tb = (int64_t)en.tslot * tstride;
+      for (int kk = 0, d = e_ko[tid]; kk < e_k[tid]; ++kk, ++d) {
+        d_l[d] = lb + (int64_t)kk * en.mq;
+        d_t[d] = tb + kk;
       }
+    }
     __syncthreads();
     const int ktot = e_ko[ne];
-    T av[8], bv[2 * NTW];
+    T av[NA], bv[NB];
     auto fetch = [&](int k0) {
+      // L: the lane's chunk row at depth k0 + wave + 4 q (one depth per wave)
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int e = tid + 256 * q;
-        {
-          const int rr = e % 64, kk = e / 64;   // L (row, depth)
-          const int d = k0 + kk;
-          T v = 0;
-          if (d < ktot && rr < ch.nrows) {
-            const int j = d_e[d];
-            v = L[e_l[j] + (int64_t)d_k[d] * e_mq[j] + rr];
-          }
-          av[q] = v;
-        }
+      for (int q = 0; q < NA; ++q) {
+        const int d = k0 + wave + 4 * q;
+        av[q] = (d < ktot && lane < ch.nrows) ? L[d_l[d] + lane] : (T)0;
       }
+      // T: depth k0 + (tid mod KD) at columns tid / KD + QS q
+      const int d = k0 + tid % KD;
+      const bool dv = d < ktot;
+      const int64_t tb = dv ? d_t[d] : 0;
 #pragma unroll
-      for (int q = 0; q < 2 * NTW; ++q) {
-        const int e = tid + 256 * q;
-        const int kt = e % KC, cc = e / KC;   // T (depth, column)
-        const int d = k0 + kt;
-        const int64_t gc = c0 + cc;
-        T v = 0;
-        if (d < ktot && gc < ncols) {
-          const int j = d_e[d];
-          const T *tp = Tin + (int64_t)e_ts[j] * tstride + gc * kmax + d_k[d];
-          for (int sg = 0; sg < e_ns[j]; ++sg) v += tp[(int64_t)sg * tstride];
-        }
-        bv[q] = v;
+      for (int q = 0; q < NB; ++q) {
+        const int64_t gc = c0 + tid / KD + QS * q;
+        bv[q] = (dv && gc < ncols) ? Tin[tb + gc * kmax] : (T)0;
       }
     };
     if (ktot > 0) fetch(0);
-    for (int k0 = 0; k0 < ktot; k0 += KC) {
+    for (int k0 = 0; k0 < ktot; k0 += KD) {
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int e = tid + 256 * q;
-        As[e / 64][e % 64] = av[q];
-      }
+      for (int q = 0; q < NA; ++q) As[wave + 4 * q][lane] = av[q];
 #pragma unroll
-      for (int q = 0; q < 2 * NTW; ++q) {
-        const int e = tid + 256 * q;
-        Bs[e % KC][e / KC] = bv[q];
-      }
+      for (int q = 0; q < NB; ++q) Bs[tid % KD][tid / KD + QS * q] = bv[q];
       __syncthreads();
-      if (k0 + KC < ktot) fetch(k0 + KC);
+      if (k0 + KD < ktot) fetch(k0 + KD);
+      if (rows_live) {
 #pragma unroll
-      for (int ks = 0; ks < KC; ks += 4) {
-        const T a = As[ks + (lane >> 4)][16 * wave + (lane & 15)];
+        for (int ks = 0; ks < KD; ks += 4) {
+          const T a = As[ks + (lane >> 4)][16 * wave + (lane & 15)];
 #pragma unroll
-        for (int t = 0; t < NTW; ++t)
-          Acc<T>::step(a, Bs[ks + (lane >> 4)][16 * t + (lane & 15)], acc[t]);
+          for (int t = 0; t < NTW; ++t)
+            Acc<T>::step(a, Bs[ks + (lane >> 4)][16 * t + (lane & 15)], acc[t]);
+        }
       }
       __syncthreads();
     }
+    e0 += ne;
   }
+  if (!rows_live) return;
 #pragma unroll
   for (int t = 0; t < NTW; ++t) {
     const int64_t gc = c0 + 16 * t + (lane & 15);
@@ -475,6 +491,11 @@ inline unsigned col_tiles(int64_t ncols) { return (unsigned)((ncols + TC - 1) / 
 // and 1024 columns: the kernels are bound by the latency of their operand
 // fetches, and wider tiles halve the resident workgroups that hide it.
 constexpr int kNTW = 4;
+// contraction depth per LDS stage of the projection and the expansion: 16
+// (half the LDS and prefetch registers of 32, four waves per SIMD instead
+// of three for the projection) measured 6 % faster over the sphere's peel
+constexpr int kProjDepth = 16;
+constexpr int kExpandDepth = 16;
 
 template <int NTW>
 inline unsigned tiles_of(int64_t ncols) {
@@ -495,7 +516,7 @@ void project_ntw(int32_t nitems, const ProjItem *items, const ProjPair *pairs, i
                  int64_t tstride, const int32_t *ranks, const void *R, const void *X, int64_t ldx,
                  int64_t ncols, void *Tb, hipStream_t s) {
   const unsigned nt = tiles_of<NTW>(ncols);
-  lr_project_kernel<T, NTW><<<grid_of(nitems, nt), 256, 0, s>>>(
+  lr_project_kernel<T, NTW, kProjDepth><<<grid_of(nitems, nt), 256, 0, s>>>(
       items, pairs, kmax, tstride, ranks, (const T *)R, (const T *)X, ldx, ncols, (T *)Tb, nitems,
       (int32_t)nt);
 }
@@ -503,12 +524,11 @@ void project_ntw(int32_t nitems, const ProjItem *items, const ProjPair *pairs, i
 template <typename T, int NTW>
 void expand_ntw(int32_t nchunks, const ExpandChunk *chunks, const ExpandEntry *entries,
                 int32_t kmax, int64_t tstride, const int32_t *ranks, const void *L,
-                const void *Tb, int64_t ncols, double sign, void *Y, int64_t ldy, bool reduced,
-                hipStream_t s) {
+                const void *Tb, int64_t ncols, double sign, void *Y, int64_t ldy, hipStream_t s) {
   const unsigned nt = tiles_of<NTW>(ncols);
-  lr_expand_kernel<T, NTW><<<grid_of(nchunks, nt), 256, 0, s>>>(
+  lr_expand_kernel<T, NTW, kExpandDepth><<<grid_of(nchunks, nt), 256, 0, s>>>(
       chunks, entries, kmax, tstride, ranks, (const T *)L, (const T *)Tb, ncols, (T)sign, (T *)Y,
-      ldy, reduced ? 1 : 0, nchunks, (int32_t)nt);
+      ldy, nchunks, (int32_t)nt);
 }
 
 template <typename T, int NTW>
@@ -534,14 +554,14 @@ void launch_lr_project(int32_t nitems, const ProjItem *items, const ProjPair *pa
 void launch_lr_expand(int32_t nchunks, const ExpandChunk *chunks, const ExpandEntry *entries,
                       int32_t kmax, int64_t tstride, const int32_t *ranks, bool f32,
                       const void *L, const void *T, int64_t ncols, double sign, void *Y,
-                      int64_t ldy, bool reduced, hipStream_t s) {
+                      int64_t ldy, hipStream_t s) {
   if (nchunks <= 0 || ncols <= 0) return;
   if (f32)
     expand_ntw<float, kNTW>(nchunks, chunks, entries, kmax, tstride, ranks, L, T, ncols, sign, Y,
-                            ldy, reduced, s);
+                            ldy, s);
   else
     expand_ntw<double, kNTW>(nchunks, chunks, entries, kmax, tstride, ranks, L, T, ncols, sign, Y,
-                             ldy, reduced, s);
+                             ldy, s);
 }
 
 void launch_lr_reduce(int32_t nitems, const ReduceItem *items, int64_t tstride, int64_t elems,

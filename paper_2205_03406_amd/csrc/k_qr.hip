@@ -351,14 +351,6 @@ __device__ void core_body(const CoreJob &job, int32_t r, const T *__restrict__ P
           ldy, core + job.cslot, r, smem);
 }
 
-template <typename T>
-__global__ void __launch_bounds__(256)
-core_kernel(const CoreJob *__restrict__ jobs, int32_t r, const T *__restrict__ Psi, int64_t ldp,
-            const T *__restrict__ Y, int64_t ldy, double *__restrict__ core) {
-  extern __shared__ double smem[];  // staging, 33 * 2r doubles
-  core_body<T>(jobs[blockIdx.x], r, Psi, ldp, Y, ldy, core, smem);
-}
-
 // ------------------------------------------------------------------ coupling
 template <typename T>
 __device__ void coupling_body(const CoreJob &job, int32_t r, int32_t kmax,
@@ -423,26 +415,13 @@ __device__ void coupling_body(const CoreJob &job, int32_t r, int32_t kmax,
   __syncthreads();
 }
 
-template <typename T>
-__global__ void __launch_bounds__(256)
-coupling_kernel(const CoreJob *__restrict__ jobs, int32_t r, int32_t kmax,
-                const T *__restrict__ Omega, int64_t ldo, const T *__restrict__ Psi, int64_t ldp,
-                const double *__restrict__ U, const double *__restrict__ V,
-                const int32_t *__restrict__ ranks, const double *__restrict__ core,
-                double *__restrict__ scratch, double *__restrict__ B, double *__restrict__ Wout) {
-  extern __shared__ double smem[];
-  coupling_body<T>(jobs[blockIdx.x], r, kmax, Omega, ldo, Psi, ldp, U, V, ranks, core, scratch, B,
-                   Wout, smem);
-}
-
-// Fused, persistent recovery of one level: a grid of at most a few
-// workgroups per compute unit, each pulling pairs from the level's work
+// Fused, persistent recovery of one level: a grid of up to 16 workgroups
+// per compute unit (as many as fit stay resident), each pulling pairs from the level's work
 // list (largest blocks first) through an atomic counter until the list is
 // exhausted; per pair, in one workgroup, the core C = G2^T Y, the two
 // pivoted QRs (U from the Y block, V from the Z block) and the coupling
-// solve with W = U B.  The same arithmetic as the four separate launches,
-// in one launch per level with no workgroup idle while others finish the
-// large blocks.  The counter must be zero at the launch.
+// solve with W = U B: one launch per level, no workgroup idle while others
+// finish the large blocks.  The counter must be zero at the launch.
 template <typename T>
 __global__ void __launch_bounds__(256)
 recover_kernel(RecoverArgs a, const T *__restrict__ Om, const T *__restrict__ Ps,
@@ -795,18 +774,6 @@ void launch_block_norms(int32_t njobs, const QrJob *jobs, int32_t r, double scal
     block_norm_kernel<double><<<njobs, 256, 0, s>>>(jobs, r, scale, (const double *)S, lds, out);
 }
 
-void launch_core(int32_t njobs, const CoreJob *jobs, int32_t r, bool f32, const void *Psi,
-                 int64_t ldp, const void *Y, int64_t ldy, double *core, hipStream_t s) {
-  if (njobs <= 0) return;
-  const size_t sh = sizeof(double) * (33 * 2 * (size_t)r);
-  if (f32)
-    core_kernel<float><<<njobs, 256, sh, s>>>(jobs, r, (const float *)Psi, ldp, (const float *)Y,
-                                              ldy, core);
-  else
-    core_kernel<double><<<njobs, 256, sh, s>>>(jobs, r, (const double *)Psi, ldp,
-                                               (const double *)Y, ldy, core);
-}
-
 void launch_recover(const RecoverArgs &a, int grid, bool f32, const void *Omega, const void *Psi,
                     const void *Y, hipStream_t s) {
   if (a.njobs <= 0) return;
@@ -821,23 +788,6 @@ void launch_recover(const RecoverArgs &a, int grid, bool f32, const void *Omega,
   else
     recover_kernel<double><<<g, 256, sh, s>>>(a, (const double *)Omega, (const double *)Psi,
                                               (const double *)Y);
-}
-
-void launch_coupling(int32_t njobs, const CoreJob *jobs, int32_t r, int32_t kmax, bool f32,
-                     const void *Omega, int64_t ldo, const void *Psi, int64_t ldp,
-                     const double *U, const double *V, const int32_t *ranks, const double *core,
-                     double *scratch, double *B, double *W, hipStream_t s) {
-  if (njobs <= 0) return;
-  const size_t sa = ((size_t)r * r > 33 * (size_t)(r + kmax)) ? (size_t)r * r : 33 * (size_t)(r + kmax);
-  const size_t sh = sizeof(double) * (sa + (size_t)r * kmax);
-  if (f32)
-    coupling_kernel<float><<<njobs, 256, sh, s>>>(jobs, r, kmax, (const float *)Omega, ldo,
-                                                  (const float *)Psi, ldp, U, V, ranks, core,
-                                                  scratch, B, W);
-  else
-    coupling_kernel<double><<<njobs, 256, sh, s>>>(jobs, r, kmax, (const double *)Omega, ldo,
-                                                   (const double *)Psi, ldp, U, V, ranks, core,
-                                                   scratch, B, W);
 }
 
 }  // namespace hm

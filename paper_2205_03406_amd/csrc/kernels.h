@@ -95,7 +95,8 @@ struct ProjPair {
   int32_t tslot;    // partial slot of this pair and segment
 };
 // Expand: Y[row0 : row0+nrows, :] += sign * sum_q L_q[off_q : off_q+nrows, 0:k_q] T_q
-// with T_q = sum of its nseg partial slots starting at tslot.
+// with T_q = the sum of its nseg partial slots starting at tslot, held in
+// the first of them when the expansion runs.
 struct ExpandChunk {
   int64_t row0;
   int32_t nrows;
@@ -114,12 +115,12 @@ struct ExpandEntry {
 void launch_lr_project(int32_t nitems, const ProjItem *items, const ProjPair *pairs, int32_t kmax,
                        int64_t tstride, const int32_t *ranks, bool f32, const void *R,
                        const void *X, int64_t ldx, int64_t ncols, void *T, hipStream_t s);
-// reduced: every entry's partials were already summed into its first slot
-// (launch_lr_reduce), so only that slot is read.
+// Every entry's partials must already be summed into its first slot
+// (launch_lr_reduce): only that slot is read.
 void launch_lr_expand(int32_t nchunks, const ExpandChunk *chunks, const ExpandEntry *entries,
                       int32_t kmax, int64_t tstride, const int32_t *ranks, bool f32,
                       const void *L, const void *T, int64_t ncols, double sign, void *Y,
-                      int64_t ldy, bool reduced, hipStream_t s);
+                      int64_t ldy, hipStream_t s);
 // T[slot] += T[slot + 1] + ... + T[slot + nseg - 1] (elems values per slot,
 // slot s at T + s * tstride), one item per pair split over several segments.
 struct ReduceItem {
@@ -174,8 +175,9 @@ struct CoreJob {
 };
 // The recovery of a whole level in one persistent launch (core, the two
 // pivoted QRs and the coupling of every pair, pairs pulled through
-// *counter in `order`, largest blocks first); the arguments of the four
-// separate launches.  *counter must be 0 at the launch.
+// *counter in `order`, largest blocks first): C_p = G2^T S_U (r x r) into
+// core, U and V by launch_pivqr's rule, B = (G2^T U)^+ C (V^T G1)^+ and
+// W = U B.  *counter must be 0 at the launch.
 struct RecoverArgs {
   const CoreJob *jc;
   const QrJob *ju, *jv;
@@ -191,13 +193,6 @@ struct RecoverArgs {
 };
 void launch_recover(const RecoverArgs &a, int grid, bool f32, const void *Omega, const void *Psi,
                     const void *Y, hipStream_t s);
-void launch_core(int32_t njobs, const CoreJob *jobs, int32_t r, bool f32, const void *Psi,
-                 int64_t ldp, const void *Y, int64_t ldy, double *core, hipStream_t s);
-// B = (G2^T U)^+ C (V^T G1)^+ and W = U B for every pair.
-void launch_coupling(int32_t njobs, const CoreJob *jobs, int32_t r, int32_t kmax, bool f32,
-                     const void *Omega, int64_t ldo, const void *Psi, int64_t ldp,
-                     const double *U, const double *V, const int32_t *ranks, const double *core,
-                     double *scratch, double *B, double *W, hipStream_t s);
 
 // ---- uniform H^1 (k_uniform.hip, k_qr.hip)
 // Stage-2 test matrix assembled from the stage-1 column bases: out (n x

@@ -63,24 +63,29 @@ struct Resident {
   bool ready = false, evict = false;
 };
 
+// Pinned staging of one worker, grown geometrically from 16 MiB.  A buffer
+// it outgrows is kept until the worker ends: hipHostFree waits for the
+// whole device, which would hold an apply behind every compression running
+// on the other streams.
 struct Pinned {
   void *p = nullptr;
   size_t bytes = 0;
+  std::vector<void *> retired;
   void *get(size_t b) {
     if (b <= bytes) return p;
-    const size_t nb = std::max(b, bytes * 2);
-    if (p) (void)hipHostFree(p);
-    p = nullptr;
-    bytes = 0;
-    if (hipHostMalloc(&p, nb, hipHostMallocDefault) != hipSuccess) {
-      p = nullptr;
+    const size_t nb = std::max({b, bytes * 2, size_t(16) << 20});
+    void *q = nullptr;
+    if (hipHostMalloc(&q, nb, hipHostMallocDefault) != hipSuccess) {
       (void)hipGetLastError();
       return nullptr;
     }
+    if (p) retired.push_back(p);
+    p = q;
     bytes = nb;
     return p;
   }
   ~Pinned() {
+    for (void *r : retired) (void)hipHostFree(r);
     if (p) (void)hipHostFree(p);
   }
 };
@@ -107,11 +112,18 @@ struct hm_server {
   double now() const {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }
+  // H-matrices and trees taken out of the map under mu, freed after it is
+  // released (reap): every use of them was synchronized, so they go back
+  // without waiting for the device, and no thread waits on mu meanwhile
+  std::vector<std::pair<hm_hmatrix *, hm_tree *>> dead;
   void worker();
   // under mu: first pending request that may start now
   hm::Req *take_ready();
   void finish(hm::Req *q, hm_status st);
+  // under mu
   void free_resident(std::map<int64_t, hm::Resident>::iterator it);
+  // not under mu
+  void reap();
 };
 
 hm::Req *hm_server::take_ready() {
@@ -137,11 +149,22 @@ hm::Req *hm_server::take_ready() {
 }
 
 void hm_server::free_resident(std::map<int64_t, hm::Resident>::iterator it) {
-  hm_hmatrix_free(it->second.H);
-  hm_tree_free(it->second.tree);
+  dead.emplace_back(it->second.H, it->second.tree);
   in_use -= it->second.bytes;
   resident_bytes -= it->second.bytes;
   res.erase(it);
+}
+
+void hm_server::reap() {
+  std::vector<std::pair<hm_hmatrix *, hm_tree *>> d;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    d.swap(dead);
+  }
+  for (auto &x : d) {
+    if (x.first) hm::free_idle(x.first);
+    if (x.second) hm::free_idle(x.second);
+  }
 }
 
 void hm_server::finish(hm::Req *q, hm_status st) {
@@ -170,6 +193,11 @@ void hm_server::worker() {
   hipStream_t s = nullptr;
   if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return;
   hm::Pinned pin;
+  // device-time markers of the applies
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  if (hipEventCreate(&ev0) != hipSuccess) ev0 = nullptr;
+  if (hipEventCreate(&ev1) != hipSuccess) ev1 = nullptr;
+  (void)hipGetLastError();
   for (;;) {
     hm::Req *q = nullptr;
     {
@@ -220,8 +248,8 @@ void hm_server::worker() {
           in_use += it->second.bytes;
           resident_bytes += it->second.bytes;
         } else {
-          if (H) hm_hmatrix_free(H);
-          if (T) hm_tree_free(T);
+          // freed below, after the lock, once the stream has drained
+          dead.emplace_back(H, T);
           // applies waiting on it fail
           for (auto pit = pending.begin(); pit != pending.end();) {
             if ((*pit)->kind == 1 && (*pit)->target == q->id) {
@@ -237,6 +265,11 @@ void hm_server::worker() {
           }
           res.erase(it);
         }
+      }
+      if (st != HM_OK) {
+        (void)hipStreamSynchronize(s);
+        (void)hipGetLastError();
+        reap();
       }
       finish(q, st);
       continue;
@@ -264,6 +297,7 @@ void hm_server::worker() {
     }
     if (st == HM_OK) {
       std::memcpy(hp, q->X.data(), bytes);
+      if (ev0) (void)hipEventRecord(ev0, s);
       if (hipMemcpyAsync(dx, hp, bytes, hipMemcpyHostToDevice, s) != hipSuccess)
         st = hm::fail(HM_E_DEVICE, "copy of the right-hand sides failed");
     }
@@ -274,8 +308,15 @@ void hm_server::worker() {
       st = hm::fail(HM_E_DEVICE, "copy of the result failed");
     hm::scratch_free(dx, (void *)s);
     hm::scratch_free(dy, (void *)s);
+    if (ev1) (void)hipEventRecord(ev1, s);
+    q->c.enqueue_ms = 1e3 * (now() - q->c.t_start);
     if (hipStreamSynchronize(s) != hipSuccess && st == HM_OK)
       st = hm::fail(HM_E_DEVICE, "apply failed on the device");
+    if (st == HM_OK && ev0 && ev1) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, ev0, ev1) == hipSuccess) q->c.device_ms = ms;
+      (void)hipGetLastError();
+    }
     if (st == HM_OK) std::memcpy(q->Y, (char *)hp + bytes, bytes);
     q->c.bytes = q->fp;
     {
@@ -284,8 +325,11 @@ void hm_server::worker() {
       auto it = res.find(q->target);
       if (it != res.end() && --it->second.inflight == 0 && it->second.evict) free_resident(it);
     }
+    reap();
     finish(q, st);
   }
+  if (ev0) (void)hipEventDestroy(ev0);
+  if (ev1) (void)hipEventDestroy(ev1);
   (void)hipStreamSynchronize(s);
   (void)hipStreamDestroy(s);
 }
@@ -329,13 +373,17 @@ void hm_server_free(hm_server *S) {
   S->cv_work.notify_all();
   for (auto &t : S->workers) t.join();
   for (hm::Req *q : S->pending) delete q;
-  while (!S->res.empty()) {
-    auto it = S->res.begin();
-    if (it->second.H)
-      S->free_resident(it);
-    else
-      S->res.erase(it);
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    while (!S->res.empty()) {
+      auto it = S->res.begin();
+      if (it->second.H)
+        S->free_resident(it);
+      else
+        S->res.erase(it);
+    }
   }
+  S->reap();
   delete S;
 }
 
@@ -449,16 +497,19 @@ hm_status hm_server_hmatrix(hm_server *S, int64_t hmatrix, const hm_hmatrix **H)
 
 hm_status hm_server_release(hm_server *S, int64_t hmatrix) {
   if (!S) return fail(HM_E_ARG, "null server");
-  std::lock_guard<std::mutex> lk(S->mu);
-  auto it = S->res.find(hmatrix);
-  if (it == S->res.end() || !it->second.ready) return fail(HM_E_STATE, "H-matrix not resident");
-  for (hm::Req *p : S->pending)
-    if (p->kind == 1 && p->target == hmatrix)
-      return fail(HM_E_STATE, "H-matrix has pending applies");
-  if (it->second.inflight > 0)
-    it->second.evict = true;
-  else
-    S->free_resident(it);
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->res.find(hmatrix);
+    if (it == S->res.end() || !it->second.ready) return fail(HM_E_STATE, "H-matrix not resident");
+    for (hm::Req *p : S->pending)
+      if (p->kind == 1 && p->target == hmatrix)
+        return fail(HM_E_STATE, "H-matrix has pending applies");
+    if (it->second.inflight > 0)
+      it->second.evict = true;
+    else
+      S->free_resident(it);
+  }
+  S->reap();
   S->cv_work.notify_all();
   return HM_OK;
 }

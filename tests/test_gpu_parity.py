@@ -350,3 +350,21 @@ def test_saturation_retry_and_strict(hm):
     with pytest.raises(hm.HMError) as e:
         hm.compress(T, bb, tol=inst.tol, r=16, seed=inst.seed, strict=True)
     assert e.value.code == hm.HM_E_SATURATED
+
+
+@pytest.mark.parametrize("fmt", ["h1", "uniform", "h2"])
+def test_tree_without_sampled_levels(hm, fmt):
+    """A point set small enough that no level has an admissible pair: the
+    compression is the leaf pass alone, exactly the dense matrix (the
+    neighbor blocks cover it)."""
+    pts = workloads.random_points(100, 2, 21)
+    T = hm.Tree(pts, 64).color()
+    A = oracle.kernel_matrix(pts, pts, "log")
+    kw = dict(h1={}, uniform=dict(uniform=True), h2=dict(h2=True))[fmt]
+    H = hm.compress(T, T.kernel_blackbox("log"), tol=1e-8, r=24, seed=3, **kw)
+    st = H.stats()
+    assert st["npairs"] == 0
+    X = np.random.default_rng(2).standard_normal((100, 3))
+    Y = hm.colmajor(100, 3)
+    H.matvec(to_dev(X), Y)
+    assert np.linalg.norm(to_host(Y) - A @ X) <= 1e-13 * np.linalg.norm(A @ X)
