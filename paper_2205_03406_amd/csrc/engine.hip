@@ -724,10 +724,20 @@ void build_plans(const hm_hmatrix &H, const Tree &T, int32_t seg, bool prefixes,
   }
 }
 
+// The peel's zero pattern of X and the scratch for the projection's tile
+// flags (bytes; one per slot and 64-column tile of a column chunk)
+struct PeelPattern {
+  ColorPattern pat;
+  uint8_t *flags;
+  int64_t flag_cap;
+};
+
 // Y +=/-= (first li_end levels of H) X; T is scratch of tcap elements.
+// pp: X is a colored test matrix with that zero pattern (peel plans only).
 void apply_levels(const hm_hmatrix &H, size_t li_end, bool trans, bool f32, const void *X,
                   int64_t ldx, int64_t ncols, void *Y, int64_t ldy, double sign, void *T,
-                  int64_t tcap, hipStream_t s, const hm_hmatrix::Orient *plans = nullptr) {
+                  int64_t tcap, hipStream_t s, const hm_hmatrix::Orient *plans = nullptr,
+                  const PeelPattern *pp = nullptr) {
   if (li_end == 0 || ncols <= 0) return;
   // plans: the two orientations' plans to use (the peel's), else the matrix's own
   const hm_hmatrix::Orient &O = plans ? plans[trans ? 1 : 0] : (trans ? H.oT : H.oA);
@@ -743,18 +753,30 @@ void apply_levels(const hm_hmatrix &H, size_t li_end, bool trans, bool f32, cons
   if (cw < 1) throw Error{HM_E_NOMEM, "low-rank scratch too small"};
   cw = std::min<int64_t>(cw, ncols);
   if (cw < ncols && cw >= 64) cw = cw / 64 * 64;
+  // a tile the projection leaves unwritten must not reach a reduction
+  if (pp && O.red_upto[li_end] > 0)
+    throw Error{HM_E_STATE, "zero-pattern projection on segmented plans"};
   for (int64_t c0 = 0; c0 < ncols; c0 += cw) {
     const int64_t w = std::min(cw, ncols - c0);
     const int64_t tstride = (int64_t)H.kmax * w;
+    ColorPattern cp{};
+    uint8_t *flags = nullptr;
+    if (pp) {
+      cp = pp->pat;
+      cp.col0 += c0;
+      flags = pp->flags;
+      if (nslots * ((w + kLowRankTile - 1) / kLowRankTile) > pp->flag_cap)
+        throw Error{HM_E_STATE, "projection flag scratch too small"};
+    }
     launch_lr_project(nitems, O.items.as<ProjItem>(), O.ppairs.as<ProjPair>(), H.kmax, tstride,
                       H.ranks.as<int32_t>(), f32, Rp, (const char *)X + c0 * ldx * es, ldx, w, T,
-                      s);
+                      pp ? &cp : nullptr, flags, s);
     // partials of pairs split over segments summed once, not per output chunk
     launch_lr_reduce(O.red_upto[li_end], O.red.as<ReduceItem>(), tstride, tstride, f32, T, s);
     LAUNCH_CHECK();
     launch_lr_expand(O.nch[li_end], O.chunks[li_end].as<ExpandChunk>(),
                      O.entries[li_end].as<ExpandEntry>(), H.kmax, tstride, H.ranks.as<int32_t>(),
-                     f32, Lp, T, w, sign, (char *)Y + c0 * ldy * es, ldy, s);
+                     f32, Lp, T, w, sign, (char *)Y + c0 * ldy * es, ldy, flags, s);
     LAUNCH_CHECK();
   }
 }
@@ -1063,6 +1085,14 @@ struct Compression {
   int32_t mw = 0;
   int64_t cmax = 0, leaf_cols = 0, wcols = 0, tcap = 0, cmax_np = 0;
   DBuf Xb, Yb, tmpx, tmpy, Tb, work, core, scratch, sat, flag, floor_u, floor_v;
+  DBuf tflags, leaf_act;     // projection tile flags; leaf colors of every leaf box
+  int64_t tflag_cap = 0;
+  // host copies of the peel's zero patterns (the work count of finalize):
+  // per level its (box, color) activity and color count (empty: the level's
+  // peel runs dense), and the leaf pass's
+  std::vector<std::vector<uint8_t>> h_act;
+  std::vector<int32_t> h_act_nc;
+  std::vector<uint8_t> h_leaf_act;
   struct LevelJobs {
     DBuf act, ju, jv, jc, kit;
     DBuf order;  // pairs by block size, largest first (the fused recovery's work list)
@@ -1343,6 +1373,15 @@ hm_status Compression::setup(hipStream_t s) {
     tcap = std::max<int64_t>(std::min(need, kTScratchCap), std::max<int64_t>(slots * kmax * 64, 64));
   }
   buf(Tb, (size_t)tcap * tes, s);
+  {
+    // one flag per slot and 64-column tile: a chunk of w columns uses
+    // slots * ceil(w / 64) <= tcap / (kmax 64) + slots
+    const int64_t slots = std::max<int64_t>(
+        peel_plans[0].slots_upto.empty() ? 0 : peel_plans[0].slots_upto.back(),
+        peel_plans[1].slots_upto.empty() ? 0 : peel_plans[1].slots_upto.back());
+    tflag_cap = tcap / ((int64_t)std::max(kmax, 1) * kLowRankTile) + slots + 64;
+    buf(tflags, (size_t)tflag_cap, s);
+  }
   int64_t wmax = 0;
   for (size_t li = 0; li < H->lv.size(); ++li) {
     const hm_hmatrix::Lv &L = H->lv[li];
@@ -1387,6 +1426,10 @@ hm_status Compression::setup(hipStream_t s) {
     setup_uniform(s);
   }
   jobs_of.resize(H->lv.size());
+  if (!uniform) {
+    h_act.assign(H->lv.size(), {});
+    h_act_nc.assign(H->lv.size(), 0);
+  }
   for (size_t li = 0; !uniform && li < H->lv.size(); ++li) {
     hm_hmatrix::Lv &L = H->lv[li];
     const Graph &G = T.graphs[L.level];
@@ -1394,6 +1437,8 @@ hm_status Compression::setup(hipStream_t s) {
     const int64_t cpad = pad16((int64_t)G.ncolors * r);
     std::vector<uint8_t> act((size_t)Lv.nbox() * G.ncolors, 0);
     for (int64_t v = 0; v < G.nv(); ++v) act[(size_t)G.vbox[v] * G.ncolors + G.color[v]] = 1;
+    h_act[li] = act;
+    h_act_nc[li] = G.ncolors;
     std::unordered_map<int64_t, int64_t> pidx;
     pidx.reserve(L.np * 2);
     for (int64_t q = 0; q < L.np; ++q) pidx[(int64_t)L.pa[q] * Lv.nbox() + L.pb[q]] = q;
@@ -1456,6 +1501,11 @@ hm_status Compression::setup(hipStream_t s) {
     put(dib, ib, s);
     put(dic, ic, s);
     nib = (int32_t)ib.size();
+    // the identity blocks' zero pattern: leaf box b is active in color c
+    std::vector<uint8_t> la((size_t)std::max<int64_t>((int64_t)LL.nbox() * GL.ncolors, 1), 0);
+    for (int64_t v = 0; v < GL.nv(); ++v) la[(size_t)GL.vbox[v] * GL.ncolors + GL.color[v]] = 1;
+    put(leaf_act, la, s);
+    h_leaf_act = la;
     std::vector<KItem> kit;
     if (direct) {
       std::vector<int32_t> w = inst_colors(T.nlev());
@@ -1510,6 +1560,8 @@ void Compression::setup_uniform(hipStream_t s) {
   buf(usat, (size_t)std::max<int64_t>(2 * H->nvtot, 1) * 4, s);
 
   ujobs_of.resize(nlv);
+  h_act.assign(nlv, {});
+  h_act_nc.assign(nlv, 0);
   for (size_t li = 0; li < nlv; ++li) {
     const hm_hmatrix::Lv &L = H->lv[li];
     const int l = L.level;
@@ -1590,6 +1642,8 @@ void Compression::setup_uniform(hipStream_t s) {
       J.nkit2 = (int32_t)k2.size();
     }
     J.nmix = (int32_t)mix.size();
+    h_act[li] = act;
+    h_act_nc[li] = UG.ncolors;
     put(J.act, act, s);
     put(J.ju, ju, s);
     put(J.jv, jv, s);
@@ -1674,6 +1728,8 @@ void Compression::setup_h2(hipStream_t s) {
   }
 
   ujobs_of.resize(nlv);
+  h_act.assign(nlv, {});
+  h_act_nc.assign(nlv, 0);
   for (size_t li = 0; li < nlv; ++li) {
     hm_hmatrix::Lv &L = H->lv[li];  // offU, offV point into the box bases (no pair copies)
     const int l = L.level;
@@ -2094,7 +2150,10 @@ void Compression::record_uniform_level(size_t li, hipStream_t s, Events &ev) {
     LAUNCH_CHECK();
   }
   ev.mark(2);
-  apply_levels(*H, li, false, mixed, X, n, c1pad, Y, n, -1.0, Tb.p, tcap, s, peel_plans);
+  const PeelPattern pp1{ColorPattern{Dv.rowbox[l].as<int32_t>(), Dv.start[l].as<int64_t>(),
+                                     J.act.as<uint8_t>(), UG.ncolors, r, 0},
+                        tflags.as<uint8_t>(), tflag_cap};
+  apply_levels(*H, li, false, mixed, X, n, c1pad, Y, n, -1.0, Tb.p, tcap, s, peel_plans, &pp1);
   launch_check_finite(n, c1pad, mixed, Y, n, flag.as<int32_t>(), s);
   LAUNCH_CHECK();
   ev.mark(3);
@@ -2221,8 +2280,12 @@ void Compression::record(hipStream_t s, Events &ev) {
       LAUNCH_CHECK();
     }
     ev.mark(2);
-    apply_levels(*H, li, false, mixed, Om, n, cpad, Yl, n, -1.0, Tb.p, tcap, s, peel_plans);
-    apply_levels(*H, li, true, mixed, Ps, n, cpad, Zl, n, -1.0, Tb.p, tcap, s, peel_plans);
+    // Omega and Psi share the zero pattern of the level's colors
+    const PeelPattern pp{ColorPattern{Dv.rowbox[l].as<int32_t>(), Dv.start[l].as<int64_t>(),
+                                      dact.as<uint8_t>(), G.ncolors, r, 0},
+                         tflags.as<uint8_t>(), tflag_cap};
+    apply_levels(*H, li, false, mixed, Om, n, cpad, Yl, n, -1.0, Tb.p, tcap, s, peel_plans, &pp);
+    apply_levels(*H, li, true, mixed, Ps, n, cpad, Zl, n, -1.0, Tb.p, tcap, s, peel_plans, &pp);
     launch_check_finite(n, 2 * cpad, mixed, Yb.p, n, flag.as<int32_t>(), s);
     LAUNCH_CHECK();
     ev.mark(3);
@@ -2285,12 +2348,18 @@ void Compression::record(hipStream_t s, Events &ev) {
   }
   cols_A += (int64_t)GL.ncolors * mw;
   ev.mark(2);
-  if (h2)
+  if (h2) {
     h2_apply(*H, H->lv.size(), false, mixed, Xb.p, n, leaf_cols, Yb.p, n, -1.0, h2q.as<double>(),
              h2u.as<double>(), h2p.as<double>(), h2cols, s);
-  else
+  } else {
+    // the identity blocks: color c is zero on the leaf boxes not active in it
+    const PeelPattern pl{ColorPattern{Dv.rowbox[T.L()].as<int32_t>(),
+                                      Dv.start[T.L()].as<int64_t>(), leaf_act.as<uint8_t>(),
+                                      GL.ncolors, mw, 0},
+                         tflags.as<uint8_t>(), tflag_cap};
     apply_levels(*H, H->lv.size(), false, mixed, Xb.p, n, leaf_cols, Yb.p, n, -1.0, Tb.p, tcap,
-                 s, peel_plans);
+                 s, peel_plans, &pl);
+  }
   launch_check_finite(n, leaf_cols, mixed, Yb.p, n, flag.as<int32_t>(), s);
   LAUNCH_CHECK();
   ev.mark(3);
@@ -2412,10 +2481,86 @@ hm_status Compression::finalize(hipStream_t s, Events &ev,
   }
   double fbb = 0, bpeel = 0;
   {
-    // peel bytes: a level with coarser factors reads X and reads and writes
-    // Y once (es bytes per element; the uniform formats' stage 2 in FP64)
-    // and reads every coarser factor once (V and W = U B, prev / 2 elements)
     const double es1 = mixed ? 4.0 : 8.0;
+    // Work of a peel through a zero pattern: sampled level ls whose test
+    // matrix has color blocks of colw columns, block c nonzero only on the
+    // boxes active in c (act, nc colors), minus the operator of levels
+    // [0, li_end) in one orientation.  A pair projects only the active
+    // blocks inside its column box (2 k rows colw flops each; an identity
+    // block has one nonzero per row: 2 k rows) and expands only the colors
+    // whose projection is nonzero (2 k |row box| colw each).  Bytes: each
+    // nonzero block of X read once, each Y element some pair updates read
+    // and written once, each factor of a pair with a nonzero projection
+    // read once.
+    auto pattern_peel = [&](size_t li_end, bool trans, const std::vector<uint8_t> &act, int nc,
+                            int64_t colw, int ls, bool identity, double &flops, double &bytes) {
+      if (li_end == 0 || nc <= 0) return;
+      const Level &LS = T.lev[ls];
+      const int words = (nc + 63) / 64;
+      std::vector<uint8_t> xread(act.size(), 0);
+      std::vector<std::vector<uint64_t>> rows_live(li_end);  // per level: colors on each row box
+      for (size_t li = 0; li < li_end; ++li) {
+        const hm_hmatrix::Lv &L = H->lv[li];
+        const Level &Lv = T.lev[L.level];
+        rows_live[li].assign((size_t)Lv.nbox() * words, 0);
+        std::unordered_map<int, std::vector<std::pair<int, int64_t>>> colors_of;  // column box
+        for (int64_t q = 0; q < L.np; ++q) {
+          const int cb = trans ? L.pa[q] : L.pb[q], rb = trans ? L.pb[q] : L.pa[q];
+          const int kv = H->h_ranks[np_total + L.g0 + q];
+          if (kv == 0) continue;
+          auto it = colors_of.find(cb);
+          if (it == colors_of.end()) {
+            std::vector<int64_t> rows(nc, 0);
+            const int64_t s0 = Lv.start[cb], s1 = Lv.start[cb + 1];
+            int b = (int)(std::upper_bound(LS.start.begin(), LS.start.end(), s0) -
+                          LS.start.begin()) - 1;
+            for (b = std::max(b, 0); b < LS.nbox() && LS.start[b] < s1; ++b) {
+              const int64_t m = LS.start[b + 1] - LS.start[b];
+              if (m == 0) continue;
+              for (int c = 0; c < nc; ++c)
+                if (act[(size_t)b * nc + c]) {
+                  rows[c] += m;
+                  xread[(size_t)b * nc + c] = 1;
+                }
+            }
+            std::vector<std::pair<int, int64_t>> v;
+            for (int c = 0; c < nc; ++c)
+              if (rows[c] > 0) v.emplace_back(c, rows[c]);
+            it = colors_of.emplace(cb, std::move(v)).first;
+          }
+          if (it->second.empty()) continue;
+          const int64_t ma = Lv.start[rb + 1] - Lv.start[rb];
+          const int64_t mb = Lv.start[cb + 1] - Lv.start[cb];
+          for (const auto &cr : it->second) {
+            flops += 2.0 * kv * (identity ? (double)cr.second : (double)cr.second * colw);
+            flops += 2.0 * kv * (double)ma * colw;
+            rows_live[li][(size_t)rb * words + cr.first / 64] |= uint64_t(1) << (cr.first % 64);
+          }
+          bytes += es1 * kv * (double)(ma + mb);
+        }
+      }
+      for (size_t e = 0; e < xread.size(); ++e)
+        if (xread[e]) bytes += es1 * (double)(LS.start[e / nc + 1] - LS.start[e / nc]) * colw;
+      // Y: each box of the finest included level, the colors of its ancestors' pairs
+      const int fine = H->lv[li_end - 1].level;
+      const Level &LF = T.lev[fine];
+      std::vector<uint64_t> u(words);
+      for (int a = 0; a < LF.nbox(); ++a) {
+        std::fill(u.begin(), u.end(), 0);
+        for (size_t li = 0; li < li_end; ++li) {
+          int b = a;
+          for (int l = fine; l > H->lv[li].level; --l) b = T.lev[l].parent[b];
+          for (int w = 0; w < words; ++w) u[w] |= rows_live[li][(size_t)b * words + w];
+        }
+        int64_t cnt = 0;
+        for (int w = 0; w < words; ++w) cnt += __builtin_popcountll(u[w]);
+        bytes += 2.0 * es1 * (double)(LF.start[a + 1] - LF.start[a]) * cnt * colw;
+      }
+    };
+    // Dense peel bytes (a level without a pattern: H^2, the uniform
+    // format's stage 2): X read and Y read and written once (es bytes per
+    // element; stage 2 in FP64), every coarser factor read once (V and
+    // W = U B, prev / 2 elements).
     std::vector<double> prev(ni, 0.0);
     for (size_t li = 0; li < H->lv.size(); ++li) {
       const int l = H->lv[li].level;
@@ -2428,17 +2573,31 @@ hm_status Compression::finalize(hipStream_t s, Events &ev,
           wu[i] = std::max(wu[i], UG.color[v] + 1);
         }
       }
+      const bool pat = li < h_act.size() && !h_act[li].empty();
       for (int i = 0; i < ni; ++i) {
         // columns of the Y and Z passes
         const double c = uniform ? (double)wu[i] * r + (double)w[i] * kmax : 2.0 * w[i] * r;
         const double ni_rows = (double)(T.inst_off[i + 1] - T.inst_off[i]);
-        fpeel += c * prev[i];
         fbb += 2.0 * ni_rows * ni_rows * c;
+        if (pat) {
+          if (uniform && prev[i] > 0) {
+            // stage 2 (A*) runs dense
+            fpeel += (double)w[i] * kmax * prev[i];
+            bpeel += 3.0 * ni_rows * (double)w[i] * kmax * 8.0 + 8.0 * prev[i] / 2.0;
+          }
+          continue;
+        }
+        fpeel += c * prev[i];
         if (prev[i] > 0) {
           const double sbytes = uniform ? (double)wu[i] * r * es1 + (double)w[i] * kmax * 8.0
                                         : c * es1;
           bpeel += 3.0 * ni_rows * sbytes + (uniform ? es1 + 8.0 : es1) * prev[i] / 2.0;
         }
+      }
+      if (pat) {
+        // A (both formats) and A* (H^1) through the level's pattern
+        pattern_peel(li, false, h_act[li], h_act_nc[li], r, l, false, fpeel, bpeel);
+        if (!uniform) pattern_peel(li, true, h_act[li], h_act_nc[li], r, l, false, fpeel, bpeel);
       }
       for (int i = 0; i < ni; ++i) prev[i] += apply_cost_of[li][i];
     }
@@ -2452,10 +2611,13 @@ hm_status Compression::finalize(hipStream_t s, Events &ev,
     }
     for (int i = 0; i < ni; ++i) {
       const double ni_rows = (double)(T.inst_off[i + 1] - T.inst_off[i]);
-      fpeel += (double)wl[i] * mwi[i] * prev[i];
       fbb += 2.0 * ni_rows * ni_rows * (double)wl[i] * mwi[i];
+      if (!h2) continue;
+      fpeel += (double)wl[i] * mwi[i] * prev[i];
       if (prev[i] > 0) bpeel += 3.0 * ni_rows * (double)wl[i] * mwi[i] * es1 + es1 * prev[i] / 2.0;
     }
+    if (!h2)
+      pattern_peel(H->lv.size(), false, h_leaf_act, GL.ncolors, mw, T.L(), true, fpeel, bpeel);
   }
   st.nfloats = nfloats;
   st.flops_blackbox = fbb;

@@ -57,6 +57,12 @@ constexpr int PMAX = 128;  // packed output rows of one projection item
 // are packed end to end (actual device ranks) into at most PMAX output rows,
 // all of them accumulated in one sweep over the item's rows (NP passes of
 // 64 output rows side by side), so each X tile is fetched once per item.
+// Given the zero pattern of a colored X, the sweep covers only the rows of
+// the sampled level's boxes that are active in a color of the column tile
+// (their segments listed in LDS first); elsewhere X is zero in the tile.
+// A box holds about one active color of the 50 to 100 of a level, so most
+// tiles of most items have no rows to sweep at all: T is left unwritten
+// and the tile flagged 0 for the expansion.
 // (Walking several column tiles per workgroup, to set the packing up once
 // and keep the prefetch running across tiles, measured slower at 2 and 4
 // tiles: neighbouring workgroups then no longer share X rows in L2.)
@@ -65,8 +71,10 @@ __global__ void __launch_bounds__(256, 2)
 lr_project_kernel(const ProjItem *__restrict__ items, const ProjPair *__restrict__ pairs,
                   int32_t kmax, int64_t tstride, const int32_t *__restrict__ ranks,
                   const T *__restrict__ R, const T *__restrict__ X, int64_t ldx, int64_t ncols,
-                  T *__restrict__ Tout, int32_t nitems, int32_t ntiles) {
+                  T *__restrict__ Tout, ColorPattern pat, uint8_t *__restrict__ flags,
+                  int32_t nitems, int32_t ntiles) {
   constexpr int NP = PMAX / 64;
+  constexpr int MAXSEG = 256;  // boxes of the sampled level inside one item
   constexpr int QS = 256 / KD;              // output rows / columns per fetch round
   constexpr int NA = PMAX / QS, NB = 16 * NTW / QS;  // fetch rounds of R and X
   static_assert(KD % 4 == 0 && 256 % KD == 0 && PMAX % QS == 0 && (16 * NTW) % QS == 0,
@@ -76,6 +84,8 @@ lr_project_kernel(const ProjItem *__restrict__ items, const ProjPair *__restrict
   __shared__ int64_t o_r[PMAX];  // R element offset of output row (segment start)
   __shared__ int64_t o_t[PMAX];  // T element offset of output row
   __shared__ int p_k[PMAX], p_o[PMAX + 1];
+  __shared__ int32_t sg_s[MAXSEG], sg_e[MAXSEG];  // live row segments [s, e) of the item
+  __shared__ int32_t w_cnt[4], s_nseg;
   typedef typename Acc<T>::type acc_t;
   int64_t item, tile;
   dev::xcd_item_tile(nitems, ntiles, item, tile);
@@ -103,20 +113,63 @@ lr_project_kernel(const ProjItem *__restrict__ items, const ProjPair *__restrict
       o_t[o] = (int64_t)pp.tslot * tstride + kk;
     }
   }
+  // live row segments for this tile's colors
+  bool dense = pat.rowbox == nullptr || it.nrows <= 0;
+  int b0 = 0, nb = 0;
+  if (!dense) {
+    b0 = pat.rowbox[it.row0];
+    nb = pat.rowbox[it.row0 + it.nrows - 1] - b0 + 1;
+    dense = nb > MAXSEG;
+  }
+  if (dense) {
+    if (tid == 0) {
+      sg_s[0] = 0;
+      sg_e[0] = it.nrows;
+      s_nseg = it.nrows > 0 ? 1 : 0;
+    }
+  } else {
+    const int64_t cend = c0 + 16 * NTW < ncols ? c0 + 16 * NTW : ncols;
+    const int ca = (int)((pat.col0 + c0) / pat.colw);
+    const int cb =
+        c0 < ncols ? (int)min<int64_t>((pat.col0 + cend - 1) / pat.colw, pat.ncolors - 1) : -1;
+    bool live = false;
+    int ss = 0, se = 0;
+    if (tid < nb) {
+      const int b = b0 + tid;
+      ss = (int)(max(pat.bstart[b], it.row0) - it.row0);
+      se = (int)(min(pat.bstart[b + 1], it.row0 + it.nrows) - it.row0);
+      for (int c = ca; c <= cb && !live; ++c) live = pat.act[(int64_t)b * pat.ncolors + c] != 0;
+      live = live && se > ss;
+    }
+    const uint64_t m = __ballot(live);
+    if (lane == 0) w_cnt[wave] = __popcll(m);
+    __syncthreads();
+    int k = 0;
+    for (int w = 0; w < wave; ++w) k += w_cnt[w];
+    if (live) {
+      k += __popcll(m & ((uint64_t(1) << lane) - 1));
+      sg_s[k] = ss;
+      sg_e[k] = se;
+    }
+    if (tid == 0) s_nseg = w_cnt[0] + w_cnt[1] + w_cnt[2] + w_cnt[3];
+  }
   __syncthreads();
   const int nout = p_o[np];
-  if (nout == 0) return;  // uniform: nothing to project
+  const int nseg = s_nseg;
+  const bool any = nout > 0 && nseg > 0;
+  if (flags && tid < np) flags[(int64_t)pairs[it.first + tid].tslot * ntiles + tile] = any ? 1 : 0;
+  if (!any) return;  // uniform: nothing to project
   acc_t acc[NP][NTW];
 #pragma unroll
   for (int p = 0; p < NP; ++p)
 #pragma unroll
     for (int t = 0; t < NTW; ++t) acc[p][t] = (acc_t){0, 0, 0, 0};
-  // thread operands: row r0 + (tid mod KD) of output rows / columns
-  // tid / KD + QS q
+  // thread operands: row r0 + (tid mod KD) (below re, the segment's end)
+  // of output rows / columns tid / KD + QS q
   T av[NA], bv[NB];
-  auto fetch = [&](int r0) {
+  auto fetch = [&](int r0, int re) {
     const int row = r0 + (tid % KD);
-    const bool rv = row < it.nrows;
+    const bool rv = row < re;
 #pragma unroll
     for (int q = 0; q < NA; ++q) {
       const int o = tid / KD + QS * q;
@@ -129,14 +182,22 @@ lr_project_kernel(const ProjItem *__restrict__ items, const ProjPair *__restrict
       bv[q] = (rv && gc < ncols) ? xr[gc * ldx] : (T)0;
     }
   };
-  fetch(0);
-  for (int r0 = 0; r0 < it.nrows; r0 += KD) {
+  // steps of KD rows through the live segments, the next one prefetched
+  int cs = 0, cr = sg_s[0];
+  fetch(cr, sg_e[0]);
+  for (;;) {
 #pragma unroll
     for (int q = 0; q < NA; ++q) As[tid % KD][tid / KD + QS * q] = av[q];
 #pragma unroll
     for (int q = 0; q < NB; ++q) Bs[tid % KD][tid / KD + QS * q] = bv[q];
     __syncthreads();
-    if (r0 + KD < it.nrows) fetch(r0 + KD);
+    int ns = cs, nr = cr + KD;
+    if (nr >= sg_e[ns]) {
+      ++ns;
+      nr = ns < nseg ? sg_s[ns] : 0;
+    }
+    const bool more = ns < nseg;
+    if (more) fetch(nr, sg_e[ns]);
 #pragma unroll
     for (int ks = 0; ks < KD; ks += 4) {
       T b[NTW];
@@ -152,6 +213,9 @@ lr_project_kernel(const ProjItem *__restrict__ items, const ProjPair *__restrict
       }
     }
     __syncthreads();
+    if (!more) break;
+    cs = ns;
+    cr = nr;
   }
 #pragma unroll
   for (int p = 0; p < NP; ++p) {
@@ -184,7 +248,8 @@ __global__ void __launch_bounds__(256, 4)
 lr_expand_kernel(const ExpandChunk *__restrict__ chunks, const ExpandEntry *__restrict__ entries,
                  int32_t kmax, int64_t tstride, const int32_t *__restrict__ ranks,
                  const T *__restrict__ L, const T *__restrict__ Tin, int64_t ncols, T sign,
-                 T *__restrict__ Y, int64_t ldy, int32_t nitems, int32_t ntiles) {
+                 T *__restrict__ Y, int64_t ldy, const uint8_t *__restrict__ flags,
+                 int32_t nitems, int32_t ntiles) {
   constexpr int QS = 256 / KD;  // T columns per fetch round
   constexpr int NA = KD / 4, NB = 16 * NTW / QS;  // fetch rounds of L and T
   static_assert(KD % 4 == 0 && 256 % KD == 0 && (16 * NTW) % QS == 0, "fetch layout");
@@ -205,11 +270,17 @@ lr_expand_kernel(const ExpandChunk *__restrict__ chunks, const ExpandEntry *__re
   acc_t acc[NTW];
 #pragma unroll
   for (int t = 0; t < NTW; ++t) acc[t] = (acc_t){0, 0, 0, 0};
+  bool touched = false;  // any depth contracted (uniform across the workgroup)
 
   for (int e0 = ch.first; e0 < ch.last;) {
     const int avail = min(EMAX, ch.last - e0);
     __syncthreads();  // the previous pass is done with the tables
-    if (tid < avail) e_k[tid] = ranks[entries[e0 + tid].kidx];
+    if (tid < avail) {
+      // an entry whose projection is zero in this tile (flag 0) adds nothing
+      const ExpandEntry en = entries[e0 + tid];
+      const bool z = flags && !flags[(int64_t)en.tslot * ntiles + tile];
+      e_k[tid] = z ? 0 : ranks[en.kidx];
+    }
     __syncthreads();
     if (tid == 0) {
       // entries while the depth fits (every rank <= kmax <= DMAX: at least one)
@@ -234,6 +305,7 @@ lr_expand_kernel(const ExpandChunk *__restrict__ chunks, const ExpandEntry *__re
     }
     __syncthreads();
     const int ktot = e_ko[ne];
+    touched = touched || ktot > 0;
     T av[NA], bv[NB];
     auto fetch = [&](int k0) {
       // L: the lane's chunk row at depth k0 + wave + 4 q (one depth per wave)
@@ -273,7 +345,7 @@ lr_expand_kernel(const ExpandChunk *__restrict__ chunks, const ExpandEntry *__re
     }
     e0 += ne;
   }
-  if (!rows_live) return;
+  if (!rows_live || !touched) return;  // nothing to add: Y is left as it is
 #pragma unroll
   for (int t = 0; t < NTW; ++t) {
     const int64_t gc = c0 + 16 * t + (lane & 15);
@@ -491,6 +563,7 @@ inline unsigned col_tiles(int64_t ncols) { return (unsigned)((ncols + TC - 1) / 
 // and 1024 columns: the kernels are bound by the latency of their operand
 // fetches, and wider tiles halve the resident workgroups that hide it.
 constexpr int kNTW = 4;
+static_assert(16 * kNTW == kLowRankTile, "projection and expansion share the column tiling");
 // contraction depth per LDS stage of the projection and the expansion: 16
 // (half the LDS and prefetch registers of 32, four waves per SIMD instead
 // of three for the projection) measured 6 % faster over the sphere's peel
@@ -514,21 +587,24 @@ inline unsigned grid_of(int64_t nitems, unsigned ntiles) {
 template <typename T, int NTW>
 void project_ntw(int32_t nitems, const ProjItem *items, const ProjPair *pairs, int32_t kmax,
                  int64_t tstride, const int32_t *ranks, const void *R, const void *X, int64_t ldx,
-                 int64_t ncols, void *Tb, hipStream_t s) {
+                 int64_t ncols, void *Tb, const ColorPattern *pat, uint8_t *flags,
+                 hipStream_t s) {
   const unsigned nt = tiles_of<NTW>(ncols);
+  const ColorPattern cp = pat ? *pat : ColorPattern{nullptr, nullptr, nullptr, 0, 1, 0};
   lr_project_kernel<T, NTW, kProjDepth><<<grid_of(nitems, nt), 256, 0, s>>>(
-      items, pairs, kmax, tstride, ranks, (const T *)R, (const T *)X, ldx, ncols, (T *)Tb, nitems,
-      (int32_t)nt);
+      items, pairs, kmax, tstride, ranks, (const T *)R, (const T *)X, ldx, ncols, (T *)Tb, cp,
+      pat ? flags : nullptr, nitems, (int32_t)nt);
 }
 
 template <typename T, int NTW>
 void expand_ntw(int32_t nchunks, const ExpandChunk *chunks, const ExpandEntry *entries,
                 int32_t kmax, int64_t tstride, const int32_t *ranks, const void *L,
-                const void *Tb, int64_t ncols, double sign, void *Y, int64_t ldy, hipStream_t s) {
+                const void *Tb, int64_t ncols, double sign, void *Y, int64_t ldy,
+                const uint8_t *flags, hipStream_t s) {
   const unsigned nt = tiles_of<NTW>(ncols);
   lr_expand_kernel<T, NTW, kExpandDepth><<<grid_of(nchunks, nt), 256, 0, s>>>(
       chunks, entries, kmax, tstride, ranks, (const T *)L, (const T *)Tb, ncols, (T)sign, (T *)Y,
-      ldy, nchunks, (int32_t)nt);
+      ldy, flags, nchunks, (int32_t)nt);
 }
 
 template <typename T, int NTW>
@@ -543,25 +619,30 @@ void near_ntw(int32_t nchunks, const ExpandChunk *chunks, const NearEntry *entri
 
 void launch_lr_project(int32_t nitems, const ProjItem *items, const ProjPair *pairs, int32_t kmax,
                        int64_t tstride, const int32_t *ranks, bool f32, const void *R,
-                       const void *X, int64_t ldx, int64_t ncols, void *T, hipStream_t s) {
+                       const void *X, int64_t ldx, int64_t ncols, void *T,
+                       const ColorPattern *pat, uint8_t *flags, hipStream_t s) {
   if (nitems <= 0 || ncols <= 0) return;
+  if (pat && (!flags || pat->colw < 1 || pat->ncolors < 1))
+    throw std::runtime_error("projection with a color pattern needs flags and colors");
   if (f32)
-    project_ntw<float, kNTW>(nitems, items, pairs, kmax, tstride, ranks, R, X, ldx, ncols, T, s);
+    project_ntw<float, kNTW>(nitems, items, pairs, kmax, tstride, ranks, R, X, ldx, ncols, T, pat,
+                             flags, s);
   else
-    project_ntw<double, kNTW>(nitems, items, pairs, kmax, tstride, ranks, R, X, ldx, ncols, T, s);
+    project_ntw<double, kNTW>(nitems, items, pairs, kmax, tstride, ranks, R, X, ldx, ncols, T,
+                              pat, flags, s);
 }
 
 void launch_lr_expand(int32_t nchunks, const ExpandChunk *chunks, const ExpandEntry *entries,
                       int32_t kmax, int64_t tstride, const int32_t *ranks, bool f32,
                       const void *L, const void *T, int64_t ncols, double sign, void *Y,
-                      int64_t ldy, hipStream_t s) {
+                      int64_t ldy, const uint8_t *flags, hipStream_t s) {
   if (nchunks <= 0 || ncols <= 0) return;
   if (f32)
     expand_ntw<float, kNTW>(nchunks, chunks, entries, kmax, tstride, ranks, L, T, ncols, sign, Y,
-                            ldy, s);
+                            ldy, flags, s);
   else
     expand_ntw<double, kNTW>(nchunks, chunks, entries, kmax, tstride, ranks, L, T, ncols, sign, Y,
-                             ldy, s);
+                             ldy, flags, s);
 }
 
 void launch_lr_reduce(int32_t nitems, const ReduceItem *items, int64_t tstride, int64_t elems,

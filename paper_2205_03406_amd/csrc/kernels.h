@@ -112,15 +112,36 @@ struct ExpandEntry {
   int32_t nseg;    // number of partial slots
   int32_t pad;
 };
+// Zero pattern of a colored test matrix X (the peel's right-hand side):
+// column block c (columns [c colw, (c + 1) colw)) is zero on the rows of
+// box b of the sampled level unless act[b * ncolors + c] != 0.  rowbox:
+// that level's box of every row; bstart: its box row starts (nbox + 1);
+// col0: the column of X where a launch's first column sits.
+struct ColorPattern {
+  const int32_t *rowbox;
+  const int64_t *bstart;
+  const uint8_t *act;
+  int32_t ncolors, colw;
+  int64_t col0;
+};
+// Column tile of the low-rank products (columns per workgroup).
+constexpr int kLowRankTile = 64;
+// With a pattern, the projection skips the rows of boxes whose blocks are
+// zero in all colors of a column tile, and records per slot and tile
+// whether T was written (flags[tslot * ntiles + tile], ntiles =
+// ceil(ncols / kLowRankTile)); a tile with no live rows leaves T unwritten
+// and flag 0.  The expansion given the flags skips the entries whose tile
+// is flagged 0.  pat == nullptr: dense X, no flags.
 void launch_lr_project(int32_t nitems, const ProjItem *items, const ProjPair *pairs, int32_t kmax,
                        int64_t tstride, const int32_t *ranks, bool f32, const void *R,
-                       const void *X, int64_t ldx, int64_t ncols, void *T, hipStream_t s);
+                       const void *X, int64_t ldx, int64_t ncols, void *T,
+                       const ColorPattern *pat, uint8_t *flags, hipStream_t s);
 // Every entry's partials must already be summed into its first slot
 // (launch_lr_reduce): only that slot is read.
 void launch_lr_expand(int32_t nchunks, const ExpandChunk *chunks, const ExpandEntry *entries,
                       int32_t kmax, int64_t tstride, const int32_t *ranks, bool f32,
                       const void *L, const void *T, int64_t ncols, double sign, void *Y,
-                      int64_t ldy, hipStream_t s);
+                      int64_t ldy, const uint8_t *flags, hipStream_t s);
 // T[slot] += T[slot + 1] + ... + T[slot + nseg - 1] (elems values per slot,
 // slot s at T + s * tstride), one item per pair split over several segments.
 struct ReduceItem {
