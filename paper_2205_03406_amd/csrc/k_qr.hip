@@ -90,14 +90,23 @@ block_norm_kernel(const QrJob *__restrict__ jobs, int32_t r, double scale,
 }
 
 // ------------------------------------------------------------------ pivqr
+// Rows of a QR block held in LDS: 32 KB of FP64 (128 rows at r = 32), so
+// four 256-thread workgroups still fit a compute unit.
+__host__ __device__ constexpr int32_t qr_lds_rows(int32_t r) {
+  return r > 0 ? 4096 / r : 0;
+}
+
 // One block (job index jx): the body of pivqr_kernel and of the fused
-// recovery kernel.
+// recovery kernel.  The FP64 working copy of the block lives in LDS (lws,
+// room for lws_rows x r) when the block has at most lws_rows rows, else in
+// the global workspace: every step of the factorization reads and writes
+// it, and from LDS those round trips take a tenth of the time.
 template <typename T>
 __device__ void pivqr_body(const QrJob &job, int jx, int32_t r, int32_t rank_fixed, double tol,
                            int32_t cap, const double *__restrict__ floor_abs,
                            const T *__restrict__ S, int64_t lds, double *__restrict__ Wk,
                            double *__restrict__ U, int32_t *__restrict__ ranks,
-                           int32_t *__restrict__ sat) {
+                           int32_t *__restrict__ sat, double *lws, int32_t lws_rows) {
   __shared__ double nrm2[64];
   __shared__ int piv[64];
   __shared__ double tau[64];
@@ -106,7 +115,7 @@ __device__ void pivqr_body(const QrJob &job, int jx, int32_t r, int32_t rank_fix
   const int m = job.m;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const T *A = S + job.col0 * lds + job.row0;
-  double *W = Wk + job.wslot;  // m x r, ld = m
+  double *W = (lws && m <= lws_rows) ? lws : Wk + job.wslot;  // m x r, ld = m
   const int kmax_here = m < r ? m : r;
   const int kcap = rank_fixed > 0 ? (rank_fixed < kmax_here ? rank_fixed : kmax_here)
                                   : (cap < kmax_here ? cap : kmax_here);
@@ -224,9 +233,10 @@ __global__ void __launch_bounds__(256)
 pivqr_kernel(const QrJob *__restrict__ jobs, int32_t r, int32_t rank_fixed, double tol,
              int32_t cap, const double *__restrict__ floor_abs, const T *__restrict__ S,
              int64_t lds, double *__restrict__ Wk, double *__restrict__ U,
-             int32_t *__restrict__ ranks, int32_t *__restrict__ sat) {
+             int32_t *__restrict__ ranks, int32_t *__restrict__ sat, int32_t lws_rows) {
+  extern __shared__ double lws[];  // lws_rows x r
   pivqr_body<T>(jobs[blockIdx.x], blockIdx.x, r, rank_fixed, tol, cap, floor_abs, S, lds, Wk, U,
-                ranks, sat);
+                ranks, sat, lws, lws_rows);
 }
 
 // ------------------------------------------------------------------ small dense helpers
@@ -438,9 +448,9 @@ recover_kernel(RecoverArgs a, const T *__restrict__ Om, const T *__restrict__ Ps
     const CoreJob cj = a.jc[q];
     core_body<T>(cj, a.r, Ps, a.ld, Ys, a.ld, a.core, smem);
     pivqr_body<T>(a.ju[q], q, a.r, a.rank_fixed, a.tol, a.cap, a.floor_u, Ys, a.ld, a.work, a.U,
-                  a.ranks_u, a.sat_u);
+                  a.ranks_u, a.sat_u, smem, qr_lds_rows(a.r));
     pivqr_body<T>(a.jv[q], q, a.r, a.rank_fixed, a.tol, a.cap, a.floor_v, Ys, a.ld, a.work, a.V,
-                  a.ranks_v, a.sat_v);
+                  a.ranks_v, a.sat_v, smem, qr_lds_rows(a.r));
     coupling_body<T>(cj, a.r, a.kmax, Om, a.ld, Ps, a.ld, a.U, a.V, a.ranks, a.core, a.scratch,
                      a.B, a.W, smem);
   }
@@ -757,12 +767,14 @@ void launch_pivqr(int32_t njobs, const QrJob *jobs, int32_t r, int32_t rank_fixe
                   int32_t cap, const double *floor_abs, bool f32, const void *S, int64_t lds,
                   double *Wk, double *U, int32_t *ranks, int32_t *sat, hipStream_t s) {
   if (njobs <= 0) return;
+  const int32_t rows = qr_lds_rows(r);
+  const size_t sh = sizeof(double) * (size_t)rows * r;
   if (f32)
-    pivqr_kernel<float><<<njobs, 256, 0, s>>>(jobs, r, rank_fixed, tol, cap, floor_abs,
-                                              (const float *)S, lds, Wk, U, ranks, sat);
+    pivqr_kernel<float><<<njobs, 256, sh, s>>>(jobs, r, rank_fixed, tol, cap, floor_abs,
+                                               (const float *)S, lds, Wk, U, ranks, sat, rows);
   else
-    pivqr_kernel<double><<<njobs, 256, 0, s>>>(jobs, r, rank_fixed, tol, cap, floor_abs,
-                                               (const double *)S, lds, Wk, U, ranks, sat);
+    pivqr_kernel<double><<<njobs, 256, sh, s>>>(jobs, r, rank_fixed, tol, cap, floor_abs,
+                                                (const double *)S, lds, Wk, U, ranks, sat, rows);
 }
 
 void launch_block_norms(int32_t njobs, const QrJob *jobs, int32_t r, double scale, bool f32,
@@ -780,7 +792,8 @@ void launch_recover(const RecoverArgs &a, int grid, bool f32, const void *Omega,
   const size_t core_sh = 33 * 2 * (size_t)a.r;
   const size_t sa = ((size_t)a.r * a.r > 33 * (size_t)(a.r + a.kmax)) ? (size_t)a.r * a.r
                                                                        : 33 * (size_t)(a.r + a.kmax);
-  const size_t sh = sizeof(double) * std::max(core_sh, sa + (size_t)a.r * a.kmax);
+  const size_t qr_sh = (size_t)qr_lds_rows(a.r) * a.r;
+  const size_t sh = sizeof(double) * std::max(std::max(core_sh, sa + (size_t)a.r * a.kmax), qr_sh);
   const unsigned g = (unsigned)std::max(1, std::min(grid, (int)a.njobs));
   if (f32)
     recover_kernel<float><<<g, 256, sh, s>>>(a, (const float *)Omega, (const float *)Psi,
