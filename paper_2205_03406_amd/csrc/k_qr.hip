@@ -12,6 +12,7 @@
 // All of this stays in FP64 in every precision mode.  Reductions over rows
 // are wave-wide shuffles; every column update is owned by one wave.
 #include <algorithm>
+#include <atomic>
 
 #include "device_common.h"
 #include "kernels.h"
@@ -90,17 +91,36 @@ block_norm_kernel(const QrJob *__restrict__ jobs, int32_t r, double scale,
 }
 
 // ------------------------------------------------------------------ pivqr
-// Rows of a QR block held in LDS: 32 KB of FP64 (128 rows at r = 32), so
-// four 256-thread workgroups still fit a compute unit.
-__host__ __device__ constexpr int32_t qr_lds_rows(int32_t r) {
-  return r > 0 ? 4096 / r : 0;
+// Rows of a QR block held in LDS: 4096 / r (128 at r = 32), fewer when the
+// device's per-workgroup LDS is smaller than 64 KB plus `other` bytes.  The
+// working copy and the explicit basis each take rows x r FP64 there (64 KB
+// per workgroup at most; the QR kernels' registers allow two workgroups per
+// compute unit, which then use 128 of the 160 KB).
+int32_t qr_lds_rows(int32_t r, size_t other) {
+  if (r <= 0) return 0;
+  static std::atomic<int> cap[64];  // per device, 0 until queried
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  int c = cap[dev].load();
+  if (c == 0) {
+    if (hipDeviceGetAttribute(&c, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+      c = 65536;
+    (void)hipGetLastError();
+    cap[dev].store(c);
+  }
+  const int64_t room = ((int64_t)c - (int64_t)other - 2048) / (2 * 8 * (int64_t)r);
+  return (int32_t)std::max<int64_t>(0, std::min<int64_t>(4096 / r, room));
 }
 
 // One block (job index jx): the body of pivqr_kernel and of the fused
-// recovery kernel.  The FP64 working copy of the block lives in LDS (lws,
-// room for lws_rows x r) when the block has at most lws_rows rows, else in
-// the global workspace: every step of the factorization reads and writes
-// it, and from LDS those round trips take a tenth of the time.
+// recovery kernel.  The FP64 working copy of the block and the explicit
+// basis are built in LDS (lws: room for 2 lws_rows x r) when the block has
+// at most lws_rows rows, else in the global workspace and in U: every step
+// of the factorization and of the basis formation reads and writes them,
+// and from LDS those round trips take a fraction of the time.
 template <typename T>
 __device__ void pivqr_body(const QrJob &job, int jx, int32_t r, int32_t rank_fixed, double tol,
                            int32_t cap, const double *__restrict__ floor_abs,
@@ -115,7 +135,8 @@ __device__ void pivqr_body(const QrJob &job, int jx, int32_t r, int32_t rank_fix
   const int m = job.m;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const T *A = S + job.col0 * lds + job.row0;
-  double *W = (lws && m <= lws_rows) ? lws : Wk + job.wslot;  // m x r, ld = m
+  const bool in_lds = lws && m <= lws_rows;
+  double *W = in_lds ? lws : Wk + job.wslot;  // m x r, ld = m
   const int kmax_here = m < r ? m : r;
   const int kcap = rank_fixed > 0 ? (rank_fixed < kmax_here ? rank_fixed : kmax_here)
                                   : (cap < kmax_here ? cap : kmax_here);
@@ -203,16 +224,17 @@ __device__ void pivqr_body(const QrJob &job, int jx, int32_t r, int32_t rank_fix
     if (sqrt(mx) > fmax(tol * r00, fl)) saturated = 1;
   }
 
-  // explicit basis: U = H_0 ... H_{rank-1} [I; 0], written column-major (ld = m)
+  // explicit basis: U = H_0 ... H_{rank-1} [I; 0], column-major (ld = m)
   double *Uo = U + job.uslot;
+  double *Ub = in_lds ? lws + (int64_t)lws_rows * r : Uo;
   for (int c = wave; c < rank; c += 4)
-    for (int i = lane; i < m; i += 64) Uo[(int64_t)c * m + i] = (i == c) ? 1.0 : 0.0;
+    for (int i = lane; i < m; i += 64) Ub[(int64_t)c * m + i] = (i == c) ? 1.0 : 0.0;
   __syncthreads();
   for (int j = rank - 1; j >= 0; --j) {
     const double *x = W + (int64_t)piv[j] * m;
     const double tj = tau[j];
     for (int c = j + wave; c < rank; c += 4) {
-      double *y = Uo + (int64_t)c * m;
+      double *y = Ub + (int64_t)c * m;
       double w = lane_dot(x, y, j + 1 + lane, m);
       w = wave_sum(w) + y[j];
       const double f = tj * w;
@@ -221,6 +243,8 @@ __device__ void pivqr_body(const QrJob &job, int jx, int32_t r, int32_t rank_fix
     }
     __syncthreads();
   }
+  if (in_lds)
+    for (int e = tid; e < m * rank; e += 256) Uo[e] = Ub[e];
   if (tid == 0) {
     ranks[jx] = rank;
     sat[jx] = saturated;
@@ -414,12 +438,20 @@ __device__ void coupling_body(const CoreJob &job, int32_t r, int32_t kmax,
     Bs[e] = (t < ku && c < kv) ? A[t * r + c] : 0.0;
   }
   __syncthreads();
-  // W = U B  (ma x kv), ld = ma
+  // W = U B  (ma x kv), ld = ma: eight columns of W per sweep over U, so a
+  // thread reads each U entry of its row once per eight columns (B from LDS)
   for (int i = tid; i < job.ma; i += 256) {
-    for (int c = 0; c < kv; ++c) {
-      double s = 0.0;
-      for (int t = 0; t < ku; ++t) s += Ua[(int64_t)t * job.ma + i] * A[t * r + c];
-      W[(int64_t)c * job.ma + i] = s;
+    for (int c0 = 0; c0 < kv; c0 += 8) {
+      double sacc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      for (int t = 0; t < ku; ++t) {
+        const double u = Ua[(int64_t)t * job.ma + i];
+#pragma unroll
+        for (int cc = 0; cc < 8; ++cc)
+          sacc[cc] += u * (c0 + cc < kv ? A[t * r + c0 + cc] : 0.0);
+      }
+#pragma unroll
+      for (int cc = 0; cc < 8; ++cc)
+        if (c0 + cc < kv) W[(int64_t)(c0 + cc) * job.ma + i] = sacc[cc];
     }
   }
   __syncthreads();
@@ -448,9 +480,9 @@ recover_kernel(RecoverArgs a, const T *__restrict__ Om, const T *__restrict__ Ps
     const CoreJob cj = a.jc[q];
     core_body<T>(cj, a.r, Ps, a.ld, Ys, a.ld, a.core, smem);
     pivqr_body<T>(a.ju[q], q, a.r, a.rank_fixed, a.tol, a.cap, a.floor_u, Ys, a.ld, a.work, a.U,
-                  a.ranks_u, a.sat_u, smem, qr_lds_rows(a.r));
+                  a.ranks_u, a.sat_u, smem, a.qr_rows);
     pivqr_body<T>(a.jv[q], q, a.r, a.rank_fixed, a.tol, a.cap, a.floor_v, Ys, a.ld, a.work, a.V,
-                  a.ranks_v, a.sat_v, smem, qr_lds_rows(a.r));
+                  a.ranks_v, a.sat_v, smem, a.qr_rows);
     coupling_body<T>(cj, a.r, a.kmax, Om, a.ld, Ps, a.ld, a.U, a.V, a.ranks, a.core, a.scratch,
                      a.B, a.W, smem);
   }
@@ -767,8 +799,8 @@ void launch_pivqr(int32_t njobs, const QrJob *jobs, int32_t r, int32_t rank_fixe
                   int32_t cap, const double *floor_abs, bool f32, const void *S, int64_t lds,
                   double *Wk, double *U, int32_t *ranks, int32_t *sat, hipStream_t s) {
   if (njobs <= 0) return;
-  const int32_t rows = qr_lds_rows(r);
-  const size_t sh = sizeof(double) * (size_t)rows * r;
+  const int32_t rows = qr_lds_rows(r, 0);
+  const size_t sh = sizeof(double) * 2 * (size_t)rows * r;
   if (f32)
     pivqr_kernel<float><<<njobs, 256, sh, s>>>(jobs, r, rank_fixed, tol, cap, floor_abs,
                                                (const float *)S, lds, Wk, U, ranks, sat, rows);
@@ -792,14 +824,16 @@ void launch_recover(const RecoverArgs &a, int grid, bool f32, const void *Omega,
   const size_t core_sh = 33 * 2 * (size_t)a.r;
   const size_t sa = ((size_t)a.r * a.r > 33 * (size_t)(a.r + a.kmax)) ? (size_t)a.r * a.r
                                                                        : 33 * (size_t)(a.r + a.kmax);
-  const size_t qr_sh = (size_t)qr_lds_rows(a.r) * a.r;
+  RecoverArgs b = a;
+  b.qr_rows = qr_lds_rows(a.r, 0);
+  const size_t qr_sh = 2 * (size_t)b.qr_rows * a.r;
   const size_t sh = sizeof(double) * std::max(std::max(core_sh, sa + (size_t)a.r * a.kmax), qr_sh);
   const unsigned g = (unsigned)std::max(1, std::min(grid, (int)a.njobs));
   if (f32)
-    recover_kernel<float><<<g, 256, sh, s>>>(a, (const float *)Omega, (const float *)Psi,
+    recover_kernel<float><<<g, 256, sh, s>>>(b, (const float *)Omega, (const float *)Psi,
                                              (const float *)Y);
   else
-    recover_kernel<double><<<g, 256, sh, s>>>(a, (const double *)Omega, (const double *)Psi,
+    recover_kernel<double><<<g, 256, sh, s>>>(b, (const double *)Omega, (const double *)Psi,
                                               (const double *)Y);
 }
 

@@ -211,6 +211,7 @@ struct RecoverArgs {
   double *work, *U, *V, *core, *scratch, *B, *W;
   int32_t *ranks;               // all ranks (coupling: ranks[pu], ranks[pv])
   int32_t *ranks_u, *ranks_v, *sat_u, *sat_v;  // this level's, indexed by pair
+  int32_t qr_rows;              // set by launch_recover: rows of a QR block held in LDS
 };
 void launch_recover(const RecoverArgs &a, int grid, bool f32, const void *Omega, const void *Psi,
                     const void *Y, hipStream_t s);
