@@ -475,9 +475,31 @@ void kernel_apply_tree(const Tree &T, int kernel, int64_t ncols, bool f32, const
                       const int64_t blks = std::max<int64_t>(
                           {(int64_t)1, (int64_t)(slice / std::max(per_blk, 1.0)),
                            (1024 + nct - 1) / std::max<int64_t>(nct, 1)});
-                      for (int64_t b = 0; b < units; b += blks)
+                      // At most two slices queued at a time: the host waits for
+                      // slice i - 1 before it enqueues slice i + 1.  A stream
+                      // that shares this stream's hardware queue (more streams
+                      // than queues) then waits behind two slices, not behind
+                      // the whole apply, and the next slice still fills the
+                      // tail of the one before.  Not under graph capture.
+                      hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+                      (void)hipStreamIsCapturing(s, &cap);
+                      (void)hipGetLastError();
+                      hipEvent_t ev[2] = {nullptr, nullptr};
+                      const bool pace = cap == hipStreamCaptureStatusNone &&
+                                        hipEventCreateWithFlags(&ev[0], hipEventDisableTiming) ==
+                                            hipSuccess &&
+                                        hipEventCreateWithFlags(&ev[1], hipEventDisableTiming) ==
+                                            hipSuccess;
+                      (void)hipGetLastError();
+                      int64_t i = 0;
+                      for (int64_t b = 0; b < units; b += blks, ++i) {
+                        if (pace && i >= 2) (void)hipEventSynchronize(ev[i & 1]);
                         launch_kapply(kernel, T.dim, T.n, D.pts.as<double>(), ncols, nt, f32, X,
                                       ldx, Y, ldy, s, blks * 64, b * 64);
+                        if (pace) (void)hipEventRecord(ev[i & 1], s);
+                      }
+                      for (hipEvent_t e : ev)
+                        if (e) (void)hipEventDestroy(e);
                     }
                   },
                   s);
