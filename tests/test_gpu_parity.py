@@ -17,7 +17,7 @@ import pytest
 import workloads
 import oracle
 from synth import exact_h1
-from devutil import to_dev, to_host, dense_of, pair_parity, block_norms
+from devutil import PerturbedDense, level_worst, to_dev, to_host, dense_of, pair_parity, block_norms
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -368,3 +368,40 @@ def test_tree_without_sampled_levels(hm, fmt):
     Y = hm.colmajor(100, 3)
     H.matvec(to_dev(X), Y)
     assert np.linalg.norm(to_host(Y) - A @ X) <= 1e-13 * np.linalg.norm(A @ X)
+
+
+def test_pattern_peel_with_many_boxes_per_item(hm):
+    """The projection's segment list holds at most 256 boxes of the sampled
+    level per item.  HODLR trees on N = 4096 points: with leaves of 8 (512
+    leaves) the level-1 column boxes hold exactly 256 boxes of the finest
+    level, the most a list takes; with leaves of 4 they hold 512, and the
+    projection sweeps such items densely instead.  Fixed rank 12 lies well
+    below the blocks' numerical rank (error 1.2e-6), so the truncated factors
+    move with rounding: each block is held to 10 times the oracle's own
+    response to a one-ulp perturbation of its products (as for the uniform
+    format at fixed rank), the whole operator likewise, and the error against
+    the kernel matrix to 1.5 times the oracle's."""
+    for n, leaf in ((4096, 8), (4096, 4)):
+        pts = workloads.uniform_line(n, 7)
+        T = hm.Tree(pts, leaf, "index_binary", "weak").color()
+        O = oracle.OTree(pts, leaf, "index_binary", "weak")
+        A = oracle.kernel_matrix(pts, pts, "log")
+        H = hm.compress(T, T.kernel_blackbox("log"), rank=12, r=22, seed=17)
+        Ho = oracle.compress(O, oracle.DenseBlackBox(A), 22, k=12, seed=17)
+        Hp = oracle.compress(O, PerturbedDense(A, seed=1), 22, k=12, seed=17)
+        blocks = {l: H.export_level(l) for l in O.sampled_levels()}
+        bn = block_norms(O, A)
+        sens = level_worst(O, Ho.lowrank, Hp.lowrank, bn)
+        gpu = level_worst(O, Ho.lowrank, blocks, bn)
+        D, Do, Dp = dense_of(hm, H, n), Ho.dense(), Hp.dense()
+        nA = np.linalg.norm(A)
+        whole, whole_p = np.linalg.norm(D - Do) / nA, np.linalg.norm(Dp - Do) / nA
+        err, err_o = np.linalg.norm(D - A) / nA, np.linalg.norm(Do - A) / nA
+        print("leaf %d: err %.2e (oracle %.2e), GPU vs oracle %.1e (rounding response %.1e), "
+              "per level %s against %s" % (leaf, err, err_o, whole, whole_p,
+                                           ["%.1e" % gpu[l] for l in sorted(gpu)],
+                                           ["%.1e" % sens[l] for l in sorted(sens)]))
+        for l in gpu:
+            assert gpu[l] <= 10 * sens[l] + 1e-10, (leaf, l, gpu[l], sens[l])
+        assert whole <= 10 * whole_p + 1e-10
+        assert err <= 1.5 * err_o + 1e-12
