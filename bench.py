@@ -57,7 +57,7 @@ def parse():
     ap.add_argument("--no-configs", action="store_true", help="skip the HODLR and star-curve lines")
     ap.add_argument("--batched-steps", type=int, default=3)
     ap.add_argument("--no-served", action="store_true")
-    ap.add_argument("--served-requests", type=int, default=80)
+    ap.add_argument("--served-requests", type=int, default=200)
     ap.add_argument("--served-loads", default="0.8",
                     help="comma-separated offered loads (fractions of the FP64 capacity)")
     ap.add_argument("--profile-steps", type=int, default=0,

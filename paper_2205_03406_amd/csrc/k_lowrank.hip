@@ -7,8 +7,9 @@
 // Every output row chunk is owned by one workgroup, which sums all of its
 // contributions in registers before a single read-modify-write of Y: the
 // result is deterministic (no atomics) and each Y element is written once
-// per call.  Tiles are 64 rows x 64 columns, K staged through LDS in chunks
-// of 32; FP64 (or FP32 in the mixed path) on the vector ALUs.
+// per call.  Tiles are 64 rows x 64 columns on the matrix cores (FP64, or
+// FP32 in the mixed path), the contraction staged through LDS 16 (project,
+// expand) or 32 (near) deep.
 #include <algorithm>
 #include <stdexcept>
 #include <string>
