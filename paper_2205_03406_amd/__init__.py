@@ -82,7 +82,8 @@ class TorchAllocator:
     (torch.cuda.caching_allocator_alloc / caching_allocator_delete), so that
     the library's device blocks belong to torch (they show in
     torch.cuda.memory_allocated()).  `allocs`, `frees` and `live` (pointer ->
-    bytes) count the blocks taken and returned.  The object must outlive
+    bytes) count the blocks taken and returned; `peak_bytes` is the most
+    bytes live at once since the last reset_peak().  The object must outlive
     every H-matrix, plan, tree and server that uses it."""
 
     def __init__(self):
@@ -91,6 +92,8 @@ class TorchAllocator:
         self.allocs = 0
         self.frees = 0
         self.live = {}
+        self._bytes = 0
+        self.peak_bytes = 0
         self._lock = threading.Lock()
 
         def _alloc(ctx, nbytes, stream):
@@ -101,12 +104,14 @@ class TorchAllocator:
             with self._lock:
                 self.allocs += 1
                 self.live[p] = int(nbytes)
+                self._bytes += int(nbytes)
+                self.peak_bytes = max(self.peak_bytes, self._bytes)
             return p
 
         def _free(ctx, p, stream):
             with self._lock:
                 self.frees += 1
-                self.live.pop(p, None)
+                self._bytes -= self.live.pop(p, 0)
             try:
                 torch.cuda.caching_allocator_delete(p)
             except Exception:
@@ -118,7 +123,12 @@ class TorchAllocator:
 
     def live_bytes(self):
         with self._lock:
-            return sum(self.live.values())
+            return self._bytes
+
+    def reset_peak(self):
+        """Restart peak_bytes from the bytes live now."""
+        with self._lock:
+            self.peak_bytes = self._bytes
 
 
 _TORCH_ALLOC = None

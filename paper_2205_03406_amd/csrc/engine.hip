@@ -2701,18 +2701,154 @@ int64_t hmatrix_device_bytes(const hm_hmatrix *H) {
   return b;
 }
 
-// Peak device bytes of one compression of T (factor pools at the largest
-// rank, sample and scratch buffers, plans), from the same sizes
-// compress_impl allocates; an admission estimate (plans are approximated).
+// Device bytes of T's device copy (device_tree: coordinates, permutation,
+// per-level row boxes and box starts, instance offsets, forest items), each
+// block rounded as the block cache rounds it.
+int64_t tree_device_bytes(const Tree &T) {
+  auto blk = [](int64_t b) { return (std::max<int64_t>(b, 64) + 255) / 256 * 256; };
+  int64_t b = blk((int64_t)T.dim * T.n * 8) + blk(T.n * 8) + blk((int64_t)(T.ninst() + 1) * 8);
+  for (int l = 0; l < T.nlev(); ++l)
+    b += blk(T.n * 4) + blk((int64_t)(T.lev[l].nbox() + 1) * 8);
+  if (T.ninst() > 1) b += blk((T.n / 64 + T.ninst()) * (int64_t)sizeof(KItem));
+  return b;
+}
+
+// Device bytes of the low-rank plans build_plans makes for T's sampled
+// levels (both orientations; every prefix of levels when `prefixes`), from
+// the same loops without building them, each list rounded as the block cache
+// rounds it.
+static int64_t plan_bytes(const Tree &T, int64_t kmax, int32_t seg, bool prefixes) {
+  auto blk = [](int64_t b) { return (std::max<int64_t>(b, 64) + 255) / 256 * 256; };
+  std::vector<int> levels;
+  for (int l = 1; l < T.nlev(); ++l)
+    if (!T.graphs[l].pa.empty()) levels.push_back(l);
+  const int nlv = (int)levels.size();
+  const int64_t per_group = std::max<int64_t>(1, 128 / std::max<int64_t>(1, kmax));
+  int64_t bytes = 0;
+  for (int o = 0; o < 2; ++o) {
+    const bool trans = o == 1;
+    int64_t nitems = 0, npps = 0, nred = 0;
+    std::vector<std::vector<int32_t>> cnt(nlv);  // pairs per row box
+    for (int li = 0; li < nlv; ++li) {
+      const Graph &G = T.graphs[levels[li]];
+      const Level &Lev = T.lev[levels[li]];
+      const std::vector<int32_t> &colbox = trans ? G.pa : G.pb;
+      std::vector<int64_t> per(Lev.nbox(), 0);
+      for (int32_t b : colbox) per[b]++;
+      for (int b = 0; b < Lev.nbox(); ++b) {
+        const int64_t m = Lev.start[b + 1] - Lev.start[b];
+        if (!per[b] || m <= 0) continue;
+        const int64_t nsg = seg > 0 ? (m + seg - 1) / seg : 1;
+        nitems += (per[b] + per_group - 1) / per_group * nsg;
+        npps += per[b] * nsg;
+        if (nsg > 1) nred += per[b];
+      }
+      cnt[li].assign(Lev.nbox(), 0);
+      for (int32_t a : trans ? G.pb : G.pa) cnt[li][a]++;
+    }
+    bytes += blk(nitems * (int64_t)sizeof(ProjItem)) + blk(npps * (int64_t)sizeof(ProjPair)) +
+             blk(nred * (int64_t)sizeof(ReduceItem));
+    for (int le = prefixes ? 1 : std::max(nlv, 1); le <= nlv; ++le) {
+      const int fl = levels[le - 1];
+      const Level &F = T.lev[fl];
+      int64_t nch = 0, nen = 0;
+      for (int b = 0; b < F.nbox(); ++b) {
+        int box = b, lvl = fl;
+        int64_t per_chunk = 0;
+        for (int li = le - 1; li >= 0; --li) {
+          while (lvl > levels[li]) box = T.lev[lvl--].parent[box];
+          per_chunk += cnt[li][box];
+        }
+        const int64_t chunks = (F.start[b + 1] - F.start[b] + 63) / 64;
+        if (per_chunk > 0) {
+          nch += chunks;
+          nen += chunks * per_chunk;
+        }
+      }
+      bytes += blk(nch * (int64_t)sizeof(ExpandChunk)) + blk(nen * (int64_t)sizeof(ExpandEntry));
+    }
+  }
+  return bytes;
+}
+
+// Device bytes of the other work lists of a compression of T: the leaf near
+// field's plans (both orientations), the per-level job lists of the
+// recovery and its color-activity table, the leaf pass lists, and for H^2
+// the pass lists (upward and downward sums of every level, the long bases
+// and their 64-row chunks for the full operator and every level-truncated
+// one); upper bounds where a list's length depends on ranks.
+static int64_t list_bytes(const Tree &T, const hm_compress_opts &o) {
+  auto blk = [](int64_t b) { return (std::max<int64_t>(b, 64) + 255) / 256 * 256; };
+  const Graph &GL = T.leaf_graph();
+  const Level &LL = T.lev[T.L()];
+  int64_t b = 0;
+  {
+    int64_t nch = 0, nen = 0;
+    std::vector<int64_t> cols(LL.nbox(), 0);
+    for (size_t q = 0; q < GL.pa.size(); ++q) cols[GL.pa[q]] += (T.box_size(T.L(), GL.pb[q]) + 127) / 128;
+    for (int a = 0; a < LL.nbox(); ++a) {
+      if (!cols[a]) continue;
+      const int64_t chunks = (T.box_size(T.L(), a) + 63) / 64;
+      nch += chunks;
+      nen += chunks * cols[a];
+    }
+    b += 2 * (blk(nch * (int64_t)sizeof(ExpandChunk)) + blk(nen * (int64_t)sizeof(NearEntry)));
+    const int64_t npl = (int64_t)GL.pa.size();
+    b += 2 * blk(GL.nv() * 4) + blk((int64_t)LL.nbox() * GL.ncolors) + 3 * blk(npl * 8) +
+         2 * blk(npl * 4) + (T.ninst() > 1 ? blk((T.n / 64 + T.ninst()) * (int64_t)sizeof(KItem)) : 0);
+  }
+  int64_t nb = 0, np = 0, nlv = 0;
+  for (int l = 1; l < T.nlev(); ++l) {
+    const Graph &G = T.graphs[l];
+    if (G.pa.empty()) continue;
+    const int64_t npl = (int64_t)G.pa.size(), nbl = T.lev[l].nbox();
+    b += 2 * blk(npl * (int64_t)sizeof(QrJob)) + blk(npl * (int64_t)sizeof(CoreJob)) +
+         blk(npl * 4) + blk(nbl * G.ncolors) +
+         (T.ninst() > 1 ? blk((T.n / 64 + T.ninst()) * (int64_t)sizeof(KItem)) : 0);
+    if (o.format != HM_FORMAT_H1) {
+      // the shared-basis formats' lists (build_uniform_graphs ran): stage-1
+      // activity and QR jobs, stage-2 slots, basis offsets, the combination
+      // jobs (256-row pieces) and terms, the coupling jobs; H^2 adds the
+      // norm jobs, the augmentation jobs, the transfers and the nesting
+      const int64_t pieces = nbl + T.n / 256 + 1;
+      b += blk(nbl * std::max(T.ugraphs[l].ncolors, 1)) + 3 * blk(nbl * (int64_t)sizeof(QrJob)) +
+           blk(nbl * std::max(G.ncolors, 1) * 4) + blk(nbl * 8) +
+           blk(pieces * (int64_t)sizeof(MixJob)) + blk(npl * (int64_t)sizeof(MixTerm)) +
+           blk(npl * (int64_t)sizeof(UCJob));
+      if (o.format == HM_FORMAT_H2)
+        b += 2 * blk(pieces * (int64_t)sizeof(AugJob)) + blk(nbl * (int64_t)sizeof(TransferJob)) +
+             blk(nbl * (int64_t)sizeof(NestJob));
+      if (T.ninst() > 1) b += 2 * blk((T.n / 64 + T.ninst()) * (int64_t)sizeof(KItem));
+    }
+    nb += nbl;
+    np += npl;
+    ++nlv;
+  }
+  if (o.format == HM_FORMAT_H2) {
+    const int64_t rec = (nb + T.n / 64 + nb) * (int64_t)sizeof(H2Leaf);
+    b += nlv * (3 * blk(nb * (int64_t)sizeof(H2Sum)) + 3 * blk((np + 2 * nb) * (int64_t)sizeof(H2Term)));
+    b += (nlv + 1) * 2 * blk(rec);
+  }
+  return b + 4096;
+}
+
+// Peak device bytes of one compression of T with a black box in tree order
+// (factor pools at the largest rank, sample and scratch buffers, plans and
+// work lists, and T's device copy when T has none on this device yet), from
+// the same sizes compress_impl allocates; the server's admission estimate.
 int64_t compress_footprint(Tree &T, const hm_compress_opts &o) {
   const int p = o.oversample > 0 ? o.oversample : 10;
   const int kfix = o.rank > 0 ? o.rank : 0;
   const int r = o.r > 0 ? o.r : (kfix > 0 ? kfix + p : 0);
   if (r <= 0) return 0;
   const int64_t kmax = kfix > 0 ? std::min(kfix, r) : r - p;
-  const int64_t es = o.prec == HM_PREC_MIXED ? 4 : 8;
+  const bool mixed = o.prec == HM_PREC_MIXED;
+  const int64_t es = mixed ? 4 : 8;
   const int64_t n = T.n;
-  int64_t szU = 0, szV = 0, np = 0, cmax = 0, wmax = 0, cmax_np = 0, slots = 0;
+  const bool uniform = o.format != HM_FORMAT_H1, h2 = o.format == HM_FORMAT_H2;
+  if (uniform) build_uniform_graphs(T);
+  int64_t szU = 0, szV = 0, np = 0, nb = 0, nlv = 0, cmax = 0, wmax = 0, cmax_np = 0;
+  int64_t w1 = 0, w2 = 0;  // shared-basis formats: widest stage-1 and stage-2 samples
   for (int l = 1; l < T.nlev(); ++l) {
     const Graph &G = T.graphs[l];
     if (G.pa.empty()) continue;
@@ -2724,63 +2860,72 @@ int64_t compress_footprint(Tree &T, const hm_compress_opts &o) {
       szU += ma * kmax;
       szV += mb * kmax;
       rows += ma + mb;
-      slots += (std::max(ma, mb) + 255) / 256;
     }
     np += (int64_t)G.pa.size();
+    nb += Lv.nbox();
+    ++nlv;
     cmax = std::max<int64_t>(cmax, pad16((int64_t)G.ncolors * r));
     wmax = std::max(wmax, rows * r);
     cmax_np = std::max<int64_t>(cmax_np, (int64_t)G.pa.size());
+    if (uniform) {
+      w1 = std::max(w1, pad16((int64_t)T.ugraphs[l].ncolors * r));
+      w2 = std::max(w2, pad16((int64_t)G.ncolors * kmax));
+    }
   }
   const Graph &GL = T.leaf_graph();
   int64_t szD = 0;
   for (size_t q = 0; q < GL.pa.size(); ++q)
     szD += T.box_size(T.L(), GL.pa[q]) * T.box_size(T.L(), GL.pb[q]);
   const int64_t leaf_cols = pad16((int64_t)GL.ncolors * T.leaf_width());
-  const int64_t wcols = std::max<int64_t>(2 * cmax, leaf_cols);
-  const int64_t pools = szU * (8 + 8 + 4) + szV * (8 + 4) + np * kmax * kmax * 8 + szD * 8 +
-                        np * 8 + n * 8;
-  const int64_t tcap = std::max(std::min<int64_t>(slots * kmax * wcols, kTScratchCap),
-                                slots * kmax * 64);
-  const int64_t scratch = 2 * n * wcols * es + tcap * es + wmax * 8 + 2 * cmax_np * r * r * 8 +
-                          np * 8 + cmax_np * 16;
-  const int64_t plans = 64 * np + 4096;
-  int64_t uni = 0;
-  if (o.format == HM_FORMAT_H2 || o.format == HM_FORMAT_UNIFORM_H1) {
-    // sample buffers of the two stages (stage 2 in FP64), beyond the H^1
-    // ones counted above
-    build_uniform_graphs(T);
-    int64_t w1 = leaf_cols, w2 = 0;
-    for (int l = 1; l < T.nlev(); ++l)
-      if (!T.graphs[l].pa.empty()) {
-        w1 = std::max(w1, pad16((int64_t)T.ugraphs[l].ncolors * r));
-        w2 = std::max(w2, pad16((int64_t)T.graphs[l].ncolors * kmax));
-      }
-    uni += 2 * std::max<int64_t>(0, std::max(n * w1 * es, n * w2 * 8) - n * wcols * es);
-    uni += tcap * (8 - es);
+  // factor pools: per-pair bases, their products and FP32 copies (not kept
+  // by H^2), couplings, leaf blocks, ranks, permutation
+  const int64_t pools = (h2 ? 0 : szU * (8 + 8 + 4) + szV * (8 + 4)) + np * kmax * kmax * 8 +
+                        szD * 8 + np * 8 + n * 8;
+  // the two sample buffers (the shared-basis formats' stage 2 in FP64) and
+  // the peel's partial projections: one slot per pair and sample column,
+  // capped (H^2 peels through its passes and keeps no slots)
+  int64_t wcols = std::max<int64_t>(2 * cmax, leaf_cols), xbytes = n * wcols * es, tes = es;
+  if (uniform) {
+    w1 = std::max(w1, leaf_cols);
+    xbytes = std::max(n * w1 * es, n * w2 * 8);
+    wcols = std::max(w1, w2);
+    tes = 8;
   }
-  if (o.format == HM_FORMAT_H2) {
-    // every box of the sampled range may hold a basis: bases, singular
-    // values, transfers; the augmented sample buffer; the expansion scratch
-    // of the peel (two nb x kmax x h2cols blocks, capped at 64 MB each, and
-    // the chunk partials: at most one 64-row chunk per box plus n / 64)
-    int64_t nb = 0;
+  const int64_t slots = h2 ? 0 : np;
+  const int64_t tcap = std::max(std::min<int64_t>(slots * kmax * std::max<int64_t>(wcols, 1), kTScratchCap),
+                                std::max<int64_t>(slots * kmax * 64, 64));
+  const int64_t tflags = tcap / std::max<int64_t>(kmax * kLowRankTile, 1) + slots + 64;
+  int64_t work = std::max<int64_t>(wmax, 1) * 8;
+  if (h2) work = std::max(work, n * r * 8);
+  const int64_t scratch = 2 * xbytes + tcap * tes + tflags + work +
+                          2 * std::max<int64_t>(cmax_np, 1) * r * r * 8 + 2 * np * 4 + 64 +
+                          (mixed ? 2 * cmax_np * 8 : 0) + nlv * 4;
+  int64_t uni = 0;
+  if (h2) {
+    // per level: implied bases U and V (a level's boxes cover at most n
+    // rows), singular values and transfers of every box; basis ranks and
+    // saturation flags; the augmented sample; the expansion scratch of the
+    // peel (two nb x kmax x h2cols blocks, capped at 64 MB each, and the
+    // chunk partials: at most one 64-row chunk per box plus n / 64)
     for (int l = 1; l < T.nlev(); ++l)
-      if (!T.graphs[l].pa.empty()) {
+      if (!T.graphs[l].pa.empty())
         uni += 2 * n * kmax * 8 + 2 * T.lev[l].nbox() * (kmax + kmax * kmax) * 8;
-        nb += T.lev[l].nbox();
-      }
-    uni += n * r * 8 * 2;
+    uni += 16 * nb + n * r * 8 + (mixed ? nb * 8 : 0);
     const int64_t h2cols = std::min<int64_t>(
         256, std::max<int64_t>(16, (int64_t(64) << 20) / std::max<int64_t>(nb * kmax * 8, 1)));
     uni += 2 * nb * kmax * h2cols * 8 + (nb + n / 64 + 1) * kmax * h2cols * 8;
-  } else if (o.format == HM_FORMAT_UNIFORM_H1) {
-    // shared bases (each level's boxes cover at most n rows, U and V) and
-    // the combination buffer
-    for (int l = 1; l < T.nlev(); ++l)
-      if (!T.graphs[l].pa.empty()) uni += 2 * n * kmax * 8;
-    uni += n * kmax * 8;
+  } else if (uniform) {
+    // shared bases U and V of every level, their ranks and saturation
+    // flags, the combination buffer
+    uni += nlv * 2 * n * kmax * 8 + 16 * nb + n * kmax * 8;
   }
-  return pools + scratch + plans + uni;
+  const int64_t plans =
+      (h2 ? 0 : plan_bytes(T, kmax, kSeg, false) + plan_bytes(T, kmax, 0, true)) + list_bytes(T, o);
+  int dev = -1;
+  const int64_t tree = T.dev && hipGetDevice(&dev) == hipSuccess && T.dev->device == dev
+                           ? 0
+                           : tree_device_bytes(T);
+  return pools + scratch + plans + uni + tree;
 }
 
 // Device bytes of one hm_matvec call (scratch and order conversion).

@@ -125,6 +125,7 @@ int32_t dsatur(int64_t nv, const int64_t *xadj, const int32_t *adj, int32_t *col
 
 // ------------------------------------------------------------------ sizes
 int64_t hmatrix_device_bytes(const hm_hmatrix *H);
+int64_t tree_device_bytes(const Tree &T);
 int64_t compress_footprint(Tree &T, const hm_compress_opts &o);
 int64_t matvec_footprint(const hm_hmatrix *H, int64_t nrhs, int dtype);
 // frees the idle device blocks kept for reuse by H-matrices, trees and compressions

@@ -242,7 +242,8 @@ void hm_server::worker() {
         if (st == HM_OK) {
           it->second.tree = T;
           it->second.H = H;
-          it->second.bytes = hm::hmatrix_device_bytes(H);
+          // the H-matrix and the device copy of its tree, held together
+          it->second.bytes = hm::hmatrix_device_bytes(H) + hm::tree_device_bytes(T->t);
           it->second.n = q->n;
           it->second.ready = true;
           in_use += it->second.bytes;

@@ -152,3 +152,40 @@ def test_release_and_errors(hm):
     with pytest.raises(hm.HMError):
         srv.submit_matvec(12345, np.zeros((10, 1)))
     srv.close()
+
+
+@pytest.mark.parametrize("fmt", ["h1", "h1_mixed", "uniform", "h2"])
+def test_request_footprints_cover_their_allocations(hm, fmt):
+    """Admission reserves a request's footprint (the completion's `bytes`),
+    so that estimate must cover the device memory the request takes.  With a
+    counting allocator under the server and one request at a time, the peak
+    of the allocator's live bytes while a request runs, above what was live
+    before it, stays within the request's bytes: a compression in each format
+    (the H-matrix it leaves resident included) and applies of 1 to 300
+    right-hand sides in both precisions."""
+    kw = dict(h1={}, h1_mixed=dict(prec=hm.HM_PREC_MIXED), uniform=dict(uniform=True),
+              h2=dict(h2=True))[fmt]
+    al = hm.TorchAllocator()
+    srv = hm.Server(nslots=1, allocator=al)
+    pts = workloads.sphere(6000, 5)
+    base = al.live_bytes()
+    al.reset_peak()
+    h = srv.submit_compress(pts, 64, kernel="inv_r", tol=1e-6, r=32, seed=9, **kw)
+    c = _drain(srv, 1)[h]
+    assert c["status"] == 0
+    used = al.peak_bytes - base
+    print("%s compression: peak %d of a %d byte footprint" % (fmt, used, c["bytes"]))
+    assert 0 < used <= c["bytes"], (used, c["bytes"])
+    rng = np.random.default_rng(6)
+    for nrhs, dt in [(1, np.float64), (16, np.float32), (300, np.float64), (300, np.float32)]:
+        base = al.live_bytes()
+        al.reset_peak()
+        rid = srv.submit_matvec(h, rng.standard_normal((pts.shape[0], nrhs)).astype(dt))
+        c = _drain(srv, 1)[rid]
+        assert c["status"] == 0
+        used = al.peak_bytes - base
+        print("  apply %d x %s: peak %.2f MB of %.2f MB" % (nrhs, np.dtype(dt).name, used / 1e6,
+                                                          c["bytes"] / 1e6))
+        assert 0 < used <= c["bytes"], (nrhs, dt, used, c["bytes"])
+    srv.close()
+    assert al.live_bytes() == 0
