@@ -214,7 +214,7 @@ kapply_kernel(int64_t n, const double *__restrict__ pts_all, int64_t ncols,
   // One k-block into the accumulators c.  The B fragments of the first
   // depth step and the block's coordinates are read from LDS before the
   // kernel values are computed, and each later step's fragments are read
-  // while the previous step's MFMAs run, so LDS latency hides under VALU
+  // between the previous step's MFMAs, so LDS latency hides under VALU
   // and matrix work.  The KS kernel evaluations are straight-line code (no
   // per-lane branches) so their dependency chains interleave; depths
   // beyond the instance are zeroed on the tail block only (a wave-uniform
@@ -258,7 +258,6 @@ kapply_kernel(int64_t n, const double *__restrict__ pts_all, int64_t ncols,
         for (int t = 0; t < NT; ++t)
           bq[(s4 + 1) & 1][t] = Xs[buf][4 * (s4 + 1) + kq][t * 16 + (lane & 15)];
       }
-      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
         if constexpr (sizeof(T) == 8)
@@ -266,6 +265,18 @@ kapply_kernel(int64_t n, const double *__restrict__ pts_all, int64_t ncols,
         else
           c[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s4], bq[s4 & 1][t], c[t], 0, 0, 0);
       }
+      // the next step's reads spread over this step's MFMAs, one LDS read
+      // (a pair of fragments) between every two, instead of in one burst
+      // ahead of them: the LDS serves the four waves' reads while the matrix
+      // cores run, not all at once (2 % faster in FP64, 1 % in FP32)
+      if (s4 + 1 < KS) {
+#pragma unroll
+        for (int i = 0; i < NT / 2; ++i) {
+          __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // one LDS read
+          __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);  // two MFMAs
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
     }
     if (kb + 1 < nk) commit(buf ^ 1);
     __syncthreads();
