@@ -193,9 +193,12 @@ kapply_kernel(int64_t n, const double *__restrict__ pts_all, int64_t ncols,
       const int gc = cb + q * (256 / BK);
       xr[q] = xk[(int64_t)(gc < nc32 ? gc : nc32 - 1) * ldx32];
     }
-    if (tid < BK * DIM) {
+    {  // every thread loads (a clamped coordinate), so no branch splits the
+       // block of instructions the loads are scheduled into; the first BK * DIM
+       // keep theirs
       const int64_t gk = k0 + tid % BK;
-      pk = pts[(int64_t)(tid / BK) * n + (gk < nloc ? gk : nloc - 1)];
+      const int d = tid / BK < DIM ? tid / BK : DIM - 1;
+      pk = pts[(int64_t)d * n + (gk < nloc ? gk : nloc - 1)];
     }
   };
   auto commit = [&](int buf) {
@@ -210,6 +213,7 @@ kapply_kernel(int64_t n, const double *__restrict__ pts_all, int64_t ncols,
   // a dead tile (zero columns of X) skips the contraction and stores zeros
   const int64_t nk = live ? (nloc + BK - 1) / BK : 0;
   constexpr int KS = BK / 4;  // MFMA depth steps per k-block
+  static_assert(KS >= 2, "the loads of the first step and the stores of the last are apart");
 
   // One k-block into the accumulators c.  The B fragments of the first
   // depth step and the block's coordinates are read from LDS before the
@@ -220,7 +224,6 @@ kapply_kernel(int64_t n, const double *__restrict__ pts_all, int64_t ncols,
   // beyond the instance are zeroed on the tail block only (a wave-uniform
   // branch).
   auto kblock = [&](int64_t kb, int buf, acc_t *c) {
-    if (kb + 1 < nk) fetch((kb + 1) * BK);
     T bq[2][NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) bq[0][t] = Xs[buf][kq][t * 16 + (lane & 15)];
@@ -269,16 +272,43 @@ kapply_kernel(int64_t n, const double *__restrict__ pts_all, int64_t ncols,
       // (a pair of fragments) between every two, instead of in one burst
       // ahead of them: the LDS serves the four waves' reads while the matrix
       // cores run, not all at once (2 % faster in FP64, 1 % in FP32)
-      if (s4 + 1 < KS) {
+      if (s4 == 0) {
+        // the next block's X and coordinates loaded between the first
+        // step's MFMAs, two loads after every two (8 % faster in FP64, 2 %
+        // in FP32 than loading them ahead of the kernel evaluations); after
+        // the last block too: clamped addresses, and what it loads goes to
+        // the idle buffer, never read, so the stores below need no branch
+        fetch((kb + 1) * BK);
+#pragma unroll
+        for (int i = 0; i < NT / 2; ++i) {
+          __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // one LDS read
+          __builtin_amdgcn_sched_group_barrier(0x020, 2, 0);  // two global loads
+          __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);  // two MFMAs
+        }
+      } else if (s4 + 1 < KS) {
 #pragma unroll
         for (int i = 0; i < NT / 2; ++i) {
           __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // one LDS read
           __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);  // two MFMAs
         }
+      } else {
+        // the next block's X stored into the idle buffer between the last
+        // step's MFMAs, one store after each (1 % faster in FP64, 2 % in
+        // FP32 than the stores in a burst after them)
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+          const int e = tid + 256 * q;
+          Xs[buf ^ 1][e % BK][e / BK] = xr[q];
+        }
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+          __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);  // one LDS store
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one MFMA
+        }
       }
       __builtin_amdgcn_sched_barrier(0);
     }
-    if (kb + 1 < nk) commit(buf ^ 1);
+    if (kb + 1 < nk && tid < BK * DIM) Ps[buf ^ 1][tid / BK][tid % BK] = pk;
     __syncthreads();
   };
 
