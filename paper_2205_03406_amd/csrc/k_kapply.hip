@@ -201,13 +201,12 @@ kapply_kernel(int64_t n, const double *__restrict__ pts_all, int64_t ncols,
       pk = pts[(int64_t)d * n + (gk < nloc ? gk : nloc - 1)];
     }
   };
-  auto commit = [&](int buf) {
+  auto store_x = [&](int buf) {
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int e = tid + 256 * q;
       Xs[buf][e % BK][e / BK] = xr[q];
     }
-    if (tid < BK * DIM) Ps[buf][tid / BK][tid % BK] = pk;
   };
 
   // a dead tile (zero columns of X) skips the contraction and stores zeros
@@ -223,7 +222,18 @@ kapply_kernel(int64_t n, const double *__restrict__ pts_all, int64_t ncols,
   // per-lane branches) so their dependency chains interleave; depths
   // beyond the instance are zeroed on the tail block only (a wave-uniform
   // branch).
+  //   Where the next block's global loads and LDS stores go.  FP64 (4 depth
+  // steps per block): the loads between the first step's MFMAs, the stores
+  // between the last step's (62.2 TFLOP/s on the sphere against 57.0 with
+  // the loads at the top of the block and the stores in a burst after the
+  // MFMAs).  FP32 (8 steps, twice the elements per thread): at the top and
+  // in a burst (83.4 against 79.1 TFLOP/s spread as in FP64, 79.5 spread
+  // over two steps each).  After the last block the loads are issued too:
+  // clamped addresses, and what they load goes to the idle buffer and is
+  // never read, so no branch splits the instructions they are placed among.
+  constexpr bool kSpread = sizeof(T) == 8;
   auto kblock = [&](int64_t kb, int buf, acc_t *c) {
+    if constexpr (!kSpread) fetch((kb + 1) * BK);
     T bq[2][NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) bq[0][t] = Xs[buf][kq][t * 16 + (lane & 15)];
@@ -272,12 +282,7 @@ kapply_kernel(int64_t n, const double *__restrict__ pts_all, int64_t ncols,
       // (a pair of fragments) between every two, instead of in one burst
       // ahead of them: the LDS serves the four waves' reads while the matrix
       // cores run, not all at once (2 % faster in FP64, 1 % in FP32)
-      if (s4 == 0) {
-        // the next block's X and coordinates loaded between the first
-        // step's MFMAs, two loads after every two (8 % faster in FP64, 2 %
-        // in FP32 than loading them ahead of the kernel evaluations); after
-        // the last block too: clamped addresses, and what it loads goes to
-        // the idle buffer, never read, so the stores below need no branch
+      if (kSpread && s4 == 0) {
         fetch((kb + 1) * BK);
 #pragma unroll
         for (int i = 0; i < NT / 2; ++i) {
@@ -291,15 +296,8 @@ kapply_kernel(int64_t n, const double *__restrict__ pts_all, int64_t ncols,
           __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // one LDS read
           __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);  // two MFMAs
         }
-      } else {
-        // the next block's X stored into the idle buffer between the last
-        // step's MFMAs, one store after each (1 % faster in FP64, 2 % in
-        // FP32 than the stores in a burst after them)
-#pragma unroll
-        for (int q = 0; q < PER; ++q) {
-          const int e = tid + 256 * q;
-          Xs[buf ^ 1][e % BK][e / BK] = xr[q];
-        }
+      } else if (kSpread) {
+        store_x(buf ^ 1);
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
           __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);  // one LDS store
@@ -308,12 +306,14 @@ kapply_kernel(int64_t n, const double *__restrict__ pts_all, int64_t ncols,
       }
       __builtin_amdgcn_sched_barrier(0);
     }
+    if constexpr (!kSpread) store_x(buf ^ 1);
     if (kb + 1 < nk && tid < BK * DIM) Ps[buf ^ 1][tid / BK][tid % BK] = pk;
     __syncthreads();
   };
 
   fetch(0);
-  commit(0);
+  store_x(0);
+  if (tid < BK * DIM) Ps[0][tid / BK][tid % BK] = pk;
   __syncthreads();
   if constexpr (sizeof(T) == 8) {
     for (int64_t kb = 0; kb < nk; ++kb) kblock(kb, (int)(kb & 1), acc);
