@@ -284,6 +284,17 @@ typedef struct {
  *   opts   see hm_compress_opts
  *   out    the H-matrix (device resident), free with hm_hmatrix_free.
  * The call synchronizes `stream` before returning.
+ * Errors (out is then left unwritten, and every device block the call took
+ * is released, through opts->allocator when one is given; only a tree
+ * device copy the call made stays with the tree):
+ *   HM_E_ARG        a null pointer, an empty tree, neither rank nor tol, r > 64
+ *                   or r - p < 1 in tolerance mode, an unknown format, a black
+ *                   box without an apply of the precision it needs;
+ *   HM_E_STATE      the tree is not colored;
+ *   HM_E_CALLBACK   the black box returned nonzero (it is not called again);
+ *   HM_E_NUMERIC    a block of black-box samples holds a NaN or an Inf;
+ *   HM_E_SATURATED  HM_FLAG_STRICT and a block still at the cap r - p;
+ *   HM_E_NOMEM, HM_E_DEVICE  an allocation or a HIP call failed.
  */
 typedef struct {
   int32_t rank;       /* fixed rank k > 0, or 0 for tolerance mode */
