@@ -377,6 +377,24 @@ hm_status hm_compress(hm_tree *tree, const hm_blackbox *bb, const hm_compress_op
                       void *stream, hm_hmatrix **out);
 void hm_hmatrix_free(hm_hmatrix *H);
 
+/* Device memory planning (host computation only, no device work).
+ * hm_compress_footprint: the most device bytes one hm_compress of `tree`
+ * with `opts` and a black box in tree order holds at once, from the sizes
+ * the compression computes (factor pools at the largest rank, sample and
+ * scratch buffers, plans and work lists, and the tree's device copy when
+ * the tree has none on the current device yet; the H-matrix's own blocks,
+ * which stay after the call, are part of it), the retries of
+ * opts->max_retries not included.  The server reserves it before it starts
+ * a compression.  A black
+ * box in the original order takes two more N x (widest sample) buffers.
+ * HM_E_ARG for null pointers, r outside 1..64 or an unknown format;
+ * HM_E_STATE when the tree is not colored.
+ * hm_matvec_footprint: the device bytes one hm_matvec / hm_matvec_op of
+ * nrhs right-hand sides of dtype takes as scratch (X and Y are the
+ * caller's).  HM_E_ARG for bad arguments. */
+hm_status hm_compress_footprint(hm_tree *tree, const hm_compress_opts *opts, int64_t *bytes);
+hm_status hm_matvec_footprint(const hm_hmatrix *H, int64_t nrhs, int dtype, int64_t *bytes);
+
 /* Plans: compress the same tree with the same black box and options many
  * times (for instance a black box whose device data change between calls),
  * with the whole device pipeline captured once into a HIP graph.

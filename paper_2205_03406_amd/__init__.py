@@ -49,7 +49,7 @@ EXPORTED = [
     "hm_server_release", "hm_server_info", "hm_compress_plan", "hm_plan_execute",
     "hm_plan_hmatrix", "hm_plan_free", "hm_uniform_graph", "hm_matvec_op",
     "hm_hmatrix_blackbox", "hm_product_blackbox", "hm_blackbox_free", "hm_mfma_rate",
-    "hm_matvec_static",
+    "hm_matvec_static", "hm_compress_footprint", "hm_matvec_footprint",
 ]
 
 
@@ -232,6 +232,8 @@ def _load():
         "hm_dense_blackbox": [P, I64, I64, I, C.POINTER(BlackBox)],
         "hm_dense_blackbox_free": [C.POINTER(BlackBox)],
         "hm_compress": [P, C.POINTER(BlackBox), C.POINTER(Opts), P, pp],
+        "hm_compress_footprint": [P, C.POINTER(Opts), P],
+        "hm_matvec_footprint": [P, I64, I, P],
         "hm_hmatrix_free": [P],
         "hm_matvec": [P, I64, I, P, I64, P, I64, I, P],
         "hm_matvec_op": [P, I, I64, I, P, I64, P, I64, I, P],
@@ -585,6 +587,13 @@ class HMatrix:
         _check(_lib.hm_hmatrix_stats(self.h, C.byref(s)))
         return s.as_dict()
 
+    def matvec_footprint(self, nrhs, dtype=np.float64):
+        """Device bytes of scratch one matvec of nrhs columns takes (hm_matvec_footprint)."""
+        b = C.c_int64()
+        _check(_lib.hm_matvec_footprint(self.h, nrhs, HM_F32 if np.dtype(dtype) == np.float32
+                                        else HM_F64, C.byref(b)))
+        return b.value
+
     def matvec(self, X, Y, order=HM_ORDER_ORIGINAL, stream=None, trans=False):
         """Y = H X, or H* X with trans=True (hm_matvec_op)."""
         px, ldx, nc, dt = _colmajor(X, "X")
@@ -764,6 +773,17 @@ def _flags(timing, strict, combine):
         raise ValueError("combine must be 'sum' or 'gaussian'")
     return ((HM_FLAG_TIMING if timing else 0) | (HM_FLAG_STRICT if strict else 0)
             | (HM_FLAG_MIX_GAMMA if combine == "gaussian" else 0))
+
+
+def compress_footprint(tree: Tree, rank=0, tol=0.0, r=0, p=10, prec=HM_PREC_F64,
+                       uniform=False, h2=False) -> int:
+    """hm_compress_footprint: the most device bytes a compression of tree
+    with these options holds at once (host computation, no device work)."""
+    o = Opts(rank=rank, tol=tol, oversample=p, r=r, prec=prec, flags=0, seed=0,
+             max_retries=0, format=_format(uniform, h2), allocator=None)
+    b = C.c_int64()
+    _check(_lib.hm_compress_footprint(tree.h, C.byref(o), C.byref(b)))
+    return b.value
 
 
 def compress(tree: Tree, bb: BlackBox, rank=0, tol=0.0, r=0, p=10, prec=HM_PREC_F64, seed=0,

@@ -3589,6 +3589,29 @@ hm_status hm_philox4x32_10(const uint32_t *ctr, int64_t count, uint32_t key0, ui
   API_END
 }
 
+hm_status hm_compress_footprint(hm_tree *tree, const hm_compress_opts *opts, int64_t *bytes) {
+  API_BEGIN
+  if (!tree || !opts || !bytes) return fail(HM_E_ARG, "hm_compress_footprint: null argument");
+  for (const Graph &G : tree->t.graphs)
+    if (!G.colored && G.nv() > 0) return fail(HM_E_STATE, "tree is not colored (hm_tree_color)");
+  const int p = opts->oversample > 0 ? opts->oversample : 10;
+  const int r = opts->r > 0 ? opts->r : (opts->rank > 0 ? opts->rank + p : 0);
+  if (r <= 0 || r > 64) return fail(HM_E_ARG, "hm_compress_footprint: r must be in 1..64");
+  if (opts->format != HM_FORMAT_H1 && opts->format != HM_FORMAT_UNIFORM_H1 &&
+      opts->format != HM_FORMAT_H2)
+    return fail(HM_E_ARG, "hm_compress_footprint: unknown format");
+  *bytes = hm::compress_footprint(tree->t, *opts);
+  return HM_OK;
+  API_END
+}
+
+hm_status hm_matvec_footprint(const hm_hmatrix *H, int64_t nrhs, int dtype, int64_t *bytes) {
+  if (!H || !bytes || nrhs < 0 || (dtype != HM_F64 && dtype != HM_F32))
+    return fail(HM_E_ARG, "hm_matvec_footprint: bad argument");
+  *bytes = hm::matvec_footprint(H, nrhs, dtype);
+  return HM_OK;
+}
+
 hm_status hm_hmatrix_stats(const hm_hmatrix *H, hm_stats *out) {
   if (!H || !out) return fail(HM_E_ARG, "null argument");
   *out = H->stats;
