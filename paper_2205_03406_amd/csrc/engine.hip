@@ -3217,8 +3217,7 @@ hm_status hm_tree_color(hm_tree *tree) {
              jobs[b].G->xadj[jobs[b].v1] - jobs[b].G->xadj[jobs[b].v0];
     });
     std::atomic<size_t> next{0};
-    const int nth = std::max(1, std::min<int>((int)jobs.size(),
-                                              (int)std::thread::hardware_concurrency()));
+    const int nth = std::max(1, std::min<int>((int)jobs.size(), host_threads()));
     std::vector<std::thread> th;
     for (int t = 0; t < nth; ++t)
       th.emplace_back([&] {

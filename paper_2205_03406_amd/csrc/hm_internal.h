@@ -5,6 +5,7 @@
 #include <functional>
 #include <memory>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/hm.h"
@@ -64,11 +65,33 @@ struct Level {
   int32_t nbox() const { return (int32_t)parent.size(); }
 };
 
+// Allocator whose element construction without arguments leaves the
+// element uninitialized, so that resizing a large buffer that is filled
+// right after does not write it twice (the graph builder's adjacency).
+template <class T>
+struct NoInitAlloc : std::allocator<T> {
+  template <class U>
+  struct rebind {
+    using other = NoInitAlloc<U>;
+  };
+  NoInitAlloc() = default;
+  template <class U>
+  NoInitAlloc(const NoInitAlloc<U> &) {}
+  template <class U>
+  void construct(U *p) noexcept {
+    ::new ((void *)p) U;
+  }
+  template <class U, class... A>
+  void construct(U *p, A &&...a) {
+    ::new ((void *)p) U(std::forward<A>(a)...);
+  }
+};
+
 struct Graph {
   std::vector<int32_t> vbox;     // active box per vertex
   std::vector<int32_t> vclass;   // neighbor-set class of the vertex's box set
   std::vector<int64_t> xadj;
-  std::vector<int32_t> adj;
+  std::vector<int32_t, NoInitAlloc<int32_t>> adj;
   std::vector<int32_t> pa, pb, pv;  // pairs and their vertex
   std::vector<int32_t> color;
   int32_t ncolors = 0;
@@ -122,6 +145,9 @@ hm_status build_forest(const double *pts, const int64_t *counts, int ninst, int 
 // a neighbor of the other.  Idempotent and serialized (one builder at a time).
 void build_uniform_graphs(Tree &T);
 int32_t dsatur(int64_t nv, const int64_t *xadj, const int32_t *adj, int32_t *color);
+// Host worker threads: the CPUs this process may run on (its affinity
+// mask), at most 16.
+int host_threads();
 
 // ------------------------------------------------------------------ sizes
 int64_t hmatrix_device_bytes(const hm_hmatrix *H);

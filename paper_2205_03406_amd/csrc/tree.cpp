@@ -5,10 +5,12 @@
 // matrices" (tree and lists), eq:h1constraints and def:incompatibility_graph
 // (level graphs), the leaf-extraction section (leaf graph), alg:dsatur.
 //
-// Design notes (MI355X build): this runs on the host once per geometry.  It
+// Design notes: this runs on the host once per geometry.  It
 // works level by level with candidate sets drawn from the parent level
 // (a box's neighbors are among the children of its parent's neighbors), so
 // the cost is O(N log N + boxes * 6^d + edges) rather than quadratic.
+#include <sched.h>
+
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -26,6 +28,18 @@
 #include "hm_internal.h"
 
 namespace hm {
+
+// Set on the threads of a forest build's pool: the trees they build use no
+// worker threads of their own (the pool already holds the CPUs).
+static thread_local bool t_in_pool = false;
+
+int host_threads() {
+  cpu_set_t set;
+  int n = 0;
+  if (sched_getaffinity(0, sizeof(set), &set) == 0) n = CPU_COUNT(&set);
+  if (n <= 0) n = (int)std::thread::hardware_concurrency();
+  return std::max(1, std::min(n, 16));
+}
 
 namespace {
 
@@ -71,6 +85,7 @@ uint32_t cell(double x, double lo, double s, int kb) {
 
 struct Builder {
   Tree &T;
+  int workers = 1;  // threads per graph's edge passes
   explicit Builder(Tree &t) : T(t) {}
 
   // children[l][P] = boxes of level l+1 whose parent is P
@@ -292,36 +307,82 @@ struct Builder {
         for (int32_t g : sets[G.vclass[v]]) containing[fc[g]++] = (int32_t)v;
       }
     }
-    // each row is marked in a vertex bitmap and read back in ascending order
+    // each row is marked in a vertex bitmap and read back in ascending order.
+    // Rows are independent: chunks of kRows rows go to worker threads, each
+    // with its own bitmap.  A first pass counts every row, a second writes
+    // it at its offset, so the result does not depend on the number of
+    // threads and the adjacency is written once, in place.
     const int64_t words = (nv + 63) / 64;
-    std::vector<uint64_t> mark(words, 0);
-    std::vector<int64_t> touched;
-    auto put = [&](int32_t v) {
-      uint64_t &w = mark[v >> 6];
-      if (!w) touched.push_back(v >> 6);
-      w |= uint64_t(1) << (v & 63);
-    };
+    constexpr int64_t kRows = 64;
+    const int64_t nchunk = (nv + kRows - 1) / kRows;
+    const int nth = (int)std::min<int64_t>(workers, nchunk);
     G.xadj.assign(nv + 1, 0);
-    G.adj.clear();
-    for (int64_t u = 0; u < nv; ++u) {
-      touched.clear();
-      const int bu = G.vbox[u];
-      for (int32_t g : sets[G.vclass[u]])
-        if (g != bu)
-          for (int64_t q = pa[g]; q < pa[g + 1]; ++q) put(by_active[q]);
-      for (int64_t q = pc[bu]; q < pc[bu + 1]; ++q)
-        if (G.vbox[containing[q]] != bu) put(containing[q]);
-      std::sort(touched.begin(), touched.end());
-      for (int64_t w : touched) {
-        uint64_t bits = mark[w];
-        mark[w] = 0;
-        while (bits) {
-          G.adj.push_back((int32_t)(w * 64 + __builtin_ctzll(bits)));
-          bits &= bits - 1;
+    std::atomic<int64_t> next{0};
+    auto pass = [&](bool write) {
+      std::vector<uint64_t> mark(words, 0);
+      std::vector<int64_t> touched;
+      int64_t wlo = 0, whi = -1;  // range of the touched words
+      auto put = [&](int32_t v) {
+        uint64_t &w = mark[v >> 6];
+        if (!w) {
+          touched.push_back(v >> 6);
+          wlo = std::min<int64_t>(wlo, v >> 6);
+          whi = std::max<int64_t>(whi, v >> 6);
+        }
+        w |= uint64_t(1) << (v & 63);
+      };
+      for (int64_t c = next++; c < nchunk; c = next++) {
+        for (int64_t u = c * kRows; u < std::min(nv, (c + 1) * kRows); ++u) {
+          touched.clear();
+          wlo = words;
+          whi = -1;
+          const int bu = G.vbox[u];
+          for (int32_t g : sets[G.vclass[u]])
+            if (g != bu)
+              for (int64_t q = pa[g]; q < pa[g + 1]; ++q) put(by_active[q]);
+          for (int64_t q = pc[bu]; q < pc[bu + 1]; ++q)
+            if (G.vbox[containing[q]] != bu) put(containing[q]);
+          if (!write) {
+            int64_t cnt = 0;
+            for (int64_t w : touched) {
+              cnt += __builtin_popcountll(mark[w]);
+              mark[w] = 0;
+            }
+            G.xadj[u + 1] = cnt;  // row length, summed below
+            continue;
+          }
+          int32_t *o = G.adj.data() + G.xadj[u];
+          auto emit = [&](int64_t w) {
+            uint64_t bits = mark[w];
+            mark[w] = 0;
+            while (bits) {
+              *o++ = (int32_t)(w * 64 + __builtin_ctzll(bits));
+              bits &= bits - 1;
+            }
+          };
+          if (whi - wlo + 1 <= 8 * (int64_t)touched.size()) {
+            // dense row: walk the touched range in order (no sort)
+            for (int64_t w = wlo; w <= whi; ++w)
+              if (mark[w]) emit(w);
+          } else {
+            std::sort(touched.begin(), touched.end());
+            for (int64_t w : touched) emit(w);
+          }
         }
       }
-      G.xadj[u + 1] = (int64_t)G.adj.size();
-    }
+    };
+    auto run = [&](bool write) {
+      next = 0;
+      std::vector<std::thread> th;
+      for (int t = 1; t < nth; ++t) th.emplace_back(pass, write);
+      pass(write);
+      for (auto &t : th) t.join();
+    };
+    run(false);
+    for (int64_t u = 0; u < nv; ++u) G.xadj[u + 1] += G.xadj[u];
+    G.adj.clear();
+    G.adj.resize((size_t)G.xadj[nv]);  // uninitialized: the second pass writes every entry
+    run(true);
   }
 
   void level_graph(int l, Graph &G) {
@@ -439,6 +500,7 @@ hm_status build_tree(const double *pts, int64_t n, int dim, int leaf, int kind, 
   T.leaf = leaf;
   T.pts.assign(pts, pts + n * dim);
   Builder B(T);
+  B.workers = t_in_pool ? 1 : host_threads();
   const bool timing = std::getenv("HM_TIMING") != nullptr;
   auto t0 = std::chrono::steady_clock::now();
   auto lap = [&](const char *what) {
@@ -487,11 +549,12 @@ hm_status build_forest(const double *pts, const int64_t *counts, int ninst, int 
   std::vector<hm_status> rc(ninst, HM_OK);
   {
     // instances are independent: a pool of host threads takes them in turn
-    const int nth = std::max(1, std::min<int>(ninst, (int)std::thread::hardware_concurrency()));
+    const int nth = std::max(1, std::min<int>(ninst, host_threads()));
     std::vector<std::thread> th;
     std::atomic<int> next{0};
     for (int t = 0; t < nth; ++t)
       th.emplace_back([&] {
+        t_in_pool = true;
         for (int i = next++; i < ninst; i = next++)
           rc[i] = build_tree(pts + off[i] * dim, counts[i], dim, leaf, kind, adm, parts[i]);
       });
