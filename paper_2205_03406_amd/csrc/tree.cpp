@@ -18,6 +18,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <set>
@@ -579,9 +580,41 @@ hm_status build_forest(const double *pts, const int64_t *counts, int ninst, int 
     for (int64_t t = 0; t < counts[i]; ++t) F.perm[off[i] + t] = parts[i].perm[t] + off[i];
   // boxes of instance i at forest level l: its own level min(l, L_i)
   std::vector<std::vector<int32_t>> boff(nlev, std::vector<int32_t>(ninst + 1, 0));
+  for (int l = 0; l < nlev; ++l)
+    for (int i = 0; i < ninst; ++i)
+      boff[l][i + 1] = boff[l][i] + parts[i].lev[std::min(l, parts[i].L())].nbox();
+  // the levels, and below the graphs, are independent of each other: each
+  // is filled by one thread of a pool, into vectors sized up front
+  auto pool = [](int count, const std::function<void(int)> &f) {
+    std::atomic<int> next{0};
+    auto run = [&] {
+      for (int k = next++; k < count; k = next++) f(k);
+    };
+    const int nth = std::max(1, std::min(count, host_threads()));
+    std::vector<std::thread> th;
+    for (int t = 1; t < nth; ++t) th.emplace_back(run);
+    run();
+    for (auto &t : th) t.join();
+  };
   F.lev.resize(nlev);
-  for (int l = 0; l < nlev; ++l) {
+  pool(nlev, [&](int l) {
     Level &Lv = F.lev[l];
+    const int64_t nb = boff[l][ninst];
+    int64_t nn = 0, ni = 0;
+    for (int i = 0; i < ninst; ++i) {
+      const Tree &P = parts[i];
+      const Level &S = P.lev[std::min(l, P.L())];
+      nn += S.nei_ptr[S.nbox()];
+      if (l <= P.L()) ni += S.int_ptr[S.nbox()];
+    }
+    Lv.start.reserve(nb + 1);
+    Lv.parent.reserve(nb);
+    Lv.org.reserve(nb * F.ostride);
+    Lv.blev.reserve(nb);
+    Lv.nei.reserve(nn);
+    Lv.nei_ptr.reserve(nb + 1);
+    Lv.intl.reserve(ni);
+    Lv.int_ptr.reserve(nb + 1);
     Lv.nei_ptr.push_back(0);
     Lv.int_ptr.push_back(0);
     for (int i = 0; i < ninst; ++i) {
@@ -590,7 +623,6 @@ hm_status build_forest(const double *pts, const int64_t *counts, int ninst, int 
       const bool carried = l > P.L();
       const Level &S = P.lev[sl];
       const int32_t b0 = boff[l][i];
-      boff[l][i + 1] = b0 + S.nbox();
       for (int b = 0; b < S.nbox(); ++b) {
         Lv.start.push_back(S.start[b] + off[i]);
         Lv.parent.push_back(l == 0 ? -1 : (carried ? b : S.parent[b]) + boff[l - 1][i]);
@@ -604,19 +636,36 @@ hm_status build_forest(const double *pts, const int64_t *counts, int ninst, int 
       }
     }
     Lv.start.push_back(F.n);
-  }
+  });
   // graphs: disjoint unions, instance-major vertex numbering
   F.graphs.resize(nlev + 1);
   F.gvoff.assign(nlev + 1, std::vector<int64_t>(ninst + 1, 0));
-  for (int g = 0; g <= nlev; ++g) {
+  static const Graph empty;
+  pool(nlev + 1, [&](int g) {
     Graph &G = F.graphs[g];
+    const int bl = g < nlev ? g : nlev - 1;  // box level of the graph's ids
+    auto part = [&](int i) -> const Graph & {
+      const Tree &P = parts[i];
+      return g == nlev ? P.leaf_graph() : (g <= P.L() ? P.graphs[g] : empty);
+    };
+    int64_t tv = 0, ta = 0, tp = 0;
+    for (int i = 0; i < ninst; ++i) {
+      const Graph &S = part(i);
+      tv += S.nv();
+      ta += (int64_t)S.adj.size();
+      tp += (int64_t)S.pa.size();
+    }
+    G.vbox.reserve(tv);
+    G.vclass.reserve(tv);
+    G.xadj.reserve(tv + 1);
+    G.adj.reserve(ta);
+    G.pa.reserve(tp);
+    G.pb.reserve(tp);
+    G.pv.reserve(tp);
     G.xadj.push_back(0);
     int32_t cls0 = 0;
-    const int bl = g < nlev ? g : nlev - 1;  // box level of the graph's ids
     for (int i = 0; i < ninst; ++i) {
-      const Tree &P = parts[i];
-      static const Graph empty;
-      const Graph &S = g == nlev ? P.leaf_graph() : (g <= P.L() ? P.graphs[g] : empty);
+      const Graph &S = part(i);
       const int64_t v0 = G.nv();
       F.gvoff[g][i] = v0;
       const int32_t b0 = boff[bl][i];
@@ -637,7 +686,7 @@ hm_status build_forest(const double *pts, const int64_t *counts, int ninst, int 
       }
     }
     F.gvoff[g][ninst] = G.nv();
-  }
+  });
   return HM_OK;
 }
 
