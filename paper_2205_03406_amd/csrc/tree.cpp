@@ -751,7 +751,10 @@ void build_uniform_graphs(Tree &T) {
 // DSatur.  Vertices are ranked once by (degree descending, id ascending); the
 // uncolored vertices of each saturation value sit in a bitset over ranks, so
 // the next vertex is the lowest set rank of the highest non-empty saturation.
-// Per-vertex bitsets record the colors already on a neighbor.
+// Bitsets record the colors already on a neighbor of each vertex, stored
+// color word major (word q of all vertices together), so that coloring a
+// vertex with c touches one array of nv words while it updates its
+// neighbors.
 int32_t dsatur(int64_t nv, const int64_t *xadj, const int32_t *adj, int32_t *color) {
   if (nv <= 0) return 0;
   int64_t maxdeg = 0;
@@ -782,19 +785,20 @@ int32_t dsatur(int64_t nv, const int64_t *xadj, const int32_t *adj, int32_t *col
     L[w] &= L[w] - 1;
     count[top]--;
     const int64_t v = byrank[rk];
-    const uint64_t *sv = &seen[(size_t)(v * cwords)];
     int32_t c = 0;
-    for (int64_t q = 0; q < cwords; ++q)
-      if (~sv[q]) {
-        c = int32_t(q * 64 + __builtin_ctzll(~sv[q]));
+    for (int64_t q = 0; q < cwords; ++q) {
+      const uint64_t sq = seen[(size_t)(q * nv + v)];
+      if (~sq) {
+        c = int32_t(q * 64 + __builtin_ctzll(~sq));
         break;
       }
+    }
     color[v] = c;
     ncol = std::max(ncol, c + 1);
     const uint64_t mask = uint64_t(1) << (c % 64);
     for (int64_t t = xadj[v]; t < xadj[v + 1]; ++t) {
       const int64_t u = adj[t];
-      uint64_t &bit = seen[(size_t)(u * cwords + c / 64)];
+      uint64_t &bit = seen[(size_t)((c / 64) * nv + u)];
       if (bit & mask) continue;
       bit |= mask;
       if (color[u] >= 0) continue;
